@@ -1,0 +1,294 @@
+"""CPU FP64 oracle for the coupled pressure-temperature solve.
+
+TEST INFRASTRUCTURE ONLY.  Plain, slow, single-threaded C (built with gcc,
+``-O2 -ffp-contract=off``, no fast-math) plus the NumPy dense brute-force
+helpers in ``dense.py``.  Only the test-suite, the smoke check and the CPU
+baseline leg of the benchmark may import this package; the product library
+never does, and it shares no source with the HIP path.
+
+What it computes, and the passage each part follows:
+  residual / Jacobian / Schur approximation  Section 2.2, eq. (Fm), (Fe),
+      (AXR)-(rhouT), (Se)                    -> physics.c
+  AMG setup and V-cycle                      Section 3 (AMG background),
+      components named in amg.c             -> amg.c
+  block preconditioner and GMRES             Section 3.2 (five-step list),
+      Section 4 (right-preconditioned GMRES, restart 30) -> krylov.c
+  3-D convolution smoother network           cnn.c
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "liboracle.so")
+_SRC = ["physics.c", "amg.c", "krylov.c", "cnn.c"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle shared library with gcc (no GPU, no HIP)."""
+    srcs = [os.path.join(_HERE, s) for s in _SRC if os.path.exists(os.path.join(_HERE, s))]
+    if not force and os.path.exists(_LIB):
+        newest = max(os.path.getmtime(s) for s in srcs + [os.path.join(_HERE, "tp_oracle.h")])
+        if os.path.getmtime(_LIB) >= newest:
+            return _LIB
+    tmp = _LIB + f".tmp{os.getpid()}"
+    cmd = ["gcc", "-std=gnu99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+           "-shared", "-Wall", "-Wno-unused-function", "-Wno-maybe-uninitialized", "-o", tmp] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double)]
+
+
+class _Props(C.Structure):
+    _fields_ = [(k, C.c_double) for k in
+                ("rho0", "p0", "T0", "c_p", "c_T", "mu0", "mu_B", "cv", "rho_r", "c_r", "g")]
+
+
+class _Well(C.Structure):
+    _fields_ = [("cell", C.c_int32), ("kind", C.c_int32), ("rate", C.c_double),
+                ("T_inj", C.c_double)]
+
+
+class _AmgParams(C.Structure):
+    _fields_ = [("theta", C.c_double), ("seed", C.c_uint64), ("max_levels", C.c_int32),
+                ("coarse_max", C.c_int32), ("omega", C.c_double), ("nu_pre", C.c_int32),
+                ("nu_post", C.c_int32), ("skip_lu", C.c_int32), ("smoother", C.c_int32),
+                ("cheb_degree", C.c_int32), ("cheb_lo", C.c_double), ("restriction", C.c_int32)]
+
+
+class _Jac(C.Structure):
+    _fields_ = [("n", C.c_int32), ("rowptr", C.c_void_p), ("col", C.c_void_p),
+                ("pp", C.c_void_p), ("pT", C.c_void_p), ("Tp", C.c_void_p), ("TT", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        _lib = C.CDLL(_LIB)
+        _lib.or_amg_setup.restype = C.c_int
+        _lib.or_amg_nlev.restype = C.c_int32
+        _lib.or_stencil_nnz.restype = C.c_int32
+        _lib.or_stencil_pattern.restype = C.c_int32
+        _lib.or_splitmix64.restype = C.c_uint64
+        _lib.or_splitmix64.argtypes = [C.c_uint64]
+        _lib.or_gmres.restype = C.c_int
+        _lib.or_amg_free.argtypes = [C.c_void_p]
+        _lib.or_amg_nlev.argtypes = [C.c_void_p]
+        _lib.or_amg_level_R_nnz.restype = C.c_int32
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _grid(g):
+    return _Grid(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz)
+
+
+def _props(pr):
+    return _Props(*pr.as_tuple())
+
+
+def _wells(ws):
+    arr = (_Well * max(1, len(ws)))()
+    for k, w in enumerate(ws):
+        arr[k] = _Well(w.cell, w.kind, w.rate, w.T_inj)
+    return arr
+
+
+def splitmix64(x: int) -> int:
+    return int(lib().or_splitmix64(C.c_uint64(x & (2 ** 64 - 1))))
+
+
+def stencil_pattern(grid):
+    g = _grid(grid)
+    nnz = lib().or_stencil_nnz(C.byref(g))
+    rowptr = np.zeros(grid.n + 1, np.int32)
+    col = np.zeros(nnz, np.int32)
+    lib().or_stencil_pattern(C.byref(g), _p(rowptr), _p(col))
+    return rowptr, col
+
+
+def residual(prob, x=None):
+    x = prob.x_k if x is None else x
+    G = np.zeros(2 * prob.grid.n)
+    ws = _wells(prob.wells)
+    lib().or_residual(C.byref(_grid(prob.grid)), C.byref(_props(prob.props)),
+                      _p(_f64(prob.K)), _p(_f64(prob.phi)), _p(_f64(prob.kappa)),
+                      C.c_int32(len(prob.wells)), ws, C.c_double(prob.dt),
+                      _p(_f64(prob.x_prev)), _p(_f64(x)), _p(G))
+    return G
+
+
+def residual_complex(prob, xc):
+    """G on a complex state (for complex-step differentiation)."""
+    xc = np.ascontiguousarray(xc, dtype=np.complex128)
+    G = np.zeros(2 * prob.grid.n, dtype=np.complex128)
+    ws = _wells(prob.wells)
+    lib().or_residual_c(C.byref(_grid(prob.grid)), C.byref(_props(prob.props)),
+                        _p(_f64(prob.K)), _p(_f64(prob.phi)), _p(_f64(prob.kappa)),
+                        C.c_int32(len(prob.wells)), ws, C.c_double(prob.dt),
+                        _p(_f64(prob.x_prev)), _p(xc), _p(G))
+    return G
+
+
+class Jacobian:
+    """The four blocks of eq. AXR plus the Schur approximation, CSR on the stencil."""
+
+    def __init__(self, n, rowptr, col, pp, pT, Tp, TT, S):
+        self.n, self.rowptr, self.col = n, rowptr, col
+        self.pp, self.pT, self.Tp, self.TT, self.S = pp, pT, Tp, TT, S
+
+    def block(self, name):
+        import scipy.sparse as sp
+        return sp.csr_matrix((getattr(self, name), self.col, self.rowptr), shape=(self.n, self.n))
+
+    def dense(self):
+        """Full 2n x 2n interleaved Jacobian (dense; tiny grids only)."""
+        n = self.n
+        A = np.zeros((2 * n, 2 * n))
+        for i in range(n):
+            for k in range(self.rowptr[i], self.rowptr[i + 1]):
+                j = self.col[k]
+                A[2 * i, 2 * j] = self.pp[k]
+                A[2 * i, 2 * j + 1] = self.pT[k]
+                A[2 * i + 1, 2 * j] = self.Tp[k]
+                A[2 * i + 1, 2 * j + 1] = self.TT[k]
+        return A
+
+    def _cstruct(self):
+        self._keep = [_i32(self.rowptr), _i32(self.col), _f64(self.pp), _f64(self.pT),
+                      _f64(self.Tp), _f64(self.TT)]
+        k = self._keep
+        return _Jac(self.n, _p(k[0]), _p(k[1]), _p(k[2]), _p(k[3]), _p(k[4]), _p(k[5]))
+
+
+def jacobian(prob, x=None):
+    x = prob.x_k if x is None else x
+    rowptr, col = stencil_pattern(prob.grid)
+    nnz = len(col)
+    arrs = [np.zeros(nnz) for _ in range(5)]
+    ws = _wells(prob.wells)
+    lib().or_jacobian(C.byref(_grid(prob.grid)), C.byref(_props(prob.props)),
+                      _p(_f64(prob.K)), _p(_f64(prob.phi)), _p(_f64(prob.kappa)),
+                      C.c_int32(len(prob.wells)), ws, C.c_double(prob.dt),
+                      _p(_f64(prob.x_prev)), _p(_f64(x)), _p(rowptr), _p(col),
+                      *[_p(a) for a in arrs])
+    return Jacobian(prob.grid.n, rowptr, col, *arrs)
+
+
+class AMG:
+    """Oracle AMG hierarchy (owns a C handle)."""
+
+    def __init__(self, n, rowptr, col, val, theta=0.25, seed=12345, max_levels=25,
+                 coarse_max=256, omega=1.0, nu_pre=1, nu_post=1, skip_lu=False,
+                 smoother=1, cheb_degree=3, cheb_lo=0.3, restriction=0):
+        self._rowptr, self._col, self._val = _i32(rowptr), _i32(col), _f64(val)
+        prm = _AmgParams(theta, seed, max_levels, coarse_max, omega, nu_pre, nu_post,
+                         1 if skip_lu else 0, smoother, cheb_degree, cheb_lo, restriction)
+        h = C.c_void_p()
+        self.status = lib().or_amg_setup(C.c_int32(n), _p(self._rowptr), _p(self._col),
+                                         _p(self._val), C.byref(prm), C.byref(h))
+        self.h = h
+        self.n = n
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.or_amg_free(self.h)
+            self.h = None
+
+    @property
+    def nlev(self):
+        return int(lib().or_amg_nlev(self.h))
+
+    def level(self, l):
+        n, nnzA, nnzP = C.c_int32(), C.c_int32(), C.c_int32()
+        lib().or_amg_level_sizes(self.h, C.c_int32(l), C.byref(n), C.byref(nnzA), C.byref(nnzP))
+        n, nnzA, nnzP = n.value, nnzA.value, nnzP.value
+        out = dict(n=n, A_rowptr=np.zeros(n + 1, np.int32), A_col=np.zeros(nnzA, np.int32),
+                   A_val=np.zeros(nnzA), dinv=np.zeros(n))
+        coarsest = l == self.nlev - 1
+        if not coarsest:
+            out.update(cf=np.zeros(n, np.int32), P_rowptr=np.zeros(n + 1, np.int32),
+                       P_col=np.zeros(nnzP, np.int32), P_val=np.zeros(nnzP))
+        lib().or_amg_level_copy(self.h, C.c_int32(l), _p(out["A_rowptr"]), _p(out["A_col"]),
+                                _p(out["A_val"]), _p(out.get("cf")), _p(out.get("P_rowptr")),
+                                _p(out.get("P_col")), _p(out.get("P_val")), _p(out["dinv"]))
+        if not coarsest:
+            nr = lib().or_amg_level_R_nnz(self.h, C.c_int32(l))
+            nc = self.level_n(l + 1)
+            out.update(R_rowptr=np.zeros(nc + 1, np.int32), R_col=np.zeros(nr, np.int32),
+                       R_val=np.zeros(nr))
+            lib().or_amg_level_R_copy(self.h, C.c_int32(l), _p(out["R_rowptr"]),
+                                      _p(out["R_col"]), _p(out["R_val"]))
+        return out
+
+    def level_n(self, l):
+        n, a, b = C.c_int32(), C.c_int32(), C.c_int32()
+        lib().or_amg_level_sizes(self.h, C.c_int32(l), C.byref(n), C.byref(a), C.byref(b))
+        return n.value
+
+    def vcycle(self, b):
+        b = _f64(b)
+        x = np.zeros_like(b)
+        lib().or_vcycle(self.h, _p(b), _p(x))
+        return x
+
+
+def spmv(rowptr, col, val, x):
+    x = _f64(x)
+    y = np.zeros(len(rowptr) - 1)
+    lib().or_spmv(C.c_int32(len(rowptr) - 1), _p(_i32(rowptr)), _p(_i32(col)), _p(_f64(val)),
+                  _p(x), _p(y))
+    return y
+
+
+VARIANTS = {"identity": -1, "lower": 0, "upper": 1, "full": 2}
+
+
+def precond_apply(J: Jacobian, amg_pp, amg_S, r, variant="lower"):
+    js = J._cstruct()
+    r = _f64(r)
+    z = np.zeros_like(r)
+    lib().or_precond_apply(C.byref(js), amg_pp.h if amg_pp else None,
+                           amg_S.h if amg_S else None, C.c_int32(VARIANTS[variant]),
+                           _p(r), _p(z))
+    return z
+
+
+def gmres(J: Jacobian, amg_pp, amg_S, b, x0=None, variant="lower", rtol=1e-8,
+          restart=30, maxit=1000):
+    js = J._cstruct()
+    b = _f64(b)
+    x = np.zeros_like(b) if x0 is None else _f64(x0).copy()
+    it, rel = C.c_int32(), C.c_double()
+    hist = np.zeros(maxit + 1)
+    st = lib().or_gmres(C.byref(js), amg_pp.h if amg_pp else None,
+                        amg_S.h if amg_S else None, C.c_int32(VARIANTS[variant]),
+                        _p(b), _p(x), C.c_double(rtol), C.c_int32(restart),
+                        C.c_int32(maxit), C.byref(it), C.byref(rel), _p(hist))
+    return x, dict(converged=(st == 0), iters=it.value, rel_true=rel.value,
+                   history=hist[: it.value + 1])

@@ -1,0 +1,269 @@
+"""Seeded synthetic workloads for the coupled pressure-temperature solve.
+
+This module only draws inputs: grids, permeability/porosity/conductivity
+fields, Newton states and well lists.  It holds none of the discretisation,
+preconditioner or Krylov arithmetic, so the GPU library and the CPU oracle
+can both consume the very same arrays.
+
+Physical model (Section 2.1 of the paper): single-phase flow with an
+exponential density law and backward-Euler time stepping.  The fluid laws
+and sizes follow the five benchmark workloads:
+
+  * W1  32x32 2-D, homogeneous k = 1e-13 m^2, porosity 0.2, perturbed state;
+  * W2  64x64x32 layered log-normal permeability, corner wells at 450 K;
+  * W3  128x128x64, same layered field (4 decades through the clip);
+  * W4  96^3 channelised field (sinusoidal 1e-11 streaks in 1e-15 matrix),
+        hot injection at 550 K;
+  * W5  256x256x64 layered field with streaks overlaid.
+
+Random numbers come from numpy's PCG64 with a fixed draw order, so a
+(workload, seed) pair always yields bit-identical arrays.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+@dataclasses.dataclass(frozen=True)
+class Grid:
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    dy: float
+    dz: float
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+@dataclasses.dataclass(frozen=True)
+class Props:
+    """Fluid/rock constants, SI units.
+
+    rho = rho0*exp(c_p (p-p0) + c_T (T-T0));  mu = mu0*exp(mu_B (1/T - 1/T0)).
+    cv, c_r: specific heats of fluid and rock (values of the paper's
+    parameter table); rho_r: rock density (not given by the paper);
+    g: gravitational acceleration along -z (0 disables gravity).
+    """
+    rho0: float = 1000.0
+    p0: float = 1.0e7
+    T0: float = 350.0
+    c_p: float = 4.5e-10
+    c_T: float = -3.0e-4
+    mu0: float = 1.0e-3
+    mu_B: float = 1500.0
+    cv: float = 2093.4
+    rho_r: float = 2500.0
+    c_r: float = 920.0
+    g: float = 0.0
+
+    def as_tuple(self):
+        return (self.rho0, self.p0, self.T0, self.c_p, self.c_T, self.mu0,
+                self.mu_B, self.cv, self.rho_r, self.c_r, self.g)
+
+
+@dataclasses.dataclass(frozen=True)
+class Well:
+    cell: int
+    kind: int          # 0 injector, 1 producer
+    rate: float        # m^3/s, >= 0
+    T_inj: float       # K (used by injectors)
+
+
+@dataclasses.dataclass
+class Problem:
+    """One linearised coupled solve: the Jacobian is taken at x_k."""
+    name: str
+    grid: Grid
+    props: Props
+    K: np.ndarray          # (n,) permeability, m^2
+    phi: np.ndarray        # (n,) porosity
+    kappa: np.ndarray      # (n,) thermal conductivity, W/m/K
+    wells: list
+    dt: float
+    x_prev: np.ndarray     # (2n,) interleaved [p0, T0, p1, T1, ...]
+    x_k: np.ndarray        # (2n,) interleaved Newton iterate
+    seed: int
+
+
+DAY = 86400.0
+WELL_RATE = 1.0e-5
+
+
+def _porosity_from_logk(logk: np.ndarray) -> np.ndarray:
+    return np.clip(0.2 + 0.05 * (logk + 13.0), 0.1, 0.3)
+
+
+def layered_field(rng: np.random.Generator, grid: Grid):
+    """Layer-wise correlated log-normal permeability.
+
+    Each z-layer draws a mean m_l ~ N(-13, 1); every cell adds U(-0.2, 0.2)
+    jitter and log10 k is clipped to [-15, -11] (four decades).
+    """
+    m = rng.normal(-13.0, 1.0, size=grid.nz)
+    jit = rng.uniform(-0.2, 0.2, size=(grid.nz, grid.ny, grid.nx))
+    logk = np.clip(m[:, None, None] + jit, -15.0, -11.0)
+    return logk.reshape(-1)
+
+
+def add_streaks(rng: np.random.Generator, grid: Grid, logk: np.ndarray,
+                nstreak: int, logk_streak: float = -11.0) -> np.ndarray:
+    """Overlay sinusoidal high-permeability channels.
+
+    Streak s has centre line y = y0 + A sin(2 pi x / L + psi) in the x-y
+    plane at height z0, with y0 ~ U(0, ny), A ~ U(4, 16), L ~ U(32, 96),
+    psi ~ U(0, 2 pi), z0 ~ U(0, nz), half-widths hy, hz in {1, 2} cells.
+    A cell centre within the half-widths of a centre line joins the streak.
+    """
+    logk = logk.reshape(grid.nz, grid.ny, grid.nx).copy()
+    xc = np.arange(grid.nx) + 0.5
+    yc = np.arange(grid.ny) + 0.5
+    zc = np.arange(grid.nz) + 0.5
+    for _ in range(nstreak):
+        y0 = rng.uniform(0.0, grid.ny)
+        amp = rng.uniform(4.0, 16.0)
+        lam = rng.uniform(32.0, 96.0)
+        psi = rng.uniform(0.0, 2.0 * math.pi)
+        z0 = rng.uniform(0.0, grid.nz)
+        hy = int(rng.integers(1, 3))
+        hz = int(rng.integers(1, 3))
+        ycl = y0 + amp * np.sin(2.0 * math.pi * xc / lam + psi)       # (nx,)
+        iny = np.abs(yc[:, None] - ycl[None, :]) < hy                 # (ny, nx)
+        inz = np.abs(zc - z0) < hz                                    # (nz,)
+        mask = inz[:, None, None] & iny[None, :, :]
+        logk[mask] = logk_streak
+    return logk.reshape(-1)
+
+
+def perturbed_state(rng: np.random.Generator, n: int, props: Props,
+                    sigma_p: float = 1.0e5, sigma_T: float = 5.0):
+    """x_prev uniform (p0, T0); x_k = x_prev + (N(0, sigma_p), N(0, sigma_T))."""
+    x_prev = np.empty(2 * n)
+    x_prev[0::2] = props.p0
+    x_prev[1::2] = props.T0
+    dp = rng.normal(0.0, sigma_p, size=n)
+    dT = rng.normal(0.0, sigma_T, size=n)
+    x_k = x_prev.copy()
+    x_k[0::2] += dp
+    x_k[1::2] += dT
+    return x_prev, x_k
+
+
+def corner_wells(grid: Grid, T_inj: float, rate: float = WELL_RATE):
+    return [Well(0, 0, rate, T_inj), Well(grid.n - 1, 1, rate, T_inj)]
+
+
+def make_problem(name: str, seed: int | None = None, props: Props | None = None,
+                 kappa: float | None = None, grid: Grid | None = None) -> Problem:
+    """Build one of the named workloads (W1..W5) or a scaled variant.
+
+    ``grid`` overrides the size of the named workload (same recipe on a
+    different grid), used for small parity cases.
+    """
+    props = props or Props()
+    if name == "W1":
+        seed = 1 if seed is None else seed
+        grid = grid or Grid(32, 32, 1, 20.0 / 32, 20.0 / 32, 1.0)
+        rng = np.random.default_rng(np.random.PCG64(seed))
+        n = grid.n
+        K = np.full(n, 1.0e-13)
+        phi = np.full(n, 0.2)
+        kap = np.full(n, 2.0 if kappa is None else kappa)
+        x_prev, x_k = perturbed_state(rng, n, props)
+        return Problem(name, grid, props, K, phi, kap, [], DAY, x_prev, x_k, seed)
+    if name in ("W2", "W3"):
+        seed = (2 if name == "W2" else 3) if seed is None else seed
+        dims = (64, 64, 32) if name == "W2" else (128, 128, 64)
+        grid = grid or Grid(*dims, 1.0, 1.0, 1.0)
+        rng = np.random.default_rng(np.random.PCG64(seed))
+        logk = layered_field(rng, grid)
+        K = 10.0 ** logk
+        phi = _porosity_from_logk(logk)
+        kap = np.full(grid.n, 2.0 if kappa is None else kappa)
+        x_prev, x_k = perturbed_state(rng, grid.n, props)
+        return Problem(name, grid, props, K, phi, kap, corner_wells(grid, 450.0),
+                       DAY, x_prev, x_k, seed)
+    if name == "W4":
+        seed = 4001 if seed is None else seed
+        grid = grid or Grid(96, 96, 96, 1.0, 1.0, 1.0)
+        rng = np.random.default_rng(np.random.PCG64(seed))
+        logk = np.full(grid.n, -15.0)
+        nstreak = max(1, int(round(24 * grid.n / 96 ** 3)))
+        logk = add_streaks(rng, grid, logk, nstreak)
+        K = 10.0 ** logk
+        phi = np.where(logk > -13.0, 0.3, 0.1)
+        kap = np.full(grid.n, 2.0 if kappa is None else kappa)
+        x_prev, x_k = perturbed_state(rng, grid.n, props)
+        return Problem(name, grid, props, K, phi, kap, corner_wells(grid, 550.0),
+                       DAY, x_prev, x_k, seed)
+    if name == "W5":
+        seed = 5 if seed is None else seed
+        grid = grid or Grid(256, 256, 64, 1.0, 1.0, 1.0)
+        rng = np.random.default_rng(np.random.PCG64(seed))
+        logk = layered_field(rng, grid)
+        nstreak = max(1, int(round(24 * grid.n / 96 ** 3)))
+        logk = add_streaks(rng, grid, logk, nstreak)
+        K = 10.0 ** logk
+        phi = _porosity_from_logk(logk)
+        kap = np.full(grid.n, 20.0 if kappa is None else kappa)
+        x_prev = np.empty(2 * grid.n)
+        x_prev[0::2] = props.p0
+        x_prev[1::2] = props.T0
+        return Problem(name, grid, props, K, phi, kap, corner_wells(grid, 450.0),
+                       DAY, x_prev, x_prev.copy(), seed)
+    raise ValueError(f"unknown workload {name!r}")
+
+
+def random_rhs(seed: int, m: int) -> np.ndarray:
+    rng = np.random.default_rng(np.random.PCG64(seed))
+    return rng.standard_normal(m)
+
+
+def poisson_csr(dims, dirichlet: bool = True):
+    """Constant-coefficient 5-point (2-D) or 7-point (3-D) Laplacian, CSR.
+
+    Unit grid spacing; Dirichlet rows keep the full diagonal 2*d so the
+    operator is the standard SPD finite-difference Laplacian.  Columns are
+    sorted ascending.  Used as an AMG test operator.
+    """
+    dims = tuple(int(d) for d in dims)
+    nd = len(dims)
+    if nd == 2:
+        dims = (dims[0], dims[1], 1)
+    nx, ny, nz = dims
+    n = nx * ny * nz
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    cols, vals = [], []
+    diag = 2.0 * nd
+    for iz in range(nz):
+        for iy in range(ny):
+            for ix in range(nx):
+                i = ix + nx * (iy + ny * iz)
+                row = []
+                if iz > 0:
+                    row.append((i - nx * ny, -1.0))
+                if iy > 0:
+                    row.append((i - nx, -1.0))
+                if ix > 0:
+                    row.append((i - 1, -1.0))
+                nb = sum(1 for _ in row)
+                row.append((i, 0.0))
+                if ix < nx - 1:
+                    row.append((i + 1, -1.0))
+                if iy < ny - 1:
+                    row.append((i + nx, -1.0))
+                if iz < nz - 1:
+                    row.append((i + nx * ny, -1.0))
+                nnb = len(row) - 1
+                d = diag if dirichlet else float(nnb)
+                row[nb] = (i, d)
+                for c, v in row:
+                    cols.append(c)
+                    vals.append(v)
+                rowptr[i + 1] = len(cols)
+    return (n, rowptr, np.asarray(cols, dtype=np.int32), np.asarray(vals, dtype=np.float64))

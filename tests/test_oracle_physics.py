@@ -1,0 +1,294 @@
+"""Pins of the oracle's TPFA residual, Jacobian and Schur approximation.
+
+Each test checks the oracle against something other than itself: invariants
+of the discretisation (flux telescoping, column sums), exact special cases,
+complex-step differentiation of the oracle's own residual, manufactured
+solutions with a known order of accuracy, and the block factorisation of
+Section 3.2 as a dense identity.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1902_00095_amd import synth
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def tiny(name="W2", dims=(4, 3, 3), g=0.0, wells=True, seed=7, props=None):
+    grid = synth.Grid(*dims, 1.0, 1.25, 0.8)
+    pr = props or synth.Props(g=g)
+    p = synth.make_problem(name, seed=seed, grid=grid, props=pr)
+    if not wells:
+        p.wells = []
+    return p
+
+
+def test_constants_match_paper_table():
+    vals = {}
+    for line in open("tests/golden/physical_constants.txt"):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, v, _ = line.split()
+        vals[k] = float(v)
+    pr = synth.Props()
+    assert pr.cv == vals["cv"] and pr.c_r == vals["c_r"]
+
+
+def test_uniform_state_zero_residual():
+    p = tiny(wells=False)
+    p.x_k[:] = p.x_prev
+    G = oracle.residual(p)
+    assert np.all(G == 0.0)
+
+
+@pytest.mark.parametrize("g", [0.0, 9.80665])
+def test_flux_telescoping(g):
+    """Interior fluxes cancel in the domain sums: sum_i G^m_i and sum_i G^e_i
+    do not depend on the permeability or conductivity (Section 2.2)."""
+    p = tiny(g=g)
+    G1 = oracle.residual(p)
+    q = dataclasses.replace(p, K=p.K * 37.0, kappa=p.kappa * 5.0)
+    G2 = oracle.residual(q)
+    scale_m = np.abs(G2[0::2]).sum()
+    scale_e = np.abs(G2[1::2]).sum()
+    assert abs(G1[0::2].sum() - G2[0::2].sum()) <= 1e-13 * scale_m
+    assert abs(G1[1::2].sum() - G2[1::2].sum()) <= 1e-13 * scale_e
+    # and fluxes do change the individual residuals
+    assert np.abs(G1 - G2).max() > 1e-3 * np.abs(G2).max()
+
+
+def test_hydrostatic_state_has_no_mass_flux():
+    """A column in hydrostatic equilibrium (dPhi = 0 on every vertical face)
+    carries no mass flux, so G^m is the accumulation term alone; with
+    x_prev = x_k that is zero."""
+    pr = synth.Props(g=9.80665)
+    grid = synth.Grid(3, 2, 6, 1.0, 1.0, 2.0)
+    p = synth.make_problem("W2", grid=grid, props=pr)
+    p.wells = []
+    n = grid.n
+    x = np.empty(2 * n)
+    x[1::2] = pr.T0
+    rho = lambda pp: pr.rho0 * np.exp(pr.c_p * (pp - pr.p0))
+    pcol = [pr.p0]
+    for iz in range(1, grid.nz):          # going up: p_hi = p_lo - rho_bar g dz
+        lo = pcol[-1]
+        hi = lo
+        for _ in range(60):               # fixed point on the implicit face density
+            hi = lo - 0.5 * (rho(lo) + rho(hi)) * pr.g * grid.dz
+        pcol.append(hi)
+    for iz in range(grid.nz):
+        for iy in range(grid.ny):
+            for ix in range(grid.nx):
+                x[2 * (ix + grid.nx * (iy + grid.ny * iz))] = pcol[iz]
+    p.x_prev[:] = x
+    p.x_k[:] = x
+    G = oracle.residual(p)
+    flux_scale = 1e-13 * 1e6 * 1e4       # Upsilon * lambda * |dp| of one face
+    assert np.abs(G[0::2]).max() <= 1e-9 * flux_scale
+
+
+def test_linear_pressure_equal_interior_fluxes():
+    """Constant rho, mu and K with a linear pressure field: every interior
+    x-face carries the same flux, so interior cells have zero mass residual."""
+    pr = synth.Props(c_p=0.0, c_T=0.0, mu_B=0.0)
+    grid = synth.Grid(6, 1, 1, 0.5, 1.0, 1.0)
+    p = synth.make_problem("W1", grid=grid, props=pr)
+    ix = np.arange(6)
+    p.x_k[0::2] = pr.p0 + 1000.0 * ix
+    p.x_k[1::2] = pr.T0
+    p.x_prev[:] = p.x_k
+    G = oracle.residual(p)
+    face = 1e-13 * (1.0 / 0.5) * (1000.0 / 1e-3) * 1000.0
+    assert np.abs(G[2:-2:2]).max() <= 1e-12 * face
+    assert abs(G[0] + face) <= 1e-12 * face and abs(G[-2] - face) <= 1e-12 * face
+
+
+def _complex_step_jacobian(p, h=1e-30):
+    n = p.grid.n
+    Jc = np.zeros((2 * n, 2 * n))
+    for k in range(2 * n):
+        xc = p.x_k.astype(np.complex128)
+        step = h * max(1.0, abs(p.x_k[k]))
+        xc[k] += 1j * step
+        Jc[:, k] = oracle.residual_complex(p, xc).imag / step
+    return Jc
+
+
+@pytest.mark.parametrize("g", [0.0, 9.80665])
+def test_jacobian_matches_complex_step(g):
+    """eq. AXR blocks equal the complex-step derivative of the oracle's own
+    residual (upwind decided on real parts = frozen upwind)."""
+    p = tiny(g=g, dims=(3, 3, 2))
+    J = oracle.jacobian(p)
+    Jd = J.dense()
+    Jc = _complex_step_jacobian(p)
+    n = p.grid.n
+    for r0, c0 in [(0, 0), (0, 1), (1, 0), (1, 1)]:
+        a = Jd[r0::2, c0::2]
+        b = Jc[r0::2, c0::2]
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max() + 1e-300, (r0, c0)
+    # central differences as a second, independent check
+    k = 2 * (n // 2)
+    hstep = 1.0
+    xp, xm = p.x_k.copy(), p.x_k.copy()
+    xp[k] += hstep
+    xm[k] -= hstep
+    fd = (oracle.residual(p, xp) - oracle.residual(p, xm)) / (2 * hstep)
+    assert np.abs(fd - Jd[:, k]).max() <= 1e-5 * np.abs(Jd[:, k]).max()
+
+
+def test_jacobian_column_sums_independent_of_transmissibility():
+    """Fluxes sum to zero in a column (Section 3.1): the column sums of all
+    four blocks and of the Schur approximation do not depend on K or kappa."""
+    p = tiny()
+    J1 = oracle.jacobian(p)
+    q = dataclasses.replace(p, K=p.K * 13.0, kappa=p.kappa * 3.0)
+    J2 = oracle.jacobian(q)
+    for name in ["pp", "pT", "Tp", "TT", "S"]:
+        c1 = np.asarray(J1.block(name).sum(axis=0)).ravel()
+        c2 = np.asarray(J2.block(name).sum(axis=0)).ravel()
+        scale = abs(J2.block(name)).max()
+        assert np.abs(c1 - c2).max() <= 1e-11 * scale, name
+
+
+def test_schur_equals_ATT_for_constant_properties():
+    """With constant rho and mu, A_pT = 0 and the paper's approximation is
+    exact: S~_T = A_TT = S (Section 3.3, eq. Se)."""
+    pr = synth.Props(c_p=0.0, c_T=0.0, mu_B=0.0)
+    p = tiny(props=pr)
+    J = oracle.jacobian(p)
+    assert np.all(J.pT == 0.0)
+    np.testing.assert_array_equal(J.S, J.TT)
+
+
+def test_schur_approximation_structure():
+    """S~_T is a Z-matrix (off-diagonals <= 0); with zero flux it is the
+    symmetric conduction + accumulation operator."""
+    p = tiny()
+    J = oracle.jacobian(p)
+    S = J.block("S").toarray()
+    off = S - np.diag(np.diag(S))
+    assert off.max() <= 0.0
+    q = tiny(g=0.0)
+    q.x_k[0::2] = q.props.p0
+    q.wells = []
+    Sq = oracle.jacobian(q).block("S").toarray()
+    np.testing.assert_allclose(Sq, Sq.T, rtol=0, atol=1e-13 * np.abs(Sq).max())
+
+
+def test_schur_approximation_beats_simple_forms():
+    """The condition number of S~_T^{-1} S is far below that of A_TT^{-1} S,
+    qualitatively as in the paper's condition-number table."""
+    p = tiny(dims=(6, 6, 3), seed=11)
+    J = oracle.jacobian(p)
+    App, ApT, ATp, ATT, St = (J.block(k).toarray() for k in ["pp", "pT", "Tp", "TT", "S"])
+    S = ATT - ATp @ np.linalg.solve(App, ApT)
+    k_T = np.linalg.cond(np.linalg.solve(St, S))
+    k_A = np.linalg.cond(np.linalg.solve(ATT, S))
+    assert k_T < k_A
+
+
+def test_block_factorisation_identity():
+    """eq. Afact and eq. Ainv as dense identities on the oracle Jacobian."""
+    p = tiny(dims=(3, 3, 2))
+    J = oracle.jacobian(p)
+    App, ApT, ATp, ATT = (J.block(k).toarray() for k in ["pp", "pT", "Tp", "TT"])
+    n = App.shape[0]
+    I, Z = np.eye(n), np.zeros((n, n))
+    S = ATT - ATp @ np.linalg.solve(App, ApT)
+    L = np.block([[I, Z], [ATp @ np.linalg.inv(App), I]])
+    D = np.block([[App, Z], [Z, S]])
+    U = np.block([[I, np.linalg.solve(App, ApT)], [Z, I]])
+    A = np.block([[App, ApT], [ATp, ATT]])
+    np.testing.assert_allclose(L @ D @ U, A, rtol=0, atol=1e-9 * np.abs(A).max())
+    Ainv = (np.block([[I, -np.linalg.solve(App, ApT)], [Z, I]])
+            @ np.block([[np.linalg.inv(App), Z], [Z, np.linalg.inv(S)]])
+            @ np.block([[I, Z], [-ATp @ np.linalg.inv(App), I]]))
+    # A spans ten decades of scale, so compare against a direct inverse
+    Ad = np.linalg.inv(A)
+    np.testing.assert_allclose(Ainv, Ad, rtol=0, atol=1e-6 * np.abs(Ad).max())
+
+
+def _manufactured_order(kind):
+    """Observed order of the TPFA operator against -div(c grad u) for
+    u = cos(pi x / L) cos(pi y / L) cos(pi z / L) (zero normal derivative on
+    the box, so the no-flow boundary is exact)."""
+    errs, hs = [], []
+    L = 1.0
+    for m in (8, 16, 32):
+        h = L / m
+        grid = synth.Grid(m, m, m // 4, h, h, h)
+        Lz = grid.nz * h
+        pr = synth.Props(c_p=0.0, c_T=0.0, mu_B=0.0)
+        p = synth.make_problem("W1", grid=grid, props=pr)
+        p.wells = []
+        n = grid.n
+        i = np.arange(n)
+        x = (i % m + 0.5) * h
+        y = ((i // m) % m + 0.5) * h
+        z = (i // (m * m) + 0.5) * h
+        u = np.cos(np.pi * x / L) * np.cos(np.pi * y / L) * np.cos(np.pi * z / Lz)
+        lap = -(np.pi ** 2) * (2 / L ** 2 + 1 / Lz ** 2) * u
+        if kind == "heat":
+            p.x_k[0::2] = pr.p0
+            p.x_k[1::2] = pr.T0 + u
+            p.x_prev[:] = p.x_k
+            G = oracle.residual(p)[1::2] / grid.dx ** 3
+            exact = -p.kappa[0] * lap
+        else:
+            p.x_k[0::2] = pr.p0 + 1e3 * u
+            p.x_k[1::2] = pr.T0
+            p.x_prev[:] = p.x_k
+            G = oracle.residual(p)[0::2] / grid.dx ** 3
+            exact = -p.K[0] * (pr.rho0 / pr.mu0) * 1e3 * lap
+        errs.append(np.sqrt(np.mean((G - exact) ** 2)) / np.sqrt(np.mean(exact ** 2)))
+        hs.append(h)
+    orders = [np.log(errs[k] / errs[k + 1]) / np.log(hs[k] / hs[k + 1]) for k in range(2)]
+    return orders
+
+
+@pytest.mark.parametrize("kind", ["heat", "pressure"])
+def test_manufactured_solution_second_order(kind):
+    orders = _manufactured_order(kind)
+    assert min(orders) >= 1.9, orders
+
+
+def test_advective_energy_flux_upwinds_temperature():
+    """Constant properties, no conduction, linear pressure rising in +x: flow
+    runs towards -x, so each face carries c_v T_{i+1} F.  A quadratic
+    temperature separates the upwind from the downwind choice; the ratio to
+    the boundary mass flux exposes the specific heat."""
+    pr = synth.Props(c_p=0.0, c_T=0.0, mu_B=0.0)
+    grid = synth.Grid(7, 1, 1, 1.0, 1.0, 1.0)
+    p = synth.make_problem("W1", grid=grid, props=pr, kappa=0.0)
+    ix = np.arange(7)
+    p.x_k[0::2] = pr.p0 + 500.0 * ix
+    p.x_k[1::2] = pr.T0 + ix.astype(float) ** 2
+    p.x_prev[:] = p.x_k
+    G = oracle.residual(p)
+    f = G[-2]                       # mass leaving the last cell through its one face
+    assert f > 0
+    T = p.x_k[1::2]
+    for i in range(1, 6):
+        expect = -pr.cv * f * (T[i + 1] - T[i])
+        assert abs(G[2 * i + 1] - expect) <= 1e-12 * abs(expect)
+
+
+def test_well_terms_signs_and_enthalpy():
+    """An injector adds mass (negative residual) carrying c_v T_inj per unit
+    mass; a producer removes mass carrying c_v T_i (eq. f, eq. fT)."""
+    grid = synth.Grid(3, 3, 1, 1.0, 1.0, 1.0)
+    p = synth.make_problem("W2", grid=grid)
+    p.x_k[:] = p.x_prev
+    p.x_k[1::2] = 360.0
+    p.x_prev[:] = p.x_k
+    G = oracle.residual(p)
+    inj, prod = p.wells
+    assert G[2 * inj.cell] < 0 and G[2 * prod.cell] > 0
+    assert abs(G[2 * inj.cell + 1] / G[2 * inj.cell] - p.props.cv * inj.T_inj) <= 1e-12 * p.props.cv * inj.T_inj
+    assert abs(G[2 * prod.cell + 1] / G[2 * prod.cell] - p.props.cv * 360.0) <= 1e-12 * p.props.cv * 360
+    others = [i for i in range(grid.n) if i not in (inj.cell, prod.cell)]
+    assert np.all(G[2 * np.array(others)] == 0.0)

@@ -1,0 +1,39 @@
+"""The seeded input generator: determinism and the stated field statistics."""
+import numpy as np
+
+from paper_1902_00095_amd import synth
+
+
+def test_deterministic():
+    a = synth.make_problem("W2", grid=synth.Grid(16, 16, 8, 1, 1, 1))
+    b = synth.make_problem("W2", grid=synth.Grid(16, 16, 8, 1, 1, 1))
+    for k in ("K", "phi", "x_k"):
+        assert np.array_equal(getattr(a, k), getattr(b, k))
+    c = synth.make_problem("W2", seed=99, grid=synth.Grid(16, 16, 8, 1, 1, 1))
+    assert not np.array_equal(a.K, c.K)
+
+
+def test_layered_field_statistics():
+    p = synth.make_problem("W2")
+    logk = np.log10(p.K).reshape(p.grid.nz, -1)
+    assert logk.min() >= -15 - 1e-12 and logk.max() <= -11 + 1e-12
+    spread = logk.max(axis=1) - logk.min(axis=1)
+    assert np.all(spread <= 0.4 + 1e-9)          # +-0.2 jitter within a layer
+    assert np.std(logk.mean(axis=1)) > 0.5       # layer means ~ N(-13, 1)
+    assert p.phi.min() >= 0.1 and p.phi.max() <= 0.3
+    assert np.corrcoef(np.log10(p.K), p.phi)[0, 1] > 0.9
+
+
+def test_channel_field():
+    p = synth.make_problem("W4", grid=synth.Grid(48, 48, 48, 1, 1, 1))
+    frac = np.mean(p.K > 1e-12)
+    assert 0.005 < frac < 0.3
+    assert set(np.unique(p.K)) <= {1e-15, 1e-11}
+    assert p.wells[0].T_inj == 550.0
+
+
+def test_perturbation_statistics():
+    p = synth.make_problem("W2")
+    dp = p.x_k[0::2] - p.x_prev[0::2]
+    dT = p.x_k[1::2] - p.x_prev[1::2]
+    assert abs(np.std(dp) / 1e5 - 1) < 0.02 and abs(np.std(dT) / 5 - 1) < 0.02
