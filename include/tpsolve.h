@@ -1,0 +1,199 @@
+/*
+ * tpsolve.h -- C ABI of the MI355X (gfx950) coupled pressure-temperature
+ * solver: the block-preconditioned Krylov solve of the Jacobian of
+ * non-isothermal single-phase porous-media flow (Roy, Jonsthovel, Lemon &
+ * Wathen, "A block preconditioner for non-isothermal flow in porous media",
+ * J. Comput. Phys. preprint 2019).
+ *
+ * Conventions for every call
+ *   - Pointers named as device arrays are HIP device pointers owned by the
+ *     caller; the library never frees them.  Host pointers are marked "host".
+ *   - Every call is ordered on the HIP stream passed as `stream` (NULL = the
+ *     null stream).  Calls that return sizes or statistics to the host
+ *     synchronise that stream before returning.
+ *   - Return value: TP_OK (0); a negative hard error; TP_NOT_CONVERGED (1),
+ *     a soft status whose outputs are usable.  tp_last_error() gives a
+ *     thread-local message for the last nonzero status.  No C++ exception
+ *     crosses this interface.
+ *   - Vectors at this interface are interleaved cell by cell:
+ *     [p_0, T_0, p_1, T_1, ...], the ordering of the unknowns of Section 3.
+ *   - Indices are int32; all floating point at this interface is FP64.
+ *   - Handles (tp_amg_t, tp_prec_t) own device memory obtained from the
+ *     allocator registered with tp_init (default: the HIP stream-ordered
+ *     pool).  A handle is used by one stream at a time.
+ */
+#ifndef TPSOLVE_H
+#define TPSOLVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    TP_OK = 0,
+    TP_ERR_ARG = -1,      /* null pointer, size mismatch, parameter out of range */
+    TP_ERR_HIP = -2,      /* a HIP runtime call failed (message names it) */
+    TP_ERR_OOM = -3,      /* device allocation failed */
+    TP_ERR_NUMERIC = -4,  /* zero pivot, non-finite values, stalled coarsening */
+    TP_ERR_CAPACITY = -5, /* a fixed-capacity structure overflowed (message says which) */
+    TP_NOT_CONVERGED = 1  /* Krylov limit reached; x holds the last iterate */
+};
+
+const char* tp_last_error(void);
+
+/* Device memory provider.  alloc(bytes, stream, ctx) returns device memory
+ * or NULL; free(ptr, stream, ctx) returns it.  Memory must stay valid until
+ * freed (stream-ordered reuse is allowed). */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* stream, void* ctx);
+    void (*free)(void* ptr, void* stream, void* ctx);
+    void* ctx;
+} tp_allocator;
+
+/* Select the device and, optionally, an allocator (NULL: HIP stream-ordered
+ * pool).  Must be called once before any other call; may be called again to
+ * switch allocators when no handle is alive. */
+int tp_init(const tp_allocator* alloc, int device);
+
+/* ---------------------------------------------------------------------------
+ * Discretisation (Section 2.2): two-point flux finite volumes on a uniform
+ * Cartesian grid, backward Euler, residual forms F_m and F_e (eq. Fm, Fe),
+ * Jacobian blocks of eq. AXR and the Schur approximation of eq. Se.
+ * ------------------------------------------------------------------------ */
+typedef struct { int32_t nx, ny, nz; double dx, dy, dz; } tp_grid;  /* cell i = ix + nx (iy + ny iz) */
+
+/* rho = rho0 exp(c_p (p - p0) + c_T (T - T0)); mu = mu0 exp(mu_B (1/T - 1/T0));
+ * cv, c_r specific heats of fluid and rock; rho_r rock density; g gravity
+ * along -z (0 disables). SI units. */
+typedef struct { double rho0, p0, T0, c_p, c_T, mu0, mu_B, cv, rho_r, c_r, g; } tp_props;
+
+/* Constant-rate point well (eq. f, eq. fT): kind 0 injector (mass
+ * rate*rho(p, T_inj), enthalpy c_v T_inj), kind 1 producer (mass
+ * rate*rho(p, T), enthalpy c_v T). rate >= 0 in m^3/s. */
+typedef struct { int32_t cell; int32_t kind; double rate, T_inj; } tp_well;
+#define TP_MAX_WELLS 32
+
+/* Jacobian storage: one CSR pattern (sorted columns, full 5/7-point stencil
+ * including structural zeros) shared by A_pp, A_pT, A_Tp, A_TT and the Schur
+ * approximation S.  All arrays are caller-owned device memory sized by
+ * tp_jacobian_sizes. */
+typedef struct {
+    int32_t n, nnz;
+    int32_t *rowptr, *col;            /* n+1, nnz */
+    double *pp, *pT, *Tp, *TT, *S;    /* nnz each */
+} tp_jacobian;
+
+/* n = nx*ny*nz cells and nnz of the stencil pattern. TP_ERR_ARG if any
+ * dimension < 1 or nnz would exceed 2^31-1. */
+int tp_jacobian_sizes(const tp_grid* grid, int32_t* n, int32_t* nnz);
+
+/* Assemble G(x_k) (eq. Fm, Fe; 2n interleaved, device) and J = dG/dx at
+ * x_k (eq. AXR ... eq. rhouT, upwind choice frozen) plus S (eq. Se with the
+ * specific heat on the advective term).  K, phi, kappa: n device arrays;
+ * x_prev, x_k: 2n device arrays; wells: host array of nwells <= TP_MAX_WELLS.
+ * Homogeneous no-flow boundaries.  Errors: TP_ERR_ARG on null pointers,
+ * J->n/nnz not matching the grid, a well cell out of range, rate < 0 or
+ * dt <= 0. */
+int assemble_tpfa(const tp_grid* grid, const tp_props* props, const double* K,
+                  const double* phi, const double* kappa, int32_t nwells,
+                  const tp_well* wells, double dt, const double* x_prev,
+                  const double* x_k, tp_jacobian* J, double* G, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Algebraic multigrid (Section 3: A_pp and the Schur approximation are each
+ * applied by one AMG V-cycle).  Strength theta, seeded PMIS coarsening with
+ * key (|S^T_i|, splitmix64(seed ^ level<<40 ^ i), i), direct interpolation,
+ * Galerkin or Petrov-Galerkin coarse operators R (A P), smoother, dense LU on
+ * the coarsest level.  The setup runs in FP64; `storage` only selects how the
+ * hierarchy is stored and applied.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    double theta;          /* strength threshold, (0,1); 0.25 */
+    uint64_t seed;         /* PMIS hash seed */
+    int32_t max_levels;    /* 1..25 */
+    int32_t coarse_max;    /* stop when n_l <= coarse_max (<= 4096); 256 */
+    int32_t smoother;      /* 0 l1-Jacobi, 1 Chebyshev on D_l1^{-1} A over [cheb_lo, 1] */
+    int32_t cheb_degree;   /* 1..8; 3 */
+    double cheb_lo;        /* (0,1); 0.3 */
+    double omega;          /* l1-Jacobi weight; 1.0 */
+    int32_t nu_pre, nu_post; /* sweeps; 1, 1 */
+    int32_t restriction;   /* 0 R = P^T; 1 R = Q^T, Q direct interpolation of A^T */
+    int32_t storage;       /* 0 FP64; 1 FP32 (values and V-cycle vectors) */
+} tp_amg_params;
+
+typedef struct tp_amg* tp_amg_t;
+
+/* Build the hierarchy of the n x n CSR matrix (device arrays, sorted
+ * columns, diagonal present in every row).  Synchronises `stream`.
+ * Errors: TP_ERR_ARG (bad sizes/params), TP_ERR_NUMERIC (zero pivot in the
+ * coarsest LU, coarsening stalled above 4096 rows), TP_ERR_CAPACITY (a
+ * product row exceeded the on-chip hash table), TP_ERR_OOM. */
+int amg_setup(int32_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+              const tp_amg_params* params, tp_amg_t* out, void* stream);
+
+int amg_num_levels(tp_amg_t amg, int32_t* nlev);
+/* sizes of level l (P/R sizes are 0 on the coarsest level) */
+int amg_level_info(tp_amg_t amg, int32_t level, int32_t* n, int32_t* nnzA,
+                   int32_t* nnzP, int32_t* nnzR);
+/* Copy level arrays into caller device buffers (any pointer may be NULL;
+ * sizes from amg_level_info; cf: 1 = C point, 0 = F point).  FP64 values of
+ * the setup.  Stream-ordered; does not synchronise. */
+int amg_level_copy(tp_amg_t amg, int32_t level, int32_t* A_rowptr, int32_t* A_col,
+                   double* A_val, int32_t* cf, int32_t* P_rowptr, int32_t* P_col,
+                   double* P_val, int32_t* R_rowptr, int32_t* R_col, double* R_val,
+                   void* stream);
+/* x = V(b): one V(nu_pre, nu_post)-cycle from a zero guess (device, n). */
+int amg_vcycle(tp_amg_t amg, const double* b, double* x, void* stream);
+int amg_destroy(tp_amg_t amg);
+
+/* ---------------------------------------------------------------------------
+ * Block preconditioner (Section 3.2, the five-step application list).
+ * variant 0 lower (steps 1-3, default), 1 upper, 2 full (steps 1-5, step 4
+ * read as b_p - A_pT d_T).  Borrows J and both hierarchies: they must
+ * outlive the handle.
+ * ------------------------------------------------------------------------ */
+typedef struct tp_prec* tp_prec_t;
+int precond_create(const tp_jacobian* J, tp_amg_t amg_pp, tp_amg_t amg_S,
+                   int32_t variant, tp_prec_t* out);
+/* z = M^{-1} r, 2n interleaved device vectors */
+int precond_apply(tp_prec_t M, const double* r, double* z, void* stream);
+int precond_destroy(tp_prec_t M);
+
+/* ---------------------------------------------------------------------------
+ * Flexible GMRES (right preconditioned, restarted; Section 4: GMRES with
+ * restart 30) with classical Gram-Schmidt applied twice, Givens rotations on
+ * the Hessenberg matrix, all in FP64 on the device.  Stops when the true
+ * relative residual ||b - J x||_2 / ||b||_2 <= rtol (checked in FP64 at the
+ * end of every cycle) or after maxit iterations.
+ * ------------------------------------------------------------------------ */
+typedef struct { double rtol; int32_t restart; int32_t maxit; } tp_krylov_params;
+typedef struct {
+    int32_t iters, restarts;
+    double rel_true, rel_est;
+} tp_krylov_stats;
+
+/* Solve J x = b (2n interleaved device vectors; x holds the initial guess on
+ * entry).  history: optional host array of maxit+1 relative residual
+ * estimates.  Synchronises `stream`.  Returns TP_OK or TP_NOT_CONVERGED;
+ * TP_ERR_NUMERIC on a non-finite residual. */
+int fgmres_solve(const tp_jacobian* J, tp_prec_t M, const double* b, double* x,
+                 const tp_krylov_params* params, tp_krylov_stats* stats,
+                 double* history, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Measurement support: HIP-event timing of the fine-level smoother kernel
+ * (the V-cycle's dominant kernel) on the stream it is launched on.
+ * ------------------------------------------------------------------------ */
+/* enable (1) / disable (0) and reset the counters */
+int tp_timer_enable(int32_t on);
+/* totals since the last enable: launches, summed kernel milliseconds and
+ * algorithmic bytes (matrix values, indices and vectors each counted once) */
+int tp_timer_read(int64_t* launches, double* ms, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

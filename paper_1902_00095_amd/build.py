@@ -1,0 +1,37 @@
+"""Build the tpsolve HIP library for gfx950 (in-tree shared object)."""
+from __future__ import annotations
+
+import glob
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIB = os.path.join(HERE, "libtpsolve.so")
+
+# -ffp-contract=off keeps the setup arithmetic in the order written (no fused
+# multiply-add), so AMG setup values follow one canonical rounding sequence;
+# packed-fp32 instructions are disabled (see DESIGN notes on the toolchain).
+HIPCC_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+               "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               "-Wall", "-Wno-unused-result"]
+
+
+def sources():
+    return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
+
+
+def build(verbose: bool = False) -> str:
+    tmp = LIB + f".tmp{os.getpid()}"
+    cmd = (["/opt/rocm/bin/hipcc"] + HIPCC_FLAGS
+           + ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+           + sources() + ["-o", tmp])
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

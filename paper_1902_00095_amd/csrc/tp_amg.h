@@ -1,0 +1,45 @@
+// tp_amg.h -- AMG hierarchy object shared by the setup, the V-cycle and the
+// block preconditioner.
+#pragma once
+
+#include "tp_internal.h"
+
+namespace tp {
+
+struct Csr {
+    int32_t n = 0, m = 0, nnz = 0;  // n rows, m columns
+    DBuf<int32_t> rowptr, col;
+    DBuf<double> val;
+};
+
+// Lanes cooperating on one CSR row in the row-group SpMV kernels.
+int lanes_for(int32_t n, int64_t nnz);
+
+struct Level {
+    Csr A, P, R;          // FP64 setup results (P, R empty on the coarsest level)
+    DBuf<int32_t> cf;     // 1 C, 0 F
+    DBuf<double> dinv;    // 1 / sum_j |a_ij|
+    DBuf<float> A32, P32, R32, dinv32;  // storage == 1 copies
+    int gA = 1, gP = 1, gR = 1;
+    // V-cycle work vectors (element type follows the storage)
+    DBuf<char> b, x, x2, r, d;
+};
+
+}  // namespace tp
+
+struct tp_amg {
+    tp_amg_params prm;
+    std::vector<tp::Level> lev;  // lev.back() is the coarsest level
+    int32_t nc = 0;              // coarsest size
+    tp::DBuf<double> cinv;       // nc x nc inverse of the coarsest operator
+    hipStream_t stream = nullptr;
+};
+
+namespace tp {
+// Run one V-cycle on the level-0 right-hand side already placed in lev[0].b
+// (or at `b_ext` when non-null, same element type as the storage).  Returns
+// a device pointer to the level-0 solution (element type of the storage).
+const void* vcycle_run(tp_amg* h, const void* b_ext, hipStream_t s);
+// element size of the hierarchy's storage
+inline size_t storage_bytes(const tp_amg* h) { return h->prm.storage == 1 ? 4 : 8; }
+}  // namespace tp

@@ -1,0 +1,744 @@
+// tp_amg_setup.hip -- AMG hierarchy construction on the GPU, FP64.
+//
+// The paper applies A_pp^{-1} and the inverse of its Schur approximation by
+// one AMG V-cycle each (Section 3.2, Section 4).  The components:
+//   strength      j in S_i iff j != i, m_i > 0 and -s_i a_ij >= theta m_i,
+//                 s_i = sign(a_ii), m_i = max_{k != i} -s_i a_ik;
+//   coarsening    PMIS (De Sterck, Yang & Heys, SIMAX 2006): measure
+//                 lambda_i = |S^T_i|, key (lambda_i, splitmix64(seed ^
+//                 level << 40 ^ i), i) compared lexicographically; each round
+//                 selects, from a snapshot, the undecided points whose key
+//                 beats every undecided strong neighbour (S_i u S^T_i), then
+//                 marks undecided points depending on a C point as F;
+//   interpolation direct interpolation (Stueben 2001) with same-sign
+//                 couplings lumped into the diagonal;
+//   restriction   R = P^T, or R = Q^T with Q the direct interpolation of A^T
+//                 on the same C/F split (Petrov-Galerkin);
+//   coarse op.    A_c = R (A P), each entry summed in ascending inner index;
+//   coarsest      dense LU with partial pivoting, kept as an explicit inverse.
+// PMIS decisions are integer comparisons, so the C/F split is exact on any
+// hardware.  Floating-point steps are written in one fixed operation order
+// and compiled without contraction, so the hierarchy values follow a single
+// rounding sequence.  There are no floating-point atomics.
+#include "tp_amg.h"
+
+#include <algorithm>
+
+namespace tp {
+
+constexpr int B = 256;
+
+int lanes_for(int32_t n, int64_t nnz) {
+    double avg = n > 0 ? (double)nnz / n : 1.0;
+    int g = 1;
+    while (g < avg && g < 64) g <<= 1;
+    return g;
+}
+
+// ---- strength ------------------------------------------------------------------
+__device__ inline void row_sign_max(const int32_t* rowptr, const int32_t* col, const double* val,
+                                    int32_t i, double* s_out, double* m_out) {
+    double aii = 0.0;
+    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q)
+        if (col[q] == i) aii = val[q];
+    double s = aii < 0.0 ? -1.0 : 1.0;
+    double m = 0.0;
+    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q)
+        if (col[q] != i && -s * val[q] > m) m = -s * val[q];
+    *s_out = s;
+    *m_out = m;
+}
+
+__global__ void __launch_bounds__(B)
+k_strength(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+           const double* __restrict__ val, double theta, int32_t* __restrict__ cnt,
+           const int32_t* __restrict__ Srowptr, int32_t* __restrict__ Scol) {
+    int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n) return;
+    double s, m;
+    row_sign_max(rowptr, col, val, i, &s, &m);
+    int32_t c = 0;
+    int32_t out = Scol ? Srowptr[i] : 0;
+    if (m > 0.0) {
+        for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+            if (col[q] != i && -s * val[q] >= theta * m) {
+                if (Scol) Scol[out + c] = col[q];
+                ++c;
+            }
+        }
+    }
+    if (cnt) cnt[i] = c;
+}
+
+// ---- transpose ------------------------------------------------------------------
+__global__ void __launch_bounds__(B)
+k_fill_i32(int32_t* __restrict__ a, int32_t v, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * B + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+__global__ void __launch_bounds__(B)
+k_col_count(int64_t nnz, const int32_t* __restrict__ col, int32_t* __restrict__ cnt) {
+    int64_t k = (int64_t)blockIdx.x * B + threadIdx.x;
+    if (k < nnz) atomicAdd(&cnt[col[k]], 1);
+}
+
+__global__ void __launch_bounds__(B)
+k_transpose_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                 const double* __restrict__ val, int32_t* __restrict__ cursor,
+                 int32_t* __restrict__ Tcol, double* __restrict__ Tval) {
+    int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n) return;
+    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+        int32_t pos = atomicAdd(&cursor[col[q]], 1);
+        Tcol[pos] = i;
+        if (Tval) Tval[pos] = val[q];
+    }
+}
+
+// sort each row by column (insertion sort; rows are short)
+__global__ void __launch_bounds__(B)
+k_sort_rows(int32_t n, const int32_t* __restrict__ rowptr, int32_t* __restrict__ col,
+            double* __restrict__ val) {
+    int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n) return;
+    int32_t a = rowptr[i], e = rowptr[i + 1];
+    for (int32_t u = a + 1; u < e; ++u) {
+        int32_t c = col[u];
+        double v = val ? val[u] : 0.0;
+        int32_t w = u - 1;
+        while (w >= a && col[w] > c) {
+            col[w + 1] = col[w];
+            if (val) val[w + 1] = val[w];
+            --w;
+        }
+        col[w + 1] = c;
+        if (val) val[w + 1] = v;
+    }
+}
+
+// T = A^T (m rows); values optional; rows sorted when `sorted`
+static void transpose(const int32_t* rowptr, const int32_t* col, const double* val, int32_t n,
+                      int32_t m, int32_t nnz, bool sorted, Csr& T, hipStream_t s) {
+    T.n = m;
+    T.m = n;
+    T.nnz = nnz;
+    T.rowptr.alloc(m + 1, s);
+    T.col.alloc(nnz, s);
+    if (val) T.val.alloc(nnz, s);
+    DBuf<int32_t> cursor(m + 1, s);
+    TP_LAUNCH(k_fill_i32, cdiv(m + 1, B), B, 0, s, T.rowptr.p, 0, (int64_t)m + 1);
+    if (nnz > 0) TP_LAUNCH(k_col_count, cdiv(nnz, B), B, 0, s, (int64_t)nnz, col, T.rowptr.p);
+    scan_exclusive(T.rowptr.p, T.rowptr.p, m, s);
+    TP_HIP(hipMemcpyAsync(cursor.p, T.rowptr.p, sizeof(int32_t) * (m + 1), hipMemcpyDeviceToDevice, s));
+    if (n > 0) TP_LAUNCH(k_transpose_fill, cdiv(n, B), B, 0, s, n, rowptr, col, val, cursor.p, T.col.p,
+                         val ? T.val.p : nullptr);
+    if (sorted && m > 0)
+        TP_LAUNCH(k_sort_rows, cdiv(m, B), B, 0, s, m, T.rowptr.p, T.col.p, val ? T.val.p : nullptr);
+}
+
+// ---- PMIS -------------------------------------------------------------------------
+__device__ inline uint64_t splitmix64(uint64_t x) {
+    // SplitMix64 (Steele, Lea & Flood 2014): golden-gamma increment, then the
+    // variant-13 finaliser.
+    uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+__device__ inline bool key_gt(int32_t li, uint64_t hi, int32_t i, int32_t lj, uint64_t hj, int32_t j) {
+    if (li != lj) return li > lj;
+    if (hi != hj) return hi > hj;
+    return i > j;
+}
+
+__global__ void __launch_bounds__(B)
+k_pmis_init(int32_t n, const int32_t* __restrict__ STrowptr, int8_t* __restrict__ st) {
+    int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n) return;
+    st[i] = (STrowptr[i + 1] - STrowptr[i]) == 0 ? (int8_t)-1 : (int8_t)0;
+}
+
+__global__ void __launch_bounds__(B)
+k_pmis_select(int32_t n, uint64_t hseed, const int32_t* __restrict__ Srp, const int32_t* __restrict__ Sc,
+              const int32_t* __restrict__ STrp, const int32_t* __restrict__ STc,
+              const int8_t* __restrict__ old, int8_t* __restrict__ nxt) {
+    int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n) return;
+    int8_t o = old[i];
+    if (o != 0) { nxt[i] = o; return; }
+    int32_t li = STrp[i + 1] - STrp[i];
+    uint64_t hi = splitmix64(hseed ^ (uint64_t)i);
+    bool isC = true;
+    for (int32_t q = Srp[i]; q < Srp[i + 1] && isC; ++q) {
+        int32_t j = Sc[q];
+        if (old[j] == 0) {
+            int32_t lj = STrp[j + 1] - STrp[j];
+            if (!key_gt(li, hi, i, lj, splitmix64(hseed ^ (uint64_t)j), j)) isC = false;
+        }
+    }
+    for (int32_t q = STrp[i]; q < STrp[i + 1] && isC; ++q) {
+        int32_t j = STc[q];
+        if (old[j] == 0) {
+            int32_t lj = STrp[j + 1] - STrp[j];
+            if (!key_gt(li, hi, i, lj, splitmix64(hseed ^ (uint64_t)j), j)) isC = false;
+        }
+    }
+    nxt[i] = isC ? (int8_t)1 : (int8_t)0;
+}
+
+// undecided points with a strong C dependence become F; count the rest
+__global__ void __launch_bounds__(B)
+k_pmis_fmark(int32_t n, const int32_t* __restrict__ Srp, const int32_t* __restrict__ Sc,
+             int8_t* st, int32_t* __restrict__ undecided) {
+    int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n) return;
+    if (st[i] != 0) return;
+    for (int32_t q = Srp[i]; q < Srp[i + 1]; ++q)
+        if (st[Sc[q]] == 1) { st[i] = -1; return; }
+    atomicAdd(undecided, 1);
+}
+
+__global__ void __launch_bounds__(B)
+k_cf_flags(int32_t n, const int8_t* __restrict__ st, int32_t* __restrict__ cf) {
+    int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i < n) cf[i] = st[i] == 1 ? 1 : 0;
+}
+
+// ---- direct interpolation -------------------------------------------------------------
+__global__ void __launch_bounds__(B)
+k_interp_count(int32_t n, const int32_t* __restrict__ Srp, const int32_t* __restrict__ Sc,
+               const int32_t* __restrict__ cf, int32_t* __restrict__ cnt) {
+    int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n) return;
+    if (cf[i]) { cnt[i] = 1; return; }
+    int32_t c = 0;
+    for (int32_t q = Srp[i]; q < Srp[i + 1]; ++q) c += cf[Sc[q]];
+    cnt[i] = c;
+}
+
+__global__ void __launch_bounds__(B)
+k_interp_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+              const double* __restrict__ val, const int32_t* __restrict__ Srp,
+              const int32_t* __restrict__ Sc, const int32_t* __restrict__ cf,
+              const int32_t* __restrict__ cmap, const int32_t* __restrict__ Prp,
+              int32_t* __restrict__ Pc, double* __restrict__ Pv) {
+    int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n) return;
+    int32_t q = Prp[i];
+    if (cf[i]) { Pc[q] = cmap[i]; Pv[q] = 1.0; return; }
+    if (Prp[i + 1] == q) return;  // no strong C neighbour: empty row
+    double aii = 0.0;
+    for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+        if (col[k] == i) aii = val[k];
+    double s = aii < 0.0 ? -1.0 : 1.0;
+    double sum_all = 0.0, lump = 0.0;
+    for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+        if (col[k] == i) continue;
+        double a = val[k];
+        if (s * a < 0.0) sum_all += a;
+        else lump += a;
+    }
+    double sum_p = 0.0;
+    int32_t k2 = Srp[i];
+    const int32_t se = Srp[i + 1];
+    for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+        int32_t j = col[k];
+        while (k2 < se && Sc[k2] < j) ++k2;
+        if (k2 < se && Sc[k2] == j && cf[j]) sum_p += val[k];
+    }
+    double alpha = sum_all / sum_p;
+    double dtil = aii + lump;
+    k2 = Srp[i];
+    for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+        int32_t j = col[k];
+        while (k2 < se && Sc[k2] < j) ++k2;
+        if (k2 < se && Sc[k2] == j && cf[j]) {
+            Pc[q] = cmap[j];
+            Pv[q] = -(alpha * val[k]) / dtil;
+            ++q;
+        }
+    }
+}
+
+// ---- SpGEMM C = A B with an LDS hash per row --------------------------------------------
+constexpr int HASH = 2048;
+constexpr int SG_WAVE = 64;
+
+__device__ inline int32_t hslot(int32_t c) {
+    return (int32_t)(((uint32_t)c * 2654435761u) >> (32 - 11));  // log2(HASH) = 11
+}
+
+// Insert the column set of row i of A*B into tab; returns false on overflow.
+__device__ inline void sg_insert_row(const int32_t* Arp, const int32_t* Ac, const int32_t* Brp,
+                                     const int32_t* Bc, int32_t i, int32_t* tab, int32_t* count,
+                                     int32_t* overflow) {
+    for (int32_t kk = Arp[i] + threadIdx.x; kk < Arp[i + 1]; kk += SG_WAVE) {
+        int32_t r = Ac[kk];
+        for (int32_t q = Brp[r]; q < Brp[r + 1]; ++q) {
+            int32_t c = Bc[q];
+            int32_t h = hslot(c);
+            int probes = 0;
+            while (true) {
+                int32_t old = atomicCAS(&tab[h], -1, c);
+                if (old == -1) { atomicAdd(count, 1); break; }
+                if (old == c) break;
+                h = (h + 1) & (HASH - 1);
+                if (++probes >= HASH) { *overflow = 1; break; }
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(SG_WAVE)
+k_spgemm_count(int32_t n, const int32_t* __restrict__ Arp, const int32_t* __restrict__ Ac,
+               const int32_t* __restrict__ Brp, const int32_t* __restrict__ Bc,
+               int32_t* __restrict__ cnt, int32_t* __restrict__ gflag) {
+    __shared__ int32_t tab[HASH];
+    __shared__ int32_t count, overflow;
+    for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        for (int h = threadIdx.x; h < HASH; h += SG_WAVE) tab[h] = -1;
+        if (threadIdx.x == 0) { count = 0; overflow = 0; }
+        __syncthreads();
+        sg_insert_row(Arp, Ac, Brp, Bc, i, tab, &count, &overflow);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            cnt[i] = count;
+            if (overflow) *gflag = 1;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(SG_WAVE)
+k_spgemm_fill(int32_t n, const int32_t* __restrict__ Arp, const int32_t* __restrict__ Ac,
+              const double* __restrict__ Av, const int32_t* __restrict__ Brp,
+              const int32_t* __restrict__ Bc, const double* __restrict__ Bv,
+              const int32_t* __restrict__ Crp, int32_t* __restrict__ Cc, double* __restrict__ Cv,
+              int32_t* __restrict__ gflag) {
+    __shared__ int32_t tab[HASH];
+    __shared__ int32_t list[HASH];
+    __shared__ int32_t count, overflow, ncomp;
+    for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        for (int h = threadIdx.x; h < HASH; h += SG_WAVE) tab[h] = -1;
+        if (threadIdx.x == 0) { count = 0; overflow = 0; ncomp = 0; }
+        __syncthreads();
+        sg_insert_row(Arp, Ac, Brp, Bc, i, tab, &count, &overflow);
+        __syncthreads();
+        if (overflow) {
+            if (threadIdx.x == 0) *gflag = 1;
+            __syncthreads();
+            continue;
+        }
+        // compact the keys
+        for (int h = threadIdx.x; h < HASH; h += SG_WAVE) {
+            int32_t c = tab[h];
+            if (c != -1) list[atomicAdd(&ncomp, 1)] = c;
+        }
+        __syncthreads();
+        const int32_t u = ncomp;
+        const int32_t base = Crp[i];
+        if (u != Crp[i + 1] - base) {  // must equal the symbolic count
+            if (threadIdx.x == 0) *gflag = 2;
+            __syncthreads();
+            continue;
+        }
+        // rank sort into tab[0..u)
+        for (int32_t e = threadIdx.x; e < u; e += SG_WAVE) {
+            int32_t key = list[e], rank = 0;
+            for (int32_t x = 0; x < u; ++x) rank += list[x] < key;
+            tab[rank] = key;
+        }
+        __syncthreads();
+        // one lane per output entry: sum over k ascending (the row of A is sorted)
+        for (int32_t e = threadIdx.x; e < u; e += SG_WAVE) {
+            int32_t c = tab[e];
+            double acc = 0.0;
+            for (int32_t kk = Arp[i]; kk < Arp[i + 1]; ++kk) {
+                int32_t r = Ac[kk];
+                int32_t lo = Brp[r], hi = Brp[r + 1] - 1;
+                while (lo <= hi) {
+                    int32_t mid = (lo + hi) >> 1;
+                    int32_t v = Bc[mid];
+                    if (v == c) { acc += Av[kk] * Bv[mid]; break; }
+                    if (v < c) lo = mid + 1; else hi = mid - 1;
+                }
+            }
+            Cc[base + e] = c;
+            Cv[base + e] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+static void spgemm(const Csr& A, const Csr& Bm, Csr& C, hipStream_t s) {
+    C.n = A.n;
+    C.m = Bm.m;
+    C.rowptr.alloc(A.n + 1, s);
+    DBuf<int32_t> flag(1, s);
+    TP_LAUNCH(k_fill_i32, 1, B, 0, s, flag.p, 0, (int64_t)1);
+    int grid = std::min<int>(std::max<int>(A.n, 1), 65536);
+    if (A.n > 0)
+        TP_LAUNCH(k_spgemm_count, grid, SG_WAVE, 0, s, A.n, A.rowptr.p, A.col.p, Bm.rowptr.p, Bm.col.p,
+                  C.rowptr.p, flag.p);
+    scan_exclusive(C.rowptr.p, C.rowptr.p, A.n, s);
+    int32_t f = read_i32(flag.p, s);
+    if (f) fail(TP_ERR_CAPACITY, "SpGEMM row exceeded the %d-entry LDS hash table", HASH);
+    C.nnz = read_i32(C.rowptr.p + A.n, s);
+    C.col.alloc(C.nnz, s);
+    C.val.alloc(C.nnz, s);
+    if (A.n > 0)
+        TP_LAUNCH(k_spgemm_fill, grid, SG_WAVE, 0, s, A.n, A.rowptr.p, A.col.p, A.val.p, Bm.rowptr.p,
+                  Bm.col.p, Bm.val.p, C.rowptr.p, C.col.p, C.val.p, flag.p);
+    f = read_i32(flag.p, s);
+    if (f) fail(TP_ERR_CAPACITY, "SpGEMM numeric pass failed (code %d)", f);
+}
+
+// ---- l1 diagonal, precision copies ----------------------------------------------------
+__global__ void __launch_bounds__(B)
+k_l1_dinv(int32_t n, const int32_t* __restrict__ rowptr, const double* __restrict__ val,
+          double* __restrict__ dinv) {
+    int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n) return;
+    double d = 0.0;
+    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) d += fabs(val[q]);
+    dinv[i] = d > 0.0 ? 1.0 / d : 0.0;
+}
+
+__global__ void __launch_bounds__(B)
+k_to_f32(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
+    int64_t i = (int64_t)blockIdx.x * B + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+// ---- coarsest level: dense LU with partial pivoting, then explicit inverse ----------
+__global__ void __launch_bounds__(B)
+k_csr_to_dense(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+               const double* __restrict__ val, double* __restrict__ Dm) {
+    int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n) return;
+    for (int32_t j = 0; j < n; ++j) Dm[(int64_t)i * n + j] = 0.0;
+    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) Dm[(int64_t)i * n + col[q]] = val[q];
+}
+
+constexpr int LU_T = 1024;
+
+// Single workgroup: in-place LU of Dm (row-major n x n), pivots to piv.
+__global__ void __launch_bounds__(LU_T)
+k_dense_lu(int32_t n, double* __restrict__ a, int32_t* __restrict__ piv, int32_t* __restrict__ bad) {
+    __shared__ double sv[LU_T];
+    __shared__ int32_t si[LU_T];
+    const int t = threadIdx.x;
+    for (int32_t k = 0; k < n; ++k) {
+        // pivot: largest |a_ik|, ties -> lowest row
+        double best = -1.0;
+        int32_t bi = n;
+        for (int32_t i = k + t; i < n; i += LU_T) {
+            double v = fabs(a[(int64_t)i * n + k]);
+            if (v > best || (v == best && i < bi)) { best = v; bi = i; }
+        }
+        sv[t] = best;
+        si[t] = bi;
+        __syncthreads();
+        for (int off = LU_T / 2; off > 0; off >>= 1) {
+            if (t < off) {
+                double v = sv[t + off];
+                int32_t j = si[t + off];
+                if (v > sv[t] || (v == sv[t] && j < si[t])) { sv[t] = v; si[t] = j; }
+            }
+            __syncthreads();
+        }
+        const int32_t p = si[0];
+        const double pv = sv[0];
+        __syncthreads();
+        if (t == 0) {
+            piv[k] = p;
+            if (!(pv > 0.0)) *bad = 1;
+        }
+        if (!(pv > 0.0)) return;  // uniform across the block
+        if (p != k)
+            for (int32_t j = t; j < n; j += LU_T) {
+                double tmp = a[(int64_t)k * n + j];
+                a[(int64_t)k * n + j] = a[(int64_t)p * n + j];
+                a[(int64_t)p * n + j] = tmp;
+            }
+        __syncthreads();
+        const double akk = a[(int64_t)k * n + k];
+        for (int32_t i = k + 1 + t; i < n; i += LU_T) a[(int64_t)i * n + k] /= akk;
+        __syncthreads();
+        const int32_t m = n - k - 1;
+        for (int64_t e = t; e < (int64_t)m * m; e += LU_T) {
+            int32_t i = k + 1 + (int32_t)(e / m), j = k + 1 + (int32_t)(e % m);
+            a[(int64_t)i * n + j] -= a[(int64_t)i * n + k] * a[(int64_t)k * n + j];
+        }
+        __syncthreads();
+    }
+}
+
+// Column j of the inverse: permute e_j, forward (unit L), backward (U).
+__global__ void __launch_bounds__(B)
+k_lu_inverse(int32_t n, const double* __restrict__ lu, const int32_t* __restrict__ piv,
+             double* __restrict__ work, double* __restrict__ inv) {
+    int32_t j = blockIdx.x * B + threadIdx.x;
+    if (j >= n) return;
+    double* x = work + (int64_t)j * n;
+    for (int32_t i = 0; i < n; ++i) x[i] = (i == j) ? 1.0 : 0.0;
+    for (int32_t k = 0; k < n; ++k)
+        if (piv[k] != k) { double t = x[k]; x[k] = x[piv[k]]; x[piv[k]] = t; }
+    for (int32_t i = 0; i < n; ++i) {
+        double s = x[i];
+        for (int32_t q = 0; q < i; ++q) s -= lu[(int64_t)i * n + q] * x[q];
+        x[i] = s;
+    }
+    for (int32_t i = n - 1; i >= 0; --i) {
+        double s = x[i];
+        for (int32_t q = i + 1; q < n; ++q) s -= lu[(int64_t)i * n + q] * x[q];
+        x[i] = s / lu[(int64_t)i * n + i];
+    }
+    for (int32_t i = 0; i < n; ++i) inv[(int64_t)i * n + j] = x[i];
+}
+
+static void build_coarse_inverse(tp_amg* h, const Csr& A, hipStream_t s) {
+    const int32_t n = A.n;
+    h->nc = n;
+    if (n > 4096) fail(TP_ERR_NUMERIC, "coarsening stalled at %d rows (> 4096), no dense factorisation", n);
+    DBuf<double> lu((size_t)n * n, s), work((size_t)n * n, s);
+    DBuf<int32_t> piv(n, s), bad(1, s);
+    h->cinv.alloc((size_t)n * n, s);
+    TP_LAUNCH(k_fill_i32, 1, B, 0, s, bad.p, 0, (int64_t)1);
+    if (n > 0) {
+        TP_LAUNCH(k_csr_to_dense, cdiv(n, B), B, 0, s, n, A.rowptr.p, A.col.p, A.val.p, lu.p);
+        TP_LAUNCH(k_dense_lu, 1, LU_T, 0, s, n, lu.p, piv.p, bad.p);
+    }
+    if (read_i32(bad.p, s)) fail(TP_ERR_NUMERIC, "zero pivot in the coarsest-level LU (n=%d)", n);
+    if (n > 0) TP_LAUNCH(k_lu_inverse, cdiv(n, B), B, 0, s, n, lu.p, piv.p, work.p, h->cinv.p);
+}
+
+// ---- setup driver ---------------------------------------------------------------------
+static void copy_csr_in(Csr& A, int32_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                        hipStream_t s) {
+    A.n = A.m = n;
+    A.nnz = read_i32(rowptr + n, s);
+    TP_CHECK_ARG(A.nnz >= n, "amg_setup: nnz %d < n %d (diagonal missing)", A.nnz, n);
+    A.rowptr.alloc(n + 1, s);
+    A.col.alloc(A.nnz, s);
+    A.val.alloc(A.nnz, s);
+    TP_HIP(hipMemcpyAsync(A.rowptr.p, rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
+    TP_HIP(hipMemcpyAsync(A.col.p, col, sizeof(int32_t) * A.nnz, hipMemcpyDeviceToDevice, s));
+    TP_HIP(hipMemcpyAsync(A.val.p, val, sizeof(double) * A.nnz, hipMemcpyDeviceToDevice, s));
+}
+
+// strength matrix (pattern) of A
+static void strength(const Csr& A, double theta, Csr& S, hipStream_t s) {
+    S.n = S.m = A.n;
+    S.rowptr.alloc(A.n + 1, s);
+    if (A.n > 0)
+        TP_LAUNCH(k_strength, cdiv(A.n, B), B, 0, s, A.n, A.rowptr.p, A.col.p, A.val.p, theta, S.rowptr.p,
+                  (const int32_t*)nullptr, (int32_t*)nullptr);
+    scan_exclusive(S.rowptr.p, S.rowptr.p, A.n, s);
+    S.nnz = read_i32(S.rowptr.p + A.n, s);
+    S.col.alloc(S.nnz, s);
+    if (A.n > 0)
+        TP_LAUNCH(k_strength, cdiv(A.n, B), B, 0, s, A.n, A.rowptr.p, A.col.p, A.val.p, theta,
+                  (int32_t*)nullptr, S.rowptr.p, S.col.p);
+}
+
+static void direct_interp(const Csr& A, const Csr& S, const int32_t* cf, const int32_t* cmap, int32_t nc,
+                          Csr& P, hipStream_t s) {
+    P.n = A.n;
+    P.m = nc;
+    P.rowptr.alloc(A.n + 1, s);
+    if (A.n > 0) TP_LAUNCH(k_interp_count, cdiv(A.n, B), B, 0, s, A.n, S.rowptr.p, S.col.p, cf, P.rowptr.p);
+    scan_exclusive(P.rowptr.p, P.rowptr.p, A.n, s);
+    P.nnz = read_i32(P.rowptr.p + A.n, s);
+    P.col.alloc(P.nnz, s);
+    P.val.alloc(P.nnz, s);
+    if (A.n > 0)
+        TP_LAUNCH(k_interp_fill, cdiv(A.n, B), B, 0, s, A.n, A.rowptr.p, A.col.p, A.val.p, S.rowptr.p,
+                  S.col.p, cf, cmap, P.rowptr.p, P.col.p, P.val.p);
+}
+
+static void make_f32(DBuf<float>& dst, const DBuf<double>& src, size_t n, hipStream_t s) {
+    dst.alloc(n, s);
+    if (n) TP_LAUNCH(k_to_f32, cdiv(n, B), B, 0, s, (int64_t)n, src.p, dst.p);
+}
+
+static void alloc_work(tp_amg* h, hipStream_t s) {
+    size_t es = storage_bytes(h);
+    for (auto& L : h->lev) {
+        size_t n = (size_t)std::max(L.A.n, 1);
+        L.b.alloc(n * es, s);
+        L.x.alloc(n * es, s);
+        L.x2.alloc(n * es, s);
+        L.r.alloc(n * es, s);
+        L.d.alloc(n * es, s);
+        L.gA = lanes_for(L.A.n, L.A.nnz);
+        L.gP = lanes_for(L.P.n, L.P.nnz);
+        L.gR = lanes_for(L.R.n, L.R.nnz);
+        if (h->prm.storage == 1) {
+            make_f32(L.A32, L.A.val, L.A.nnz, s);
+            make_f32(L.dinv32, L.dinv, L.A.n, s);
+            if (L.P.nnz) make_f32(L.P32, L.P.val, L.P.nnz, s);
+            if (L.R.nnz) make_f32(L.R32, L.R.val, L.R.nnz, s);
+        }
+    }
+}
+
+static void setup(tp_amg* h, int32_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                  hipStream_t s) {
+    const tp_amg_params& prm = h->prm;
+    h->lev.emplace_back();
+    copy_csr_in(h->lev[0].A, n, rowptr, col, val, s);
+    DBuf<int32_t> undecided(512, s);
+    for (int32_t l = 0;; ++l) {
+        Level& L = h->lev[l];
+        Csr& A = L.A;
+        L.dinv.alloc(std::max(A.n, 1), s);
+        if (A.n > 0) TP_LAUNCH(k_l1_dinv, cdiv(A.n, B), B, 0, s, A.n, A.rowptr.p, A.val.p, L.dinv.p);
+        if (A.n <= prm.coarse_max || l + 1 >= prm.max_levels) break;
+        Csr S, ST;
+        strength(A, prm.theta, S, s);
+        transpose(S.rowptr.p, S.col.p, nullptr, S.n, S.n, S.nnz, false, ST, s);
+        // PMIS rounds
+        DBuf<int8_t> st(A.n, s), st2(A.n, s);
+        TP_LAUNCH(k_pmis_init, cdiv(A.n, B), B, 0, s, A.n, ST.rowptr.p, st.p);
+        const uint64_t hseed = prm.seed ^ ((uint64_t)l << 40);
+        int round = 0;
+        for (;; ++round) {
+            if (round >= 512) fail(TP_ERR_NUMERIC, "PMIS did not finish in 512 rounds");
+            TP_LAUNCH(k_fill_i32, 1, B, 0, s, undecided.p + round, 0, (int64_t)1);
+            TP_LAUNCH(k_pmis_select, cdiv(A.n, B), B, 0, s, A.n, hseed, S.rowptr.p, S.col.p, ST.rowptr.p,
+                      ST.col.p, st.p, st2.p);
+            TP_LAUNCH(k_pmis_fmark, cdiv(A.n, B), B, 0, s, A.n, S.rowptr.p, S.col.p, st2.p,
+                      undecided.p + round);
+            std::swap(st.p, st2.p);
+            if (read_i32(undecided.p + round, s) == 0) break;
+        }
+        L.cf.alloc(A.n, s);
+        TP_LAUNCH(k_cf_flags, cdiv(A.n, B), B, 0, s, A.n, st.p, L.cf.p);
+        DBuf<int32_t> cmap(A.n + 1, s);
+        scan_exclusive(L.cf.p, cmap.p, A.n, s);
+        const int32_t nc = read_i32(cmap.p + A.n, s);
+        if (nc == 0 || (double)nc > 0.9 * (double)A.n) {  // empty or stalled coarsening
+            L.cf.release();
+            break;
+        }
+        direct_interp(A, S, L.cf.p, cmap.p, nc, L.P, s);
+        if (prm.restriction == 1) {
+            Csr At, St, Q;
+            transpose(A.rowptr.p, A.col.p, A.val.p, A.n, A.n, A.nnz, true, At, s);
+            strength(At, prm.theta, St, s);
+            direct_interp(At, St, L.cf.p, cmap.p, nc, Q, s);
+            transpose(Q.rowptr.p, Q.col.p, Q.val.p, Q.n, nc, Q.nnz, true, L.R, s);
+        } else {
+            transpose(L.P.rowptr.p, L.P.col.p, L.P.val.p, L.P.n, nc, L.P.nnz, true, L.R, s);
+        }
+        Csr AP;
+        spgemm(A, L.P, AP, s);
+        h->lev.emplace_back();
+        Level& Ln = h->lev[l + 1];        // (reference after emplace_back)
+        spgemm(h->lev[l].R, AP, Ln.A, s);
+        Ln.A.m = nc;
+    }
+    build_coarse_inverse(h, h->lev.back().A, s);
+    alloc_work(h, s);
+    TP_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace tp
+
+extern "C" {
+
+int amg_setup(int32_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+              const tp_amg_params* params, tp_amg_t* out, void* stream) {
+    TP_GUARD({
+        TP_CHECK_ARG(out && params, "amg_setup: null argument");
+        *out = nullptr;
+        TP_CHECK_ARG(n >= 1 && rowptr && col && val, "amg_setup: empty or null matrix");
+        const tp_amg_params& p = *params;
+        TP_CHECK_ARG(p.theta > 0.0 && p.theta < 1.0, "amg_setup: theta must be in (0,1)");
+        TP_CHECK_ARG(p.max_levels >= 1 && p.max_levels <= 25, "amg_setup: max_levels must be in [1,25]");
+        TP_CHECK_ARG(p.coarse_max >= 0 && p.coarse_max <= 4096, "amg_setup: coarse_max must be in [0,4096]");
+        TP_CHECK_ARG(p.smoother == 0 || p.smoother == 1, "amg_setup: smoother must be 0 or 1");
+        TP_CHECK_ARG(p.smoother == 0 || (p.cheb_degree >= 1 && p.cheb_degree <= 8),
+                     "amg_setup: cheb_degree must be in [1,8]");
+        TP_CHECK_ARG(p.smoother == 0 || (p.cheb_lo > 0.0 && p.cheb_lo < 1.0), "amg_setup: cheb_lo in (0,1)");
+        TP_CHECK_ARG(p.nu_pre >= 0 && p.nu_pre <= 8 && p.nu_post >= 0 && p.nu_post <= 8,
+                     "amg_setup: sweeps must be in [0,8]");
+        TP_CHECK_ARG(p.restriction == 0 || p.restriction == 1, "amg_setup: restriction must be 0 or 1");
+        TP_CHECK_ARG(p.storage == 0 || p.storage == 1, "amg_setup: storage must be 0 or 1");
+        hipStream_t s = (hipStream_t)stream;
+        tp_amg* h = new tp_amg();
+        h->prm = p;
+        h->stream = s;
+        try {
+            tp::setup(h, n, rowptr, col, val, s);
+        } catch (...) {
+            delete h;
+            throw;
+        }
+        *out = h;
+    });
+    return TP_OK;
+}
+
+int amg_num_levels(tp_amg_t amg, int32_t* nlev) {
+    TP_GUARD({
+        TP_CHECK_ARG(amg && nlev, "null argument");
+        *nlev = (int32_t)amg->lev.size();
+    });
+    return TP_OK;
+}
+
+int amg_level_info(tp_amg_t amg, int32_t level, int32_t* n, int32_t* nnzA, int32_t* nnzP, int32_t* nnzR) {
+    TP_GUARD({
+        TP_CHECK_ARG(amg && n && nnzA && nnzP && nnzR, "null argument");
+        TP_CHECK_ARG(level >= 0 && level < (int32_t)amg->lev.size(), "level out of range");
+        const tp::Level& L = amg->lev[level];
+        *n = L.A.n;
+        *nnzA = L.A.nnz;
+        *nnzP = L.P.nnz;
+        *nnzR = L.R.nnz;
+    });
+    return TP_OK;
+}
+
+int amg_level_copy(tp_amg_t amg, int32_t level, int32_t* A_rowptr, int32_t* A_col, double* A_val,
+                   int32_t* cf, int32_t* P_rowptr, int32_t* P_col, double* P_val, int32_t* R_rowptr,
+                   int32_t* R_col, double* R_val, void* stream) {
+    TP_GUARD({
+        TP_CHECK_ARG(amg, "null handle");
+        TP_CHECK_ARG(level >= 0 && level < (int32_t)amg->lev.size(), "level out of range");
+        hipStream_t s = (hipStream_t)stream;
+        const tp::Level& L = amg->lev[level];
+        auto cp = [&](void* dst, const void* src, size_t bytes) {
+            if (dst && src && bytes) TP_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+        };
+        cp(A_rowptr, L.A.rowptr.p, sizeof(int32_t) * (L.A.n + 1));
+        cp(A_col, L.A.col.p, sizeof(int32_t) * L.A.nnz);
+        cp(A_val, L.A.val.p, sizeof(double) * L.A.nnz);
+        cp(cf, L.cf.p, sizeof(int32_t) * L.A.n);
+        if (L.P.nnz || L.P.n) {
+            cp(P_rowptr, L.P.rowptr.p, sizeof(int32_t) * (L.P.n + 1));
+            cp(P_col, L.P.col.p, sizeof(int32_t) * L.P.nnz);
+            cp(P_val, L.P.val.p, sizeof(double) * L.P.nnz);
+            cp(R_rowptr, L.R.rowptr.p, sizeof(int32_t) * (L.R.n + 1));
+            cp(R_col, L.R.col.p, sizeof(int32_t) * L.R.nnz);
+            cp(R_val, L.R.val.p, sizeof(double) * L.R.nnz);
+        }
+    });
+    return TP_OK;
+}
+
+int amg_destroy(tp_amg_t amg) {
+    TP_GUARD({
+        if (!amg) return TP_OK;
+        hipStream_t s = amg->stream;
+        delete amg;  // buffers are freed stream-ordered on the setup stream
+        TP_HIP(hipStreamSynchronize(s));
+    });
+    return TP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,470 @@
+// tp_krylov.hip -- block preconditioner and flexible GMRES on the GPU.
+//
+// Preconditioner: the five-step application list of Section 3.2.  The lower
+// form (steps 1-3) solves A_pp x_p = b_p, forms b~_T = b_T - A_Tp x_p and
+// solves S~ d_T = b~_T, each solve being one AMG V-cycle; the full form adds
+// steps 4-5 with b~_p = b_p - A_pT d_T; the upper form runs the Schur solve
+// first.  Internally the p and T halves of a vector are stored split
+// ([p_0..p_{n-1}, T_0..T_{n-1}]), a symmetric permutation of the
+// interleaved ordering at the interface.
+//
+// FGMRES (Saad 1993; right preconditioning as in Section 4, restart 30):
+// classical Gram-Schmidt applied twice (CGS2) with all inner products
+// reduced over a fixed grid in a fixed order, so results are run-to-run
+// deterministic; Hessenberg, Givens rotations and the small triangular solve
+// stay on the device in FP64.  One 8-byte device->host read per iteration
+// carries the residual estimate for the stopping test.
+#include "tp_amg.h"
+
+#include <cmath>
+
+namespace tp {
+void cast_d2s(int32_t n, const double* a, void* b, size_t es, hipStream_t s);
+void cast_s2d(int32_t n, const void* a, double* b, size_t es, hipStream_t s);
+}  // namespace tp
+
+struct tp_prec {
+    tp_jacobian J;
+    tp_amg* pp = nullptr;
+    tp_amg* S = nullptr;
+    int variant = 0;
+    tp::DBuf<double> rs, zs;  // split work vectors (2n) for the interleaved entry point
+};
+
+namespace tp {
+
+constexpr int KB = 256;
+constexpr int MAXK = 32;      // restart length bound (H has MAXK+1 rows)
+constexpr int TILE = 1024;
+
+// ---- layout ----------------------------------------------------------------------
+__global__ void __launch_bounds__(KB)
+k_deinterleave(int32_t n, const double* __restrict__ in, double* __restrict__ out) {
+    int32_t i = blockIdx.x * KB + threadIdx.x;
+    if (i >= n) return;
+    out[i] = in[2 * i];
+    out[n + i] = in[2 * i + 1];
+}
+
+__global__ void __launch_bounds__(KB)
+k_interleave(int32_t n, const double* __restrict__ in, double* __restrict__ out) {
+    int32_t i = blockIdx.x * KB + threadIdx.x;
+    if (i >= n) return;
+    out[2 * i] = in[i];
+    out[2 * i + 1] = in[n + i];
+}
+
+__global__ void __launch_bounds__(KB)
+k_zero_d(int64_t N, double* __restrict__ x) {
+    int64_t i = (int64_t)blockIdx.x * KB + threadIdx.x;
+    if (i < N) x[i] = 0.0;
+}
+
+// ---- sparse products on the Jacobian -----------------------------------------------
+constexpr int JG = 8;  // lanes per stencil row
+
+// out = rhs - M x (rhs may be null: out = -M x is never needed; null -> M x)
+template <typename To>
+__global__ void __launch_bounds__(KB)
+k_spmv_sub(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+           const double* __restrict__ av, const double* __restrict__ x, const double* __restrict__ rhs,
+           To* __restrict__ out) {
+    const int64_t tid = (int64_t)blockIdx.x * KB + threadIdx.x;
+    const int32_t i = (int32_t)(tid / JG);
+    const int lane = (int)(tid % JG);
+    double s = 0.0;
+    if (i < n)
+        for (int32_t q = rp[i] + lane; q < rp[i + 1]; q += JG) s += av[q] * x[ci[q]];
+#pragma unroll
+    for (int off = JG / 2; off > 0; off >>= 1) s += __shfl_down(s, off, JG);
+    if (i < n && lane == 0) out[i] = (To)(rhs[i] - s);
+}
+
+// w = J z (split vectors); with b: w = b - J z
+__global__ void __launch_bounds__(KB)
+k_block_spmv(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+             const double* __restrict__ pp, const double* __restrict__ pT, const double* __restrict__ Tp,
+             const double* __restrict__ TT, const double* __restrict__ z, const double* __restrict__ b,
+             double* __restrict__ w) {
+    const int64_t tid = (int64_t)blockIdx.x * KB + threadIdx.x;
+    const int32_t i = (int32_t)(tid / JG);
+    const int lane = (int)(tid % JG);
+    double sm = 0.0, se = 0.0;
+    if (i < n) {
+        const double* zp = z;
+        const double* zT = z + n;
+        for (int32_t q = rp[i] + lane; q < rp[i + 1]; q += JG) {
+            const int32_t j = ci[q];
+            const double a = zp[j], c = zT[j];
+            sm += pp[q] * a + pT[q] * c;
+            se += Tp[q] * a + TT[q] * c;
+        }
+    }
+#pragma unroll
+    for (int off = JG / 2; off > 0; off >>= 1) {
+        sm += __shfl_down(sm, off, JG);
+        se += __shfl_down(se, off, JG);
+    }
+    if (i < n && lane == 0) {
+        if (b) {
+            w[i] = b[i] - sm;
+            w[n + i] = b[n + i] - se;
+        } else {
+            w[i] = sm;
+            w[n + i] = se;
+        }
+    }
+}
+
+// ---- CGS2 building blocks -------------------------------------------------------------
+// mode 0: part[blk][i] = sum_e V_i[e] w[e]                      (i < k)
+// mode 1: w -= sum_i h_i V_i, then part[blk][i] = V_i . w_new     (i < k)
+// mode 2: w -= sum_i h_i V_i (k may be 0), then part[blk][0] = w_new . w_new
+__global__ void __launch_bounds__(KB)
+k_cgs(int64_t N, int k, const double* __restrict__ V, const double* __restrict__ h, double* __restrict__ w,
+      int mode, double* __restrict__ part) {
+    __shared__ double wt[TILE];
+    __shared__ double acc[MAXK + 1];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int nwaves = KB / 64;
+    for (int i = t; i <= MAXK; i += KB) acc[i] = 0.0;
+    __syncthreads();
+    const int64_t ntiles = (N + TILE - 1) / TILE;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t base = tile * TILE;
+        for (int e = t; e < TILE; e += KB) {
+            int64_t g = base + e;
+            double v = 0.0;
+            if (g < N) {
+                v = w[g];
+                if (mode >= 1) {
+                    for (int i = 0; i < k; ++i) v -= h[i] * V[(int64_t)i * N + g];
+                    w[g] = v;
+                }
+            }
+            wt[e] = v;
+        }
+        __syncthreads();
+        if (mode == 2) {
+            if (wave == 0) {
+                double s = 0.0;
+                for (int e = lane; e < TILE; e += 64) s += wt[e] * wt[e];
+                for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+                if (lane == 0) acc[0] += s;
+            }
+        } else {
+            for (int i = wave; i < k; i += nwaves) {
+                const double* Vi = V + (int64_t)i * N + base;
+                double s = 0.0;
+                for (int e = lane; e < TILE; e += 64)
+                    if (base + e < N) s += Vi[e] * wt[e];
+                for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+                if (lane == 0) acc[i] += s;
+            }
+        }
+        __syncthreads();
+    }
+    const int cnt = mode == 2 ? 1 : k;
+    for (int i = t; i < cnt; i += KB) part[(int64_t)blockIdx.x * (MAXK + 1) + i] = acc[i];
+}
+
+// out[i] = sum over blocks of part[b][i], fixed order (one block)
+__global__ void __launch_bounds__(KB)
+k_reduce_parts(int nb, int k, const double* __restrict__ part, double* __restrict__ out) {
+    __shared__ double sh[KB];
+    for (int i = 0; i < k; ++i) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nb; b += KB) s += part[(int64_t)b * (MAXK + 1) + i];
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int off = KB / 2; off > 0; off >>= 1) {
+            if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[i] = sh[0];
+        __syncthreads();
+    }
+}
+
+// Arnoldi column j: H[:,j] = h1 + h2, H[j+1,j] = ||w||, Givens update of H and
+// g; est = |g[j+1]|.  sc layout: [0] ||w||, [1] est.
+__global__ void k_arnoldi(int j, int m, const double* __restrict__ h1, const double* __restrict__ h2,
+                          const double* __restrict__ nrm2, double* __restrict__ H, double* __restrict__ cs,
+                          double* __restrict__ sn, double* __restrict__ g, double* __restrict__ sc) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int i = 0; i <= j; ++i) H[i * m + j] = h1[i] + h2[i];
+    const double hn = sqrt(nrm2[0]);
+    H[(j + 1) * m + j] = hn;
+    for (int i = 0; i < j; ++i) {
+        double a = H[i * m + j], c = H[(i + 1) * m + j];
+        H[i * m + j] = cs[i] * a + sn[i] * c;
+        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+    }
+    double a = H[j * m + j], c = H[(j + 1) * m + j];
+    double den = hypot(a, c);
+    cs[j] = a / den;
+    sn[j] = c / den;
+    H[j * m + j] = den;
+    H[(j + 1) * m + j] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    sc[0] = hn;
+    sc[1] = fabs(g[j + 1]);
+}
+
+// v = w / nrm (nrm on device)
+__global__ void __launch_bounds__(KB)
+k_scale_div(int64_t N, const double* __restrict__ w, const double* __restrict__ nrm, double* __restrict__ v) {
+    int64_t i = (int64_t)blockIdx.x * KB + threadIdx.x;
+    if (i < N) v[i] = w[i] / nrm[0];
+}
+
+// start of a cycle: beta = sqrt(nrm2); g = [beta, 0, ...]; sc[0] = beta
+__global__ void k_cycle_init(int m, const double* __restrict__ nrm2, double* __restrict__ g,
+                             double* __restrict__ sc) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double beta = sqrt(nrm2[0]);
+    for (int i = 0; i <= m; ++i) g[i] = 0.0;
+    g[0] = beta;
+    sc[0] = beta;
+}
+
+// y = H(0:k,0:k)^{-1} g(0:k)
+__global__ void k_hess_solve(int k, int m, const double* __restrict__ H, const double* __restrict__ g,
+                             double* __restrict__ y) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int i = k - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int q = i + 1; q < k; ++q) s -= H[i * m + q] * y[q];
+        y[i] = s / H[i * m + i];
+    }
+}
+
+// x += sum_i y_i Z_i
+__global__ void __launch_bounds__(KB)
+k_xupdate(int64_t N, int k, const double* __restrict__ Z, const double* __restrict__ y, double* __restrict__ x) {
+    int64_t e = (int64_t)blockIdx.x * KB + threadIdx.x;
+    if (e >= N) return;
+    double v = x[e];
+    for (int i = 0; i < k; ++i) v += y[i] * Z[(int64_t)i * N + e];
+    x[e] = v;
+}
+
+// ---- preconditioner on split vectors ------------------------------------------------------
+static void vsolve(tp_amg* h, const double* rhs, double* out, int32_t n, hipStream_t s) {
+    const size_t es = storage_bytes(h);
+    cast_d2s(n, rhs, h->lev[0].b.p, es, s);
+    const void* x = vcycle_run(h, nullptr, s);
+    cast_s2d(n, x, out, es, s);
+}
+
+// rhs - M x written in the storage precision of h's level-0 right-hand side
+static void sub_into_b(const tp_jacobian& J, const double* M, const double* x, const double* rhs, tp_amg* h,
+                       hipStream_t s) {
+    const int32_t n = J.n;
+    const int grid = cdiv((int64_t)n * JG, KB);
+    if (storage_bytes(h) == 4)
+        TP_LAUNCH(k_spmv_sub<float>, grid, KB, 0, s, n, J.rowptr, J.col, M, x, rhs, (float*)h->lev[0].b.p);
+    else
+        TP_LAUNCH(k_spmv_sub<double>, grid, KB, 0, s, n, J.rowptr, J.col, M, x, rhs, (double*)h->lev[0].b.p);
+}
+
+static void run_from_b(tp_amg* h, double* out, int32_t n, hipStream_t s) {
+    const void* x = vcycle_run(h, nullptr, s);
+    cast_s2d(n, x, out, storage_bytes(h), s);
+}
+
+void prec_apply_split(tp_prec* M, const double* r, double* z, hipStream_t s) {
+    const int32_t n = M->J.n;
+    const double* rp = r;
+    const double* rT = r + n;
+    double* zp = z;
+    double* zT = z + n;
+    if (M->variant == 1) {
+        vsolve(M->S, rT, zT, n, s);
+        sub_into_b(M->J, M->J.pT, zT, rp, M->pp, s);
+        run_from_b(M->pp, zp, n, s);
+        return;
+    }
+    vsolve(M->pp, rp, zp, n, s);                 // step 1
+    sub_into_b(M->J, M->J.Tp, zp, rT, M->S, s);  // step 2
+    run_from_b(M->S, zT, n, s);                  // step 3
+    if (M->variant == 2) {
+        sub_into_b(M->J, M->J.pT, zT, rp, M->pp, s);  // step 4
+        run_from_b(M->pp, zp, n, s);                  // step 5
+    }
+}
+
+// ---- FGMRES driver ------------------------------------------------------------------------------
+struct Gmres {
+    int32_t n;
+    int64_t N;
+    int m;
+    int nb;
+    DBuf<double> V, Z, w, b, x, r, H, cs, sn, g, y, h1, h2, nrm2, part, sc;
+    HostMail mail;
+    Gmres(int32_t n_, int m_, hipStream_t s) : n(n_), N(2 * (int64_t)n_), m(m_) {
+        nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (N + TILE - 1) / TILE));
+        V.alloc((size_t)(m + 1) * N, s);
+        Z.alloc((size_t)m * N, s);
+        w.alloc(N, s);
+        b.alloc(N, s);
+        x.alloc(N, s);
+        r.alloc(N, s);
+        H.alloc((size_t)(m + 1) * m, s);
+        cs.alloc(m, s);
+        sn.alloc(m, s);
+        g.alloc(m + 1, s);
+        y.alloc(m, s);
+        h1.alloc(MAXK + 1, s);
+        h2.alloc(MAXK + 1, s);
+        nrm2.alloc(1, s);
+        part.alloc((size_t)nb * (MAXK + 1), s);
+        sc.alloc(4, s);
+    }
+};
+
+static void dots(Gmres& G, int k, const double* h, double* w, int mode, double* out, hipStream_t s) {
+    TP_LAUNCH(k_cgs, G.nb, KB, 0, s, G.N, k, G.V.p, h, w, mode, G.part.p);
+    TP_LAUNCH(k_reduce_parts, 1, KB, 0, s, G.nb, mode == 2 ? 1 : k, G.part.p, out);
+}
+
+static double read_d(const double* dptr, HostMail& mail, hipStream_t s) {
+    TP_HIP(hipMemcpyAsync(mail.p, dptr, sizeof(double), hipMemcpyDeviceToHost, s));
+    TP_HIP(hipStreamSynchronize(s));
+    return *mail.as<double>();
+}
+
+static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* x_il,
+                  const tp_krylov_params& kp, tp_krylov_stats* st, double* history, hipStream_t s) {
+    const int32_t n = J.n;
+    const int m = kp.restart;
+    Gmres G(n, m, s);
+    const int gn = cdiv(n, KB);
+    const int gN = cdiv(G.N, KB);
+    const int gJ = cdiv((int64_t)n * JG, KB);
+    TP_LAUNCH(k_deinterleave, gn, KB, 0, s, n, b_il, G.b.p);
+    TP_LAUNCH(k_deinterleave, gn, KB, 0, s, n, x_il, G.x.p);
+    dots(G, 0, nullptr, G.b.p, 2, G.nrm2.p, s);
+    const double bnorm = std::sqrt(read_d(G.nrm2.p, G.mail, s));
+    int it = 0, restarts = 0;
+    double rel = 0.0, est = 0.0;
+    int status = TP_OK;
+    if (bnorm == 0.0) {
+        TP_LAUNCH(k_zero_d, gN, KB, 0, s, G.N, G.x.p);
+        if (history) history[0] = 0.0;
+        rel = est = 0.0;
+    } else {
+        TP_LAUNCH(k_block_spmv, gJ, KB, 0, s, n, J.rowptr, J.col, J.pp, J.pT, J.Tp, J.TT, G.x.p, G.b.p, G.r.p);
+        dots(G, 0, nullptr, G.r.p, 2, G.nrm2.p, s);
+        rel = std::sqrt(read_d(G.nrm2.p, G.mail, s)) / bnorm;
+        est = rel;
+        if (history) history[0] = rel;
+        while (rel > kp.rtol && it < kp.maxit) {
+            if (!std::isfinite(rel)) fail(TP_ERR_NUMERIC, "non-finite residual in FGMRES");
+            // v_0 = r / beta (nrm2 holds ||r||^2)
+            TP_LAUNCH(k_cycle_init, 1, 1, 0, s, m, G.nrm2.p, G.g.p, G.sc.p);
+            TP_LAUNCH(k_scale_div, gN, KB, 0, s, G.N, G.r.p, G.sc.p, G.V.p);
+            int k = 0;
+            for (int j = 0; j < m && it < kp.maxit; ++j) {
+                double* vj = G.V.p + (int64_t)j * G.N;
+                double* zj = G.Z.p + (int64_t)j * G.N;
+                prec_apply_split(M, vj, zj, s);
+                TP_LAUNCH(k_block_spmv, gJ, KB, 0, s, n, J.rowptr, J.col, J.pp, J.pT, J.Tp, J.TT, zj,
+                          (const double*)nullptr, G.w.p);
+                dots(G, j + 1, nullptr, G.w.p, 0, G.h1.p, s);
+                dots(G, j + 1, G.h1.p, G.w.p, 1, G.h2.p, s);
+                dots(G, j + 1, G.h2.p, G.w.p, 2, G.nrm2.p, s);
+                TP_LAUNCH(k_arnoldi, 1, 1, 0, s, j, m, G.h1.p, G.h2.p, G.nrm2.p, G.H.p, G.cs.p, G.sn.p, G.g.p,
+                          G.sc.p);
+                TP_LAUNCH(k_scale_div, gN, KB, 0, s, G.N, G.w.p, G.sc.p, G.V.p + (int64_t)(j + 1) * G.N);
+                TP_HIP(hipMemcpyAsync(G.mail.p, G.sc.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+                TP_HIP(hipStreamSynchronize(s));
+                const double hn = G.mail.as<double>()[0];
+                est = G.mail.as<double>()[1] / bnorm;
+                ++it;
+                k = j + 1;
+                if (history) history[it] = est;
+                if (!std::isfinite(est)) fail(TP_ERR_NUMERIC, "non-finite Arnoldi value in FGMRES");
+                if (est <= kp.rtol || hn == 0.0) break;
+            }
+            TP_LAUNCH(k_hess_solve, 1, 1, 0, s, k, m, G.H.p, G.g.p, G.y.p);
+            TP_LAUNCH(k_xupdate, gN, KB, 0, s, G.N, k, G.Z.p, G.y.p, G.x.p);
+            TP_LAUNCH(k_block_spmv, gJ, KB, 0, s, n, J.rowptr, J.col, J.pp, J.pT, J.Tp, J.TT, G.x.p, G.b.p,
+                      G.r.p);
+            dots(G, 0, nullptr, G.r.p, 2, G.nrm2.p, s);
+            rel = std::sqrt(read_d(G.nrm2.p, G.mail, s)) / bnorm;
+            ++restarts;
+        }
+    }
+    TP_LAUNCH(k_interleave, gn, KB, 0, s, n, G.x.p, x_il);
+    TP_HIP(hipStreamSynchronize(s));
+    if (!std::isfinite(rel)) fail(TP_ERR_NUMERIC, "non-finite true residual in FGMRES");
+    if (st) {
+        st->iters = it;
+        st->restarts = restarts > 0 ? restarts - 1 : 0;
+        st->rel_true = rel;
+        st->rel_est = est;
+    }
+    status = rel <= kp.rtol ? TP_OK : TP_NOT_CONVERGED;
+    if (status != TP_OK) set_error("FGMRES reached maxit=%d with relative residual %.3e", kp.maxit, rel);
+    return status;
+}
+
+}  // namespace tp
+
+extern "C" {
+
+int precond_create(const tp_jacobian* J, tp_amg_t amg_pp, tp_amg_t amg_S, int32_t variant, tp_prec_t* out) {
+    TP_GUARD({
+        TP_CHECK_ARG(J && amg_pp && amg_S && out, "precond_create: null argument");
+        TP_CHECK_ARG(variant >= 0 && variant <= 2, "precond_create: variant must be 0, 1 or 2");
+        TP_CHECK_ARG(J->rowptr && J->col && J->pp && J->pT && J->Tp && J->TT, "precond_create: null Jacobian array");
+        TP_CHECK_ARG(amg_pp->lev[0].A.n == J->n && amg_S->lev[0].A.n == J->n,
+                     "precond_create: hierarchy size does not match J->n");
+        tp_prec* M = new tp_prec();
+        M->J = *J;
+        M->pp = amg_pp;
+        M->S = amg_S;
+        M->variant = variant;
+        *out = M;
+    });
+    return TP_OK;
+}
+
+int precond_apply(tp_prec_t M, const double* r, double* z, void* stream) {
+    TP_GUARD({
+        TP_CHECK_ARG(M && r && z, "precond_apply: null argument");
+        hipStream_t s = (hipStream_t)stream;
+        const int32_t n = M->J.n;
+        if (M->rs.n != (size_t)2 * n) {
+            M->rs.alloc(2 * (size_t)n, s);
+            M->zs.alloc(2 * (size_t)n, s);
+        }
+        TP_LAUNCH(tp::k_deinterleave, tp::cdiv(n, tp::KB), tp::KB, 0, s, n, r, M->rs.p);
+        tp::prec_apply_split(M, M->rs.p, M->zs.p, s);
+        TP_LAUNCH(tp::k_interleave, tp::cdiv(n, tp::KB), tp::KB, 0, s, n, M->zs.p, z);
+    });
+    return TP_OK;
+}
+
+int precond_destroy(tp_prec_t M) {
+    TP_GUARD({ delete M; });
+    return TP_OK;
+}
+
+int fgmres_solve(const tp_jacobian* J, tp_prec_t M, const double* b, double* x,
+                 const tp_krylov_params* params, tp_krylov_stats* stats, double* history, void* stream) {
+    TP_GUARD({
+        TP_CHECK_ARG(J && M && b && x && params, "fgmres_solve: null argument");
+        TP_CHECK_ARG(params->restart >= 1 && params->restart <= tp::MAXK - 1,
+                     "fgmres_solve: restart must be in [1,%d]", tp::MAXK - 1);
+        TP_CHECK_ARG(params->maxit >= 0, "fgmres_solve: maxit must be >= 0");
+        TP_CHECK_ARG(params->rtol >= 0.0, "fgmres_solve: rtol must be >= 0");
+        TP_CHECK_ARG(J->n == M->J.n, "fgmres_solve: J and preconditioner sizes differ");
+        return tp::fgmres(*J, M, b, x, *params, stats, history, (hipStream_t)stream);
+    });
+    return TP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,289 @@
+// tp_vcycle.hip -- the AMG V(nu_pre, nu_post)-cycle on the GPU.
+//
+// One cycle from a zero guess on level l:
+//   pre-smooth, r = b - A x, b_{l+1} = R r, recurse (explicit dense inverse
+//   on the coarsest level), x += P x_{l+1}, post-smooth.
+// Smoothers act on D^{-1} A with D_ii = sum_j |a_ij| (l1 diagonal):
+//   l1-Jacobi   x <- x + w D^{-1}(b - A x)
+//   Chebyshev   the polynomial iteration on [lo, 1] (Saad, Iterative
+//               Methods for Sparse Linear Systems, 2nd ed., Sec. 12.3); by
+//               Gershgorin the spectrum of D^{-1}A lies in the disc touching
+//               1 from the left, so no eigenvalue estimate is needed.
+// Every kernel streams its CSR arrays once: G lanes cooperate on a row (G
+// a power of two near the mean row length, 64-lane wavefronts hold 64/G
+// rows) so consecutive lanes read consecutive values and column indices.
+// Element type T is double (storage 0) or float (storage 1).
+#include "tp_amg.h"
+
+namespace tp {
+
+constexpr int VB = 256;
+
+template <typename T, int G>
+__device__ inline T group_sum(T v) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_down(v, off, G);
+    return v;
+}
+
+template <typename T, int G>
+__device__ inline T row_dot(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                            const T* __restrict__ v, const T* __restrict__ x, int32_t i, int lane,
+                            bool valid) {
+    T s = 0;
+    if (valid) {
+        const int32_t e = rp[i + 1];
+        for (int32_t q = rp[i] + lane; q < e; q += G) s += v[q] * x[ci[q]];
+    }
+    return group_sum<T, G>(s);
+}
+
+// Chebyshev sweep step: r = D^{-1}(b - A x_in); d = first ? r/theta : c1 d + c2 r;
+// x_out = x_in + d
+template <typename T, int G>
+__global__ void __launch_bounds__(VB)
+k_cheb_step(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+            const T* __restrict__ av, const T* __restrict__ dinv, const T* __restrict__ b,
+            const T* __restrict__ xin, T* __restrict__ xout, T* __restrict__ d, int first,
+            T theta, T c1, T c2) {
+    const int64_t tid = (int64_t)blockIdx.x * VB + threadIdx.x;
+    const int32_t i = (int32_t)(tid / G);
+    const int lane = (int)(tid % G);
+    const bool valid = i < n;
+    T ax = row_dot<T, G>(rp, ci, av, xin, i, lane, valid);
+    if (valid && lane == 0) {
+        T r = dinv[i] * (b[i] - ax);
+        T dn = first ? r / theta : c1 * d[i] + c2 * r;
+        d[i] = dn;
+        xout[i] = xin[i] + dn;
+    }
+}
+
+template <typename T, int G>
+__global__ void __launch_bounds__(VB)
+k_jac_step(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+           const T* __restrict__ av, const T* __restrict__ dinv, const T* __restrict__ b,
+           const T* __restrict__ xin, T* __restrict__ xout, T w) {
+    const int64_t tid = (int64_t)blockIdx.x * VB + threadIdx.x;
+    const int32_t i = (int32_t)(tid / G);
+    const int lane = (int)(tid % G);
+    const bool valid = i < n;
+    T ax = row_dot<T, G>(rp, ci, av, xin, i, lane, valid);
+    if (valid && lane == 0) xout[i] = xin[i] + w * dinv[i] * (b[i] - ax);
+}
+
+// r = b - A x
+template <typename T, int G>
+__global__ void __launch_bounds__(VB)
+k_residual(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+           const T* __restrict__ av, const T* __restrict__ b, const T* __restrict__ x,
+           T* __restrict__ r) {
+    const int64_t tid = (int64_t)blockIdx.x * VB + threadIdx.x;
+    const int32_t i = (int32_t)(tid / G);
+    const int lane = (int)(tid % G);
+    const bool valid = i < n;
+    T ax = row_dot<T, G>(rp, ci, av, x, i, lane, valid);
+    if (valid && lane == 0) r[i] = b[i] - ax;
+}
+
+// y = M x (restriction), or y += M x (prolongation, add = 1)
+template <typename T, int G>
+__global__ void __launch_bounds__(VB)
+k_spmv(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+       const T* __restrict__ av, const T* __restrict__ x, T* __restrict__ y, int add) {
+    const int64_t tid = (int64_t)blockIdx.x * VB + threadIdx.x;
+    const int32_t i = (int32_t)(tid / G);
+    const int lane = (int)(tid % G);
+    const bool valid = i < n;
+    T s = row_dot<T, G>(rp, ci, av, x, i, lane, valid);
+    if (valid && lane == 0) y[i] = add ? y[i] + s : s;
+}
+
+// first sweep from a zero guess
+template <typename T>
+__global__ void __launch_bounds__(VB)
+k_smooth0(int32_t n, const T* __restrict__ dinv, const T* __restrict__ b, T* __restrict__ x,
+          T* __restrict__ d, int cheb, T theta, T w) {
+    int32_t i = blockIdx.x * VB + threadIdx.x;
+    if (i >= n) return;
+    if (cheb) {
+        T r = dinv[i] * b[i];
+        T dn = r / theta;
+        d[i] = dn;
+        x[i] = dn;
+    } else {
+        x[i] = w * dinv[i] * b[i];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(VB)
+k_zero(int32_t n, T* __restrict__ x) {
+    int32_t i = blockIdx.x * VB + threadIdx.x;
+    if (i < n) x[i] = 0;
+}
+
+// coarsest level: x = inv * b, one wavefront per row, FP64 accumulation
+template <typename T>
+__global__ void __launch_bounds__(VB)
+k_coarse_solve(int32_t n, const double* __restrict__ inv, const T* __restrict__ b, T* __restrict__ x) {
+    const int64_t tid = (int64_t)blockIdx.x * VB + threadIdx.x;
+    const int32_t i = (int32_t)(tid / 64);
+    const int lane = (int)(tid % 64);
+    double s = 0.0;
+    if (i < n)
+        for (int32_t j = lane; j < n; j += 64) s += inv[(int64_t)i * n + j] * (double)b[j];
+    s = group_sum<double, 64>(s);
+    if (i < n && lane == 0) x[i] = (T)s;
+}
+
+// ---- dispatch ---------------------------------------------------------------------
+#define TP_G_DISPATCH(G, ...)                                  \
+    switch (G) {                                               \
+    case 1: { constexpr int GG = 1; __VA_ARGS__; } break;      \
+    case 2: { constexpr int GG = 2; __VA_ARGS__; } break;      \
+    case 4: { constexpr int GG = 4; __VA_ARGS__; } break;      \
+    case 8: { constexpr int GG = 8; __VA_ARGS__; } break;      \
+    case 16: { constexpr int GG = 16; __VA_ARGS__; } break;    \
+    case 32: { constexpr int GG = 32; __VA_ARGS__; } break;    \
+    default: { constexpr int GG = 64; __VA_ARGS__; } break;    \
+    }
+
+template <typename T> struct LevelVals;
+template <> struct LevelVals<double> {
+    static const double* A(const Level& L) { return L.A.val.p; }
+    static const double* P(const Level& L) { return L.P.val.p; }
+    static const double* R(const Level& L) { return L.R.val.p; }
+    static const double* dinv(const Level& L) { return L.dinv.p; }
+};
+template <> struct LevelVals<float> {
+    static const float* A(const Level& L) { return L.A32.p; }
+    static const float* P(const Level& L) { return L.P32.p; }
+    static const float* R(const Level& L) { return L.R32.p; }
+    static const float* dinv(const Level& L) { return L.dinv32.p; }
+};
+
+static inline int grid_rows(int32_t n, int G) { return cdiv((int64_t)std::max(n, 1) * G, VB); }
+
+// smoothing sweeps on level L; x_cur in/out (ping-pong between x and x2)
+template <typename T>
+static T* smooth(tp_amg* h, int l, const T* b, T* xc, bool zero, int nu, hipStream_t s) {
+    Level& L = h->lev[l];
+    const tp_amg_params& p = h->prm;
+    const int32_t n = L.A.n;
+    const T* av = LevelVals<T>::A(L);
+    const T* dv = LevelVals<T>::dinv(L);
+    T* xa = (T*)L.x.p;
+    T* xb = (T*)L.x2.p;
+    T* d = (T*)L.d.p;
+    T* cur = xc;
+    auto other = [&](T* q) { return q == xa ? xb : xa; };
+    const double lo = p.cheb_lo, theta = 0.5 * (1.0 + lo), delta = 0.5 * (1.0 - lo);
+    const double sigma = theta / delta;
+    const size_t es = sizeof(T);
+    for (int sw = 0; sw < nu; ++sw) {
+        bool z = zero && sw == 0;
+        if (z) {
+            TP_LAUNCH(k_smooth0<T>, cdiv(n, VB), VB, 0, s, n, dv, b, cur, d, p.smoother == 1, (T)theta,
+                      (T)p.omega);
+        }
+        if (p.smoother == 0) {
+            if (z) continue;
+            T* nx = other(cur);
+            double bytes = (double)L.A.nnz * (es + 4) + 4.0 * (n + 1) + 4.0 * es * n;
+            int ti = l == 0 ? timer_begin(s, bytes) : -1;
+            TP_G_DISPATCH(L.gA, TP_LAUNCH((k_jac_step<T, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p,
+                                          L.A.col.p, av, dv, b, cur, nx, (T)p.omega));
+            timer_end(ti, s);
+            cur = nx;
+            continue;
+        }
+        double rho0 = 1.0 / sigma;
+        int k0 = 0;
+        if (z) k0 = 1;  // first Chebyshev step done by k_smooth0
+        for (int k = k0; k < p.cheb_degree; ++k) {
+            T* nx = other(cur);
+            int first = (k == 0);
+            double c1 = 0.0, c2 = 0.0;
+            if (!first) {
+                double rho1 = 1.0 / (2.0 * sigma - rho0);
+                c1 = rho1 * rho0;
+                c2 = 2.0 * rho1 / delta;
+                rho0 = rho1;
+            }
+            double bytes = (double)L.A.nnz * (es + 4) + 4.0 * (n + 1) + (first ? 5.0 : 6.0) * es * n;
+            int ti = l == 0 ? timer_begin(s, bytes) : -1;
+            TP_G_DISPATCH(L.gA, TP_LAUNCH((k_cheb_step<T, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p,
+                                          L.A.col.p, av, dv, b, cur, nx, d, first, (T)theta, (T)c1, (T)c2));
+            timer_end(ti, s);
+            cur = nx;
+        }
+    }
+    return cur;
+}
+
+template <typename T>
+static T* vcycle_level(tp_amg* h, int l, const T* b, hipStream_t s) {
+    Level& L = h->lev[l];
+    const int32_t n = L.A.n;
+    const int last = (int)h->lev.size() - 1;
+    T* x = (T*)L.x.p;
+    if (l == last) {
+        TP_LAUNCH(k_coarse_solve<T>, cdiv((int64_t)std::max(n, 1) * 64, VB), VB, 0, s, n, h->cinv.p, b, x);
+        return x;
+    }
+    const tp_amg_params& p = h->prm;
+    T* cur = x;
+    if (p.nu_pre > 0) cur = smooth<T>(h, l, b, cur, true, p.nu_pre, s);
+    else TP_LAUNCH(k_zero<T>, cdiv(n, VB), VB, 0, s, n, cur);
+    T* r = (T*)L.r.p;
+    TP_G_DISPATCH(L.gA, TP_LAUNCH((k_residual<T, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p, L.A.col.p,
+                                  LevelVals<T>::A(L), b, cur, r));
+    Level& Ln = h->lev[l + 1];
+    T* bc = (T*)Ln.b.p;
+    TP_G_DISPATCH(L.gR, TP_LAUNCH((k_spmv<T, GG>), grid_rows(L.R.n, GG), VB, 0, s, L.R.n, L.R.rowptr.p,
+                                  L.R.col.p, LevelVals<T>::R(L), r, bc, 0));
+    T* xc = vcycle_level<T>(h, l + 1, bc, s);
+    TP_G_DISPATCH(L.gP, TP_LAUNCH((k_spmv<T, GG>), grid_rows(n, GG), VB, 0, s, n, L.P.rowptr.p, L.P.col.p,
+                                  LevelVals<T>::P(L), xc, cur, 1));
+    if (p.nu_post > 0) cur = smooth<T>(h, l, b, cur, false, p.nu_post, s);
+    return cur;
+}
+
+const void* vcycle_run(tp_amg* h, const void* b_ext, hipStream_t s) {
+    const void* b = b_ext ? b_ext : (const void*)h->lev[0].b.p;
+    if (h->prm.storage == 1) return vcycle_level<float>(h, 0, (const float*)b, s);
+    return vcycle_level<double>(h, 0, (const double*)b, s);
+}
+
+template <typename Ti, typename To>
+__global__ void __launch_bounds__(VB)
+k_cast(int32_t n, const Ti* __restrict__ a, To* __restrict__ b) {
+    int32_t i = blockIdx.x * VB + threadIdx.x;
+    if (i < n) b[i] = (To)a[i];
+}
+
+// host helpers used by the preconditioner
+void cast_d2s(int32_t n, const double* a, void* b, size_t es, hipStream_t s) {
+    if (es == 4) TP_LAUNCH((k_cast<double, float>), cdiv(n, VB), VB, 0, s, n, a, (float*)b);
+    else TP_HIP(hipMemcpyAsync(b, a, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+}
+void cast_s2d(int32_t n, const void* a, double* b, size_t es, hipStream_t s) {
+    if (es == 4) TP_LAUNCH((k_cast<float, double>), cdiv(n, VB), VB, 0, s, n, (const float*)a, b);
+    else TP_HIP(hipMemcpyAsync(b, a, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+}
+
+}  // namespace tp
+
+extern "C" int amg_vcycle(tp_amg_t amg, const double* b, double* x, void* stream) {
+    TP_GUARD({
+        TP_CHECK_ARG(amg && b && x, "amg_vcycle: null argument");
+        hipStream_t s = (hipStream_t)stream;
+        const int32_t n = amg->lev[0].A.n;
+        const size_t es = tp::storage_bytes(amg);
+        tp::cast_d2s(n, b, amg->lev[0].b.p, es, s);
+        const void* r = tp::vcycle_run(amg, nullptr, s);
+        tp::cast_s2d(n, r, x, es, s);
+    });
+    return TP_OK;
+}

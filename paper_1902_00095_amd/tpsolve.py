@@ -1,0 +1,358 @@
+"""Python binding of the tpsolve C ABI (include/tpsolve.h).
+
+Argument marshalling only: every step runs in the HIP library
+``libtpsolve.so``.  PyTorch provides device memory (tensors passed by
+pointer) and the current HIP stream.  Importing this module does not need a
+GPU; loading the library does need the built shared object and fails loudly
+when it is missing -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtpsolve.so")
+
+TP_OK, TP_ERR_ARG, TP_ERR_HIP, TP_ERR_OOM, TP_ERR_NUMERIC, TP_ERR_CAPACITY = 0, -1, -2, -3, -4, -5
+TP_NOT_CONVERGED = 1
+
+
+class TpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tpsolve status {code}: {msg}")
+        self.code = code
+
+
+class _Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double)]
+
+
+class _Props(C.Structure):
+    _fields_ = [(k, C.c_double) for k in
+                ("rho0", "p0", "T0", "c_p", "c_T", "mu0", "mu_B", "cv", "rho_r", "c_r", "g")]
+
+
+class _Well(C.Structure):
+    _fields_ = [("cell", C.c_int32), ("kind", C.c_int32), ("rate", C.c_double),
+                ("T_inj", C.c_double)]
+
+
+class _Jac(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("rowptr", C.c_void_p), ("col", C.c_void_p),
+                ("pp", C.c_void_p), ("pT", C.c_void_p), ("Tp", C.c_void_p), ("TT", C.c_void_p),
+                ("S", C.c_void_p)]
+
+
+class _AmgParams(C.Structure):
+    _fields_ = [("theta", C.c_double), ("seed", C.c_uint64), ("max_levels", C.c_int32),
+                ("coarse_max", C.c_int32), ("smoother", C.c_int32), ("cheb_degree", C.c_int32),
+                ("cheb_lo", C.c_double), ("omega", C.c_double), ("nu_pre", C.c_int32),
+                ("nu_post", C.c_int32), ("restriction", C.c_int32), ("storage", C.c_int32)]
+
+
+class _KParams(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("restart", C.c_int32), ("maxit", C.c_int32)]
+
+
+class _KStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("rel_true", C.c_double),
+                ("rel_est", C.c_double)]
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class _Allocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", C.c_void_p)]
+
+
+EXPORTS = ["tp_last_error", "tp_init", "tp_jacobian_sizes", "assemble_tpfa", "amg_setup",
+           "amg_num_levels", "amg_level_info", "amg_level_copy", "amg_vcycle", "amg_destroy",
+           "precond_create", "precond_apply", "precond_destroy", "fgmres_solve",
+           "tp_timer_enable", "tp_timer_read"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libtpsolve.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"tpsolve HIP library not built: {path} is missing "
+                           "(run __graft_entry__.build())")
+    lib = C.CDLL(path)
+    lib.tp_last_error.restype = C.c_char_p
+    for name in EXPORTS[1:]:
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(code, ok=(TP_OK,)):
+    if code not in ok:
+        raise TpError(code, _lib.tp_last_error().decode(errors="replace"))
+    return code
+
+
+@dataclasses.dataclass
+class AmgParams:
+    theta: float = 0.25
+    seed: int = 12345
+    max_levels: int = 25
+    coarse_max: int = 256
+    smoother: int = 1          # 0 l1-Jacobi, 1 Chebyshev
+    cheb_degree: int = 3
+    cheb_lo: float = 0.3
+    omega: float = 1.0
+    nu_pre: int = 1
+    nu_post: int = 1
+    restriction: int = 0       # 0 Galerkin, 1 Petrov-Galerkin (Schur operator)
+    storage: int = 0           # 0 FP64, 1 FP32
+
+    def c(self):
+        return _AmgParams(self.theta, self.seed, self.max_levels, self.coarse_max, self.smoother,
+                          self.cheb_degree, self.cheb_lo, self.omega, self.nu_pre, self.nu_post,
+                          self.restriction, self.storage)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+_keep_alloc = None
+
+
+def init(device: int = 0, torch_allocator: bool = False):
+    """Select the device; optionally route library allocations through
+    torch's caching allocator (default: the HIP stream-ordered pool)."""
+    global _keep_alloc
+    lib = load()
+    if torch_allocator:
+        torch = _torch()
+
+        def _a(nbytes, stream, ctx):
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device,
+                                                      torch.cuda.current_stream(device))
+
+        def _f(ptr, stream, ctx):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        al = _Allocator(_ALLOC_FN(_a), _FREE_FN(_f), None)
+        _keep_alloc = al
+        _check(lib.tp_init(C.byref(al), C.c_int(device)))
+    else:
+        _keep_alloc = None
+        _check(lib.tp_init(None, C.c_int(device)))
+
+
+def grid_c(g):
+    return _Grid(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz)
+
+
+def jacobian_sizes(grid):
+    lib = load()
+    n, nnz = C.c_int32(), C.c_int32()
+    _check(lib.tp_jacobian_sizes(C.byref(grid_c(grid)), C.byref(n), C.byref(nnz)))
+    return n.value, nnz.value
+
+
+class Jacobian:
+    """Device Jacobian: shared CSR pattern + pp, pT, Tp, TT, S value tensors."""
+
+    def __init__(self, n, nnz, device="cuda"):
+        torch = _torch()
+        self.n, self.nnz = n, nnz
+        self.rowptr = torch.zeros(n + 1, dtype=torch.int32, device=device)
+        self.col = torch.zeros(nnz, dtype=torch.int32, device=device)
+        for k in ("pp", "pT", "Tp", "TT", "S"):
+            setattr(self, k, torch.zeros(nnz, dtype=torch.float64, device=device))
+
+    @classmethod
+    def from_host(cls, n, rowptr, col, pp, pT, Tp, TT, S, device="cuda"):
+        torch = _torch()
+        J = cls.__new__(cls)
+        J.n, J.nnz = n, len(col)
+        J.rowptr = torch.as_tensor(np.asarray(rowptr, np.int32), device=device)
+        J.col = torch.as_tensor(np.asarray(col, np.int32), device=device)
+        for k, v in zip(("pp", "pT", "Tp", "TT", "S"), (pp, pT, Tp, TT, S)):
+            setattr(J, k, torch.as_tensor(np.asarray(v, np.float64), device=device))
+        return J
+
+    def c(self):
+        return _Jac(self.n, self.nnz, self.rowptr.data_ptr(), self.col.data_ptr(),
+                    self.pp.data_ptr(), self.pT.data_ptr(), self.Tp.data_ptr(),
+                    self.TT.data_ptr(), self.S.data_ptr())
+
+
+def assemble_tpfa(grid, props, K, phi, kappa, wells, dt, x_prev, x_k, J=None, G=None,
+                  stream=None):
+    """Assemble G(x_k) and the Jacobian on the device (tensors in, tensors out)."""
+    torch = _torch()
+    lib = load()
+    n, nnz = jacobian_sizes(grid)
+    if J is None:
+        J = Jacobian(n, nnz, device=x_k.device)
+    if G is None:
+        G = torch.empty(2 * n, dtype=torch.float64, device=x_k.device)
+    ws = (_Well * max(1, len(wells)))()
+    for i, w in enumerate(wells):
+        ws[i] = _Well(w.cell, w.kind, w.rate, w.T_inj)
+    pr = _Props(*props.as_tuple())
+    jc = J.c()
+    _check(lib.assemble_tpfa(C.byref(grid_c(grid)), C.byref(pr), _ptr(K), _ptr(phi), _ptr(kappa),
+                             C.c_int32(len(wells)), ws, C.c_double(dt), _ptr(x_prev), _ptr(x_k),
+                             C.byref(jc), _ptr(G), _stream(stream)))
+    return J, G
+
+
+class AMG:
+    """Device AMG hierarchy of an n x n CSR matrix (tensors)."""
+
+    def __init__(self, rowptr, col, val, params: AmgParams | None = None, stream=None):
+        lib = load()
+        self.params = params or AmgParams()
+        self.n = int(rowptr.numel() - 1)
+        self._keep = (rowptr, col, val)
+        h = C.c_void_p()
+        pc = self.params.c()
+        _check(lib.amg_setup(C.c_int32(self.n), _ptr(rowptr), _ptr(col), _ptr(val), C.byref(pc),
+                             C.byref(h), _stream(stream)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            _check(_lib.amg_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def nlev(self):
+        v = C.c_int32()
+        _check(_lib.amg_num_levels(self.h, C.byref(v)))
+        return v.value
+
+    def level_sizes(self, l):
+        n, a, p, r = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(_lib.amg_level_info(self.h, C.c_int32(l), C.byref(n), C.byref(a), C.byref(p),
+                                   C.byref(r)))
+        return n.value, a.value, p.value, r.value
+
+    def level(self, l, stream=None):
+        torch = _torch()
+        n, nnzA, nnzP, nnzR = self.level_sizes(l)
+        dev = self._keep[0].device
+        i32 = dict(dtype=torch.int32, device=dev)
+        f64 = dict(dtype=torch.float64, device=dev)
+        out = dict(n=n, A_rowptr=torch.zeros(n + 1, **i32), A_col=torch.zeros(nnzA, **i32),
+                   A_val=torch.zeros(nnzA, **f64))
+        coarse = l == self.nlev - 1
+        if not coarse:
+            nc = self.level_sizes(l + 1)[0]
+            out.update(cf=torch.zeros(n, **i32), P_rowptr=torch.zeros(n + 1, **i32),
+                       P_col=torch.zeros(nnzP, **i32), P_val=torch.zeros(nnzP, **f64),
+                       R_rowptr=torch.zeros(nc + 1, **i32), R_col=torch.zeros(nnzR, **i32),
+                       R_val=torch.zeros(nnzR, **f64))
+        g = out.get
+        _check(_lib.amg_level_copy(self.h, C.c_int32(l), _ptr(g("A_rowptr")), _ptr(g("A_col")),
+                                   _ptr(g("A_val")), _ptr(g("cf")), _ptr(g("P_rowptr")),
+                                   _ptr(g("P_col")), _ptr(g("P_val")), _ptr(g("R_rowptr")),
+                                   _ptr(g("R_col")), _ptr(g("R_val")), _stream(stream)))
+        torch.cuda.current_stream().synchronize()
+        return out
+
+    def vcycle(self, b, x=None, stream=None):
+        torch = _torch()
+        if x is None:
+            x = torch.empty_like(b)
+        _check(_lib.amg_vcycle(self.h, _ptr(b), _ptr(x), _stream(stream)))
+        return x
+
+
+VARIANTS = {"lower": 0, "upper": 1, "full": 2}
+
+
+class Precond:
+    def __init__(self, J: Jacobian, amg_pp: AMG, amg_S: AMG, variant="lower"):
+        lib = load()
+        self._keep = (J, amg_pp, amg_S)
+        self._jc = J.c()
+        h = C.c_void_p()
+        _check(lib.precond_create(C.byref(self._jc), amg_pp.h, amg_S.h,
+                                  C.c_int32(VARIANTS[variant]), C.byref(h)))
+        self.h = h
+
+    def apply(self, r, z=None, stream=None):
+        torch = _torch()
+        if z is None:
+            z = torch.empty_like(r)
+        _check(_lib.precond_apply(self.h, _ptr(r), _ptr(z), _stream(stream)))
+        return z
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            _check(_lib.precond_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fgmres_solve(J: Jacobian, M: Precond, b, x=None, rtol=1e-8, restart=30, maxit=1000,
+                 history=False, stream=None):
+    """Solve J x = b; returns (x, stats dict).  x (tensor) is the initial
+    guess when given and is overwritten."""
+    torch = _torch()
+    lib = load()
+    if x is None:
+        x = torch.zeros_like(b)
+    kp = _KParams(rtol, restart, maxit)
+    st = _KStats()
+    hist = np.zeros(maxit + 1) if history else None
+    jc = J.c()
+    code = lib.fgmres_solve(C.byref(jc), M.h, _ptr(b), _ptr(x), C.byref(kp), C.byref(st),
+                            hist.ctypes.data_as(C.c_void_p) if hist is not None else None,
+                            _stream(stream))
+    _check(code, ok=(TP_OK, TP_NOT_CONVERGED))
+    out = dict(converged=code == TP_OK, iters=st.iters, restarts=st.restarts,
+               rel_true=st.rel_true, rel_est=st.rel_est)
+    if hist is not None:
+        out["history"] = hist[: st.iters + 1]
+    return x, out
+
+
+def timer_enable(on=True):
+    _check(load().tp_timer_enable(C.c_int32(1 if on else 0)))
+
+
+def timer_read():
+    lib = load()
+    n, ms, b = C.c_int64(), C.c_double(), C.c_double()
+    _check(lib.tp_timer_read(C.byref(n), C.byref(ms), C.byref(b)))
+    return n.value, ms.value, b.value
