@@ -21,6 +21,12 @@ struct Level {
     DBuf<double> dinv;    // 1 / sum_j |a_ij|
     DBuf<float> A32, P32, R32, dinv32;  // storage == 1 copies
     int gA = 1, gP = 1, gR = 1;
+    // Diagonal (DIA) copy of A when its column offsets form a small set
+    // (stencil levels): dia[d * n + i] = a(i, i + off[d]), zero outside.
+    int ndia = 0;
+    int dia_off[7] = {0, 0, 0, 0, 0, 0, 0};
+    DBuf<double> dia;
+    DBuf<float> dia32;
     // V-cycle work vectors (element type follows the storage)
     DBuf<char> b, x, x2, r, d;
 };

@@ -96,24 +96,21 @@ k_transpose_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* _
     }
 }
 
-// sort each row by column (insertion sort; rows are short)
-__global__ void __launch_bounds__(B)
-k_sort_rows(int32_t n, const int32_t* __restrict__ rowptr, int32_t* __restrict__ col,
-            double* __restrict__ val) {
-    int32_t i = blockIdx.x * B + threadIdx.x;
-    if (i >= n) return;
-    int32_t a = rowptr[i], e = rowptr[i + 1];
-    for (int32_t u = a + 1; u < e; ++u) {
-        int32_t c = col[u];
-        double v = val ? val[u] : 0.0;
-        int32_t w = u - 1;
-        while (w >= a && col[w] > c) {
-            col[w + 1] = col[w];
-            if (val) val[w + 1] = val[w];
-            --w;
+// Sorted copy of each row: one 64-lane workgroup per row; an entry's
+// destination is its rank (number of smaller column indices in the row;
+// columns within a row are distinct).
+__global__ void __launch_bounds__(64)
+k_sort_rows(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col_in,
+            const double* __restrict__ val_in, int32_t* __restrict__ col, double* __restrict__ val) {
+    for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const int32_t a = rowptr[i], L = rowptr[i + 1] - a;
+        for (int32_t e = threadIdx.x; e < L; e += 64) {
+            const int32_t key = col_in[a + e];
+            int32_t rank = 0;
+            for (int32_t q = 0; q < L; ++q) rank += col_in[a + q] < key;
+            col[a + rank] = key;
+            if (val) val[a + rank] = val_in[a + e];
         }
-        col[w + 1] = c;
-        if (val) val[w + 1] = v;
     }
 }
 
@@ -131,10 +128,18 @@ static void transpose(const int32_t* rowptr, const int32_t* col, const double* v
     if (nnz > 0) TP_LAUNCH(k_col_count, cdiv(nnz, B), B, 0, s, (int64_t)nnz, col, T.rowptr.p);
     scan_exclusive(T.rowptr.p, T.rowptr.p, m, s);
     TP_HIP(hipMemcpyAsync(cursor.p, T.rowptr.p, sizeof(int32_t) * (m + 1), hipMemcpyDeviceToDevice, s));
-    if (n > 0) TP_LAUNCH(k_transpose_fill, cdiv(n, B), B, 0, s, n, rowptr, col, val, cursor.p, T.col.p,
-                         val ? T.val.p : nullptr);
-    if (sorted && m > 0)
-        TP_LAUNCH(k_sort_rows, cdiv(m, B), B, 0, s, m, T.rowptr.p, T.col.p, val ? T.val.p : nullptr);
+    if (!sorted) {
+        if (n > 0) TP_LAUNCH(k_transpose_fill, cdiv(n, B), B, 0, s, n, rowptr, col, val, cursor.p, T.col.p,
+                             val ? T.val.p : nullptr);
+        return;
+    }
+    DBuf<int32_t> tcol(nnz, s);
+    DBuf<double> tval(val ? nnz : 0, s);
+    if (n > 0) TP_LAUNCH(k_transpose_fill, cdiv(n, B), B, 0, s, n, rowptr, col, val, cursor.p, tcol.p,
+                         val ? tval.p : nullptr);
+    if (m > 0)
+        TP_LAUNCH(k_sort_rows, std::min(m, 65536), 64, 0, s, m, T.rowptr.p, tcol.p,
+                  val ? tval.p : nullptr, T.col.p, val ? T.val.p : nullptr);
 }
 
 // ---- PMIS -------------------------------------------------------------------------
@@ -264,28 +269,48 @@ k_interp_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __re
 
 // ---- SpGEMM C = A B with an LDS hash per row --------------------------------------------
 constexpr int HASH = 2048;
+constexpr int HASH_LOG = 11;
 constexpr int SG_WAVE = 64;
 
-__device__ inline int32_t hslot(int32_t c) {
-    return (int32_t)(((uint32_t)c * 2654435761u) >> (32 - 11));  // log2(HASH) = 11
+// Table size for one row: a power of two >= twice the product count
+// (bounded by HASH); rows with more distinct columns than HASH overflow.
+__device__ inline int row_table_log(const int32_t* Arp, const int32_t* Ac, const int32_t* Brp, int32_t i,
+                                    int32_t* sh_bound) {
+    int32_t b = 0;
+    for (int32_t kk = Arp[i] + threadIdx.x; kk < Arp[i + 1]; kk += SG_WAVE) {
+        int32_t r = Ac[kk];
+        b += Brp[r + 1] - Brp[r];
+    }
+    for (int off = 32; off > 0; off >>= 1) b += __shfl_down(b, off, 64);
+    if (threadIdx.x == 0) *sh_bound = b;
+    __syncthreads();
+    b = *sh_bound;
+    int lg = 6;
+    while (lg < HASH_LOG && (1 << lg) < 2 * b) ++lg;
+    return lg;
 }
 
-// Insert the column set of row i of A*B into tab; returns false on overflow.
+__device__ inline int32_t hslot(int32_t c, int lg) {
+    return (int32_t)(((uint32_t)c * 2654435761u) >> (32 - lg));
+}
+
+// Insert the column set of row i of A*B into tab (size 1 << lg).
 __device__ inline void sg_insert_row(const int32_t* Arp, const int32_t* Ac, const int32_t* Brp,
-                                     const int32_t* Bc, int32_t i, int32_t* tab, int32_t* count,
+                                     const int32_t* Bc, int32_t i, int32_t* tab, int lg, int32_t* count,
                                      int32_t* overflow) {
+    const int32_t mask = (1 << lg) - 1;
     for (int32_t kk = Arp[i] + threadIdx.x; kk < Arp[i + 1]; kk += SG_WAVE) {
         int32_t r = Ac[kk];
         for (int32_t q = Brp[r]; q < Brp[r + 1]; ++q) {
             int32_t c = Bc[q];
-            int32_t h = hslot(c);
+            int32_t h = hslot(c, lg);
             int probes = 0;
             while (true) {
                 int32_t old = atomicCAS(&tab[h], -1, c);
                 if (old == -1) { atomicAdd(count, 1); break; }
                 if (old == c) break;
-                h = (h + 1) & (HASH - 1);
-                if (++probes >= HASH) { *overflow = 1; break; }
+                h = (h + 1) & mask;
+                if (++probes > mask) { *overflow = 1; break; }
             }
         }
     }
@@ -296,12 +321,13 @@ k_spgemm_count(int32_t n, const int32_t* __restrict__ Arp, const int32_t* __rest
                const int32_t* __restrict__ Brp, const int32_t* __restrict__ Bc,
                int32_t* __restrict__ cnt, int32_t* __restrict__ gflag) {
     __shared__ int32_t tab[HASH];
-    __shared__ int32_t count, overflow;
+    __shared__ int32_t count, overflow, bound;
     for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
-        for (int h = threadIdx.x; h < HASH; h += SG_WAVE) tab[h] = -1;
+        const int lg = row_table_log(Arp, Ac, Brp, i, &bound);
+        for (int h = threadIdx.x; h < (1 << lg); h += SG_WAVE) tab[h] = -1;
         if (threadIdx.x == 0) { count = 0; overflow = 0; }
         __syncthreads();
-        sg_insert_row(Arp, Ac, Brp, Bc, i, tab, &count, &overflow);
+        sg_insert_row(Arp, Ac, Brp, Bc, i, tab, lg, &count, &overflow);
         __syncthreads();
         if (threadIdx.x == 0) {
             cnt[i] = count;
@@ -319,12 +345,13 @@ k_spgemm_fill(int32_t n, const int32_t* __restrict__ Arp, const int32_t* __restr
               int32_t* __restrict__ gflag) {
     __shared__ int32_t tab[HASH];
     __shared__ int32_t list[HASH];
-    __shared__ int32_t count, overflow, ncomp;
+    __shared__ int32_t count, overflow, ncomp, bound;
     for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
-        for (int h = threadIdx.x; h < HASH; h += SG_WAVE) tab[h] = -1;
+        const int lg = row_table_log(Arp, Ac, Brp, i, &bound);
+        for (int h = threadIdx.x; h < (1 << lg); h += SG_WAVE) tab[h] = -1;
         if (threadIdx.x == 0) { count = 0; overflow = 0; ncomp = 0; }
         __syncthreads();
-        sg_insert_row(Arp, Ac, Brp, Bc, i, tab, &count, &overflow);
+        sg_insert_row(Arp, Ac, Brp, Bc, i, tab, lg, &count, &overflow);
         __syncthreads();
         if (overflow) {
             if (threadIdx.x == 0) *gflag = 1;
@@ -332,7 +359,7 @@ k_spgemm_fill(int32_t n, const int32_t* __restrict__ Arp, const int32_t* __restr
             continue;
         }
         // compact the keys
-        for (int h = threadIdx.x; h < HASH; h += SG_WAVE) {
+        for (int h = threadIdx.x; h < (1 << lg); h += SG_WAVE) {
             int32_t c = tab[h];
             if (c != -1) list[atomicAdd(&ncomp, 1)] = c;
         }
@@ -424,38 +451,37 @@ k_csr_to_dense(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __r
 
 constexpr int LU_T = 1024;
 
-// Single workgroup: in-place LU of Dm (row-major n x n), pivots to piv.
+// Single workgroup: in-place LU of a (row-major n x n), pivots to piv.  The
+// pivot search (largest |a_ik|, ties -> lowest row) runs in wavefront 0 with
+// cross-lane reductions; three workgroup barriers per elimination step.
 __global__ void __launch_bounds__(LU_T)
 k_dense_lu(int32_t n, double* __restrict__ a, int32_t* __restrict__ piv, int32_t* __restrict__ bad) {
-    __shared__ double sv[LU_T];
-    __shared__ int32_t si[LU_T];
+    __shared__ double s_pv;
+    __shared__ int32_t s_p;
     const int t = threadIdx.x;
     for (int32_t k = 0; k < n; ++k) {
-        // pivot: largest |a_ik|, ties -> lowest row
-        double best = -1.0;
-        int32_t bi = n;
-        for (int32_t i = k + t; i < n; i += LU_T) {
-            double v = fabs(a[(int64_t)i * n + k]);
-            if (v > best || (v == best && i < bi)) { best = v; bi = i; }
-        }
-        sv[t] = best;
-        si[t] = bi;
-        __syncthreads();
-        for (int off = LU_T / 2; off > 0; off >>= 1) {
-            if (t < off) {
-                double v = sv[t + off];
-                int32_t j = si[t + off];
-                if (v > sv[t] || (v == sv[t] && j < si[t])) { sv[t] = v; si[t] = j; }
+        if (t < 64) {
+            double best = -1.0;
+            int32_t bi = n;
+            for (int32_t i = k + t; i < n; i += 64) {
+                double v = fabs(a[(int64_t)i * n + k]);
+                if (v > best || (v == best && i < bi)) { best = v; bi = i; }
             }
-            __syncthreads();
+            for (int off = 32; off > 0; off >>= 1) {
+                double ov = __shfl_down(best, off, 64);
+                int32_t oi = __shfl_down(bi, off, 64);
+                if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+            }
+            if (t == 0) {
+                s_pv = best;
+                s_p = bi;
+                piv[k] = bi;
+                if (!(best > 0.0)) *bad = 1;
+            }
         }
-        const int32_t p = si[0];
-        const double pv = sv[0];
         __syncthreads();
-        if (t == 0) {
-            piv[k] = p;
-            if (!(pv > 0.0)) *bad = 1;
-        }
+        const int32_t p = s_p;
+        const double pv = s_pv;
         if (!(pv > 0.0)) return;  // uniform across the block
         if (p != k)
             for (int32_t j = t; j < n; j += LU_T) {
@@ -465,45 +491,59 @@ k_dense_lu(int32_t n, double* __restrict__ a, int32_t* __restrict__ piv, int32_t
             }
         __syncthreads();
         const double akk = a[(int64_t)k * n + k];
-        for (int32_t i = k + 1 + t; i < n; i += LU_T) a[(int64_t)i * n + k] /= akk;
-        __syncthreads();
         const int32_t m = n - k - 1;
-        for (int64_t e = t; e < (int64_t)m * m; e += LU_T) {
-            int32_t i = k + 1 + (int32_t)(e / m), j = k + 1 + (int32_t)(e % m);
-            a[(int64_t)i * n + j] -= a[(int64_t)i * n + k] * a[(int64_t)k * n + j];
+        // multipliers and trailing update in one pass: row i (one lane
+        // group per row) first scales its pivot-column entry, then updates
+        for (int64_t e = t; e < (int64_t)m * (m + 1); e += LU_T) {
+            int32_t i = k + 1 + (int32_t)(e / (m + 1)), jj = (int32_t)(e % (m + 1));
+            if (jj == 0) continue;
+            int32_t j = k + jj;
+            double l = a[(int64_t)i * n + k] / akk;
+            a[(int64_t)i * n + j] -= l * a[(int64_t)k * n + j];
         }
+        __syncthreads();
+        for (int32_t i = k + 1 + t; i < n; i += LU_T) a[(int64_t)i * n + k] /= akk;
         __syncthreads();
     }
 }
 
-// Column j of the inverse: permute e_j, forward (unit L), backward (U).
-__global__ void __launch_bounds__(B)
+// One workgroup per column j of the inverse: x = P e_j, forward with the
+// unit lower factor, backward with the upper factor; x lives in LDS and the
+// row updates of each step run in parallel across the workgroup.
+constexpr int INV_T = 256;
+__global__ void __launch_bounds__(INV_T)
 k_lu_inverse(int32_t n, const double* __restrict__ lu, const int32_t* __restrict__ piv,
-             double* __restrict__ work, double* __restrict__ inv) {
-    int32_t j = blockIdx.x * B + threadIdx.x;
-    if (j >= n) return;
-    double* x = work + (int64_t)j * n;
-    for (int32_t i = 0; i < n; ++i) x[i] = (i == j) ? 1.0 : 0.0;
-    for (int32_t k = 0; k < n; ++k)
-        if (piv[k] != k) { double t = x[k]; x[k] = x[piv[k]]; x[piv[k]] = t; }
-    for (int32_t i = 0; i < n; ++i) {
-        double s = x[i];
-        for (int32_t q = 0; q < i; ++q) s -= lu[(int64_t)i * n + q] * x[q];
-        x[i] = s;
+             double* __restrict__ inv) {
+    extern __shared__ double x[];
+    const int32_t j = blockIdx.x;
+    const int t = threadIdx.x;
+    for (int32_t i = t; i < n; i += INV_T) x[i] = (i == j) ? 1.0 : 0.0;
+    __syncthreads();
+    if (t == 0)
+        for (int32_t k = 0; k < n; ++k)
+            if (piv[k] != k) { double tmp = x[k]; x[k] = x[piv[k]]; x[piv[k]] = tmp; }
+    __syncthreads();
+    for (int32_t k = 0; k < n; ++k) {          // forward: x_i -= L_ik x_k, i > k
+        const double xk = x[k];
+        if (xk != 0.0)
+            for (int32_t i = k + 1 + t; i < n; i += INV_T) x[i] -= lu[(int64_t)i * n + k] * xk;
+        __syncthreads();
     }
-    for (int32_t i = n - 1; i >= 0; --i) {
-        double s = x[i];
-        for (int32_t q = i + 1; q < n; ++q) s -= lu[(int64_t)i * n + q] * x[q];
-        x[i] = s / lu[(int64_t)i * n + i];
+    for (int32_t k = n - 1; k >= 0; --k) {     // backward: x_k /= U_kk, x_i -= U_ik x_k, i < k
+        if (t == 0) x[k] = x[k] / lu[(int64_t)k * n + k];
+        __syncthreads();
+        const double xk = x[k];
+        for (int32_t i = t; i < k; i += INV_T) x[i] -= lu[(int64_t)i * n + k] * xk;
+        __syncthreads();
     }
-    for (int32_t i = 0; i < n; ++i) inv[(int64_t)i * n + j] = x[i];
+    for (int32_t i = t; i < n; i += INV_T) inv[(int64_t)i * n + j] = x[i];
 }
 
 static void build_coarse_inverse(tp_amg* h, const Csr& A, hipStream_t s) {
     const int32_t n = A.n;
     h->nc = n;
     if (n > 4096) fail(TP_ERR_NUMERIC, "coarsening stalled at %d rows (> 4096), no dense factorisation", n);
-    DBuf<double> lu((size_t)n * n, s), work((size_t)n * n, s);
+    DBuf<double> lu((size_t)n * n, s);
     DBuf<int32_t> piv(n, s), bad(1, s);
     h->cinv.alloc((size_t)n * n, s);
     TP_LAUNCH(k_fill_i32, 1, B, 0, s, bad.p, 0, (int64_t)1);
@@ -512,7 +552,7 @@ static void build_coarse_inverse(tp_amg* h, const Csr& A, hipStream_t s) {
         TP_LAUNCH(k_dense_lu, 1, LU_T, 0, s, n, lu.p, piv.p, bad.p);
     }
     if (read_i32(bad.p, s)) fail(TP_ERR_NUMERIC, "zero pivot in the coarsest-level LU (n=%d)", n);
-    if (n > 0) TP_LAUNCH(k_lu_inverse, cdiv(n, B), B, 0, s, n, lu.p, piv.p, work.p, h->cinv.p);
+    if (n > 0) TP_LAUNCH(k_lu_inverse, n, INV_T, sizeof(double) * n, s, n, lu.p, piv.p, h->cinv.p);
 }
 
 // ---- setup driver ---------------------------------------------------------------------
@@ -564,6 +604,72 @@ static void make_f32(DBuf<float>& dst, const DBuf<double>& src, size_t n, hipStr
     if (n) TP_LAUNCH(k_to_f32, cdiv(n, B), B, 0, s, (int64_t)n, src.p, dst.p);
 }
 
+// ---- DIA detection --------------------------------------------------------------------
+// Every entry's offset col - row must belong to the offsets of one probe row.
+__global__ void __launch_bounds__(B)
+k_dia_check(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col, int nd,
+            const int32_t* __restrict__ offs, int32_t* __restrict__ bad) {
+    int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n) return;
+    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+        int32_t o = col[q] - i;
+        bool found = false;
+        for (int d = 0; d < nd; ++d) found |= (offs[d] == o);
+        if (!found) *bad = 1;
+    }
+}
+
+__global__ void __launch_bounds__(B)
+k_dia_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+           const double* __restrict__ val, int nd, const int32_t* __restrict__ offs,
+           double* __restrict__ dia) {
+    int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n) return;
+    for (int d = 0; d < nd; ++d) dia[(int64_t)d * n + i] = 0.0;
+    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+        int32_t o = col[q] - i;
+        for (int d = 0; d < nd; ++d)
+            if (offs[d] == o) dia[(int64_t)d * n + i] = val[q];
+    }
+}
+
+static void try_dia(tp_amg* h, Level& L, hipStream_t s) {
+    const int32_t n = L.A.n;
+    if (n < 1024 || L.A.nnz > 8LL * n) return;
+    // probe: the longest row among a few sampled rows
+    int32_t best_len = -1, best_row = 0;
+    for (uint32_t k = 1; k <= 15; ++k) {
+        int32_t r = (int32_t)((k * 2654435761u) % (uint32_t)n);
+        int32_t rp[2];
+        TP_HIP(hipMemcpyAsync(rp, L.A.rowptr.p + r, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        TP_HIP(hipStreamSynchronize(s));
+        if (rp[1] - rp[0] > best_len) { best_len = rp[1] - rp[0]; best_row = r; }
+    }
+    if (best_len < 3 || best_len > 7 || (best_len % 2) == 0) return;
+    int32_t rp0 = 0, cols[7];
+    TP_HIP(hipMemcpyAsync(&rp0, L.A.rowptr.p + best_row, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    TP_HIP(hipStreamSynchronize(s));
+    TP_HIP(hipMemcpyAsync(cols, L.A.col.p + rp0, sizeof(int32_t) * best_len, hipMemcpyDeviceToHost, s));
+    TP_HIP(hipStreamSynchronize(s));
+    int32_t offs[7];
+    for (int d = 0; d < best_len; ++d) offs[d] = cols[d] - best_row;
+    DBuf<int32_t> doffs(best_len, s), bad(1, s);
+    TP_HIP(hipMemcpyAsync(doffs.p, offs, sizeof(int32_t) * best_len, hipMemcpyHostToDevice, s));
+    TP_LAUNCH(k_fill_i32, 1, B, 0, s, bad.p, 0, (int64_t)1);
+    TP_LAUNCH(k_dia_check, cdiv(n, B), B, 0, s, n, L.A.rowptr.p, L.A.col.p, best_len, doffs.p, bad.p);
+    if (read_i32(bad.p, s)) return;
+    L.ndia = best_len;
+    for (int d = 0; d < best_len; ++d) L.dia_off[d] = offs[d];
+    L.dia.alloc((size_t)best_len * n, s);
+    TP_LAUNCH(k_dia_fill, cdiv(n, B), B, 0, s, n, L.A.rowptr.p, L.A.col.p, L.A.val.p, best_len, doffs.p,
+              L.dia.p);
+    if (h->prm.storage == 1) {
+        L.dia32.alloc((size_t)best_len * n, s);
+        TP_LAUNCH(k_to_f32, cdiv((int64_t)best_len * n, B), B, 0, s, (int64_t)best_len * n, L.dia.p, L.dia32.p);
+    }
+    TP_HIP(hipStreamSynchronize(s));  // doffs is host-staged above
+}
+
 static void alloc_work(tp_amg* h, hipStream_t s) {
     size_t es = storage_bytes(h);
     for (auto& L : h->lev) {
@@ -576,6 +682,7 @@ static void alloc_work(tp_amg* h, hipStream_t s) {
         L.gA = lanes_for(L.A.n, L.A.nnz);
         L.gP = lanes_for(L.P.n, L.P.nnz);
         L.gR = lanes_for(L.R.n, L.R.nnz);
+        if (&L != &h->lev.back()) try_dia(h, L, s);
         if (h->prm.storage == 1) {
             make_f32(L.A32, L.A.val, L.A.nnz, s);
             make_f32(L.dinv32, L.dinv, L.A.n, s);

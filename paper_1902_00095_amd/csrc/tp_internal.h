@@ -6,6 +6,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdarg>
 #include <cstdint>
@@ -118,9 +119,21 @@ struct KernelTimer {
     size_t used = 0;
 };
 KernelTimer& timer();
-// Record events around a launch when the timer is on (begin returns index).
-int timer_begin(hipStream_t s, double bytes);
-void timer_end(int idx, hipStream_t s);
+// When the timer is on, reserve an event pair for one launch of the timed
+// kernel (returns false when off).  The pair is handed to
+// hipExtLaunchKernelGGL, which stamps the kernel's own dispatch start and
+// completion, so the interval is the kernel's execution time.
+bool timer_events(double bytes, hipEvent_t* start, hipEvent_t* stop);
 void timer_collect();  // fold recorded pairs into totals (synchronises events)
+
+// Launch, with the timer's event pair when `timed` (null events otherwise).
+#define TP_LAUNCH_TIMED(timed, bytes, kernel, grid, block, shmem, stream, ...)           \
+    do {                                                                              \
+        hipEvent_t e0_ = nullptr, e1_ = nullptr;                                      \
+        if (timed) ::tp::timer_events((bytes), &e0_, &e1_);                           \
+        hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), shmem, stream, e0_, e1_, 0, \
+                              __VA_ARGS__);                                           \
+        TP_HIP(hipGetLastError());                                                    \
+    } while (0)
 
 }  // namespace tp

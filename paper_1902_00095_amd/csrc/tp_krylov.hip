@@ -35,7 +35,6 @@ namespace tp {
 
 constexpr int KB = 256;
 constexpr int MAXK = 32;      // restart length bound (H has MAXK+1 rows)
-constexpr int TILE = 1024;
 
 // ---- layout ----------------------------------------------------------------------
 __global__ void __launch_bounds__(KB)
@@ -52,6 +51,10 @@ k_interleave(int32_t n, const double* __restrict__ in, double* __restrict__ out)
     if (i >= n) return;
     out[2 * i] = in[i];
     out[2 * i + 1] = in[n + i];
+}
+
+__global__ void k_zero_u32(unsigned int* p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0u;
 }
 
 __global__ void __launch_bounds__(KB)
@@ -117,99 +120,122 @@ k_block_spmv(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restric
 }
 
 // ---- CGS2 building blocks -------------------------------------------------------------
-// mode 0: part[blk][i] = sum_e V_i[e] w[e]                      (i < k)
-// mode 1: w -= sum_i h_i V_i, then part[blk][i] = V_i . w_new     (i < k)
-// mode 2: w -= sum_i h_i V_i (k may be 0), then part[blk][0] = w_new . w_new
-__global__ void __launch_bounds__(KB)
-k_cgs(int64_t N, int k, const double* __restrict__ V, const double* __restrict__ h, double* __restrict__ w,
-      int mode, double* __restrict__ part) {
-    __shared__ double wt[TILE];
-    __shared__ double acc[MAXK + 1];
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int nwaves = KB / 64;
-    for (int i = t; i <= MAXK; i += KB) acc[i] = 0.0;
-    __syncthreads();
-    const int64_t ntiles = (N + TILE - 1) / TILE;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int64_t base = tile * TILE;
-        for (int e = t; e < TILE; e += KB) {
-            int64_t g = base + e;
-            double v = 0.0;
-            if (g < N) {
-                v = w[g];
-                if (mode >= 1) {
-                    for (int i = 0; i < k; ++i) v -= h[i] * V[(int64_t)i * N + g];
-                    w[g] = v;
-                }
-            }
-            wt[e] = v;
-        }
-        __syncthreads();
-        if (mode == 2) {
-            if (wave == 0) {
-                double s = 0.0;
-                for (int e = lane; e < TILE; e += 64) s += wt[e] * wt[e];
-                for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-                if (lane == 0) acc[0] += s;
-            }
-        } else {
-            for (int i = wave; i < k; i += nwaves) {
-                const double* Vi = V + (int64_t)i * N + base;
-                double s = 0.0;
-                for (int e = lane; e < TILE; e += 64)
-                    if (base + e < N) s += Vi[e] * wt[e];
-                for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-                if (lane == 0) acc[i] += s;
-            }
-        }
-        __syncthreads();
-    }
-    const int cnt = mode == 2 ? 1 : k;
-    for (int i = t; i < cnt; i += KB) part[(int64_t)blockIdx.x * (MAXK + 1) + i] = acc[i];
+// One pass over the basis V_0..V_{k-1} (each column read once):
+//   mode 0: out[i] = V_i . w
+//   mode 1: w <- w - sum_i h_i V_i, then out[i] = V_i . w_new
+//   mode 2: w <- w - sum_i h_i V_i (k may be 0), then out[0] = w_new . w_new
+// Elements are assigned to threads by a fixed grid-stride pattern; each
+// block writes partial sums (vector-major), and the last block to finish
+// reduces them in a fixed order, so the result is run-to-run deterministic.
+// With `arn` set (mode 2), that last block also performs the Arnoldi column
+// update (Givens rotations) for column j.
+constexpr int CG_T = 256;
+constexpr int CG_W = CG_T / 64;
+
+struct ArnoldiArgs {
+    int j, m;
+    const double* h1;
+    const double* h2;
+    double* H;
+    double* cs;
+    double* sn;
+    double* g;
+    double* sc;  // [0] ||w||, [1] |g[j+1]|
+};
+
+__device__ inline double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
 }
 
-// out[i] = sum over blocks of part[b][i], fixed order (one block)
-__global__ void __launch_bounds__(KB)
-k_reduce_parts(int nb, int k, const double* __restrict__ part, double* __restrict__ out) {
-    __shared__ double sh[KB];
-    for (int i = 0; i < k; ++i) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nb; b += KB) s += part[(int64_t)b * (MAXK + 1) + i];
-        sh[threadIdx.x] = s;
-        __syncthreads();
-        for (int off = KB / 2; off > 0; off >>= 1) {
-            if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[i] = sh[0];
-        __syncthreads();
-    }
-}
-
-// Arnoldi column j: H[:,j] = h1 + h2, H[j+1,j] = ||w||, Givens update of H and
-// g; est = |g[j+1]|.  sc layout: [0] ||w||, [1] est.
-__global__ void k_arnoldi(int j, int m, const double* __restrict__ h1, const double* __restrict__ h2,
-                          const double* __restrict__ nrm2, double* __restrict__ H, double* __restrict__ cs,
-                          double* __restrict__ sn, double* __restrict__ g, double* __restrict__ sc) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    for (int i = 0; i <= j; ++i) H[i * m + j] = h1[i] + h2[i];
-    const double hn = sqrt(nrm2[0]);
+__device__ void arnoldi_update(const ArnoldiArgs& a, double nrm2) {
+    const int j = a.j, m = a.m;
+    double* H = a.H;
+    for (int i = 0; i <= j; ++i) H[i * m + j] = a.h1[i] + a.h2[i];
+    const double hn = sqrt(nrm2);
     H[(j + 1) * m + j] = hn;
     for (int i = 0; i < j; ++i) {
-        double a = H[i * m + j], c = H[(i + 1) * m + j];
-        H[i * m + j] = cs[i] * a + sn[i] * c;
-        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+        double x = H[i * m + j], y = H[(i + 1) * m + j];
+        H[i * m + j] = a.cs[i] * x + a.sn[i] * y;
+        H[(i + 1) * m + j] = -a.sn[i] * x + a.cs[i] * y;
     }
-    double a = H[j * m + j], c = H[(j + 1) * m + j];
-    double den = hypot(a, c);
-    cs[j] = a / den;
-    sn[j] = c / den;
+    double x = H[j * m + j], y = H[(j + 1) * m + j];
+    double den = hypot(x, y);
+    a.cs[j] = x / den;
+    a.sn[j] = y / den;
     H[j * m + j] = den;
     H[(j + 1) * m + j] = 0.0;
-    g[j + 1] = -sn[j] * g[j];
-    g[j] = cs[j] * g[j];
-    sc[0] = hn;
-    sc[1] = fabs(g[j + 1]);
+    a.g[j + 1] = -a.sn[j] * a.g[j];
+    a.g[j] = a.cs[j] * a.g[j];
+    a.sc[0] = hn;
+    a.sc[1] = fabs(a.g[j + 1]);
+}
+
+template <int K>
+__global__ void __launch_bounds__(CG_T)
+k_cgs(int64_t N, const double* __restrict__ V, const double* __restrict__ h, double* __restrict__ w,
+      int mode, double* __restrict__ part) {
+    constexpr int KA = K > 0 ? K : 1;
+    __shared__ double red[CG_W][KA];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int nb = gridDim.x;
+    double acc[KA];
+    double hh[KA];
+#pragma unroll
+    for (int i = 0; i < KA; ++i) {
+        acc[i] = 0.0;
+        hh[i] = (mode >= 1 && i < K) ? h[i] : 0.0;
+    }
+    const int64_t stride = (int64_t)nb * CG_T;
+    for (int64_t e = (int64_t)blockIdx.x * CG_T + t; e < N; e += stride) {
+        double we = w[e];
+        double v[KA];
+#pragma unroll
+        for (int i = 0; i < K; ++i) v[i] = V[(int64_t)i * N + e];
+        if (mode >= 1) {
+#pragma unroll
+            for (int i = 0; i < K; ++i) we -= hh[i] * v[i];
+            w[e] = we;
+        }
+        if (mode == 2) {
+            acc[0] += we * we;
+        } else {
+#pragma unroll
+            for (int i = 0; i < K; ++i) acc[i] += v[i] * we;
+        }
+    }
+    const int cnt = mode == 2 ? 1 : K;
+#pragma unroll
+    for (int i = 0; i < KA; ++i) {
+        if (i < cnt) {
+            double s = wave_sum(acc[i]);
+            if (lane == 0) red[wave][i] = s;
+        }
+    }
+    __syncthreads();
+    if (t < cnt) {
+        double s = 0.0;
+        for (int q = 0; q < CG_W; ++q) s += red[q][t];
+        part[(int64_t)t * nb + blockIdx.x] = s;
+    }
+}
+
+// Sum the per-block partials (one wavefront per vector, fixed order); with
+// `arn`, thread 0 then performs the Arnoldi column update.
+constexpr int FIN_T = 1024;
+__global__ void __launch_bounds__(FIN_T)
+k_cgs_finish(int nb, int cnt, const double* __restrict__ part, double* __restrict__ out, int arn,
+             ArnoldiArgs aa) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    for (int i = wave; i < cnt; i += FIN_T / 64) {
+        double s = 0.0;
+        for (int b = lane; b < nb; b += 64) s += part[(int64_t)i * nb + b];
+        s = wave_sum(s);
+        if (lane == 0) out[i] = s;
+    }
+    if (!arn) return;
+    __syncthreads();
+    if (t == 0) arnoldi_update(aa, out[0]);
 }
 
 // v = w / nrm (nrm on device)
@@ -302,9 +328,10 @@ struct Gmres {
     int m;
     int nb;
     DBuf<double> V, Z, w, b, x, r, H, cs, sn, g, y, h1, h2, nrm2, part, sc;
+    DBuf<unsigned int> ticket;
     HostMail mail;
     Gmres(int32_t n_, int m_, hipStream_t s) : n(n_), N(2 * (int64_t)n_), m(m_) {
-        nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (N + TILE - 1) / TILE));
+        nb = (int)std::min<int64_t>(512, std::max<int64_t>(1, (N + 2 * CG_T - 1) / (2 * CG_T)));
         V.alloc((size_t)(m + 1) * N, s);
         Z.alloc((size_t)m * N, s);
         w.alloc(N, s);
@@ -319,14 +346,31 @@ struct Gmres {
         h1.alloc(MAXK + 1, s);
         h2.alloc(MAXK + 1, s);
         nrm2.alloc(1, s);
-        part.alloc((size_t)nb * (MAXK + 1), s);
+        part.alloc((size_t)nb * MAXK, s);
         sc.alloc(4, s);
+        ticket.alloc(1, s);
+        TP_LAUNCH(k_zero_u32, 1, 64, 0, s, ticket.p);
     }
 };
 
-static void dots(Gmres& G, int k, const double* h, double* w, int mode, double* out, hipStream_t s) {
-    TP_LAUNCH(k_cgs, G.nb, KB, 0, s, G.N, k, G.V.p, h, w, mode, G.part.p);
-    TP_LAUNCH(k_reduce_parts, 1, KB, 0, s, G.nb, mode == 2 ? 1 : k, G.part.p, out);
+static void dots(Gmres& G, int k, const double* h, double* w, int mode, double* out, hipStream_t s,
+                 int arn = 0, int j = 0) {
+    ArnoldiArgs aa{j, G.m, G.h1.p, G.h2.p, G.H.p, G.cs.p, G.sn.p, G.g.p, G.sc.p};
+#define TP_CGS_CASE(KK)                                                                                 \
+    case KK:                                                                                            \
+        TP_LAUNCH(k_cgs<KK>, G.nb, CG_T, 0, s, G.N, G.V.p, h, w, mode, G.part.p);                       \
+        break;
+    switch (k) {
+        TP_CGS_CASE(0) TP_CGS_CASE(1) TP_CGS_CASE(2) TP_CGS_CASE(3) TP_CGS_CASE(4) TP_CGS_CASE(5)
+        TP_CGS_CASE(6) TP_CGS_CASE(7) TP_CGS_CASE(8) TP_CGS_CASE(9) TP_CGS_CASE(10) TP_CGS_CASE(11)
+        TP_CGS_CASE(12) TP_CGS_CASE(13) TP_CGS_CASE(14) TP_CGS_CASE(15) TP_CGS_CASE(16) TP_CGS_CASE(17)
+        TP_CGS_CASE(18) TP_CGS_CASE(19) TP_CGS_CASE(20) TP_CGS_CASE(21) TP_CGS_CASE(22) TP_CGS_CASE(23)
+        TP_CGS_CASE(24) TP_CGS_CASE(25) TP_CGS_CASE(26) TP_CGS_CASE(27) TP_CGS_CASE(28) TP_CGS_CASE(29)
+        TP_CGS_CASE(30) TP_CGS_CASE(31)
+    default: fail(TP_ERR_ARG, "basis size %d exceeds %d", k, MAXK - 1);
+    }
+#undef TP_CGS_CASE
+    TP_LAUNCH(k_cgs_finish, 1, FIN_T, 0, s, G.nb, mode == 2 ? 1 : k, G.part.p, out, arn, aa);
 }
 
 static double read_d(const double* dptr, HostMail& mail, hipStream_t s) {
@@ -374,9 +418,7 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
                           (const double*)nullptr, G.w.p);
                 dots(G, j + 1, nullptr, G.w.p, 0, G.h1.p, s);
                 dots(G, j + 1, G.h1.p, G.w.p, 1, G.h2.p, s);
-                dots(G, j + 1, G.h2.p, G.w.p, 2, G.nrm2.p, s);
-                TP_LAUNCH(k_arnoldi, 1, 1, 0, s, j, m, G.h1.p, G.h2.p, G.nrm2.p, G.H.p, G.cs.p, G.sn.p, G.g.p,
-                          G.sc.p);
+                dots(G, j + 1, G.h2.p, G.w.p, 2, G.nrm2.p, s, 1, j);
                 TP_LAUNCH(k_scale_div, gN, KB, 0, s, G.N, G.w.p, G.sc.p, G.V.p + (int64_t)(j + 1) * G.N);
                 TP_HIP(hipMemcpyAsync(G.mail.p, G.sc.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
                 TP_HIP(hipStreamSynchronize(s));

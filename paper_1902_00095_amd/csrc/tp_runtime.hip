@@ -146,24 +146,20 @@ KernelTimer& timer() {
     return t;
 }
 
-int timer_begin(hipStream_t s, double bytes) {
+bool timer_events(double bytes, hipEvent_t* start, hipEvent_t* stop) {
     KernelTimer& t = timer();
-    if (!t.on) return -1;
+    if (!t.on) return false;
     if (t.used * 2 + 2 > t.ev.size()) {
         size_t old = t.ev.size();
         t.ev.resize(old == 0 ? 512 : old * 2);
         for (size_t i = old; i < t.ev.size(); ++i) TP_HIP(hipEventCreate(&t.ev[i]));
         t.ev_bytes.resize(t.ev.size() / 2);
     }
-    int idx = (int)t.used++;
+    size_t idx = t.used++;
     t.ev_bytes[idx] = bytes;
-    TP_HIP(hipEventRecord(t.ev[2 * idx], s));
-    return idx;
-}
-
-void timer_end(int idx, hipStream_t s) {
-    if (idx < 0) return;
-    TP_HIP(hipEventRecord(timer().ev[2 * idx + 1], s));
+    *start = t.ev[2 * idx];
+    *stop = t.ev[2 * idx + 1];
+    return true;
 }
 
 void timer_collect() {

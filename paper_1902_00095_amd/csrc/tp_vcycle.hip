@@ -99,6 +99,72 @@ k_spmv(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci
     if (valid && lane == 0) y[i] = add ? y[i] + s : s;
 }
 
+// ---- DIA (stencil-level) kernels: one thread per row, no column indices --------
+template <int ND>
+struct DiaOff {
+    int32_t o[ND];
+};
+
+template <typename T, int ND>
+__device__ inline T dia_dot(int32_t n, const T* __restrict__ dv, DiaOff<ND> off, const T* __restrict__ x,
+                            int32_t i) {
+    T s = 0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        int32_t j = i + off.o[d];
+        j = j < 0 ? 0 : (j >= n ? n - 1 : j);  // out-of-range slots hold 0
+        s += dv[(int64_t)d * n + i] * x[j];
+    }
+    return s;
+}
+
+template <typename T, int ND>
+__global__ void __launch_bounds__(VB)
+k_cheb_step_dia(int32_t n, const T* __restrict__ dv, DiaOff<ND> off, const T* __restrict__ dinv,
+                const T* __restrict__ b, const T* __restrict__ xin, T* __restrict__ xout, T* __restrict__ d,
+                int first, T theta, T c1, T c2) {
+    const int32_t i = blockIdx.x * VB + threadIdx.x;
+    if (i >= n) return;
+    T ax = dia_dot<T, ND>(n, dv, off, xin, i);
+    T r = dinv[i] * (b[i] - ax);
+    T dn = first ? r / theta : c1 * d[i] + c2 * r;
+    d[i] = dn;
+    xout[i] = xin[i] + dn;
+}
+
+template <typename T, int ND>
+__global__ void __launch_bounds__(VB)
+k_jac_step_dia(int32_t n, const T* __restrict__ dv, DiaOff<ND> off, const T* __restrict__ dinv,
+               const T* __restrict__ b, const T* __restrict__ xin, T* __restrict__ xout, T w) {
+    const int32_t i = blockIdx.x * VB + threadIdx.x;
+    if (i >= n) return;
+    T ax = dia_dot<T, ND>(n, dv, off, xin, i);
+    xout[i] = xin[i] + w * dinv[i] * (b[i] - ax);
+}
+
+template <typename T, int ND>
+__global__ void __launch_bounds__(VB)
+k_residual_dia(int32_t n, const T* __restrict__ dv, DiaOff<ND> off, const T* __restrict__ b,
+               const T* __restrict__ x, T* __restrict__ r) {
+    const int32_t i = blockIdx.x * VB + threadIdx.x;
+    if (i >= n) return;
+    r[i] = b[i] - dia_dot<T, ND>(n, dv, off, x, i);
+}
+
+#define TP_ND_DISPATCH(nd, ...)                                 \
+    switch (nd) {                                               \
+    case 3: { constexpr int NDD = 3; __VA_ARGS__; } break;      \
+    case 5: { constexpr int NDD = 5; __VA_ARGS__; } break;      \
+    default: { constexpr int NDD = 7; __VA_ARGS__; } break;     \
+    }
+
+template <int ND>
+static DiaOff<ND> dia_offsets(const Level& L) {
+    DiaOff<ND> o;
+    for (int d = 0; d < ND; ++d) o.o[d] = L.dia_off[d];
+    return o;
+}
+
 // first sweep from a zero guess
 template <typename T>
 __global__ void __launch_bounds__(VB)
@@ -151,12 +217,14 @@ k_coarse_solve(int32_t n, const double* __restrict__ inv, const T* __restrict__ 
 
 template <typename T> struct LevelVals;
 template <> struct LevelVals<double> {
+    static const double* D(const Level& L) { return L.dia.p; }
     static const double* A(const Level& L) { return L.A.val.p; }
     static const double* P(const Level& L) { return L.P.val.p; }
     static const double* R(const Level& L) { return L.R.val.p; }
     static const double* dinv(const Level& L) { return L.dinv.p; }
 };
 template <> struct LevelVals<float> {
+    static const float* D(const Level& L) { return L.dia32.p; }
     static const float* A(const Level& L) { return L.A32.p; }
     static const float* P(const Level& L) { return L.P32.p; }
     static const float* R(const Level& L) { return L.R32.p; }
@@ -190,11 +258,17 @@ static T* smooth(tp_amg* h, int l, const T* b, T* xc, bool zero, int nu, hipStre
         if (p.smoother == 0) {
             if (z) continue;
             T* nx = other(cur);
-            double bytes = (double)L.A.nnz * (es + 4) + 4.0 * (n + 1) + 4.0 * es * n;
-            int ti = l == 0 ? timer_begin(s, bytes) : -1;
-            TP_G_DISPATCH(L.gA, TP_LAUNCH((k_jac_step<T, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p,
-                                          L.A.col.p, av, dv, b, cur, nx, (T)p.omega));
-            timer_end(ti, s);
+            double bytes = (L.ndia ? (double)L.ndia * n * es : (double)L.A.nnz * (es + 4) + 4.0 * (n + 1)) +
+                           4.0 * es * n;
+            const bool timed = l == 0;
+            if (L.ndia) {
+                TP_ND_DISPATCH(L.ndia, TP_LAUNCH_TIMED(timed, bytes, (k_jac_step_dia<T, NDD>), cdiv(n, VB), VB, 0,
+                                                       s, n, LevelVals<T>::D(L), dia_offsets<NDD>(L), dv, b, cur,
+                                                       nx, (T)p.omega));
+            } else {
+                TP_G_DISPATCH(L.gA, TP_LAUNCH_TIMED(timed, bytes, (k_jac_step<T, GG>), grid_rows(n, GG), VB, 0, s,
+                                                    n, L.A.rowptr.p, L.A.col.p, av, dv, b, cur, nx, (T)p.omega));
+            }
             cur = nx;
             continue;
         }
@@ -211,11 +285,18 @@ static T* smooth(tp_amg* h, int l, const T* b, T* xc, bool zero, int nu, hipStre
                 c2 = 2.0 * rho1 / delta;
                 rho0 = rho1;
             }
-            double bytes = (double)L.A.nnz * (es + 4) + 4.0 * (n + 1) + (first ? 5.0 : 6.0) * es * n;
-            int ti = l == 0 ? timer_begin(s, bytes) : -1;
-            TP_G_DISPATCH(L.gA, TP_LAUNCH((k_cheb_step<T, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p,
-                                          L.A.col.p, av, dv, b, cur, nx, d, first, (T)theta, (T)c1, (T)c2));
-            timer_end(ti, s);
+            double bytes = (L.ndia ? (double)L.ndia * n * es : (double)L.A.nnz * (es + 4) + 4.0 * (n + 1)) +
+                           (first ? 5.0 : 6.0) * es * n;
+            const bool timed = l == 0;
+            if (L.ndia) {
+                TP_ND_DISPATCH(L.ndia, TP_LAUNCH_TIMED(timed, bytes, (k_cheb_step_dia<T, NDD>), cdiv(n, VB), VB, 0,
+                                                       s, n, LevelVals<T>::D(L), dia_offsets<NDD>(L), dv, b, cur,
+                                                       nx, d, first, (T)theta, (T)c1, (T)c2));
+            } else {
+                TP_G_DISPATCH(L.gA, TP_LAUNCH_TIMED(timed, bytes, (k_cheb_step<T, GG>), grid_rows(n, GG), VB, 0, s,
+                                                    n, L.A.rowptr.p, L.A.col.p, av, dv, b, cur, nx, d, first,
+                                                    (T)theta, (T)c1, (T)c2));
+            }
             cur = nx;
         }
     }
@@ -237,8 +318,13 @@ static T* vcycle_level(tp_amg* h, int l, const T* b, hipStream_t s) {
     if (p.nu_pre > 0) cur = smooth<T>(h, l, b, cur, true, p.nu_pre, s);
     else TP_LAUNCH(k_zero<T>, cdiv(n, VB), VB, 0, s, n, cur);
     T* r = (T*)L.r.p;
-    TP_G_DISPATCH(L.gA, TP_LAUNCH((k_residual<T, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p, L.A.col.p,
-                                  LevelVals<T>::A(L), b, cur, r));
+    if (L.ndia) {
+        TP_ND_DISPATCH(L.ndia, TP_LAUNCH((k_residual_dia<T, NDD>), cdiv(n, VB), VB, 0, s, n, LevelVals<T>::D(L),
+                                         dia_offsets<NDD>(L), b, cur, r));
+    } else {
+        TP_G_DISPATCH(L.gA, TP_LAUNCH((k_residual<T, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p,
+                                      L.A.col.p, LevelVals<T>::A(L), b, cur, r));
+    }
     Level& Ln = h->lev[l + 1];
     T* bc = (T*)Ln.b.p;
     TP_G_DISPATCH(L.gR, TP_LAUNCH((k_spmv<T, GG>), grid_rows(L.R.n, GG), VB, 0, s, L.R.n, L.R.rowptr.p,
