@@ -169,10 +169,21 @@ int precond_destroy(tp_prec_t M);
  * relative residual ||b - J x||_2 / ||b||_2 <= rtol (checked in FP64 at the
  * end of every cycle) or after maxit iterations.
  * ------------------------------------------------------------------------ */
-typedef struct { double rtol; int32_t restart; int32_t maxit; } tp_krylov_params;
+typedef struct {
+    double rtol;
+    int32_t restart;
+    int32_t maxit;
+    /* Stagnation guard for a learned post-smoother attached to the Schur
+     * hierarchy: when the residual estimate of iteration j exceeds
+     * stag_ratio times that of iteration j-2 (or the network produced a
+     * non-finite value), the network is switched off for the rest of the
+     * solve and the hierarchy's own post-smoother is used.  0 disables. */
+    double stag_ratio;
+} tp_krylov_params;
 typedef struct {
     int32_t iters, restarts;
     double rel_true, rel_est;
+    int32_t fallback_iter;  /* iteration at which the network was switched off, -1 none */
 } tp_krylov_stats;
 
 /* Solve J x = b (2n interleaved device vectors; x holds the initial guess on
@@ -182,6 +193,54 @@ typedef struct {
 int fgmres_solve(const tp_jacobian* J, tp_prec_t M, const double* b, double* x,
                  const tp_krylov_params* params, tp_krylov_stats* stats,
                  double* history, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned post-smoother on the finest level of the Schur-approximation
+ * hierarchy (a method pattern on top of the paper's V-cycle; the paper has
+ * no learned component).  Network: 3x3x3 convolution 8 -> 16 channels +
+ * bias, ReLU, 3x3x3 convolution 16 -> 1 + bias, zero padding; BF16 weights
+ * and inputs, FP32 accumulation.  Parameters (3905 floats) are laid out
+ * W1[16][8][27], b1[16], W2[16][27], b2[1], tap t = (dz+1)*9 + (dy+1)*3 + (dx+1).
+ * Input features per cell (8 x n, channel-major, FP32): (D^{-1} r)/s with
+ * s = RMS(D^{-1} r) and D the l1 diagonal; a_{i,nbr}/a_ii for the -x, +x,
+ * -y, +y, -z, +z neighbours (0 off-grid); a_ii / D_ii.  The smoother update
+ * is x <- x + s * out.
+ * ------------------------------------------------------------------------ */
+typedef struct tp_cnn* tp_cnn_t;
+#define TP_CNN_NPARAM 3905
+/* params: host array of TP_CNN_NPARAM finite floats (copied). */
+int cnn_create(const float* params, tp_cnn_t* out);
+/* current FP32 master parameters into a host array */
+int cnn_get_params(tp_cnn_t net, float* params);
+int cnn_destroy(tp_cnn_t net);
+/* gradient of the last loss evaluation (cnn_loss_grad / amg_cnn_loss_grad) into a host array */
+int cnn_get_grad(tp_cnn_t net, float* grad);
+/* out (n, device) = network(feat) on the grid; feat: 8 x n device FP32 */
+int cnn_forward(tp_cnn_t net, const tp_grid* grid, const float* feat, float* out, void* stream);
+/* Loss mean_i (out_i - target_i)^2 and its gradient, kept in the handle for
+ * cnn_adam_step; grad (device, TP_CNN_NPARAM) and loss (host) optional. */
+int cnn_loss_grad(tp_cnn_t net, const tp_grid* grid, const float* feat, const float* target,
+                  double* loss, float* grad, void* stream);
+/* One Adam step (beta 0.9/0.999, eps 1e-8) with the last gradient. */
+int cnn_adam_step(tp_cnn_t net, float lr, void* stream);
+/* Attach `net` as the finest-level post-smoother of `amg` (the grid must
+ * have amg's level-0 size; the level must be that grid's stencil matrix);
+ * net = NULL detaches.  The network must outlive the attachment. */
+int amg_attach_post_smoother(tp_amg_t amg, tp_cnn_t net, const tp_grid* grid);
+/* Features (8 x n device FP32) of residual r (n device FP64) on the
+ * finest level of a hierarchy with an attached network; scale (host, optional). */
+int amg_features(tp_amg_t amg, const double* r, float* feat, float* scale, void* stream);
+/* Loss of the attached network measured in the D^{-1} A norm of the
+ * hierarchy's finest-level operator A (D its l1 diagonal):
+ * L = mean_i (D^{-1} A (out - target))_i^2 with out = network(feat); for
+ * target = e/s this is the residual the correction leaves behind.  The
+ * gradient is kept in the network handle for cnn_adam_step; loss (host) optional. */
+int amg_cnn_loss_grad(tp_amg_t amg, const float* feat, const float* target, double* loss,
+                      void* stream);
+/* Training pair at the finest-level post-smoothing point: b = A y, one
+ * V-cycle from a zero guess stopped before level-0 post-smoothing gives x;
+ * r = b - A x and e = y - x (all n, device FP64). */
+int amg_presmoothed_pair(tp_amg_t amg, const double* y, double* r, double* e, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Measurement support: HIP-event timing of the fine-level smoother kernel

@@ -292,3 +292,52 @@ def gmres(J: Jacobian, amg_pp, amg_S, b, x0=None, variant="lower", rtol=1e-8,
                         C.c_int32(maxit), C.byref(it), C.byref(rel), _p(hist))
     return x, dict(converged=(st == 0), iters=it.value, rel_true=rel.value,
                    history=hist[: it.value + 1])
+
+
+# ---- learned post-smoother network -------------------------------------------------
+CNN_SIZES = dict(W1=16 * 8 * 27, b1=16, W2=16 * 27, b2=1)
+CNN_NPARAM = sum(CNN_SIZES.values())
+
+
+def cnn_unpack(theta):
+    theta = np.asarray(theta, dtype=np.float64)
+    o = 0
+    out = {}
+    for k, m in CNN_SIZES.items():
+        out[k] = theta[o:o + m]
+        o += m
+    return out
+
+
+def cnn_forward(grid, theta, f):
+    """out (n,) and pre-activations h (16, n) for features f (8, n)."""
+    p = cnn_unpack(theta)
+    n = grid.n
+    f = _f64(f).reshape(8, n)
+    h = np.zeros((16, n))
+    out = np.zeros(n)
+    lib().or_cnn_forward(C.byref(_grid(grid)), _p(_f64(p["W1"])), _p(_f64(p["b1"])),
+                         _p(_f64(p["W2"])), C.c_double(float(p["b2"][0])), _p(f), _p(h), _p(out))
+    return out, h
+
+
+def cnn_backward(grid, theta, f, y):
+    """(loss, gradient with the layout of theta) for target y."""
+    p = cnn_unpack(theta)
+    n = grid.n
+    g = np.zeros(CNN_NPARAM)
+    lib().or_cnn_backward.restype = C.c_double
+    loss = lib().or_cnn_backward(C.byref(_grid(grid)), _p(_f64(p["W1"])), _p(_f64(p["b1"])),
+                                 _p(_f64(p["W2"])), C.c_double(float(p["b2"][0])),
+                                 _p(_f64(f).reshape(8, n)), _p(_f64(y)), _p(g))
+    return float(loss), g
+
+
+def cnn_features(grid, rowptr, col, val, r):
+    """features (8, n) and the scale s of the learned smoother's input."""
+    n = grid.n
+    f = np.zeros((8, n))
+    lib().or_cnn_features.restype = C.c_double
+    s = lib().or_cnn_features(C.byref(_grid(grid)), _p(_i32(rowptr)), _p(_i32(col)), _p(_f64(val)),
+                              _p(_f64(r)), _p(f))
+    return f, float(s)

@@ -104,6 +104,14 @@ int or_gmres(const or_jac* J, const or_amg* amg_pp, const or_amg* amg_S,
              int32_t restart, int32_t maxit, int32_t* iters, double* rel_true,
              double* history);
 
+/* ---- Learned post-smoother network (see cnn.c) ------------------------ */
+void or_cnn_forward(const or_grid* g, const double* W1, const double* b1, const double* W2,
+                    double b2, const double* f, double* h, double* out);
+double or_cnn_backward(const or_grid* g, const double* W1, const double* b1, const double* W2,
+                       double b2, const double* f, const double* y, double* grad);
+double or_cnn_features(const or_grid* g, const int32_t* rowptr, const int32_t* col,
+                       const double* val, const double* r, double* f);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2,15 +2,11 @@
 // block preconditioner.
 #pragma once
 
-#include "tp_internal.h"
+#include "tp_cnn.h"
+
+#include <memory>
 
 namespace tp {
-
-struct Csr {
-    int32_t n = 0, m = 0, nnz = 0;  // n rows, m columns
-    DBuf<int32_t> rowptr, col;
-    DBuf<double> val;
-};
 
 // Lanes cooperating on one CSR row in the row-group SpMV kernels.
 int lanes_for(int32_t n, int64_t nnz);
@@ -39,6 +35,8 @@ struct tp_amg {
     int32_t nc = 0;              // coarsest size
     tp::DBuf<double> cinv;       // nc x nc inverse of the coarsest operator
     hipStream_t stream = nullptr;
+    std::unique_ptr<tp::tp_cnn_attach> cnn;  // learned finest-level post-smoother (optional)
+    bool stop_before_post = false;           // pair generation: end the cycle before post-smoothing
 };
 
 namespace tp {

@@ -115,7 +115,7 @@ k_sort_rows(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __rest
 }
 
 // T = A^T (m rows); values optional; rows sorted when `sorted`
-static void transpose(const int32_t* rowptr, const int32_t* col, const double* val, int32_t n,
+void transpose(const int32_t* rowptr, const int32_t* col, const double* val, int32_t n,
                       int32_t m, int32_t nnz, bool sorted, Csr& T, hipStream_t s) {
     T.n = m;
     T.m = n;

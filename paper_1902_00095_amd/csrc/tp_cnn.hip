@@ -1,0 +1,514 @@
+// tp_cnn.hip -- learned post-smoother: a two-layer 3-D convolutional network
+// applied on the finest level of the Schur-approximation hierarchy.
+//
+// Network (zero padding, 27-point 3x3x3 taps, tap t = (dz+1)*9 + (dy+1)*3 + (dx+1)):
+//   h_o(i) = b1_o + sum_{c<8} sum_t W1[o][c][t] f_c(i + t)      (16 outputs)
+//   out(i) = b2 + sum_{o<16} sum_t W2[o][t] max(h_o(i + t), 0)
+// Inputs per cell: f_0 = (D^{-1} r)_i / s with s = RMS(D^{-1} r) and D the
+// l1 diagonal, f_1..f_6 = a_{i,nbr}/a_ii (-x,+x,-y,+y,-z,+z), f_7 = a_ii/D_ii.
+// The smoother update is x <- x + s * out.  Weights are stored in BF16 and
+// features rounded to BF16; products accumulate in FP32 (the hidden
+// activations stay FP32).  A FP32 master copy
+// of the weights is kept for training (Adam).  All reductions (scale,
+// loss, gradients) use a fixed assignment of cells to threads and a fixed
+// combination order: results are run-to-run deterministic.
+#include "tp_cnn.h"
+
+#include <cmath>
+
+namespace tp {
+
+constexpr int CB = 256;
+
+__device__ inline float bf16_round(float x) {
+    // round to nearest even on the upper 16 bits (finite inputs)
+    uint32_t u = __float_as_uint(x);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;
+    return __uint_as_float(u & 0xFFFF0000u);
+}
+
+__device__ inline int32_t tap_nbr(int32_t ix, int32_t iy, int32_t iz, int t, int32_t nx, int32_t ny,
+                                  int32_t nz) {
+    int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+    int32_t x = ix + dx, y = iy + dy, z = iz + dz;
+    if (x < 0 || y < 0 || z < 0 || x >= nx || y >= ny || z >= nz) return -1;
+    return x + nx * (y + ny * z);
+}
+
+// ---- features -----------------------------------------------------------------------
+// static channels 1..7 from the stencil matrix (FP64 CSR)
+__global__ void __launch_bounds__(CB)
+k_feat_static(tp_grid g, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+              const double* __restrict__ val, float* __restrict__ f, float* __restrict__ dinv) {
+    const int32_t n = g.nx * g.ny * g.nz, nxy = g.nx * g.ny;
+    const int32_t i = blockIdx.x * CB + threadIdx.x;
+    if (i >= n) return;
+    double d = 0.0, aii = 0.0;
+    for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+        d += fabs(val[k]);
+        if (col[k] == i) aii = val[k];
+    }
+    const int32_t ix = i % g.nx, iy = (i / g.nx) % g.ny, iz = i / nxy;
+    const int32_t off[6] = {-1, 1, -g.nx, g.nx, -nxy, nxy};
+    const bool ok[6] = {ix > 0, ix < g.nx - 1, iy > 0, iy < g.ny - 1, iz > 0, iz < g.nz - 1};
+    for (int q = 0; q < 6; ++q) {
+        double a = 0.0;
+        if (ok[q])
+            for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+                if (col[k] == i + off[q]) a = val[k];
+        f[(int64_t)(1 + q) * n + i] = (float)(a / aii);
+    }
+    f[(int64_t)7 * n + i] = (float)(aii / d);
+    dinv[i] = (float)(1.0 / d);
+}
+
+// z = D^{-1} r into channel 0 (unscaled); per-block partial sums of z^2
+template <typename T>
+__global__ void __launch_bounds__(CB)
+k_feat_resid(int32_t n, const T* __restrict__ r, const float* __restrict__ dinv, float* __restrict__ f0,
+             double* __restrict__ part) {
+    __shared__ double sh[CB];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * CB + threadIdx.x; i < n; i += (int64_t)gridDim.x * CB) {
+        float z = (float)r[i] * dinv[i];
+        f0[i] = z;
+        acc += (double)z * (double)z;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = CB / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// s = sqrt(sum part / n); f0 /= s  (single block sums the partials, then all scale)
+__global__ void __launch_bounds__(CB)
+k_feat_scale_sum(int nb, int32_t n, const double* __restrict__ part, float* __restrict__ scale) {
+    __shared__ double sh[CB];
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nb; b += CB) a += part[b];
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int off = CB / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) scale[0] = n > 0 ? (float)sqrt(sh[0] / n) : 0.f;
+}
+
+__global__ void __launch_bounds__(CB)
+k_feat_normalise(int32_t n, const float* __restrict__ scale, float* __restrict__ f0) {
+    const int32_t i = blockIdx.x * CB + threadIdx.x;
+    if (i >= n) return;
+    const float s = scale[0];
+    f0[i] = s > 0.f ? f0[i] / s : 0.f;
+}
+
+// ---- forward ------------------------------------------------------------------------------
+// layer 1: h (16 x n FP32) from features (8 x n), weights from the BF16 copy
+__global__ void __launch_bounds__(CB)
+k_cnn_l1(tp_grid g, const float* __restrict__ f, const float* __restrict__ w1, const float* __restrict__ b1,
+         float* __restrict__ h) {
+    __shared__ float W[CNN_CH * CNN_CIN * CNN_NT];
+    for (int k = threadIdx.x; k < CNN_CH * CNN_CIN * CNN_NT; k += CB) W[k] = w1[k];
+    __syncthreads();
+    const int32_t n = g.nx * g.ny * g.nz;
+    const int32_t i = blockIdx.x * CB + threadIdx.x;
+    if (i >= n) return;
+    const int32_t ix = i % g.nx, iy = (i / g.nx) % g.ny, iz = i / (g.nx * g.ny);
+    float acc[CNN_CH];
+#pragma unroll
+    for (int o = 0; o < CNN_CH; ++o) acc[o] = b1[o];
+    for (int t = 0; t < CNN_NT; ++t) {
+        const int32_t j = tap_nbr(ix, iy, iz, t, g.nx, g.ny, g.nz);
+        if (j < 0) continue;
+#pragma unroll
+        for (int c = 0; c < CNN_CIN; ++c) {
+            const float fv = bf16_round(f[(int64_t)c * n + j]);
+#pragma unroll
+            for (int o = 0; o < CNN_CH; ++o) acc[o] += W[(o * CNN_CIN + c) * CNN_NT + t] * fv;
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < CNN_CH; ++o) h[(int64_t)o * n + i] = acc[o];
+}
+
+// layer 2 (FP32 activations): out = b2 + W2 * relu(h); with x: x += scale * out
+template <typename T>
+__global__ void __launch_bounds__(CB)
+k_cnn_l2(tp_grid g, const float* __restrict__ h, const float* __restrict__ w2, const float* __restrict__ b2,
+         float* __restrict__ out, T* __restrict__ x, const float* __restrict__ scale,
+         int32_t* __restrict__ bad) {
+    __shared__ float W[CNN_CH * CNN_NT];
+    for (int k = threadIdx.x; k < CNN_CH * CNN_NT; k += CB) W[k] = w2[k];
+    __syncthreads();
+    const int32_t n = g.nx * g.ny * g.nz;
+    const int32_t i = blockIdx.x * CB + threadIdx.x;
+    if (i >= n) return;
+    const int32_t ix = i % g.nx, iy = (i / g.nx) % g.ny, iz = i / (g.nx * g.ny);
+    float acc = b2[0];
+    for (int t = 0; t < CNN_NT; ++t) {
+        const int32_t j = tap_nbr(ix, iy, iz, t, g.nx, g.ny, g.nz);
+        if (j < 0) continue;
+#pragma unroll
+        for (int o = 0; o < CNN_CH; ++o) {
+            const float a = h[(int64_t)o * n + j];
+            acc += W[o * CNN_NT + t] * (a > 0.f ? a : 0.f);
+        }
+    }
+    if (out) out[i] = acc;
+    if (x) {
+        if (!isfinite(acc)) *bad = 1;
+        else x[i] = x[i] + (T)(scale[0] * acc);
+    }
+}
+
+// ---- loss and gradients ------------------------------------------------------------------
+// dout = 2 (out - y) / n; per-block partial sums of (out - y)^2
+__global__ void __launch_bounds__(CB)
+k_cnn_dout(int32_t n, const float* __restrict__ out, const float* __restrict__ y, float* __restrict__ dout,
+           double* __restrict__ part) {
+    __shared__ double sh[CB];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * CB + threadIdx.x; i < n; i += (int64_t)gridDim.x * CB) {
+        const float d = out[i] - y[i];
+        dout[i] = 2.f * d / (float)n;
+        acc += (double)d * (double)d;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = CB / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// dh_o(j) = [h_o(j) > 0] sum_t W2[o][t] dout(j - off_t)
+__global__ void __launch_bounds__(CB)
+k_cnn_dh(tp_grid g, const float* __restrict__ h, const float* __restrict__ w2, const float* __restrict__ dout,
+         float* __restrict__ dh) {
+    __shared__ float W[CNN_CH * CNN_NT];
+    for (int k = threadIdx.x; k < CNN_CH * CNN_NT; k += CB) W[k] = w2[k];
+    __syncthreads();
+    const int32_t n = g.nx * g.ny * g.nz;
+    const int32_t j = blockIdx.x * CB + threadIdx.x;
+    if (j >= n) return;
+    const int32_t ix = j % g.nx, iy = (j / g.nx) % g.ny, iz = j / (g.nx * g.ny);
+    float acc[CNN_CH];
+#pragma unroll
+    for (int o = 0; o < CNN_CH; ++o) acc[o] = 0.f;
+    for (int t = 0; t < CNN_NT; ++t) {
+        const int32_t i = tap_nbr(ix, iy, iz, CNN_NT - 1 - t, g.nx, g.ny, g.nz);
+        if (i < 0) continue;
+        const float d = dout[i];
+#pragma unroll
+        for (int o = 0; o < CNN_CH; ++o) acc[o] += W[o * CNN_NT + t] * d;
+    }
+#pragma unroll
+    for (int o = 0; o < CNN_CH; ++o) dh[(int64_t)o * n + j] = h[(int64_t)o * n + j] > 0.f ? acc[o] : 0.f;
+}
+
+// One workgroup per parameter: sum over cells of (upstream) x (input at the tap).
+//   p <  3456           dW1[o][c][t] = sum_i dh_o(i) f_c(i + t)        (features BF16-rounded)
+//   p <  3472           db1[o]       = sum_i dh_o(i)
+//   p <  3904           dW2[o][t]    = sum_i dout(i) relu(h_o(i + t))
+//   p == 3904           db2          = sum_i dout(i)
+__global__ void __launch_bounds__(CB)
+k_cnn_grad(tp_grid g, const float* __restrict__ f, const float* __restrict__ h, const float* __restrict__ dh,
+           const float* __restrict__ dout, float* __restrict__ grad) {
+    __shared__ float sh[CB];
+    const int32_t n = g.nx * g.ny * g.nz;
+    const int p = blockIdx.x;
+    float acc = 0.f;
+    int kind, o = 0, c = 0, t = 13;
+    if (p < 3456) { kind = 0; o = p / (CNN_CIN * CNN_NT); c = (p / CNN_NT) % CNN_CIN; t = p % CNN_NT; }
+    else if (p < 3472) { kind = 1; o = p - 3456; }
+    else if (p < 3904) { kind = 2; o = (p - 3472) / CNN_NT; t = (p - 3472) % CNN_NT; }
+    else { kind = 3; }
+    for (int32_t i = threadIdx.x; i < n; i += CB) {
+        const int32_t ix = i % g.nx, iy = (i / g.nx) % g.ny, iz = i / (g.nx * g.ny);
+        if (kind == 0) {
+            const int32_t j = tap_nbr(ix, iy, iz, t, g.nx, g.ny, g.nz);
+            if (j >= 0) acc += dh[(int64_t)o * n + i] * bf16_round(f[(int64_t)c * n + j]);
+        } else if (kind == 1) {
+            acc += dh[(int64_t)o * n + i];
+        } else if (kind == 2) {
+            const int32_t j = tap_nbr(ix, iy, iz, t, g.nx, g.ny, g.nz);
+            if (j >= 0) {
+                const float a = h[(int64_t)o * n + j];
+                acc += dout[i] * (a > 0.f ? a : 0.f);
+            }
+        } else {
+            acc += dout[i];
+        }
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = CB / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) grad[p] = sh[0];
+}
+
+// Adam (Kingma & Ba 2015) on the FP32 master weights; refresh the BF16 copies
+__global__ void __launch_bounds__(CB)
+k_adam(int np, const float* __restrict__ grad, float* __restrict__ w, float* __restrict__ m,
+       float* __restrict__ v, float* __restrict__ wbf, float lr, float b1, float b2, float eps, float c1,
+       float c2) {
+    const int p = blockIdx.x * CB + threadIdx.x;
+    if (p >= np) return;
+    const float gr = grad[p];
+    const float mm = b1 * m[p] + (1.f - b1) * gr;
+    const float vv = b2 * v[p] + (1.f - b2) * gr * gr;
+    m[p] = mm;
+    v[p] = vv;
+    const float wn = w[p] - lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+    w[p] = wn;
+    wbf[p] = bf16_round(wn);
+}
+
+__global__ void __launch_bounds__(CB)
+k_bf16_copy(int np, const float* __restrict__ w, float* __restrict__ wbf) {
+    const int p = blockIdx.x * CB + threadIdx.x;
+    if (p < np) wbf[p] = bf16_round(w[p]);
+}
+
+__global__ void __launch_bounds__(CB)
+k_loss_sum(int nb, int32_t n, const double* __restrict__ part, double* __restrict__ loss) {
+    __shared__ double sh[CB];
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nb; b += CB) a += part[b];
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int off = CB / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = sh[0] / n;
+}
+
+// ---- loss in the D^{-1} A norm --------------------------------------------------------------
+// v = D^{-1} A (out - target); per-block partial sums of v^2; v overwritten by dL/dv = 2 v / n
+__global__ void __launch_bounds__(CB)
+k_op_forward(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+             const double* __restrict__ val, const float* __restrict__ dinv, const float* __restrict__ out,
+             const float* __restrict__ target, float* __restrict__ dv, double* __restrict__ part) {
+    __shared__ double sh[CB];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * CB + threadIdx.x; i < n; i += (int64_t)gridDim.x * CB) {
+        double s = 0.0;
+        for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            const int32_t j = col[k];
+            s += val[k] * (double)(out[j] - target[j]);
+        }
+        const float v = (float)(s * (double)dinv[i]);
+        acc += (double)v * (double)v;
+        dv[i] = 2.f * v / (float)n;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = CB / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// dout = A^T (D^{-1} dv), with A^T given explicitly (sorted CSR)
+__global__ void __launch_bounds__(CB)
+k_op_backward(int32_t n, const int32_t* __restrict__ trp, const int32_t* __restrict__ tcol,
+              const double* __restrict__ tval, const float* __restrict__ dinv, const float* __restrict__ dv,
+              float* __restrict__ dout) {
+    const int32_t j = blockIdx.x * CB + threadIdx.x;
+    if (j >= n) return;
+    double s = 0.0;
+    for (int32_t k = trp[j]; k < trp[j + 1]; ++k) {
+        const int32_t i = tcol[k];
+        s += tval[k] * (double)(dinv[i] * dv[i]);
+    }
+    dout[j] = (float)s;
+}
+
+// ---- host helpers ---------------------------------------------------------------------------
+static int red_blocks(int32_t n) { return std::max(1, std::min(1024, cdiv(n, CB * 4))); }
+
+void cnn_work_reserve(tp_cnn* c, int32_t n, hipStream_t s) {
+    if (c->n_work >= n) return;
+    c->h.alloc((size_t)CNN_CH * n, s);
+    c->dh.alloc((size_t)CNN_CH * n, s);
+    c->out.alloc(n, s);
+    c->dout.alloc(n, s);
+    c->part.alloc(1024, s);
+    c->n_work = n;
+}
+
+// forward on given features; out may be null; with x: smoother update x += scale * out
+template <typename T>
+void cnn_forward_into(tp_cnn* c, const tp_grid& g, const float* f, float* out, T* x, const float* scale,
+                      int32_t* bad, hipStream_t s) {
+    const int32_t n = g.nx * g.ny * g.nz;
+    cnn_work_reserve(c, n, s);
+    TP_LAUNCH(k_cnn_l1, cdiv(n, CB), CB, 0, s, g, f, c->wbf.p, c->w.p + CNN_OFF_B1, c->h.p);
+    TP_LAUNCH(k_cnn_l2<T>, cdiv(n, CB), CB, 0, s, g, c->h.p, c->wbf.p + CNN_OFF_W2, c->w.p + CNN_OFF_B2, out, x,
+              scale, bad);
+}
+template void cnn_forward_into<double>(tp_cnn*, const tp_grid&, const float*, float*, double*, const float*,
+                                       int32_t*, hipStream_t);
+template void cnn_forward_into<float>(tp_cnn*, const tp_grid&, const float*, float*, float*, const float*,
+                                      int32_t*, hipStream_t);
+
+// features for residual r on the finest level of a hierarchy with an attached smoother
+template <typename T>
+void cnn_features_into(tp_cnn_attach* a, const T* r, float* f, hipStream_t s) {
+    const int32_t n = a->g.nx * a->g.ny * a->g.nz;
+    const int nb = red_blocks(n);
+    TP_LAUNCH(k_feat_resid<T>, nb, CB, 0, s, n, r, a->dinv.p, f, a->part.p);
+    TP_LAUNCH(k_feat_scale_sum, 1, CB, 0, s, nb, n, a->part.p, a->scale.p);
+    TP_LAUNCH(k_feat_normalise, cdiv(n, CB), CB, 0, s, n, a->scale.p, f);
+}
+template void cnn_features_into<double>(tp_cnn_attach*, const double*, float*, hipStream_t);
+template void cnn_features_into<float>(tp_cnn_attach*, const float*, float*, hipStream_t);
+
+// gradient of the loss from c->dout (set by the caller) and c->h of the last forward
+void cnn_backward_from_dout(tp_cnn* c, const tp_grid& g, const float* feat, hipStream_t s) {
+    const int32_t n = g.nx * g.ny * g.nz;
+    TP_LAUNCH(k_cnn_dh, cdiv(n, CB), CB, 0, s, g, c->h.p, c->wbf.p + CNN_OFF_W2, c->dout.p, c->dh.p);
+    TP_LAUNCH(k_cnn_grad, CNN_NPARAM, CB, 0, s, g, feat, c->h.p, c->dh.p, c->dout.p, c->grad.p);
+}
+
+// loss in the D^{-1} A norm of the attached finest level (A^T built on first use)
+void cnn_op_loss_grad(tp_cnn_attach* a, const int32_t* rowptr, const int32_t* col, const double* val,
+                      int32_t nnz, const float* feat, const float* target, hipStream_t s) {
+    tp_cnn* c = a->net;
+    const tp_grid& g = a->g;
+    const int32_t n = g.nx * g.ny * g.nz;
+    if (!a->At.rowptr.p) transpose(rowptr, col, val, n, n, nnz, true, a->At, s);
+    cnn_work_reserve(c, n, s);
+    cnn_forward_into<float>(c, g, feat, c->out.p, nullptr, nullptr, nullptr, s);
+    const int nb = red_blocks(n);
+    TP_LAUNCH(k_op_forward, nb, CB, 0, s, n, rowptr, col, val, a->dinv.p, c->out.p, target, c->dh.p, c->part.p);
+    TP_LAUNCH(k_loss_sum, 1, CB, 0, s, nb, n, c->part.p, c->loss.p);
+    TP_LAUNCH(k_op_backward, cdiv(n, CB), CB, 0, s, n, a->At.rowptr.p, a->At.col.p, a->At.val.p, a->dinv.p,
+              c->dh.p, c->dout.p);
+    cnn_backward_from_dout(c, g, feat, s);
+}
+
+void cnn_attach_build(tp_cnn_attach* a, const tp_grid& g, const int32_t* rowptr, const int32_t* col,
+                      const double* val, hipStream_t s) {
+    const int32_t n = g.nx * g.ny * g.nz;
+    a->g = g;
+    a->feat.alloc((size_t)CNN_CIN * n, s);
+    a->dinv.alloc(n, s);
+    a->part.alloc(1024, s);
+    a->scale.alloc(1, s);
+    a->bad.alloc(1, s);
+    TP_LAUNCH(k_feat_static, cdiv(n, CB), CB, 0, s, g, rowptr, col, val, a->feat.p, a->dinv.p);
+}
+
+}  // namespace tp
+
+extern "C" {
+
+int cnn_create(const float* params, tp_cnn_t* out) {
+    TP_GUARD({
+        TP_CHECK_ARG(params && out, "cnn_create: null argument");
+        for (int p = 0; p < CNN_NPARAM; ++p)
+            TP_CHECK_ARG(std::isfinite(params[p]), "cnn_create: parameter %d is not finite", p);
+        hipStream_t s = nullptr;
+        tp_cnn* c = new tp_cnn();
+        c->w.alloc(CNN_NPARAM, s);
+        c->wbf.alloc(CNN_NPARAM, s);
+        c->m.alloc(CNN_NPARAM, s);
+        c->v.alloc(CNN_NPARAM, s);
+        c->grad.alloc(CNN_NPARAM, s);
+        c->loss.alloc(1, s);
+        TP_HIP(hipMemcpyAsync(c->w.p, params, sizeof(float) * CNN_NPARAM, hipMemcpyHostToDevice, s));
+        TP_HIP(hipMemsetAsync(c->m.p, 0, sizeof(float) * CNN_NPARAM, s));
+        TP_HIP(hipMemsetAsync(c->v.p, 0, sizeof(float) * CNN_NPARAM, s));
+        TP_LAUNCH(tp::k_bf16_copy, tp::cdiv(CNN_NPARAM, tp::CB), tp::CB, 0, s, CNN_NPARAM, c->w.p, c->wbf.p);
+        TP_HIP(hipStreamSynchronize(s));
+        *out = c;
+    });
+    return TP_OK;
+}
+
+int cnn_get_params(tp_cnn_t c, float* params) {
+    TP_GUARD({
+        TP_CHECK_ARG(c && params, "cnn_get_params: null argument");
+        TP_HIP(hipMemcpy(params, c->w.p, sizeof(float) * CNN_NPARAM, hipMemcpyDeviceToHost));
+    });
+    return TP_OK;
+}
+
+int cnn_get_grad(tp_cnn_t c, float* grad) {
+    TP_GUARD({
+        TP_CHECK_ARG(c && grad, "cnn_get_grad: null argument");
+        TP_HIP(hipDeviceSynchronize());
+        TP_HIP(hipMemcpy(grad, c->grad.p, sizeof(float) * CNN_NPARAM, hipMemcpyDeviceToHost));
+    });
+    return TP_OK;
+}
+
+int cnn_destroy(tp_cnn_t c) {
+    TP_GUARD({
+        if (c) {
+            TP_HIP(hipDeviceSynchronize());
+            delete c;
+            TP_HIP(hipDeviceSynchronize());
+        }
+    });
+    return TP_OK;
+}
+
+int cnn_forward(tp_cnn_t c, const tp_grid* grid, const float* feat, float* out, void* stream) {
+    TP_GUARD({
+        TP_CHECK_ARG(c && grid && feat && out, "cnn_forward: null argument");
+        TP_CHECK_ARG(grid->nx >= 1 && grid->ny >= 1 && grid->nz >= 1, "cnn_forward: bad grid");
+        tp::cnn_forward_into<float>(c, *grid, feat, out, nullptr, nullptr, nullptr, (hipStream_t)stream);
+    });
+    return TP_OK;
+}
+
+int cnn_loss_grad(tp_cnn_t c, const tp_grid* grid, const float* feat, const float* target, double* loss,
+                  float* grad, void* stream) {
+    TP_GUARD({
+        TP_CHECK_ARG(c && grid && feat && target, "cnn_loss_grad: null argument");
+        hipStream_t s = (hipStream_t)stream;
+        const tp_grid g = *grid;
+        const int32_t n = g.nx * g.ny * g.nz;
+        TP_CHECK_ARG(n >= 1, "cnn_loss_grad: bad grid");
+        tp::cnn_work_reserve(c, n, s);  // before taking c->out.p
+        tp::cnn_forward_into<float>(c, g, feat, c->out.p, nullptr, nullptr, nullptr, s);
+        const int nb = tp::red_blocks(n);
+        TP_LAUNCH(tp::k_cnn_dout, nb, tp::CB, 0, s, n, c->out.p, target, c->dout.p, c->part.p);
+        TP_LAUNCH(tp::k_loss_sum, 1, tp::CB, 0, s, nb, n, c->part.p, c->loss.p);
+        tp::cnn_backward_from_dout(c, g, feat, s);
+        if (grad)
+            TP_HIP(hipMemcpyAsync(grad, c->grad.p, sizeof(float) * CNN_NPARAM, hipMemcpyDeviceToDevice, s));
+        if (loss) {
+            TP_HIP(hipMemcpyAsync(loss, c->loss.p, sizeof(double), hipMemcpyDeviceToHost, s));
+            TP_HIP(hipStreamSynchronize(s));
+        }
+    });
+    return TP_OK;
+}
+
+int cnn_adam_step(tp_cnn_t c, float lr, void* stream) {
+    TP_GUARD({
+        TP_CHECK_ARG(c, "cnn_adam_step: null handle");
+        TP_CHECK_ARG(lr > 0.f && std::isfinite(lr), "cnn_adam_step: lr must be > 0");
+        c->step += 1;
+        const float b1 = 0.9f, b2 = 0.999f;
+        const float c1 = 1.f - std::pow(b1, (float)c->step), c2 = 1.f - std::pow(b2, (float)c->step);
+        TP_LAUNCH(tp::k_adam, tp::cdiv(CNN_NPARAM, tp::CB), tp::CB, 0, (hipStream_t)stream, CNN_NPARAM, c->grad.p,
+                  c->w.p, c->m.p, c->v.p, c->wbf.p, lr, b1, b2, 1e-8f, c1, c2);
+    });
+    return TP_OK;
+}
+
+}  // extern "C"

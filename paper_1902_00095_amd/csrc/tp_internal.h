@@ -93,6 +93,12 @@ struct DBuf {
     T* get() const { return p; }
 };
 
+struct Csr {
+    int32_t n = 0, m = 0, nnz = 0;  // n rows, m columns
+    DBuf<int32_t> rowptr, col;
+    DBuf<double> val;
+};
+
 // Pinned host scalar mailbox for the few device->host reads of a solve.
 struct HostMail {
     void* p = nullptr;

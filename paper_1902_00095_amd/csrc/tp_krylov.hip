@@ -57,6 +57,10 @@ __global__ void k_zero_u32(unsigned int* p) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0u;
 }
 
+__global__ void k_zero_i32(int32_t* p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
 __global__ void __launch_bounds__(KB)
 k_zero_d(int64_t N, double* __restrict__ x) {
     int64_t i = (int64_t)blockIdx.x * KB + threadIdx.x;
@@ -393,6 +397,10 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
     const double bnorm = std::sqrt(read_d(G.nrm2.p, G.mail, s));
     int it = 0, restarts = 0;
     double rel = 0.0, est = 0.0;
+    std::vector<double> ests;
+    bool cnn_on = M->S->cnn && M->S->cnn->enabled;
+    int fallback_iter = -1;
+    if (cnn_on) TP_LAUNCH(k_zero_i32, 1, 64, 0, s, M->S->cnn->bad.p);
     int status = TP_OK;
     if (bnorm == 0.0) {
         TP_LAUNCH(k_zero_d, gN, KB, 0, s, G.N, G.x.p);
@@ -427,6 +435,20 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
                 ++it;
                 k = j + 1;
                 if (history) history[it] = est;
+                ests.push_back(est);
+                if (cnn_on) {
+                    tp_cnn_attach* a = M->S->cnn.get();
+                    int32_t bad = 0;
+                    TP_HIP(hipMemcpyAsync(&bad, a->bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                    TP_HIP(hipStreamSynchronize(s));
+                    const size_t q = ests.size();
+                    const bool stag = kp.stag_ratio > 0.0 && q >= 3 && ests[q - 1] > kp.stag_ratio * ests[q - 3];
+                    if (bad || stag) {
+                        a->enabled = false;
+                        cnn_on = false;
+                        fallback_iter = it;
+                    }
+                }
                 if (!std::isfinite(est)) fail(TP_ERR_NUMERIC, "non-finite Arnoldi value in FGMRES");
                 if (est <= kp.rtol || hn == 0.0) break;
             }
@@ -442,7 +464,9 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
     TP_LAUNCH(k_interleave, gn, KB, 0, s, n, G.x.p, x_il);
     TP_HIP(hipStreamSynchronize(s));
     if (!std::isfinite(rel)) fail(TP_ERR_NUMERIC, "non-finite true residual in FGMRES");
+    if (M->S->cnn) M->S->cnn->enabled = true;  // the switch lasts for one solve
     if (st) {
+        st->fallback_iter = fallback_iter;
         st->iters = it;
         st->restarts = restarts > 0 ? restarts - 1 : 0;
         st->rel_true = rel;

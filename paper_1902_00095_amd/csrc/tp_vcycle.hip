@@ -332,6 +332,21 @@ static T* vcycle_level(tp_amg* h, int l, const T* b, hipStream_t s) {
     T* xc = vcycle_level<T>(h, l + 1, bc, s);
     TP_G_DISPATCH(L.gP, TP_LAUNCH((k_spmv<T, GG>), grid_rows(n, GG), VB, 0, s, n, L.P.rowptr.p, L.P.col.p,
                                   LevelVals<T>::P(L), xc, cur, 1));
+    if (l == 0 && h->stop_before_post) return cur;
+    if (l == 0 && h->cnn && h->cnn->enabled) {
+        // learned post-smoother: r = b - A x; x += s * CNN(features(r))
+        if (L.ndia) {
+            TP_ND_DISPATCH(L.ndia, TP_LAUNCH((k_residual_dia<T, NDD>), cdiv(n, VB), VB, 0, s, n,
+                                             LevelVals<T>::D(L), dia_offsets<NDD>(L), b, cur, r));
+        } else {
+            TP_G_DISPATCH(L.gA, TP_LAUNCH((k_residual<T, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p,
+                                          L.A.col.p, LevelVals<T>::A(L), b, cur, r));
+        }
+        tp_cnn_attach* a = h->cnn.get();
+        cnn_features_into<T>(a, r, a->feat.p, s);
+        cnn_forward_into<T>(a->net, a->g, a->feat.p, nullptr, cur, a->scale.p, a->bad.p, s);
+        return cur;
+    }
     if (p.nu_post > 0) cur = smooth<T>(h, l, b, cur, false, p.nu_post, s);
     return cur;
 }
@@ -360,6 +375,105 @@ void cast_s2d(int32_t n, const void* a, double* b, size_t es, hipStream_t s) {
 }
 
 }  // namespace tp
+
+namespace tp {
+
+__global__ void __launch_bounds__(VB)
+k_pair_finish(int32_t n, const double* __restrict__ y, const double* __restrict__ x, double* __restrict__ e) {
+    int32_t i = blockIdx.x * VB + threadIdx.x;
+    if (i < n) e[i] = y[i] - x[i];
+}
+
+}  // namespace tp
+
+extern "C" int amg_presmoothed_pair(tp_amg_t amg, const double* y, double* r, double* e, void* stream) {
+    TP_GUARD({
+        TP_CHECK_ARG(amg && y && r && e, "amg_presmoothed_pair: null argument");
+        TP_CHECK_ARG(amg->lev.size() >= 2, "amg_presmoothed_pair: needs at least two levels");
+        hipStream_t s = (hipStream_t)stream;
+        tp::Level& L = amg->lev[0];
+        const int32_t n = L.A.n;
+        // b = A y (FP64 level operator)
+        tp::DBuf<double> b(n, s), x(n, s);
+        TP_G_DISPATCH(L.gA, TP_LAUNCH((tp::k_spmv<double, GG>), tp::grid_rows(n, GG), tp::VB, 0, s, n,
+                                      L.A.rowptr.p, L.A.col.p, L.A.val.p, y, b.p, 0));
+        const size_t es = tp::storage_bytes(amg);
+        tp::cast_d2s(n, b.p, amg->lev[0].b.p, es, s);
+        amg->stop_before_post = true;
+        const void* xv = nullptr;
+        try {
+            xv = tp::vcycle_run(amg, nullptr, s);
+        } catch (...) {
+            amg->stop_before_post = false;
+            throw;
+        }
+        amg->stop_before_post = false;
+        tp::cast_s2d(n, xv, x.p, es, s);
+        TP_G_DISPATCH(L.gA, TP_LAUNCH((tp::k_residual<double, GG>), tp::grid_rows(n, GG), tp::VB, 0, s, n,
+                                      L.A.rowptr.p, L.A.col.p, L.A.val.p, b.p, x.p, r));
+        TP_LAUNCH(tp::k_pair_finish, tp::cdiv(n, tp::VB), tp::VB, 0, s, n, y, x.p, e);
+        TP_HIP(hipStreamSynchronize(s));
+    });
+    return TP_OK;
+}
+
+extern "C" int amg_attach_post_smoother(tp_amg_t amg, tp_cnn_t net, const tp_grid* grid) {
+    TP_GUARD({
+        TP_CHECK_ARG(amg, "amg_attach_post_smoother: null hierarchy");
+        if (!net) {
+            amg->cnn.reset();
+            return TP_OK;
+        }
+        TP_CHECK_ARG(grid, "amg_attach_post_smoother: null grid");
+        const int64_t n = (int64_t)grid->nx * grid->ny * grid->nz;
+        TP_CHECK_ARG(n == amg->lev[0].A.n, "amg_attach_post_smoother: grid has %lld cells, level 0 has %d rows",
+                     (long long)n, amg->lev[0].A.n);
+        TP_CHECK_ARG(amg->lev.size() >= 2, "amg_attach_post_smoother: needs at least two levels");
+        hipStream_t s = amg->stream;
+        auto a = std::make_unique<tp::tp_cnn_attach>();
+        a->net = net;
+        const tp::Level& L = amg->lev[0];
+        tp::cnn_attach_build(a.get(), *grid, L.A.rowptr.p, L.A.col.p, L.A.val.p, s);
+        TP_LAUNCH(tp::k_zero<int32_t>, 1, tp::VB, 0, s, 1, a->bad.p);
+        tp::cnn_work_reserve(net, (int32_t)n, s);
+        TP_HIP(hipStreamSynchronize(s));
+        amg->cnn = std::move(a);
+    });
+    return TP_OK;
+}
+
+extern "C" int amg_features(tp_amg_t amg, const double* r, float* feat, float* scale, void* stream) {
+    TP_GUARD({
+        TP_CHECK_ARG(amg && r && feat, "amg_features: null argument");
+        TP_CHECK_ARG(amg->cnn, "amg_features: no network attached (amg_attach_post_smoother)");
+        hipStream_t s = (hipStream_t)stream;
+        tp::tp_cnn_attach* a = amg->cnn.get();
+        const int32_t n = amg->lev[0].A.n;
+        TP_HIP(hipMemcpyAsync(feat + n, a->feat.p + n, sizeof(float) * 7 * (size_t)n, hipMemcpyDeviceToDevice, s));
+        tp::cnn_features_into<double>(a, r, feat, s);
+        if (scale) {
+            TP_HIP(hipMemcpyAsync(scale, a->scale.p, sizeof(float), hipMemcpyDeviceToHost, s));
+            TP_HIP(hipStreamSynchronize(s));
+        }
+    });
+    return TP_OK;
+}
+
+extern "C" int amg_cnn_loss_grad(tp_amg_t amg, const float* feat, const float* target, double* loss,
+                                 void* stream) {
+    TP_GUARD({
+        TP_CHECK_ARG(amg && feat && target, "amg_cnn_loss_grad: null argument");
+        TP_CHECK_ARG(amg->cnn, "amg_cnn_loss_grad: no network attached");
+        hipStream_t s = (hipStream_t)stream;
+        const tp::Level& L = amg->lev[0];
+        tp::cnn_op_loss_grad(amg->cnn.get(), L.A.rowptr.p, L.A.col.p, L.A.val.p, L.A.nnz, feat, target, s);
+        if (loss) {
+            TP_HIP(hipMemcpyAsync(loss, amg->cnn->net->loss.p, sizeof(double), hipMemcpyDeviceToHost, s));
+            TP_HIP(hipStreamSynchronize(s));
+        }
+    });
+    return TP_OK;
+}
 
 extern "C" int amg_vcycle(tp_amg_t amg, const double* b, double* x, void* stream) {
     TP_GUARD({

@@ -56,12 +56,13 @@ class _AmgParams(C.Structure):
 
 
 class _KParams(C.Structure):
-    _fields_ = [("rtol", C.c_double), ("restart", C.c_int32), ("maxit", C.c_int32)]
+    _fields_ = [("rtol", C.c_double), ("restart", C.c_int32), ("maxit", C.c_int32),
+                ("stag_ratio", C.c_double)]
 
 
 class _KStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("rel_true", C.c_double),
-                ("rel_est", C.c_double)]
+                ("rel_est", C.c_double), ("fallback_iter", C.c_int32)]
 
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -75,7 +76,11 @@ class _Allocator(C.Structure):
 EXPORTS = ["tp_last_error", "tp_init", "tp_jacobian_sizes", "assemble_tpfa", "amg_setup",
            "amg_num_levels", "amg_level_info", "amg_level_copy", "amg_vcycle", "amg_destroy",
            "precond_create", "precond_apply", "precond_destroy", "fgmres_solve",
+           "cnn_create", "cnn_get_params", "cnn_get_grad", "cnn_destroy", "cnn_forward", "cnn_loss_grad",
+           "cnn_adam_step", "amg_attach_post_smoother", "amg_features", "amg_presmoothed_pair",
+           "amg_cnn_loss_grad",
            "tp_timer_enable", "tp_timer_read"]
+CNN_NPARAM = 3905
 
 _lib = None
 
@@ -88,6 +93,9 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"tpsolve HIP library not built: {path} is missing "
                            "(run __graft_entry__.build())")
+    # torch first: its HIP runtime must be the one the process uses, so the
+    # library's libamdhip64 dependency resolves to the copy torch loaded
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     lib.tp_last_error.restype = C.c_char_p
     for name in EXPORTS[1:]:
@@ -146,6 +154,8 @@ def init(device: int = 0, torch_allocator: bool = False):
     torch's caching allocator (default: the HIP stream-ordered pool)."""
     global _keep_alloc
     lib = load()
+    import torch
+    torch.cuda.init()
     if torch_allocator:
         torch = _torch()
 
@@ -284,6 +294,33 @@ class AMG:
         torch.cuda.current_stream().synchronize()
         return out
 
+    def attach(self, net, grid):
+        """Use `net` (Net or None) as the finest-level post-smoother."""
+        self._net = net
+        _check(_lib.amg_attach_post_smoother(self.h, net.h if net is not None else None,
+                                             C.byref(grid_c(grid)) if grid is not None else None))
+
+    def features(self, r, feat=None, stream=None):
+        torch = _torch()
+        if feat is None:
+            feat = torch.empty(8 * self.n, dtype=torch.float32, device=r.device)
+        s = C.c_float()
+        _check(_lib.amg_features(self.h, _ptr(r), _ptr(feat), C.byref(s), _stream(stream)))
+        return feat, s.value
+
+    def op_loss_grad(self, feat, target, stream=None):
+        """Loss of the attached network in the D^{-1} A norm (gradient kept for Adam)."""
+        loss = C.c_double()
+        _check(_lib.amg_cnn_loss_grad(self.h, _ptr(feat), _ptr(target), C.byref(loss), _stream(stream)))
+        return loss.value
+
+    def presmoothed_pair(self, y, stream=None):
+        torch = _torch()
+        r = torch.empty_like(y)
+        e = torch.empty_like(y)
+        _check(_lib.amg_presmoothed_pair(self.h, _ptr(y), _ptr(r), _ptr(e), _stream(stream)))
+        return r, e
+
     def vcycle(self, b, x=None, stream=None):
         torch = _torch()
         if x is None:
@@ -324,15 +361,64 @@ class Precond:
             pass
 
 
+class Net:
+    """Learned post-smoother network (device parameters, FP32 master + BF16 copy)."""
+
+    def __init__(self, params):
+        lib = load()
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == CNN_NPARAM
+        h = C.c_void_p()
+        _check(lib.cnn_create(p.ctypes.data_as(C.c_void_p), C.byref(h)))
+        self.h = h
+
+    def params(self):
+        p = np.zeros(CNN_NPARAM, dtype=np.float32)
+        _check(_lib.cnn_get_params(self.h, p.ctypes.data_as(C.c_void_p)))
+        return p
+
+    def grad(self):
+        g = np.zeros(CNN_NPARAM, dtype=np.float32)
+        _check(_lib.cnn_get_grad(self.h, g.ctypes.data_as(C.c_void_p)))
+        return g
+
+    def forward(self, grid, feat, out=None, stream=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(grid.n, dtype=torch.float32, device=feat.device)
+        _check(_lib.cnn_forward(self.h, C.byref(grid_c(grid)), _ptr(feat), _ptr(out), _stream(stream)))
+        return out
+
+    def loss_grad(self, grid, feat, target, grad=None, stream=None):
+        loss = C.c_double()
+        _check(_lib.cnn_loss_grad(self.h, C.byref(grid_c(grid)), _ptr(feat), _ptr(target),
+                                  C.byref(loss), _ptr(grad), _stream(stream)))
+        return loss.value
+
+    def adam_step(self, lr, stream=None):
+        _check(_lib.cnn_adam_step(self.h, C.c_float(lr), _stream(stream)))
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            _check(_lib.cnn_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def fgmres_solve(J: Jacobian, M: Precond, b, x=None, rtol=1e-8, restart=30, maxit=1000,
-                 history=False, stream=None):
+                 history=False, stag_ratio=0.95, stream=None):
     """Solve J x = b; returns (x, stats dict).  x (tensor) is the initial
     guess when given and is overwritten."""
     torch = _torch()
     lib = load()
     if x is None:
         x = torch.zeros_like(b)
-    kp = _KParams(rtol, restart, maxit)
+    kp = _KParams(rtol, restart, maxit, stag_ratio)
     st = _KStats()
     hist = np.zeros(maxit + 1) if history else None
     jc = J.c()
@@ -341,7 +427,7 @@ def fgmres_solve(J: Jacobian, M: Precond, b, x=None, rtol=1e-8, restart=30, maxi
                             _stream(stream))
     _check(code, ok=(TP_OK, TP_NOT_CONVERGED))
     out = dict(converged=code == TP_OK, iters=st.iters, restarts=st.restarts,
-               rel_true=st.rel_true, rel_est=st.rel_est)
+               rel_true=st.rel_true, rel_est=st.rel_est, fallback_iter=st.fallback_iter)
     if hist is not None:
         out["history"] = hist[: st.iters + 1]
     return x, out

@@ -1,0 +1,201 @@
+"""GPU tests of the learned post-smoother: network forward and gradients
+against the CPU oracle on the same BF16-rounded inputs, features, the Adam
+step's closed form, the training-pair invariant, the stagnation fallback,
+and what training gains over the plain smoother."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1902_00095_amd import learned, solver, synth
+from paper_1902_00095_amd import tpsolve as tps
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _init():
+    import torch
+    assert torch.cuda.is_available()
+    tps.init(0)
+    yield
+
+
+def bf16(a):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def dev(a, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda", dtype=dtype)
+
+
+def _case(seed=0, dims=(10, 9, 8)):
+    g = synth.Grid(*dims, 1, 1, 1)
+    rng = np.random.default_rng(seed)
+    th = learned.init_params(seed)
+    th[3456:3472] = rng.standard_normal(16).astype(np.float32) * 0.1
+    th[3472:3904] *= 10
+    th = bf16(th)
+    f = bf16(rng.standard_normal((8, g.n)).astype(np.float32))
+    return g, th, f
+
+
+def test_forward_matches_oracle():
+    say("cnn forward")
+    g, th, f = _case()
+    net = tps.Net(th)
+    out = net.forward(g, dev(f.reshape(-1))).cpu().numpy()
+    ref, _ = oracle.cnn_forward(g, th.astype(np.float64), f.astype(np.float64))
+    assert np.abs(out - ref).max() <= 1e-4 * np.abs(ref).max()
+
+
+def test_gradient_matches_oracle():
+    say("cnn gradient")
+    import torch
+    g, th, f = _case(1)
+    y = np.random.default_rng(5).standard_normal(g.n).astype(np.float32)
+    net = tps.Net(th)
+    grad = torch.zeros(tps.CNN_NPARAM, dtype=torch.float32, device="cuda")
+    loss = net.loss_grad(g, dev(f.reshape(-1)), dev(y), grad)
+    lo, go = oracle.cnn_backward(g, th.astype(np.float64), f.astype(np.float64), y.astype(np.float64))
+    assert abs(loss - lo) <= 1e-4 * lo
+    gg = grad.cpu().numpy()
+    for a, b in ((0, 3456), (3456, 3472), (3472, 3904), (3904, 3905)):
+        assert np.abs(gg[a:b] - go[a:b]).max() <= 1e-3 * np.abs(go[a:b]).max(), (a, b)
+
+
+def test_adam_first_step_closed_form():
+    """From zero moments the bias-corrected first step is -lr g / (|g| + eps)."""
+    import torch
+    g, th, f = _case(2)
+    y = np.random.default_rng(6).standard_normal(g.n).astype(np.float32)
+    net = tps.Net(th)
+    grad = torch.zeros(tps.CNN_NPARAM, dtype=torch.float32, device="cuda")
+    net.loss_grad(g, dev(f.reshape(-1)), dev(y), grad)
+    net.adam_step(1e-3)
+    new = net.params()
+    gr = grad.cpu().numpy().astype(np.float64)
+    expect = th - 1e-3 * gr / (np.abs(gr) + 1e-8)
+    assert np.abs(new - expect).max() <= 2e-6
+
+
+def test_features_match_oracle():
+    say("features")
+    p = synth.make_problem("W2", grid=synth.Grid(12, 10, 8, 1, 1, 1))
+    d = solver.to_device(p)
+    J, G = solver.assemble(p, d)
+    a_S = learned.schur_hierarchy(J)
+    net = tps.Net(learned.init_params())
+    a_S.attach(net, p.grid)
+    r = synth.random_rhs(4, p.grid.n) * 1e3
+    f, s = a_S.features(dev(r))
+    Jo = oracle.jacobian(p)
+    fo, so = oracle.cnn_features(p.grid, Jo.rowptr, Jo.col, Jo.S, r)
+    assert abs(s - so) <= 1e-6 * so
+    np.testing.assert_allclose(f.cpu().numpy().reshape(8, -1), fo, rtol=2e-6, atol=1e-6)
+
+
+def test_pair_invariant():
+    """r = S e exactly up to rounding (r = S y - S x, e = y - x)."""
+    import torch
+    say("pair")
+    p = synth.make_problem("W4", seed=1000, grid=synth.Grid(16, 16, 16, 1, 1, 1))
+    d = solver.to_device(p)
+    J, G = solver.assemble(p, d)
+    a_S = learned.schur_hierarchy(J)
+    y = torch.randn(p.grid.n, dtype=torch.float64, device="cuda")
+    r, e = a_S.presmoothed_pair(y)
+    Jo = oracle.jacobian(p)
+    Se = oracle.spmv(Jo.rowptr, Jo.col, J.S.cpu().numpy(), e.cpu().numpy())
+    rn = r.cpu().numpy()
+    assert np.abs(Se - rn).max() <= 1e-9 * np.abs(rn).max()
+    assert np.linalg.norm(e.cpu().numpy()) < np.linalg.norm(y.cpu().numpy())
+
+
+def test_untrained_and_adversarial_networks_fall_back():
+    say("fallback")
+    p = synth.make_problem("W4", seed=4001, grid=synth.Grid(24, 24, 24, 1, 1, 1))
+    good = tps.Net(learned.init_params())
+    res = learned.compare(good, p)
+    say(f"  untrained: plain {res['plain']['iters']} learned {res['learned']['iters']} "
+        f"fallback {res['learned']['fallback_iter']}")
+    assert res["learned"]["converged"] and res["learned"]["rel_true"] <= 1e-8
+    th = learned.init_params(7) * 1e4            # huge corrections: stagnation
+    bad = tps.Net(th)
+    res = learned.compare(bad, p)
+    say(f"  adversarial: learned {res['learned']['iters']} fallback {res['learned']['fallback_iter']}")
+    assert res["learned"]["converged"] and res["learned"]["rel_true"] <= 1e-8
+    assert res["learned"]["fallback_iter"] >= 0
+    with pytest.raises(tps.TpError):
+        tps.Net(np.full(tps.CNN_NPARAM, np.nan, dtype=np.float32))
+
+
+def test_operator_loss_gradient_matches_oracle():
+    """Gradient of L = mean((D^{-1} S (out - t))^2) on the GPU against
+    central differences of the same loss built from the oracle's FP64
+    forward pass and the oracle Jacobian, at the BF16-rounded weights."""
+    import scipy.sparse as sp
+    say("operator loss gradient")
+    p = synth.make_problem("W4", seed=1001, grid=synth.Grid(10, 9, 8, 1, 1, 1))
+    d = solver.to_device(p)
+    J, G = solver.assemble(p, d)
+    g, th, f = _case(4, (10, 9, 8))
+    th = bf16(th)
+    net = tps.Net(th)
+    a_S = learned.schur_hierarchy(J)
+    a_S.attach(net, p.grid)
+    t = np.random.default_rng(8).standard_normal(g.n).astype(np.float32)
+    loss = a_S.op_loss_grad(dev(f.reshape(-1)), dev(t))
+    gg = net.grad().astype(np.float64)
+    Jo = oracle.jacobian(p)
+    A = sp.csr_matrix((Jo.S, Jo.col, Jo.rowptr))
+    Dinv = 1.0 / np.abs(A).sum(axis=1).A1
+    th64 = th.astype(np.float64)
+    f64 = f.astype(np.float64)
+
+    def L(theta):
+        out, _ = oracle.cnn_forward(g, theta, f64)
+        v = Dinv * (A @ (out - t.astype(np.float64)))
+        return float(np.mean(v * v))
+
+    assert abs(loss - L(th64)) <= 1e-4 * L(th64)
+    scale = np.abs(gg).max()
+    for k in list(range(0, 3456, 331)) + [3460, 3500, 3700, 3904]:
+        h = 1e-3 * max(1.0, abs(th64[k]))
+        tp_, tm = th64.copy(), th64.copy()
+        tp_[k] += h
+        tm[k] -= h
+        fd = (L(tp_) - L(tm)) / (2 * h)
+        assert abs(fd - gg[k]) <= 2e-3 * scale, (k, fd, gg[k])
+
+
+def test_training_lowers_loss_and_reports_gain():
+    """Train on seeded fields (seeds 1000+) with the operator-norm loss,
+    evaluate on held-out seeds (4001+): the held-out loss falls at least
+    tenfold, the learned form (with the stagnation guard) reaches the same
+    true residual, and the iteration counts of both forms are reported."""
+    say("training")
+    grid = synth.Grid(24, 24, 24, 1, 1, 1)
+    net = tps.Net(learned.init_params())
+    train = learned.make_pairs(range(1000, 1032), grid, net=net, smooth_y=1)
+    held = learned.make_pairs(range(4001, 4003), grid, net=net, smooth_y=1)
+    l0 = learned.eval_loss(net, held)
+    learned.train(net, train, 2000, lr=3e-3)
+    l1 = learned.eval_loss(net, held)
+    say(f"  held-out loss {l0:.4e} -> {l1:.4e}")
+    assert l1 < 0.1 * l0
+    for seed in (4001, 4002):
+        p = synth.make_problem("W4", seed=seed, grid=grid)
+        res = learned.compare(net, p)
+        say(f"  seed {seed}: plain {res['plain']['iters']} its, learned {res['learned']['iters']} its "
+            f"(fallback {res['learned']['fallback_iter']}), rel {res['learned']['rel_true']:.2e}")
+        assert res["learned"]["converged"] and res["learned"]["rel_true"] <= 1e-8
