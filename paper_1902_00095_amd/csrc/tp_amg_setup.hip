@@ -410,16 +410,16 @@ static void spgemm(const Csr& A, const Csr& Bm, Csr& C, hipStream_t s) {
         TP_LAUNCH(k_spgemm_count, grid, SG_WAVE, 0, s, A.n, A.rowptr.p, A.col.p, Bm.rowptr.p, Bm.col.p,
                   C.rowptr.p, flag.p);
     scan_exclusive(C.rowptr.p, C.rowptr.p, A.n, s);
-    int32_t f = read_i32(flag.p, s);
-    if (f) fail(TP_ERR_CAPACITY, "SpGEMM row exceeded the %d-entry LDS hash table", HASH);
+    // (an overflowing row is caught by the numeric pass, which only writes
+    // rows whose distinct-column count matches the symbolic one)
     C.nnz = read_i32(C.rowptr.p + A.n, s);
     C.col.alloc(C.nnz, s);
     C.val.alloc(C.nnz, s);
     if (A.n > 0)
         TP_LAUNCH(k_spgemm_fill, grid, SG_WAVE, 0, s, A.n, A.rowptr.p, A.col.p, A.val.p, Bm.rowptr.p,
                   Bm.col.p, Bm.val.p, C.rowptr.p, C.col.p, C.val.p, flag.p);
-    f = read_i32(flag.p, s);
-    if (f) fail(TP_ERR_CAPACITY, "SpGEMM numeric pass failed (code %d)", f);
+    const int32_t f = read_i32(flag.p, s);
+    if (f) fail(TP_ERR_CAPACITY, "SpGEMM row exceeded the %d-entry LDS hash table (code %d)", HASH, f);
 }
 
 // ---- l1 diagonal, precision copies ----------------------------------------------------
@@ -633,17 +633,28 @@ k_dia_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restr
     }
 }
 
+__global__ void k_probe_lens(int32_t n, const int32_t* __restrict__ rowptr, int32_t* __restrict__ lens) {
+    const uint32_t k = threadIdx.x;
+    if (k < 1 || k > 15) return;
+    const int32_t r = (int32_t)((k * 2654435761u) % (uint32_t)n);
+    lens[k] = rowptr[r + 1] - rowptr[r];
+}
+
 static void try_dia(tp_amg* h, Level& L, hipStream_t s) {
     const int32_t n = L.A.n;
     if (n < 1024 || L.A.nnz > 8LL * n) return;
-    // probe: the longest row among a few sampled rows
+    // probe: the longest row among 15 hashed rows (one gather, one read)
     int32_t best_len = -1, best_row = 0;
+    int32_t lens[16];
+    {
+        DBuf<int32_t> dl(16, s);
+        TP_LAUNCH(k_probe_lens, 1, 64, 0, s, n, L.A.rowptr.p, dl.p);
+        TP_HIP(hipMemcpyAsync(lens, dl.p, sizeof(int32_t) * 16, hipMemcpyDeviceToHost, s));
+        TP_HIP(hipStreamSynchronize(s));
+    }
     for (uint32_t k = 1; k <= 15; ++k) {
         int32_t r = (int32_t)((k * 2654435761u) % (uint32_t)n);
-        int32_t rp[2];
-        TP_HIP(hipMemcpyAsync(rp, L.A.rowptr.p + r, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        TP_HIP(hipStreamSynchronize(s));
-        if (rp[1] - rp[0] > best_len) { best_len = rp[1] - rp[0]; best_row = r; }
+        if (lens[k] > best_len) { best_len = lens[k]; best_row = r; }
     }
     if (best_len < 3 || best_len > 7 || (best_len % 2) == 0) return;
     int32_t rp0 = 0, cols[7];
@@ -711,16 +722,18 @@ static void setup(tp_amg* h, int32_t n, const int32_t* rowptr, const int32_t* co
         DBuf<int8_t> st(A.n, s), st2(A.n, s);
         TP_LAUNCH(k_pmis_init, cdiv(A.n, B), B, 0, s, A.n, ST.rowptr.p, st.p);
         const uint64_t hseed = prm.seed ^ ((uint64_t)l << 40);
+        // Rounds are idempotent once every point is decided, so the host
+        // reads the undecided count only after every third round.
         int round = 0;
         for (;; ++round) {
-            if (round >= 512) fail(TP_ERR_NUMERIC, "PMIS did not finish in 512 rounds");
+            if (round >= 510) fail(TP_ERR_NUMERIC, "PMIS did not finish in 510 rounds");
             TP_LAUNCH(k_fill_i32, 1, B, 0, s, undecided.p + round, 0, (int64_t)1);
             TP_LAUNCH(k_pmis_select, cdiv(A.n, B), B, 0, s, A.n, hseed, S.rowptr.p, S.col.p, ST.rowptr.p,
                       ST.col.p, st.p, st2.p);
             TP_LAUNCH(k_pmis_fmark, cdiv(A.n, B), B, 0, s, A.n, S.rowptr.p, S.col.p, st2.p,
                       undecided.p + round);
             std::swap(st.p, st2.p);
-            if (read_i32(undecided.p + round, s) == 0) break;
+            if (round % 3 == 2 && read_i32(undecided.p + round, s) == 0) break;
         }
         L.cf.alloc(A.n, s);
         TP_LAUNCH(k_cf_flags, cdiv(A.n, B), B, 0, s, A.n, st.p, L.cf.p);
@@ -841,9 +854,11 @@ int amg_level_copy(tp_amg_t amg, int32_t level, int32_t* A_rowptr, int32_t* A_co
 int amg_destroy(tp_amg_t amg) {
     TP_GUARD({
         if (!amg) return TP_OK;
-        hipStream_t s = amg->stream;
-        delete amg;  // buffers are freed stream-ordered on the setup stream
-        TP_HIP(hipStreamSynchronize(s));
+        // the hierarchy may have been used on streams other than its setup
+        // stream: wait for all device work before returning its memory
+        TP_HIP(hipDeviceSynchronize());
+        delete amg;
+        TP_HIP(hipDeviceSynchronize());
     });
     return TP_OK;
 }

@@ -34,12 +34,50 @@ def assemble(prob, dev):
                              prob.wells, prob.dt, dev["x_prev"], dev["x_k"])
 
 
-def setup(J, cfg: SolveConfig):
+_side = {}
+
+
+def _side_streams():
+    import torch
+    dev = torch.cuda.current_device()
+    if dev not in _side:
+        _side[dev] = (torch.cuda.Stream(), torch.cuda.Stream())   # default priority
+    return _side[dev]
+
+
+def setup(J, cfg: SolveConfig, concurrent: bool = True):
+    """Both hierarchies; with `concurrent`, built at the same time on two
+    streams from two host threads (the two setups are independent; each
+    call synchronises its own stream before returning)."""
+    import threading
+
+    import torch
     p_pp = dataclasses.replace(cfg.amg, restriction=0, storage=cfg.storage)
     p_S = dataclasses.replace(cfg.amg, restriction=1, storage=cfg.storage)
-    a_pp = tps.AMG(J.rowptr, J.col, J.pp, p_pp)
-    a_S = tps.AMG(J.rowptr, J.col, J.S, p_S)
-    return a_pp, a_S, tps.Precond(J, a_pp, a_S, cfg.variant)
+    if not concurrent:
+        a_pp = tps.AMG(J.rowptr, J.col, J.pp, p_pp)
+        a_S = tps.AMG(J.rowptr, J.col, J.S, p_S)
+        return a_pp, a_S, tps.Precond(J, a_pp, a_S, cfg.variant)
+    s1, s2 = _side_streams()
+    ev = torch.cuda.Event()
+    ev.record()                       # J is complete on the current stream
+    s1.wait_event(ev)
+    s2.wait_event(ev)
+    out, err = {}, []
+
+    def run(key, vals, prm, st):
+        try:
+            out[key] = tps.AMG(J.rowptr, J.col, vals, prm, stream=st)
+        except Exception as e:        # re-raised below
+            err.append(e)
+
+    th = threading.Thread(target=run, args=("S", J.S, p_S, s2))
+    th.start()
+    run("pp", J.pp, p_pp, s1)
+    th.join()
+    if err:
+        raise err[0]
+    return out["pp"], out["S"], tps.Precond(J, out["pp"], out["S"], cfg.variant)
 
 
 def solve(J, G, cfg: SolveConfig, history=False):
