@@ -138,6 +138,10 @@ int amg_num_levels(tp_amg_t amg, int32_t* nlev);
 /* sizes of level l (P/R sizes are 0 on the coarsest level) */
 int amg_level_info(tp_amg_t amg, int32_t level, int32_t* n, int32_t* nnzA,
                    int32_t* nnzP, int32_t* nnzR);
+/* Storage format of level l's operator in the V-cycle: ndia > 0 when it is
+ * kept diagonal-major with ndia diagonals (stencil levels), else CSR read by
+ * `lanes` cooperating lanes per row. */
+int amg_level_format(tp_amg_t amg, int32_t level, int32_t* ndia, int32_t* lanes);
 /* Copy level arrays into caller device buffers (any pointer may be NULL;
  * sizes from amg_level_info; cf: 1 = C point, 0 = F point).  FP64 values of
  * the setup.  Stream-ordered; does not synchronise. */
@@ -246,6 +250,13 @@ int amg_presmoothed_pair(tp_amg_t amg, const double* y, double* r, double* e, vo
  * Measurement support: HIP-event timing of the fine-level smoother kernel
  * (the V-cycle's dominant kernel) on the stream it is launched on.
  * ------------------------------------------------------------------------ */
+/* Mean execution time of the finest-level Chebyshev sweep kernel of `amg`,
+ * replayed `reps` times back to back on `stream` (its own level-0 operator
+ * and work vectors, contents zeroed first) between one HIP event pair;
+ * bytes_per_launch is the kernel's algorithmic byte count.  Overwrites the
+ * hierarchy's work vectors; synchronises `stream`. */
+int amg_time_fine_smoother(tp_amg_t amg, int32_t reps, double* ms_per_launch,
+                           double* bytes_per_launch, void* stream);
 /* enable (1) / disable (0) and reset the counters */
 int tp_timer_enable(int32_t on);
 /* totals since the last enable: launches, summed kernel milliseconds and

@@ -824,6 +824,16 @@ int amg_level_info(tp_amg_t amg, int32_t level, int32_t* n, int32_t* nnzA, int32
     return TP_OK;
 }
 
+int amg_level_format(tp_amg_t amg, int32_t level, int32_t* ndia, int32_t* lanes) {
+    TP_GUARD({
+        TP_CHECK_ARG(amg && ndia && lanes, "null argument");
+        TP_CHECK_ARG(level >= 0 && level < (int32_t)amg->lev.size(), "level out of range");
+        *ndia = amg->lev[level].ndia;
+        *lanes = amg->lev[level].gA;
+    });
+    return TP_OK;
+}
+
 int amg_level_copy(tp_amg_t amg, int32_t level, int32_t* A_rowptr, int32_t* A_col, double* A_val,
                    int32_t* cf, int32_t* P_rowptr, int32_t* P_col, double* P_val, int32_t* R_rowptr,
                    int32_t* R_col, double* R_val, void* stream) {

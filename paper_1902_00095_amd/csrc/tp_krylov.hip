@@ -152,27 +152,42 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-__device__ void arnoldi_update(const ArnoldiArgs& a, double nrm2) {
-    const int j = a.j, m = a.m;
-    double* H = a.H;
-    for (int i = 0; i <= j; ++i) H[i * m + j] = a.h1[i] + a.h2[i];
-    const double hn = sqrt(nrm2);
-    H[(j + 1) * m + j] = hn;
-    for (int i = 0; i < j; ++i) {
-        double x = H[i * m + j], y = H[(i + 1) * m + j];
-        H[i * m + j] = a.cs[i] * x + a.sn[i] * y;
-        H[(i + 1) * m + j] = -a.sn[i] * x + a.cs[i] * y;
+// Givens update of Hessenberg column j; the column, the previous rotations
+// and g are staged in LDS by the whole workgroup, rotated by one thread,
+// then written back in parallel.
+__device__ void arnoldi_update_block(const ArnoldiArgs& a, double nrm2, double* hc, double* cs, double* sn,
+                                     double* gg) {
+    const int j = a.j, m = a.m, t = threadIdx.x;
+    for (int i = t; i <= j; i += blockDim.x) {
+        hc[i] = a.h1[i] + a.h2[i];
+        if (i < j) { cs[i] = a.cs[i]; sn[i] = a.sn[i]; }
     }
-    double x = H[j * m + j], y = H[(j + 1) * m + j];
-    double den = hypot(x, y);
-    a.cs[j] = x / den;
-    a.sn[j] = y / den;
-    H[j * m + j] = den;
-    H[(j + 1) * m + j] = 0.0;
-    a.g[j + 1] = -a.sn[j] * a.g[j];
-    a.g[j] = a.cs[j] * a.g[j];
-    a.sc[0] = hn;
-    a.sc[1] = fabs(a.g[j + 1]);
+    if (t == 0) { gg[0] = a.g[j]; }
+    __syncthreads();
+    if (t == 0) {
+        const double hn = sqrt(nrm2);
+        hc[j + 1] = hn;
+        for (int i = 0; i < j; ++i) {
+            double x = hc[i], y = hc[i + 1];
+            hc[i] = cs[i] * x + sn[i] * y;
+            hc[i + 1] = -sn[i] * x + cs[i] * y;
+        }
+        double x = hc[j], y = hc[j + 1];
+        double den = hypot(x, y);
+        cs[j] = x / den;
+        sn[j] = y / den;
+        hc[j] = den;
+        hc[j + 1] = 0.0;
+        const double gj = gg[0];
+        a.g[j + 1] = -sn[j] * gj;
+        a.g[j] = cs[j] * gj;
+        a.cs[j] = cs[j];
+        a.sn[j] = sn[j];
+        a.sc[0] = hn;
+        a.sc[1] = fabs(-sn[j] * gj);
+    }
+    __syncthreads();
+    for (int i = t; i <= j + 1; i += blockDim.x) a.H[i * m + j] = hc[i];
 }
 
 template <int K>
@@ -230,16 +245,20 @@ constexpr int FIN_T = 1024;
 __global__ void __launch_bounds__(FIN_T)
 k_cgs_finish(int nb, int cnt, const double* __restrict__ part, double* __restrict__ out, int arn,
              ArnoldiArgs aa) {
+    __shared__ double hc[MAXK + 1], cs[MAXK], sn[MAXK], gg[1], nrm;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     for (int i = wave; i < cnt; i += FIN_T / 64) {
         double s = 0.0;
         for (int b = lane; b < nb; b += 64) s += part[(int64_t)i * nb + b];
         s = wave_sum(s);
-        if (lane == 0) out[i] = s;
+        if (lane == 0) {
+            out[i] = s;
+            if (i == 0) nrm = s;
+        }
     }
     if (!arn) return;
     __syncthreads();
-    if (t == 0) arnoldi_update(aa, out[0]);
+    arnoldi_update_block(aa, nrm, hc, cs, sn, gg);
 }
 
 // v = w / nrm (nrm on device)
@@ -333,8 +352,13 @@ struct Gmres {
     int nb;
     DBuf<double> V, Z, w, b, x, r, H, cs, sn, g, y, h1, h2, nrm2, part, sc;
     DBuf<unsigned int> ticket;
-    HostMail mail;
-    Gmres(int32_t n_, int m_, hipStream_t s) : n(n_), N(2 * (int64_t)n_), m(m_) {
+    HostMail& mail;
+    static HostMail& host_mail() {
+        // one pinned mailbox per host thread, kept for the process lifetime
+        static thread_local HostMail* box = new HostMail();
+        return *box;
+    }
+    Gmres(int32_t n_, int m_, hipStream_t s) : n(n_), N(2 * (int64_t)n_), m(m_), mail(host_mail()) {
         nb = (int)std::min<int64_t>(512, std::max<int64_t>(1, (N + 2 * CG_T - 1) / (2 * CG_T)));
         V.alloc((size_t)(m + 1) * N, s);
         Z.alloc((size_t)m * N, s);

@@ -188,6 +188,13 @@ int tp_init(const tp_allocator* alloc, int device) {
         TP_CHECK_ARG(device >= 0 && device < count, "device %d out of range (%d devices)", device, count);
         TP_HIP(hipSetDevice(device));
         tp::g_device = device;
+        // keep freed blocks in the device's stream-ordered pool instead of
+        // returning them to the driver at every synchronisation
+        hipMemPool_t pool = nullptr;
+        if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess && pool) {
+            uint64_t keep = UINT64_MAX;
+            TP_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+        }
         if (alloc) {
             TP_CHECK_ARG(alloc->alloc && alloc->free, "allocator needs alloc and free");
             tp::g_alloc = *alloc;

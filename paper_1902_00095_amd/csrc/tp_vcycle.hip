@@ -647,6 +647,60 @@ extern "C" int amg_cnn_loss_grad(tp_amg_t amg, const float* feat, const float* t
     return TP_OK;
 }
 
+namespace tp {
+template <typename T>
+static double replay_fine_smoother(tp_amg* h, int reps, hipStream_t s, double* bytes) {
+    Level& L = h->lev[0];
+    const int32_t n = L.A.n;
+    const size_t es = sizeof(T);
+    T* xa = (T*)L.x.p;
+    T* xb = (T*)L.x2.p;
+    T* d = (T*)L.d.p;
+    T* b = (T*)L.b.p;
+    for (T* v : {xa, xb, d, b}) TP_LAUNCH(k_zero<T>, cdiv(n, VB), VB, 0, s, n, v);
+    const T* dv = LevelVals<T>::dinv(L);
+    const double lo = h->prm.cheb_lo, theta = 0.5 * (1.0 + lo), delta = 0.5 * (1.0 - lo), sigma = theta / delta;
+    const double rho1 = 1.0 / (2.0 * sigma - 1.0 / sigma), c1 = rho1 / sigma, c2 = 2.0 * rho1 / delta;
+    hipEvent_t e0, e1;
+    TP_HIP(hipEventCreate(&e0));
+    TP_HIP(hipEventCreate(&e1));
+    TP_HIP(hipEventRecord(e0, s));
+    for (int k = 0; k < reps; ++k) {
+        T* in = (k & 1) ? xb : xa;
+        T* out = (k & 1) ? xa : xb;
+        if (L.ndia) {
+            TP_ND_DISPATCH(L.ndia, TP_LAUNCH((k_cheb_step_dia<T, NDD>), cdiv(n, VB), VB, 0, s, n, LevelVals<T>::D(L),
+                                             dia_offsets<NDD>(L), dv, b, in, out, d, 0, (T)theta, (T)c1, (T)c2));
+        } else {
+            TP_G_DISPATCH(L.gA, TP_LAUNCH((k_cheb_step<T, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p,
+                                          L.A.col.p, LevelVals<T>::A(L), dv, b, in, out, d, 0, (T)theta, (T)c1,
+                                          (T)c2));
+        }
+    }
+    TP_HIP(hipEventRecord(e1, s));
+    TP_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    TP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    TP_HIP(hipEventDestroy(e0));
+    TP_HIP(hipEventDestroy(e1));
+    *bytes = (L.ndia ? (double)L.ndia * n * es : (double)L.A.nnz * (es + 4) + 4.0 * (n + 1)) + 6.0 * es * n;
+    return (double)ms / reps;
+}
+}  // namespace tp
+
+extern "C" int amg_time_fine_smoother(tp_amg_t amg, int32_t reps, double* ms_per_launch,
+                                      double* bytes_per_launch, void* stream) {
+    TP_GUARD({
+        TP_CHECK_ARG(amg && ms_per_launch && bytes_per_launch, "amg_time_fine_smoother: null argument");
+        TP_CHECK_ARG(reps >= 1 && reps <= 100000, "amg_time_fine_smoother: reps out of range");
+        TP_CHECK_ARG(amg->lev.size() >= 2, "amg_time_fine_smoother: needs at least two levels");
+        hipStream_t s = (hipStream_t)stream;
+        *ms_per_launch = amg->prm.storage == 1 ? tp::replay_fine_smoother<float>(amg, reps, s, bytes_per_launch)
+                                               : tp::replay_fine_smoother<double>(amg, reps, s, bytes_per_launch);
+    });
+    return TP_OK;
+}
+
 extern "C" int amg_vcycle(tp_amg_t amg, const double* b, double* x, void* stream) {
     TP_GUARD({
         TP_CHECK_ARG(amg && b && x, "amg_vcycle: null argument");

@@ -74,12 +74,12 @@ class _Allocator(C.Structure):
 
 
 EXPORTS = ["tp_last_error", "tp_init", "tp_jacobian_sizes", "assemble_tpfa", "amg_setup",
-           "amg_num_levels", "amg_level_info", "amg_level_copy", "amg_vcycle", "amg_destroy",
+           "amg_num_levels", "amg_level_info", "amg_level_format", "amg_level_copy", "amg_vcycle", "amg_destroy",
            "precond_create", "precond_apply", "precond_destroy", "fgmres_solve",
            "cnn_create", "cnn_get_params", "cnn_get_grad", "cnn_destroy", "cnn_forward", "cnn_loss_grad",
            "cnn_adam_step", "amg_attach_post_smoother", "amg_features", "amg_presmoothed_pair",
            "amg_cnn_loss_grad",
-           "tp_timer_enable", "tp_timer_read"]
+           "amg_time_fine_smoother", "tp_timer_enable", "tp_timer_read"]
 CNN_NPARAM = 3905
 
 _lib = None
@@ -270,6 +270,40 @@ class AMG:
         _check(_lib.amg_level_info(self.h, C.c_int32(l), C.byref(n), C.byref(a), C.byref(p),
                                    C.byref(r)))
         return n.value, a.value, p.value, r.value
+
+    def time_fine_smoother(self, reps=200, stream=None):
+        ms, b = C.c_double(), C.c_double()
+        _check(_lib.amg_time_fine_smoother(self.h, C.c_int32(reps), C.byref(ms), C.byref(b),
+                                           _stream(stream)))
+        return ms.value, b.value
+
+    def level_format(self, l):
+        nd, g = C.c_int32(), C.c_int32()
+        _check(_lib.amg_level_format(self.h, C.c_int32(l), C.byref(nd), C.byref(g)))
+        return nd.value, g.value
+
+    def vcycle_bytes(self):
+        """Algorithmic bytes of one V-cycle (each array read or written once
+        per pass): Chebyshev(3) pre/post sweeps with the zero-guess steps
+        fused, residual, restriction, prolongation, coarse dense inverse."""
+        es = 4 if self.params.storage == 1 else 8
+        deg = self.params.cheb_degree
+        total = 0.0
+        L = self.nlev
+        for l in range(L):
+            n, nnzA, nnzP, nnzR = self.level_sizes(l)
+            if l == L - 1:
+                total += n * n * 8 + 2 * n * es
+                continue
+            nc = self.level_sizes(l + 1)[0]
+            nd, _ = self.level_format(l)
+            mA = nd * n * es if nd else nnzA * (es + 4) + (n + 1) * 4
+            mP = nnzP * (es + 4) + (n + 1) * 4
+            mR = nnzR * (es + 4) + (nc + 1) * 4
+            pre = (mA + 4 * n * es) + (deg - 2) * (mA + 6 * n * es)
+            post = (mA + 5 * n * es) + (deg - 1) * (mA + 6 * n * es)
+            total += pre + (mA + 3 * n * es) + (mR + (n + nc) * es) + (mP + (2 * n + nc) * es) + post
+        return total
 
     def level(self, l, stream=None):
         torch = _torch()
