@@ -30,6 +30,7 @@ struct Level {
 }  // namespace tp
 
 struct tp_amg {
+    tp::Arena arena;             // owns every setup allocation (declared first: destroyed last)
     tp_amg_params prm;
     std::vector<tp::Level> lev;  // lev.back() is the coarsest level
     int32_t nc = 0;              // coarsest size

@@ -793,6 +793,7 @@ int amg_setup(int32_t n, const int32_t* rowptr, const int32_t* col, const double
         h->prm = p;
         h->stream = s;
         try {
+            tp::ArenaScope scope(&h->arena);
             tp::setup(h, n, rowptr, col, val, s);
         } catch (...) {
             delete h;

@@ -59,33 +59,55 @@ void* dalloc(size_t bytes, hipStream_t s);
 void dfree(void* p, hipStream_t s);
 int current_device();
 
+// Bump allocator over large device chunks.  While an ArenaScope is active on
+// a host thread, every DBuf allocation of that thread is carved from the
+// arena and its individual free is a no-op; the arena returns its chunks
+// when it is destroyed.  Used for AMG setups (no frees during setup, a few
+// frees at teardown).
+struct Arena {
+    std::vector<void*> chunks;
+    char* cur = nullptr;
+    size_t left = 0;
+    hipStream_t s = nullptr;
+    size_t bytes_used = 0;
+    ~Arena();
+};
+bool arena_active();
+struct ArenaScope {
+    Arena* prev;
+    explicit ArenaScope(Arena* a);
+    ~ArenaScope();
+};
+
 // Owning device buffer (stream-ordered free).
 template <typename T>
 struct DBuf {
     T* p = nullptr;
     size_t n = 0;
     hipStream_t s = nullptr;
+    bool in_arena = false;
     DBuf() = default;
     DBuf(size_t count, hipStream_t st) { alloc(count, st); }
     void alloc(size_t count, hipStream_t st) {
         release();
         s = st;
         n = count;
+        in_arena = arena_active();
         p = count ? static_cast<T*>(dalloc(count * sizeof(T), st)) : nullptr;
     }
     void release() {
-        if (p) dfree(p, s);
+        if (p && !in_arena) dfree(p, s);
         p = nullptr;
         n = 0;
     }
     ~DBuf() { release(); }
     DBuf(const DBuf&) = delete;
     DBuf& operator=(const DBuf&) = delete;
-    DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), s(o.s) { o.p = nullptr; o.n = 0; }
+    DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), s(o.s), in_arena(o.in_arena) { o.p = nullptr; o.n = 0; }
     DBuf& operator=(DBuf&& o) noexcept {
         if (this != &o) {
             release();
-            p = o.p; n = o.n; s = o.s;
+            p = o.p; n = o.n; s = o.s; in_arena = o.in_arena;
             o.p = nullptr; o.n = 0;
         }
         return *this;

@@ -23,7 +23,13 @@ void cast_d2s(int32_t n, const double* a, void* b, size_t es, hipStream_t s);
 void cast_s2d(int32_t n, const void* a, double* b, size_t es, hipStream_t s);
 }  // namespace tp
 
+namespace tp {
+struct Gmres;
+void gmres_free(Gmres* g);
+}  // namespace tp
+
 struct tp_prec {
+    tp::Gmres* ws = nullptr;  // FGMRES workspace kept across solves of the same size
     tp_jacobian J;
     tp_amg* pp = nullptr;
     tp_amg* S = nullptr;
@@ -407,11 +413,21 @@ static double read_d(const double* dptr, HostMail& mail, hipStream_t s) {
     return *mail.as<double>();
 }
 
+void gmres_free(Gmres* g) { delete g; }
+
 static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* x_il,
                   const tp_krylov_params& kp, tp_krylov_stats* st, double* history, hipStream_t s) {
     const int32_t n = J.n;
     const int m = kp.restart;
-    Gmres G(n, m, s);
+    if (!M->ws || M->ws->n != n || M->ws->m != m) {
+        if (M->ws) {
+            TP_HIP(hipDeviceSynchronize());
+            delete M->ws;
+            M->ws = nullptr;
+        }
+        M->ws = new Gmres(n, m, s);
+    }
+    Gmres& G = *M->ws;
     const int gn = cdiv(n, KB);
     const int gN = cdiv(G.N, KB);
     const int gJ = cdiv((int64_t)n * JG, KB);
@@ -539,7 +555,13 @@ int precond_apply(tp_prec_t M, const double* r, double* z, void* stream) {
 }
 
 int precond_destroy(tp_prec_t M) {
-    TP_GUARD({ delete M; });
+    TP_GUARD({
+        if (M) {
+            TP_HIP(hipDeviceSynchronize());
+            tp::gmres_free(M->ws);
+            delete M;
+        }
+    });
     return TP_OK;
 }
 

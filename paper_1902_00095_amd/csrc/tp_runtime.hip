@@ -27,9 +27,49 @@ void fail(int code, const char* fmt, ...) {
 
 int current_device() { return g_device; }
 
+static thread_local Arena* g_arena = nullptr;
+constexpr size_t ARENA_CHUNK = size_t(64) << 20;
+constexpr size_t ARENA_ALIGN = 256;
+
+bool arena_active() { return g_arena != nullptr; }
+ArenaScope::ArenaScope(Arena* a) : prev(g_arena) { g_arena = a; }
+ArenaScope::~ArenaScope() { g_arena = prev; }
+
+static void* raw_alloc(size_t bytes, hipStream_t s);
+
+static void* arena_alloc(Arena* a, size_t bytes, hipStream_t s) {
+    bytes = (bytes + ARENA_ALIGN - 1) / ARENA_ALIGN * ARENA_ALIGN;
+    if (bytes > a->left) {
+        const size_t sz = bytes > ARENA_CHUNK / 4 ? bytes : ARENA_CHUNK;
+        void* c = raw_alloc(sz, s);
+        a->chunks.push_back(c);
+        if (a->chunks.size() == 1) a->s = s;
+        if (sz == bytes && bytes > ARENA_CHUNK / 4) {  // dedicated chunk, keep the open one
+            a->bytes_used += bytes;
+            return c;
+        }
+        a->cur = static_cast<char*>(c);
+        a->left = sz;
+    }
+    void* p = a->cur;
+    a->cur += bytes;
+    a->left -= bytes;
+    a->bytes_used += bytes;
+    return p;
+}
+
+Arena::~Arena() {
+    for (void* c : chunks) dfree(c, s);
+}
+
 void* dalloc(size_t bytes, hipStream_t s) {
     if (g_device < 0) fail(TP_ERR_ARG, "tp_init has not been called");
     if (bytes == 0) bytes = 1;
+    if (g_arena) return arena_alloc(g_arena, bytes, s);
+    return raw_alloc(bytes, s);
+}
+
+static void* raw_alloc(size_t bytes, hipStream_t s) {
     void* p = nullptr;
     if (g_has_alloc) {
         p = g_alloc.alloc(bytes, (void*)s, g_alloc.ctx);
