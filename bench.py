@@ -213,11 +213,15 @@ def main():
     torch.cuda.synchronize()
     precond_ms = (time.perf_counter() - ts) * 1e3 / nrep
 
-    # whole preconditioner apply: both V-cycles, the A_Tp product, casts
+    # whole preconditioner apply: both V-cycles; the A_Tp product (its CSR
+    # block and z_p, r_T read, the Schur right-hand side written); splitting r
+    # and interleaving z (2n doubles read and written each); with FP32
+    # storage, the conversions of r_p in and of z_p, z_T out
     n = prob.grid.n
-    es_b = 8
-    pre_bytes = a_pp.vcycle_bytes() + a_S.vcycle_bytes() + (J.nnz * 12 + (n + 1) * 4 + 3 * n * 8) \
-        + 4 * n * es_b * 2 + 2 * n * 8 * 2
+    es = 4 if args.storage == 1 else 8
+    conv = 3 * n * (8 + es) if args.storage == 1 else 0
+    pre_bytes = a_pp.vcycle_bytes() + a_S.vcycle_bytes() \
+        + (J.nnz * 12 + (n + 1) * 4 + 2 * n * 8 + n * es) + 2 * (2 * n * 8 * 2) + conv
     vcycle_gbs = pre_bytes / (precond_ms * 1e-3) / 1e9
     # the dominant kernel replayed back to back on the same operator (both
     # hierarchies' fine levels have the same shape; the Schur one is timed)

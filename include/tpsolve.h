@@ -162,7 +162,12 @@ int amg_destroy(tp_amg_t amg);
 typedef struct tp_prec* tp_prec_t;
 int precond_create(const tp_jacobian* J, tp_amg_t amg_pp, tp_amg_t amg_S,
                    int32_t variant, tp_prec_t* out);
-/* z = M^{-1} r, 2n interleaved device vectors */
+/* z = M^{-1} r, 2n interleaved device vectors.  The apply is captured as a
+ * HIP graph (kernels only) on its first use and replayed afterwards on
+ * `stream`; while a learned smoother is active or the kernel timer is on,
+ * its kernels are launched one by one.  Calls on one handle must not overlap
+ * (they share the handle's staging vectors and the hierarchies' work
+ * vectors). */
 int precond_apply(tp_prec_t M, const double* r, double* z, void* stream);
 int precond_destroy(tp_prec_t M);
 
@@ -183,6 +188,11 @@ typedef struct {
      * non-finite value), the network is switched off for the rest of the
      * solve and the hierarchy's own post-smoother is used.  0 disables. */
     double stag_ratio;
+    /* 1: the preconditioner apply is captured once per (handle, stream) as a
+     * HIP graph and replayed each iteration (not while a learned smoother is
+     * active or the kernel timer is on); 0: its kernels are launched one by
+     * one.  Both give bit-identical iterates. */
+    int32_t graph;
 } tp_krylov_params;
 typedef struct {
     int32_t iters, restarts;

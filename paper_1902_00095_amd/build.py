@@ -10,8 +10,9 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtpsolve.so")
 
 # -ffp-contract=off keeps the setup arithmetic in the order written (no fused
-# multiply-add), so AMG setup values follow one canonical rounding sequence;
-# packed-fp32 instructions are disabled (see DESIGN notes on the toolchain).
+# multiply-add), so AMG setup values follow one canonical rounding sequence.
+# Packed FP32 instructions are disabled: some of their forms have produced
+# silently wrong results on this target.
 HIPCC_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
                "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                "-Wall", "-Wno-unused-result"]

@@ -43,8 +43,10 @@ struct tp_amg {
 namespace tp {
 // Run one V-cycle on the level-0 right-hand side already placed in lev[0].b
 // (or at `b_ext` when non-null, same element type as the storage).  Returns
-// a device pointer to the level-0 solution (element type of the storage).
-const void* vcycle_run(tp_amg* h, const void* b_ext, hipStream_t s);
+// a device pointer to the level-0 solution (element type of the storage):
+// `x_ext` when non-null and the cycle ends in a smoothing step that can
+// write there, else one of the level's work vectors.
+const void* vcycle_run(tp_amg* h, const void* b_ext, hipStream_t s, void* x_ext = nullptr);
 // element size of the hierarchy's storage
 inline size_t storage_bytes(const tp_amg* h) { return h->prm.storage == 1 ? 4 : 8; }
 }  // namespace tp

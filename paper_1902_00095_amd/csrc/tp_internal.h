@@ -27,9 +27,11 @@ void set_error(const char* fmt, ...);
 #define TP_HIP(call)                                                                  \
     do {                                                                              \
         hipError_t e_ = (call);                                                       \
-        if (e_ != hipSuccess)                                                         \
+        if (e_ != hipSuccess) {                                                       \
+            (void)hipGetLastError(); /* reported here: do not leave it to the next call */ \
             ::tp::fail(TP_ERR_HIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
                        __FILE__, __LINE__);                                           \
+        }                                                                             \
     } while (0)
 
 #define TP_CHECK_ARG(cond, ...)                                                       \
@@ -157,10 +159,14 @@ void timer_collect();  // fold recorded pairs into totals (synchronises events)
 // Launch, with the timer's event pair when `timed` (null events otherwise).
 #define TP_LAUNCH_TIMED(timed, bytes, kernel, grid, block, shmem, stream, ...)           \
     do {                                                                              \
-        hipEvent_t e0_ = nullptr, e1_ = nullptr;                                      \
-        if (timed) ::tp::timer_events((bytes), &e0_, &e1_);                           \
-        hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), shmem, stream, e0_, e1_, 0, \
-                              __VA_ARGS__);                                           \
+        if (timed) {                                                                  \
+            hipEvent_t e0_ = nullptr, e1_ = nullptr;                                  \
+            ::tp::timer_events((bytes), &e0_, &e1_);                                  \
+            hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), shmem, stream, e0_, e1_, 0, \
+                                  __VA_ARGS__);                                       \
+        } else {                                                                      \
+            hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), shmem, stream, __VA_ARGS__); \
+        }                                                                             \
         TP_HIP(hipGetLastError());                                                    \
     } while (0)
 

@@ -30,6 +30,13 @@ void gmres_free(Gmres* g);
 
 struct tp_prec {
     tp::Gmres* ws = nullptr;  // FGMRES workspace kept across solves of the same size
+    // The split-vector apply captured once as a HIP graph (kernels only, no
+    // stream-specific state) on fixed staging vectors rin -> zout.
+    // Captured on a private stream (capture is not allowed on the legacy
+    // null stream that callers often pass).
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t cap = nullptr;
+    tp::DBuf<double> rin, zout;
     tp_jacobian J;
     tp_amg* pp = nullptr;
     tp_amg* S = nullptr;
@@ -98,7 +105,7 @@ __global__ void __launch_bounds__(KB)
 k_block_spmv(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
              const double* __restrict__ pp, const double* __restrict__ pT, const double* __restrict__ Tp,
              const double* __restrict__ TT, const double* __restrict__ z, const double* __restrict__ b,
-             double* __restrict__ w) {
+             double* __restrict__ w, double* __restrict__ zcopy) {
     const int64_t tid = (int64_t)blockIdx.x * KB + threadIdx.x;
     const int32_t i = (int32_t)(tid / JG);
     const int lane = (int)(tid % JG);
@@ -125,6 +132,10 @@ k_block_spmv(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restric
         } else {
             w[i] = sm;
             w[n + i] = se;
+        }
+        if (zcopy) {
+            zcopy[i] = z[i];
+            zcopy[n + i] = z[n + i];
         }
     }
 }
@@ -267,11 +278,15 @@ k_cgs_finish(int nb, int cnt, const double* __restrict__ part, double* __restric
     arnoldi_update_block(aa, nrm, hc, cs, sn, gg);
 }
 
-// v = w / nrm (nrm on device)
+// v = w / nrm (nrm on device); optionally also into v2 (the graph's input)
 __global__ void __launch_bounds__(KB)
-k_scale_div(int64_t N, const double* __restrict__ w, const double* __restrict__ nrm, double* __restrict__ v) {
+k_scale_div(int64_t N, const double* __restrict__ w, const double* __restrict__ nrm, double* __restrict__ v,
+            double* __restrict__ v2) {
     int64_t i = (int64_t)blockIdx.x * KB + threadIdx.x;
-    if (i < N) v[i] = w[i] / nrm[0];
+    if (i >= N) return;
+    const double q = w[i] / nrm[0];
+    v[i] = q;
+    if (v2) v2[i] = q;
 }
 
 // start of a cycle: beta = sqrt(nrm2); g = [beta, 0, ...]; sc[0] = beta
@@ -306,8 +321,15 @@ k_xupdate(int64_t N, int k, const double* __restrict__ Z, const double* __restri
 }
 
 // ---- preconditioner on split vectors ------------------------------------------------------
+// One V-cycle of h on rhs into out.  With FP64 storage the cycle reads rhs
+// and writes out directly; with FP32 storage both are converted.
 static void vsolve(tp_amg* h, const double* rhs, double* out, int32_t n, hipStream_t s) {
     const size_t es = storage_bytes(h);
+    if (es == 8) {
+        const void* x = vcycle_run(h, rhs, s, out);
+        if (x != out) cast_s2d(n, x, out, es, s);
+        return;
+    }
     cast_d2s(n, rhs, h->lev[0].b.p, es, s);
     const void* x = vcycle_run(h, nullptr, s);
     cast_s2d(n, x, out, es, s);
@@ -325,8 +347,9 @@ static void sub_into_b(const tp_jacobian& J, const double* M, const double* x, c
 }
 
 static void run_from_b(tp_amg* h, double* out, int32_t n, hipStream_t s) {
-    const void* x = vcycle_run(h, nullptr, s);
-    cast_s2d(n, x, out, storage_bytes(h), s);
+    const size_t es = storage_bytes(h);
+    const void* x = vcycle_run(h, nullptr, s, es == 8 ? out : nullptr);
+    if (x != out) cast_s2d(n, x, out, es, s);
 }
 
 void prec_apply_split(tp_prec* M, const double* r, double* z, hipStream_t s) {
@@ -348,6 +371,39 @@ void prec_apply_split(tp_prec* M, const double* r, double* z, hipStream_t s) {
         sub_into_b(M->J, M->J.pT, zT, rp, M->pp, s);  // step 4
         run_from_b(M->pp, zp, n, s);                  // step 5
     }
+}
+
+// ---- graph of the preconditioner apply -------------------------------------------------------
+static bool graph_usable(tp_prec* M) {
+    return !(M->S->cnn && M->S->cnn->enabled) && !(M->pp->cnn && M->pp->cnn->enabled) && !timer().on;
+}
+
+// capture prec_apply_split(rin -> zout) the first time (staging vectors
+// allocated on the solve stream s); the instantiated graph is then launched
+// on whatever stream the solve runs on
+static void graph_ensure(tp_prec* M, hipStream_t s) {
+    if (M->gexec) return;
+    const int32_t n = M->J.n;
+    M->rin.alloc(2 * (size_t)n, s);
+    M->zout.alloc(2 * (size_t)n, s);
+    if (!M->cap) TP_HIP(hipStreamCreateWithFlags(&M->cap, hipStreamNonBlocking));
+    const hipStream_t c = M->cap;
+    hipGraph_t g = nullptr;
+    TP_HIP(hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal));
+    try {
+        prec_apply_split(M, M->rin.p, M->zout.p, c);
+    } catch (...) {
+        hipGraph_t junk = nullptr;
+        (void)hipStreamEndCapture(c, &junk);
+        if (junk) (void)hipGraphDestroy(junk);
+        throw;
+    }
+    TP_HIP(hipStreamEndCapture(c, &g));
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    TP_HIP(e);
+    M->gexec = ex;
 }
 
 // ---- FGMRES driver ------------------------------------------------------------------------------
@@ -447,7 +503,8 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
         if (history) history[0] = 0.0;
         rel = est = 0.0;
     } else {
-        TP_LAUNCH(k_block_spmv, gJ, KB, 0, s, n, J.rowptr, J.col, J.pp, J.pT, J.Tp, J.TT, G.x.p, G.b.p, G.r.p);
+        TP_LAUNCH(k_block_spmv, gJ, KB, 0, s, n, J.rowptr, J.col, J.pp, J.pT, J.Tp, J.TT, G.x.p, G.b.p, G.r.p,
+                  (double*)nullptr);
         dots(G, 0, nullptr, G.r.p, 2, G.nrm2.p, s);
         rel = std::sqrt(read_d(G.nrm2.p, G.mail, s)) / bnorm;
         est = rel;
@@ -455,19 +512,29 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
         while (rel > kp.rtol && it < kp.maxit) {
             if (!std::isfinite(rel)) fail(TP_ERR_NUMERIC, "non-finite residual in FGMRES");
             // v_0 = r / beta (nrm2 holds ||r||^2)
+            const bool use_graph = kp.graph != 0 && graph_usable(M);
+            if (use_graph) graph_ensure(M, s);
             TP_LAUNCH(k_cycle_init, 1, 1, 0, s, m, G.nrm2.p, G.g.p, G.sc.p);
-            TP_LAUNCH(k_scale_div, gN, KB, 0, s, G.N, G.r.p, G.sc.p, G.V.p);
+            TP_LAUNCH(k_scale_div, gN, KB, 0, s, G.N, G.r.p, G.sc.p, G.V.p, use_graph ? M->rin.p : nullptr);
             int k = 0;
             for (int j = 0; j < m && it < kp.maxit; ++j) {
                 double* vj = G.V.p + (int64_t)j * G.N;
                 double* zj = G.Z.p + (int64_t)j * G.N;
-                prec_apply_split(M, vj, zj, s);
-                TP_LAUNCH(k_block_spmv, gJ, KB, 0, s, n, J.rowptr, J.col, J.pp, J.pT, J.Tp, J.TT, zj,
-                          (const double*)nullptr, G.w.p);
+                if (use_graph) {
+                    // rin already holds v_j; the product kernel copies zout into Z_j
+                    TP_HIP(hipGraphLaunch(M->gexec, s));
+                    TP_LAUNCH(k_block_spmv, gJ, KB, 0, s, n, J.rowptr, J.col, J.pp, J.pT, J.Tp, J.TT, M->zout.p,
+                              (const double*)nullptr, G.w.p, zj);
+                } else {
+                    prec_apply_split(M, vj, zj, s);
+                    TP_LAUNCH(k_block_spmv, gJ, KB, 0, s, n, J.rowptr, J.col, J.pp, J.pT, J.Tp, J.TT, zj,
+                              (const double*)nullptr, G.w.p, (double*)nullptr);
+                }
                 dots(G, j + 1, nullptr, G.w.p, 0, G.h1.p, s);
                 dots(G, j + 1, G.h1.p, G.w.p, 1, G.h2.p, s);
                 dots(G, j + 1, G.h2.p, G.w.p, 2, G.nrm2.p, s, 1, j);
-                TP_LAUNCH(k_scale_div, gN, KB, 0, s, G.N, G.w.p, G.sc.p, G.V.p + (int64_t)(j + 1) * G.N);
+                TP_LAUNCH(k_scale_div, gN, KB, 0, s, G.N, G.w.p, G.sc.p, G.V.p + (int64_t)(j + 1) * G.N,
+                          use_graph ? M->rin.p : nullptr);
                 TP_HIP(hipMemcpyAsync(G.mail.p, G.sc.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
                 TP_HIP(hipStreamSynchronize(s));
                 const double hn = G.mail.as<double>()[0];
@@ -495,7 +562,7 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
             TP_LAUNCH(k_hess_solve, 1, 1, 0, s, k, m, G.H.p, G.g.p, G.y.p);
             TP_LAUNCH(k_xupdate, gN, KB, 0, s, G.N, k, G.Z.p, G.y.p, G.x.p);
             TP_LAUNCH(k_block_spmv, gJ, KB, 0, s, n, J.rowptr, J.col, J.pp, J.pT, J.Tp, J.TT, G.x.p, G.b.p,
-                      G.r.p);
+                      G.r.p, (double*)nullptr);
             dots(G, 0, nullptr, G.r.p, 2, G.nrm2.p, s);
             rel = std::sqrt(read_d(G.nrm2.p, G.mail, s)) / bnorm;
             ++restarts;
@@ -543,13 +610,20 @@ int precond_apply(tp_prec_t M, const double* r, double* z, void* stream) {
         TP_CHECK_ARG(M && r && z, "precond_apply: null argument");
         hipStream_t s = (hipStream_t)stream;
         const int32_t n = M->J.n;
-        if (M->rs.n != (size_t)2 * n) {
-            M->rs.alloc(2 * (size_t)n, s);
-            M->zs.alloc(2 * (size_t)n, s);
+        if (tp::graph_usable(M)) {
+            tp::graph_ensure(M, s);
+            TP_LAUNCH(tp::k_deinterleave, tp::cdiv(n, tp::KB), tp::KB, 0, s, n, r, M->rin.p);
+            TP_HIP(hipGraphLaunch(M->gexec, s));
+            TP_LAUNCH(tp::k_interleave, tp::cdiv(n, tp::KB), tp::KB, 0, s, n, M->zout.p, z);
+        } else {
+            if (M->rs.n != (size_t)2 * n) {
+                M->rs.alloc(2 * (size_t)n, s);
+                M->zs.alloc(2 * (size_t)n, s);
+            }
+            TP_LAUNCH(tp::k_deinterleave, tp::cdiv(n, tp::KB), tp::KB, 0, s, n, r, M->rs.p);
+            tp::prec_apply_split(M, M->rs.p, M->zs.p, s);
+            TP_LAUNCH(tp::k_interleave, tp::cdiv(n, tp::KB), tp::KB, 0, s, n, M->zs.p, z);
         }
-        TP_LAUNCH(tp::k_deinterleave, tp::cdiv(n, tp::KB), tp::KB, 0, s, n, r, M->rs.p);
-        tp::prec_apply_split(M, M->rs.p, M->zs.p, s);
-        TP_LAUNCH(tp::k_interleave, tp::cdiv(n, tp::KB), tp::KB, 0, s, n, M->zs.p, z);
     });
     return TP_OK;
 }
@@ -559,6 +633,8 @@ int precond_destroy(tp_prec_t M) {
         if (M) {
             TP_HIP(hipDeviceSynchronize());
             tp::gmres_free(M->ws);
+            if (M->gexec) (void)hipGraphExecDestroy(M->gexec);
+            if (M->cap) (void)hipStreamDestroy(M->cap);
             delete M;
         }
     });

@@ -50,12 +50,21 @@ k_cheb_step(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict
     const int32_t i = (int32_t)(tid / G);
     const int lane = (int)(tid % G);
     const bool valid = i < n;
+    const bool head = valid && lane == 0;
+    // the row's own operands do not depend on the product: load them first
+    T bi = 0, di = 0, xi = 0, dprev = 0;
+    if (head) {
+        bi = b[i];
+        di = dinv[i];
+        xi = xin[i];
+        if (!first) dprev = d[i];
+    }
     T ax = row_dot<T, G>(rp, ci, av, xin, i, lane, valid);
-    if (valid && lane == 0) {
-        T r = dinv[i] * (b[i] - ax);
-        T dn = first ? r / theta : c1 * d[i] + c2 * r;
+    if (head) {
+        T r = di * (bi - ax);
+        T dn = first ? r / theta : c1 * dprev + c2 * r;
         d[i] = dn;
-        xout[i] = xin[i] + dn;
+        xout[i] = xi + dn;
     }
 }
 
@@ -68,8 +77,15 @@ k_jac_step(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict_
     const int32_t i = (int32_t)(tid / G);
     const int lane = (int)(tid % G);
     const bool valid = i < n;
+    const bool head = valid && lane == 0;
+    T bi = 0, di = 0, xi = 0;
+    if (head) {
+        bi = b[i];
+        di = dinv[i];
+        xi = xin[i];
+    }
     T ax = row_dot<T, G>(rp, ci, av, xin, i, lane, valid);
-    if (valid && lane == 0) xout[i] = xin[i] + w * dinv[i] * (b[i] - ax);
+    if (head) xout[i] = xi + w * di * (bi - ax);
 }
 
 // r = b - A x
@@ -82,8 +98,10 @@ k_residual(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict_
     const int32_t i = (int32_t)(tid / G);
     const int lane = (int)(tid % G);
     const bool valid = i < n;
+    const bool head = valid && lane == 0;
+    const T bi = head ? b[i] : T(0);
     T ax = row_dot<T, G>(rp, ci, av, x, i, lane, valid);
-    if (valid && lane == 0) r[i] = b[i] - ax;
+    if (head) r[i] = bi - ax;
 }
 
 // y = M x (restriction), or y += M x (prolongation, add = 1)
@@ -95,8 +113,10 @@ k_spmv(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci
     const int32_t i = (int32_t)(tid / G);
     const int lane = (int)(tid % G);
     const bool valid = i < n;
+    const bool head = valid && lane == 0;
+    const T yi = head && add ? y[i] : T(0);
     T s = row_dot<T, G>(rp, ci, av, x, i, lane, valid);
-    if (valid && lane == 0) y[i] = add ? y[i] + s : s;
+    if (head) y[i] = add ? yi + s : s;
 }
 
 // ---- DIA (stencil-level) kernels: one thread per row, no column indices --------
@@ -178,16 +198,24 @@ k_cheb01(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ 
     const int32_t i = (int32_t)(tid / G);
     const int lane = (int)(tid % G);
     const bool valid = i < n;
+    const bool head = valid && lane == 0;
+    T bi = 0, di = 0;
+    if (head) {
+        bi = b[i];
+        di = dinv[i];
+    }
     T s = 0;
-    if (valid)
-        for (int32_t q = rp[i] + lane; q < rp[i + 1]; q += G) {
+    if (valid) {
+        const int32_t e = rp[i + 1];
+        for (int32_t q = rp[i] + lane; q < e; q += G) {
             const int32_t j = ci[q];
             s += av[q] * ((dinv[j] * b[j]) / theta);
         }
+    }
     s = group_sum<T, G>(s);
-    if (valid && lane == 0) {
-        const T x0 = (dinv[i] * b[i]) / theta;
-        const T r = dinv[i] * (b[i] - s);
+    if (head) {
+        const T x0 = (di * bi) / theta;
+        const T r = di * (bi - s);
         const T dn = c1 * x0 + c2 * r;
         d[i] = dn;
         xout[i] = x0 + dn;
@@ -351,9 +379,11 @@ template <> struct LevelVals<float> {
 static inline int grid_rows(int32_t n, int G) { return cdiv((int64_t)std::max(n, 1) * G, VB); }
 
 // smoothing sweeps on level L; x_cur in/out (ping-pong between x and x2)
+// final_out (optional): buffer for the sweep's last step, so the result can
+// land in the caller's vector; the returned pointer says where it is.
 template <typename T>
 static T* smooth(tp_amg* h, int l, const T* b, T* xc, bool zero, int nu, hipStream_t s,
-                 bool first_done = false) {
+                 bool first_done = false, T* final_out = nullptr) {
     Level& L = h->lev[l];
     const tp_amg_params& p = h->prm;
     const int32_t n = L.A.n;
@@ -364,6 +394,7 @@ static T* smooth(tp_amg* h, int l, const T* b, T* xc, bool zero, int nu, hipStre
     T* d = (T*)L.d.p;
     T* cur = xc;
     auto other = [&](T* q) { return q == xa ? xb : xa; };
+    auto target = [&](T* q, bool last) { return last && final_out ? final_out : other(q); };
     const double lo = p.cheb_lo, theta = 0.5 * (1.0 + lo), delta = 0.5 * (1.0 - lo);
     const double sigma = theta / delta;
     const size_t es = sizeof(T);
@@ -374,7 +405,7 @@ static T* smooth(tp_amg* h, int l, const T* b, T* xc, bool zero, int nu, hipStre
             // steps 0 and 1 in one pass
             const double rho1 = 1.0 / (2.0 * sigma - 1.0 / sigma);
             const double c1 = rho1 * (1.0 / sigma), c2 = 2.0 * rho1 / delta;
-            T* nx = other(cur);
+            T* nx = target(cur, sw == nu - 1 && p.cheb_degree == 2);
             const bool timed = l == 0;
             const double bytes = (L.ndia ? (double)L.ndia * n * es : (double)L.A.nnz * (es + 4) + 4.0 * (n + 1)) +
                                  4.0 * es * n;
@@ -399,7 +430,7 @@ static T* smooth(tp_amg* h, int l, const T* b, T* xc, bool zero, int nu, hipStre
                 first_done = false;
                 continue;
             }
-            T* nx = other(cur);
+            T* nx = target(cur, sw == nu - 1);
             double bytes = (L.ndia ? (double)L.ndia * n * es : (double)L.A.nnz * (es + 4) + 4.0 * (n + 1)) +
                            4.0 * es * n;
             const bool timed = l == 0;
@@ -426,7 +457,7 @@ static T* smooth(tp_amg* h, int l, const T* b, T* xc, bool zero, int nu, hipStre
             first_done = false;
         }
         for (int k = k0; k < p.cheb_degree; ++k) {
-            T* nx = other(cur);
+            T* nx = target(cur, sw == nu - 1 && k == p.cheb_degree - 1);
             int first = (k == 0);
             double c1 = 0.0, c2 = 0.0;
             if (!first) {
@@ -454,7 +485,7 @@ static T* smooth(tp_amg* h, int l, const T* b, T* xc, bool zero, int nu, hipStre
 }
 
 template <typename T>
-static T* vcycle_level(tp_amg* h, int l, const T* b, hipStream_t s) {
+static T* vcycle_level(tp_amg* h, int l, const T* b, hipStream_t s, T* final_out = nullptr) {
     Level& L = h->lev[l];
     const int32_t n = L.A.n;
     const int last = (int)h->lev.size() - 1;
@@ -467,6 +498,9 @@ static T* vcycle_level(tp_amg* h, int l, const T* b, hipStream_t s) {
     T* cur = x;
     if (p.nu_pre > 0) cur = smooth<T>(h, l, b, cur, true, p.nu_pre, s);
     else TP_LAUNCH(k_zero<T>, cdiv(n, VB), VB, 0, s, n, cur);
+    // (residual and restriction stay two row-parallel passes: forming the
+    // residual entries inside the restriction recomputes each fine row for
+    // every coarse row that holds it and serialises its gathers)
     T* r = (T*)L.r.p;
     if (L.ndia) {
         TP_ND_DISPATCH(L.ndia, TP_LAUNCH((k_residual_dia<T, NDD>), cdiv(n, VB), VB, 0, s, n, LevelVals<T>::D(L),
@@ -519,14 +553,14 @@ static T* vcycle_level(tp_amg* h, int l, const T* b, hipStream_t s) {
         cnn_forward_into<T>(a->net, a->g, a->feat.p, nullptr, cur, a->scale.p, a->bad.p, s);
         return cur;
     }
-    if (p.nu_post > 0) cur = smooth<T>(h, l, b, cur, false, p.nu_post, s);
+    if (p.nu_post > 0) cur = smooth<T>(h, l, b, cur, false, p.nu_post, s, false, final_out);
     return cur;
 }
 
-const void* vcycle_run(tp_amg* h, const void* b_ext, hipStream_t s) {
+const void* vcycle_run(tp_amg* h, const void* b_ext, hipStream_t s, void* x_ext) {
     const void* b = b_ext ? b_ext : (const void*)h->lev[0].b.p;
-    if (h->prm.storage == 1) return vcycle_level<float>(h, 0, (const float*)b, s);
-    return vcycle_level<double>(h, 0, (const double*)b, s);
+    if (h->prm.storage == 1) return vcycle_level<float>(h, 0, (const float*)b, s, (float*)x_ext);
+    return vcycle_level<double>(h, 0, (const double*)b, s, (double*)x_ext);
 }
 
 template <typename Ti, typename To>
@@ -536,14 +570,15 @@ k_cast(int32_t n, const Ti* __restrict__ a, To* __restrict__ b) {
     if (i < n) b[i] = (To)a[i];
 }
 
-// host helpers used by the preconditioner
+// host helpers used by the preconditioner (kernels only, so the apply can
+// be captured in a graph without copy or fill nodes)
 void cast_d2s(int32_t n, const double* a, void* b, size_t es, hipStream_t s) {
     if (es == 4) TP_LAUNCH((k_cast<double, float>), cdiv(n, VB), VB, 0, s, n, a, (float*)b);
-    else TP_HIP(hipMemcpyAsync(b, a, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    else TP_LAUNCH((k_cast<double, double>), cdiv(n, VB), VB, 0, s, n, a, (double*)b);
 }
 void cast_s2d(int32_t n, const void* a, double* b, size_t es, hipStream_t s) {
     if (es == 4) TP_LAUNCH((k_cast<float, double>), cdiv(n, VB), VB, 0, s, n, (const float*)a, b);
-    else TP_HIP(hipMemcpyAsync(b, a, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    else TP_LAUNCH((k_cast<double, double>), cdiv(n, VB), VB, 0, s, n, (const double*)a, b);
 }
 
 }  // namespace tp

@@ -57,7 +57,7 @@ class _AmgParams(C.Structure):
 
 class _KParams(C.Structure):
     _fields_ = [("rtol", C.c_double), ("restart", C.c_int32), ("maxit", C.c_int32),
-                ("stag_ratio", C.c_double)]
+                ("stag_ratio", C.c_double), ("graph", C.c_int32)]
 
 
 class _KStats(C.Structure):
@@ -445,14 +445,15 @@ class Net:
 
 
 def fgmres_solve(J: Jacobian, M: Precond, b, x=None, rtol=1e-8, restart=30, maxit=1000,
-                 history=False, stag_ratio=0.95, stream=None):
+                 history=False, stag_ratio=0.95, graph=True, stream=None):
     """Solve J x = b; returns (x, stats dict).  x (tensor) is the initial
-    guess when given and is overwritten."""
+    guess when given and is overwritten.  graph: replay the preconditioner
+    apply from a captured HIP graph."""
     torch = _torch()
     lib = load()
     if x is None:
         x = torch.zeros_like(b)
-    kp = _KParams(rtol, restart, maxit, stag_ratio)
+    kp = _KParams(rtol, restart, maxit, stag_ratio, 1 if graph else 0)
     st = _KStats()
     hist = np.zeros(maxit + 1) if history else None
     jc = J.c()

@@ -223,6 +223,49 @@ def test_fgmres_rtol_1e8_and_determinism():
     assert np.array_equal(np_(x1), np_(x2))
 
 
+@pytest.mark.parametrize("variant,storage", [("lower", 0), ("full", 1)])
+def test_graph_replay_matches_eager(variant, storage):
+    """The preconditioner apply replayed from a captured HIP graph gives the
+    same iterates, bit for bit, as launching its kernels one by one: every
+    FGMRES iteration replays the graph once, so equal residual histories
+    check every replay.  Solves alternate between the two modes, with other
+    device work and host synchronisations in between, on two right-hand
+    sides, and on a second stream."""
+    import torch
+    say("graph replay", variant, storage)
+    p = CASES["W2s"]()
+    d = solver.to_device(p)
+    J, G = solver.assemble(p, d)
+    cfg = solver.SolveConfig(rtol=1e-10, variant=variant, storage=storage)
+    a_pp, a_S, M = solver.setup(J, cfg)
+    gen = torch.Generator(device="cpu").manual_seed(7)
+    # second right-hand side: -G with every entry perturbed by up to 50 %, so
+    # it keeps the rows' scale (which spans ten decades)
+    pert = 1.0 + 0.5 * (2.0 * torch.rand(G.shape, generator=gen, dtype=torch.float64) - 1.0)
+    rhs = [-G, -G * pert.to("cuda")]
+    scratch = torch.ones(256, 256, device="cuda", dtype=torch.float64)
+    side = torch.cuda.Stream()
+    for b in rhs:
+        runs = []
+        for graph, stream in ((False, None), (True, None), (True, None), (False, None), (True, side)):
+            scratch = scratch @ scratch.t() / 256.0     # unrelated device work between solves
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            x, st = tps.fgmres_solve(J, M, b, x=x, rtol=1e-10, history=True, graph=graph, stream=stream)
+            if stream is not None:
+                torch.cuda.current_stream().wait_stream(stream)
+            torch.cuda.synchronize()
+            runs.append((np_(x), st))
+        x0, s0 = runs[0]
+        say(f"  its {s0['iters']} rel {s0['rel_true']:.2e}")
+        assert s0["converged"]
+        for x, st in runs[1:]:
+            assert st["iters"] == s0["iters"]
+            assert np.array_equal(st["history"], s0["history"])
+            assert np.array_equal(x, x0)
+    del a_pp, a_S
+
+
 def test_mixed_precision_solve():
     """FP32 hierarchy inside the FP64 outer loop reaches the same true
     residual; its error against a tight reference stays at the FP64 path's."""
