@@ -106,15 +106,18 @@ int assemble_tpfa(const tp_grid* grid, const tp_props* props, const double* K,
  * Algebraic multigrid (Section 3: A_pp and the Schur approximation are each
  * applied by one AMG V-cycle).  Strength theta, seeded PMIS coarsening with
  * key (|S^T_i|, splitmix64(seed ^ level<<40 ^ i), i), direct interpolation,
- * Galerkin or Petrov-Galerkin coarse operators R (A P), smoother, dense LU on
- * the coarsest level.  The setup runs in FP64; `storage` only selects how the
+ * Galerkin or Petrov-Galerkin coarse operators R (A P), smoother, and on the
+ * coarsest level an explicit inverse (blocked Gauss-Jordan elimination with
+ * partial pivoting).  The setup runs in FP64; `storage` only selects how the
  * hierarchy is stored and applied.
  * ------------------------------------------------------------------------ */
 typedef struct {
     double theta;          /* strength threshold, (0,1); 0.25 */
     uint64_t seed;         /* PMIS hash seed */
     int32_t max_levels;    /* 1..25 */
-    int32_t coarse_max;    /* stop when n_l <= coarse_max (<= 4096); 256 */
+    int32_t coarse_max;    /* stop when n_l <= coarse_max (<= 4096); 1200: a dense
+                              coarsest level of ~1000 rows is one GEMV, cheaper
+                              than the several latency-bound levels it replaces */
     int32_t smoother;      /* 0 l1-Jacobi, 1 Chebyshev on D_l1^{-1} A over [cheb_lo, 1] */
     int32_t cheb_degree;   /* 1..8; 3 */
     double cheb_lo;        /* (0,1); 0.3 */
@@ -129,7 +132,7 @@ typedef struct tp_amg* tp_amg_t;
 /* Build the hierarchy of the n x n CSR matrix (device arrays, sorted
  * columns, diagonal present in every row).  Synchronises `stream`.
  * Errors: TP_ERR_ARG (bad sizes/params), TP_ERR_NUMERIC (zero pivot in the
- * coarsest LU, coarsening stalled above 4096 rows), TP_ERR_CAPACITY (a
+ * coarsest-level elimination, coarsening stalled above 4096 rows), TP_ERR_CAPACITY (a
  * product row exceeded the on-chip hash table), TP_ERR_OOM. */
 int amg_setup(int32_t n, const int32_t* rowptr, const int32_t* col, const double* val,
               const tp_amg_params* params, tp_amg_t* out, void* stream);

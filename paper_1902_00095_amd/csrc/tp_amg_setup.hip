@@ -15,12 +15,15 @@
 //   restriction   R = P^T, or R = Q^T with Q the direct interpolation of A^T
 //                 on the same C/F split (Petrov-Galerkin);
 //   coarse op.    A_c = R (A P), each entry summed in ascending inner index;
-//   coarsest      dense LU with partial pivoting, kept as an explicit inverse.
+//   coarsest      explicit inverse by blocked Gauss-Jordan elimination with partial
+//                 pivoting (same pivot rule as an LU: largest modulus, lowest row).
 // PMIS decisions are integer comparisons, so the C/F split is exact on any
 // hardware.  Floating-point steps are written in one fixed operation order
 // and compiled without contraction, so the hierarchy values follow a single
 // rounding sequence.  There are no floating-point atomics.
 #include "tp_amg.h"
+
+#include <cfloat>
 
 #include <algorithm>
 
@@ -439,120 +442,450 @@ k_to_f32(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
     if (i < n) b[i] = (float)a[i];
 }
 
-// ---- coarsest level: dense LU with partial pivoting, then explicit inverse ----------
+// ---- coarsest level: explicit inverse by blocked Gauss-Jordan elimination --------------
+// The inverse is formed with partial (row) pivoting, NB columns at a time.
+// For the panel K = [k, k+NB) with pivot rows B (after interchanges) and the
+// other rows O, one step turns
+//   M_BK -> M_BK^{-1},  M_OK -> -M_OK M_BK^{-1}                  (panel kernel: T)
+//   M_BR -> M_BK^{-1} M_BR,  M_OR -> M_OR - M_OK M_BK^{-1} M_BR  (update kernel)
+// for every other column R; both are T M_BR(old), plus M_OR for the O rows.
+// The update reads the previous matrix X and writes the next one Y, applying
+// the panel's row interchanges as a gather (row i of Y comes from row
+// rowsrc[i] of X), so no step works in place.  After the last panel the
+// interchanges are undone as column interchanges in reverse order.
+__global__ void __launch_bounds__(B)
+k_fill_f64(int64_t n, double* __restrict__ x, double v) {
+    for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) x[i] = v;
+}
+
 __global__ void __launch_bounds__(B)
 k_csr_to_dense(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                const double* __restrict__ val, double* __restrict__ Dm) {
     int32_t i = blockIdx.x * B + threadIdx.x;
     if (i >= n) return;
-    for (int32_t j = 0; j < n; ++j) Dm[(int64_t)i * n + j] = 0.0;
     for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) Dm[(int64_t)i * n + col[q]] = val[q];
 }
 
-constexpr int LU_T = 1024;
 
-// Single workgroup: in-place LU of a (row-major n x n), pivots to piv.  The
-// pivot search (largest |a_ik|, ties -> lowest row) runs in wavefront 0 with
-// cross-lane reductions; three workgroup barriers per elimination step.
-__global__ void __launch_bounds__(LU_T)
-k_dense_lu(int32_t n, double* __restrict__ a, int32_t* __restrict__ piv, int32_t* __restrict__ bad) {
-    __shared__ double s_pv;
-    __shared__ int32_t s_p;
-    const int t = threadIdx.x;
-    for (int32_t k = 0; k < n; ++k) {
-        if (t < 64) {
-            double best = -1.0;
-            int32_t bi = n;
-            for (int32_t i = k + t; i < n; i += 64) {
-                double v = fabs(a[(int64_t)i * n + k]);
-                if (v > best || (v == best && i < bi)) { best = v; bi = i; }
-            }
-            for (int off = 32; off > 0; off >>= 1) {
-                double ov = __shfl_down(best, off, 64);
-                int32_t oi = __shfl_down(bi, off, 64);
-                if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-            }
-            if (t == 0) {
-                s_pv = best;
-                s_p = bi;
-                piv[k] = bi;
-                if (!(best > 0.0)) *bad = 1;
+// One workgroup of GJ_T = 256 threads (one wavefront per SIMD); thread t
+// holds rows t, t + GJ_T, ... of the panel columns in registers (the column
+// loop is unrolled, so every register index is fixed; RPT * NB <= 64 keeps
+// the array in registers).
+// Per column: each wavefront finds its largest |a_ic| among rows not yet used
+// as pivots (ties -> lowest row) and publishes that row; the owner of row
+// k+c publishes it too; one barrier; every thread then knows the pivot row
+// and applies the interchange and the elimination to its rows.
+template <int NB, int RPT, int GJ_T>
+__global__ void __launch_bounds__(GJ_T) __attribute__((amdgpu_waves_per_eu(1, 1)))  // a lone workgroup: registers over occupancy
+k_gj_panel(int32_t n, int32_t k, const double* __restrict__ X, double* __restrict__ T,
+           int32_t* __restrict__ piv, int32_t* __restrict__ rowsrc, int32_t* __restrict__ bad) {
+    constexpr int GJ_W = GJ_T / 64;
+    static_assert(RPT * NB <= 64, "panel rows must stay in registers");
+    __shared__ double s_row[2][GJ_W][NB];
+    __shared__ double s_val[2][GJ_W];
+    __shared__ int32_t s_idx[2][GJ_W];
+    __shared__ double s_kc[2][NB];
+    __shared__ int32_t s_piv[NB];
+    __shared__ int32_t s_pos[2 * NB], s_from[2 * NB];
+    __shared__ int s_m;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int nb = min(NB, n - k);
+    double v[RPT][NB];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int32_t i = t + q * GJ_T;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) v[q][c] = (i < n && c < nb) ? X[(int64_t)i * n + k + c] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+        if (c >= nb) break;
+        const int par = c & 1;
+        const int32_t kc = k + c;
+        double best = -1.0;
+        int32_t bi = n;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int32_t i = t + q * GJ_T;
+            const double x = fabs(v[q][c]);
+            if (i < n && i >= kc && x > best) {
+                best = x;
+                bi = i;
             }
         }
-        __syncthreads();
-        const int32_t p = s_p;
-        const double pv = s_pv;
-        if (!(pv > 0.0)) return;  // uniform across the block
-        if (p != k)
-            for (int32_t j = t; j < n; j += LU_T) {
-                double tmp = a[(int64_t)k * n + j];
-                a[(int64_t)k * n + j] = a[(int64_t)p * n + j];
-                a[(int64_t)p * n + j] = tmp;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ob = __shfl_xor(best, off, 64);
+            const int32_t oi = __shfl_xor(bi, off, 64);
+            if (ob > best || (ob == best && oi < bi)) {
+                best = ob;
+                bi = oi;
             }
-        __syncthreads();
-        const double akk = a[(int64_t)k * n + k];
-        const int32_t m = n - k - 1;
-        // multipliers and trailing update in one pass: row i (one lane
-        // group per row) first scales its pivot-column entry, then updates
-        for (int64_t e = t; e < (int64_t)m * (m + 1); e += LU_T) {
-            int32_t i = k + 1 + (int32_t)(e / (m + 1)), jj = (int32_t)(e % (m + 1));
-            if (jj == 0) continue;
-            int32_t j = k + jj;
-            double l = a[(int64_t)i * n + k] / akk;
-            a[(int64_t)i * n + j] -= l * a[(int64_t)k * n + j];
+        }
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int32_t i = t + q * GJ_T;
+            if (i == bi) {
+#pragma unroll
+                for (int c2 = 0; c2 < NB; ++c2) s_row[par][wave][c2] = v[q][c2];
+            }
+            if (i == kc) {
+#pragma unroll
+                for (int c2 = 0; c2 < NB; ++c2) s_kc[par][c2] = v[q][c2];
+            }
+        }
+        if (lane == 0) {
+            s_val[par][wave] = best;
+            s_idx[par][wave] = bi;
         }
         __syncthreads();
-        for (int32_t i = k + 1 + t; i < n; i += LU_T) a[(int64_t)i * n + k] /= akk;
-        __syncthreads();
+        double pb = -1.0;
+        int32_t p = n;
+        int pw = 0;
+#pragma unroll
+        for (int w = 0; w < GJ_W; ++w) {
+            const double x = s_val[par][w];
+            const int32_t iw = s_idx[par][w];
+            if (x > pb || (x == pb && iw < p)) {
+                pb = x;
+                p = iw;
+                pw = w;
+            }
+        }
+        const bool ok = p < n && pb > 0.0;
+        if (!ok) p = kc;  // singular: keep every index in range, the host sees the flag
+        if (t == 0) {
+            s_piv[c] = p;
+            if (!ok) *bad = 1;
+        }
+        const double* prow = ok ? s_row[par][pw] : s_kc[par];
+        const double d = 1.0 / prow[c];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int32_t i = t + q * GJ_T;
+            if (i == kc) {
+#pragma unroll
+                for (int c2 = 0; c2 < NB; ++c2) v[q][c2] = c2 == c ? d : prow[c2] * d;
+            } else {
+                if (i == p) {
+#pragma unroll
+                    for (int c2 = 0; c2 < NB; ++c2) v[q][c2] = s_kc[par][c2];
+                }
+                const double f = v[q][c];
+#pragma unroll
+                for (int c2 = 0; c2 < NB; ++c2) v[q][c2] = c2 == c ? -(f * d) : v[q][c2] - f * (prow[c2] * d);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int32_t i = t + q * GJ_T;
+        if (i < n)
+#pragma unroll
+            for (int c = 0; c < NB; ++c) T[(int64_t)i * NB + c] = v[q][c];
+    }
+    // the panel's interchanges composed: the rows they touch are pos[0..m)
+    // (the pivot positions k..k+nb first); afterwards row pos[e] holds what
+    // row pos[from[e]] held before
+    __syncthreads();
+    if (t < nb) piv[k + t] = s_piv[t];
+    if (t == 0) {
+        int m = nb;
+        for (int c = 0; c < nb; ++c) s_pos[c] = k + c;
+        for (int c = 0; c < nb; ++c) {
+            const int32_t p = s_piv[c];
+            bool seen = false;
+            for (int e = 0; e < m; ++e) seen = seen || s_pos[e] == p;
+            if (!seen) s_pos[m++] = p;
+        }
+        for (int e = 0; e < m; ++e) s_from[e] = e;
+        for (int c = 0; c < nb; ++c) {
+            int ep = 0;
+            for (int e = 0; e < m; ++e) ep = s_pos[e] == s_piv[c] ? e : ep;
+            const int32_t x = s_from[c];
+            s_from[c] = s_from[ep];
+            s_from[ep] = x;
+        }
+        s_m = m;
+    }
+    __syncthreads();
+    const int m = s_m;
+    for (int32_t i = t; i < n; i += GJ_T) {
+        int32_t src = i;
+        for (int e = 0; e < m; ++e) src = s_pos[e] == i ? s_pos[s_from[e]] : src;
+        rowsrc[i] = src;
     }
 }
 
-// One workgroup per column j of the inverse: x = P e_j, forward with the
-// unit lower factor, backward with the upper factor; x lives in LDS and the
-// row updates of each step run in parallel across the workgroup.
-constexpr int INV_T = 256;
-__global__ void __launch_bounds__(INV_T)
-k_lu_inverse(int32_t n, const double* __restrict__ lu, const int32_t* __restrict__ piv,
-             double* __restrict__ inv) {
-    extern __shared__ double x[];
-    const int32_t j = blockIdx.x;
-    const int t = threadIdx.x;
-    for (int32_t i = t; i < n; i += INV_T) x[i] = (i == j) ? 1.0 : 0.0;
+// Y_ij = T_i,j-k (j in the panel), else [row i not a pivot row] X_rowsrc[i],j
+// + sum_c T_ic X_rowsrc[k+c],j.  64 x 64 tiles, each thread one column and
+// 16 rows, all loads issued before the first store.
+constexpr int GU_T = 256;
+template <int NB>
+__global__ void __launch_bounds__(GU_T)
+k_gj_update(int32_t n, int32_t k, int32_t nb, const double* __restrict__ X, const double* __restrict__ T,
+            const int32_t* __restrict__ rowsrc, double* __restrict__ Y) {
+    __shared__ double s_T[64][NB];
+    __shared__ double s_B[NB][64];
+    __shared__ int32_t s_src[64];
+    const int t = threadIdx.x, tx = t & 63, ty = t >> 6;
+    const int32_t j0 = blockIdx.x * 64, i0 = blockIdx.y * 64;
+    for (int e = t; e < 64 * NB; e += GU_T) {
+        const int r = e / NB, c = e % NB;
+        const int32_t i = i0 + r;
+        s_T[r][c] = (i < n && c < nb) ? T[(int64_t)i * NB + c] : 0.0;
+    }
+    for (int e = t; e < NB * 64; e += GU_T) {
+        const int c = e / 64, x = e % 64;
+        const int32_t j = j0 + x;
+        s_B[c][x] = (j < n && c < nb) ? X[(int64_t)rowsrc[k + c] * n + j] : 0.0;
+    }
+    if (t < 64) s_src[t] = i0 + t < n ? rowsrc[i0 + t] : 0;
     __syncthreads();
-    if (t == 0)
-        for (int32_t k = 0; k < n; ++k)
-            if (piv[k] != k) { double tmp = x[k]; x[k] = x[piv[k]]; x[piv[k]] = tmp; }
+    const int32_t j = j0 + tx;
+    if (j >= n) return;
+    const bool inK = j >= k && j < k + nb;
+    constexpr int RT = 64 / (GU_T / 64);  // rows per thread
+    double acc[RT];
+#pragma unroll
+    for (int q = 0; q < RT; ++q) {
+        const int r = ty + q * (GU_T / 64);
+        const int32_t i = i0 + r;
+        acc[q] = (i < n && !inK && !(i >= k && i < k + nb)) ? X[(int64_t)s_src[r] * n + j] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < RT; ++q) {
+        const int r = ty + q * (GU_T / 64);
+        const int32_t i = i0 + r;
+        if (i >= n) break;
+        if (inK) {
+            Y[(int64_t)i * n + j] = s_T[r][j - k];
+        } else {
+#pragma unroll
+            for (int c = 0; c < NB; ++c) acc[q] += s_T[r][c] * s_B[c][tx];
+            Y[(int64_t)i * n + j] = acc[q];
+        }
+    }
+}
+
+// source column of every column of the inverse: the interchanges replayed on
+// an index vector in reverse order (one thread; piv and src in LDS)
+constexpr int GS_T = 1024;
+__global__ void __launch_bounds__(GS_T)
+k_gj_src(int32_t n, const int32_t* __restrict__ piv, int32_t* __restrict__ src) {
+    __shared__ int32_t s_piv[4096], s_src[4096];
+    for (int32_t i = threadIdx.x; i < n; i += GS_T) {
+        s_piv[i] = piv[i];
+        s_src[i] = i;
+    }
     __syncthreads();
-    for (int32_t k = 0; k < n; ++k) {          // forward: x_i -= L_ik x_k, i > k
-        const double xk = x[k];
-        if (xk != 0.0)
-            for (int32_t i = k + 1 + t; i < n; i += INV_T) x[i] -= lu[(int64_t)i * n + k] * xk;
+    if (threadIdx.x == 0)
+        for (int32_t l = n - 1; l >= 0; --l) {
+            const int32_t p = s_piv[l];
+            const int32_t x = s_src[l];
+            s_src[l] = s_src[p];
+            s_src[p] = x;
+        }
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < n; i += GS_T) src[i] = s_src[i];
+}
+
+__global__ void __launch_bounds__(B)
+k_gj_gather(int32_t n, const double* __restrict__ a, const int32_t* __restrict__ src, double* __restrict__ inv) {
+    const int64_t e = (int64_t)blockIdx.x * B + threadIdx.x;
+    if (e >= (int64_t)n * n) return;
+    const int32_t i = (int32_t)(e / n), j = (int32_t)(e % n);
+    inv[e] = a[(int64_t)i * n + src[j]];
+}
+
+// returns the buffer holding the result
+template <int NB, int RPT, int GJ_T>
+static double* gj_run(int32_t n, double* X, double* Y, double* T, int32_t* rowsrc, int32_t* piv, int32_t* bad,
+                      hipStream_t s) {
+    const dim3 g(cdiv(n, 64), cdiv(n, 64));
+    for (int32_t k = 0; k < n; k += NB) {
+        TP_LAUNCH((k_gj_panel<NB, RPT, GJ_T>), 1, GJ_T, 0, s, n, k, (const double*)X, T, piv, rowsrc, bad);
+        TP_LAUNCH((k_gj_update<NB>), g, GU_T, 0, s, n, k, std::min(NB, n - k), (const double*)X,
+                  (const double*)T, (const int32_t*)rowsrc, Y);
+        std::swap(X, Y);
+    }
+    return X;
+}
+
+// ---- the same elimination without interchanges, verified -------------------------------
+// Partial pivoting leaves the rows in place exactly when, at every column, the
+// diagonal entry is the largest candidate (ties go to the lowest row, i.e. the
+// diagonal).  The coarse operators met here (Galerkin products of the TPFA
+// blocks) satisfy this, so the steps above run with diagonal pivots: the
+// NB x NB pivot block is inverted by one workgroup (recording its LU upper
+// factor), and the update kernel, besides forming the next matrix, re-runs the
+// forward elimination of every candidate row below the block against that
+// factor and flags a column where the row would beat the pivot.  A flag sends
+// the whole inverse through the row-pivoted kernels instead, so the pivot
+// sequence is always the one partial pivoting would choose.
+constexpr int BG_NB = 32;
+constexpr int BG_T = BG_NB * BG_NB;
+
+__global__ void __launch_bounds__(BG_T)
+k_bgj_block(int32_t n, int32_t k, const double* __restrict__ X, double* __restrict__ binv, double* __restrict__ U,
+            int32_t* __restrict__ need_piv) {
+    __shared__ double s_a[BG_NB][BG_NB + 1];
+    const int t = threadIdx.x, r = t / BG_NB, j = t % BG_NB;
+    const int nb = min(BG_NB, n - k);
+    const bool in = r < nb && j < nb;
+    s_a[r][j] = in ? X[(int64_t)(k + r) * n + k + j] : (r == j ? 1.0 : 0.0);
+    __syncthreads();
+    bool flag = false;
+    for (int c = 0; c < nb; ++c) {
+        const double p = s_a[c][c];
+        if (t == 0) flag = flag || !(fabs(p) > 0.0 && fabs(p) <= DBL_MAX);  // zero or non-finite pivot
+        if (in && j == c && r > c) flag = flag || !(fabs(s_a[r][c]) <= fabs(p));
+        if (in && r == c && j >= c) U[c * BG_NB + j] = s_a[c][j];
+        const double m = s_a[r][c], u = s_a[c][j];
+        __syncthreads();
+        const double d = 1.0 / p;
+        if (r == c) s_a[r][j] = j == c ? d : u * d;
+        else s_a[r][j] = j == c ? -(m * d) : s_a[r][j] - m * (u * d);
         __syncthreads();
     }
-    for (int32_t k = n - 1; k >= 0; --k) {     // backward: x_k /= U_kk, x_i -= U_ik x_k, i < k
-        if (t == 0) x[k] = x[k] / lu[(int64_t)k * n + k];
-        __syncthreads();
-        const double xk = x[k];
-        for (int32_t i = t; i < k; i += INV_T) x[i] -= lu[(int64_t)i * n + k] * xk;
-        __syncthreads();
+    if (in) binv[r * BG_NB + j] = s_a[r][j];
+    if (flag) *need_piv = 1;
+}
+
+// Y_ij = W_i,j-k (j in the block), else [i not in the block] X_ij + sum_c W_ic X_k+c,j
+// with W = Binv for the block's rows and W = -X_iK Binv for the others.
+// 64 x 64 tiles, each thread one column and 16 rows.  The first column of
+// tiles also checks the rows below the block (see above).
+constexpr int BU_T = 256;
+__global__ void __launch_bounds__(BU_T)
+k_bgj_update(int32_t n, int32_t k, int32_t nb, const double* __restrict__ X, const double* __restrict__ binv,
+             const double* __restrict__ U, double* __restrict__ Y, int32_t* __restrict__ need_piv) {
+    __shared__ double s_xk[64][BG_NB + 1];
+    __shared__ double s_bi[BG_NB][BG_NB + 1];
+    __shared__ double s_W[64][BG_NB + 1];
+    __shared__ double s_B[BG_NB][64];
+    const int t = threadIdx.x, tx = t & 63, ty = t >> 6;
+    const int32_t j0 = blockIdx.x * 64, i0 = blockIdx.y * 64;
+    for (int e = t; e < 64 * BG_NB; e += BU_T) {
+        const int r = e / BG_NB, c = e % BG_NB;
+        const int32_t i = i0 + r;
+        s_xk[r][c] = (i < n && c < nb) ? X[(int64_t)i * n + k + c] : 0.0;
     }
-    for (int32_t i = t; i < n; i += INV_T) inv[(int64_t)i * n + j] = x[i];
+    for (int e = t; e < BG_NB * BG_NB; e += BU_T) {
+        const int r = e / BG_NB, c = e % BG_NB;
+        s_bi[r][c] = (r < nb && c < nb) ? binv[r * BG_NB + c] : 0.0;
+    }
+    for (int e = t; e < BG_NB * 64; e += BU_T) {
+        const int c = e / 64, x = e % 64;
+        const int32_t j = j0 + x;
+        s_B[c][x] = (j < n && c < nb) ? X[(int64_t)(k + c) * n + j] : 0.0;
+    }
+    __syncthreads();
+    for (int e = t; e < 64 * BG_NB; e += BU_T) {
+        const int r = e / BG_NB, c = e % BG_NB;
+        const int32_t i = i0 + r;
+        double w;
+        if (i >= k && i < k + nb) {
+            w = s_bi[i - k][c];
+        } else {
+            w = 0.0;
+            for (int c2 = 0; c2 < nb; ++c2) w += s_xk[r][c2] * s_bi[c2][c];
+            w = -w;
+        }
+        s_W[r][c] = w;
+    }
+    if (blockIdx.x == 0 && t < 64) {
+        // forward elimination of candidate row i against the block's U
+        const int32_t i = i0 + t;
+        if (i >= k + nb && i < n) {
+            double v[BG_NB];
+#pragma unroll
+            for (int c = 0; c < BG_NB; ++c) v[c] = s_xk[t][c];
+            bool flag = false;
+#pragma unroll
+            for (int c = 0; c < BG_NB; ++c) {
+                if (c < nb) {
+                    const double p = U[c * BG_NB + c];
+                    flag = flag || !(fabs(v[c]) <= fabs(p));
+                    const double f = v[c] / p;
+#pragma unroll
+                    for (int c2 = c + 1; c2 < BG_NB; ++c2) v[c2] -= f * U[c * BG_NB + c2];
+                }
+            }
+            if (flag) *need_piv = 1;
+        }
+    }
+    __syncthreads();
+    const int32_t j = j0 + tx;
+    if (j >= n) return;
+    const bool inK = j >= k && j < k + nb;
+    constexpr int RT = 64 / (BU_T / 64);
+    double acc[RT];
+#pragma unroll
+    for (int q = 0; q < RT; ++q) {
+        const int r = ty + q * (BU_T / 64);
+        const int32_t i = i0 + r;
+        acc[q] = (i < n && !inK && !(i >= k && i < k + nb)) ? X[(int64_t)i * n + j] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < RT; ++q) {
+        const int r = ty + q * (BU_T / 64);
+        const int32_t i = i0 + r;
+        if (i >= n) break;
+        if (inK) {
+            Y[(int64_t)i * n + j] = s_W[r][j - k];
+        } else {
+#pragma unroll 8
+            for (int c = 0; c < BG_NB; ++c) acc[q] += s_W[r][c] * s_B[c][tx];
+            Y[(int64_t)i * n + j] = acc[q];
+        }
+    }
 }
 
 static void build_coarse_inverse(tp_amg* h, const Csr& A, hipStream_t s) {
     const int32_t n = A.n;
     h->nc = n;
     if (n > 4096) fail(TP_ERR_NUMERIC, "coarsening stalled at %d rows (> 4096), no dense factorisation", n);
-    DBuf<double> lu((size_t)n * n, s);
-    DBuf<int32_t> piv(n, s), bad(1, s);
     h->cinv.alloc((size_t)n * n, s);
-    TP_LAUNCH(k_fill_i32, 1, B, 0, s, bad.p, 0, (int64_t)1);
-    if (n > 0) {
-        TP_LAUNCH(k_csr_to_dense, cdiv(n, B), B, 0, s, n, A.rowptr.p, A.col.p, A.val.p, lu.p);
-        TP_LAUNCH(k_dense_lu, 1, LU_T, 0, s, n, lu.p, piv.p, bad.p);
+    if (n == 0) return;
+    DBuf<double> W((size_t)n * n, s), T((size_t)16 * n, s), binv(BG_NB * BG_NB, s), U(BG_NB * BG_NB, s);
+    DBuf<int32_t> piv(n, s), rowsrc(n, s), src(n, s), flags(2, s);
+    const int64_t nn = (int64_t)n * n;
+    const int fill_grid = (int)std::min<int64_t>(cdiv(nn, B), 4096);
+    TP_LAUNCH(k_fill_i32, 1, B, 0, s, flags.p, 0, (int64_t)2);
+    // diagonal pivots: ping-pong so that the last step writes cinv
+    const int steps = cdiv(n, BG_NB);
+    double* X = steps % 2 == 0 ? h->cinv.p : W.p;
+    double* Y = steps % 2 == 0 ? W.p : h->cinv.p;
+    TP_LAUNCH(k_fill_f64, fill_grid, B, 0, s, nn, X, 0.0);
+    TP_LAUNCH(k_csr_to_dense, cdiv(n, B), B, 0, s, n, A.rowptr.p, A.col.p, A.val.p, X);
+    const dim3 g(cdiv(n, 64), cdiv(n, 64));
+    for (int32_t k = 0; k < n; k += BG_NB) {
+        TP_LAUNCH(k_bgj_block, 1, BG_T, 0, s, n, k, (const double*)X, binv.p, U.p, flags.p);
+        TP_LAUNCH(k_bgj_update, g, BU_T, 0, s, n, k, std::min(BG_NB, n - k), (const double*)X,
+                  (const double*)binv.p, (const double*)U.p, Y, flags.p);
+        std::swap(X, Y);
     }
-    if (read_i32(bad.p, s)) fail(TP_ERR_NUMERIC, "zero pivot in the coarsest-level LU (n=%d)", n);
-    if (n > 0) TP_LAUNCH(k_lu_inverse, n, INV_T, sizeof(double) * n, s, n, lu.p, piv.p, h->cinv.p);
+    if (read_i32(flags.p, s) == 0) return;  // no interchange needed: cinv holds the inverse
+    // partial pivoting would interchange rows: the row-pivoted elimination
+    X = W.p;
+    Y = h->cinv.p;
+    TP_LAUNCH(k_fill_f64, fill_grid, B, 0, s, nn, X, 0.0);
+    TP_LAUNCH(k_csr_to_dense, cdiv(n, B), B, 0, s, n, A.rowptr.p, A.col.p, A.val.p, X);
+    int32_t* bad = flags.p + 1;
+    double* res;
+    if (n <= 512) res = gj_run<16, 2, 256>(n, X, Y, T.p, rowsrc.p, piv.p, bad, s);
+    else if (n <= 1024) res = gj_run<16, 4, 256>(n, X, Y, T.p, rowsrc.p, piv.p, bad, s);
+    else if (n <= 1280) res = gj_run<12, 5, 256>(n, X, Y, T.p, rowsrc.p, piv.p, bad, s);
+    else if (n <= 2048) res = gj_run<8, 8, 256>(n, X, Y, T.p, rowsrc.p, piv.p, bad, s);
+    else res = gj_run<4, 16, 256>(n, X, Y, T.p, rowsrc.p, piv.p, bad, s);
+    if (read_i32(bad, s)) fail(TP_ERR_NUMERIC, "zero pivot in the coarsest-level elimination (n=%d)", n);
+    // res is one of W, cinv: gather into the other, then make sure cinv holds it
+    double* out = res == W.p ? h->cinv.p : W.p;
+    TP_LAUNCH(k_gj_src, 1, GS_T, 0, s, n, piv.p, src.p);
+    TP_LAUNCH(k_gj_gather, cdiv(nn, B), B, 0, s, n, (const double*)res, src.p, out);
+    if (out != h->cinv.p)
+        TP_HIP(hipMemcpyAsync(h->cinv.p, out, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
 }
 
 // ---- setup driver ---------------------------------------------------------------------

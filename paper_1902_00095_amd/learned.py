@@ -40,8 +40,13 @@ class Sample:
     amg: object = None   # Schur hierarchy of the field (operator-norm loss)
 
 
-def schur_hierarchy(J, storage=0):
-    return tps.AMG(J.rowptr, J.col, J.S, tps.AmgParams(restriction=1, storage=storage))
+def schur_hierarchy(J, storage=0, coarse_max=None):
+    """The Schur-approximation hierarchy the learned smoother attaches to
+    (coarse_max None: the library default)."""
+    prm = tps.AmgParams(restriction=1, storage=storage)
+    if coarse_max is not None:
+        prm.coarse_max = coarse_max
+    return tps.AMG(J.rowptr, J.col, J.S, prm)
 
 
 def make_pairs(seeds, grid, net=None, per_field=1, workload="W4", smooth_y=0):

@@ -115,7 +115,7 @@ class AmgParams:
     theta: float = 0.25
     seed: int = 12345
     max_levels: int = 25
-    coarse_max: int = 256
+    coarse_max: int = 1200
     smoother: int = 1          # 0 l1-Jacobi, 1 Chebyshev
     cheb_degree: int = 3
     cheb_lo: float = 0.3

@@ -93,7 +93,7 @@ def test_features_match_oracle():
     p = synth.make_problem("W2", grid=synth.Grid(12, 10, 8, 1, 1, 1))
     d = solver.to_device(p)
     J, G = solver.assemble(p, d)
-    a_S = learned.schur_hierarchy(J)
+    a_S = learned.schur_hierarchy(J, coarse_max=64)   # keep the tiny grid multi-level
     net = tps.Net(learned.init_params())
     a_S.attach(net, p.grid)
     r = synth.random_rhs(4, p.grid.n) * 1e3
@@ -111,7 +111,7 @@ def test_pair_invariant():
     p = synth.make_problem("W4", seed=1000, grid=synth.Grid(16, 16, 16, 1, 1, 1))
     d = solver.to_device(p)
     J, G = solver.assemble(p, d)
-    a_S = learned.schur_hierarchy(J)
+    a_S = learned.schur_hierarchy(J, coarse_max=64)   # keep the tiny grid multi-level
     y = torch.randn(p.grid.n, dtype=torch.float64, device="cuda")
     r, e = a_S.presmoothed_pair(y)
     Jo = oracle.jacobian(p)
@@ -151,7 +151,7 @@ def test_operator_loss_gradient_matches_oracle():
     g, th, f = _case(4, (10, 9, 8))
     th = bf16(th)
     net = tps.Net(th)
-    a_S = learned.schur_hierarchy(J)
+    a_S = learned.schur_hierarchy(J, coarse_max=64)   # keep the tiny grid multi-level
     a_S.attach(net, p.grid)
     t = np.random.default_rng(8).standard_normal(g.n).astype(np.float32)
     loss = a_S.op_loss_grad(dev(f.reshape(-1)), dev(t))
