@@ -292,9 +292,10 @@ def main():
         tc = time.perf_counter()
         Jo = oracle.jacobian(prob)
         bo = -oracle.residual(prob)
-        cm = cfg.amg.coarse_max     # the GPU path's hierarchy shape
-        ao_pp = oracle.AMG(Jo.n, Jo.rowptr, Jo.col, Jo.pp, coarse_max=cm)
-        ao_S = oracle.AMG(Jo.n, Jo.rowptr, Jo.col, Jo.S, restriction=1, coarse_max=cm)
+        kw = cfg.amg.oracle_kwargs()   # the GPU path's hierarchy parameters
+        kw.pop("restriction")
+        ao_pp = oracle.AMG(Jo.n, Jo.rowptr, Jo.col, Jo.pp, restriction=0, **kw)
+        ao_S = oracle.AMG(Jo.n, Jo.rowptr, Jo.col, Jo.S, restriction=1, **kw)
         xo, io = oracle.gmres(Jo, ao_pp, ao_S, bo, rtol=args.rtol)
         cpu_ms = (time.perf_counter() - tc) * 1e3
         line["cpu_baseline"] = {"value": round(cpu_ms, 1), "unit": "ms/solve", "cores": 1,

@@ -242,74 +242,6 @@ k_cheb01_dia(int32_t n, const T* __restrict__ dv, DiaOff<ND> off, const T* __res
     xout[i] = x0 + dn;
 }
 
-// Prolongation fused into the first post-smoothing step: every neighbour's
-// corrected value xn_j = x_j + (P x_c)_j is formed on the fly (P row summed in
-// order), then
-//   cheb:   r = D^{-1}(b - A xn); d = r / theta; x_out = xn_i + d
-//   jacobi: x_out = xn_i + w D^{-1}(b - A xn)
-template <typename T>
-__device__ inline T prolonged(const int32_t* __restrict__ prp, const int32_t* __restrict__ pci,
-                              const T* __restrict__ pv, const T* __restrict__ xc, const T* __restrict__ x,
-                              int32_t j) {
-    T s = 0;
-    for (int32_t k = prp[j]; k < prp[j + 1]; ++k) s += pv[k] * xc[pci[k]];
-    return x[j] + s;
-}
-
-template <typename T, int G>
-__global__ void __launch_bounds__(VB)
-k_prolong_smooth(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                 const T* __restrict__ av, const int32_t* __restrict__ prp, const int32_t* __restrict__ pci,
-                 const T* __restrict__ pv, const T* __restrict__ xc, const T* __restrict__ dinv,
-                 const T* __restrict__ b, const T* __restrict__ xin, T* __restrict__ xout, T* __restrict__ d,
-                 int cheb, T theta, T w) {
-    const int64_t tid = (int64_t)blockIdx.x * VB + threadIdx.x;
-    const int32_t i = (int32_t)(tid / G);
-    const int lane = (int)(tid % G);
-    const bool valid = i < n;
-    T s = 0;
-    if (valid)
-        for (int32_t q = rp[i] + lane; q < rp[i + 1]; q += G) s += av[q] * prolonged(prp, pci, pv, xc, xin, ci[q]);
-    s = group_sum<T, G>(s);
-    if (valid && lane == 0) {
-        const T xn = prolonged(prp, pci, pv, xc, xin, i);
-        const T r = dinv[i] * (b[i] - s);
-        if (cheb) {
-            const T dn = r / theta;
-            d[i] = dn;
-            xout[i] = xn + dn;
-        } else {
-            xout[i] = xn + w * r;
-        }
-    }
-}
-
-template <typename T, int ND>
-__global__ void __launch_bounds__(VB)
-k_prolong_smooth_dia(int32_t n, const T* __restrict__ dv, DiaOff<ND> off, const int32_t* __restrict__ prp,
-                     const int32_t* __restrict__ pci, const T* __restrict__ pv, const T* __restrict__ xc,
-                     const T* __restrict__ dinv, const T* __restrict__ b, const T* __restrict__ xin,
-                     T* __restrict__ xout, T* __restrict__ d, int cheb, T theta, T w) {
-    const int32_t i = blockIdx.x * VB + threadIdx.x;
-    if (i >= n) return;
-    T s = 0;
-#pragma unroll
-    for (int q = 0; q < ND; ++q) {
-        int32_t j = i + off.o[q];
-        j = j < 0 ? 0 : (j >= n ? n - 1 : j);
-        s += dv[(int64_t)q * n + i] * prolonged(prp, pci, pv, xc, xin, j);
-    }
-    const T xn = prolonged(prp, pci, pv, xc, xin, i);
-    const T r = dinv[i] * (b[i] - s);
-    if (cheb) {
-        const T dn = r / theta;
-        d[i] = dn;
-        xout[i] = xn + dn;
-    } else {
-        xout[i] = xn + w * r;
-    }
-}
-
 // first sweep from a zero guess
 template <typename T>
 __global__ void __launch_bounds__(VB)
@@ -383,7 +315,7 @@ static inline int grid_rows(int32_t n, int G) { return cdiv((int64_t)std::max(n,
 // land in the caller's vector; the returned pointer says where it is.
 template <typename T>
 static T* smooth(tp_amg* h, int l, const T* b, T* xc, bool zero, int nu, hipStream_t s,
-                 bool first_done = false, T* final_out = nullptr) {
+                 T* final_out = nullptr) {
     Level& L = h->lev[l];
     const tp_amg_params& p = h->prm;
     const int32_t n = L.A.n;
@@ -426,10 +358,6 @@ static T* smooth(tp_amg* h, int l, const T* b, T* xc, bool zero, int nu, hipStre
         }
         if (p.smoother == 0) {
             if (z) continue;
-            if (first_done) {
-                first_done = false;
-                continue;
-            }
             T* nx = target(cur, sw == nu - 1);
             double bytes = (L.ndia ? (double)L.ndia * n * es : (double)L.A.nnz * (es + 4) + 4.0 * (n + 1)) +
                            4.0 * es * n;
@@ -451,10 +379,6 @@ static T* smooth(tp_amg* h, int l, const T* b, T* xc, bool zero, int nu, hipStre
         if (fused01) {  // steps 0 and 1 done by k_cheb01
             k0 = 2;
             rho0 = 1.0 / (2.0 * sigma - rho0);
-        }
-        if (first_done) {  // step 0 done by the fused prolongation kernel
-            k0 = 1;
-            first_done = false;
         }
         for (int k = k0; k < p.cheb_degree; ++k) {
             T* nx = target(cur, sw == nu - 1 && k == p.cheb_degree - 1);
@@ -514,30 +438,11 @@ static T* vcycle_level(tp_amg* h, int l, const T* b, hipStream_t s, T* final_out
     TP_G_DISPATCH(L.gR, TP_LAUNCH((k_spmv<T, GG>), grid_rows(L.R.n, GG), VB, 0, s, L.R.n, L.R.rowptr.p,
                                   L.R.col.p, LevelVals<T>::R(L), r, bc, 0));
     T* xc = vcycle_level<T>(h, l + 1, bc, s);
-    const bool learned = l == 0 && h->cnn && h->cnn->enabled;
     // (prolongation stays a separate row-parallel pass: fusing it into the
     // first post-smoothing step recomputes P x_c for every neighbour and
     // turns the step latency-bound)
-    if (true || (l == 0 && h->stop_before_post) || learned || p.nu_post == 0) {
-        TP_G_DISPATCH(L.gP, TP_LAUNCH((k_spmv<T, GG>), grid_rows(n, GG), VB, 0, s, n, L.P.rowptr.p, L.P.col.p,
-                                      LevelVals<T>::P(L), xc, cur, 1));
-    } else {
-        // prolongation fused into the first post-smoothing step
-        T* nx = cur == (T*)L.x.p ? (T*)L.x2.p : (T*)L.x.p;
-        const double lo = p.cheb_lo, theta = 0.5 * (1.0 + lo);
-        if (L.ndia) {
-            TP_ND_DISPATCH(L.ndia, TP_LAUNCH((k_prolong_smooth_dia<T, NDD>), cdiv(n, VB), VB, 0, s, n,
-                                             LevelVals<T>::D(L), dia_offsets<NDD>(L), L.P.rowptr.p, L.P.col.p,
-                                             LevelVals<T>::P(L), xc, LevelVals<T>::dinv(L), b, cur, nx,
-                                             (T*)L.d.p, p.smoother == 1, (T)theta, (T)p.omega));
-        } else {
-            TP_G_DISPATCH(L.gA, TP_LAUNCH((k_prolong_smooth<T, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p,
-                                          L.A.col.p, LevelVals<T>::A(L), L.P.rowptr.p, L.P.col.p,
-                                          LevelVals<T>::P(L), xc, LevelVals<T>::dinv(L), b, cur, nx, (T*)L.d.p,
-                                          p.smoother == 1, (T)theta, (T)p.omega));
-        }
-        return smooth<T>(h, l, b, nx, false, p.nu_post, s, true);
-    }
+    TP_G_DISPATCH(L.gP, TP_LAUNCH((k_spmv<T, GG>), grid_rows(n, GG), VB, 0, s, n, L.P.rowptr.p, L.P.col.p,
+                                  LevelVals<T>::P(L), xc, cur, 1));
     if (l == 0 && h->stop_before_post) return cur;
     if (l == 0 && h->cnn && h->cnn->enabled) {
         // learned post-smoother: r = b - A x; x += s * CNN(features(r))
@@ -553,7 +458,7 @@ static T* vcycle_level(tp_amg* h, int l, const T* b, hipStream_t s, T* final_out
         cnn_forward_into<T>(a->net, a->g, a->feat.p, nullptr, cur, a->scale.p, a->bad.p, s);
         return cur;
     }
-    if (p.nu_post > 0) cur = smooth<T>(h, l, b, cur, false, p.nu_post, s, false, final_out);
+    if (p.nu_post > 0) cur = smooth<T>(h, l, b, cur, false, p.nu_post, s, final_out);
     return cur;
 }
 

@@ -117,13 +117,21 @@ class AmgParams:
     max_levels: int = 25
     coarse_max: int = 1200
     smoother: int = 1          # 0 l1-Jacobi, 1 Chebyshev
-    cheb_degree: int = 3
-    cheb_lo: float = 0.3
+    cheb_degree: int = 8
+    cheb_lo: float = 0.05
     omega: float = 1.0
     nu_pre: int = 1
     nu_post: int = 1
     restriction: int = 0       # 0 Galerkin, 1 Petrov-Galerkin (Schur operator)
     storage: int = 0           # 0 FP64, 1 FP32
+
+    def oracle_kwargs(self):
+        """The same parameters as keyword arguments of the CPU oracle's AMG
+        (for tests and the CPU baseline, which must build the same hierarchy)."""
+        return dict(theta=self.theta, seed=self.seed, max_levels=self.max_levels,
+                    coarse_max=self.coarse_max, omega=self.omega, nu_pre=self.nu_pre,
+                    nu_post=self.nu_post, smoother=self.smoother, cheb_degree=self.cheb_degree,
+                    cheb_lo=self.cheb_lo, restriction=self.restriction)
 
     def c(self):
         return _AmgParams(self.theta, self.seed, self.max_levels, self.coarse_max, self.smoother,

@@ -49,6 +49,11 @@ CM = tps.AmgParams().coarse_max
 SMALL = 64
 
 
+def o_amg(n, rowptr, col, val, prm):
+    """The oracle hierarchy built with exactly the GPU's parameters."""
+    return oracle.AMG(n, rowptr, col, val, **prm.oracle_kwargs())
+
+
 def relmax(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
@@ -92,8 +97,9 @@ def test_amg_setup_bit_exact_on_identical_input(case, which, restr):
     p = CASES[case]()
     Jo, Jd = _oracle_J_on_device(p)
     val = getattr(Jo, which)
-    ho = oracle.AMG(Jo.n, Jo.rowptr, Jo.col, val, restriction=restr, coarse_max=SMALL)
-    hg = tps.AMG(Jd.rowptr, Jd.col, getattr(Jd, which), tps.AmgParams(restriction=restr, coarse_max=SMALL))
+    prm = tps.AmgParams(restriction=restr, coarse_max=SMALL)
+    ho = o_amg(Jo.n, Jo.rowptr, Jo.col, val, prm)
+    hg = tps.AMG(Jd.rowptr, Jd.col, getattr(Jd, which), prm)
     assert hg.nlev == ho.nlev
     for l in range(ho.nlev):
         Lo, Lg = ho.level(l), hg.level(l)
@@ -138,10 +144,9 @@ def test_vcycle_matches_oracle(case, smoother, cm):
     Jo, Jd = _oracle_J_on_device(p)
     b = synth.random_rhs(7, Jo.n)
     for which, restr in (("pp", 0), ("S", 1)):
-        ho = oracle.AMG(Jo.n, Jo.rowptr, Jo.col, getattr(Jo, which), restriction=restr,
-                        smoother=smoother, coarse_max=cm)
-        hg = tps.AMG(Jd.rowptr, Jd.col, getattr(Jd, which),
-                     tps.AmgParams(restriction=restr, smoother=smoother, coarse_max=cm))
+        prm = tps.AmgParams(restriction=restr, smoother=smoother, coarse_max=cm)
+        ho = o_amg(Jo.n, Jo.rowptr, Jo.col, getattr(Jo, which), prm)
+        hg = tps.AMG(Jd.rowptr, Jd.col, getattr(Jd, which), prm)
         assert hg.nlev == ho.nlev
         xo = ho.vcycle(b)
         xg = np_(hg.vcycle(dev(b)))
@@ -155,9 +160,9 @@ def test_vcycle_fp32_storage_error():
     Jo, Jd = _oracle_J_on_device(p)
     b = synth.random_rhs(9, Jo.n)
     for which, restr in (("pp", 0), ("S", 1)):
-        ho = oracle.AMG(Jo.n, Jo.rowptr, Jo.col, getattr(Jo, which), restriction=restr, coarse_max=SMALL)
-        hg = tps.AMG(Jd.rowptr, Jd.col, getattr(Jd, which),
-                     tps.AmgParams(restriction=restr, storage=1, coarse_max=SMALL))
+        prm = tps.AmgParams(restriction=restr, storage=1, coarse_max=SMALL)
+        ho = o_amg(Jo.n, Jo.rowptr, Jo.col, getattr(Jo, which), prm)
+        hg = tps.AMG(Jd.rowptr, Jd.col, getattr(Jd, which), prm)
         err = relmax(np_(hg.vcycle(dev(b))), ho.vcycle(b))
         say(f"  fp32 V-cycle {which}: rel err {err:.2e}")
         assert err <= 1e-3
@@ -190,10 +195,11 @@ def test_precond_matches_oracle(variant):
     say("precond", variant)
     p = CASES["W2s"]()
     Jo, Jd = _oracle_J_on_device(p)
-    ao_pp = oracle.AMG(Jo.n, Jo.rowptr, Jo.col, Jo.pp, coarse_max=CM)
-    ao_S = oracle.AMG(Jo.n, Jo.rowptr, Jo.col, Jo.S, restriction=1, coarse_max=CM)
-    ag_pp = tps.AMG(Jd.rowptr, Jd.col, Jd.pp, tps.AmgParams(restriction=0))
-    ag_S = tps.AMG(Jd.rowptr, Jd.col, Jd.S, tps.AmgParams(restriction=1))
+    p_pp, p_S = tps.AmgParams(restriction=0), tps.AmgParams(restriction=1)
+    ao_pp = o_amg(Jo.n, Jo.rowptr, Jo.col, Jo.pp, p_pp)
+    ao_S = o_amg(Jo.n, Jo.rowptr, Jo.col, Jo.S, p_S)
+    ag_pp = tps.AMG(Jd.rowptr, Jd.col, Jd.pp, p_pp)
+    ag_S = tps.AMG(Jd.rowptr, Jd.col, Jd.S, p_S)
     M = tps.Precond(Jd, ag_pp, ag_S, variant)
     r = synth.random_rhs(3, 2 * Jo.n)
     r[1::2] *= 1e5
@@ -220,8 +226,8 @@ def test_fgmres_end_to_end(case):
     dx, st, _ = solver.solve(J, G, solver.SolveConfig(rtol=rtol), history=True)
     Jo = oracle.jacobian(p)
     bo = -oracle.residual(p)
-    ao_pp = oracle.AMG(Jo.n, Jo.rowptr, Jo.col, Jo.pp, coarse_max=CM)
-    ao_S = oracle.AMG(Jo.n, Jo.rowptr, Jo.col, Jo.S, restriction=1, coarse_max=CM)
+    ao_pp = o_amg(Jo.n, Jo.rowptr, Jo.col, Jo.pp, tps.AmgParams(restriction=0))
+    ao_S = o_amg(Jo.n, Jo.rowptr, Jo.col, Jo.S, tps.AmgParams(restriction=1))
     xo, io = oracle.gmres(Jo, ao_pp, ao_S, bo, rtol=rtol)
     xt, it = oracle.gmres(Jo, ao_pp, ao_S, bo, rtol=1e-14, maxit=3000)
     say(f"  gpu its {st['iters']} rel {st['rel_true']:.2e}; oracle its {io['iters']}")
