@@ -119,13 +119,14 @@ typedef struct {
                               coarsest level of ~1000 rows is one GEMV, cheaper
                               than the several latency-bound levels it replaces */
     int32_t smoother;      /* 0 l1-Jacobi, 1 Chebyshev on D_l1^{-1} A over [cheb_lo, 1] */
-    int32_t cheb_degree;   /* 1..8; 8 */
-    double cheb_lo;        /* (0,1); 0.05 (degree and interval chosen by measured
+    int32_t cheb_degree;   /* 1..16; 10 (on the finest level) */
+    double cheb_lo;        /* (0,1); 0.03 (degrees and interval chosen by measured
                               time-to-solution on the layered and channelised fields) */
     double omega;          /* l1-Jacobi weight; 1.0 */
     int32_t nu_pre, nu_post; /* sweeps; 1, 1 */
     int32_t restriction;   /* 0 R = P^T; 1 R = Q^T, Q direct interpolation of A^T */
     int32_t storage;       /* 0 FP64; 1 FP32 (values and V-cycle vectors) */
+    int32_t cheb_degree_coarse; /* Chebyshev degree on levels >= 1, 0..16 (0: cheb_degree); 1 */
 } tp_amg_params;
 
 typedef struct tp_amg* tp_amg_t;

@@ -471,7 +471,9 @@ static void smooth(const or_amg* h, int32_t l, const double* b, double* x, int x
             for (int32_t i = 0; i < n; ++i) r[i] = dinv[i] * (b[i] - r[i]);
         }
         for (int32_t i = 0; i < n; ++i) { d[i] = r[i] / theta; x[i] = (zero ? 0.0 : x[i]) + d[i]; }
-        for (int32_t k = 1; k < h->prm.cheb_degree; ++k) {
+        const int32_t deg = (l > 0 && h->prm.cheb_degree_coarse > 0) ? h->prm.cheb_degree_coarse
+                                                                      : h->prm.cheb_degree;
+        for (int32_t k = 1; k < deg; ++k) {
             double rho1 = 1.0 / (2.0 * sigma - rho0);
             double c1 = rho1 * rho0, c2 = 2.0 * rho1 / delta;
             or_spmv(n, A->rowptr, A->col, A->val, x, r);

@@ -61,6 +61,7 @@ typedef struct {
     int32_t cheb_degree; /* polynomial degree per smoothing sweep (3) */
     double cheb_lo;      /* interval [cheb_lo, 1] of D_l1^{-1} A (0.3) */
     int32_t restriction; /* 0 Galerkin R = P^T; 1 Petrov-Galerkin R = P(A^T)^T */
+    int32_t cheb_degree_coarse; /* degree on levels >= 1 (0: cheb_degree) */
 } or_amg_params;
 
 typedef struct or_amg or_amg;

@@ -1114,8 +1114,10 @@ int amg_setup(int32_t n, const int32_t* rowptr, const int32_t* col, const double
         TP_CHECK_ARG(p.max_levels >= 1 && p.max_levels <= 25, "amg_setup: max_levels must be in [1,25]");
         TP_CHECK_ARG(p.coarse_max >= 0 && p.coarse_max <= 4096, "amg_setup: coarse_max must be in [0,4096]");
         TP_CHECK_ARG(p.smoother == 0 || p.smoother == 1, "amg_setup: smoother must be 0 or 1");
-        TP_CHECK_ARG(p.smoother == 0 || (p.cheb_degree >= 1 && p.cheb_degree <= 8),
-                     "amg_setup: cheb_degree must be in [1,8]");
+        TP_CHECK_ARG(p.smoother == 0 || (p.cheb_degree >= 1 && p.cheb_degree <= 16),
+                     "amg_setup: cheb_degree must be in [1,16]");
+        TP_CHECK_ARG(p.cheb_degree_coarse >= 0 && p.cheb_degree_coarse <= 16,
+                     "amg_setup: cheb_degree_coarse must be in [0,16]");
         TP_CHECK_ARG(p.smoother == 0 || (p.cheb_lo > 0.0 && p.cheb_lo < 1.0), "amg_setup: cheb_lo in (0,1)");
         TP_CHECK_ARG(p.nu_pre >= 0 && p.nu_pre <= 8 && p.nu_post >= 0 && p.nu_post <= 8,
                      "amg_setup: sweeps must be in [0,8]");

@@ -66,8 +66,12 @@ int current_device();
 // arena and its individual free is a no-op; the arena returns its chunks
 // when it is destroyed.  Used for AMG setups (no frees during setup, a few
 // frees at teardown).
+struct ArenaChunk {
+    void* p;
+    size_t bytes;
+};
 struct Arena {
-    std::vector<void*> chunks;
+    std::vector<ArenaChunk> chunks;
     char* cur = nullptr;
     size_t left = 0;
     hipStream_t s = nullptr;
@@ -75,6 +79,7 @@ struct Arena {
     ~Arena();
 };
 bool arena_active();
+void release_chunk_cache();  // frees every cached arena chunk
 struct ArenaScope {
     Arena* prev;
     explicit ArenaScope(Arena* a);

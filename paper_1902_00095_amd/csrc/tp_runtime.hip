@@ -2,6 +2,7 @@
 #include "tp_internal.h"
 
 #include <cstring>
+#include <mutex>
 
 namespace tp {
 
@@ -37,19 +38,70 @@ ArenaScope::~ArenaScope() { g_arena = prev; }
 
 static void* raw_alloc(size_t bytes, hipStream_t s);
 
+// Released arena chunks are kept for the next hierarchy (up to CACHE_MAX
+// bytes): one hierarchy per operator is built and dropped every Newton step,
+// and returning its chunks to the device allocator is slow for the large ones.
+// A chunk enters the cache only after the arena's stream has drained.
+constexpr size_t CACHE_MAX = size_t(4) << 30;
+static std::mutex g_cache_mu;
+static std::vector<ArenaChunk> g_cache;
+static size_t g_cache_bytes = 0;
+
+// a cached chunk of at least `bytes` and at most twice that, else a new one
+static ArenaChunk chunk_get(size_t bytes, hipStream_t s) {
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        int best = -1;
+        for (int i = 0; i < (int)g_cache.size(); ++i) {
+            const size_t b = g_cache[i].bytes;
+            if (b >= bytes && b <= 2 * bytes && (best < 0 || b < g_cache[best].bytes)) best = i;
+        }
+        if (best >= 0) {
+            const ArenaChunk c = g_cache[best];
+            g_cache.erase(g_cache.begin() + best);
+            g_cache_bytes -= c.bytes;
+            return c;
+        }
+    }
+    return ArenaChunk{raw_alloc(bytes, s), bytes};
+}
+
+static void chunk_put(const ArenaChunk& c, hipStream_t s) {
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        if (g_cache_bytes + c.bytes <= CACHE_MAX) {
+            g_cache.push_back(c);
+            g_cache_bytes += c.bytes;
+            return;
+        }
+    }
+    dfree(c.p, s);
+}
+
+void release_chunk_cache() {
+    std::vector<ArenaChunk> all;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        all.swap(g_cache);
+        g_cache_bytes = 0;
+    }
+    for (const ArenaChunk& c : all) dfree(c.p, nullptr);
+}
+
 static void* arena_alloc(Arena* a, size_t bytes, hipStream_t s) {
     bytes = (bytes + ARENA_ALIGN - 1) / ARENA_ALIGN * ARENA_ALIGN;
     if (bytes > a->left) {
         const size_t sz = bytes > ARENA_CHUNK / 4 ? bytes : ARENA_CHUNK;
-        void* c = raw_alloc(sz, s);
-        a->chunks.push_back(c);
+        const ArenaChunk ch = chunk_get(sz, s);
+        void* c = ch.p;
+        a->chunks.push_back(ch);
         if (a->chunks.size() == 1) a->s = s;
-        if (sz == bytes && bytes > ARENA_CHUNK / 4) {  // dedicated chunk, keep the open one
+        if (bytes > ARENA_CHUNK / 4) {  // dedicated chunk, keep the open one
             a->bytes_used += bytes;
             return c;
         }
         a->cur = static_cast<char*>(c);
-        a->left = sz;
+        a->left = ch.bytes;
     }
     void* p = a->cur;
     a->cur += bytes;
@@ -59,7 +111,9 @@ static void* arena_alloc(Arena* a, size_t bytes, hipStream_t s) {
 }
 
 Arena::~Arena() {
-    for (void* c : chunks) dfree(c, s);
+    if (chunks.empty()) return;
+    (void)hipStreamSynchronize(s);  // the chunks may be handed to another stream next
+    for (const ArenaChunk& c : chunks) chunk_put(c, s);
 }
 
 void* dalloc(size_t bytes, hipStream_t s) {
@@ -226,6 +280,8 @@ int tp_init(const tp_allocator* alloc, int device) {
         int count = 0;
         TP_HIP(hipGetDeviceCount(&count));
         TP_CHECK_ARG(device >= 0 && device < count, "device %d out of range (%d devices)", device, count);
+        // cached arena chunks belong to the previous device and allocator
+        if (tp::g_device >= 0) tp::release_chunk_cache();
         TP_HIP(hipSetDevice(device));
         tp::g_device = device;
         // keep freed blocks in the device's stream-ordered pool instead of

@@ -330,14 +330,15 @@ static T* smooth(tp_amg* h, int l, const T* b, T* xc, bool zero, int nu, hipStre
     const double lo = p.cheb_lo, theta = 0.5 * (1.0 + lo), delta = 0.5 * (1.0 - lo);
     const double sigma = theta / delta;
     const size_t es = sizeof(T);
+    const int deg = (l > 0 && p.cheb_degree_coarse > 0) ? p.cheb_degree_coarse : p.cheb_degree;
     for (int sw = 0; sw < nu; ++sw) {
         bool z = zero && sw == 0;
         bool fused01 = false;
-        if (z && p.smoother == 1 && p.cheb_degree >= 2) {
+        if (z && p.smoother == 1 && deg >= 2) {
             // steps 0 and 1 in one pass
             const double rho1 = 1.0 / (2.0 * sigma - 1.0 / sigma);
             const double c1 = rho1 * (1.0 / sigma), c2 = 2.0 * rho1 / delta;
-            T* nx = target(cur, sw == nu - 1 && p.cheb_degree == 2);
+            T* nx = target(cur, sw == nu - 1 && deg == 2);
             const bool timed = l == 0;
             const double bytes = (L.ndia ? (double)L.ndia * n * es : (double)L.A.nnz * (es + 4) + 4.0 * (n + 1)) +
                                  4.0 * es * n;
@@ -380,8 +381,8 @@ static T* smooth(tp_amg* h, int l, const T* b, T* xc, bool zero, int nu, hipStre
             k0 = 2;
             rho0 = 1.0 / (2.0 * sigma - rho0);
         }
-        for (int k = k0; k < p.cheb_degree; ++k) {
-            T* nx = target(cur, sw == nu - 1 && k == p.cheb_degree - 1);
+        for (int k = k0; k < deg; ++k) {
+            T* nx = target(cur, sw == nu - 1 && k == deg - 1);
             int first = (k == 0);
             double c1 = 0.0, c2 = 0.0;
             if (!first) {

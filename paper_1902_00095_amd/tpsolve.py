@@ -52,7 +52,8 @@ class _AmgParams(C.Structure):
     _fields_ = [("theta", C.c_double), ("seed", C.c_uint64), ("max_levels", C.c_int32),
                 ("coarse_max", C.c_int32), ("smoother", C.c_int32), ("cheb_degree", C.c_int32),
                 ("cheb_lo", C.c_double), ("omega", C.c_double), ("nu_pre", C.c_int32),
-                ("nu_post", C.c_int32), ("restriction", C.c_int32), ("storage", C.c_int32)]
+                ("nu_post", C.c_int32), ("restriction", C.c_int32), ("storage", C.c_int32),
+                ("cheb_degree_coarse", C.c_int32)]
 
 
 class _KParams(C.Structure):
@@ -117,13 +118,14 @@ class AmgParams:
     max_levels: int = 25
     coarse_max: int = 1200
     smoother: int = 1          # 0 l1-Jacobi, 1 Chebyshev
-    cheb_degree: int = 8
-    cheb_lo: float = 0.05
+    cheb_degree: int = 10
+    cheb_lo: float = 0.03
     omega: float = 1.0
     nu_pre: int = 1
     nu_post: int = 1
     restriction: int = 0       # 0 Galerkin, 1 Petrov-Galerkin (Schur operator)
     storage: int = 0           # 0 FP64, 1 FP32
+    cheb_degree_coarse: int = 1  # degree on levels >= 1 (0: cheb_degree)
 
     def oracle_kwargs(self):
         """The same parameters as keyword arguments of the CPU oracle's AMG
@@ -131,12 +133,13 @@ class AmgParams:
         return dict(theta=self.theta, seed=self.seed, max_levels=self.max_levels,
                     coarse_max=self.coarse_max, omega=self.omega, nu_pre=self.nu_pre,
                     nu_post=self.nu_post, smoother=self.smoother, cheb_degree=self.cheb_degree,
-                    cheb_lo=self.cheb_lo, restriction=self.restriction)
+                    cheb_lo=self.cheb_lo, restriction=self.restriction,
+                    cheb_degree_coarse=self.cheb_degree_coarse)
 
     def c(self):
         return _AmgParams(self.theta, self.seed, self.max_levels, self.coarse_max, self.smoother,
                           self.cheb_degree, self.cheb_lo, self.omega, self.nu_pre, self.nu_post,
-                          self.restriction, self.storage)
+                          self.restriction, self.storage, self.cheb_degree_coarse)
 
 
 def _torch():
@@ -295,7 +298,7 @@ class AMG:
         per pass): Chebyshev(3) pre/post sweeps with the zero-guess steps
         fused, residual, restriction, prolongation, coarse dense inverse."""
         es = 4 if self.params.storage == 1 else 8
-        deg = self.params.cheb_degree
+        d0, dc = self.params.cheb_degree, self.params.cheb_degree_coarse
         total = 0.0
         L = self.nlev
         for l in range(L):
@@ -303,12 +306,16 @@ class AMG:
             if l == L - 1:
                 total += n * n * 8 + 2 * n * es
                 continue
+            deg = dc if (l > 0 and dc > 0) else d0
             nc = self.level_sizes(l + 1)[0]
             nd, _ = self.level_format(l)
             mA = nd * n * es if nd else nnzA * (es + 4) + (n + 1) * 4
             mP = nnzP * (es + 4) + (n + 1) * 4
             mR = nnzR * (es + 4) + (nc + 1) * 4
-            pre = (mA + 4 * n * es) + (deg - 2) * (mA + 6 * n * es)
+            if deg >= 2:   # steps 0 and 1 fused, then deg - 2 steps
+                pre = (mA + 4 * n * es) + (deg - 2) * (mA + 6 * n * es)
+            else:          # the zero-guess step alone reads no matrix
+                pre = 4 * n * es
             post = (mA + 5 * n * es) + (deg - 1) * (mA + 6 * n * es)
             total += pre + (mA + 3 * n * es) + (mR + (n + nc) * es) + (mP + (2 * n + nc) * es) + post
         return total
