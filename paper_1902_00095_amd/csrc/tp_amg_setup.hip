@@ -81,9 +81,11 @@ k_fill_i32(int32_t* __restrict__ a, int32_t v, int64_t n) {
 }
 
 __global__ void __launch_bounds__(B)
-k_col_count(int64_t nnz, const int32_t* __restrict__ col, int32_t* __restrict__ cnt) {
-    int64_t k = (int64_t)blockIdx.x * B + threadIdx.x;
-    if (k < nnz) atomicAdd(&cnt[col[k]], 1);
+k_col_count(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+            int32_t* __restrict__ cnt) {
+    int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n) return;
+    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) atomicAdd(&cnt[col[q]], 1);
 }
 
 __global__ void __launch_bounds__(B)
@@ -117,7 +119,9 @@ k_sort_rows(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __rest
     }
 }
 
-// T = A^T (m rows); values optional; rows sorted when `sorted`
+// T = A^T (m rows); values optional; rows sorted when `sorted`.  nnz is the
+// entry count or an upper bound of it: it only sizes the allocations (the
+// counts come from rowptr), and T.nnz keeps the value passed.
 void transpose(const int32_t* rowptr, const int32_t* col, const double* val, int32_t n,
                       int32_t m, int32_t nnz, bool sorted, Csr& T, hipStream_t s) {
     T.n = m;
@@ -128,7 +132,7 @@ void transpose(const int32_t* rowptr, const int32_t* col, const double* val, int
     if (val) T.val.alloc(nnz, s);
     DBuf<int32_t> cursor(m + 1, s);
     TP_LAUNCH(k_fill_i32, cdiv(m + 1, B), B, 0, s, T.rowptr.p, 0, (int64_t)m + 1);
-    if (nnz > 0) TP_LAUNCH(k_col_count, cdiv(nnz, B), B, 0, s, (int64_t)nnz, col, T.rowptr.p);
+    if (n > 0) TP_LAUNCH(k_col_count, cdiv(n, B), B, 0, s, n, rowptr, col, T.rowptr.p);
     scan_exclusive(T.rowptr.p, T.rowptr.p, m, s);
     TP_HIP(hipMemcpyAsync(cursor.p, T.rowptr.p, sizeof(int32_t) * (m + 1), hipMemcpyDeviceToDevice, s));
     if (!sorted) {
@@ -319,13 +323,18 @@ __device__ inline void sg_insert_row(const int32_t* Arp, const int32_t* Ac, cons
     }
 }
 
+// The two kernels below take the rows listed in rows[0 .. *nrows) (the rows
+// the short-row path handed over).
 __global__ void __launch_bounds__(SG_WAVE)
-k_spgemm_count(int32_t n, const int32_t* __restrict__ Arp, const int32_t* __restrict__ Ac,
+k_spgemm_count(const int32_t* __restrict__ rows, const int32_t* __restrict__ nrows,
+               const int32_t* __restrict__ Arp, const int32_t* __restrict__ Ac,
                const int32_t* __restrict__ Brp, const int32_t* __restrict__ Bc,
                int32_t* __restrict__ cnt, int32_t* __restrict__ gflag) {
     __shared__ int32_t tab[HASH];
     __shared__ int32_t count, overflow, bound;
-    for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const int32_t nr = *nrows;
+    for (int32_t idx = blockIdx.x; idx < nr; idx += gridDim.x) {
+        const int32_t i = rows[idx];
         const int lg = row_table_log(Arp, Ac, Brp, i, &bound);
         for (int h = threadIdx.x; h < (1 << lg); h += SG_WAVE) tab[h] = -1;
         if (threadIdx.x == 0) { count = 0; overflow = 0; }
@@ -341,7 +350,8 @@ k_spgemm_count(int32_t n, const int32_t* __restrict__ Arp, const int32_t* __rest
 }
 
 __global__ void __launch_bounds__(SG_WAVE)
-k_spgemm_fill(int32_t n, const int32_t* __restrict__ Arp, const int32_t* __restrict__ Ac,
+k_spgemm_fill(const int32_t* __restrict__ rows, const int32_t* __restrict__ nrows,
+              const int32_t* __restrict__ Arp, const int32_t* __restrict__ Ac,
               const double* __restrict__ Av, const int32_t* __restrict__ Brp,
               const int32_t* __restrict__ Bc, const double* __restrict__ Bv,
               const int32_t* __restrict__ Crp, int32_t* __restrict__ Cc, double* __restrict__ Cv,
@@ -349,7 +359,9 @@ k_spgemm_fill(int32_t n, const int32_t* __restrict__ Arp, const int32_t* __restr
     __shared__ int32_t tab[HASH];
     __shared__ int32_t list[HASH];
     __shared__ int32_t count, overflow, ncomp, bound;
-    for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const int32_t nr = *nrows;
+    for (int32_t idx = blockIdx.x; idx < nr; idx += gridDim.x) {
+        const int32_t i = rows[idx];
         const int lg = row_table_log(Arp, Ac, Brp, i, &bound);
         for (int h = threadIdx.x; h < (1 << lg); h += SG_WAVE) tab[h] = -1;
         if (threadIdx.x == 0) { count = 0; overflow = 0; ncomp = 0; }
@@ -357,6 +369,12 @@ k_spgemm_fill(int32_t n, const int32_t* __restrict__ Arp, const int32_t* __restr
         sg_insert_row(Arp, Ac, Brp, Bc, i, tab, lg, &count, &overflow);
         __syncthreads();
         if (overflow) {
+            // keep the row's slots valid (column 0, value 0) for the kernels
+            // that follow; the flag fails the setup at its end
+            for (int32_t q = Crp[i] + threadIdx.x; q < Crp[i + 1]; q += SG_WAVE) {
+                Cc[q] = 0;
+                Cv[q] = 0.0;
+            }
             if (threadIdx.x == 0) *gflag = 1;
             __syncthreads();
             continue;
@@ -370,6 +388,10 @@ k_spgemm_fill(int32_t n, const int32_t* __restrict__ Arp, const int32_t* __restr
         const int32_t u = ncomp;
         const int32_t base = Crp[i];
         if (u != Crp[i + 1] - base) {  // must equal the symbolic count
+            for (int32_t q = base + threadIdx.x; q < Crp[i + 1]; q += SG_WAVE) {
+                Cc[q] = 0;
+                Cv[q] = 0.0;
+            }
             if (threadIdx.x == 0) *gflag = 2;
             __syncthreads();
             continue;
@@ -402,27 +424,137 @@ k_spgemm_fill(int32_t n, const int32_t* __restrict__ Arp, const int32_t* __restr
     }
 }
 
-static void spgemm(const Csr& A, const Csr& Bm, Csr& C, hipStream_t s) {
+// ---- short rows: 16 lanes per output row -------------------------------------------------
+// A row with at most SR_G entries whose products number at most SR_MAX is
+// expanded into LDS in A-entry-major order (inner index ascending, and within
+// it B's sorted columns).  A column's output position is the number of
+// distinct smaller columns; its value is the sum of its products in that
+// order, i.e. in ascending inner index, the order of the hash-table path.
+// Other rows are appended to a list for the hash-table kernels.
+constexpr int SR_G = 16;
+constexpr int SR_MAX = 128;
+constexpr int SR_T = 256;
+constexpr int SR_ROWS = SR_T / SR_G;
+
+__global__ void __launch_bounds__(SR_T)
+k_spgemm_short(int32_t n, const int32_t* __restrict__ Arp, const int32_t* __restrict__ Ac,
+               const double* __restrict__ Av, const int32_t* __restrict__ Brp, const int32_t* __restrict__ Bc,
+               const double* __restrict__ Bv, int32_t* __restrict__ cnt, const int32_t* __restrict__ Crp,
+               int32_t* __restrict__ Cc, double* __restrict__ Cv, int32_t* __restrict__ long_rows,
+               int32_t* __restrict__ nlong, int32_t* __restrict__ gflag, int numeric) {
+    __shared__ int32_t s_c[SR_ROWS][SR_MAX];
+    __shared__ double s_v[SR_ROWS][SR_MAX];
+    __shared__ int8_t s_first[SR_ROWS][SR_MAX];
+    const int g = threadIdx.x / SR_G, lane = threadIdx.x % SR_G;
+    const int32_t i = blockIdx.x * SR_ROWS + g;
+    const bool valid = i < n;
+    const int32_t a0 = valid ? Arp[i] : 0, la = valid ? Arp[i + 1] - a0 : 0;
+    // this lane's inner index and its B row
+    int32_t b0 = 0, lb = 0;
+    double av = 0.0;
+    if (lane < la && la <= SR_G) {
+        const int32_t r = Ac[a0 + lane];
+        b0 = Brp[r];
+        lb = Brp[r + 1] - b0;
+        av = Av[a0 + lane];
+    }
+    // exclusive scan of the B-row lengths across the row's lanes
+    int32_t off = lb;
+#pragma unroll
+    for (int d = 1; d < SR_G; d <<= 1) {
+        const int32_t o = __shfl_up(off, d, SR_G);
+        if (lane >= d) off += o;
+    }
+    const int32_t total = __shfl(off, SR_G - 1, SR_G);
+    off -= lb;
+    const bool is_short = valid && la <= SR_G && total <= SR_MAX;
+    if (valid && !is_short) {
+        if (lane == 0) long_rows[atomicAdd(nlong, 1)] = i;
+        return;  // the whole group leaves together (uniform across its lanes)
+    }
+    if (!valid) return;
+    for (int32_t q = 0; q < lb; ++q) {
+        s_c[g][off + q] = Bc[b0 + q];
+        if (numeric) s_v[g][off + q] = av * Bv[b0 + q];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // first occurrences of every column
+    int32_t nfirst = 0;
+    for (int32_t e = lane; e < total; e += SR_G) {
+        const int32_t c = s_c[g][e];
+        bool first = true;
+        for (int32_t e2 = 0; e2 < e; ++e2) first = first && s_c[g][e2] != c;
+        s_first[g][e] = first ? 1 : 0;
+        nfirst += first ? 1 : 0;
+    }
+#pragma unroll
+    for (int d = SR_G / 2; d > 0; d >>= 1) nfirst += __shfl_xor(nfirst, d, SR_G);
+    if (!numeric) {
+        if (lane == 0) cnt[i] = nfirst;
+        return;
+    }
+    const int32_t base = Crp[i];
+    if (nfirst != Crp[i + 1] - base) {  // must equal the symbolic count
+        for (int32_t q = base + lane; q < Crp[i + 1]; q += SR_G) {
+            Cc[q] = 0;
+            Cv[q] = 0.0;
+        }
+        if (lane == 0) *gflag = 2;
+        return;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int32_t e = lane; e < total; e += SR_G) {
+        if (!s_first[g][e]) continue;
+        const int32_t c = s_c[g][e];
+        int32_t pos = 0;
+        double acc = 0.0;
+        for (int32_t e2 = 0; e2 < total; ++e2) {
+            const int32_t c2 = s_c[g][e2];
+            pos += (s_first[g][e2] && c2 < c) ? 1 : 0;
+            if (c2 == c) acc += s_v[g][e2];
+        }
+        Cc[base + pos] = c;
+        Cv[base + pos] = acc;
+    }
+}
+
+// C = A B; a row whose distinct columns exceed the LDS table sets *flag
+// (checked by the caller once the whole setup is queued)
+static void spgemm(const Csr& A, const Csr& Bm, Csr& C, int32_t* flag, hipStream_t s) {
     C.n = A.n;
     C.m = Bm.m;
     C.rowptr.alloc(A.n + 1, s);
-    DBuf<int32_t> flag(1, s);
-    TP_LAUNCH(k_fill_i32, 1, B, 0, s, flag.p, 0, (int64_t)1);
-    int grid = std::min<int>(std::max<int>(A.n, 1), 65536);
-    if (A.n > 0)
-        TP_LAUNCH(k_spgemm_count, grid, SG_WAVE, 0, s, A.n, A.rowptr.p, A.col.p, Bm.rowptr.p, Bm.col.p,
-                  C.rowptr.p, flag.p);
+    DBuf<int32_t> long_rows(std::max(A.n, 1), s), nlong(1, s);
+    TP_LAUNCH(k_fill_i32, 1, B, 0, s, nlong.p, 0, (int64_t)1);
+    const int grid = std::min<int>(std::max<int>(A.n, 1), 16384);
+    const int sgrid = cdiv(std::max(A.n, 1), SR_ROWS);
+    if (A.n > 0) {
+        TP_LAUNCH(k_spgemm_short, sgrid, SR_T, 0, s, A.n, A.rowptr.p, A.col.p, A.val.p, Bm.rowptr.p, Bm.col.p,
+                  Bm.val.p, C.rowptr.p, (const int32_t*)nullptr, (int32_t*)nullptr, (double*)nullptr,
+                  long_rows.p, nlong.p, flag, 0);
+        TP_LAUNCH(k_spgemm_count, grid, SG_WAVE, 0, s, (const int32_t*)long_rows.p, (const int32_t*)nlong.p,
+                  A.rowptr.p, A.col.p, Bm.rowptr.p, Bm.col.p, C.rowptr.p, flag);
+    }
     scan_exclusive(C.rowptr.p, C.rowptr.p, A.n, s);
     // (an overflowing row is caught by the numeric pass, which only writes
     // rows whose distinct-column count matches the symbolic one)
     C.nnz = read_i32(C.rowptr.p + A.n, s);
     C.col.alloc(C.nnz, s);
     C.val.alloc(C.nnz, s);
-    if (A.n > 0)
-        TP_LAUNCH(k_spgemm_fill, grid, SG_WAVE, 0, s, A.n, A.rowptr.p, A.col.p, A.val.p, Bm.rowptr.p,
-                  Bm.col.p, Bm.val.p, C.rowptr.p, C.col.p, C.val.p, flag.p);
-    const int32_t f = read_i32(flag.p, s);
-    if (f) fail(TP_ERR_CAPACITY, "SpGEMM row exceeded the %d-entry LDS hash table (code %d)", HASH, f);
+    if (A.n > 0) {
+        // the short pass lists the long rows again: start the list afresh
+        TP_LAUNCH(k_fill_i32, 1, B, 0, s, nlong.p, 0, (int64_t)1);
+        TP_LAUNCH(k_spgemm_short, sgrid, SR_T, 0, s, A.n, A.rowptr.p, A.col.p, A.val.p, Bm.rowptr.p, Bm.col.p,
+                  Bm.val.p, (int32_t*)nullptr, (const int32_t*)C.rowptr.p, C.col.p, C.val.p, long_rows.p, nlong.p,
+                  flag, 1);
+        TP_LAUNCH(k_spgemm_fill, grid, SG_WAVE, 0, s, (const int32_t*)long_rows.p, (const int32_t*)nlong.p,
+                  A.rowptr.p, A.col.p, A.val.p, Bm.rowptr.p, Bm.col.p, Bm.val.p, C.rowptr.p, C.col.p, C.val.p,
+                  flag);
+    }
 }
 
 // ---- l1 diagonal, precision copies ----------------------------------------------------
@@ -724,31 +856,53 @@ static double* gj_run(int32_t n, double* X, double* Y, double* T, int32_t* rowsr
 // the whole inverse through the row-pivoted kernels instead, so the pivot
 // sequence is always the one partial pivoting would choose.
 constexpr int BG_NB = 32;
-constexpr int BG_T = BG_NB * BG_NB;
 
-__global__ void __launch_bounds__(BG_T)
+// One workgroup inverts the pivot block in LDS (Gauss-Jordan with diagonal
+// pivots, recording the LU upper factor); thread t owns column t % 32 of rows
+// t / 32 + 8q.  Rows and columns past nb carry the identity and stay
+// untouched.
+constexpr int BK_T = 1024;
+__global__ void __launch_bounds__(BK_T)
 k_bgj_block(int32_t n, int32_t k, const double* __restrict__ X, double* __restrict__ binv, double* __restrict__ U,
             int32_t* __restrict__ need_piv) {
     __shared__ double s_a[BG_NB][BG_NB + 1];
-    const int t = threadIdx.x, r = t / BG_NB, j = t % BG_NB;
+    constexpr int RQ = BG_NB * BG_NB / BK_T;
+    const int t = threadIdx.x, j = t % BG_NB, r0 = t / BG_NB;
     const int nb = min(BG_NB, n - k);
-    const bool in = r < nb && j < nb;
-    s_a[r][j] = in ? X[(int64_t)(k + r) * n + k + j] : (r == j ? 1.0 : 0.0);
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+        const int r = r0 + q * (BK_T / BG_NB);
+        s_a[r][j] = (r < nb && j < nb) ? X[(int64_t)(k + r) * n + k + j] : (r == j ? 1.0 : 0.0);
+    }
     __syncthreads();
     bool flag = false;
     for (int c = 0; c < nb; ++c) {
         const double p = s_a[c][c];
         if (t == 0) flag = flag || !(fabs(p) > 0.0 && fabs(p) <= DBL_MAX);  // zero or non-finite pivot
-        if (in && j == c && r > c) flag = flag || !(fabs(s_a[r][c]) <= fabs(p));
-        if (in && r == c && j >= c) U[c * BG_NB + j] = s_a[c][j];
-        const double m = s_a[r][c], u = s_a[c][j];
+        const double u = s_a[c][j];
+        double m[RQ];
+#pragma unroll
+        for (int q = 0; q < RQ; ++q) {
+            const int r = r0 + q * (BK_T / BG_NB);
+            m[q] = s_a[r][c];
+            if (j == c && r > c && r < nb) flag = flag || !(fabs(m[q]) <= fabs(p));
+            if (r == c && j >= c && j < nb) U[c * BG_NB + j] = u;
+        }
         __syncthreads();
         const double d = 1.0 / p;
-        if (r == c) s_a[r][j] = j == c ? d : u * d;
-        else s_a[r][j] = j == c ? -(m * d) : s_a[r][j] - m * (u * d);
+#pragma unroll
+        for (int q = 0; q < RQ; ++q) {
+            const int r = r0 + q * (BK_T / BG_NB);
+            if (r == c) s_a[r][j] = j == c ? d : u * d;
+            else s_a[r][j] = j == c ? -(m[q] * d) : s_a[r][j] - m[q] * (u * d);
+        }
         __syncthreads();
     }
-    if (in) binv[r * BG_NB + j] = s_a[r][j];
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+        const int r = r0 + q * (BK_T / BG_NB);
+        if (r < nb && j < nb) binv[r * BG_NB + j] = s_a[r][j];
+    }
     if (flag) *need_piv = 1;
 }
 
@@ -764,6 +918,7 @@ k_bgj_update(int32_t n, int32_t k, int32_t nb, const double* __restrict__ X, con
     __shared__ double s_bi[BG_NB][BG_NB + 1];
     __shared__ double s_W[64][BG_NB + 1];
     __shared__ double s_B[BG_NB][64];
+    __shared__ double s_U[BG_NB][BG_NB + 1];
     const int t = threadIdx.x, tx = t & 63, ty = t >> 6;
     const int32_t j0 = blockIdx.x * 64, i0 = blockIdx.y * 64;
     for (int e = t; e < 64 * BG_NB; e += BU_T) {
@@ -780,6 +935,11 @@ k_bgj_update(int32_t n, int32_t k, int32_t nb, const double* __restrict__ X, con
         const int32_t j = j0 + x;
         s_B[c][x] = (j < n && c < nb) ? X[(int64_t)(k + c) * n + j] : 0.0;
     }
+    if (blockIdx.x == 0)
+        for (int e = t; e < BG_NB * BG_NB; e += BU_T) {
+            const int r = e / BG_NB, c = e % BG_NB;
+            s_U[r][c] = (r < nb && c < nb && c >= r) ? U[r * BG_NB + c] : 0.0;
+        }
     __syncthreads();
     for (int e = t; e < 64 * BG_NB; e += BU_T) {
         const int r = e / BG_NB, c = e % BG_NB;
@@ -805,11 +965,11 @@ k_bgj_update(int32_t n, int32_t k, int32_t nb, const double* __restrict__ X, con
 #pragma unroll
             for (int c = 0; c < BG_NB; ++c) {
                 if (c < nb) {
-                    const double p = U[c * BG_NB + c];
+                    const double p = s_U[c][c];
                     flag = flag || !(fabs(v[c]) <= fabs(p));
                     const double f = v[c] / p;
 #pragma unroll
-                    for (int c2 = c + 1; c2 < BG_NB; ++c2) v[c2] -= f * U[c * BG_NB + c2];
+                    for (int c2 = c + 1; c2 < BG_NB; ++c2) v[c2] -= f * s_U[c][c2];
                 }
             }
             if (flag) *need_piv = 1;
@@ -861,7 +1021,7 @@ static void build_coarse_inverse(tp_amg* h, const Csr& A, hipStream_t s) {
     TP_LAUNCH(k_csr_to_dense, cdiv(n, B), B, 0, s, n, A.rowptr.p, A.col.p, A.val.p, X);
     const dim3 g(cdiv(n, 64), cdiv(n, 64));
     for (int32_t k = 0; k < n; k += BG_NB) {
-        TP_LAUNCH(k_bgj_block, 1, BG_T, 0, s, n, k, (const double*)X, binv.p, U.p, flags.p);
+        TP_LAUNCH(k_bgj_block, 1, BK_T, 0, s, n, k, (const double*)X, binv.p, U.p, flags.p);
         TP_LAUNCH(k_bgj_update, g, BU_T, 0, s, n, k, std::min(BG_NB, n - k), (const double*)X,
                   (const double*)binv.p, (const double*)U.p, Y, flags.p);
         std::swap(X, Y);
@@ -910,7 +1070,7 @@ static void strength(const Csr& A, double theta, Csr& S, hipStream_t s) {
         TP_LAUNCH(k_strength, cdiv(A.n, B), B, 0, s, A.n, A.rowptr.p, A.col.p, A.val.p, theta, S.rowptr.p,
                   (const int32_t*)nullptr, (int32_t*)nullptr);
     scan_exclusive(S.rowptr.p, S.rowptr.p, A.n, s);
-    S.nnz = read_i32(S.rowptr.p + A.n, s);
+    S.nnz = A.nnz;  // an upper bound (S is a subset of A's pattern): no host read
     S.col.alloc(S.nnz, s);
     if (A.n > 0)
         TP_LAUNCH(k_strength, cdiv(A.n, B), B, 0, s, A.n, A.rowptr.p, A.col.p, A.val.p, theta,
@@ -924,7 +1084,9 @@ static void direct_interp(const Csr& A, const Csr& S, const int32_t* cf, const i
     P.rowptr.alloc(A.n + 1, s);
     if (A.n > 0) TP_LAUNCH(k_interp_count, cdiv(A.n, B), B, 0, s, A.n, S.rowptr.p, S.col.p, cf, P.rowptr.p);
     scan_exclusive(P.rowptr.p, P.rowptr.p, A.n, s);
-    P.nnz = read_i32(P.rowptr.p + A.n, s);
+    // an upper bound (an F row interpolates from its strong C neighbours, a
+    // C row has one entry); the exact count is read once at the end of setup
+    P.nnz = A.nnz;
     P.col.alloc(P.nnz, s);
     P.val.alloc(P.nnz, s);
     if (A.n > 0)
@@ -938,20 +1100,6 @@ static void make_f32(DBuf<float>& dst, const DBuf<double>& src, size_t n, hipStr
 }
 
 // ---- DIA detection --------------------------------------------------------------------
-// Every entry's offset col - row must belong to the offsets of one probe row.
-__global__ void __launch_bounds__(B)
-k_dia_check(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col, int nd,
-            const int32_t* __restrict__ offs, int32_t* __restrict__ bad) {
-    int32_t i = blockIdx.x * B + threadIdx.x;
-    if (i >= n) return;
-    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
-        int32_t o = col[q] - i;
-        bool found = false;
-        for (int d = 0; d < nd; ++d) found |= (offs[d] == o);
-        if (!found) *bad = 1;
-    }
-}
-
 __global__ void __launch_bounds__(B)
 k_dia_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
            const double* __restrict__ val, int nd, const int32_t* __restrict__ offs,
@@ -966,52 +1114,74 @@ k_dia_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restr
     }
 }
 
-__global__ void k_probe_lens(int32_t n, const int32_t* __restrict__ rowptr, int32_t* __restrict__ lens) {
+// One wavefront: lanes 1..15 measure 15 hashed rows; lane 0 takes the
+// longest (ties: the first probed) and, when its length is odd in 3..7, writes
+// its column offsets: out[0] = number of diagonals (0: not a stencil level),
+// out[1..] = offsets.
+__global__ void __launch_bounds__(64)
+k_dia_probe(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+            int32_t* __restrict__ out) {
+    __shared__ int32_t lens[16];
     const uint32_t k = threadIdx.x;
-    if (k < 1 || k > 15) return;
-    const int32_t r = (int32_t)((k * 2654435761u) % (uint32_t)n);
-    lens[k] = rowptr[r + 1] - rowptr[r];
+    if (k < 16) {
+        const int32_t r = (int32_t)((k * 2654435761u) % (uint32_t)n);
+        lens[k] = k >= 1 ? rowptr[r + 1] - rowptr[r] : -1;
+    }
+    __syncthreads();
+    if (k != 0) return;
+    int32_t best_len = -1, best_row = 0;
+    for (uint32_t q = 1; q <= 15; ++q)
+        if (lens[q] > best_len) {
+            best_len = lens[q];
+            best_row = (int32_t)((q * 2654435761u) % (uint32_t)n);
+        }
+    const int nd = (best_len >= 3 && best_len <= 7 && best_len % 2 == 1) ? best_len : 0;
+    out[0] = nd;
+    const int32_t rp0 = rowptr[best_row];
+    for (int d = 0; d < nd; ++d) out[1 + d] = col[rp0 + d] - best_row;
 }
 
+// Every entry's offset col - row must belong to the probe row's offsets.
+__global__ void __launch_bounds__(B)
+k_dia_check(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+            const int32_t* __restrict__ probe, int32_t* __restrict__ bad) {
+    int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n) return;
+    const int nd = probe[0];
+    if (nd == 0) {
+        if (i == 0) *bad = 1;
+        return;
+    }
+    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+        int32_t o = col[q] - i;
+        bool found = false;
+        for (int d = 0; d < nd; ++d) found |= (probe[1 + d] == o);
+        if (!found) *bad = 1;
+    }
+}
+
+// DIA copy of a stencil level: one device probe and check, one host read.
 static void try_dia(tp_amg* h, Level& L, hipStream_t s) {
     const int32_t n = L.A.n;
     if (n < 1024 || L.A.nnz > 8LL * n) return;
-    // probe: the longest row among 15 hashed rows (one gather, one read)
-    int32_t best_len = -1, best_row = 0;
-    int32_t lens[16];
-    {
-        DBuf<int32_t> dl(16, s);
-        TP_LAUNCH(k_probe_lens, 1, 64, 0, s, n, L.A.rowptr.p, dl.p);
-        TP_HIP(hipMemcpyAsync(lens, dl.p, sizeof(int32_t) * 16, hipMemcpyDeviceToHost, s));
-        TP_HIP(hipStreamSynchronize(s));
-    }
-    for (uint32_t k = 1; k <= 15; ++k) {
-        int32_t r = (int32_t)((k * 2654435761u) % (uint32_t)n);
-        if (lens[k] > best_len) { best_len = lens[k]; best_row = r; }
-    }
-    if (best_len < 3 || best_len > 7 || (best_len % 2) == 0) return;
-    int32_t rp0 = 0, cols[7];
-    TP_HIP(hipMemcpyAsync(&rp0, L.A.rowptr.p + best_row, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    DBuf<int32_t> res(9, s);  // [0] bad, [1] nd, [2..8] offsets
+    TP_LAUNCH(k_fill_i32, 1, B, 0, s, res.p, 0, (int64_t)1);
+    TP_LAUNCH(k_dia_probe, 1, 64, 0, s, n, L.A.rowptr.p, L.A.col.p, res.p + 1);
+    TP_LAUNCH(k_dia_check, cdiv(n, B), B, 0, s, n, L.A.rowptr.p, L.A.col.p, (const int32_t*)(res.p + 1), res.p);
+    int32_t hres[9] = {0};
+    TP_HIP(hipMemcpyAsync(hres, res.p, sizeof(hres), hipMemcpyDeviceToHost, s));
     TP_HIP(hipStreamSynchronize(s));
-    TP_HIP(hipMemcpyAsync(cols, L.A.col.p + rp0, sizeof(int32_t) * best_len, hipMemcpyDeviceToHost, s));
-    TP_HIP(hipStreamSynchronize(s));
-    int32_t offs[7];
-    for (int d = 0; d < best_len; ++d) offs[d] = cols[d] - best_row;
-    DBuf<int32_t> doffs(best_len, s), bad(1, s);
-    TP_HIP(hipMemcpyAsync(doffs.p, offs, sizeof(int32_t) * best_len, hipMemcpyHostToDevice, s));
-    TP_LAUNCH(k_fill_i32, 1, B, 0, s, bad.p, 0, (int64_t)1);
-    TP_LAUNCH(k_dia_check, cdiv(n, B), B, 0, s, n, L.A.rowptr.p, L.A.col.p, best_len, doffs.p, bad.p);
-    if (read_i32(bad.p, s)) return;
-    L.ndia = best_len;
-    for (int d = 0; d < best_len; ++d) L.dia_off[d] = offs[d];
-    L.dia.alloc((size_t)best_len * n, s);
-    TP_LAUNCH(k_dia_fill, cdiv(n, B), B, 0, s, n, L.A.rowptr.p, L.A.col.p, L.A.val.p, best_len, doffs.p,
-              L.dia.p);
+    if (hres[0] || hres[1] == 0) return;
+    const int nd = hres[1];
+    L.ndia = nd;
+    for (int d = 0; d < nd; ++d) L.dia_off[d] = hres[2 + d];
+    L.dia.alloc((size_t)nd * n, s);
+    TP_LAUNCH(k_dia_fill, cdiv(n, B), B, 0, s, n, L.A.rowptr.p, L.A.col.p, L.A.val.p, nd,
+              (const int32_t*)(res.p + 2), L.dia.p);
     if (h->prm.storage == 1) {
-        L.dia32.alloc((size_t)best_len * n, s);
-        TP_LAUNCH(k_to_f32, cdiv((int64_t)best_len * n, B), B, 0, s, (int64_t)best_len * n, L.dia.p, L.dia32.p);
+        L.dia32.alloc((size_t)nd * n, s);
+        TP_LAUNCH(k_to_f32, cdiv((int64_t)nd * n, B), B, 0, s, (int64_t)nd * n, L.dia.p, L.dia32.p);
     }
-    TP_HIP(hipStreamSynchronize(s));  // doffs is host-staged above
 }
 
 static void alloc_work(tp_amg* h, hipStream_t s) {
@@ -1036,12 +1206,48 @@ static void alloc_work(tp_amg* h, hipStream_t s) {
     }
 }
 
+// The sizes of P and R were allocated from upper bounds during the level
+// loop; their exact entry counts (rowptr[n]) and the SpGEMM overflow flag are
+// gathered by one kernel and read once.
+struct SizeSrc {
+    const int32_t* p[64];
+    int32_t count;
+};
+
+__global__ void k_gather_i32(SizeSrc src, int32_t* __restrict__ out) {
+    const int t = threadIdx.x;
+    if (t < src.count) out[t] = *src.p[t];
+}
+
+static void exact_sizes(tp_amg* h, const int32_t* flag, hipStream_t s) {
+    SizeSrc src{};
+    int c = 0;
+    for (size_t l = 0; l + 1 < h->lev.size(); ++l) {
+        Level& L = h->lev[l];
+        src.p[c++] = L.P.rowptr.p + L.P.n;
+        src.p[c++] = L.R.rowptr.p + L.R.n;
+    }
+    src.p[c++] = flag;
+    src.count = c;
+    DBuf<int32_t> out(c, s);
+    TP_LAUNCH(k_gather_i32, 1, 64, 0, s, src, out.p);
+    std::vector<int32_t> v(c);
+    TP_HIP(hipMemcpyAsync(v.data(), out.p, sizeof(int32_t) * c, hipMemcpyDeviceToHost, s));
+    TP_HIP(hipStreamSynchronize(s));
+    if (v[c - 1]) fail(TP_ERR_CAPACITY, "SpGEMM row exceeded the %d-entry LDS hash table (code %d)", HASH, v[c - 1]);
+    for (size_t l = 0; l + 1 < h->lev.size(); ++l) {
+        h->lev[l].P.nnz = v[2 * l];
+        h->lev[l].R.nnz = v[2 * l + 1];
+    }
+}
+
 static void setup(tp_amg* h, int32_t n, const int32_t* rowptr, const int32_t* col, const double* val,
                   hipStream_t s) {
     const tp_amg_params& prm = h->prm;
     h->lev.emplace_back();
     copy_csr_in(h->lev[0].A, n, rowptr, col, val, s);
-    DBuf<int32_t> undecided(512, s);
+    DBuf<int32_t> undecided(512, s), sg_flag(1, s);
+    TP_LAUNCH(k_fill_i32, 1, B, 0, s, sg_flag.p, 0, (int64_t)1);
     for (int32_t l = 0;; ++l) {
         Level& L = h->lev[l];
         Csr& A = L.A;
@@ -1088,12 +1294,13 @@ static void setup(tp_amg* h, int32_t n, const int32_t* rowptr, const int32_t* co
             transpose(L.P.rowptr.p, L.P.col.p, L.P.val.p, L.P.n, nc, L.P.nnz, true, L.R, s);
         }
         Csr AP;
-        spgemm(A, L.P, AP, s);
+        spgemm(A, L.P, AP, sg_flag.p, s);
         h->lev.emplace_back();
         Level& Ln = h->lev[l + 1];        // (reference after emplace_back)
-        spgemm(h->lev[l].R, AP, Ln.A, s);
+        spgemm(h->lev[l].R, AP, Ln.A, sg_flag.p, s);
         Ln.A.m = nc;
     }
+    exact_sizes(h, sg_flag.p, s);
     build_coarse_inverse(h, h->lev.back().A, s);
     alloc_work(h, s);
     TP_HIP(hipStreamSynchronize(s));
