@@ -906,98 +906,106 @@ k_bgj_block(int32_t n, int32_t k, const double* __restrict__ X, double* __restri
     if (flag) *need_piv = 1;
 }
 
-// Y_ij = W_i,j-k (j in the block), else [i not in the block] X_ij + sum_c W_ic X_k+c,j
-// with W = Binv for the block's rows and W = -X_iK Binv for the others.
-// 64 x 64 tiles, each thread one column and 16 rows.  The first column of
-// tiles also checks the rows below the block (see above).
+// W = Binv on the block's rows and W = -X_iK Binv on the others (n x 32,
+// one thread per entry, a row's 32 entries in one half-wavefront).  The
+// same half-wavefront re-runs the forward elimination of a candidate row
+// below the block against the block's U (lanes hold the row's entries, the
+// pivot entry is broadcast by a shuffle) and flags a column where the row
+// would beat the pivot.
+constexpr int BW_T = 256;
+__global__ void __launch_bounds__(BW_T)
+k_bgj_w(int32_t n, int32_t k, int32_t nb, const double* __restrict__ X, const double* __restrict__ binv,
+        const double* __restrict__ U, double* __restrict__ W, int32_t* __restrict__ need_piv) {
+    __shared__ double s_bi[BG_NB][BG_NB + 1];
+    __shared__ double s_U[BG_NB][BG_NB + 1];
+    __shared__ double s_x[BW_T / BG_NB][BG_NB + 1];
+    const int t = threadIdx.x, c = t % BG_NB, rr = t / BG_NB;
+    const int32_t i = blockIdx.x * (BW_T / BG_NB) + rr;
+    for (int e = t; e < BG_NB * BG_NB; e += BW_T) {
+        const int r = e / BG_NB, q = e % BG_NB;
+        s_bi[r][q] = (r < nb && q < nb) ? binv[r * BG_NB + q] : 0.0;
+        s_U[r][q] = (r < nb && q < nb && q >= r) ? U[r * BG_NB + q] : 0.0;
+    }
+    const double xv = (i < n && c < nb) ? X[(int64_t)i * n + k + c] : 0.0;
+    s_x[rr][c] = xv;
+    __syncthreads();
+    if (i >= n) return;
+    double w;
+    if (i >= k && i < k + nb) {
+        w = s_bi[i - k][c];
+    } else {
+        w = 0.0;
+        for (int q = 0; q < nb; ++q) w += s_x[rr][q] * s_bi[q][c];
+        w = -w;
+    }
+    W[(int64_t)i * BG_NB + c] = w;
+    if (i >= k + nb) {
+        double v = xv;
+        bool flag = false;
+        for (int q = 0; q < nb; ++q) {
+            const double vq = __shfl(v, (t & ~(BG_NB - 1) & 63) + q, 64);
+            const double p = s_U[q][q];
+            flag = flag || !(fabs(vq) <= fabs(p));
+            if (c > q) v -= (vq / p) * s_U[q][c];
+        }
+        if (flag) *need_piv = 1;
+    }
+}
+
+// Y_ij = W_i,j-k (j in the block), else [i not in the block] X_ij + sum_c W_ic X_k+c,j.
+// 64 x 64 tiles; each thread a 4 x 4 micro-tile, all its loads of X before
+// its stores.
 constexpr int BU_T = 256;
 __global__ void __launch_bounds__(BU_T)
-k_bgj_update(int32_t n, int32_t k, int32_t nb, const double* __restrict__ X, const double* __restrict__ binv,
-             const double* __restrict__ U, double* __restrict__ Y, int32_t* __restrict__ need_piv) {
-    __shared__ double s_xk[64][BG_NB + 1];
-    __shared__ double s_bi[BG_NB][BG_NB + 1];
+k_bgj_update(int32_t n, int32_t k, int32_t nb, const double* __restrict__ X, const double* __restrict__ W,
+             double* __restrict__ Y) {
     __shared__ double s_W[64][BG_NB + 1];
-    __shared__ double s_B[BG_NB][64];
-    __shared__ double s_U[BG_NB][BG_NB + 1];
-    const int t = threadIdx.x, tx = t & 63, ty = t >> 6;
+    __shared__ double s_B[BG_NB][64 + 2];
+    const int t = threadIdx.x, tx = t % 16, ty = t / 16;
     const int32_t j0 = blockIdx.x * 64, i0 = blockIdx.y * 64;
     for (int e = t; e < 64 * BG_NB; e += BU_T) {
         const int r = e / BG_NB, c = e % BG_NB;
         const int32_t i = i0 + r;
-        s_xk[r][c] = (i < n && c < nb) ? X[(int64_t)i * n + k + c] : 0.0;
-    }
-    for (int e = t; e < BG_NB * BG_NB; e += BU_T) {
-        const int r = e / BG_NB, c = e % BG_NB;
-        s_bi[r][c] = (r < nb && c < nb) ? binv[r * BG_NB + c] : 0.0;
+        s_W[r][c] = (i < n && c < nb) ? W[(int64_t)i * BG_NB + c] : 0.0;
     }
     for (int e = t; e < BG_NB * 64; e += BU_T) {
         const int c = e / 64, x = e % 64;
         const int32_t j = j0 + x;
         s_B[c][x] = (j < n && c < nb) ? X[(int64_t)(k + c) * n + j] : 0.0;
     }
-    if (blockIdx.x == 0)
-        for (int e = t; e < BG_NB * BG_NB; e += BU_T) {
-            const int r = e / BG_NB, c = e % BG_NB;
-            s_U[r][c] = (r < nb && c < nb && c >= r) ? U[r * BG_NB + c] : 0.0;
-        }
-    __syncthreads();
-    for (int e = t; e < 64 * BG_NB; e += BU_T) {
-        const int r = e / BG_NB, c = e % BG_NB;
-        const int32_t i = i0 + r;
-        double w;
-        if (i >= k && i < k + nb) {
-            w = s_bi[i - k][c];
-        } else {
-            w = 0.0;
-            for (int c2 = 0; c2 < nb; ++c2) w += s_xk[r][c2] * s_bi[c2][c];
-            w = -w;
-        }
-        s_W[r][c] = w;
-    }
-    if (blockIdx.x == 0 && t < 64) {
-        // forward elimination of candidate row i against the block's U
-        const int32_t i = i0 + t;
-        if (i >= k + nb && i < n) {
-            double v[BG_NB];
+    double acc[4][4];
 #pragma unroll
-            for (int c = 0; c < BG_NB; ++c) v[c] = s_xk[t][c];
-            bool flag = false;
+    for (int a = 0; a < 4; ++a) {
+        const int32_t i = i0 + 4 * ty + a;
+        const bool keep = i < n && !(i >= k && i < k + nb);
 #pragma unroll
-            for (int c = 0; c < BG_NB; ++c) {
-                if (c < nb) {
-                    const double p = s_U[c][c];
-                    flag = flag || !(fabs(v[c]) <= fabs(p));
-                    const double f = v[c] / p;
-#pragma unroll
-                    for (int c2 = c + 1; c2 < BG_NB; ++c2) v[c2] -= f * s_U[c][c2];
-                }
-            }
-            if (flag) *need_piv = 1;
+        for (int q = 0; q < 4; ++q) {
+            const int32_t j = j0 + 4 * tx + q;
+            acc[a][q] = (keep && j < n && !(j >= k && j < k + nb)) ? X[(int64_t)i * n + j] : 0.0;
         }
     }
     __syncthreads();
-    const int32_t j = j0 + tx;
-    if (j >= n) return;
-    const bool inK = j >= k && j < k + nb;
-    constexpr int RT = 64 / (BU_T / 64);
-    double acc[RT];
-#pragma unroll
-    for (int q = 0; q < RT; ++q) {
-        const int r = ty + q * (BU_T / 64);
-        const int32_t i = i0 + r;
-        acc[q] = (i < n && !inK && !(i >= k && i < k + nb)) ? X[(int64_t)i * n + j] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < RT; ++q) {
-        const int r = ty + q * (BU_T / 64);
-        const int32_t i = i0 + r;
-        if (i >= n) break;
-        if (inK) {
-            Y[(int64_t)i * n + j] = s_W[r][j - k];
-        } else {
 #pragma unroll 8
-            for (int c = 0; c < BG_NB; ++c) acc[q] += s_W[r][c] * s_B[c][tx];
-            Y[(int64_t)i * n + j] = acc[q];
+    for (int c = 0; c < BG_NB; ++c) {
+        double wv[4], bv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) wv[a] = s_W[4 * ty + a][c];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bv[q] = s_B[c][4 * tx + q];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[a][q] += wv[a] * bv[q];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int32_t i = i0 + 4 * ty + a;
+        if (i >= n) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int32_t j = j0 + 4 * tx + q;
+            if (j >= n) continue;
+            Y[(int64_t)i * n + j] = (j >= k && j < k + nb) ? s_W[4 * ty + a][j - k] : acc[a][q];
         }
     }
 }
@@ -1008,7 +1016,8 @@ static void build_coarse_inverse(tp_amg* h, const Csr& A, hipStream_t s) {
     if (n > 4096) fail(TP_ERR_NUMERIC, "coarsening stalled at %d rows (> 4096), no dense factorisation", n);
     h->cinv.alloc((size_t)n * n, s);
     if (n == 0) return;
-    DBuf<double> W((size_t)n * n, s), T((size_t)16 * n, s), binv(BG_NB * BG_NB, s), U(BG_NB * BG_NB, s);
+    DBuf<double> W((size_t)n * n, s), T((size_t)16 * n, s), binv(BG_NB * BG_NB, s), U(BG_NB * BG_NB, s),
+        Wk((size_t)BG_NB * n, s);
     DBuf<int32_t> piv(n, s), rowsrc(n, s), src(n, s), flags(2, s);
     const int64_t nn = (int64_t)n * n;
     const int fill_grid = (int)std::min<int64_t>(cdiv(nn, B), 4096);
@@ -1022,8 +1031,10 @@ static void build_coarse_inverse(tp_amg* h, const Csr& A, hipStream_t s) {
     const dim3 g(cdiv(n, 64), cdiv(n, 64));
     for (int32_t k = 0; k < n; k += BG_NB) {
         TP_LAUNCH(k_bgj_block, 1, BK_T, 0, s, n, k, (const double*)X, binv.p, U.p, flags.p);
-        TP_LAUNCH(k_bgj_update, g, BU_T, 0, s, n, k, std::min(BG_NB, n - k), (const double*)X,
-                  (const double*)binv.p, (const double*)U.p, Y, flags.p);
+        const int32_t nb = std::min(BG_NB, n - k);
+        TP_LAUNCH(k_bgj_w, cdiv(n, BW_T / BG_NB), BW_T, 0, s, n, k, nb, (const double*)X, (const double*)binv.p,
+                  (const double*)U.p, Wk.p, flags.p);
+        TP_LAUNCH(k_bgj_update, g, BU_T, 0, s, n, k, nb, (const double*)X, (const double*)Wk.p, Y);
         std::swap(X, Y);
     }
     if (read_i32(flags.p, s) == 0) return;  // no interchange needed: cinv holds the inverse

@@ -415,6 +415,7 @@ struct Gmres {
     DBuf<double> V, Z, w, b, x, r, H, cs, sn, g, y, h1, h2, nrm2, part, sc;
     DBuf<unsigned int> ticket;
     HostMail& mail;
+    hipEvent_t ev[2] = {nullptr, nullptr};  // one per mailbox slot (pipelined iterations)
     static HostMail& host_mail() {
         // one pinned mailbox per host thread, kept for the process lifetime
         static thread_local HostMail* box = new HostMail();
@@ -440,6 +441,11 @@ struct Gmres {
         sc.alloc(4, s);
         ticket.alloc(1, s);
         TP_LAUNCH(k_zero_u32, 1, 64, 0, s, ticket.p);
+        for (auto& e : ev) TP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    ~Gmres() {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
     }
 };
 
@@ -516,8 +522,9 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
             if (use_graph) graph_ensure(M, s);
             TP_LAUNCH(k_cycle_init, 1, 1, 0, s, m, G.nrm2.p, G.g.p, G.sc.p);
             TP_LAUNCH(k_scale_div, gN, KB, 0, s, G.N, G.r.p, G.sc.p, G.V.p, use_graph ? M->rin.p : nullptr);
-            int k = 0;
-            for (int j = 0; j < m && it < kp.maxit; ++j) {
+            // Arnoldi step j: z_j = M^{-1} v_j, w = J z_j, CGS2 against v_0..v_j, Givens on
+            // column j, v_{j+1} = w / h_{j+1,j}; (h_{j+1,j}, |g_{j+1}|) go to mailbox slot `slot`
+            auto enqueue = [&](int j, int slot) {
                 double* vj = G.V.p + (int64_t)j * G.N;
                 double* zj = G.Z.p + (int64_t)j * G.N;
                 if (use_graph) {
@@ -535,10 +542,30 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
                 dots(G, j + 1, G.h2.p, G.w.p, 2, G.nrm2.p, s, 1, j);
                 TP_LAUNCH(k_scale_div, gN, KB, 0, s, G.N, G.w.p, G.sc.p, G.V.p + (int64_t)(j + 1) * G.N,
                           use_graph ? M->rin.p : nullptr);
-                TP_HIP(hipMemcpyAsync(G.mail.p, G.sc.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-                TP_HIP(hipStreamSynchronize(s));
-                const double hn = G.mail.as<double>()[0];
-                est = G.mail.as<double>()[1] / bnorm;
+                TP_HIP(hipMemcpyAsync(G.mail.as<double>() + 2 * slot, G.sc.p, 2 * sizeof(double),
+                                      hipMemcpyDeviceToHost, s));
+                TP_HIP(hipEventRecord(G.ev[slot], s));
+            };
+            // Without a learned smoother, step j+1 is queued before the host waits
+            // for step j's values, so the device never idles on the host's check.
+            // If step j ends the cycle, step j+1 has only written column j+1 of
+            // H, V_{j+2}, Z_{j+1} and the rotation j+1 (g_{j+1}, g_{j+2}); the
+            // update below uses columns 0..j and g_0..g_j, so it is discarded.
+            const bool pipelined = !cnn_on;
+            int k = 0;
+            if (it < kp.maxit) enqueue(0, 0);
+            for (int j = 0; j < m && it < kp.maxit; ++j) {
+                const int slot = j & 1;
+                // no step ahead when the last two estimates' ratio predicts that
+                // step j already meets the tolerance (the step would be wasted)
+                const size_t q = ests.size();
+                const bool likely_last =
+                    q >= 2 && ests[q - 2] > 0.0 && ests[q - 1] * (ests[q - 1] / ests[q - 2]) <= kp.rtol;
+                const bool ahead = pipelined && !likely_last && j + 1 < m && it + 1 < kp.maxit;
+                if (ahead) enqueue(j + 1, slot ^ 1);
+                TP_HIP(hipEventSynchronize(G.ev[slot]));
+                const double hn = G.mail.as<double>()[2 * slot];
+                est = G.mail.as<double>()[2 * slot + 1] / bnorm;
                 ++it;
                 k = j + 1;
                 if (history) history[it] = est;
@@ -558,6 +585,7 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
                 }
                 if (!std::isfinite(est)) fail(TP_ERR_NUMERIC, "non-finite Arnoldi value in FGMRES");
                 if (est <= kp.rtol || hn == 0.0) break;
+                if (!ahead && j + 1 < m && it < kp.maxit) enqueue(j + 1, slot ^ 1);
             }
             TP_LAUNCH(k_hess_solve, 1, 1, 0, s, k, m, G.H.p, G.g.p, G.y.p);
             TP_LAUNCH(k_xupdate, gN, KB, 0, s, G.N, k, G.Z.p, G.y.p, G.x.p);
