@@ -22,6 +22,7 @@ struct tp_cnn {
     int32_t n_work = 0;
     tp::DBuf<float> h, dh, out, dout;
     tp::DBuf<double> part;
+    tp::DBuf<float> gpart;  // per-workgroup partial gradients
 };
 
 namespace tp {

@@ -108,32 +108,81 @@ k_feat_normalise(int32_t n, const float* __restrict__ scale, float* __restrict__
 }
 
 // ---- forward ------------------------------------------------------------------------------
-// layer 1: h (16 x n FP32) from features (8 x n), weights from the BF16 copy
-__global__ void __launch_bounds__(CB)
+// Layer 1 as an implicit GEMM on the matrix cores: for 16 cells at a time,
+// H (16 channels x 16 cells) = W1 (16 x 216, k = c*27 + t) * F (216 x 16) + b1,
+// F[k][cell] = bf16(f_c(neighbour t of cell)) (0 off the grid), in seven
+// v_mfma_f32_16x16x32_bf16 steps (K padded to 224) with FP32 accumulation.
+// Lane layout of that instruction (16 lanes per row group q = lane / 16):
+// A[m][k] at lane m + 16 (k / 8 % 4), B[k][n] at lane n + 16 (k / 8 % 4),
+// D[m][n] at lane n + 16 (m / 4), element m % 4.  One wavefront per 16-cell
+// group; the weight fragments stay in registers across groups.
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float float4v;
+constexpr int MF_K = CNN_CIN * CNN_NT;  // 216
+constexpr int MF_KS = (MF_K + 31) / 32;  // 7 K-steps of 32
+// cell tile of one workgroup (16 x 4 x 4 cells: sixteen 16-cell rows along x)
+// and its one-cell halo, staged in LDS as BF16 (zero outside the grid)
+constexpr int TX = 16, TY = 4, TZ = 4, HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
+constexpr int HCELLS = HX * HY * HZ;
+constexpr int MF_T = 256;
+
+__global__ void __launch_bounds__(MF_T)
 k_cnn_l1(tp_grid g, const float* __restrict__ f, const float* __restrict__ w1, const float* __restrict__ b1,
          float* __restrict__ h) {
-    __shared__ float W[CNN_CH * CNN_CIN * CNN_NT];
-    for (int k = threadIdx.x; k < CNN_CH * CNN_CIN * CNN_NT; k += CB) W[k] = w1[k];
-    __syncthreads();
+    __shared__ __bf16 s_f[CNN_CIN * HCELLS];
     const int32_t n = g.nx * g.ny * g.nz;
-    const int32_t i = blockIdx.x * CB + threadIdx.x;
-    if (i >= n) return;
-    const int32_t ix = i % g.nx, iy = (i / g.nx) % g.ny, iz = i / (g.nx * g.ny);
-    float acc[CNN_CH];
+    const int32_t tx = g.nx > 0 ? (g.nx + TX - 1) / TX : 0, ty = (g.ny + TY - 1) / TY;
+    const int32_t bz = blockIdx.x / (tx * ty), by = (blockIdx.x / tx) % ty, bx = blockIdx.x % tx;
+    const int32_t x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
+    for (int e = threadIdx.x; e < CNN_CIN * HCELLS; e += MF_T) {
+        const int c = e / HCELLS, r = e % HCELLS;
+        const int hz = r / (HX * HY), hy = (r / HX) % HY, hx = r % HX;
+        const int32_t x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+        float v = 0.f;
+        if (x >= 0 && y >= 0 && z >= 0 && x < g.nx && y < g.ny && z < g.nz)
+            v = bf16_round(f[(int64_t)c * n + x + (int64_t)g.nx * (y + (int64_t)g.ny * z)]);
+        s_f[e] = (__bf16)v;  // exact: v is a BF16 value
+    }
+    const int lane = threadIdx.x & 63, q = lane >> 4, col = lane & 15, wv = threadIdx.x >> 6;
+    bf16x8 a[MF_KS];
 #pragma unroll
-    for (int o = 0; o < CNN_CH; ++o) acc[o] = b1[o];
-    for (int t = 0; t < CNN_NT; ++t) {
-        const int32_t j = tap_nbr(ix, iy, iz, t, g.nx, g.ny, g.nz);
-        if (j < 0) continue;
+    for (int st = 0; st < MF_KS; ++st)
 #pragma unroll
-        for (int c = 0; c < CNN_CIN; ++c) {
-            const float fv = bf16_round(f[(int64_t)c * n + j]);
+        for (int j = 0; j < 8; ++j) {
+            const int k = 32 * st + 8 * q + j;
+            a[st][j] = (__bf16)(k < MF_K ? w1[col * MF_K + k] : 0.f);  // BF16-rounded values: exact
+        }
+    float4v bias;
 #pragma unroll
-            for (int o = 0; o < CNN_CH; ++o) acc[o] += W[(o * CNN_CIN + c) * CNN_NT + t] * fv;
+    for (int r = 0; r < 4; ++r) bias[r] = b1[4 * q + r];
+    __syncthreads();
+#pragma unroll 1
+    for (int row = wv; row < TY * TZ; row += MF_T / 64) {
+        const int ly = row % TY, lz = row / TY;
+        float4v acc = bias;
+#pragma unroll
+        for (int st = 0; st < MF_KS; ++st) {
+            bf16x8 b;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = 32 * st + 8 * q + j;
+                if (k < MF_K) {
+                    const int c = k / CNN_NT, t = k % CNN_NT;
+                    const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;  // tap offsets + 1
+                    b[j] = s_f[c * HCELLS + ((lz + dz) * HY + (ly + dy)) * HX + col + dx];
+                } else {
+                    b[j] = (__bf16)0.f;
+                }
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[st], b, acc, 0, 0, 0);
+        }
+        const int32_t x = x0 + col, y = y0 + ly, z = z0 + lz;
+        if (x < g.nx && y < g.ny && z < g.nz) {
+            const int64_t cell = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) h[(int64_t)(4 * q + r) * n + cell] = acc[r];
         }
     }
-#pragma unroll
-    for (int o = 0; o < CNN_CH; ++o) h[(int64_t)o * n + i] = acc[o];
 }
 
 // layer 2 (FP32 activations): out = b2 + W2 * relu(h); with x: x += scale * out
@@ -187,72 +236,185 @@ k_cnn_dout(int32_t n, const float* __restrict__ out, const float* __restrict__ y
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-// dh_o(j) = [h_o(j) > 0] sum_t W2[o][t] dout(j - off_t)
-__global__ void __launch_bounds__(CB)
-k_cnn_dh(tp_grid g, const float* __restrict__ h, const float* __restrict__ w2, const float* __restrict__ dout,
-         float* __restrict__ dh) {
-    __shared__ float W[CNN_CH * CNN_NT];
-    for (int k = threadIdx.x; k < CNN_CH * CNN_NT; k += CB) W[k] = w2[k];
-    __syncthreads();
-    const int32_t n = g.nx * g.ny * g.nz;
-    const int32_t j = blockIdx.x * CB + threadIdx.x;
-    if (j >= n) return;
-    const int32_t ix = j % g.nx, iy = (j / g.nx) % g.ny, iz = j / (g.nx * g.ny);
-    float acc[CNN_CH];
-#pragma unroll
-    for (int o = 0; o < CNN_CH; ++o) acc[o] = 0.f;
-    for (int t = 0; t < CNN_NT; ++t) {
-        const int32_t i = tap_nbr(ix, iy, iz, CNN_NT - 1 - t, g.nx, g.ny, g.nz);
-        if (i < 0) continue;
-        const float d = dout[i];
-#pragma unroll
-        for (int o = 0; o < CNN_CH; ++o) acc[o] += W[o * CNN_NT + t] * d;
-    }
-#pragma unroll
-    for (int o = 0; o < CNN_CH; ++o) dh[(int64_t)o * n + j] = h[(int64_t)o * n + j] > 0.f ? acc[o] : 0.f;
+// ---- weight and bias gradients --------------------------------------------------------------
+// Per cell tile (the forward pass's 16 x 4 x 4 tiling) and with the one-cell halo of the
+// features and of dout staged in LDS:
+//   dh_o(j)      = [h_o(j) > 0] sum_t W2[o][t] dout(j - off_t)            (FP32, in the tile)
+//   dW1[o][c][t] = sum_j dh_o(j) f_c(j + off_t)     db1[o] = sum_j dh_o(j)
+//   dW2[o][t]    = sum_j relu(h_o(j)) dout(j - off_t)                   db2 = sum_j dout(j)
+// (the second is the first layer's gradient sum with i = j + off_t substituted). The three
+// cell sums are contractions over the tile's 256 cells, run on 16x16x32 BF16 MFMA with FP32
+// accumulation: [W1 | b1] as 14 column blocks of 16 (216 im2col columns of the BF16 features,
+// a column of ones, 7 zero columns) against dh, and W2 as 2 blocks (27 taps of dout) against
+// relu(h), four blocks per wave. FP32 operands that are not BF16 values enter split in two
+// BF16 parts v = hi + lo (|v - hi - lo| <= 2^-18 |v|): dh x feature takes 2 products,
+// relu(h) x dout takes 3 (hi.hi, hi.lo, lo.hi). Each workgroup accumulates over the tiles it
+// visits and writes its own partial gradient; k_cnn_grad_reduce sums the partials in a fixed
+// order, so the result is deterministic.
+constexpr int GT_CELLS = TX * TY * TZ;  // 256 = one cell per thread
+constexpr int GW_MAX = 512;             // partial-gradient workgroups at most
+
+__device__ inline void split_bf16(float v, __bf16& hi, __bf16& lo) {
+    const float a = bf16_round(v);
+    hi = (__bf16)a;                   // exact
+    lo = (__bf16)bf16_round(v - a);   // v - a is exact in FP32
 }
 
-// One workgroup per parameter: sum over cells of (upstream) x (input at the tap).
-//   p <  3456           dW1[o][c][t] = sum_i dh_o(i) f_c(i + t)        (features BF16-rounded)
-//   p <  3472           db1[o]       = sum_i dh_o(i)
-//   p <  3904           dW2[o][t]    = sum_i dout(i) relu(h_o(i + t))
-//   p == 3904           db2          = sum_i dout(i)
-__global__ void __launch_bounds__(CB)
-k_cnn_grad(tp_grid g, const float* __restrict__ f, const float* __restrict__ h, const float* __restrict__ dh,
-           const float* __restrict__ dout, float* __restrict__ grad) {
-    __shared__ float sh[CB];
+__global__ void __launch_bounds__(MF_T)
+k_cnn_wgrad(tp_grid g, const float* __restrict__ f, const float* __restrict__ h,
+            const float* __restrict__ dout, const float* __restrict__ w2, float* __restrict__ part) {
+    __shared__ __bf16 s_f[CNN_CIN * HCELLS];
+    __shared__ float s_do[HCELLS];
+    __shared__ __bf16 s_doh[HCELLS], s_dol[HCELLS];
+    __shared__ __attribute__((aligned(16))) __bf16 s_dh[2][CNN_CH * GT_CELLS];  // [hi|lo][o][cell]
+    __shared__ __attribute__((aligned(16))) __bf16 s_rh[2][CNN_CH * GT_CELLS];
+    __shared__ __attribute__((aligned(16))) float s_w2[CNN_NT * CNN_CH];          // [t][o]
+    __shared__ float s_red[MF_T / 64];
     const int32_t n = g.nx * g.ny * g.nz;
-    const int p = blockIdx.x;
-    float acc = 0.f;
-    int kind, o = 0, c = 0, t = 13;
-    if (p < 3456) { kind = 0; o = p / (CNN_CIN * CNN_NT); c = (p / CNN_NT) % CNN_CIN; t = p % CNN_NT; }
-    else if (p < 3472) { kind = 1; o = p - 3456; }
-    else if (p < 3904) { kind = 2; o = (p - 3472) / CNN_NT; t = (p - 3472) % CNN_NT; }
-    else { kind = 3; }
-    for (int32_t i = threadIdx.x; i < n; i += CB) {
-        const int32_t ix = i % g.nx, iy = (i / g.nx) % g.ny, iz = i / (g.nx * g.ny);
-        if (kind == 0) {
-            const int32_t j = tap_nbr(ix, iy, iz, t, g.nx, g.ny, g.nz);
-            if (j >= 0) acc += dh[(int64_t)o * n + i] * bf16_round(f[(int64_t)c * n + j]);
-        } else if (kind == 1) {
-            acc += dh[(int64_t)o * n + i];
-        } else if (kind == 2) {
-            const int32_t j = tap_nbr(ix, iy, iz, t, g.nx, g.ny, g.nz);
-            if (j >= 0) {
-                const float a = h[(int64_t)o * n + j];
-                acc += dout[i] * (a > 0.f ? a : 0.f);
-            }
+    const int32_t tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, tz = (g.nz + TZ - 1) / TZ;
+    const int32_t ntiles = tx * ty * tz;
+    for (int k = threadIdx.x; k < CNN_NT * CNN_CH; k += MF_T) s_w2[k] = w2[(k % CNN_CH) * CNN_NT + k / CNN_CH];
+    const int lane = threadIdx.x & 63, q = lane >> 4, col = lane & 15, wv = threadIdx.x >> 6;
+    // per-lane operand source of each of the wave's four column blocks: an LDS offset of the
+    // tap (relative to the cell's place in the halo), or a constant column (1 or 0)
+    int boff[4], bconst[4];  // bconst: -1 gather, else the constant value
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int job = wv + 4 * i;
+        if (job < 14) {
+            const int p = 16 * job + col;
+            const int c = p / CNN_NT, t = p % CNN_NT;
+            boff[i] = c * HCELLS + ((t / 9) * HY + (t / 3) % 3) * HX + t % 3;
+            bconst[i] = p < MF_K ? -1 : (p == MF_K ? 1 : 0);
+            if (bconst[i] >= 0) boff[i] = 0;
         } else {
-            acc += dout[i];
+            const int t = 16 * (job - 14) + col;
+            boff[i] = ((2 - t / 9) * HY + (2 - (t / 3) % 3)) * HX + 2 - t % 3;
+            bconst[i] = t < CNN_NT ? -1 : 0;
+            if (bconst[i] >= 0) boff[i] = 0;
         }
     }
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int off = CB / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    float4v acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = float4v{0.f, 0.f, 0.f, 0.f};
+    float db2 = 0.f;
+    const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
+    for (int32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int32_t bz = tile / (tx * ty), by = (tile / tx) % ty, bx = tile % tx;
+        const int32_t x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
+        __syncthreads();  // the previous tile's operands are consumed; s_w2 is written
+        for (int e = threadIdx.x; e < CNN_CIN * HCELLS; e += MF_T) {
+            const int c = e / HCELLS, r = e % HCELLS;
+            const int hz = r / (HX * HY), hy = (r / HX) % HY, hx = r % HX;
+            const int32_t x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+            const bool in = x >= 0 && y >= 0 && z >= 0 && x < g.nx && y < g.ny && z < g.nz;
+            const int64_t cell = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+            s_f[e] = (__bf16)(in ? bf16_round(f[(int64_t)c * n + cell]) : 0.f);
+            if (c == 0) s_do[r] = in ? dout[cell] : 0.f;
+        }
         __syncthreads();
+        for (int e = threadIdx.x; e < HCELLS; e += MF_T) split_bf16(s_do[e], s_doh[e], s_dol[e]);
+        {
+            const int32_t x = x0 + lx, y = y0 + ly, z = z0 + lz;
+            const bool in = x < g.nx && y < g.ny && z < g.nz;
+            const int64_t cell = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+            const int hb = ((lz + 2) * HY + ly + 2) * HX + lx + 2;  // halo index of j - off_t at t = 0
+            float d[CNN_CH];
+#pragma unroll
+            for (int o = 0; o < CNN_CH; ++o) d[o] = 0.f;
+#pragma unroll 1
+            for (int t = 0; t < CNN_NT; ++t) {
+                const float dv = s_do[hb - ((t / 9) * HY + (t / 3) % 3) * HX - t % 3];
+                const float4v* wt = (const float4v*)&s_w2[t * CNN_CH];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float4v w = wt[k];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) d[4 * k + r] += w[r] * dv;
+                }
+            }
+#pragma unroll
+            for (int o = 0; o < CNN_CH; ++o) {
+                const float hv = in ? h[(int64_t)o * n + cell] : 0.f;
+                const float dh = hv > 0.f ? d[o] : 0.f;
+                split_bf16(dh, s_dh[0][o * GT_CELLS + threadIdx.x], s_dh[1][o * GT_CELLS + threadIdx.x]);
+                split_bf16(hv > 0.f ? hv : 0.f, s_rh[0][o * GT_CELLS + threadIdx.x],
+                           s_rh[1][o * GT_CELLS + threadIdx.x]);
+            }
+            db2 += s_do[((lz + 1) * HY + ly + 1) * HX + lx + 1];  // zero outside the grid
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int st = 0; st < GT_CELLS / 32; ++st) {
+            // this lane's cells in the K-step: 8 consecutive x of tile row 2 st + q / 2
+            const int row = 2 * st + (q >> 1);
+            const int cb = ((row / TY) * HY + row % TY) * HX + 8 * (q & 1);  // halo index, tap (0,0,0)
+            const int ka = col * GT_CELLS + 32 * st + 8 * q;
+            const bf16x8 dhh = *(const bf16x8*)&s_dh[0][ka], dhl = *(const bf16x8*)&s_dh[1][ka];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int job = wv + 4 * i;
+                if (i < 3 || wv < 2) {  // jobs 0..13: [W1 | b1]; 14, 15: W2
+                    bf16x8 b;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        b[j] = bconst[i] < 0 ? s_f[boff[i] + cb + j] : (__bf16)(float)bconst[i];
+                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dhh, b, acc[i], 0, 0, 0);
+                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dhl, b, acc[i], 0, 0, 0);
+                } else {
+                    const bf16x8 rhh = *(const bf16x8*)&s_rh[0][ka], rhl = *(const bf16x8*)&s_rh[1][ka];
+                    bf16x8 bh, bl;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const bool gth = bconst[i] < 0;
+                        bh[j] = gth ? s_doh[boff[i] + cb + j] : (__bf16)0.f;
+                        bl[j] = gth ? s_dol[boff[i] + cb + j] : (__bf16)0.f;
+                    }
+                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rhh, bh, acc[i], 0, 0, 0);
+                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rhh, bl, acc[i], 0, 0, 0);
+                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rhl, bh, acc[i], 0, 0, 0);
+                }
+            }
+        }
     }
-    if (threadIdx.x == 0) grad[p] = sh[0];
+    float* pw = part + (int64_t)blockIdx.x * CNN_NPARAM;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int job = wv + 4 * i;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int o = 4 * q + r;
+            if (job < 14) {
+                const int p = 16 * job + col;
+                if (p < MF_K) pw[o * MF_K + p] = acc[i][r];
+                else if (p == MF_K) pw[CNN_OFF_B1 + o] = acc[i][r];
+            } else {
+                const int t = 16 * (job - 14) + col;
+                if (t < CNN_NT) pw[CNN_OFF_W2 + o * CNN_NT + t] = acc[i][r];
+            }
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) db2 += __shfl_down(db2, off);
+    if (lane == 0) s_red[wv] = db2;
+    __syncthreads();
+    if (threadIdx.x == 0) pw[CNN_OFF_B2] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+}
+
+// grad[p] = sum over workgroups of the partials, in workgroup order
+__global__ void __launch_bounds__(CB)
+k_cnn_grad_reduce(int nwg, const float* __restrict__ part, float* __restrict__ grad) {
+    const int p = blockIdx.x * CB + threadIdx.x;
+    if (p >= CNN_NPARAM) return;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    int b = 0;
+    for (; b + 4 <= nwg; b += 4) {
+        a0 += part[(int64_t)b * CNN_NPARAM + p];
+        a1 += part[(int64_t)(b + 1) * CNN_NPARAM + p];
+        a2 += part[(int64_t)(b + 2) * CNN_NPARAM + p];
+        a3 += part[(int64_t)(b + 3) * CNN_NPARAM + p];
+    }
+    for (; b < nwg; ++b) a0 += part[(int64_t)b * CNN_NPARAM + p];
+    grad[p] = (a0 + a1) + (a2 + a3);
 }
 
 // Adam (Kingma & Ba 2015) on the FP32 master weights; refresh the BF16 copies
@@ -344,6 +506,7 @@ void cnn_work_reserve(tp_cnn* c, int32_t n, hipStream_t s) {
     c->out.alloc(n, s);
     c->dout.alloc(n, s);
     c->part.alloc(1024, s);
+    if (!c->gpart.p) c->gpart.alloc((size_t)GW_MAX * CNN_NPARAM, s);
     c->n_work = n;
 }
 
@@ -353,7 +516,10 @@ void cnn_forward_into(tp_cnn* c, const tp_grid& g, const float* f, float* out, T
                       int32_t* bad, hipStream_t s) {
     const int32_t n = g.nx * g.ny * g.nz;
     cnn_work_reserve(c, n, s);
-    TP_LAUNCH(k_cnn_l1, cdiv(n, CB), CB, 0, s, g, f, c->wbf.p, c->w.p + CNN_OFF_B1, c->h.p);
+    {
+        const int64_t tiles = (int64_t)((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + TZ - 1) / TZ);
+        if (tiles > 0) TP_LAUNCH(k_cnn_l1, (int)tiles, MF_T, 0, s, g, f, c->wbf.p, c->w.p + CNN_OFF_B1, c->h.p);
+    }
     TP_LAUNCH(k_cnn_l2<T>, cdiv(n, CB), CB, 0, s, g, c->h.p, c->wbf.p + CNN_OFF_W2, c->w.p + CNN_OFF_B2, out, x,
               scale, bad);
 }
@@ -377,8 +543,10 @@ template void cnn_features_into<float>(tp_cnn_attach*, const float*, float*, hip
 // gradient of the loss from c->dout (set by the caller) and c->h of the last forward
 void cnn_backward_from_dout(tp_cnn* c, const tp_grid& g, const float* feat, hipStream_t s) {
     const int32_t n = g.nx * g.ny * g.nz;
-    TP_LAUNCH(k_cnn_dh, cdiv(n, CB), CB, 0, s, g, c->h.p, c->wbf.p + CNN_OFF_W2, c->dout.p, c->dh.p);
-    TP_LAUNCH(k_cnn_grad, CNN_NPARAM, CB, 0, s, g, feat, c->h.p, c->dh.p, c->dout.p, c->grad.p);
+    const int64_t tiles = (int64_t)((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + TZ - 1) / TZ);
+    const int nwg = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, GW_MAX));
+    TP_LAUNCH(k_cnn_wgrad, nwg, MF_T, 0, s, g, feat, c->h.p, c->dout.p, c->wbf.p + CNN_OFF_W2, c->gpart.p);
+    TP_LAUNCH(k_cnn_grad_reduce, cdiv(CNN_NPARAM, CB), CB, 0, s, nwg, c->gpart.p, c->grad.p);
 }
 
 // loss in the D^{-1} A norm of the attached finest level (A^T built on first use)

@@ -49,19 +49,26 @@ def _case(seed=0, dims=(10, 9, 8)):
     return g, th, f
 
 
-def test_forward_matches_oracle():
-    say("cnn forward")
-    g, th, f = _case()
+# one partial tile; several tiles with ragged ends in x, y and z; more tiles (768)
+# than the gradient kernel has workgroups, so that workgroups visit several
+DIMS = [(10, 9, 8), (37, 11, 9), (40, 64, 64)]
+
+
+@pytest.mark.parametrize("dims", DIMS)
+def test_forward_matches_oracle(dims):
+    say("cnn forward", dims)
+    g, th, f = _case(0, dims)
     net = tps.Net(th)
     out = net.forward(g, dev(f.reshape(-1))).cpu().numpy()
     ref, _ = oracle.cnn_forward(g, th.astype(np.float64), f.astype(np.float64))
     assert np.abs(out - ref).max() <= 1e-4 * np.abs(ref).max()
 
 
-def test_gradient_matches_oracle():
-    say("cnn gradient")
+@pytest.mark.parametrize("dims", DIMS)
+def test_gradient_matches_oracle(dims):
+    say("cnn gradient", dims)
     import torch
-    g, th, f = _case(1)
+    g, th, f = _case(1, dims)
     y = np.random.default_rng(5).standard_normal(g.n).astype(np.float32)
     net = tps.Net(th)
     grad = torch.zeros(tps.CNN_NPARAM, dtype=torch.float32, device="cuda")
