@@ -37,6 +37,7 @@ struct tp_amg {
     tp::DBuf<double> cinv;       // nc x nc inverse of the coarsest operator
     hipStream_t stream = nullptr;
     std::unique_ptr<tp::tp_cnn_attach> cnn;  // learned finest-level post-smoother (optional)
+    uint64_t cnn_gen = 0;                    // attachments made so far (identifies the current one)
     bool stop_before_post = false;           // pair generation: end the cycle before post-smoothing
 };
 

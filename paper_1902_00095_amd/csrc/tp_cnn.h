@@ -36,6 +36,7 @@ struct tp_cnn_attach {
     DBuf<double> part;
     DBuf<float> scale;
     DBuf<int32_t> bad;
+    DBuf<float> h;      // 16 x n hidden activations of the smoother's own forward passes
     Csr At;             // transpose of the level operator (operator-norm training loss)
     bool enabled = true;
 };
@@ -43,7 +44,7 @@ struct tp_cnn_attach {
 void cnn_work_reserve(tp_cnn* c, int32_t n, hipStream_t s);
 template <typename T>
 void cnn_forward_into(tp_cnn* c, const tp_grid& g, const float* f, float* out, T* x, const float* scale,
-                      int32_t* bad, hipStream_t s);
+                      int32_t* bad, hipStream_t s, float* hw = nullptr);
 template <typename T>
 void cnn_features_into(tp_cnn_attach* a, const T* r, float* f, hipStream_t s);
 void cnn_backward_from_dout(tp_cnn* c, const tp_grid& g, const float* feat, hipStream_t s);

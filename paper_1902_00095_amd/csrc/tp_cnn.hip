@@ -108,50 +108,58 @@ k_feat_normalise(int32_t n, const float* __restrict__ scale, float* __restrict__
 }
 
 // ---- forward ------------------------------------------------------------------------------
-// Layer 1 as an implicit GEMM on the matrix cores: for 16 cells at a time,
-// H (16 channels x 16 cells) = W1 (16 x 216, k = c*27 + t) * F (216 x 16) + b1,
+// Layer 1 as an implicit GEMM on the matrix cores: for a row of 16 cells along x,
+// H (16 channels x 16 cells) = W1 (16 x 216) * F (216 x 16) + b1 with
 // F[k][cell] = bf16(f_c(neighbour t of cell)) (0 off the grid), in seven
-// v_mfma_f32_16x16x32_bf16 steps (K padded to 224) with FP32 accumulation.
-// Lane layout of that instruction (16 lanes per row group q = lane / 16):
-// A[m][k] at lane m + 16 (k / 8 % 4), B[k][n] at lane n + 16 (k / 8 % 4),
-// D[m][n] at lane n + 16 (m / 4), element m % 4.  One wavefront per 16-cell
-// group; the weight fragments stay in registers across groups.
+// v_mfma_f32_16x16x32_bf16 steps with FP32 accumulation. Lane layout of that
+// instruction (16 lanes per group q = lane / 16): A[m][k] at lane m + 16 (k / 8 % 4),
+// element k % 8; B[k][n] at lane n + 16 (k / 8 % 4); D[m][n] at lane n + 16 (m / 4),
+// element m % 4. The contraction index runs tap-major, k = 8 t + c, so the eight
+// values a lane contributes to B are the eight channels of one cell at one tap:
+// with the features of the tile and its one-cell halo staged in LDS channel-
+// interleaved (16 bytes per cell) each B fragment is a single 16-byte LDS read.
+// Group q of K-step st takes tap 4 st + q (tap 27, past the end, contributes 0).
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float float4v;
-constexpr int MF_K = CNN_CIN * CNN_NT;  // 216
+constexpr int MF_K = CNN_CIN * CNN_NT;   // 216
 constexpr int MF_KS = (MF_K + 31) / 32;  // 7 K-steps of 32
 // cell tile of one workgroup (16 x 4 x 4 cells: sixteen 16-cell rows along x)
-// and its one-cell halo, staged in LDS as BF16 (zero outside the grid)
+// and its one-cell halo (zero outside the grid)
 constexpr int TX = 16, TY = 4, TZ = 4, HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
 constexpr int HCELLS = HX * HY * HZ;
 constexpr int MF_T = 256;
 
+__device__ inline int halo_tap(int t) { return ((t / 9) * HY + (t / 3) % 3) * HX + t % 3; }
+
 __global__ void __launch_bounds__(MF_T)
 k_cnn_l1(tp_grid g, const float* __restrict__ f, const float* __restrict__ w1, const float* __restrict__ b1,
          float* __restrict__ h) {
-    __shared__ __bf16 s_f[CNN_CIN * HCELLS];
+    __shared__ bf16x8 s_f[HCELLS];  // [halo cell][channel]
     const int32_t n = g.nx * g.ny * g.nz;
-    const int32_t tx = g.nx > 0 ? (g.nx + TX - 1) / TX : 0, ty = (g.ny + TY - 1) / TY;
+    const int32_t tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY;
     const int32_t bz = blockIdx.x / (tx * ty), by = (blockIdx.x / tx) % ty, bx = blockIdx.x % tx;
     const int32_t x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
-    for (int e = threadIdx.x; e < CNN_CIN * HCELLS; e += MF_T) {
-        const int c = e / HCELLS, r = e % HCELLS;
+    for (int r = threadIdx.x; r < HCELLS; r += MF_T) {
         const int hz = r / (HX * HY), hy = (r / HX) % HY, hx = r % HX;
         const int32_t x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
-        float v = 0.f;
-        if (x >= 0 && y >= 0 && z >= 0 && x < g.nx && y < g.ny && z < g.nz)
-            v = bf16_round(f[(int64_t)c * n + x + (int64_t)g.nx * (y + (int64_t)g.ny * z)]);
-        s_f[e] = (__bf16)v;  // exact: v is a BF16 value
+        const bool in = x >= 0 && y >= 0 && z >= 0 && x < g.nx && y < g.ny && z < g.nz;
+        const int64_t cell = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+        bf16x8 v;
+#pragma unroll
+        for (int c = 0; c < CNN_CIN; ++c) v[c] = (__bf16)(in ? bf16_round(f[(int64_t)c * n + cell]) : 0.f);
+        s_f[r] = v;  // the conversions are exact: BF16 values
     }
     const int lane = threadIdx.x & 63, q = lane >> 4, col = lane & 15, wv = threadIdx.x >> 6;
     bf16x8 a[MF_KS];
+    int toff[MF_KS];
 #pragma unroll
-    for (int st = 0; st < MF_KS; ++st)
+    for (int st = 0; st < MF_KS; ++st) {
+        const int t = 4 * st + q;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int k = 32 * st + 8 * q + j;
-            a[st][j] = (__bf16)(k < MF_K ? w1[col * MF_K + k] : 0.f);  // BF16-rounded values: exact
-        }
+        for (int c = 0; c < CNN_CIN; ++c)
+            a[st][c] = (__bf16)(t < CNN_NT ? w1[col * MF_K + c * CNN_NT + t] : 0.f);  // BF16 values: exact
+        toff[st] = t < CNN_NT ? halo_tap(t) : -1;
+    }
     float4v bias;
 #pragma unroll
     for (int r = 0; r < 4; ++r) bias[r] = b1[4 * q + r];
@@ -159,21 +167,12 @@ k_cnn_l1(tp_grid g, const float* __restrict__ f, const float* __restrict__ w1, c
 #pragma unroll 1
     for (int row = wv; row < TY * TZ; row += MF_T / 64) {
         const int ly = row % TY, lz = row / TY;
+        const int cb = (lz * HY + ly) * HX + col;
         float4v acc = bias;
 #pragma unroll
         for (int st = 0; st < MF_KS; ++st) {
-            bf16x8 b;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int k = 32 * st + 8 * q + j;
-                if (k < MF_K) {
-                    const int c = k / CNN_NT, t = k % CNN_NT;
-                    const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;  // tap offsets + 1
-                    b[j] = s_f[c * HCELLS + ((lz + dz) * HY + (ly + dy)) * HX + col + dx];
-                } else {
-                    b[j] = (__bf16)0.f;
-                }
-            }
+            bf16x8 b = s_f[toff[st] < 0 ? 0 : cb + toff[st]];
+            if (toff[st] < 0) b = bf16x8{};  // A is zero there too; keep B finite
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[st], b, acc, 0, 0, 0);
         }
         const int32_t x = x0 + col, y = y0 + ly, z = z0 + lz;
@@ -185,29 +184,46 @@ k_cnn_l1(tp_grid g, const float* __restrict__ f, const float* __restrict__ w1, c
     }
 }
 
-// layer 2 (FP32 activations): out = b2 + W2 * relu(h); with x: x += scale * out
+// Layer 2 (FP32): out = b2 + W2 * relu(h); with x: x += scale * out. relu(h) of the
+// tile and its halo is staged in LDS channel-planar (conflict-free), one thread per cell.
 template <typename T>
-__global__ void __launch_bounds__(CB)
+__global__ void __launch_bounds__(MF_T)
 k_cnn_l2(tp_grid g, const float* __restrict__ h, const float* __restrict__ w2, const float* __restrict__ b2,
          float* __restrict__ out, T* __restrict__ x, const float* __restrict__ scale,
          int32_t* __restrict__ bad) {
-    __shared__ float W[CNN_CH * CNN_NT];
-    for (int k = threadIdx.x; k < CNN_CH * CNN_NT; k += CB) W[k] = w2[k];
-    __syncthreads();
+    __shared__ float s_h[CNN_CH * HCELLS];                             // [o][halo cell]
+    __shared__ __attribute__((aligned(16))) float s_w[CNN_NT * CNN_CH];  // [t][o]
     const int32_t n = g.nx * g.ny * g.nz;
-    const int32_t i = blockIdx.x * CB + threadIdx.x;
-    if (i >= n) return;
-    const int32_t ix = i % g.nx, iy = (i / g.nx) % g.ny, iz = i / (g.nx * g.ny);
+    const int32_t tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY;
+    const int32_t bz = blockIdx.x / (tx * ty), by = (blockIdx.x / tx) % ty, bx = blockIdx.x % tx;
+    const int32_t x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
+    for (int k = threadIdx.x; k < CNN_NT * CNN_CH; k += MF_T) s_w[k] = w2[(k % CNN_CH) * CNN_NT + k / CNN_CH];
+    for (int e = threadIdx.x; e < CNN_CH * HCELLS; e += MF_T) {
+        const int o = e / HCELLS, r = e % HCELLS;
+        const int hz = r / (HX * HY), hy = (r / HX) % HY, hx = r % HX;
+        const int32_t xx = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+        float v = 0.f;
+        if (xx >= 0 && y >= 0 && z >= 0 && xx < g.nx && y < g.ny && z < g.nz)
+            v = h[(int64_t)o * n + xx + (int64_t)g.nx * (y + (int64_t)g.ny * z)];
+        s_h[e] = v > 0.f ? v : 0.f;
+    }
+    __syncthreads();
+    const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
+    const int32_t xi = x0 + lx, yi = y0 + ly, zi = z0 + lz;
+    if (xi >= g.nx || yi >= g.ny || zi >= g.nz) return;
+    const int cb = (lz * HY + ly) * HX + lx;
     float acc = b2[0];
     for (int t = 0; t < CNN_NT; ++t) {
-        const int32_t j = tap_nbr(ix, iy, iz, t, g.nx, g.ny, g.nz);
-        if (j < 0) continue;
+        const int j = cb + halo_tap(t);
+        const float4v* wt = (const float4v*)&s_w[t * CNN_CH];
 #pragma unroll
-        for (int o = 0; o < CNN_CH; ++o) {
-            const float a = h[(int64_t)o * n + j];
-            acc += W[o * CNN_NT + t] * (a > 0.f ? a : 0.f);
+        for (int k = 0; k < 4; ++k) {
+            const float4v w = wt[k];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc += w[r] * s_h[(4 * k + r) * HCELLS + j];
         }
     }
+    const int64_t i = xi + (int64_t)g.nx * (yi + (int64_t)g.ny * zi);
     if (out) out[i] = acc;
     if (x) {
         if (!isfinite(acc)) *bad = 1;
@@ -510,23 +526,29 @@ void cnn_work_reserve(tp_cnn* c, int32_t n, hipStream_t s) {
     c->n_work = n;
 }
 
-// forward on given features; out may be null; with x: smoother update x += scale * out
+// forward on given features; out may be null; with x: smoother update x += scale * out;
+// hidden activations in hw (16 x n) or, when null, in the network's own work buffer
 template <typename T>
 void cnn_forward_into(tp_cnn* c, const tp_grid& g, const float* f, float* out, T* x, const float* scale,
-                      int32_t* bad, hipStream_t s) {
+                      int32_t* bad, hipStream_t s, float* hw) {
     const int32_t n = g.nx * g.ny * g.nz;
-    cnn_work_reserve(c, n, s);
+    if (!hw) {
+        cnn_work_reserve(c, n, s);
+        hw = c->h.p;
+    }
     {
         const int64_t tiles = (int64_t)((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + TZ - 1) / TZ);
-        if (tiles > 0) TP_LAUNCH(k_cnn_l1, (int)tiles, MF_T, 0, s, g, f, c->wbf.p, c->w.p + CNN_OFF_B1, c->h.p);
+        if (tiles > 0) {
+            TP_LAUNCH(k_cnn_l1, (int)tiles, MF_T, 0, s, g, f, c->wbf.p, c->w.p + CNN_OFF_B1, hw);
+            TP_LAUNCH(k_cnn_l2<T>, (int)tiles, MF_T, 0, s, g, hw, c->wbf.p + CNN_OFF_W2, c->w.p + CNN_OFF_B2,
+                      out, x, scale, bad);
+        }
     }
-    TP_LAUNCH(k_cnn_l2<T>, cdiv(n, CB), CB, 0, s, g, c->h.p, c->wbf.p + CNN_OFF_W2, c->w.p + CNN_OFF_B2, out, x,
-              scale, bad);
 }
 template void cnn_forward_into<double>(tp_cnn*, const tp_grid&, const float*, float*, double*, const float*,
-                                       int32_t*, hipStream_t);
+                                       int32_t*, hipStream_t, float*);
 template void cnn_forward_into<float>(tp_cnn*, const tp_grid&, const float*, float*, float*, const float*,
-                                      int32_t*, hipStream_t);
+                                      int32_t*, hipStream_t, float*);
 
 // features for residual r on the finest level of a hierarchy with an attached smoother
 template <typename T>
@@ -575,6 +597,7 @@ void cnn_attach_build(tp_cnn_attach* a, const tp_grid& g, const int32_t* rowptr,
     a->part.alloc(1024, s);
     a->scale.alloc(1, s);
     a->bad.alloc(1, s);
+    a->h.alloc((size_t)CNN_CH * n, s);
     TP_LAUNCH(k_feat_static, cdiv(n, CB), CB, 0, s, g, rowptr, col, val, a->feat.p, a->dinv.p);
 }
 

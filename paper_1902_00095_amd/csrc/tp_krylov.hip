@@ -35,6 +35,10 @@ struct tp_prec {
     // Captured on a private stream (capture is not allowed on the legacy
     // null stream that callers often pass).
     hipGraphExec_t gexec = nullptr;
+    // the same with the learned post-smoother of the Schur hierarchy enabled,
+    // valid for the attachment numbered gen_cnn
+    hipGraphExec_t gexec_cnn = nullptr;
+    uint64_t gen_cnn = 0;
     hipStream_t cap = nullptr;
     tp::DBuf<double> rin, zout;
     tp_jacobian J;
@@ -278,11 +282,13 @@ k_cgs_finish(int nb, int cnt, const double* __restrict__ part, double* __restric
     arnoldi_update_block(aa, nrm, hc, cs, sn, gg);
 }
 
-// v = w / nrm (nrm on device); optionally also into v2 (the graph's input)
+// v = w / nrm (nrm on device); optionally also into v2 (the graph's input);
+// flag (when given) = the learned smoother's failure flag bad (0 without one)
 __global__ void __launch_bounds__(KB)
 k_scale_div(int64_t N, const double* __restrict__ w, const double* __restrict__ nrm, double* __restrict__ v,
-            double* __restrict__ v2) {
+            double* __restrict__ v2, const int32_t* __restrict__ bad, double* __restrict__ flag) {
     int64_t i = (int64_t)blockIdx.x * KB + threadIdx.x;
+    if (i == 0 && flag) flag[0] = bad ? (double)bad[0] : 0.0;
     if (i >= N) return;
     const double q = w[i] / nrm[0];
     v[i] = q;
@@ -374,20 +380,35 @@ void prec_apply_split(tp_prec* M, const double* r, double* z, hipStream_t s) {
 }
 
 // ---- graph of the preconditioner apply -------------------------------------------------------
-static bool graph_usable(tp_prec* M) {
-    return !(M->S->cnn && M->S->cnn->enabled) && !(M->pp->cnn && M->pp->cnn->enabled) && !timer().on;
-}
+// (a learned smoother on the pressure hierarchy, which the solver never
+// switches off, and the smoother timer keep the apply eager)
+static bool graph_usable(tp_prec* M) { return !(M->pp->cnn && M->pp->cnn->enabled) && !timer().on; }
 
-// capture prec_apply_split(rin -> zout) the first time (staging vectors
-// allocated on the solve stream s); the instantiated graph is then launched
-// on whatever stream the solve runs on
-static void graph_ensure(tp_prec* M, hipStream_t s) {
-    if (M->gexec) return;
+static bool schur_cnn_on(tp_prec* M) { return M->S->cnn && M->S->cnn->enabled; }
+
+// Graph of prec_apply_split(rin -> zout), with or without the Schur hierarchy's
+// learned post-smoother (captured the first time each is needed, the learned one
+// again after every new attachment; staging vectors allocated on the solve
+// stream s). The instantiated graph is launched on whatever stream the solve
+// runs on.
+static hipGraphExec_t graph_ensure(tp_prec* M, hipStream_t s, bool with_cnn) {
+    hipGraphExec_t& slot = with_cnn ? M->gexec_cnn : M->gexec;
+    if (with_cnn && slot && M->gen_cnn != M->S->cnn_gen) {
+        TP_HIP(hipDeviceSynchronize());  // a replay of the stale graph may still run
+        (void)hipGraphExecDestroy(slot);
+        slot = nullptr;
+    }
+    if (slot) return slot;
     const int32_t n = M->J.n;
-    M->rin.alloc(2 * (size_t)n, s);
-    M->zout.alloc(2 * (size_t)n, s);
+    if (M->rin.n != 2 * (size_t)n) {
+        M->rin.alloc(2 * (size_t)n, s);
+        M->zout.alloc(2 * (size_t)n, s);
+    }
     if (!M->cap) TP_HIP(hipStreamCreateWithFlags(&M->cap, hipStreamNonBlocking));
     const hipStream_t c = M->cap;
+    tp_cnn_attach* a = M->S->cnn.get();
+    const bool was = a && a->enabled;
+    if (a) a->enabled = with_cnn;
     hipGraph_t g = nullptr;
     TP_HIP(hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal));
     try {
@@ -396,14 +417,18 @@ static void graph_ensure(tp_prec* M, hipStream_t s) {
         hipGraph_t junk = nullptr;
         (void)hipStreamEndCapture(c, &junk);
         if (junk) (void)hipGraphDestroy(junk);
+        if (a) a->enabled = was;
         throw;
     }
+    if (a) a->enabled = was;
     TP_HIP(hipStreamEndCapture(c, &g));
     hipGraphExec_t ex = nullptr;
     hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     TP_HIP(e);
-    M->gexec = ex;
+    slot = ex;
+    if (with_cnn) M->gen_cnn = M->S->cnn_gen;
+    return ex;
 }
 
 // ---- FGMRES driver ------------------------------------------------------------------------------
@@ -519,17 +544,19 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
             if (!std::isfinite(rel)) fail(TP_ERR_NUMERIC, "non-finite residual in FGMRES");
             // v_0 = r / beta (nrm2 holds ||r||^2)
             const bool use_graph = kp.graph != 0 && graph_usable(M);
-            if (use_graph) graph_ensure(M, s);
+            if (use_graph) graph_ensure(M, s, cnn_on);
             TP_LAUNCH(k_cycle_init, 1, 1, 0, s, m, G.nrm2.p, G.g.p, G.sc.p);
-            TP_LAUNCH(k_scale_div, gN, KB, 0, s, G.N, G.r.p, G.sc.p, G.V.p, use_graph ? M->rin.p : nullptr);
+            TP_LAUNCH(k_scale_div, gN, KB, 0, s, G.N, G.r.p, G.sc.p, G.V.p, use_graph ? M->rin.p : nullptr,
+                      (const int32_t*)nullptr, (double*)nullptr);
             // Arnoldi step j: z_j = M^{-1} v_j, w = J z_j, CGS2 against v_0..v_j, Givens on
-            // column j, v_{j+1} = w / h_{j+1,j}; (h_{j+1,j}, |g_{j+1}|) go to mailbox slot `slot`
+            // column j, v_{j+1} = w / h_{j+1,j}; (h_{j+1,j}, |g_{j+1}|, the learned smoother's
+            // failure flag) go to mailbox slot `slot`
             auto enqueue = [&](int j, int slot) {
                 double* vj = G.V.p + (int64_t)j * G.N;
                 double* zj = G.Z.p + (int64_t)j * G.N;
                 if (use_graph) {
                     // rin already holds v_j; the product kernel copies zout into Z_j
-                    TP_HIP(hipGraphLaunch(M->gexec, s));
+                    TP_HIP(hipGraphLaunch(graph_ensure(M, s, cnn_on), s));
                     TP_LAUNCH(k_block_spmv, gJ, KB, 0, s, n, J.rowptr, J.col, J.pp, J.pT, J.Tp, J.TT, M->zout.p,
                               (const double*)nullptr, G.w.p, zj);
                 } else {
@@ -541,17 +568,20 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
                 dots(G, j + 1, G.h1.p, G.w.p, 1, G.h2.p, s);
                 dots(G, j + 1, G.h2.p, G.w.p, 2, G.nrm2.p, s, 1, j);
                 TP_LAUNCH(k_scale_div, gN, KB, 0, s, G.N, G.w.p, G.sc.p, G.V.p + (int64_t)(j + 1) * G.N,
-                          use_graph ? M->rin.p : nullptr);
-                TP_HIP(hipMemcpyAsync(G.mail.as<double>() + 2 * slot, G.sc.p, 2 * sizeof(double),
+                          use_graph ? M->rin.p : nullptr, cnn_on ? (const int32_t*)M->S->cnn->bad.p : nullptr,
+                          G.sc.p + 2);
+                TP_HIP(hipMemcpyAsync(G.mail.as<double>() + 4 * slot, G.sc.p, 3 * sizeof(double),
                                       hipMemcpyDeviceToHost, s));
                 TP_HIP(hipEventRecord(G.ev[slot], s));
             };
-            // Without a learned smoother, step j+1 is queued before the host waits
-            // for step j's values, so the device never idles on the host's check.
-            // If step j ends the cycle, step j+1 has only written column j+1 of
-            // H, V_{j+2}, Z_{j+1} and the rotation j+1 (g_{j+1}, g_{j+2}); the
-            // update below uses columns 0..j and g_0..g_j, so it is discarded.
-            const bool pipelined = !cnn_on;
+            // Step j+1 is queued before the host waits for step j's values, so the
+            // device never idles on the host's check. If step j ends the cycle, step
+            // j+1 has only written column j+1 of H, V_{j+2}, Z_{j+1} and the rotation
+            // j+1 (g_{j+1}, g_{j+2}); the update below uses columns 0..j and g_0..g_j,
+            // so it is discarded. When the host switches the learned smoother off
+            // after step j, step j+1 has already run with it: FGMRES keeps each
+            // step's own z, so a preconditioner that changes between steps is valid.
+            const bool pipelined = true;
             int k = 0;
             if (it < kp.maxit) enqueue(0, 0);
             for (int j = 0; j < m && it < kp.maxit; ++j) {
@@ -564,17 +594,15 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
                 const bool ahead = pipelined && !likely_last && j + 1 < m && it + 1 < kp.maxit;
                 if (ahead) enqueue(j + 1, slot ^ 1);
                 TP_HIP(hipEventSynchronize(G.ev[slot]));
-                const double hn = G.mail.as<double>()[2 * slot];
-                est = G.mail.as<double>()[2 * slot + 1] / bnorm;
+                const double hn = G.mail.as<double>()[4 * slot];
+                est = G.mail.as<double>()[4 * slot + 1] / bnorm;
+                const bool bad = G.mail.as<double>()[4 * slot + 2] != 0.0;
                 ++it;
                 k = j + 1;
                 if (history) history[it] = est;
                 ests.push_back(est);
                 if (cnn_on) {
                     tp_cnn_attach* a = M->S->cnn.get();
-                    int32_t bad = 0;
-                    TP_HIP(hipMemcpyAsync(&bad, a->bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-                    TP_HIP(hipStreamSynchronize(s));
                     const size_t q = ests.size();
                     const bool stag = kp.stag_ratio > 0.0 && q >= 3 && ests[q - 1] > kp.stag_ratio * ests[q - 3];
                     if (bad || stag) {
@@ -639,9 +667,9 @@ int precond_apply(tp_prec_t M, const double* r, double* z, void* stream) {
         hipStream_t s = (hipStream_t)stream;
         const int32_t n = M->J.n;
         if (tp::graph_usable(M)) {
-            tp::graph_ensure(M, s);
+            hipGraphExec_t ex = tp::graph_ensure(M, s, tp::schur_cnn_on(M));
             TP_LAUNCH(tp::k_deinterleave, tp::cdiv(n, tp::KB), tp::KB, 0, s, n, r, M->rin.p);
-            TP_HIP(hipGraphLaunch(M->gexec, s));
+            TP_HIP(hipGraphLaunch(ex, s));
             TP_LAUNCH(tp::k_interleave, tp::cdiv(n, tp::KB), tp::KB, 0, s, n, M->zout.p, z);
         } else {
             if (M->rs.n != (size_t)2 * n) {
@@ -662,6 +690,7 @@ int precond_destroy(tp_prec_t M) {
             TP_HIP(hipDeviceSynchronize());
             tp::gmres_free(M->ws);
             if (M->gexec) (void)hipGraphExecDestroy(M->gexec);
+            if (M->gexec_cnn) (void)hipGraphExecDestroy(M->gexec_cnn);
             if (M->cap) (void)hipStreamDestroy(M->cap);
             delete M;
         }

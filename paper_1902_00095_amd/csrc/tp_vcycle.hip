@@ -456,7 +456,7 @@ static T* vcycle_level(tp_amg* h, int l, const T* b, hipStream_t s, T* final_out
         }
         tp_cnn_attach* a = h->cnn.get();
         cnn_features_into<T>(a, r, a->feat.p, s);
-        cnn_forward_into<T>(a->net, a->g, a->feat.p, nullptr, cur, a->scale.p, a->bad.p, s);
+        cnn_forward_into<T>(a->net, a->g, a->feat.p, nullptr, cur, a->scale.p, a->bad.p, s, a->h.p);
         return cur;
     }
     if (p.nu_post > 0) cur = smooth<T>(h, l, b, cur, false, p.nu_post, s, final_out);
@@ -533,6 +533,7 @@ extern "C" int amg_presmoothed_pair(tp_amg_t amg, const double* y, double* r, do
 extern "C" int amg_attach_post_smoother(tp_amg_t amg, tp_cnn_t net, const tp_grid* grid) {
     TP_GUARD({
         TP_CHECK_ARG(amg, "amg_attach_post_smoother: null hierarchy");
+        ++amg->cnn_gen;  // a graph captured with the previous attachment is stale
         if (!net) {
             amg->cnn.reset();
             return TP_OK;

@@ -33,6 +33,10 @@ def bf16(a):
     return u.astype(np.uint32).view(np.float32)
 
 
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
 def dev(a, dtype=None):
     import torch
     return torch.as_tensor(np.ascontiguousarray(a), device="cuda", dtype=dtype)
@@ -144,6 +148,46 @@ def test_untrained_and_adversarial_networks_fall_back():
     assert res["learned"]["fallback_iter"] >= 0
     with pytest.raises(tps.TpError):
         tps.Net(np.full(tps.CNN_NPARAM, np.nan, dtype=np.float32))
+
+
+def test_learned_graph_replay_matches_eager():
+    """With the learned post-smoother attached, the preconditioner replayed from
+    its captured graph gives the same iterates, bit for bit, as eager launches;
+    after a new network is attached the graph is captured again (the results
+    follow the new network), and after detaching the plain graph is used."""
+    import torch
+    say("learned graph replay")
+    p = synth.make_problem("W4", seed=4001, grid=synth.Grid(24, 24, 24, 1, 1, 1))
+    d = solver.to_device(p)
+    J, G = solver.assemble(p, d)
+    cfg = solver.SolveConfig()
+    a_pp, a_S, M = solver.setup(J, cfg)
+    nets = [tps.Net(learned.init_params(3)), tps.Net(learned.init_params(5) * 3)]
+    scratch = torch.ones(128, 128, device="cuda", dtype=torch.float64)
+    seen = []
+    for net in nets + [None]:
+        a_S.attach(net, p.grid if net is not None else None)
+        runs = []
+        for graph in (False, True, True, False, True):
+            scratch = scratch @ scratch.t() / 128.0     # unrelated device work between solves
+            torch.cuda.synchronize()
+            x, st = tps.fgmres_solve(J, M, -G, rtol=1e-8, history=True, graph=graph)
+            torch.cuda.synchronize()
+            runs.append((np_(x), st))
+        x0, s0 = runs[0]
+        say(f"  its {s0['iters']} fallback {s0['fallback_iter']} rel {s0['rel_true']:.2e}")
+        assert s0["converged"] and s0["rel_true"] <= 1e-8
+        for x, st in runs[1:]:
+            assert st["iters"] == s0["iters"] and st["fallback_iter"] == s0["fallback_iter"]
+            assert np.array_equal(st["history"], s0["history"])
+            assert np.array_equal(x, x0)
+        seen.append(s0["history"])
+    # each attachment changes the iterates (a stale graph would repeat them)
+    assert not np.array_equal(seen[0][:3], seen[1][:3])
+    assert not np.array_equal(seen[1][:3], seen[2][:3])
+    for net in nets:
+        net.close()
+    M.close(); a_pp.close(); a_S.close()
 
 
 def test_operator_loss_gradient_matches_oracle():
