@@ -250,12 +250,15 @@ int amg_attach_post_smoother(tp_amg_t amg, tp_cnn_t net, const tp_grid* grid);
  * finest level of a hierarchy with an attached network; scale (host, optional). */
 int amg_features(tp_amg_t amg, const double* r, float* feat, float* scale, void* stream);
 /* Loss of the attached network measured in the D^{-1} A norm of the
- * hierarchy's finest-level operator A (D its l1 diagonal):
- * L = mean_i (D^{-1} A (out - target))_i^2 with out = network(feat); for
- * target = e/s this is the residual the correction leaves behind.  The
- * gradient is kept in the network handle for cnn_adam_step; loss (host) optional. */
-int amg_cnn_loss_grad(tp_amg_t amg, const float* feat, const float* target, double* loss,
-                      void* stream);
+ * hierarchy's finest-level operator A (D its l1 diagonal), plus an optional
+ * error term: L = mean_i (D^{-1} A (out - target))_i^2
+ *               + err_weight * mean_i (out - target)_i^2, out = network(feat);
+ * for target = e/s the first term is the residual the correction leaves
+ * behind and the second the error (err_weight >= 0, finite; 0 for the pure
+ * residual loss).  The gradient is kept in the network handle for
+ * cnn_adam_step; loss (host) optional. */
+int amg_cnn_loss_grad(tp_amg_t amg, const float* feat, const float* target, float err_weight,
+                      double* loss, void* stream);
 /* Training pair at the finest-level post-smoothing point: b = A y, one
  * V-cycle from a zero guess stopped before level-0 post-smoothing gives x;
  * r = b - A x and e = y - x (all n, device FP64). */

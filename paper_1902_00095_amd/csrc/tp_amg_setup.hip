@@ -424,24 +424,27 @@ k_spgemm_fill(const int32_t* __restrict__ rows, const int32_t* __restrict__ nrow
     }
 }
 
-// ---- short rows: 16 lanes per output row -------------------------------------------------
+// ---- short rows: a lane group per output row ---------------------------------------------
 // A row with at most SR_G entries whose products number at most SR_MAX is
 // expanded into LDS in A-entry-major order (inner index ascending, and within
 // it B's sorted columns).  A column's output position is the number of
 // distinct smaller columns; its value is the sum of its products in that
 // order, i.e. in ascending inner index, the order of the hash-table path.
-// Other rows are appended to a list for the hash-table kernels.
-constexpr int SR_G = 16;
-constexpr int SR_MAX = 128;
+// Other rows are appended to a list for the hash-table kernels. The per-lane
+// work grows with the square of the row's product count over SR_G, so
+// products with long rows (coarse levels, the Galerkin product) take 64-lane
+// groups with room for 256 products; the fine-level A P takes 16 lanes, 128
+// products. Both give the same values, in the same order.
 constexpr int SR_T = 256;
-constexpr int SR_ROWS = SR_T / SR_G;
 
+template <int SR_G, int SR_MAX>
 __global__ void __launch_bounds__(SR_T)
 k_spgemm_short(int32_t n, const int32_t* __restrict__ Arp, const int32_t* __restrict__ Ac,
                const double* __restrict__ Av, const int32_t* __restrict__ Brp, const int32_t* __restrict__ Bc,
                const double* __restrict__ Bv, int32_t* __restrict__ cnt, const int32_t* __restrict__ Crp,
                int32_t* __restrict__ Cc, double* __restrict__ Cv, int32_t* __restrict__ long_rows,
                int32_t* __restrict__ nlong, int32_t* __restrict__ gflag, int numeric) {
+    constexpr int SR_ROWS = SR_T / SR_G;
     __shared__ int32_t s_c[SR_ROWS][SR_MAX];
     __shared__ double s_v[SR_ROWS][SR_MAX];
     __shared__ int8_t s_first[SR_ROWS][SR_MAX];
@@ -531,11 +534,23 @@ static void spgemm(const Csr& A, const Csr& Bm, Csr& C, int32_t* flag, hipStream
     DBuf<int32_t> long_rows(std::max(A.n, 1), s), nlong(1, s);
     TP_LAUNCH(k_fill_i32, 1, B, 0, s, nlong.p, 0, (int64_t)1);
     const int grid = std::min<int>(std::max<int>(A.n, 1), 16384);
-    const int sgrid = cdiv(std::max(A.n, 1), SR_ROWS);
+    // products per output row, estimated from the operands' mean row lengths
+    // (host sizes: exact for level operators, upper bounds for P and R)
+    const double est = ((double)A.nnz / std::max(A.n, 1)) * ((double)Bm.nnz / std::max(Bm.n, 1));
+    const bool wide = est >= 64.0;
+    auto short_pass = [&](int32_t* cnt, const int32_t* crp, int32_t* cc, double* cv, int numeric) {
+        if (wide) {
+            TP_LAUNCH((k_spgemm_short<64, 256>), cdiv(A.n, SR_T / 64), SR_T, 0, s, A.n, A.rowptr.p, A.col.p,
+                      A.val.p, Bm.rowptr.p, Bm.col.p, Bm.val.p, cnt, crp, cc, cv, long_rows.p, nlong.p, flag,
+                      numeric);
+        } else {
+            TP_LAUNCH((k_spgemm_short<16, 128>), cdiv(A.n, SR_T / 16), SR_T, 0, s, A.n, A.rowptr.p, A.col.p,
+                      A.val.p, Bm.rowptr.p, Bm.col.p, Bm.val.p, cnt, crp, cc, cv, long_rows.p, nlong.p, flag,
+                      numeric);
+        }
+    };
     if (A.n > 0) {
-        TP_LAUNCH(k_spgemm_short, sgrid, SR_T, 0, s, A.n, A.rowptr.p, A.col.p, A.val.p, Bm.rowptr.p, Bm.col.p,
-                  Bm.val.p, C.rowptr.p, (const int32_t*)nullptr, (int32_t*)nullptr, (double*)nullptr,
-                  long_rows.p, nlong.p, flag, 0);
+        short_pass(C.rowptr.p, nullptr, nullptr, nullptr, 0);
         TP_LAUNCH(k_spgemm_count, grid, SG_WAVE, 0, s, (const int32_t*)long_rows.p, (const int32_t*)nlong.p,
                   A.rowptr.p, A.col.p, Bm.rowptr.p, Bm.col.p, C.rowptr.p, flag);
     }
@@ -548,9 +563,7 @@ static void spgemm(const Csr& A, const Csr& Bm, Csr& C, int32_t* flag, hipStream
     if (A.n > 0) {
         // the short pass lists the long rows again: start the list afresh
         TP_LAUNCH(k_fill_i32, 1, B, 0, s, nlong.p, 0, (int64_t)1);
-        TP_LAUNCH(k_spgemm_short, sgrid, SR_T, 0, s, A.n, A.rowptr.p, A.col.p, A.val.p, Bm.rowptr.p, Bm.col.p,
-                  Bm.val.p, (int32_t*)nullptr, (const int32_t*)C.rowptr.p, C.col.p, C.val.p, long_rows.p, nlong.p,
-                  flag, 1);
+        short_pass(nullptr, C.rowptr.p, C.col.p, C.val.p, 1);
         TP_LAUNCH(k_spgemm_fill, grid, SG_WAVE, 0, s, (const int32_t*)long_rows.p, (const int32_t*)nlong.p,
                   A.rowptr.p, A.col.p, A.val.p, Bm.rowptr.p, Bm.col.p, Bm.val.p, C.rowptr.p, C.col.p, C.val.p,
                   flag);
@@ -855,12 +868,12 @@ static double* gj_run(int32_t n, double* X, double* Y, double* T, int32_t* rowsr
 // factor and flags a column where the row would beat the pivot.  A flag sends
 // the whole inverse through the row-pivoted kernels instead, so the pivot
 // sequence is always the one partial pivoting would choose.
-constexpr int BG_NB = 32;
+constexpr int BG_NB = 64;
 
 // One workgroup inverts the pivot block in LDS (Gauss-Jordan with diagonal
-// pivots, recording the LU upper factor); thread t owns column t % 32 of rows
-// t / 32 + 8q.  Rows and columns past nb carry the identity and stay
-// untouched.
+// pivots, recording the LU upper factor); thread t owns column t % BG_NB of
+// rows t / BG_NB + (BK_T / BG_NB) q.  Rows and columns past nb carry the
+// identity and stay untouched.
 constexpr int BK_T = 1024;
 __global__ void __launch_bounds__(BK_T)
 k_bgj_block(int32_t n, int32_t k, const double* __restrict__ X, double* __restrict__ binv, double* __restrict__ U,
@@ -906,9 +919,9 @@ k_bgj_block(int32_t n, int32_t k, const double* __restrict__ X, double* __restri
     if (flag) *need_piv = 1;
 }
 
-// W = Binv on the block's rows and W = -X_iK Binv on the others (n x 32,
-// one thread per entry, a row's 32 entries in one half-wavefront).  The
-// same half-wavefront re-runs the forward elimination of a candidate row
+// W = Binv on the block's rows and W = -X_iK Binv on the others (n x BG_NB,
+// one thread per entry, a row's BG_NB entries in one wavefront).  The
+// same wavefront re-runs the forward elimination of a candidate row
 // below the block against the block's U (lanes hold the row's entries, the
 // pivot entry is broadcast by a shuffle) and flags a column where the row
 // would beat the pivot.

@@ -49,7 +49,7 @@ template <typename T>
 void cnn_features_into(tp_cnn_attach* a, const T* r, float* f, hipStream_t s);
 void cnn_backward_from_dout(tp_cnn* c, const tp_grid& g, const float* feat, hipStream_t s);
 void cnn_op_loss_grad(tp_cnn_attach* a, const int32_t* rowptr, const int32_t* col, const double* val,
-                      int32_t nnz, const float* feat, const float* target, hipStream_t s);
+                      int32_t nnz, const float* feat, const float* target, float err_weight, hipStream_t s);
 void transpose(const int32_t* rowptr, const int32_t* col, const double* val, int32_t n, int32_t m,
                int32_t nnz, bool sorted, Csr& T, hipStream_t s);
 void cnn_attach_build(tp_cnn_attach* a, const tp_grid& g, const int32_t* rowptr, const int32_t* col,

@@ -471,11 +471,12 @@ k_loss_sum(int nb, int32_t n, const double* __restrict__ part, double* __restric
 }
 
 // ---- loss in the D^{-1} A norm --------------------------------------------------------------
-// v = D^{-1} A (out - target); per-block partial sums of v^2; v overwritten by dL/dv = 2 v / n
+// v = D^{-1} A (out - target); per-block partial sums of v^2 + w (out - target)^2 (w: weight
+// of the error term); v overwritten by dL/dv = 2 v / n
 __global__ void __launch_bounds__(CB)
 k_op_forward(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
              const double* __restrict__ val, const float* __restrict__ dinv, const float* __restrict__ out,
-             const float* __restrict__ target, float* __restrict__ dv, double* __restrict__ part) {
+             const float* __restrict__ target, float w, float* __restrict__ dv, double* __restrict__ part) {
     __shared__ double sh[CB];
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * CB + threadIdx.x; i < n; i += (int64_t)gridDim.x * CB) {
@@ -485,7 +486,8 @@ k_op_forward(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
             s += val[k] * (double)(out[j] - target[j]);
         }
         const float v = (float)(s * (double)dinv[i]);
-        acc += (double)v * (double)v;
+        const float e = out[i] - target[i];
+        acc += (double)v * (double)v + (double)w * ((double)e * (double)e);
         dv[i] = 2.f * v / (float)n;
     }
     sh[threadIdx.x] = acc;
@@ -497,10 +499,11 @@ k_op_forward(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-// dout = A^T (D^{-1} dv), with A^T given explicitly (sorted CSR)
+// dout = A^T (D^{-1} dv) + 2 w (out - target) / n, with A^T given explicitly (sorted CSR)
 __global__ void __launch_bounds__(CB)
 k_op_backward(int32_t n, const int32_t* __restrict__ trp, const int32_t* __restrict__ tcol,
               const double* __restrict__ tval, const float* __restrict__ dinv, const float* __restrict__ dv,
+              const float* __restrict__ out, const float* __restrict__ target, float w,
               float* __restrict__ dout) {
     const int32_t j = blockIdx.x * CB + threadIdx.x;
     if (j >= n) return;
@@ -509,6 +512,7 @@ k_op_backward(int32_t n, const int32_t* __restrict__ trp, const int32_t* __restr
         const int32_t i = tcol[k];
         s += tval[k] * (double)(dinv[i] * dv[i]);
     }
+    if (w != 0.f) s += (double)(2.f * w * (out[j] - target[j]) / (float)n);
     dout[j] = (float)s;
 }
 
@@ -573,7 +577,7 @@ void cnn_backward_from_dout(tp_cnn* c, const tp_grid& g, const float* feat, hipS
 
 // loss in the D^{-1} A norm of the attached finest level (A^T built on first use)
 void cnn_op_loss_grad(tp_cnn_attach* a, const int32_t* rowptr, const int32_t* col, const double* val,
-                      int32_t nnz, const float* feat, const float* target, hipStream_t s) {
+                      int32_t nnz, const float* feat, const float* target, float err_weight, hipStream_t s) {
     tp_cnn* c = a->net;
     const tp_grid& g = a->g;
     const int32_t n = g.nx * g.ny * g.nz;
@@ -581,10 +585,11 @@ void cnn_op_loss_grad(tp_cnn_attach* a, const int32_t* rowptr, const int32_t* co
     cnn_work_reserve(c, n, s);
     cnn_forward_into<float>(c, g, feat, c->out.p, nullptr, nullptr, nullptr, s);
     const int nb = red_blocks(n);
-    TP_LAUNCH(k_op_forward, nb, CB, 0, s, n, rowptr, col, val, a->dinv.p, c->out.p, target, c->dh.p, c->part.p);
+    TP_LAUNCH(k_op_forward, nb, CB, 0, s, n, rowptr, col, val, a->dinv.p, c->out.p, target, err_weight, c->dh.p,
+              c->part.p);
     TP_LAUNCH(k_loss_sum, 1, CB, 0, s, nb, n, c->part.p, c->loss.p);
     TP_LAUNCH(k_op_backward, cdiv(n, CB), CB, 0, s, n, a->At.rowptr.p, a->At.col.p, a->At.val.p, a->dinv.p,
-              c->dh.p, c->dout.p);
+              c->dh.p, c->out.p, target, err_weight, c->dout.p);
     cnn_backward_from_dout(c, g, feat, s);
 }
 

@@ -573,14 +573,16 @@ extern "C" int amg_features(tp_amg_t amg, const double* r, float* feat, float* s
     return TP_OK;
 }
 
-extern "C" int amg_cnn_loss_grad(tp_amg_t amg, const float* feat, const float* target, double* loss,
-                                 void* stream) {
+extern "C" int amg_cnn_loss_grad(tp_amg_t amg, const float* feat, const float* target, float err_weight,
+                                 double* loss, void* stream) {
     TP_GUARD({
         TP_CHECK_ARG(amg && feat && target, "amg_cnn_loss_grad: null argument");
         TP_CHECK_ARG(amg->cnn, "amg_cnn_loss_grad: no network attached");
+        TP_CHECK_ARG(err_weight >= 0.f && std::isfinite(err_weight), "amg_cnn_loss_grad: err_weight must be finite and >= 0");
         hipStream_t s = (hipStream_t)stream;
         const tp::Level& L = amg->lev[0];
-        tp::cnn_op_loss_grad(amg->cnn.get(), L.A.rowptr.p, L.A.col.p, L.A.val.p, L.A.nnz, feat, target, s);
+        tp::cnn_op_loss_grad(amg->cnn.get(), L.A.rowptr.p, L.A.col.p, L.A.val.p, L.A.nnz, feat, target, err_weight,
+                             s);
         if (loss) {
             TP_HIP(hipMemcpyAsync(loss, amg->cnn->net->loss.p, sizeof(double), hipMemcpyDeviceToHost, s));
             TP_HIP(hipStreamSynchronize(s));

@@ -78,19 +78,20 @@ def make_pairs(seeds, grid, net=None, per_field=1, workload="W4", smooth_y=0):
     return out
 
 
-def sample_loss(net, smp, loss="op"):
+def sample_loss(net, smp, loss="op", err_weight=0.0):
     """Operator-norm loss ||D^{-1} S (out - e/s)||^2 / n (the residual the
-    correction leaves) or the Euclidean error loss ||out - e/s||^2 / n."""
+    correction leaves) plus err_weight ||out - e/s||^2 / n, or the Euclidean
+    error loss ||out - e/s||^2 / n alone."""
     if loss == "op":
-        return smp.amg.op_loss_grad(smp.feat, smp.target)
+        return smp.amg.op_loss_grad(smp.feat, smp.target, err_weight)
     return net.loss_grad(smp.grid, smp.feat, smp.target)
 
 
-def train(net, samples, steps, lr=1e-3, log_every=0, loss="op"):
+def train(net, samples, steps, lr=1e-3, log_every=0, loss="op", err_weight=0.0):
     losses = []
     for it in range(steps):
         smp = samples[it % len(samples)]
-        loss_v = sample_loss(net, smp, loss)
+        loss_v = sample_loss(net, smp, loss, err_weight)
         net.adam_step(lr)
         losses.append(loss_v)
         if log_every and (it % log_every == 0 or it == steps - 1):
@@ -98,8 +99,8 @@ def train(net, samples, steps, lr=1e-3, log_every=0, loss="op"):
     return np.asarray(losses)
 
 
-def eval_loss(net, samples, loss="op"):
-    return float(np.mean([sample_loss(net, s, loss) for s in samples]))
+def eval_loss(net, samples, loss="op", err_weight=0.0):
+    return float(np.mean([sample_loss(net, s, loss, err_weight) for s in samples]))
 
 
 def compare(net, prob, cfg=None, stag_ratio=0.95):

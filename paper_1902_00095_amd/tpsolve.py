@@ -357,10 +357,12 @@ class AMG:
         _check(_lib.amg_features(self.h, _ptr(r), _ptr(feat), C.byref(s), _stream(stream)))
         return feat, s.value
 
-    def op_loss_grad(self, feat, target, stream=None):
-        """Loss of the attached network in the D^{-1} A norm (gradient kept for Adam)."""
+    def op_loss_grad(self, feat, target, err_weight=0.0, stream=None):
+        """Loss of the attached network in the D^{-1} A norm, plus err_weight
+        times the mean squared error (gradient kept for Adam)."""
         loss = C.c_double()
-        _check(_lib.amg_cnn_loss_grad(self.h, _ptr(feat), _ptr(target), C.byref(loss), _stream(stream)))
+        _check(_lib.amg_cnn_loss_grad(self.h, _ptr(feat), _ptr(target), C.c_float(err_weight), C.byref(loss),
+                                      _stream(stream)))
         return loss.value
 
     def presmoothed_pair(self, y, stream=None):

@@ -190,12 +190,14 @@ def test_learned_graph_replay_matches_eager():
     M.close(); a_pp.close(); a_S.close()
 
 
-def test_operator_loss_gradient_matches_oracle():
-    """Gradient of L = mean((D^{-1} S (out - t))^2) on the GPU against
-    central differences of the same loss built from the oracle's FP64
-    forward pass and the oracle Jacobian, at the BF16-rounded weights."""
+@pytest.mark.parametrize("ew", [0.0, 0.5])
+def test_operator_loss_gradient_matches_oracle(ew):
+    """Gradient of L = mean((D^{-1} S (out - t))^2) + ew mean((out - t)^2) on
+    the GPU against central differences of the same loss built from the
+    oracle's FP64 forward pass and the oracle Jacobian, at the BF16-rounded
+    weights."""
     import scipy.sparse as sp
-    say("operator loss gradient")
+    say("operator loss gradient", ew)
     p = synth.make_problem("W4", seed=1001, grid=synth.Grid(10, 9, 8, 1, 1, 1))
     d = solver.to_device(p)
     J, G = solver.assemble(p, d)
@@ -205,7 +207,7 @@ def test_operator_loss_gradient_matches_oracle():
     a_S = learned.schur_hierarchy(J, coarse_max=64)   # keep the tiny grid multi-level
     a_S.attach(net, p.grid)
     t = np.random.default_rng(8).standard_normal(g.n).astype(np.float32)
-    loss = a_S.op_loss_grad(dev(f.reshape(-1)), dev(t))
+    loss = a_S.op_loss_grad(dev(f.reshape(-1)), dev(t), ew)
     gg = net.grad().astype(np.float64)
     Jo = oracle.jacobian(p)
     A = sp.csr_matrix((Jo.S, Jo.col, Jo.rowptr))
@@ -215,8 +217,9 @@ def test_operator_loss_gradient_matches_oracle():
 
     def L(theta):
         out, _ = oracle.cnn_forward(g, theta, f64)
-        v = Dinv * (A @ (out - t.astype(np.float64)))
-        return float(np.mean(v * v))
+        e = out - t.astype(np.float64)
+        v = Dinv * (A @ e)
+        return float(np.mean(v * v) + ew * np.mean(e * e))
 
     assert abs(loss - L(th64)) <= 1e-4 * L(th64)
     scale = np.abs(gg).max()
