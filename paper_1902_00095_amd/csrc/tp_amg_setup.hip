@@ -119,6 +119,174 @@ k_sort_rows(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __rest
     }
 }
 
+// ---- one wavefront per row (levels with long rows) ---------------------------------------
+// On coarse levels rows hold tens of entries and the levels have few rows, so a
+// thread per row walks a long dependent chain of loads with little parallelism.
+// These variants give each row a 64-lane wavefront: entries are loaded
+// lane-parallel; a floating-point sum is still taken in row order (each entry's
+// term is broadcast to the wavefront in turn, all lanes adding the same
+// sequence), and outputs are compacted in row order by ballot, so the results
+// equal the thread-per-row kernels' bit for bit.
+constexpr int WR = 64;
+constexpr int WR_ROWS = B / WR;
+constexpr double WR_MIN_AVG = 24.0;  // mean row length from which a level uses them
+
+__device__ inline int below_count(uint64_t mask, int lane) {
+    return __popcll(mask & ((1ull << lane) - 1ull));
+}
+
+__device__ inline void row_sign_max_w(const int32_t* rowptr, const int32_t* col, const double* val, int32_t i,
+                                      int lane, double* s_out, double* m_out) {
+    const int32_t a = rowptr[i], e = rowptr[i + 1];
+    double aii = 0.0;
+    bool has = false;
+    for (int32_t q = a + lane; q < e; q += WR)
+        if (col[q] == i) { aii = val[q]; has = true; }
+    const uint64_t hm = __ballot(has);
+    aii = hm ? __shfl(aii, __ffsll((unsigned long long)hm) - 1, WR) : 0.0;
+    const double s = aii < 0.0 ? -1.0 : 1.0;
+    double m = 0.0;
+    for (int32_t q = a + lane; q < e; q += WR)
+        if (col[q] != i && -s * val[q] > m) m = -s * val[q];
+#pragma unroll
+    for (int d = WR / 2; d > 0; d >>= 1) m = fmax(m, __shfl_xor(m, d, WR));
+    *s_out = s;
+    *m_out = m;
+}
+
+__global__ void __launch_bounds__(B)
+k_strength_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+             const double* __restrict__ val, double theta, int32_t* __restrict__ cnt,
+             const int32_t* __restrict__ Srowptr, int32_t* __restrict__ Scol) {
+    const int32_t i = blockIdx.x * WR_ROWS + threadIdx.x / WR;
+    const int lane = threadIdx.x % WR;
+    if (i >= n) return;  // whole wavefront
+    double s, m;
+    row_sign_max_w(rowptr, col, val, i, lane, &s, &m);
+    int32_t c = 0;
+    const int32_t out = Scol ? Srowptr[i] : 0;
+    if (m > 0.0) {
+        for (int32_t b = rowptr[i]; b < rowptr[i + 1]; b += WR) {
+            const int32_t q = b + lane;
+            const bool strong = q < rowptr[i + 1] && col[q] != i && -s * val[q] >= theta * m;
+            const uint64_t mk = __ballot(strong);
+            if (Scol && strong) Scol[out + c + below_count(mk, lane)] = col[q];
+            c += __popcll(mk);
+        }
+    }
+    if (cnt && lane == 0) cnt[i] = c;
+}
+
+__global__ void __launch_bounds__(B)
+k_interp_count_w(int32_t n, const int32_t* __restrict__ Srp, const int32_t* __restrict__ Sc,
+                 const int32_t* __restrict__ cf, int32_t* __restrict__ cnt) {
+    const int32_t i = blockIdx.x * WR_ROWS + threadIdx.x / WR;
+    const int lane = threadIdx.x % WR;
+    if (i >= n) return;
+    int32_t c = 0;
+    for (int32_t q = Srp[i] + lane; q < Srp[i + 1]; q += WR) c += cf[Sc[q]];
+#pragma unroll
+    for (int d = WR / 2; d > 0; d >>= 1) c += __shfl_xor(c, d, WR);
+    if (lane == 0) cnt[i] = cf[i] ? 1 : c;
+}
+
+// is j among the sorted strong columns Sc[a, e)?
+__device__ inline bool in_sorted(const int32_t* Sc, int32_t a, int32_t e, int32_t j) {
+    int32_t lo = a, hi = e;  // first position in [a, e) whose column is >= j
+    while (lo < hi) {
+        const int32_t mid = lo + (hi - lo) / 2;
+        if (Sc[mid] < j) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < e && Sc[lo] == j;
+}
+
+__global__ void __launch_bounds__(B)
+k_interp_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                const double* __restrict__ val, const int32_t* __restrict__ Srp,
+                const int32_t* __restrict__ Sc, const int32_t* __restrict__ cf,
+                const int32_t* __restrict__ cmap, const int32_t* __restrict__ Prp,
+                int32_t* __restrict__ Pc, double* __restrict__ Pv) {
+    const int32_t i = blockIdx.x * WR_ROWS + threadIdx.x / WR;
+    const int lane = threadIdx.x % WR;
+    if (i >= n) return;
+    const int32_t q0 = Prp[i];
+    if (cf[i]) {
+        if (lane == 0) { Pc[q0] = cmap[i]; Pv[q0] = 1.0; }
+        return;
+    }
+    if (Prp[i + 1] == q0) return;  // no strong C neighbour: empty row
+    const int32_t a = rowptr[i], e = rowptr[i + 1], sa = Srp[i], se = Srp[i + 1];
+    double aii = 0.0;
+    bool has = false;
+    for (int32_t q = a + lane; q < e; q += WR)
+        if (col[q] == i) { aii = val[q]; has = true; }
+    const uint64_t hm = __ballot(has);
+    aii = hm ? __shfl(aii, __ffsll((unsigned long long)hm) - 1, WR) : 0.0;
+    const double s = aii < 0.0 ? -1.0 : 1.0;
+    // the three sums in row order, exactly as one thread would take them
+    double sum_all = 0.0, lump = 0.0, sum_p = 0.0;
+    for (int32_t b = a; b < e; b += WR) {
+        const int32_t q = b + lane;
+        const bool ok = q < e;
+        const int32_t j = ok ? col[q] : -1;
+        const double v = ok ? val[q] : 0.0;
+        const bool sc = ok && j != i && cf[j] && in_sorted(Sc, sa, se, j);
+        const uint64_t scm = __ballot(sc);
+        const int len = min(WR, (int)(e - b));
+        for (int l = 0; l < len; ++l) {
+            const int32_t jl = __shfl(j, l, WR);
+            const double vl = __shfl(v, l, WR);
+            if (jl != i) {
+                if (s * vl < 0.0) sum_all += vl;
+                else lump += vl;
+            }
+            if ((scm >> l) & 1ull) sum_p += vl;
+        }
+    }
+    const double alpha = sum_all / sum_p;
+    const double dtil = aii + lump;
+    int32_t c = 0;
+    for (int32_t b = a; b < e; b += WR) {
+        const int32_t q = b + lane;
+        const bool ok = q < e;
+        const int32_t j = ok ? col[q] : -1;
+        const bool sc = ok && j != i && cf[j] && in_sorted(Sc, sa, se, j);
+        const uint64_t scm = __ballot(sc);
+        if (sc) {
+            const int32_t pos = q0 + c + below_count(scm, lane);
+            Pc[pos] = cmap[j];
+            Pv[pos] = -(alpha * val[q]) / dtil;
+        }
+        c += __popcll(scm);
+    }
+}
+
+__global__ void __launch_bounds__(B)
+k_col_count_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+              int32_t* __restrict__ cnt) {
+    const int32_t i = blockIdx.x * WR_ROWS + threadIdx.x / WR;
+    const int lane = threadIdx.x % WR;
+    if (i >= n) return;
+    for (int32_t q = rowptr[i] + lane; q < rowptr[i + 1]; q += WR) atomicAdd(&cnt[col[q]], 1);
+}
+
+__global__ void __launch_bounds__(B)
+k_transpose_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                   const double* __restrict__ val, int32_t* __restrict__ cursor,
+                   int32_t* __restrict__ Tcol, double* __restrict__ Tval) {
+    const int32_t i = blockIdx.x * WR_ROWS + threadIdx.x / WR;
+    const int lane = threadIdx.x % WR;
+    if (i >= n) return;
+    for (int32_t q = rowptr[i] + lane; q < rowptr[i + 1]; q += WR) {
+        const int32_t pos = atomicAdd(&cursor[col[q]], 1);
+        Tcol[pos] = i;
+        if (Tval) Tval[pos] = val[q];
+    }
+}
+
+static bool long_rows(int32_t n, int32_t nnz) { return n > 0 && (double)nnz / n >= WR_MIN_AVG; }
+
 // T = A^T (m rows); values optional; rows sorted when `sorted`.  nnz is the
 // entry count or an upper bound of it: it only sizes the allocations (the
 // counts come from rowptr), and T.nnz keeps the value passed.
@@ -132,18 +300,25 @@ void transpose(const int32_t* rowptr, const int32_t* col, const double* val, int
     if (val) T.val.alloc(nnz, s);
     DBuf<int32_t> cursor(m + 1, s);
     TP_LAUNCH(k_fill_i32, cdiv(m + 1, B), B, 0, s, T.rowptr.p, 0, (int64_t)m + 1);
-    if (n > 0) TP_LAUNCH(k_col_count, cdiv(n, B), B, 0, s, n, rowptr, col, T.rowptr.p);
+    const bool w = long_rows(n, nnz);
+    if (n > 0) {
+        if (w) TP_LAUNCH(k_col_count_w, cdiv(n, WR_ROWS), B, 0, s, n, rowptr, col, T.rowptr.p);
+        else TP_LAUNCH(k_col_count, cdiv(n, B), B, 0, s, n, rowptr, col, T.rowptr.p);
+    }
+    auto fill = [&](int32_t* tc, double* tv) {
+        if (n == 0) return;
+        if (w) TP_LAUNCH(k_transpose_fill_w, cdiv(n, WR_ROWS), B, 0, s, n, rowptr, col, val, cursor.p, tc, tv);
+        else TP_LAUNCH(k_transpose_fill, cdiv(n, B), B, 0, s, n, rowptr, col, val, cursor.p, tc, tv);
+    };
     scan_exclusive(T.rowptr.p, T.rowptr.p, m, s);
     TP_HIP(hipMemcpyAsync(cursor.p, T.rowptr.p, sizeof(int32_t) * (m + 1), hipMemcpyDeviceToDevice, s));
     if (!sorted) {
-        if (n > 0) TP_LAUNCH(k_transpose_fill, cdiv(n, B), B, 0, s, n, rowptr, col, val, cursor.p, T.col.p,
-                             val ? T.val.p : nullptr);
+        fill(T.col.p, val ? T.val.p : nullptr);
         return;
     }
     DBuf<int32_t> tcol(nnz, s);
     DBuf<double> tval(val ? nnz : 0, s);
-    if (n > 0) TP_LAUNCH(k_transpose_fill, cdiv(n, B), B, 0, s, n, rowptr, col, val, cursor.p, tcol.p,
-                         val ? tval.p : nullptr);
+    fill(tcol.p, val ? tval.p : nullptr);
     if (m > 0)
         TP_LAUNCH(k_sort_rows, std::min(m, 65536), 64, 0, s, m, T.rowptr.p, tcol.p,
                   val ? tval.p : nullptr, T.col.p, val ? T.val.p : nullptr);
@@ -868,7 +1043,7 @@ static double* gj_run(int32_t n, double* X, double* Y, double* T, int32_t* rowsr
 // factor and flags a column where the row would beat the pivot.  A flag sends
 // the whole inverse through the row-pivoted kernels instead, so the pivot
 // sequence is always the one partial pivoting would choose.
-constexpr int BG_NB = 64;
+constexpr int BG_NB = 32;
 
 // One workgroup inverts the pivot block in LDS (Gauss-Jordan with diagonal
 // pivots, recording the LU upper factor); thread t owns column t % BG_NB of
@@ -1090,15 +1265,18 @@ static void copy_csr_in(Csr& A, int32_t n, const int32_t* rowptr, const int32_t*
 static void strength(const Csr& A, double theta, Csr& S, hipStream_t s) {
     S.n = S.m = A.n;
     S.rowptr.alloc(A.n + 1, s);
-    if (A.n > 0)
-        TP_LAUNCH(k_strength, cdiv(A.n, B), B, 0, s, A.n, A.rowptr.p, A.col.p, A.val.p, theta, S.rowptr.p,
-                  (const int32_t*)nullptr, (int32_t*)nullptr);
+    const bool w = long_rows(A.n, A.nnz);
+    auto pass = [&](int32_t* cnt, const int32_t* srp, int32_t* scol) {
+        if (A.n == 0) return;
+        if (w) TP_LAUNCH(k_strength_w, cdiv(A.n, WR_ROWS), B, 0, s, A.n, A.rowptr.p, A.col.p, A.val.p, theta, cnt,
+                         srp, scol);
+        else TP_LAUNCH(k_strength, cdiv(A.n, B), B, 0, s, A.n, A.rowptr.p, A.col.p, A.val.p, theta, cnt, srp, scol);
+    };
+    pass(S.rowptr.p, nullptr, nullptr);
     scan_exclusive(S.rowptr.p, S.rowptr.p, A.n, s);
     S.nnz = A.nnz;  // an upper bound (S is a subset of A's pattern): no host read
     S.col.alloc(S.nnz, s);
-    if (A.n > 0)
-        TP_LAUNCH(k_strength, cdiv(A.n, B), B, 0, s, A.n, A.rowptr.p, A.col.p, A.val.p, theta,
-                  (int32_t*)nullptr, S.rowptr.p, S.col.p);
+    pass(nullptr, S.rowptr.p, S.col.p);
 }
 
 static void direct_interp(const Csr& A, const Csr& S, const int32_t* cf, const int32_t* cmap, int32_t nc,
@@ -1106,16 +1284,23 @@ static void direct_interp(const Csr& A, const Csr& S, const int32_t* cf, const i
     P.n = A.n;
     P.m = nc;
     P.rowptr.alloc(A.n + 1, s);
-    if (A.n > 0) TP_LAUNCH(k_interp_count, cdiv(A.n, B), B, 0, s, A.n, S.rowptr.p, S.col.p, cf, P.rowptr.p);
+    const bool w = long_rows(A.n, A.nnz);
+    if (A.n > 0) {
+        if (w) TP_LAUNCH(k_interp_count_w, cdiv(A.n, WR_ROWS), B, 0, s, A.n, S.rowptr.p, S.col.p, cf, P.rowptr.p);
+        else TP_LAUNCH(k_interp_count, cdiv(A.n, B), B, 0, s, A.n, S.rowptr.p, S.col.p, cf, P.rowptr.p);
+    }
     scan_exclusive(P.rowptr.p, P.rowptr.p, A.n, s);
     // an upper bound (an F row interpolates from its strong C neighbours, a
     // C row has one entry); the exact count is read once at the end of setup
     P.nnz = A.nnz;
     P.col.alloc(P.nnz, s);
     P.val.alloc(P.nnz, s);
-    if (A.n > 0)
-        TP_LAUNCH(k_interp_fill, cdiv(A.n, B), B, 0, s, A.n, A.rowptr.p, A.col.p, A.val.p, S.rowptr.p,
-                  S.col.p, cf, cmap, P.rowptr.p, P.col.p, P.val.p);
+    if (A.n > 0) {
+        if (w) TP_LAUNCH(k_interp_fill_w, cdiv(A.n, WR_ROWS), B, 0, s, A.n, A.rowptr.p, A.col.p, A.val.p,
+                         S.rowptr.p, S.col.p, cf, cmap, P.rowptr.p, P.col.p, P.val.p);
+        else TP_LAUNCH(k_interp_fill, cdiv(A.n, B), B, 0, s, A.n, A.rowptr.p, A.col.p, A.val.p, S.rowptr.p,
+                       S.col.p, cf, cmap, P.rowptr.p, P.col.p, P.val.p);
+    }
 }
 
 static void make_f32(DBuf<float>& dst, const DBuf<double>& src, size_t n, hipStream_t s) {
@@ -1288,9 +1473,9 @@ static void setup(tp_amg* h, int32_t n, const int32_t* rowptr, const int32_t* co
         // Rounds are idempotent once every point is decided, so the host
         // reads the undecided count only after every third round.
         int round = 0;
+        TP_LAUNCH(k_fill_i32, 2, B, 0, s, undecided.p, 0, (int64_t)512);  // one counter per round
         for (;; ++round) {
             if (round >= 510) fail(TP_ERR_NUMERIC, "PMIS did not finish in 510 rounds");
-            TP_LAUNCH(k_fill_i32, 1, B, 0, s, undecided.p + round, 0, (int64_t)1);
             TP_LAUNCH(k_pmis_select, cdiv(A.n, B), B, 0, s, A.n, hseed, S.rowptr.p, S.col.p, ST.rowptr.p,
                       ST.col.p, st.p, st2.p);
             TP_LAUNCH(k_pmis_fmark, cdiv(A.n, B), B, 0, s, A.n, S.rowptr.p, S.col.p, st2.p,

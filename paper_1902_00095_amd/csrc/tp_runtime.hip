@@ -219,7 +219,58 @@ k_scan_add(int32_t* __restrict__ out, const int32_t* __restrict__ sums, int32_t 
         if (base + k < n) out[base + k] += add;
 }
 
+// Up to 16384 entries: one workgroup (1024 threads x 16 consecutive items;
+// wavefront scans by shuffles, then the 16 wavefront totals), one launch
+// instead of three. Every thread reads its items before the first barrier and
+// writes after it, so in-place use is safe.
+constexpr int SS_T = 1024;
+constexpr int SS_ITEMS = 16;
+constexpr int SS_MAX = SS_T * SS_ITEMS;
+
+__global__ void __launch_bounds__(SS_T)
+k_scan_small(const int32_t* in, int32_t* out, int32_t n) {
+    __shared__ int32_t wsum[SS_T / 64];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int32_t base = t * SS_ITEMS;
+    int32_t v[SS_ITEMS];
+    int32_t local = 0;
+#pragma unroll
+    for (int k = 0; k < SS_ITEMS; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0;
+        local += v[k];
+    }
+    int32_t x = local;  // inclusive scan over the wavefront
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    if (w == 0) {
+        int32_t y = lane < SS_T / 64 ? wsum[lane] : 0;
+#pragma unroll
+        for (int d = 1; d < SS_T / 64; d <<= 1) {
+            const int32_t z = __shfl_up(y, d, 64);
+            if (lane >= d) y += z;
+        }
+        if (lane < SS_T / 64) wsum[lane] = y;
+    }
+    __syncthreads();
+    int32_t ex = (w > 0 ? wsum[w - 1] : 0) + x - local;
+#pragma unroll
+    for (int k = 0; k < SS_ITEMS; ++k) {
+        if (base + k < n) out[base + k] = ex;
+        ex += v[k];
+    }
+    if (t == 0) out[n] = wsum[SS_T / 64 - 1];
+}
+
 void scan_exclusive(const int32_t* in, int32_t* out, int32_t n, hipStream_t s) {
+    if (n <= SS_MAX) {
+        TP_LAUNCH(k_scan_small, 1, SS_T, 0, s, in, out, n);
+        return;
+    }
     int ntiles = n > 0 ? cdiv(n, SCAN_TILE) : 1;
     DBuf<int32_t> sums(ntiles, s);
     if (n > 0) TP_LAUNCH(k_scan_tiles, ntiles, SCAN_BLOCK, 0, s, in, out, sums.p, n);
