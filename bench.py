@@ -114,19 +114,25 @@ def run_variants(prob, dev, cfg, iters64, ms64):
     r64, x64 = _time_solves(prob, dev, cfg, 2)
     r32, x32 = _time_solves(prob, dev, dc.replace(cfg, storage=1), 2)
     r32["err_vs_fp64_per_block"] = _block_err(x32, x64)
+    r16, x16 = _time_solves(prob, dev, dc.replace(cfg, storage=2), 2)
+    r16["err_vs_fp64_per_block"] = _block_err(x16, x64)
     out["fp64"] = r64
     out["fp32_hierarchy"] = r32
+    out["bf16_offdiag_hierarchy"] = r16
     # 128x128x64 (2.1M unknowns): FP64 and FP32 hierarchy, V-cycle throughput
     p3 = synth.make_problem("W3")
     d3 = solver.to_device(p3)
     w64, y64 = _time_solves(p3, d3, cfg, 2)
     w32, y32 = _time_solves(p3, d3, dc.replace(cfg, storage=1), 2)
     w32["err_vs_fp64_per_block"] = _block_err(y32, y64)
+    w16, y16 = _time_solves(p3, d3, dc.replace(cfg, storage=2), 2)
+    w16["err_vs_fp64_per_block"] = _block_err(y16, y64)
     w64.update(_apply_numbers(p3, d3, cfg))
     w32.update(_apply_numbers(p3, d3, dc.replace(cfg, storage=1)))
-    out["W3_128x128x64"] = {"fp64": w64, "fp32_hierarchy": w32,
+    w16.update(_apply_numbers(p3, d3, dc.replace(cfg, storage=2)))
+    out["W3_128x128x64"] = {"fp64": w64, "fp32_hierarchy": w32, "bf16_offdiag_hierarchy": w16,
                             "note": "FP32 error is against the FP64 GPU solution at the same rtol"}
-    del d3, y64, y32
+    del d3, y64, y32, y16
     # learned post-smoother: train (operator-norm loss) on seeded W4-recipe fields
     t0 = time.perf_counter()
     g_train = synth.Grid(24, 24, 24, 1.0, 1.0, 1.0)

@@ -125,7 +125,9 @@ typedef struct {
     double omega;          /* l1-Jacobi weight; 1.0 */
     int32_t nu_pre, nu_post; /* sweeps; 1, 1 */
     int32_t restriction;   /* 0 R = P^T; 1 R = Q^T, Q direct interpolation of A^T */
-    int32_t storage;       /* 0 FP64; 1 FP32 (values and V-cycle vectors) */
+    int32_t storage;       /* 0 FP64; 1 FP32 (values and V-cycle vectors); 2 FP32 vectors,
+                              P, R and level-operator diagonal, level-operator
+                              off-diagonal entries in BF16 (round to nearest even) */
     int32_t cheb_degree_coarse; /* Chebyshev degree on levels >= 1, 0..16 (0: cheb_degree); 1 */
 } tp_amg_params;
 

@@ -15,7 +15,11 @@ struct Level {
     Csr A, P, R;          // FP64 setup results (P, R empty on the coarsest level)
     DBuf<int32_t> cf;     // 1 C, 0 F
     DBuf<double> dinv;    // 1 / sum_j |a_ij|
-    DBuf<float> A32, P32, R32, dinv32;  // storage == 1 copies
+    DBuf<float> A32, P32, R32, dinv32;  // storage 1 copies (storage 2: P32, R32, dinv32)
+    // storage 2: BF16 values of A with the diagonal entries stored as 0 (CSR
+    // and DIA layouts) and the diagonal itself in FP32
+    DBuf<uint16_t> A16, dia16;
+    DBuf<float> diag32;
     int gA = 1, gP = 1, gR = 1;
     // Diagonal (DIA) copy of A when its column offsets form a small set
     // (stencil levels): dia[d * n + i] = a(i, i + off[d]), zero outside.
@@ -49,5 +53,5 @@ namespace tp {
 // write there, else one of the level's work vectors.
 const void* vcycle_run(tp_amg* h, const void* b_ext, hipStream_t s, void* x_ext = nullptr);
 // element size of the hierarchy's storage
-inline size_t storage_bytes(const tp_amg* h) { return h->prm.storage == 1 ? 4 : 8; }
+inline size_t storage_bytes(const tp_amg* h) { return h->prm.storage == 0 ? 8 : 4; }
 }  // namespace tp

@@ -129,7 +129,7 @@ k_sort_rows(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __rest
 // equal the thread-per-row kernels' bit for bit.
 constexpr int WR = 64;
 constexpr int WR_ROWS = B / WR;
-constexpr double WR_MIN_AVG = 24.0;  // mean row length from which a level uses them
+constexpr double WR_MIN_AVG = 10.0;  // mean row length from which a level uses them
 
 __device__ inline int below_count(uint64_t mask, int lane) {
     return __popcll(mask & ((1ull << lane) - 1ull));
@@ -762,6 +762,34 @@ k_to_f32(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
     if (i < n) b[i] = (float)a[i];
 }
 
+// storage 2: off-diagonal entries to BF16 (through FP32, round to nearest
+// even), the diagonal entry stored as 0 and kept in FP32 in diag
+__global__ void __launch_bounds__(B)
+k_split_bf16_csr(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                 const double* __restrict__ val, __bf16* __restrict__ a16, float* __restrict__ diag) {
+    const int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n) return;
+    float dg = 0.f;
+    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+        const float v = (float)val[q];
+        if (col[q] == i) {
+            dg = v;
+            a16[q] = (__bf16)0.f;
+        } else {
+            a16[q] = (__bf16)v;
+        }
+    }
+    diag[i] = dg;
+}
+
+// the same for the DIA copy: diagonal d0 (offset 0) stored as 0
+__global__ void __launch_bounds__(B)
+k_split_bf16_dia(int64_t total, int32_t n, int d0, const double* __restrict__ dia, __bf16* __restrict__ d16) {
+    const int64_t e = (int64_t)blockIdx.x * B + threadIdx.x;
+    if (e >= total) return;
+    d16[e] = (e / n == d0) ? (__bf16)0.f : (__bf16)(float)dia[e];
+}
+
 // ---- coarsest level: explicit inverse by blocked Gauss-Jordan elimination --------------
 // The inverse is formed with partial (row) pivoting, NB columns at a time.
 // For the panel K = [k, k+NB) with pivot rows B (after interchanges) and the
@@ -1390,6 +1418,13 @@ static void try_dia(tp_amg* h, Level& L, hipStream_t s) {
     if (h->prm.storage == 1) {
         L.dia32.alloc((size_t)nd * n, s);
         TP_LAUNCH(k_to_f32, cdiv((int64_t)nd * n, B), B, 0, s, (int64_t)nd * n, L.dia.p, L.dia32.p);
+    } else if (h->prm.storage == 2) {
+        int d0 = -1;
+        for (int d = 0; d < nd; ++d)
+            if (L.dia_off[d] == 0) d0 = d;
+        L.dia16.alloc((size_t)nd * n, s);
+        TP_LAUNCH(k_split_bf16_dia, cdiv((int64_t)nd * n, B), B, 0, s, (int64_t)nd * n, n, d0, L.dia.p,
+                  (__bf16*)L.dia16.p);
     }
 }
 
@@ -1406,8 +1441,16 @@ static void alloc_work(tp_amg* h, hipStream_t s) {
         L.gP = lanes_for(L.P.n, L.P.nnz);
         L.gR = lanes_for(L.R.n, L.R.nnz);
         if (&L != &h->lev.back()) try_dia(h, L, s);
-        if (h->prm.storage == 1) {
-            make_f32(L.A32, L.A.val, L.A.nnz, s);
+        if (h->prm.storage >= 1) {
+            if (h->prm.storage == 1) {
+                make_f32(L.A32, L.A.val, L.A.nnz, s);
+            } else {
+                L.A16.alloc(std::max(L.A.nnz, 1), s);
+                L.diag32.alloc(n, s);
+                if (L.A.n > 0)
+                    TP_LAUNCH(k_split_bf16_csr, cdiv(L.A.n, B), B, 0, s, L.A.n, L.A.rowptr.p, L.A.col.p, L.A.val.p,
+                              (__bf16*)L.A16.p, L.diag32.p);
+            }
             make_f32(L.dinv32, L.dinv, L.A.n, s);
             if (L.P.nnz) make_f32(L.P32, L.P.val, L.P.nnz, s);
             if (L.R.nnz) make_f32(L.R32, L.R.val, L.R.nnz, s);
@@ -1538,7 +1581,7 @@ int amg_setup(int32_t n, const int32_t* rowptr, const int32_t* col, const double
         TP_CHECK_ARG(p.nu_pre >= 0 && p.nu_pre <= 8 && p.nu_post >= 0 && p.nu_post <= 8,
                      "amg_setup: sweeps must be in [0,8]");
         TP_CHECK_ARG(p.restriction == 0 || p.restriction == 1, "amg_setup: restriction must be 0 or 1");
-        TP_CHECK_ARG(p.storage == 0 || p.storage == 1, "amg_setup: storage must be 0 or 1");
+        TP_CHECK_ARG(p.storage >= 0 && p.storage <= 2, "amg_setup: storage must be 0, 1 or 2");
         hipStream_t s = (hipStream_t)stream;
         tp_amg* h = new tp_amg();
         h->prm = p;

@@ -12,7 +12,10 @@
 // Every kernel streams its CSR arrays once: G lanes cooperate on a row (G
 // a power of two near the mean row length, 64-lane wavefronts hold 64/G
 // rows) so consecutive lanes read consecutive values and column indices.
-// Element type T is double (storage 0) or float (storage 1).
+// Vector type T is double (storage 0) or float (storage 1, 2); the level
+// operator's values have type V = T, or, for storage 2, BF16 off-diagonal
+// entries (V = __bf16, the diagonal entry stored as 0) with the diagonal in a
+// separate FP32 array `diag` that the kernels add in (a null diag: none).
 #include "tp_amg.h"
 
 namespace tp {
@@ -26,26 +29,26 @@ __device__ inline T group_sum(T v) {
     return v;
 }
 
-template <typename T, int G>
+template <typename T, typename V, int G>
 __device__ inline T row_dot(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                            const T* __restrict__ v, const T* __restrict__ x, int32_t i, int lane,
+                            const V* __restrict__ v, const T* __restrict__ x, int32_t i, int lane,
                             bool valid) {
     T s = 0;
     if (valid) {
         const int32_t e = rp[i + 1];
-        for (int32_t q = rp[i] + lane; q < e; q += G) s += v[q] * x[ci[q]];
+        for (int32_t q = rp[i] + lane; q < e; q += G) s += (T)v[q] * x[ci[q]];
     }
     return group_sum<T, G>(s);
 }
 
 // Chebyshev sweep step: r = D^{-1}(b - A x_in); d = first ? r/theta : c1 d + c2 r;
 // x_out = x_in + d
-template <typename T, int G>
+template <typename T, typename V, int G>
 __global__ void __launch_bounds__(VB)
 k_cheb_step(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-            const T* __restrict__ av, const T* __restrict__ dinv, const T* __restrict__ b,
-            const T* __restrict__ xin, T* __restrict__ xout, T* __restrict__ d, int first,
-            T theta, T c1, T c2) {
+            const V* __restrict__ av, const T* __restrict__ diag, const T* __restrict__ dinv,
+            const T* __restrict__ b, const T* __restrict__ xin, T* __restrict__ xout, T* __restrict__ d,
+            int first, T theta, T c1, T c2) {
     const int64_t tid = (int64_t)blockIdx.x * VB + threadIdx.x;
     const int32_t i = (int32_t)(tid / G);
     const int lane = (int)(tid % G);
@@ -59,8 +62,9 @@ k_cheb_step(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict
         xi = xin[i];
         if (!first) dprev = d[i];
     }
-    T ax = row_dot<T, G>(rp, ci, av, xin, i, lane, valid);
+    T ax = row_dot<T, V, G>(rp, ci, av, xin, i, lane, valid);
     if (head) {
+        if (diag) ax += diag[i] * xi;
         T r = di * (bi - ax);
         T dn = first ? r / theta : c1 * dprev + c2 * r;
         d[i] = dn;
@@ -68,11 +72,11 @@ k_cheb_step(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict
     }
 }
 
-template <typename T, int G>
+template <typename T, typename V, int G>
 __global__ void __launch_bounds__(VB)
 k_jac_step(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-           const T* __restrict__ av, const T* __restrict__ dinv, const T* __restrict__ b,
-           const T* __restrict__ xin, T* __restrict__ xout, T w) {
+           const V* __restrict__ av, const T* __restrict__ diag, const T* __restrict__ dinv,
+           const T* __restrict__ b, const T* __restrict__ xin, T* __restrict__ xout, T w) {
     const int64_t tid = (int64_t)blockIdx.x * VB + threadIdx.x;
     const int32_t i = (int32_t)(tid / G);
     const int lane = (int)(tid % G);
@@ -84,24 +88,26 @@ k_jac_step(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict_
         di = dinv[i];
         xi = xin[i];
     }
-    T ax = row_dot<T, G>(rp, ci, av, xin, i, lane, valid);
+    T ax = row_dot<T, V, G>(rp, ci, av, xin, i, lane, valid);
+    if (head && diag) ax += diag[i] * xi;
     if (head) xout[i] = xi + w * di * (bi - ax);
 }
 
 // r = b - A x
-template <typename T, int G>
+template <typename T, typename V, int G>
 __global__ void __launch_bounds__(VB)
 k_residual(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-           const T* __restrict__ av, const T* __restrict__ b, const T* __restrict__ x,
-           T* __restrict__ r) {
+           const V* __restrict__ av, const T* __restrict__ diag, const T* __restrict__ b,
+           const T* __restrict__ x, T* __restrict__ r) {
     const int64_t tid = (int64_t)blockIdx.x * VB + threadIdx.x;
     const int32_t i = (int32_t)(tid / G);
     const int lane = (int)(tid % G);
     const bool valid = i < n;
     const bool head = valid && lane == 0;
     const T bi = head ? b[i] : T(0);
-    T ax = row_dot<T, G>(rp, ci, av, x, i, lane, valid);
-    if (head) r[i] = bi - ax;
+    const T xd = head && diag ? diag[i] * x[i] : T(0);
+    T ax = row_dot<T, V, G>(rp, ci, av, x, i, lane, valid);
+    if (head) r[i] = bi - (diag ? ax + xd : ax);
 }
 
 // y = M x (restriction), or y += M x (prolongation, add = 1)
@@ -115,7 +121,7 @@ k_spmv(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci
     const bool valid = i < n;
     const bool head = valid && lane == 0;
     const T yi = head && add ? y[i] : T(0);
-    T s = row_dot<T, G>(rp, ci, av, x, i, lane, valid);
+    T s = row_dot<T, T, G>(rp, ci, av, x, i, lane, valid);
     if (head) y[i] = add ? yi + s : s;
 }
 
@@ -125,50 +131,52 @@ struct DiaOff {
     int32_t o[ND];
 };
 
-template <typename T, int ND>
-__device__ inline T dia_dot(int32_t n, const T* __restrict__ dv, DiaOff<ND> off, const T* __restrict__ x,
-                            int32_t i) {
+template <typename T, typename V, int ND>
+__device__ inline T dia_dot(int32_t n, const V* __restrict__ dv, DiaOff<ND> off, const T* __restrict__ diag,
+                            const T* __restrict__ x, int32_t i) {
     T s = 0;
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         int32_t j = i + off.o[d];
         j = j < 0 ? 0 : (j >= n ? n - 1 : j);  // out-of-range slots hold 0
-        s += dv[(int64_t)d * n + i] * x[j];
+        s += (T)dv[(int64_t)d * n + i] * x[j];
     }
+    if (diag) s += diag[i] * x[i];
     return s;
 }
 
-template <typename T, int ND>
+template <typename T, typename V, int ND>
 __global__ void __launch_bounds__(VB)
-k_cheb_step_dia(int32_t n, const T* __restrict__ dv, DiaOff<ND> off, const T* __restrict__ dinv,
-                const T* __restrict__ b, const T* __restrict__ xin, T* __restrict__ xout, T* __restrict__ d,
-                int first, T theta, T c1, T c2) {
+k_cheb_step_dia(int32_t n, const V* __restrict__ dv, DiaOff<ND> off, const T* __restrict__ diag,
+                const T* __restrict__ dinv, const T* __restrict__ b, const T* __restrict__ xin,
+                T* __restrict__ xout, T* __restrict__ d, int first, T theta, T c1, T c2) {
     const int32_t i = blockIdx.x * VB + threadIdx.x;
     if (i >= n) return;
-    T ax = dia_dot<T, ND>(n, dv, off, xin, i);
+    T ax = dia_dot<T, V, ND>(n, dv, off, diag, xin, i);
     T r = dinv[i] * (b[i] - ax);
     T dn = first ? r / theta : c1 * d[i] + c2 * r;
     d[i] = dn;
     xout[i] = xin[i] + dn;
 }
 
-template <typename T, int ND>
+template <typename T, typename V, int ND>
 __global__ void __launch_bounds__(VB)
-k_jac_step_dia(int32_t n, const T* __restrict__ dv, DiaOff<ND> off, const T* __restrict__ dinv,
-               const T* __restrict__ b, const T* __restrict__ xin, T* __restrict__ xout, T w) {
+k_jac_step_dia(int32_t n, const V* __restrict__ dv, DiaOff<ND> off, const T* __restrict__ diag,
+               const T* __restrict__ dinv, const T* __restrict__ b, const T* __restrict__ xin,
+               T* __restrict__ xout, T w) {
     const int32_t i = blockIdx.x * VB + threadIdx.x;
     if (i >= n) return;
-    T ax = dia_dot<T, ND>(n, dv, off, xin, i);
+    T ax = dia_dot<T, V, ND>(n, dv, off, diag, xin, i);
     xout[i] = xin[i] + w * dinv[i] * (b[i] - ax);
 }
 
-template <typename T, int ND>
+template <typename T, typename V, int ND>
 __global__ void __launch_bounds__(VB)
-k_residual_dia(int32_t n, const T* __restrict__ dv, DiaOff<ND> off, const T* __restrict__ b,
-               const T* __restrict__ x, T* __restrict__ r) {
+k_residual_dia(int32_t n, const V* __restrict__ dv, DiaOff<ND> off, const T* __restrict__ diag,
+               const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ r) {
     const int32_t i = blockIdx.x * VB + threadIdx.x;
     if (i >= n) return;
-    r[i] = b[i] - dia_dot<T, ND>(n, dv, off, x, i);
+    r[i] = b[i] - dia_dot<T, V, ND>(n, dv, off, diag, x, i);
 }
 
 #define TP_ND_DISPATCH(nd, ...)                                 \
@@ -189,11 +197,11 @@ static DiaOff<ND> dia_offsets(const Level& L) {
 // Chebyshev steps 0 and 1 from a zero guess in one pass: x0_j = (D^{-1} b)_j / theta
 // is formed on the fly for every neighbour, then
 //   r = D^{-1}(b - A x0); d = c1 x0_i + c2 r; x = x0_i + d.
-template <typename T, int G>
+template <typename T, typename V, int G>
 __global__ void __launch_bounds__(VB)
-k_cheb01(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci, const T* __restrict__ av,
-         const T* __restrict__ dinv, const T* __restrict__ b, T* __restrict__ xout, T* __restrict__ d, T theta,
-         T c1, T c2) {
+k_cheb01(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci, const V* __restrict__ av,
+         const T* __restrict__ diag, const T* __restrict__ dinv, const T* __restrict__ b, T* __restrict__ xout,
+         T* __restrict__ d, T theta, T c1, T c2) {
     const int64_t tid = (int64_t)blockIdx.x * VB + threadIdx.x;
     const int32_t i = (int32_t)(tid / G);
     const int lane = (int)(tid % G);
@@ -209,12 +217,13 @@ k_cheb01(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ 
         const int32_t e = rp[i + 1];
         for (int32_t q = rp[i] + lane; q < e; q += G) {
             const int32_t j = ci[q];
-            s += av[q] * ((dinv[j] * b[j]) / theta);
+            s += (T)av[q] * ((dinv[j] * b[j]) / theta);
         }
     }
     s = group_sum<T, G>(s);
     if (head) {
         const T x0 = (di * bi) / theta;
+        if (diag) s += diag[i] * x0;
         const T r = di * (bi - s);
         const T dn = c1 * x0 + c2 * r;
         d[i] = dn;
@@ -222,10 +231,11 @@ k_cheb01(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ 
     }
 }
 
-template <typename T, int ND>
+template <typename T, typename V, int ND>
 __global__ void __launch_bounds__(VB)
-k_cheb01_dia(int32_t n, const T* __restrict__ dv, DiaOff<ND> off, const T* __restrict__ dinv,
-             const T* __restrict__ b, T* __restrict__ xout, T* __restrict__ d, T theta, T c1, T c2) {
+k_cheb01_dia(int32_t n, const V* __restrict__ dv, DiaOff<ND> off, const T* __restrict__ diag,
+             const T* __restrict__ dinv, const T* __restrict__ b, T* __restrict__ xout, T* __restrict__ d, T theta,
+             T c1, T c2) {
     const int32_t i = blockIdx.x * VB + threadIdx.x;
     if (i >= n) return;
     T s = 0;
@@ -233,9 +243,10 @@ k_cheb01_dia(int32_t n, const T* __restrict__ dv, DiaOff<ND> off, const T* __res
     for (int q = 0; q < ND; ++q) {
         int32_t j = i + off.o[q];
         j = j < 0 ? 0 : (j >= n ? n - 1 : j);
-        s += dv[(int64_t)q * n + i] * ((dinv[j] * b[j]) / theta);
+        s += (T)dv[(int64_t)q * n + i] * ((dinv[j] * b[j]) / theta);
     }
     const T x0 = (dinv[i] * b[i]) / theta;
+    if (diag) s += diag[i] * x0;
     const T r = dinv[i] * (b[i] - s);
     const T dn = c1 * x0 + c2 * r;
     d[i] = dn;
@@ -292,17 +303,32 @@ k_coarse_solve(int32_t n, const double* __restrict__ inv, const T* __restrict__ 
     default: { constexpr int GG = 64; __VA_ARGS__; } break;    \
     }
 
-template <typename T> struct LevelVals;
-template <> struct LevelVals<double> {
+// Storage modes: vector type T, level-operator value type V, and where each
+// level array lives (diag: the separate FP32 diagonal of storage 2).
+struct M64 { using T = double; using V = double; };
+struct M32 { using T = float; using V = float; };
+struct M16 { using T = float; using V = __bf16; };
+template <typename M> struct LevelVals;
+template <> struct LevelVals<M64> {
     static const double* D(const Level& L) { return L.dia.p; }
     static const double* A(const Level& L) { return L.A.val.p; }
+    static const double* diag(const Level&) { return nullptr; }
     static const double* P(const Level& L) { return L.P.val.p; }
     static const double* R(const Level& L) { return L.R.val.p; }
     static const double* dinv(const Level& L) { return L.dinv.p; }
 };
-template <> struct LevelVals<float> {
+template <> struct LevelVals<M32> {
     static const float* D(const Level& L) { return L.dia32.p; }
     static const float* A(const Level& L) { return L.A32.p; }
+    static const float* diag(const Level&) { return nullptr; }
+    static const float* P(const Level& L) { return L.P32.p; }
+    static const float* R(const Level& L) { return L.R32.p; }
+    static const float* dinv(const Level& L) { return L.dinv32.p; }
+};
+template <> struct LevelVals<M16> {
+    static const __bf16* D(const Level& L) { return (const __bf16*)L.dia16.p; }
+    static const __bf16* A(const Level& L) { return (const __bf16*)L.A16.p; }
+    static const float* diag(const Level& L) { return L.diag32.p; }
     static const float* P(const Level& L) { return L.P32.p; }
     static const float* R(const Level& L) { return L.R32.p; }
     static const float* dinv(const Level& L) { return L.dinv32.p; }
@@ -313,14 +339,17 @@ static inline int grid_rows(int32_t n, int G) { return cdiv((int64_t)std::max(n,
 // smoothing sweeps on level L; x_cur in/out (ping-pong between x and x2)
 // final_out (optional): buffer for the sweep's last step, so the result can
 // land in the caller's vector; the returned pointer says where it is.
-template <typename T>
-static T* smooth(tp_amg* h, int l, const T* b, T* xc, bool zero, int nu, hipStream_t s,
-                 T* final_out = nullptr) {
+template <typename M>
+static typename M::T* smooth(tp_amg* h, int l, const typename M::T* b, typename M::T* xc, bool zero, int nu,
+                             hipStream_t s, typename M::T* final_out = nullptr) {
+    using T = typename M::T;
+    using V = typename M::V;
     Level& L = h->lev[l];
     const tp_amg_params& p = h->prm;
     const int32_t n = L.A.n;
-    const T* av = LevelVals<T>::A(L);
-    const T* dv = LevelVals<T>::dinv(L);
+    const V* av = LevelVals<M>::A(L);
+    const T* dg = LevelVals<M>::diag(L);
+    const T* dv = LevelVals<M>::dinv(L);
     T* xa = (T*)L.x.p;
     T* xb = (T*)L.x2.p;
     T* d = (T*)L.d.p;
@@ -329,7 +358,10 @@ static T* smooth(tp_amg* h, int l, const T* b, T* xc, bool zero, int nu, hipStre
     auto target = [&](T* q, bool last) { return last && final_out ? final_out : other(q); };
     const double lo = p.cheb_lo, theta = 0.5 * (1.0 + lo), delta = 0.5 * (1.0 - lo);
     const double sigma = theta / delta;
-    const size_t es = sizeof(T);
+    const size_t es = sizeof(T), vs = sizeof(V);
+    // bytes of one pass over the level operator (values, indices, separate diagonal)
+    const double abytes = (L.ndia ? (double)L.ndia * n * vs : (double)L.A.nnz * (vs + 4) + 4.0 * (n + 1)) +
+                          (dg ? (double)es * n : 0.0);
     const int deg = (l > 0 && p.cheb_degree_coarse > 0) ? p.cheb_degree_coarse : p.cheb_degree;
     for (int sw = 0; sw < nu; ++sw) {
         bool z = zero && sw == 0;
@@ -340,15 +372,14 @@ static T* smooth(tp_amg* h, int l, const T* b, T* xc, bool zero, int nu, hipStre
             const double c1 = rho1 * (1.0 / sigma), c2 = 2.0 * rho1 / delta;
             T* nx = target(cur, sw == nu - 1 && deg == 2);
             const bool timed = l == 0;
-            const double bytes = (L.ndia ? (double)L.ndia * n * es : (double)L.A.nnz * (es + 4) + 4.0 * (n + 1)) +
-                                 4.0 * es * n;
+            const double bytes = abytes + 4.0 * es * n;
             if (L.ndia) {
-                TP_ND_DISPATCH(L.ndia, TP_LAUNCH_TIMED(timed, bytes, (k_cheb01_dia<T, NDD>), cdiv(n, VB), VB, 0, s,
-                                                       n, LevelVals<T>::D(L), dia_offsets<NDD>(L), dv, b, nx, d,
+                TP_ND_DISPATCH(L.ndia, TP_LAUNCH_TIMED(timed, bytes, (k_cheb01_dia<T, V, NDD>), cdiv(n, VB), VB, 0, s,
+                                                       n, LevelVals<M>::D(L), dia_offsets<NDD>(L), dg, dv, b, nx, d,
                                                        (T)theta, (T)c1, (T)c2));
             } else {
-                TP_G_DISPATCH(L.gA, TP_LAUNCH_TIMED(timed, bytes, (k_cheb01<T, GG>), grid_rows(n, GG), VB, 0, s, n,
-                                                    L.A.rowptr.p, L.A.col.p, av, dv, b, nx, d, (T)theta, (T)c1,
+                TP_G_DISPATCH(L.gA, TP_LAUNCH_TIMED(timed, bytes, (k_cheb01<T, V, GG>), grid_rows(n, GG), VB, 0, s, n,
+                                                    L.A.rowptr.p, L.A.col.p, av, dg, dv, b, nx, d, (T)theta, (T)c1,
                                                     (T)c2));
             }
             cur = nx;
@@ -360,16 +391,15 @@ static T* smooth(tp_amg* h, int l, const T* b, T* xc, bool zero, int nu, hipStre
         if (p.smoother == 0) {
             if (z) continue;
             T* nx = target(cur, sw == nu - 1);
-            double bytes = (L.ndia ? (double)L.ndia * n * es : (double)L.A.nnz * (es + 4) + 4.0 * (n + 1)) +
-                           4.0 * es * n;
+            double bytes = abytes + 4.0 * es * n;
             const bool timed = l == 0;
             if (L.ndia) {
-                TP_ND_DISPATCH(L.ndia, TP_LAUNCH_TIMED(timed, bytes, (k_jac_step_dia<T, NDD>), cdiv(n, VB), VB, 0,
-                                                       s, n, LevelVals<T>::D(L), dia_offsets<NDD>(L), dv, b, cur,
+                TP_ND_DISPATCH(L.ndia, TP_LAUNCH_TIMED(timed, bytes, (k_jac_step_dia<T, V, NDD>), cdiv(n, VB), VB, 0,
+                                                       s, n, LevelVals<M>::D(L), dia_offsets<NDD>(L), dg, dv, b, cur,
                                                        nx, (T)p.omega));
             } else {
-                TP_G_DISPATCH(L.gA, TP_LAUNCH_TIMED(timed, bytes, (k_jac_step<T, GG>), grid_rows(n, GG), VB, 0, s,
-                                                    n, L.A.rowptr.p, L.A.col.p, av, dv, b, cur, nx, (T)p.omega));
+                TP_G_DISPATCH(L.gA, TP_LAUNCH_TIMED(timed, bytes, (k_jac_step<T, V, GG>), grid_rows(n, GG), VB, 0, s,
+                                                    n, L.A.rowptr.p, L.A.col.p, av, dg, dv, b, cur, nx, (T)p.omega));
             }
             cur = nx;
             continue;
@@ -391,16 +421,15 @@ static T* smooth(tp_amg* h, int l, const T* b, T* xc, bool zero, int nu, hipStre
                 c2 = 2.0 * rho1 / delta;
                 rho0 = rho1;
             }
-            double bytes = (L.ndia ? (double)L.ndia * n * es : (double)L.A.nnz * (es + 4) + 4.0 * (n + 1)) +
-                           (first ? 5.0 : 6.0) * es * n;
+            double bytes = abytes + (first ? 5.0 : 6.0) * es * n;
             const bool timed = l == 0;
             if (L.ndia) {
-                TP_ND_DISPATCH(L.ndia, TP_LAUNCH_TIMED(timed, bytes, (k_cheb_step_dia<T, NDD>), cdiv(n, VB), VB, 0,
-                                                       s, n, LevelVals<T>::D(L), dia_offsets<NDD>(L), dv, b, cur,
+                TP_ND_DISPATCH(L.ndia, TP_LAUNCH_TIMED(timed, bytes, (k_cheb_step_dia<T, V, NDD>), cdiv(n, VB), VB, 0,
+                                                       s, n, LevelVals<M>::D(L), dia_offsets<NDD>(L), dg, dv, b, cur,
                                                        nx, d, first, (T)theta, (T)c1, (T)c2));
             } else {
-                TP_G_DISPATCH(L.gA, TP_LAUNCH_TIMED(timed, bytes, (k_cheb_step<T, GG>), grid_rows(n, GG), VB, 0, s,
-                                                    n, L.A.rowptr.p, L.A.col.p, av, dv, b, cur, nx, d, first,
+                TP_G_DISPATCH(L.gA, TP_LAUNCH_TIMED(timed, bytes, (k_cheb_step<T, V, GG>), grid_rows(n, GG), VB, 0, s,
+                                                    n, L.A.rowptr.p, L.A.col.p, av, dg, dv, b, cur, nx, d, first,
                                                     (T)theta, (T)c1, (T)c2));
             }
             cur = nx;
@@ -409,8 +438,11 @@ static T* smooth(tp_amg* h, int l, const T* b, T* xc, bool zero, int nu, hipStre
     return cur;
 }
 
-template <typename T>
-static T* vcycle_level(tp_amg* h, int l, const T* b, hipStream_t s, T* final_out = nullptr) {
+template <typename M>
+static typename M::T* vcycle_level(tp_amg* h, int l, const typename M::T* b, hipStream_t s,
+                                   typename M::T* final_out = nullptr) {
+    using T = typename M::T;
+    using V = typename M::V;
     Level& L = h->lev[l];
     const int32_t n = L.A.n;
     const int last = (int)h->lev.size() - 1;
@@ -421,52 +453,54 @@ static T* vcycle_level(tp_amg* h, int l, const T* b, hipStream_t s, T* final_out
     }
     const tp_amg_params& p = h->prm;
     T* cur = x;
-    if (p.nu_pre > 0) cur = smooth<T>(h, l, b, cur, true, p.nu_pre, s);
+    if (p.nu_pre > 0) cur = smooth<M>(h, l, b, cur, true, p.nu_pre, s);
     else TP_LAUNCH(k_zero<T>, cdiv(n, VB), VB, 0, s, n, cur);
     // (residual and restriction stay two row-parallel passes: forming the
     // residual entries inside the restriction recomputes each fine row for
     // every coarse row that holds it and serialises its gathers)
     T* r = (T*)L.r.p;
     if (L.ndia) {
-        TP_ND_DISPATCH(L.ndia, TP_LAUNCH((k_residual_dia<T, NDD>), cdiv(n, VB), VB, 0, s, n, LevelVals<T>::D(L),
-                                         dia_offsets<NDD>(L), b, cur, r));
+        TP_ND_DISPATCH(L.ndia, TP_LAUNCH((k_residual_dia<T, V, NDD>), cdiv(n, VB), VB, 0, s, n, LevelVals<M>::D(L),
+                                         dia_offsets<NDD>(L), LevelVals<M>::diag(L), b, cur, r));
     } else {
-        TP_G_DISPATCH(L.gA, TP_LAUNCH((k_residual<T, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p,
-                                      L.A.col.p, LevelVals<T>::A(L), b, cur, r));
+        TP_G_DISPATCH(L.gA, TP_LAUNCH((k_residual<T, V, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p,
+                                      L.A.col.p, LevelVals<M>::A(L), LevelVals<M>::diag(L), b, cur, r));
     }
     Level& Ln = h->lev[l + 1];
     T* bc = (T*)Ln.b.p;
     TP_G_DISPATCH(L.gR, TP_LAUNCH((k_spmv<T, GG>), grid_rows(L.R.n, GG), VB, 0, s, L.R.n, L.R.rowptr.p,
-                                  L.R.col.p, LevelVals<T>::R(L), r, bc, 0));
-    T* xc = vcycle_level<T>(h, l + 1, bc, s);
+                                  L.R.col.p, LevelVals<M>::R(L), r, bc, 0));
+    T* xc = vcycle_level<M>(h, l + 1, bc, s);
     // (prolongation stays a separate row-parallel pass: fusing it into the
     // first post-smoothing step recomputes P x_c for every neighbour and
     // turns the step latency-bound)
     TP_G_DISPATCH(L.gP, TP_LAUNCH((k_spmv<T, GG>), grid_rows(n, GG), VB, 0, s, n, L.P.rowptr.p, L.P.col.p,
-                                  LevelVals<T>::P(L), xc, cur, 1));
+                                  LevelVals<M>::P(L), xc, cur, 1));
     if (l == 0 && h->stop_before_post) return cur;
     if (l == 0 && h->cnn && h->cnn->enabled) {
         // learned post-smoother: r = b - A x; x += s * CNN(features(r))
         if (L.ndia) {
-            TP_ND_DISPATCH(L.ndia, TP_LAUNCH((k_residual_dia<T, NDD>), cdiv(n, VB), VB, 0, s, n,
-                                             LevelVals<T>::D(L), dia_offsets<NDD>(L), b, cur, r));
+            TP_ND_DISPATCH(L.ndia, TP_LAUNCH((k_residual_dia<T, V, NDD>), cdiv(n, VB), VB, 0, s, n,
+                                             LevelVals<M>::D(L), dia_offsets<NDD>(L), LevelVals<M>::diag(L), b,
+                                             cur, r));
         } else {
-            TP_G_DISPATCH(L.gA, TP_LAUNCH((k_residual<T, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p,
-                                          L.A.col.p, LevelVals<T>::A(L), b, cur, r));
+            TP_G_DISPATCH(L.gA, TP_LAUNCH((k_residual<T, V, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p,
+                                          L.A.col.p, LevelVals<M>::A(L), LevelVals<M>::diag(L), b, cur, r));
         }
         tp_cnn_attach* a = h->cnn.get();
         cnn_features_into<T>(a, r, a->feat.p, s);
         cnn_forward_into<T>(a->net, a->g, a->feat.p, nullptr, cur, a->scale.p, a->bad.p, s, a->h.p);
         return cur;
     }
-    if (p.nu_post > 0) cur = smooth<T>(h, l, b, cur, false, p.nu_post, s, final_out);
+    if (p.nu_post > 0) cur = smooth<M>(h, l, b, cur, false, p.nu_post, s, final_out);
     return cur;
 }
 
 const void* vcycle_run(tp_amg* h, const void* b_ext, hipStream_t s, void* x_ext) {
     const void* b = b_ext ? b_ext : (const void*)h->lev[0].b.p;
-    if (h->prm.storage == 1) return vcycle_level<float>(h, 0, (const float*)b, s, (float*)x_ext);
-    return vcycle_level<double>(h, 0, (const double*)b, s, (double*)x_ext);
+    if (h->prm.storage == 2) return vcycle_level<M16>(h, 0, (const float*)b, s, (float*)x_ext);
+    if (h->prm.storage == 1) return vcycle_level<M32>(h, 0, (const float*)b, s, (float*)x_ext);
+    return vcycle_level<M64>(h, 0, (const double*)b, s, (double*)x_ext);
 }
 
 template <typename Ti, typename To>
@@ -522,8 +556,8 @@ extern "C" int amg_presmoothed_pair(tp_amg_t amg, const double* y, double* r, do
         }
         amg->stop_before_post = false;
         tp::cast_s2d(n, xv, x.p, es, s);
-        TP_G_DISPATCH(L.gA, TP_LAUNCH((tp::k_residual<double, GG>), tp::grid_rows(n, GG), tp::VB, 0, s, n,
-                                      L.A.rowptr.p, L.A.col.p, L.A.val.p, b.p, x.p, r));
+        TP_G_DISPATCH(L.gA, TP_LAUNCH((tp::k_residual<double, double, GG>), tp::grid_rows(n, GG), tp::VB, 0, s, n,
+                                      L.A.rowptr.p, L.A.col.p, L.A.val.p, (const double*)nullptr, b.p, x.p, r));
         TP_LAUNCH(tp::k_pair_finish, tp::cdiv(n, tp::VB), tp::VB, 0, s, n, y, x.p, e);
         TP_HIP(hipStreamSynchronize(s));
     });
@@ -592,17 +626,20 @@ extern "C" int amg_cnn_loss_grad(tp_amg_t amg, const float* feat, const float* t
 }
 
 namespace tp {
-template <typename T>
+template <typename M>
 static double replay_fine_smoother(tp_amg* h, int reps, hipStream_t s, double* bytes) {
+    using T = typename M::T;
+    using V = typename M::V;
     Level& L = h->lev[0];
     const int32_t n = L.A.n;
-    const size_t es = sizeof(T);
+    const size_t es = sizeof(T), vs = sizeof(V);
+    const T* dg = LevelVals<M>::diag(L);
     T* xa = (T*)L.x.p;
     T* xb = (T*)L.x2.p;
     T* d = (T*)L.d.p;
     T* b = (T*)L.b.p;
     for (T* v : {xa, xb, d, b}) TP_LAUNCH(k_zero<T>, cdiv(n, VB), VB, 0, s, n, v);
-    const T* dv = LevelVals<T>::dinv(L);
+    const T* dv = LevelVals<M>::dinv(L);
     const double lo = h->prm.cheb_lo, theta = 0.5 * (1.0 + lo), delta = 0.5 * (1.0 - lo), sigma = theta / delta;
     const double rho1 = 1.0 / (2.0 * sigma - 1.0 / sigma), c1 = rho1 / sigma, c2 = 2.0 * rho1 / delta;
     hipEvent_t e0, e1;
@@ -613,12 +650,13 @@ static double replay_fine_smoother(tp_amg* h, int reps, hipStream_t s, double* b
         T* in = (k & 1) ? xb : xa;
         T* out = (k & 1) ? xa : xb;
         if (L.ndia) {
-            TP_ND_DISPATCH(L.ndia, TP_LAUNCH((k_cheb_step_dia<T, NDD>), cdiv(n, VB), VB, 0, s, n, LevelVals<T>::D(L),
-                                             dia_offsets<NDD>(L), dv, b, in, out, d, 0, (T)theta, (T)c1, (T)c2));
+            TP_ND_DISPATCH(L.ndia, TP_LAUNCH((k_cheb_step_dia<T, V, NDD>), cdiv(n, VB), VB, 0, s, n,
+                                             LevelVals<M>::D(L), dia_offsets<NDD>(L), dg, dv, b, in, out, d, 0,
+                                             (T)theta, (T)c1, (T)c2));
         } else {
-            TP_G_DISPATCH(L.gA, TP_LAUNCH((k_cheb_step<T, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p,
-                                          L.A.col.p, LevelVals<T>::A(L), dv, b, in, out, d, 0, (T)theta, (T)c1,
-                                          (T)c2));
+            TP_G_DISPATCH(L.gA, TP_LAUNCH((k_cheb_step<T, V, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p,
+                                          L.A.col.p, LevelVals<M>::A(L), dg, dv, b, in, out, d, 0, (T)theta,
+                                          (T)c1, (T)c2));
         }
     }
     TP_HIP(hipEventRecord(e1, s));
@@ -627,7 +665,8 @@ static double replay_fine_smoother(tp_amg* h, int reps, hipStream_t s, double* b
     TP_HIP(hipEventElapsedTime(&ms, e0, e1));
     TP_HIP(hipEventDestroy(e0));
     TP_HIP(hipEventDestroy(e1));
-    *bytes = (L.ndia ? (double)L.ndia * n * es : (double)L.A.nnz * (es + 4) + 4.0 * (n + 1)) + 6.0 * es * n;
+    *bytes = (L.ndia ? (double)L.ndia * n * vs : (double)L.A.nnz * (vs + 4) + 4.0 * (n + 1)) +
+             (dg ? (double)es * n : 0.0) + 6.0 * es * n;
     return (double)ms / reps;
 }
 }  // namespace tp
@@ -639,8 +678,9 @@ extern "C" int amg_time_fine_smoother(tp_amg_t amg, int32_t reps, double* ms_per
         TP_CHECK_ARG(reps >= 1 && reps <= 100000, "amg_time_fine_smoother: reps out of range");
         TP_CHECK_ARG(amg->lev.size() >= 2, "amg_time_fine_smoother: needs at least two levels");
         hipStream_t s = (hipStream_t)stream;
-        *ms_per_launch = amg->prm.storage == 1 ? tp::replay_fine_smoother<float>(amg, reps, s, bytes_per_launch)
-                                               : tp::replay_fine_smoother<double>(amg, reps, s, bytes_per_launch);
+        *ms_per_launch = amg->prm.storage == 2   ? tp::replay_fine_smoother<tp::M16>(amg, reps, s, bytes_per_launch)
+                         : amg->prm.storage == 1 ? tp::replay_fine_smoother<tp::M32>(amg, reps, s, bytes_per_launch)
+                                                 : tp::replay_fine_smoother<tp::M64>(amg, reps, s, bytes_per_launch);
     });
     return TP_OK;
 }

@@ -18,7 +18,7 @@ class SolveConfig:
     restart: int = 30
     maxit: int = 1000
     variant: str = "lower"
-    storage: int = 0              # 0 FP64 hierarchy, 1 FP32
+    storage: int = 0              # 0 FP64 hierarchy, 1 FP32, 2 FP32 with BF16 off-diagonals
     amg: tps.AmgParams = dataclasses.field(default_factory=tps.AmgParams)
 
 

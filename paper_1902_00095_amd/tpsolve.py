@@ -124,7 +124,7 @@ class AmgParams:
     nu_pre: int = 1
     nu_post: int = 1
     restriction: int = 0       # 0 Galerkin, 1 Petrov-Galerkin (Schur operator)
-    storage: int = 0           # 0 FP64, 1 FP32
+    storage: int = 0           # 0 FP64, 1 FP32, 2 FP32 with BF16 off-diagonal operator entries
     cheb_degree_coarse: int = 1  # degree on levels >= 1 (0: cheb_degree)
 
     def oracle_kwargs(self):
@@ -296,8 +296,13 @@ class AMG:
     def vcycle_bytes(self):
         """Algorithmic bytes of one V-cycle (each array read or written once
         per pass): Chebyshev(3) pre/post sweeps with the zero-guess steps
-        fused, residual, restriction, prolongation, coarse dense inverse."""
-        es = 4 if self.params.storage == 1 else 8
+        fused, residual, restriction, prolongation, coarse dense inverse.
+        Storage 2 reads level-operator values as BF16 (2 bytes) plus the FP32
+        diagonal (4 bytes a row)."""
+        st = self.params.storage
+        es = 8 if st == 0 else 4
+        vs = 2 if st == 2 else es          # level-operator value bytes
+        dgb = 4 if st == 2 else 0          # separate diagonal, bytes per row
         d0, dc = self.params.cheb_degree, self.params.cheb_degree_coarse
         total = 0.0
         L = self.nlev
@@ -309,7 +314,7 @@ class AMG:
             deg = dc if (l > 0 and dc > 0) else d0
             nc = self.level_sizes(l + 1)[0]
             nd, _ = self.level_format(l)
-            mA = nd * n * es if nd else nnzA * (es + 4) + (n + 1) * 4
+            mA = (nd * n * vs if nd else nnzA * (vs + 4) + (n + 1) * 4) + dgb * n
             mP = nnzP * (es + 4) + (n + 1) * 4
             mR = nnzR * (es + 4) + (nc + 1) * 4
             if deg >= 2:   # steps 0 and 1 fused, then deg - 2 steps
