@@ -156,6 +156,18 @@ def run_variants(prob, dev, cfg, iters64, ms64):
                                         "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
                                         "seconds": round(train_s, 2)},
                            "plain_fp64": e_plain, "learned_fp64": e_learn, "mixed_learned": e_mixl}
+    # 256x256x64 (8.4M unknowns): 20 backward-Euler steps of up to 4 Newton iterations each,
+    # plain FP64 against the FP32 hierarchy and the FP32 hierarchy with the learned smoother
+    p5 = synth.make_problem("W5")
+    nc = solver.NewtonConfig(steps=20)
+    w5 = {}
+    for key, c5, nt in (("fp64", cfg, None), ("fp32_hierarchy", dc.replace(cfg, storage=1), None),
+                        ("mixed_learned", dc.replace(cfg, storage=1), net)):
+        _, st5 = solver.simulate(p5, c5, nc, net=nt)
+        st5.pop("newton_per_step", None)
+        w5[key] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st5.items()}
+    out["W5_256x256x64_20_steps"] = dict(w5, note="per Newton iteration: assembly, both AMG setups, FGMRES to rtol; "
+                                         "Newton stops at |G|/|G0| or |dx|/|x| <= 1e-8 or after 4 iterations")
     net.close()
     return out
 

@@ -14,6 +14,8 @@ What it computes, and the passage each part follows:
   block preconditioner and GMRES             Section 3.2 (five-step list),
       Section 4 (right-preconditioned GMRES, restart 30) -> krylov.c
   3-D convolution smoother network           cnn.c
+  Newton time stepping (sparse direct linear steps)  Section 2.2, Section 5
+                                             -> newton_simulate
 """
 from __future__ import annotations
 
@@ -199,6 +201,54 @@ def jacobian(prob, x=None):
                       _p(_f64(prob.x_prev)), _p(_f64(x)), _p(rowptr), _p(col),
                       *[_p(a) for a in arrs])
     return Jacobian(prob.grid.n, rowptr, col, *arrs)
+
+
+def sparse_interleaved(J):
+    """The full 2n x 2n Jacobian of eq. AXR, interleaved [p_i, T_i], as a
+    SciPy CSR matrix (from the four stencil blocks)."""
+    import scipy.sparse as sp
+    n = J.n
+    rows = np.repeat(np.arange(n), np.diff(J.rowptr))
+    cols = np.asarray(J.col, dtype=np.int64)
+    r = np.concatenate([2 * rows, 2 * rows, 2 * rows + 1, 2 * rows + 1])
+    c = np.concatenate([2 * cols, 2 * cols + 1, 2 * cols, 2 * cols + 1])
+    v = np.concatenate([J.pp, J.pT, J.Tp, J.TT])
+    return sp.csr_matrix((v, (r, c)), shape=(2 * n, 2 * n))
+
+
+def newton_simulate(prob, steps, max_newton=4, rtol_f=1e-8, rtol_dx=1e-8):
+    """Backward-Euler time stepping from prob.x_prev with Newton's method on
+    G(x) = 0 (Section 2.2: each Newton iteration solves eq. AXR for the
+    increment; Section 5: a step has converged when |G| relative to the
+    step's first |G|, or |dx| relative to |x|, is below 1e-8).  The linear
+    step is a sparse direct solve (SuperLU through SciPy), so the result is
+    the exact-Newton reference.  Returns (states after each step, Newton
+    iterations per step, relative |G| histories per step)."""
+    import dataclasses
+
+    import scipy.sparse.linalg as spla
+    x = np.array(prob.x_prev, dtype=np.float64)
+    states, its, hists = [], [], []
+    for _ in range(steps):
+        p = dataclasses.replace(prob, x_prev=x.copy(), x_k=x.copy())
+        g0, done, k_its, hist = None, False, 0, []
+        for k in range(max_newton + 1):
+            G = residual(p, x)
+            gn = float(np.linalg.norm(G))
+            if g0 is None:
+                g0 = gn
+            hist.append(gn / g0 if g0 > 0 else 0.0)
+            if gn <= rtol_f * g0 or done or k == max_newton:
+                break
+            A = sparse_interleaved(jacobian(p, x))
+            dx = spla.spsolve(A.tocsc(), -G)
+            x = x + dx
+            k_its += 1
+            done = float(np.linalg.norm(dx)) <= rtol_dx * float(np.linalg.norm(x))
+        states.append(x.copy())
+        its.append(k_its)
+        hists.append(hist)
+    return states, its, hists
 
 
 class AMG:
