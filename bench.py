@@ -60,7 +60,7 @@ def _time_solves(prob, dev, cfg, reps, attach=None):
     best = out[1:]
     res = dict(ms_per_solve=round(float(np.median([s["ms"] for s in best])), 3),
                iters=best[-1]["iters"], rel_true=best[-1]["rel_true"],
-               fallback_iter=best[-1]["fallback_iter"])
+               fallback_iter=best[-1]["fallback_iter"], converged=best[-1]["converged"])
     return res, best[-1]["x"]
 
 
@@ -156,6 +156,12 @@ def run_variants(prob, dev, cfg, iters64, ms64):
                                         "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
                                         "seconds": round(train_s, 2)},
                            "plain_fp64": e_plain, "learned_fp64": e_learn, "mixed_learned": e_mixl}
+    # the simple Schur approximations the paper compares S~_T with (W2)
+    sch = {}
+    for key in ("T", "ATT", "diag"):
+        rs, _ = _time_solves(prob, dev, dc.replace(cfg, schur=key, maxit=200), 1)
+        sch[{"T": "S_T", "ATT": "A_TT", "diag": "S_diag"}[key]] = rs
+    out["schur_approximations_W2"] = dict(sch, note="FGMRES capped at 200 iterations")
     # 256x256x64 (8.4M unknowns): 20 backward-Euler steps of up to 4 Newton iterations each,
     # plain FP64 against the FP32 hierarchy and the FP32 hierarchy with the learned smoother
     p5 = synth.make_problem("W5")

@@ -141,6 +141,17 @@ typedef struct tp_amg* tp_amg_t;
 int amg_setup(int32_t n, const int32_t* rowptr, const int32_t* col, const double* val,
               const tp_amg_params* params, tp_amg_t* out, void* stream);
 
+/* Hierarchy of the diagonal Schur approximation (Section 3.2, one of the
+ * simple approximations the paper compares S~_T with)
+ *   S_diag = A_TT - A_Tp diag(A_pp)^{-1} A_pT,
+ * formed on the device from the Jacobian's blocks (sparse product on the
+ * distance-two pattern of the stencil), then amg_setup on it; the hierarchy
+ * keeps its own copy (level 0).  J is read only.  Synchronises `stream`.
+ * Errors: as amg_setup, and TP_ERR_NUMERIC for a zero or non-finite A_pp
+ * diagonal entry. */
+int amg_setup_schur_diag(const tp_jacobian* J, const tp_amg_params* params, tp_amg_t* out,
+                         void* stream);
+
 int amg_num_levels(tp_amg_t amg, int32_t* nlev);
 /* sizes of level l (P/R sizes are 0 on the coarsest level) */
 int amg_level_info(tp_amg_t amg, int32_t level, int32_t* n, int32_t* nnzA,

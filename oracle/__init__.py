@@ -216,6 +216,16 @@ def sparse_interleaved(J):
     return sp.csr_matrix((v, (r, c)), shape=(2 * n, 2 * n))
 
 
+def schur_diag(J):
+    """The diagonal Schur approximation A_TT - A_Tp diag(A_pp)^{-1} A_pT
+    (Section 3.2), by SciPy sparse products: (rowptr, col, val), sorted rows."""
+    import scipy.sparse as sp
+    Dinv = sp.diags(1.0 / J.block("pp").diagonal())
+    S = (J.block("TT") - J.block("Tp") @ (Dinv @ J.block("pT"))).tocsr()
+    S.sort_indices()
+    return S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data.copy()
+
+
 def newton_simulate(prob, steps, max_newton=4, rtol_f=1e-8, rtol_dx=1e-8):
     """Backward-Euler time stepping from prob.x_prev with Newton's method on
     G(x) = 0 (Section 2.2: each Newton iteration solves eq. AXR for the

@@ -1558,6 +1558,60 @@ static void setup(tp_amg* h, int32_t n, const int32_t* rowptr, const int32_t* co
     TP_HIP(hipStreamSynchronize(s));
 }
 
+// ---- the diagonal Schur approximation ----------------------------------------------------
+// rows of A_pT (a copy, v) scaled by 1 / (A_pp)_ii; a zero or non-finite
+// pivot sets *bad
+__global__ void __launch_bounds__(B)
+k_scale_rows_inv_diag(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                      const double* __restrict__ pp, double* __restrict__ v, int32_t* __restrict__ bad) {
+    const int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n) return;
+    double d = 0.0;
+    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q)
+        if (col[q] == i) d = pp[q];
+    if (!(fabs(d) > 0.0 && fabs(d) <= DBL_MAX)) {
+        *bad = 1;
+        return;
+    }
+    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) v[q] = v[q] / d;
+}
+
+// C <- A - C on C's pattern (sorted rows); an entry of A outside it sets *bad
+__global__ void __launch_bounds__(B)
+k_sub_from(int32_t n, const int32_t* __restrict__ crp, const int32_t* __restrict__ ccol, double* __restrict__ cval,
+           const int32_t* __restrict__ arp, const int32_t* __restrict__ acol, const double* __restrict__ aval,
+           int32_t* __restrict__ bad) {
+    const int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n) return;
+    const int32_t e = crp[i + 1];
+    for (int32_t q = crp[i]; q < e; ++q) cval[q] = -cval[q];
+    int32_t qc = crp[i];
+    for (int32_t k = arp[i]; k < arp[i + 1]; ++k) {
+        const int32_t j = acol[k];
+        while (qc < e && ccol[qc] < j) ++qc;
+        if (qc < e && ccol[qc] == j) cval[qc] += aval[k];
+        else *bad = 1;
+    }
+}
+
+// S_diag = A_TT - A_Tp diag(A_pp)^{-1} A_pT on the distance-two pattern of the stencil
+static void schur_diag(const tp_jacobian& J, Csr& S, hipStream_t s) {
+    const int32_t n = J.n;
+    Csr Tp, DpT;
+    copy_csr_in(Tp, n, J.rowptr, J.col, J.Tp, s);
+    copy_csr_in(DpT, n, J.rowptr, J.col, J.pT, s);
+    DBuf<int32_t> flags(2, s);
+    TP_LAUNCH(k_fill_i32, 1, B, 0, s, flags.p, 0, (int64_t)2);
+    TP_LAUNCH(k_scale_rows_inv_diag, cdiv(n, B), B, 0, s, n, J.rowptr, J.col, J.pp, DpT.val.p, flags.p);
+    spgemm(Tp, DpT, S, flags.p + 1, s);
+    TP_LAUNCH(k_sub_from, cdiv(n, B), B, 0, s, n, S.rowptr.p, S.col.p, S.val.p, J.rowptr, J.col, J.TT, flags.p);
+    int32_t f[2] = {0, 0};
+    TP_HIP(hipMemcpyAsync(f, flags.p, sizeof(f), hipMemcpyDeviceToHost, s));
+    TP_HIP(hipStreamSynchronize(s));
+    if (f[1]) fail(TP_ERR_NUMERIC, "schur_diag: product row exceeds the SpGEMM table");
+    if (f[0]) fail(TP_ERR_NUMERIC, "schur_diag: zero or non-finite A_pp diagonal, or A_TT outside the product pattern");
+}
+
 }  // namespace tp
 
 extern "C" {
@@ -1594,6 +1648,20 @@ int amg_setup(int32_t n, const int32_t* rowptr, const int32_t* col, const double
             throw;
         }
         *out = h;
+    });
+    return TP_OK;
+}
+
+int amg_setup_schur_diag(const tp_jacobian* J, const tp_amg_params* params, tp_amg_t* out, void* stream) {
+    TP_GUARD({
+        TP_CHECK_ARG(J && out && params, "amg_setup_schur_diag: null argument");
+        *out = nullptr;
+        TP_CHECK_ARG(J->n >= 1 && J->rowptr && J->col && J->pp && J->pT && J->Tp && J->TT,
+                     "amg_setup_schur_diag: empty or null Jacobian");
+        hipStream_t s = (hipStream_t)stream;
+        tp::Csr S;
+        tp::schur_diag(*J, S, s);
+        return amg_setup(J->n, S.rowptr.p, S.col.p, S.val.p, params, out, stream);  // copies S
     });
     return TP_OK;
 }

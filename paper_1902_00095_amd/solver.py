@@ -20,6 +20,10 @@ class SolveConfig:
     variant: str = "lower"
     storage: int = 0              # 0 FP64 hierarchy, 1 FP32, 2 FP32 with BF16 off-diagonals
     amg: tps.AmgParams = dataclasses.field(default_factory=tps.AmgParams)
+    # Schur approximation the second hierarchy is built on: "T" the paper's
+    # S~_T (eq. Se), "ATT" the energy block A_TT alone, "diag"
+    # A_TT - A_Tp diag(A_pp)^{-1} A_pT (the simple forms it is compared with)
+    schur: str = "T"
 
 
 def to_device(prob, device="cuda"):
@@ -45,6 +49,16 @@ def _side_streams():
     return _side[dev]
 
 
+def _schur_amg(J, cfg, prm, stream=None):
+    if cfg.schur == "T":
+        return tps.AMG(J.rowptr, J.col, J.S, prm, stream=stream)
+    if cfg.schur == "ATT":
+        return tps.AMG(J.rowptr, J.col, J.TT, prm, stream=stream)
+    if cfg.schur == "diag":
+        return tps.AMG.schur_diag(J, prm, stream=stream)
+    raise ValueError(f"unknown Schur approximation {cfg.schur!r}")
+
+
 def setup(J, cfg: SolveConfig, concurrent: bool = True):
     """Both hierarchies; with `concurrent`, built at the same time on two
     streams from two host threads (the two setups are independent; each
@@ -56,7 +70,7 @@ def setup(J, cfg: SolveConfig, concurrent: bool = True):
     p_S = dataclasses.replace(cfg.amg, restriction=1, storage=cfg.storage)
     if not concurrent:
         a_pp = tps.AMG(J.rowptr, J.col, J.pp, p_pp)
-        a_S = tps.AMG(J.rowptr, J.col, J.S, p_S)
+        a_S = _schur_amg(J, cfg, p_S)
         return a_pp, a_S, tps.Precond(J, a_pp, a_S, cfg.variant)
     s1, s2 = _side_streams()
     ev = torch.cuda.Event()
@@ -65,15 +79,15 @@ def setup(J, cfg: SolveConfig, concurrent: bool = True):
     s2.wait_event(ev)
     out, err = {}, []
 
-    def run(key, vals, prm, st):
+    def run(key, build, st):
         try:
-            out[key] = tps.AMG(J.rowptr, J.col, vals, prm, stream=st)
+            out[key] = build(st)
         except Exception as e:        # re-raised below
             err.append(e)
 
-    th = threading.Thread(target=run, args=("S", J.S, p_S, s2))
+    th = threading.Thread(target=run, args=("S", lambda st: _schur_amg(J, cfg, p_S, st), s2))
     th.start()
-    run("pp", J.pp, p_pp, s1)
+    run("pp", lambda st: tps.AMG(J.rowptr, J.col, J.pp, p_pp, stream=st), s1)
     th.join()
     if err:
         raise err[0]

@@ -74,7 +74,7 @@ class _Allocator(C.Structure):
     _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", C.c_void_p)]
 
 
-EXPORTS = ["tp_last_error", "tp_init", "tp_jacobian_sizes", "assemble_tpfa", "amg_setup",
+EXPORTS = ["tp_last_error", "tp_init", "tp_jacobian_sizes", "assemble_tpfa", "amg_setup", "amg_setup_schur_diag",
            "amg_num_levels", "amg_level_info", "amg_level_format", "amg_level_copy", "amg_vcycle", "amg_destroy",
            "precond_create", "precond_apply", "precond_destroy", "fgmres_solve",
            "cnn_create", "cnn_get_params", "cnn_get_grad", "cnn_destroy", "cnn_forward", "cnn_loss_grad",
@@ -258,6 +258,21 @@ class AMG:
         _check(lib.amg_setup(C.c_int32(self.n), _ptr(rowptr), _ptr(col), _ptr(val), C.byref(pc),
                              C.byref(h), _stream(stream)))
         self.h = h
+
+    @classmethod
+    def schur_diag(cls, J: "Jacobian", params: AmgParams | None = None, stream=None):
+        """Hierarchy of S_diag = A_TT - A_Tp diag(A_pp)^{-1} A_pT (formed on the device)."""
+        lib = load()
+        self = cls.__new__(cls)
+        self.params = params or AmgParams()
+        self.n = J.n
+        self._keep = (J.rowptr, J.col, J)    # (device of the first: level copies)
+        h = C.c_void_p()
+        pc = self.params.c()
+        jc = J.c()
+        _check(lib.amg_setup_schur_diag(C.byref(jc), C.byref(pc), C.byref(h), _stream(stream)))
+        self.h = h
+        return self
 
     def close(self):
         if getattr(self, "h", None) and self.h.value:
