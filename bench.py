@@ -102,6 +102,11 @@ def _apply_numbers(prob, dev, cfg):
     return out
 
 
+def _progress(msg):
+    """One line per finished stage on stderr (the JSON result stays the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def run_variants(prob, dev, cfg, iters64, ms64):
     """Mixed precision at the benchmark workload and at 128x128x64 (where the
     fine levels dominate the V-cycle); the learned smoother trained here on
@@ -119,6 +124,7 @@ def run_variants(prob, dev, cfg, iters64, ms64):
     out["fp64"] = r64
     out["fp32_hierarchy"] = r32
     out["bf16_offdiag_hierarchy"] = r16
+    _progress("W2 storage variants done")
     # 128x128x64 (2.1M unknowns): FP64 and FP32 hierarchy, V-cycle throughput
     p3 = synth.make_problem("W3")
     d3 = solver.to_device(p3)
@@ -130,6 +136,7 @@ def run_variants(prob, dev, cfg, iters64, ms64):
     w64.update(_apply_numbers(p3, d3, cfg))
     w32.update(_apply_numbers(p3, d3, dc.replace(cfg, storage=1)))
     w16.update(_apply_numbers(p3, d3, dc.replace(cfg, storage=2)))
+    _progress("W3 done")
     out["W3_128x128x64"] = {"fp64": w64, "fp32_hierarchy": w32, "bf16_offdiag_hierarchy": w16,
                             "note": "FP32 error is against the FP64 GPU solution at the same rtol"}
     del d3, y64, y32, y16
@@ -156,6 +163,7 @@ def run_variants(prob, dev, cfg, iters64, ms64):
                                         "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
                                         "seconds": round(train_s, 2)},
                            "plain_fp64": e_plain, "learned_fp64": e_learn, "mixed_learned": e_mixl}
+    _progress("learned smoother trained and evaluated")
     # the simple Schur approximations the paper compares S~_T with (W2)
     sch = {}
     for key in ("T", "ATT", "diag"):
@@ -170,6 +178,7 @@ def run_variants(prob, dev, cfg, iters64, ms64):
     for key, c5, nt in (("fp64", cfg, None), ("fp32_hierarchy", dc.replace(cfg, storage=1), None),
                         ("mixed_learned", dc.replace(cfg, storage=1), net)):
         _, st5 = solver.simulate(p5, c5, nc, net=nt)
+        _progress(f"W5 {key}: {st5['solves']} solves, {st5['total_s']:.1f} s")
         st5.pop("newton_per_step", None)
         w5[key] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st5.items()}
     out["W5_256x256x64_20_steps"] = dict(w5, note="per Newton iteration: assembly, both AMG setups, FGMRES to rtol; "
@@ -303,6 +312,7 @@ def main():
         if cur == rec["source_sha256"]:   # counters taken on this kernel text
             traffic = round(rec["traffic_bytes_per_launch"])
 
+    _progress(f"timed solves done: {ms_per_step:.3f} ms/solve")
     variants = {}
     if not args.no_variants:
         variants = run_variants(prob, dev, cfg, infos[-1]["iters"], ms_per_step)
@@ -353,6 +363,7 @@ def main():
 
     if not args.no_cpu_baseline:
         import oracle
+        _progress("CPU oracle solve started")
         oracle.build(force=False)
         tc = time.perf_counter()
         Jo = oracle.jacobian(prob)
