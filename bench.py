@@ -102,6 +102,54 @@ def _apply_numbers(prob, dev, cfg):
     return out
 
 
+# The roofline kernel's HBM traffic record: scaled FETCH_SIZE + WRITE_SIZE per
+# dispatch from two rocprofv3 --pmc runs of `bench.py --quick`, keyed by a hash
+# of the kernel's source text (reported only while the text is unchanged).
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_k_cheb_step_dia_W2.json")
+TRAFFIC_KERNEL = "k_cheb_step_dia_r<double, double, 7, 128, 2>"
+TRAFFIC_SRC = "paper_1902_00095_amd/csrc/tp_vcycle.hip"
+TRAFFIC_START = "// R consecutive rows per thread"
+TRAFFIC_END = ("template <typename T, typename V, int ND, int VBk, int R>\n__global__ void __launch_bounds__(VBk)\n"
+               "k_residual_dia_r")
+CALIB_BYTES = 32 * 1024 * 1024 * 8   # the calibration copy reads and writes this many bytes
+
+
+def _kernel_text_hash():
+    import hashlib
+    text = open(os.path.join(ROOT, TRAFFIC_SRC)).read()
+    a, b = text.find(TRAFFIC_START), text.find(TRAFFIC_END)
+    return hashlib.sha256(text[a:b].encode()).hexdigest() if a >= 0 and b > a else ""
+
+
+def write_traffic(fetch_db, write_db):
+    """Per-dispatch counter means of the roofline kernel, each scaled by what the
+    counter reads for the calibration copy (the run's largest dispatch)."""
+    import sqlite3
+    import statistics
+
+    def load(path):
+        cur = sqlite3.connect(path).cursor()
+        vals, top = [], 0.0
+        for name, v in cur.execute("select name, counter_value from pmc_events"):
+            top = max(top, float(v))
+            if TRAFFIC_KERNEL in name:
+                vals.append(float(v))
+        return vals, top
+    vf, cf = load(fetch_db)
+    vw, cw = load(write_db)
+    if not vf or not vw:
+        sys.exit(f"no dispatch of {TRAFFIC_KERNEL} in {fetch_db} / {write_db}")
+    fs, ws = CALIB_BYTES / (cf * 1024), CALIB_BYTES / (cw * 1024)
+    mf, mw = statistics.mean(vf), statistics.mean(vw)
+    rec = dict(kernel=TRAFFIC_KERNEL, workload="W2 64x64x32 FP64", dispatches=len(vf), fetch_kib=mf, write_kib=mw,
+               calibration_fetch_kib=cf, calibration_write_kib=cw, fetch_scale=fs, write_scale=ws,
+               traffic_bytes_per_launch=mf * 1024 * fs + mw * 1024 * ws, source=TRAFFIC_SRC,
+               source_sha256=_kernel_text_hash(), source_start=TRAFFIC_START, source_end=TRAFFIC_END)
+    with open(TRAFFIC_JSON, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
 def _progress(msg):
     """One line per finished stage on stderr (the JSON result stays the only stdout line)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -199,7 +247,12 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--quick", action="store_true",
                     help="one untimed-warmup-free step plus the calibration copy (for counter runs)")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="write the roofline kernel's traffic record from two rocprofv3 --pmc databases and exit")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(*args.write_traffic)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -302,15 +355,10 @@ def main():
     rep_ms, rep_bytes = a_S.time_fine_smoother(400)
     M.close(); a_pp.close(); a_S.close()
     traffic = None
-    tj = os.path.join(ROOT, "profiles", "traffic_k_cheb_step_dia_W2.json")
-    if os.path.exists(tj) and args.workload == "W2" and args.storage == 0:
-        import hashlib
-        rec = json.load(open(tj))
-        text = open(os.path.join(ROOT, rec["source"])).read()
-        a, b = text.find(rec["source_start"]), text.find(rec["source_end"])
-        cur = hashlib.sha256(text[a:b].encode()).hexdigest() if a >= 0 and b > a else ""
-        if cur == rec["source_sha256"]:   # counters taken on this kernel text
-            traffic = round(rec["traffic_bytes_per_launch"])
+    if os.path.exists(TRAFFIC_JSON) and args.workload == "W2" and args.storage == 0:
+        rec = json.load(open(TRAFFIC_JSON))
+        if rec.get("source_sha256") == _kernel_text_hash() and rec.get("kernel") == TRAFFIC_KERNEL:
+            traffic = round(rec["traffic_bytes_per_launch"])   # counters taken on this kernel text
 
     _progress(f"timed solves done: {ms_per_step:.3f} ms/solve")
     variants = {}
@@ -345,7 +393,7 @@ def main():
                    "vcycle_pair_GBps": round(vcycle_gbs, 1),
                    "precond_bytes_per_apply": round(pre_bytes)},
         "variants": variants,
-        "roofline": {"bound": "hbm", "kernel": "k_cheb_step_dia<double,7> (fine-level Chebyshev sweep)",
+        "roofline": {"bound": "hbm", "kernel": "k_cheb_step_dia_r<double,double,7,128,2> (fine-level Chebyshev sweep, two rows per thread)",
                      "achieved": round(rep_bytes / (rep_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(rep_bytes / (rep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "bytes_per_launch": round(rep_bytes),

@@ -179,6 +179,94 @@ k_residual_dia(int32_t n, const V* __restrict__ dv, DiaOff<ND> off, const T* __r
     r[i] = b[i] - dia_dot<T, V, ND>(n, dv, off, diag, x, i);
 }
 
+// R consecutive rows per thread (2, in FP64): every row-indexed stream
+// (diagonals, b, 1/D, d, x at the rows, the outputs) is read and written R
+// elements at a time (16 bytes), which moves the same
+// bytes with 1/R of the memory instructions; the neighbour reads x[i + off]
+// stay per row. Each row's arithmetic is the one-row kernels', term for term,
+// so the results are equal. Used when n is a multiple of R and every
+// row-indexed array is aligned to R elements.
+template <typename X, int R> struct VecR;
+template <> struct VecR<double, 2> { using type = double2; };
+template <typename X, int R>
+__device__ inline void ldr(const X* p, X (&a)[R]) {
+    const typename VecR<X, R>::type v = *(const typename VecR<X, R>::type*)p;
+    const X* e = (const X*)&v;
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[r] = e[r];
+}
+template <typename X, int R>
+__device__ inline void str(X* p, const X (&a)[R]) {
+    typename VecR<X, R>::type v;
+    X* e = (X*)&v;
+#pragma unroll
+    for (int r = 0; r < R; ++r) e[r] = a[r];
+    *(typename VecR<X, R>::type*)p = v;
+}
+
+// (A x)_{i+r}, r < R
+template <typename T, typename V, int ND, int R>
+__device__ inline void dia_dot_r(int32_t n, const V* __restrict__ dv, DiaOff<ND> off, const T* __restrict__ diag,
+                                 const T* __restrict__ x, int32_t i, T (&s)[R]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) s[r] = 0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        V a[R];
+        ldr<V, R>(&dv[(int64_t)d * n + i], a);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            int32_t j = i + r + off.o[d];
+            j = j < 0 ? 0 : (j >= n ? n - 1 : j);  // out-of-range slots hold 0
+            s[r] += (T)a[r] * x[j];
+        }
+    }
+    if (diag) {
+        T g[R], xi[R];
+        ldr<T, R>(&diag[i], g);
+        ldr<T, R>(&x[i], xi);
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[r] += g[r] * xi[r];
+    }
+}
+
+template <typename T, typename V, int ND, int VBk, int R>
+__global__ void __launch_bounds__(VBk)
+k_cheb_step_dia_r(int32_t n, const V* __restrict__ dv, DiaOff<ND> off, const T* __restrict__ diag,
+                  const T* __restrict__ dinv, const T* __restrict__ b, const T* __restrict__ xin,
+                  T* __restrict__ xout, T* __restrict__ d, int first, T theta, T c1, T c2) {
+    const int32_t i = R * (blockIdx.x * VBk + threadIdx.x);
+    if (i >= n) return;  // n is a multiple of R: rows i .. i + R - 1 exist
+    T ax[R], di[R], bi[R], xi[R], dp[R], dn[R], xo[R];
+    dia_dot_r<T, V, ND, R>(n, dv, off, diag, xin, i, ax);
+    ldr<T, R>(&dinv[i], di);
+    ldr<T, R>(&b[i], bi);
+    ldr<T, R>(&xin[i], xi);
+    if (!first) ldr<T, R>(&d[i], dp);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const T rr = di[r] * (bi[r] - ax[r]);
+        dn[r] = first ? rr / theta : c1 * dp[r] + c2 * rr;
+        xo[r] = xi[r] + dn[r];
+    }
+    str<T, R>(&d[i], dn);
+    str<T, R>(&xout[i], xo);
+}
+
+template <typename T, typename V, int ND, int VBk, int R>
+__global__ void __launch_bounds__(VBk)
+k_residual_dia_r(int32_t n, const V* __restrict__ dv, DiaOff<ND> off, const T* __restrict__ diag,
+                 const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ res) {
+    const int32_t i = R * (blockIdx.x * VBk + threadIdx.x);
+    if (i >= n) return;
+    T ax[R], bi[R], o[R];
+    dia_dot_r<T, V, ND, R>(n, dv, off, diag, x, i, ax);
+    ldr<T, R>(&b[i], bi);
+#pragma unroll
+    for (int r = 0; r < R; ++r) o[r] = bi[r] - ax[r];
+    str<T, R>(&res[i], o);
+}
+
 #define TP_ND_DISPATCH(nd, ...)                                 \
     switch (nd) {                                               \
     case 3: { constexpr int NDD = 3; __VA_ARGS__; } break;      \
@@ -251,6 +339,47 @@ k_cheb01_dia(int32_t n, const V* __restrict__ dv, DiaOff<ND> off, const T* __res
     const T dn = c1 * x0 + c2 * r;
     d[i] = dn;
     xout[i] = x0 + dn;
+}
+
+template <typename T, typename V, int ND, int VBk, int R>
+__global__ void __launch_bounds__(VBk)
+k_cheb01_dia_r(int32_t n, const V* __restrict__ dv, DiaOff<ND> off, const T* __restrict__ diag,
+               const T* __restrict__ dinv, const T* __restrict__ b, T* __restrict__ xout, T* __restrict__ d,
+               T theta, T c1, T c2) {
+    const int32_t i = R * (blockIdx.x * VBk + threadIdx.x);
+    if (i >= n) return;
+    T sm[R], di[R], bi[R], x0[R], dn[R], xo[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) sm[r] = 0;
+#pragma unroll
+    for (int q = 0; q < ND; ++q) {
+        V a[R];
+        ldr<V, R>(&dv[(int64_t)q * n + i], a);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            int32_t j = i + r + off.o[q];
+            j = j < 0 ? 0 : (j >= n ? n - 1 : j);
+            sm[r] += (T)a[r] * ((dinv[j] * b[j]) / theta);
+        }
+    }
+    ldr<T, R>(&dinv[i], di);
+    ldr<T, R>(&b[i], bi);
+#pragma unroll
+    for (int r = 0; r < R; ++r) x0[r] = (di[r] * bi[r]) / theta;
+    if (diag) {
+        T g[R];
+        ldr<T, R>(&diag[i], g);
+#pragma unroll
+        for (int r = 0; r < R; ++r) sm[r] += g[r] * x0[r];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const T rr = di[r] * (bi[r] - sm[r]);
+        dn[r] = c1 * x0[r] + c2 * rr;
+        xo[r] = x0[r] + dn[r];
+    }
+    str<T, R>(&d[i], dn);
+    str<T, R>(&xout[i], xo);
 }
 
 // first sweep from a zero guess
@@ -334,6 +463,77 @@ template <> struct LevelVals<M16> {
     static const float* dinv(const Level& L) { return L.dinv32.p; }
 };
 
+// ---- DIA launches: R rows per thread when n and the arrays allow it -------------------
+template <typename X, int R>
+static inline bool alr(const X* p) { return p == nullptr || ((uintptr_t)p % (R * sizeof(X))) == 0; }
+// measured: 128-thread workgroups are faster up to ~131k threads, 256 above
+static inline bool small_grid(int32_t n, int R) { return n / R <= 131072; }
+// rows per thread: 2 in FP64 (16-byte accesses, 8-16% faster sweeps); in FP32 and
+// with BF16 values several rows per thread measured no faster (W3 apply 0.92 ms
+// either way; BF16 0.86 -> 0.96 ms with 4 rows), so one row
+template <typename T>
+static constexpr int rows_per_thread() { return sizeof(T) == 8 ? 2 : 1; }
+
+#define TP_DIA_R_DISPATCH(R_, LAUNCH_R, LAUNCH_1)                                        \
+    do {                                                                                \
+        constexpr int RR = R_;                                                          \
+        if constexpr (RR > 1) {                                                         \
+            if (rows_ok) {                                                              \
+                if (small_grid(n, RR)) { constexpr int BK = 128; LAUNCH_R; }            \
+                else { constexpr int BK = 256; LAUNCH_R; }                              \
+            } else {                                                                    \
+                LAUNCH_1;                                                               \
+            }                                                                           \
+        } else {                                                                        \
+            (void)rows_ok;                                                              \
+            LAUNCH_1;                                                                   \
+        }                                                                               \
+    } while (0)
+
+template <typename T, typename V>
+static void dia_cheb_step(const Level& L, int32_t n, const V* D, const T* dg, const T* dv, const T* b, const T* xin,
+                          T* xout, T* d, int first, T theta, T c1, T c2, hipStream_t s, bool timed, double bytes) {
+    constexpr int R = rows_per_thread<T>();
+    const bool rows_ok = n % R == 0 && alr<V, R>(D) && alr<T, R>(dg) && alr<T, R>(dv) && alr<T, R>(b) &&
+                         alr<T, R>(xin) && alr<T, R>(xout) && alr<T, R>(d);
+    TP_DIA_R_DISPATCH(
+        R,
+        TP_ND_DISPATCH(L.ndia, TP_LAUNCH_TIMED(timed, bytes, (k_cheb_step_dia_r<T, V, NDD, BK, RR>),
+                                               cdiv(n / RR, BK), BK, 0, s, n, D, dia_offsets<NDD>(L), dg, dv, b,
+                                               xin, xout, d, first, theta, c1, c2)),
+        TP_ND_DISPATCH(L.ndia, TP_LAUNCH_TIMED(timed, bytes, (k_cheb_step_dia<T, V, NDD>), cdiv(n, VB), VB, 0, s, n, D,
+                                               dia_offsets<NDD>(L), dg, dv, b, xin, xout, d, first, theta, c1, c2)));
+}
+
+template <typename T, typename V>
+static void dia_cheb01(const Level& L, int32_t n, const V* D, const T* dg, const T* dv, const T* b, T* xout, T* d,
+                       T theta, T c1, T c2, hipStream_t s, bool timed, double bytes) {
+    constexpr int R = rows_per_thread<T>();
+    const bool rows_ok = n % R == 0 && alr<V, R>(D) && alr<T, R>(dg) && alr<T, R>(dv) && alr<T, R>(b) &&
+                         alr<T, R>(xout) && alr<T, R>(d);
+    TP_DIA_R_DISPATCH(
+        R,
+        TP_ND_DISPATCH(L.ndia, TP_LAUNCH_TIMED(timed, bytes, (k_cheb01_dia_r<T, V, NDD, BK, RR>), cdiv(n / RR, BK),
+                                               BK, 0, s, n, D, dia_offsets<NDD>(L), dg, dv, b, xout, d, theta, c1,
+                                               c2)),
+        TP_ND_DISPATCH(L.ndia, TP_LAUNCH_TIMED(timed, bytes, (k_cheb01_dia<T, V, NDD>), cdiv(n, VB), VB, 0, s, n, D,
+                                               dia_offsets<NDD>(L), dg, dv, b, xout, d, theta, c1, c2)));
+}
+
+template <typename T, typename V>
+static void dia_residual(const Level& L, int32_t n, const V* D, const T* dg, const T* b, const T* x, T* r,
+                         hipStream_t s) {
+    constexpr int R = rows_per_thread<T>();
+    const bool rows_ok =
+        n % R == 0 && alr<V, R>(D) && alr<T, R>(dg) && alr<T, R>(b) && alr<T, R>(x) && alr<T, R>(r);
+    TP_DIA_R_DISPATCH(
+        R,
+        TP_ND_DISPATCH(L.ndia, TP_LAUNCH((k_residual_dia_r<T, V, NDD, BK, RR>), cdiv(n / RR, BK), BK, 0, s, n, D,
+                                         dia_offsets<NDD>(L), dg, b, x, r)),
+        TP_ND_DISPATCH(L.ndia, TP_LAUNCH((k_residual_dia<T, V, NDD>), cdiv(n, VB), VB, 0, s, n, D,
+                                         dia_offsets<NDD>(L), dg, b, x, r)));
+}
+
 static inline int grid_rows(int32_t n, int G) { return cdiv((int64_t)std::max(n, 1) * G, VB); }
 
 // smoothing sweeps on level L; x_cur in/out (ping-pong between x and x2)
@@ -374,9 +574,8 @@ static typename M::T* smooth(tp_amg* h, int l, const typename M::T* b, typename 
             const bool timed = l == 0;
             const double bytes = abytes + 4.0 * es * n;
             if (L.ndia) {
-                TP_ND_DISPATCH(L.ndia, TP_LAUNCH_TIMED(timed, bytes, (k_cheb01_dia<T, V, NDD>), cdiv(n, VB), VB, 0, s,
-                                                       n, LevelVals<M>::D(L), dia_offsets<NDD>(L), dg, dv, b, nx, d,
-                                                       (T)theta, (T)c1, (T)c2));
+                dia_cheb01<T, V>(L, n, LevelVals<M>::D(L), dg, dv, b, nx, d, (T)theta, (T)c1, (T)c2, s, timed,
+                                 bytes);
             } else {
                 TP_G_DISPATCH(L.gA, TP_LAUNCH_TIMED(timed, bytes, (k_cheb01<T, V, GG>), grid_rows(n, GG), VB, 0, s, n,
                                                     L.A.rowptr.p, L.A.col.p, av, dg, dv, b, nx, d, (T)theta, (T)c1,
@@ -424,9 +623,8 @@ static typename M::T* smooth(tp_amg* h, int l, const typename M::T* b, typename 
             double bytes = abytes + (first ? 5.0 : 6.0) * es * n;
             const bool timed = l == 0;
             if (L.ndia) {
-                TP_ND_DISPATCH(L.ndia, TP_LAUNCH_TIMED(timed, bytes, (k_cheb_step_dia<T, V, NDD>), cdiv(n, VB), VB, 0,
-                                                       s, n, LevelVals<M>::D(L), dia_offsets<NDD>(L), dg, dv, b, cur,
-                                                       nx, d, first, (T)theta, (T)c1, (T)c2));
+                dia_cheb_step<T, V>(L, n, LevelVals<M>::D(L), dg, dv, b, cur, nx, d, first, (T)theta, (T)c1, (T)c2,
+                                    s, timed, bytes);
             } else {
                 TP_G_DISPATCH(L.gA, TP_LAUNCH_TIMED(timed, bytes, (k_cheb_step<T, V, GG>), grid_rows(n, GG), VB, 0, s,
                                                     n, L.A.rowptr.p, L.A.col.p, av, dg, dv, b, cur, nx, d, first,
@@ -460,8 +658,7 @@ static typename M::T* vcycle_level(tp_amg* h, int l, const typename M::T* b, hip
     // every coarse row that holds it and serialises its gathers)
     T* r = (T*)L.r.p;
     if (L.ndia) {
-        TP_ND_DISPATCH(L.ndia, TP_LAUNCH((k_residual_dia<T, V, NDD>), cdiv(n, VB), VB, 0, s, n, LevelVals<M>::D(L),
-                                         dia_offsets<NDD>(L), LevelVals<M>::diag(L), b, cur, r));
+        dia_residual<T, V>(L, n, LevelVals<M>::D(L), LevelVals<M>::diag(L), b, cur, r, s);
     } else {
         TP_G_DISPATCH(L.gA, TP_LAUNCH((k_residual<T, V, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p,
                                       L.A.col.p, LevelVals<M>::A(L), LevelVals<M>::diag(L), b, cur, r));
@@ -480,9 +677,7 @@ static typename M::T* vcycle_level(tp_amg* h, int l, const typename M::T* b, hip
     if (l == 0 && h->cnn && h->cnn->enabled) {
         // learned post-smoother: r = b - A x; x += s * CNN(features(r))
         if (L.ndia) {
-            TP_ND_DISPATCH(L.ndia, TP_LAUNCH((k_residual_dia<T, V, NDD>), cdiv(n, VB), VB, 0, s, n,
-                                             LevelVals<M>::D(L), dia_offsets<NDD>(L), LevelVals<M>::diag(L), b,
-                                             cur, r));
+            dia_residual<T, V>(L, n, LevelVals<M>::D(L), LevelVals<M>::diag(L), b, cur, r, s);
         } else {
             TP_G_DISPATCH(L.gA, TP_LAUNCH((k_residual<T, V, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p,
                                           L.A.col.p, LevelVals<M>::A(L), LevelVals<M>::diag(L), b, cur, r));
@@ -650,9 +845,8 @@ static double replay_fine_smoother(tp_amg* h, int reps, hipStream_t s, double* b
         T* in = (k & 1) ? xb : xa;
         T* out = (k & 1) ? xa : xb;
         if (L.ndia) {
-            TP_ND_DISPATCH(L.ndia, TP_LAUNCH((k_cheb_step_dia<T, V, NDD>), cdiv(n, VB), VB, 0, s, n,
-                                             LevelVals<M>::D(L), dia_offsets<NDD>(L), dg, dv, b, in, out, d, 0,
-                                             (T)theta, (T)c1, (T)c2));
+            dia_cheb_step<T, V>(L, n, LevelVals<M>::D(L), dg, dv, b, in, out, d, 0, (T)theta, (T)c1, (T)c2, s,
+                                false, 0.0);
         } else {
             TP_G_DISPATCH(L.gA, TP_LAUNCH((k_cheb_step<T, V, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p,
                                           L.A.col.p, LevelVals<M>::A(L), dg, dv, b, in, out, d, 0, (T)theta,
