@@ -152,6 +152,19 @@ int amg_setup(int32_t n, const int32_t* rowptr, const int32_t* col, const double
 int amg_setup_schur_diag(const tp_jacobian* J, const tp_amg_params* params, tp_amg_t* out,
                          void* stream);
 
+/* Reuse of a hierarchy across Newton iterations (the setup is the largest
+ * part of a single solve): new values `val` (device, nnz of level 0) for the
+ * finest-level operator, on the pattern the hierarchy was built on.  The
+ * operator and what is derived from it alone are rewritten in place (l1
+ * diagonal, stencil-diagonal copy, reduced-precision copies, an attached
+ * learned smoother's static features; the dense inverse when level 0 is the
+ * coarsest); the coarse levels, P and R are kept, so the V-cycle becomes a
+ * preconditioner lagged on the coarse levels.  Preconditioner handles and
+ * their captured graphs built on this hierarchy stay valid.  Not for
+ * hierarchies from amg_setup_schur_diag (their level 0 has its own pattern).
+ * Synchronises `stream`. */
+int amg_refresh_fine(tp_amg_t amg, const double* val, void* stream);
+
 int amg_num_levels(tp_amg_t amg, int32_t* nlev);
 /* sizes of level l (P/R sizes are 0 on the coarsest level) */
 int amg_level_info(tp_amg_t amg, int32_t level, int32_t* n, int32_t* nnzA,

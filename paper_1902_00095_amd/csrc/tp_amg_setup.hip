@@ -1230,7 +1230,7 @@ static void build_coarse_inverse(tp_amg* h, const Csr& A, hipStream_t s) {
     const int32_t n = A.n;
     h->nc = n;
     if (n > 4096) fail(TP_ERR_NUMERIC, "coarsening stalled at %d rows (> 4096), no dense factorisation", n);
-    h->cinv.alloc((size_t)n * n, s);
+    if (h->cinv.n != (size_t)n * n) h->cinv.alloc((size_t)n * n, s);  // kept on a refresh (graphs hold it)
     if (n == 0) return;
     DBuf<double> W((size_t)n * n, s), T((size_t)16 * n, s), binv(BG_NB * BG_NB, s), U(BG_NB * BG_NB, s),
         Wk((size_t)BG_NB * n, s);
@@ -1612,6 +1612,61 @@ static void schur_diag(const tp_jacobian& J, Csr& S, hipStream_t s) {
     if (f[0]) fail(TP_ERR_NUMERIC, "schur_diag: zero or non-finite A_pp diagonal, or A_TT outside the product pattern");
 }
 
+// ---- refreshing the finest level (hierarchy reuse across Newton iterations) -------------
+struct DiaOffs {
+    int32_t o[7];
+};
+
+__global__ void __launch_bounds__(B)
+k_dia_refill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+             const double* __restrict__ val, int nd, DiaOffs offs, double* __restrict__ dia) {
+    int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n) return;
+    for (int d = 0; d < nd; ++d) dia[(int64_t)d * n + i] = 0.0;
+    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+        const int32_t o = col[q] - i;
+        for (int d = 0; d < nd; ++d)
+            if (offs.o[d] == o) dia[(int64_t)d * n + i] = val[q];
+    }
+}
+
+// New values for level 0 (same pattern as at setup): the operator and
+// everything derived from it alone (l1 diagonal, DIA copy, reduced-precision
+// copies, the learned smoother's static features; the dense inverse when
+// level 0 is the coarsest), all rewritten in place so that captured graphs of
+// the V-cycle stay valid. Coarser levels, P and R are kept.
+static void refresh_fine(tp_amg* h, const double* val, hipStream_t s) {
+    Level& L = h->lev[0];
+    const int32_t n = L.A.n;
+    const int64_t nnz = L.A.nnz;
+    TP_HIP(hipMemcpyAsync(L.A.val.p, val, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
+    TP_LAUNCH(k_l1_dinv, cdiv(n, B), B, 0, s, n, L.A.rowptr.p, L.A.val.p, L.dinv.p);
+    const int64_t nd_n = (int64_t)L.ndia * n;
+    if (L.ndia) {
+        DiaOffs o{};
+        for (int d = 0; d < L.ndia; ++d) o.o[d] = L.dia_off[d];
+        TP_LAUNCH(k_dia_refill, cdiv(n, B), B, 0, s, n, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.ndia, o, L.dia.p);
+    }
+    if (h->prm.storage >= 1) {
+        TP_LAUNCH(k_to_f32, cdiv(n, B), B, 0, s, (int64_t)n, L.dinv.p, L.dinv32.p);
+        if (h->prm.storage == 1) {
+            TP_LAUNCH(k_to_f32, cdiv(nnz, B), B, 0, s, nnz, L.A.val.p, L.A32.p);
+            if (L.ndia) TP_LAUNCH(k_to_f32, cdiv(nd_n, B), B, 0, s, nd_n, L.dia.p, L.dia32.p);
+        } else {
+            TP_LAUNCH(k_split_bf16_csr, cdiv(n, B), B, 0, s, n, L.A.rowptr.p, L.A.col.p, L.A.val.p,
+                      (__bf16*)L.A16.p, L.diag32.p);
+            if (L.ndia) {
+                int d0 = -1;
+                for (int d = 0; d < L.ndia; ++d)
+                    if (L.dia_off[d] == 0) d0 = d;
+                TP_LAUNCH(k_split_bf16_dia, cdiv(nd_n, B), B, 0, s, nd_n, n, d0, L.dia.p, (__bf16*)L.dia16.p);
+            }
+        }
+    }
+    if (h->lev.size() == 1) build_coarse_inverse(h, L.A, s);
+    if (h->cnn) cnn_attach_refresh(h->cnn.get(), L.A.rowptr.p, L.A.col.p, L.A.val.p, s);
+}
+
 }  // namespace tp
 
 extern "C" {
@@ -1662,6 +1717,16 @@ int amg_setup_schur_diag(const tp_jacobian* J, const tp_amg_params* params, tp_a
         tp::Csr S;
         tp::schur_diag(*J, S, s);
         return amg_setup(J->n, S.rowptr.p, S.col.p, S.val.p, params, out, stream);  // copies S
+    });
+    return TP_OK;
+}
+
+int amg_refresh_fine(tp_amg_t amg, const double* val, void* stream) {
+    TP_GUARD({
+        TP_CHECK_ARG(amg && val, "amg_refresh_fine: null argument");
+        hipStream_t s = (hipStream_t)stream;
+        tp::refresh_fine(amg, val, s);
+        TP_HIP(hipStreamSynchronize(s));
     });
     return TP_OK;
 }

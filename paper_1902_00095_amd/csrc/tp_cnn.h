@@ -54,4 +54,6 @@ void transpose(const int32_t* rowptr, const int32_t* col, const double* val, int
                int32_t nnz, bool sorted, Csr& T, hipStream_t s);
 void cnn_attach_build(tp_cnn_attach* a, const tp_grid& g, const int32_t* rowptr, const int32_t* col,
                       const double* val, hipStream_t s);
+void cnn_attach_refresh(tp_cnn_attach* a, const int32_t* rowptr, const int32_t* col, const double* val,
+                        hipStream_t s);
 }  // namespace tp

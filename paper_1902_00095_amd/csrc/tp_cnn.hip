@@ -606,6 +606,15 @@ void cnn_attach_build(tp_cnn_attach* a, const tp_grid& g, const int32_t* rowptr,
     TP_LAUNCH(k_feat_static, cdiv(n, CB), CB, 0, s, g, rowptr, col, val, a->feat.p, a->dinv.p);
 }
 
+// new values of the level operator (same pattern): static feature channels and
+// 1/D again, in place; the transpose kept for the training loss is dropped
+void cnn_attach_refresh(tp_cnn_attach* a, const int32_t* rowptr, const int32_t* col, const double* val,
+                        hipStream_t s) {
+    const int32_t n = a->g.nx * a->g.ny * a->g.nz;
+    TP_LAUNCH(k_feat_static, cdiv(n, CB), CB, 0, s, a->g, rowptr, col, val, a->feat.p, a->dinv.p);
+    a->At = Csr{};
+}
+
 }  // namespace tp
 
 extern "C" {

@@ -33,9 +33,10 @@ def to_device(prob, device="cuda"):
                 x_k=t(prob.x_k))
 
 
-def assemble(prob, dev):
+def assemble(prob, dev, J=None, G=None):
+    """G(x_k) and the Jacobian; into the buffers of J and G when given."""
     return tps.assemble_tpfa(prob.grid, prob.props, dev["K"], dev["phi"], dev["kappa"],
-                             prob.wells, prob.dt, dev["x_prev"], dev["x_k"])
+                             prob.wells, prob.dt, dev["x_prev"], dev["x_k"], J=J, G=G)
 
 
 _side = {}
@@ -108,67 +109,97 @@ class NewtonConfig:
     """Backward-Euler time stepping with Newton's method on G(x) = 0 (Section
     2.2: one Jacobian solve per Newton iteration; Section 5: a Newton
     iteration has converged when the function norm relative to the step's
-    first one, or the step norm relative to the iterate's, is below 1e-8)."""
+    first one, or the step norm relative to the iterate's, is below 1e-8).
+    reuse: build both hierarchies at a step's first Newton iteration only and
+    refresh their finest level at the later ones (coarse levels lagged)."""
     steps: int = 20
     max_newton: int = 4
     rtol_f: float = 1e-8
     rtol_dx: float = 1e-8
+    reuse: bool = False
+
+
+def _schur_values(J, cfg):
+    return {"T": J.S, "ATT": J.TT}.get(cfg.schur)
 
 
 def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None):
     """Run `ncfg.steps` time steps of `prob` from its x_prev.  Each Newton
-    iteration assembles at the current iterate, builds both hierarchies
-    (attaching `net` to the Schur hierarchy when given) and solves J dx = -G
-    to `cfg.rtol`.  Returns (x, stats): the final state (device, interleaved)
-    and per-run counts and times."""
+    iteration assembles at the current iterate (into the same Jacobian
+    buffers), builds both hierarchies (or, with `ncfg.reuse`, refreshes their
+    finest level after a step's first iteration; `net` attached to the Schur
+    hierarchy when given) and solves J dx = -G to `cfg.rtol`.  Returns (x,
+    stats): the final state (device, interleaved) and per-run counts and
+    times."""
     import time
 
     import torch
     dev = to_device(prob)
     x = dev["x_prev"].clone()
     dev["x_k"] = x
-    newton, lin, solves, unconverged = 0, 0, 0, 0
+    newton, lin, solves, unconverged, builds = 0, 0, 0, 0, 0
     solve_s = 0.0
     per_step = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for step in range(ncfg.steps):
-        dev["x_prev"] = x.clone()
-        g0 = None
-        its = 0
-        done = False
-        for k in range(ncfg.max_newton + 1):
-            J, G = assemble(prob, dev)
-            gn = float(torch.linalg.vector_norm(G))
-            if g0 is None:
-                g0 = gn
-            if gn <= ncfg.rtol_f * g0 or done or k == ncfg.max_newton:
-                if not (gn <= ncfg.rtol_f * g0 or done):
-                    unconverged += 1
-                break
-            torch.cuda.synchronize()
-            ts = time.perf_counter()
-            a_pp, a_S, M = setup(J, cfg)
-            if net is not None:
-                a_S.attach(net, prob.grid)
-            dx, st = tps.fgmres_solve(J, M, -G, rtol=cfg.rtol, restart=cfg.restart, maxit=cfg.maxit)
-            torch.cuda.synchronize()
-            solve_s += time.perf_counter() - ts
+    J = G = None
+    hier = None
+
+    def close(h):
+        if h is not None:
+            a_pp, a_S, M = h
             if net is not None:
                 a_S.attach(None, None)
             M.close(); a_pp.close(); a_S.close()
-            x += dx
-            its += 1
-            lin += st["iters"]
-            solves += 1
-            done = float(torch.linalg.vector_norm(dx)) <= ncfg.rtol_dx * float(torch.linalg.vector_norm(x))
-        newton += its
-        per_step.append(its)
-        if log:
-            log(f"step {step}: newton {its}, |G|/|G0| {gn / g0 if g0 else 0.0:.2e}")
+
+    reusable = ncfg.reuse and cfg.schur in ("T", "ATT")   # S_diag has a pattern of its own
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    try:
+        for step in range(ncfg.steps):
+            dev["x_prev"] = x.clone()
+            g0 = None
+            its = 0
+            done = False
+            for k in range(ncfg.max_newton + 1):
+                J, G = assemble(prob, dev, J, G)
+                gn = float(torch.linalg.vector_norm(G))
+                if g0 is None:
+                    g0 = gn
+                if gn <= ncfg.rtol_f * g0 or done or k == ncfg.max_newton:
+                    if not (gn <= ncfg.rtol_f * g0 or done):
+                        unconverged += 1
+                    break
+                torch.cuda.synchronize()
+                ts = time.perf_counter()
+                if hier is not None and reusable and k > 0:
+                    hier[0].refresh_fine(J.pp)
+                    hier[1].refresh_fine(_schur_values(J, cfg))
+                else:
+                    close(hier)
+                    hier = None
+                    hier = setup(J, cfg)
+                    builds += 1
+                    if net is not None:
+                        hier[1].attach(net, prob.grid)
+                dx, st = tps.fgmres_solve(J, hier[2], -G, rtol=cfg.rtol, restart=cfg.restart, maxit=cfg.maxit)
+                torch.cuda.synchronize()
+                solve_s += time.perf_counter() - ts
+                if not reusable:
+                    close(hier)
+                    hier = None
+                x += dx
+                its += 1
+                lin += st["iters"]
+                solves += 1
+                done = float(torch.linalg.vector_norm(dx)) <= ncfg.rtol_dx * float(torch.linalg.vector_norm(x))
+            newton += its
+            per_step.append(its)
+            if log:
+                log(f"step {step}: newton {its}, |G|/|G0| {gn / g0 if g0 else 0.0:.2e}")
+    finally:
+        close(hier)
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     return x, dict(steps=ncfg.steps, newton_iters=newton, linear_iters=lin, solves=solves,
-                   unconverged_steps=unconverged, newton_per_step=per_step,
+                   hierarchy_builds=builds, unconverged_steps=unconverged, newton_per_step=per_step,
                    linear_per_newton=lin / max(newton, 1), total_s=total,
                    ms_per_solve=1e3 * solve_s / max(solves, 1))

@@ -74,7 +74,7 @@ class _Allocator(C.Structure):
     _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", C.c_void_p)]
 
 
-EXPORTS = ["tp_last_error", "tp_init", "tp_jacobian_sizes", "assemble_tpfa", "amg_setup", "amg_setup_schur_diag",
+EXPORTS = ["tp_last_error", "tp_init", "tp_jacobian_sizes", "assemble_tpfa", "amg_setup", "amg_setup_schur_diag", "amg_refresh_fine",
            "amg_num_levels", "amg_level_info", "amg_level_format", "amg_level_copy", "amg_vcycle", "amg_destroy",
            "precond_create", "precond_apply", "precond_destroy", "fgmres_solve",
            "cnn_create", "cnn_get_params", "cnn_get_grad", "cnn_destroy", "cnn_forward", "cnn_loss_grad",
@@ -273,6 +273,11 @@ class AMG:
         _check(lib.amg_setup_schur_diag(C.byref(jc), C.byref(pc), C.byref(h), _stream(stream)))
         self.h = h
         return self
+
+    def refresh_fine(self, val, stream=None):
+        """New finest-level values on the same pattern; coarse levels kept."""
+        self._keep = self._keep[:2] + (val,)
+        _check(_lib.amg_refresh_fine(self.h, _ptr(val), _stream(stream)))
 
     def close(self):
         if getattr(self, "h", None) and self.h.value:

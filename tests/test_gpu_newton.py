@@ -23,13 +23,19 @@ def _init():
     yield
 
 
-@pytest.mark.parametrize("storage", [0, 1])
-def test_newton_time_steps_match_oracle(storage):
-    say("newton", storage)
+@pytest.mark.parametrize("storage,reuse", [(0, False), (1, False), (0, True), (1, True)])
+def test_newton_time_steps_match_oracle(storage, reuse):
+    """With hierarchy reuse the later Newton iterations of a step run on
+    hierarchies refreshed on the finest level only; the Newton root, and so
+    the states, must not change."""
+    say("newton", storage, reuse)
     p = synth.make_problem("W5", grid=synth.Grid(16, 16, 8, 1.0, 1.0, 1.0))
     steps = 2
     xo, its_o, _ = oracle.newton_simulate(p, steps)
-    x, st = solver.simulate(p, solver.SolveConfig(storage=storage), solver.NewtonConfig(steps=steps))
+    x, st = solver.simulate(p, solver.SolveConfig(storage=storage, amg=tps.AmgParams(coarse_max=200)),
+                            solver.NewtonConfig(steps=steps, reuse=reuse))
+    if reuse:
+        assert st["hierarchy_builds"] == steps < st["solves"]
     xg = x.cpu().numpy()
     say(f"  newton per step gpu {st['newton_per_step']} oracle {its_o}, linear/newton {st['linear_per_newton']:.1f}")
     assert st["unconverged_steps"] == 0
@@ -40,3 +46,35 @@ def test_newton_time_steps_match_oracle(storage):
         chg = np.linalg.norm(ref - p.x_prev[blk::2]) / np.linalg.norm(ref)
         say(f"  block {blk}: rel err {err:.2e} (state change over the run {chg:.2e})")
         assert err <= 1e-9
+
+
+def test_refresh_fine_in_place():
+    """Refreshing the finest level with the values it was built on leaves the
+    V-cycle bit for bit unchanged; with another state's values the level-0
+    operator reads back as the new values and the V-cycle changes; refreshing
+    back restores the original V-cycle exactly.  Both the pressure hierarchy
+    (Galerkin) and the Schur one (Petrov-Galerkin), FP64 and FP32."""
+    import torch
+    say("refresh fine")
+    p = synth.make_problem("W2", grid=synth.Grid(20, 18, 10, 1.0, 1.0, 1.0))
+    d = solver.to_device(p)
+    J1, _ = solver.assemble(p, d)
+    d2 = dict(d)
+    d2["x_k"] = d["x_k"] + 0.01 * torch.abs(d["x_k"]) * torch.randn(d["x_k"].shape, dtype=torch.float64,
+                                                                      device="cuda", generator=torch.Generator(device="cuda").manual_seed(3))
+    J2, _ = solver.assemble(p, d2)
+    b = torch.as_tensor(synth.random_rhs(5, J1.n), device="cuda")
+    for storage in (0, 1):
+        for which, restr in (("pp", 0), ("S", 1)):
+            v1, v2 = getattr(J1, which), getattr(J2, which).clone()
+            a = tps.AMG(J1.rowptr, J1.col, v1.clone(), tps.AmgParams(restriction=restr, storage=storage, coarse_max=64))
+            assert a.nlev >= 2
+            y0 = a.vcycle(b).cpu().numpy()
+            a.refresh_fine(v1.clone())
+            assert np.array_equal(a.vcycle(b).cpu().numpy(), y0)
+            a.refresh_fine(v2)
+            assert np.array_equal(a.level(0)["A_val"].cpu().numpy(), v2.cpu().numpy())
+            assert not np.array_equal(a.vcycle(b).cpu().numpy(), y0)
+            a.refresh_fine(v1.clone())
+            assert np.array_equal(a.vcycle(b).cpu().numpy(), y0), (storage, which)
+            a.close()

@@ -135,7 +135,9 @@ def test_oracle_coarsening_on_gpu_levels(case):
             assert np.array_equal(ho.level(0)["cf"], np_(L["cf"])), (which, l)
 
 
-@pytest.mark.parametrize("case", ["W1", "W2s"])
+# W1 and W2s have an even cell count (the FP64 stencil kernels take two rows
+# per thread), W2g (9x7x11) an odd one (one row per thread)
+@pytest.mark.parametrize("case", ["W1", "W2s", "W2g"])
 @pytest.mark.parametrize("smoother", [0, 1])
 @pytest.mark.parametrize("cm", [SMALL, CM])
 def test_vcycle_matches_oracle(case, smoother, cm):
