@@ -32,14 +32,15 @@ struct tp_prec {
     tp::Gmres* ws = nullptr;  // FGMRES workspace kept across solves of the same size
     // The split-vector apply captured once as a HIP graph (kernels only, no
     // stream-specific state) on fixed staging vectors rin -> zout.
-    // Captured on a private stream (capture is not allowed on the legacy
-    // null stream that callers often pass).
     hipGraphExec_t gexec = nullptr;
     // the same with the learned post-smoother of the Schur hierarchy enabled,
     // valid for the attachment numbered gen_cnn
     hipGraphExec_t gexec_cnn = nullptr;
     uint64_t gen_cnn = 0;
-    hipStream_t cap = nullptr;
+    // the stream of the handle's last launch (one stream so far: its
+    // synchronisation suffices at destruction; several: the device's)
+    hipStream_t last = nullptr;
+    bool used = false, multi = false;
     tp::DBuf<double> rin, zout;
     tp_jacobian J;
     tp_amg* pp = nullptr;
@@ -380,6 +381,25 @@ void prec_apply_split(tp_prec* M, const double* r, double* z, hipStream_t s) {
 }
 
 // ---- graph of the preconditioner apply -------------------------------------------------------
+static void note_stream(tp_prec* M, hipStream_t s) {
+    if (M->used && s != M->last) M->multi = true;
+    M->last = s;
+    M->used = true;
+}
+
+// Capture runs on a non-blocking stream of its own (capture is not allowed on
+// the legacy null stream that callers often pass): one per host thread and
+// device, created on first use and kept for the process lifetime (creating
+// and destroying one per preconditioner cost ~0.2 ms a solve).
+static hipStream_t capture_stream() {
+    int dev = 0;
+    TP_HIP(hipGetDevice(&dev));
+    thread_local std::vector<hipStream_t> cs;
+    if ((int)cs.size() <= dev) cs.resize(dev + 1, nullptr);
+    if (!cs[dev]) TP_HIP(hipStreamCreateWithFlags(&cs[dev], hipStreamNonBlocking));
+    return cs[dev];
+}
+
 // (a learned smoother on the pressure hierarchy, which the solver never
 // switches off, and the smoother timer keep the apply eager)
 static bool graph_usable(tp_prec* M) { return !(M->pp->cnn && M->pp->cnn->enabled) && !timer().on; }
@@ -404,8 +424,7 @@ static hipGraphExec_t graph_ensure(tp_prec* M, hipStream_t s, bool with_cnn) {
         M->rin.alloc(2 * (size_t)n, s);
         M->zout.alloc(2 * (size_t)n, s);
     }
-    if (!M->cap) TP_HIP(hipStreamCreateWithFlags(&M->cap, hipStreamNonBlocking));
-    const hipStream_t c = M->cap;
+    const hipStream_t c = capture_stream();
     tp_cnn_attach* a = M->S->cnn.get();
     const bool was = a && a->enabled;
     if (a) a->enabled = with_cnn;
@@ -506,6 +525,7 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
                   const tp_krylov_params& kp, tp_krylov_stats* st, double* history, hipStream_t s) {
     const int32_t n = J.n;
     const int m = kp.restart;
+    note_stream(M, s);
     if (!M->ws || M->ws->n != n || M->ws->m != m) {
         if (M->ws) {
             TP_HIP(hipDeviceSynchronize());
@@ -666,6 +686,7 @@ int precond_apply(tp_prec_t M, const double* r, double* z, void* stream) {
         TP_CHECK_ARG(M && r && z, "precond_apply: null argument");
         hipStream_t s = (hipStream_t)stream;
         const int32_t n = M->J.n;
+        tp::note_stream(M, s);
         if (tp::graph_usable(M)) {
             hipGraphExec_t ex = tp::graph_ensure(M, s, tp::schur_cnn_on(M));
             TP_LAUNCH(tp::k_deinterleave, tp::cdiv(n, tp::KB), tp::KB, 0, s, n, r, M->rin.p);
@@ -687,11 +708,12 @@ int precond_apply(tp_prec_t M, const double* r, double* z, void* stream) {
 int precond_destroy(tp_prec_t M) {
     TP_GUARD({
         if (M) {
-            TP_HIP(hipDeviceSynchronize());
+            // work of this handle may still run on the streams it was used on
+            if (M->multi) TP_HIP(hipDeviceSynchronize());
+            else if (M->used) TP_HIP(hipStreamSynchronize(M->last));
             tp::gmres_free(M->ws);
             if (M->gexec) (void)hipGraphExecDestroy(M->gexec);
             if (M->gexec_cnn) (void)hipGraphExecDestroy(M->gexec_cnn);
-            if (M->cap) (void)hipStreamDestroy(M->cap);
             delete M;
         }
     });
