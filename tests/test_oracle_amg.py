@@ -213,14 +213,17 @@ def test_two_level_cycle_closed_form(smoother, restriction):
 @pytest.mark.parametrize("dims,kw,bound", [
     ((128, 128), dict(), 0.5), ((32, 32, 32), dict(), 0.4),
     ((128, 128), dict(cheb_degree=10, cheb_degree_coarse=1, cheb_lo=0.03, coarse_max=1200), 0.40),
-    ((32, 32, 32), dict(cheb_degree=10, cheb_degree_coarse=1, cheb_lo=0.03, coarse_max=1200), 0.25)])
+    ((32, 32, 32), dict(cheb_degree=10, cheb_degree_coarse=1, cheb_lo=0.03, coarse_max=1200), 0.25),
+    ((32, 32, 32), dict(cheb_degree=10, cheb_degree_coarse=0, cheb_lo=0.03, coarse_max=1200), 0.20)])
 def test_poisson_stationary_factor(dims, kw, bound):
     """Stationary V(1,1) factor on the constant-coefficient Dirichlet
     Laplacian, 20 cycles from a random error.  PMIS with direct
     interpolation measures 0.44 (2-D) and 0.34 (3-D) with the degree-3
-    Chebyshev smoother on [0.3, 1], and 0.38 and 0.23 with the GPU path's
-    smoothers (degree 10 on the finest level, 1 below, on [0.03, 1]); the
-    0.2 target is not met with direct interpolation (a known gap)."""
+    Chebyshev smoother on [0.3, 1], 0.38 and 0.23 with the GPU path's
+    smoothers (degree 10 on the finest level, 1 below, on [0.03, 1]), and
+    0.155 in 3-D with degree 10 on every level: below 0.2.  In 2-D direct
+    interpolation on PMIS grids stays near 0.33 whatever the smoothing (a
+    known gap; the workloads are 3-D)."""
     n, rp, c, v = synth.poisson_csr(dims)
     A = _csr(n, rp, c, v)
     h = oracle.AMG(n, rp, c, v, **kw)
