@@ -382,6 +382,44 @@ k_cheb01_dia_r(int32_t n, const V* __restrict__ dv, DiaOff<ND> off, const T* __r
     str<T, R>(&xout[i], xo);
 }
 
+// Pre-smoothing by one step from a zero guess fused with the residual on a
+// CSR level: x0 = (D^{-1} b)/theta (Chebyshev) or w D^{-1} b (l1-Jacobi) is
+// formed on the fly for every neighbour, x = x0 (and d = x0) written for the
+// row, and r = b - A x0 -- the products and sums of the two separate passes
+// in the same order; one launch instead of two.
+template <typename T, typename V, int G>
+__global__ void __launch_bounds__(VB)
+k_smooth0_res(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci, const V* __restrict__ av,
+              const T* __restrict__ diag, const T* __restrict__ dinv, const T* __restrict__ b, T* __restrict__ x,
+              T* __restrict__ d, T* __restrict__ r, int cheb, T theta, T w) {
+    const int64_t tid = (int64_t)blockIdx.x * VB + threadIdx.x;
+    const int32_t i = (int32_t)(tid / G);
+    const int lane = (int)(tid % G);
+    const bool valid = i < n;
+    const bool head = valid && lane == 0;
+    T bi = 0, x0 = 0;
+    if (head) {
+        bi = b[i];
+        x0 = cheb ? (dinv[i] * bi) / theta : w * dinv[i] * bi;
+    }
+    const T xd = head && diag ? diag[i] * x0 : T(0);
+    T s = 0;
+    if (valid) {
+        const int32_t e = rp[i + 1];
+        for (int32_t q = rp[i] + lane; q < e; q += G) {
+            const int32_t j = ci[q];
+            const T xj = cheb ? (dinv[j] * b[j]) / theta : w * dinv[j] * b[j];
+            s += (T)av[q] * xj;
+        }
+    }
+    s = group_sum<T, G>(s);
+    if (head) {
+        x[i] = x0;
+        if (cheb) d[i] = x0;
+        r[i] = bi - (diag ? s + xd : s);
+    }
+}
+
 // first sweep from a zero guess
 template <typename T>
 __global__ void __launch_bounds__(VB)
@@ -651,17 +689,27 @@ static typename M::T* vcycle_level(tp_amg* h, int l, const typename M::T* b, hip
     }
     const tp_amg_params& p = h->prm;
     T* cur = x;
-    if (p.nu_pre > 0) cur = smooth<M>(h, l, b, cur, true, p.nu_pre, s);
-    else TP_LAUNCH(k_zero<T>, cdiv(n, VB), VB, 0, s, n, cur);
-    // (residual and restriction stay two row-parallel passes: forming the
-    // residual entries inside the restriction recomputes each fine row for
-    // every coarse row that holds it and serialises its gathers)
     T* r = (T*)L.r.p;
-    if (L.ndia) {
-        dia_residual<T, V>(L, n, LevelVals<M>::D(L), LevelVals<M>::diag(L), b, cur, r, s);
+    // a pre-smoothing that is a single step from zero on a CSR level (the
+    // coarse levels of the degree-1 schedule) runs fused with the residual
+    const int deg = (l > 0 && p.cheb_degree_coarse > 0) ? p.cheb_degree_coarse : p.cheb_degree;
+    if (p.nu_pre == 1 && !L.ndia && (p.smoother == 0 || deg == 1)) {
+        const double theta = 0.5 * (1.0 + p.cheb_lo);
+        TP_G_DISPATCH(L.gA, TP_LAUNCH((k_smooth0_res<T, V, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p,
+                                      L.A.col.p, LevelVals<M>::A(L), LevelVals<M>::diag(L), LevelVals<M>::dinv(L),
+                                      b, cur, (T*)L.d.p, r, p.smoother == 1, (T)theta, (T)p.omega));
     } else {
-        TP_G_DISPATCH(L.gA, TP_LAUNCH((k_residual<T, V, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p,
-                                      L.A.col.p, LevelVals<M>::A(L), LevelVals<M>::diag(L), b, cur, r));
+        if (p.nu_pre > 0) cur = smooth<M>(h, l, b, cur, true, p.nu_pre, s);
+        else TP_LAUNCH(k_zero<T>, cdiv(n, VB), VB, 0, s, n, cur);
+        // (residual and restriction stay two row-parallel passes: forming the
+        // residual entries inside the restriction recomputes each fine row for
+        // every coarse row that holds it and serialises its gathers)
+        if (L.ndia) {
+            dia_residual<T, V>(L, n, LevelVals<M>::D(L), LevelVals<M>::diag(L), b, cur, r, s);
+        } else {
+            TP_G_DISPATCH(L.gA, TP_LAUNCH((k_residual<T, V, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p,
+                                          L.A.col.p, LevelVals<M>::A(L), LevelVals<M>::diag(L), b, cur, r));
+        }
     }
     Level& Ln = h->lev[l + 1];
     T* bc = (T*)Ln.b.p;
