@@ -13,6 +13,8 @@ What it computes, and the passage each part follows:
       components named in amg.c             -> amg.c
   block preconditioner and GMRES             Section 3.2 (five-step list),
       Section 4 (right-preconditioned GMRES, restart 30) -> krylov.c
+  ILU(0) and the two-stage CPR preconditioner  Section 3 (ILU), Section 3.1,
+      Section 4 (ILU(0) as the second stage) -> ilu.c
   3-D convolution smoother network           cnn.c
   Newton time stepping (sparse direct linear steps)  Section 2.2, Section 5
                                              -> newton_simulate
@@ -27,7 +29,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_HERE, "liboracle.so")
-_SRC = ["physics.c", "amg.c", "krylov.c", "cnn.c"]
+_SRC = ["physics.c", "amg.c", "krylov.c", "cnn.c", "ilu.c"]
 
 
 def build(force: bool = True) -> str:
@@ -68,6 +70,10 @@ class _AmgParams(C.Structure):
                 ("cheb_degree_coarse", C.c_int32)]
 
 
+class _Ilu(C.Structure):
+    _fields_ = [("N", C.c_int32), ("rowptr", C.c_void_p), ("col", C.c_void_p), ("lu", C.c_void_p)]
+
+
 class _Jac(C.Structure):
     _fields_ = [("n", C.c_int32), ("rowptr", C.c_void_p), ("col", C.c_void_p),
                 ("pp", C.c_void_p), ("pT", C.c_void_p), ("Tp", C.c_void_p), ("TT", C.c_void_p)]
@@ -92,6 +98,8 @@ def lib():
         _lib.or_amg_free.argtypes = [C.c_void_p]
         _lib.or_amg_nlev.argtypes = [C.c_void_p]
         _lib.or_amg_level_R_nnz.restype = C.c_int32
+        _lib.or_ilu0.restype = C.c_int
+        _lib.or_gmres_cpr.restype = C.c_int
     return _lib
 
 
@@ -352,6 +360,73 @@ def gmres(J: Jacobian, amg_pp, amg_S, b, x0=None, variant="lower", rtol=1e-8,
                         amg_S.h if amg_S else None, C.c_int32(VARIANTS[variant]),
                         _p(b), _p(x), C.c_double(rtol), C.c_int32(restart),
                         C.c_int32(maxit), C.byref(it), C.byref(rel), _p(hist))
+    return x, dict(converged=(st == 0), iters=it.value, rel_true=rel.value,
+                   history=hist[: it.value + 1])
+
+
+# ---- ILU(0) and CPR -----------------------------------------------------------------
+def jac_fieldwise(J: Jacobian):
+    """(rowptr, col, val) of the 2n x 2n Jacobian in field-by-field order
+    [p_0..p_{n-1}, T_0..T_{n-1}] (every stored entry of the blocks kept)."""
+    js = J._cstruct()
+    n, nnz = J.n, len(J.col)
+    rowptr = np.zeros(2 * n + 1, np.int32)
+    col = np.zeros(4 * nnz, np.int32)
+    val = np.zeros(4 * nnz)
+    lib().or_jac_fieldwise(C.byref(js), _p(rowptr), _p(col), _p(val))
+    return rowptr, col, val
+
+
+class ILU0:
+    """ILU(0) factors of an N x N CSR matrix with sorted rows: `lu` holds L
+    below the diagonal (unit diagonal implied) and U on and above it."""
+
+    def __init__(self, rowptr, col, val):
+        self.rowptr, self.col = _i32(rowptr), _i32(col)
+        self.N = len(self.rowptr) - 1
+        self.lu = np.zeros(len(self.col))
+        self.status = lib().or_ilu0(C.c_int32(self.N), _p(self.rowptr), _p(self.col),
+                                    _p(_f64(val)), _p(self.lu))
+
+    def solve(self, b):
+        b = _f64(b)
+        x = np.zeros(self.N)
+        lib().or_ilu0_solve(C.c_int32(self.N), _p(self.rowptr), _p(self.col), _p(self.lu), _p(b), _p(x))
+        return x
+
+    def factors(self):
+        """(L, U) as SciPy CSR matrices (L with its unit diagonal)."""
+        import scipy.sparse as sp
+        A = sp.csr_matrix((self.lu, self.col, self.rowptr), shape=(self.N, self.N))
+        L = sp.tril(A, -1, format="csr") + sp.identity(self.N, format="csr")
+        U = sp.triu(A, 0, format="csr")
+        return L.tocsr(), U.tocsr()
+
+    def _cstruct(self):
+        return _Ilu(self.N, _p(self.rowptr), _p(self.col), _p(self.lu))
+
+
+def cpr_ilu(J: Jacobian):
+    """ILU(0) of the field-by-field Jacobian (the second stage of CPR)."""
+    return ILU0(*jac_fieldwise(J))
+
+
+def cpr_apply(J: Jacobian, amg_pp, F: ILU0, r):
+    js, fs = J._cstruct(), F._cstruct()
+    r = _f64(r)
+    z = np.zeros_like(r)
+    lib().or_cpr_apply(C.byref(js), amg_pp.h, C.byref(fs), _p(r), _p(z))
+    return z
+
+
+def gmres_cpr(J: Jacobian, amg_pp, F: ILU0, b, x0=None, rtol=1e-8, restart=30, maxit=1000):
+    js, fs = J._cstruct(), F._cstruct()
+    b = _f64(b)
+    x = np.zeros_like(b) if x0 is None else _f64(x0).copy()
+    it, rel = C.c_int32(), C.c_double()
+    hist = np.zeros(maxit + 1)
+    st = lib().or_gmres_cpr(C.byref(js), amg_pp.h, C.byref(fs), _p(b), _p(x), C.c_double(rtol),
+                            C.c_int32(restart), C.c_int32(maxit), C.byref(it), C.byref(rel), _p(hist))
     return x, dict(converged=(st == 0), iters=it.value, rel_true=rel.value,
                    history=hist[: it.value + 1])
 

@@ -82,10 +82,26 @@ static double dot(int32_t m, const double* a, const double* b)
     return s;
 }
 
-int or_gmres(const or_jac* J, const or_amg* amg_pp, const or_amg* amg_S,
-             int32_t variant, const double* b, double* x, double rtol,
-             int32_t restart, int32_t maxit, int32_t* iters, double* rel_true,
-             double* history)
+/* the preconditioner as z = apply(ctx, r) */
+typedef void (*prec_fn)(const void* ctx, const double* r, double* z);
+
+struct blk_ctx { const or_jac* J; const or_amg* pp; const or_amg* S; int32_t variant; };
+static void blk_prec(const void* c, const double* r, double* z)
+{
+    const struct blk_ctx* b = c;
+    or_precond_apply(b->J, b->pp, b->S, b->variant, r, z);
+}
+
+struct cpr_ctx { const or_jac* J; const or_amg* pp; const or_ilu* F; };
+static void cpr_prec(const void* c, const double* r, double* z)
+{
+    const struct cpr_ctx* b = c;
+    or_cpr_apply(b->J, b->pp, b->F, r, z);
+}
+
+static int gmres_core(const or_jac* J, prec_fn prec, const void* ctx, const double* b, double* x,
+                      double rtol, int32_t restart, int32_t maxit, int32_t* iters,
+                      double* rel_true, double* history)
 {
     int32_t m = 2 * J->n, it = 0, mr = restart;
     double* V = malloc(sizeof(double) * (size_t)m * (size_t)(mr + 1));
@@ -121,7 +137,7 @@ int or_gmres(const or_jac* J, const or_amg* amg_pp, const or_amg* amg_S,
         for (j = 0; j < mr && it < maxit; ++j) {
             double* vj = V + (size_t)j * m;
             double* zj = Z + (size_t)j * m;
-            or_precond_apply(J, amg_pp, amg_S, variant, vj, zj);
+            prec(ctx, vj, zj);
             jac_apply(J, zj, w);
             /* CGS2: two classical Gram-Schmidt passes */
             for (int32_t i = 0; i <= j; ++i) H[(size_t)i * mr + j] = 0.0;
@@ -177,4 +193,21 @@ int or_gmres(const or_jac* J, const or_amg* amg_pp, const or_amg* amg_S,
 done:
     free(V); free(Z); free(H); free(cs); free(sn); free(gv); free(y); free(h1); free(w); free(r);
     return converged ? 0 : 1;
+}
+
+int or_gmres(const or_jac* J, const or_amg* amg_pp, const or_amg* amg_S,
+             int32_t variant, const double* b, double* x, double rtol,
+             int32_t restart, int32_t maxit, int32_t* iters, double* rel_true,
+             double* history)
+{
+    struct blk_ctx c = { J, amg_pp, amg_S, variant };
+    return gmres_core(J, blk_prec, &c, b, x, rtol, restart, maxit, iters, rel_true, history);
+}
+
+int or_gmres_cpr(const or_jac* J, const or_amg* amg_pp, const or_ilu* F, const double* b,
+                 double* x, double rtol, int32_t restart, int32_t maxit, int32_t* iters,
+                 double* rel_true, double* history)
+{
+    struct cpr_ctx c = { J, amg_pp, F };
+    return gmres_core(J, cpr_prec, &c, b, x, rtol, restart, maxit, iters, rel_true, history);
 }

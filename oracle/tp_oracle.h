@@ -105,6 +105,31 @@ int or_gmres(const or_jac* J, const or_amg* amg_pp, const or_amg* amg_S,
              int32_t restart, int32_t maxit, int32_t* iters, double* rel_true,
              double* history);
 
+/* ---- ILU(0) and the two-stage CPR preconditioner (see ilu.c) ---------- */
+typedef struct {
+    int32_t N;
+    const int32_t *rowptr, *col;  /* pattern of the factorised matrix, sorted rows */
+    const double* lu;             /* L (strictly lower, unit diagonal implied) and U */
+} or_ilu;
+
+/* ILU(0) of the N x N CSR matrix (sorted columns, diagonal stored) into lu
+ * (same pattern).  Returns 0, -1 if a row has no diagonal entry, -4 on a zero
+ * pivot. */
+int or_ilu0(int32_t N, const int32_t* rowptr, const int32_t* col, const double* a, double* lu);
+/* x = U^{-1} L^{-1} b */
+void or_ilu0_solve(int32_t N, const int32_t* rowptr, const int32_t* col, const double* lu,
+                   const double* b, double* x);
+/* The 2n x 2n Jacobian in field-by-field order ([p; T]) from its four blocks:
+ * rowptr (2n+1), col and val (4 nnz). */
+void or_jac_fieldwise(const or_jac* J, int32_t* rowptr, int32_t* col, double* val);
+/* CPR: x1 = [V_pp(r_p); 0]; x = ILU0^{-1}(r - J x1) + x1, with F the ILU(0) of
+ * the field-by-field Jacobian; r and x interleaved. */
+void or_cpr_apply(const or_jac* J, const or_amg* amg_pp, const or_ilu* F, const double* r, double* x);
+/* GMRES (as or_gmres) right-preconditioned by CPR */
+int or_gmres_cpr(const or_jac* J, const or_amg* amg_pp, const or_ilu* F, const double* b,
+                 double* x, double rtol, int32_t restart, int32_t maxit, int32_t* iters,
+                 double* rel_true, double* history);
+
 /* ---- Learned post-smoother network (see cnn.c) ------------------------ */
 void or_cnn_forward(const or_grid* g, const double* W1, const double* b1, const double* W2,
                     double b2, const double* f, double* h, double* out);
