@@ -203,6 +203,57 @@ int precond_apply(tp_prec_t M, const double* r, double* z, void* stream);
 int precond_destroy(tp_prec_t M);
 
 /* ---------------------------------------------------------------------------
+ * ILU(0) (Section 3: incomplete LU with the factors on the sparsity pattern
+ * of the matrix) and the two-stage CPR preconditioner of Section 3.1, the
+ * comparator of Section 4 (AMG V-cycle on A_pp in the first stage, ILU(0)
+ * of the whole Jacobian in the second).
+ *
+ * Factors: L unit lower triangular and U upper triangular with
+ * (L U)_ij = a_ij at every stored position of A, by row-by-row Gaussian
+ * elimination that drops every update outside the pattern.  Triangular
+ * solves run level by level (rows grouped by the depth of their dependency
+ * chains, found by a host pass over the pattern at creation), one kernel
+ * launch per level.
+ * ------------------------------------------------------------------------ */
+typedef struct tp_ilu* tp_ilu_t;
+/* ILU(0) of an N x N CSR matrix (device arrays: rowptr N+1, col and val
+ * rowptr[N]; columns sorted and unique within each row, every diagonal
+ * stored).  Copies the matrix; synchronises `stream` (the pattern is read by
+ * the host).  Errors: TP_ERR_ARG for a malformed pattern (unsorted or
+ * duplicate columns, an index out of range, a missing diagonal),
+ * TP_ERR_NUMERIC for a zero or non-finite pivot. */
+int ilu0_create(int32_t N, const int32_t* rowptr, const int32_t* col, const double* val,
+                void* stream, tp_ilu_t* out);
+/* ILU(0) of the whole 2n x 2n Jacobian of eq. AXR in field-by-field order
+ * (rows and columns [p_0..p_{n-1}, T_0..T_{n-1}]): row p_i holds A_pp(i,:)
+ * then A_pT(i,:) at columns j and n + j, row T_i holds A_Tp(i,:) then
+ * A_TT(i,:); all 4 nnz stored entries are kept, structural zeros included.
+ * Synchronises `stream`; errors as ilu0_create. */
+int ilu0_create_jacobian(const tp_jacobian* J, void* stream, tp_ilu_t* out);
+/* New values of a Jacobian with the pattern the handle was built from
+ * (a later Newton iterate): refill and refactorise, no new analysis.
+ * Synchronises `stream` (pivot check). */
+int ilu0_refactor_jacobian(tp_ilu_t F, const tp_jacobian* J, void* stream);
+/* x = U^{-1} L^{-1} b (device, N each, in the ordering of the factorised
+ * matrix: field by field for a Jacobian handle).  b and x may be the same
+ * array.  Stream-ordered; does not synchronise. */
+int ilu0_solve(tp_ilu_t F, const double* b, double* x, void* stream);
+/* Sizes and level counts of the forward and backward solves (host outputs,
+ * any may be NULL). */
+int ilu0_info(tp_ilu_t F, int32_t* N, int32_t* nnz, int32_t* levels_lower, int32_t* levels_upper);
+/* Copy the pattern and the factors (L strictly below the diagonal, U on and
+ * above) into caller device arrays (any may be NULL). Stream-ordered. */
+int ilu0_copy(tp_ilu_t F, int32_t* rowptr, int32_t* col, double* lu, void* stream);
+int ilu0_destroy(tp_ilu_t F);
+
+/* CPR (Section 3.1): z = M^{-1} r with x1 = [V_pp(r_p); 0] and
+ * z = ILU0^{-1}(r - J x1) + x1, for a handle from ilu0_create_jacobian of
+ * the same J.  Used through precond_apply, fgmres_solve and
+ * precond_destroy like the block forms; borrows J, the hierarchy and the
+ * ILU(0) handle, which must outlive it. */
+int precond_create_cpr(const tp_jacobian* J, tp_amg_t amg_pp, tp_ilu_t ilu, tp_prec_t* out);
+
+/* ---------------------------------------------------------------------------
  * Flexible GMRES (right preconditioned, restarted; Section 4: GMRES with
  * restart 30) with classical Gram-Schmidt applied twice, Givens rotations on
  * the Hessenberg matrix, all in FP64 on the device.  Stops when the true

@@ -4,7 +4,8 @@
 // form (steps 1-3) solves A_pp x_p = b_p, forms b~_T = b_T - A_Tp x_p and
 // solves S~ d_T = b~_T, each solve being one AMG V-cycle; the full form adds
 // steps 4-5 with b~_p = b_p - A_pT d_T; the upper form runs the Schur solve
-// first.  Internally the p and T halves of a vector are stored split
+// first.  The CPR comparator (Section 3.1) is the two-stage form
+// x1 = [V_pp(r_p); 0], x = ILU0^{-1}(r - J x1) + x1.  Internally the p and T halves of a vector are stored split
 // ([p_0..p_{n-1}, T_0..T_{n-1}]), a symmetric permutation of the
 // interleaved ordering at the interface.
 //
@@ -26,6 +27,8 @@ void cast_s2d(int32_t n, const void* a, double* b, size_t es, hipStream_t s);
 namespace tp {
 struct Gmres;
 void gmres_free(Gmres* g);
+void ilu_solve(tp_ilu* F, const double* b, double* x, hipStream_t s);
+int32_t ilu_cells(const tp_ilu* F);
 }  // namespace tp
 
 struct tp_prec {
@@ -44,8 +47,10 @@ struct tp_prec {
     tp::DBuf<double> rin, zout;
     tp_jacobian J;
     tp_amg* pp = nullptr;
-    tp_amg* S = nullptr;
-    int variant = 0;
+    tp_amg* S = nullptr;  // null for CPR
+    tp_ilu* ilu = nullptr;  // CPR second stage (ILU(0) of the field-ordered Jacobian)
+    int variant = 0;      // 0 lower, 1 upper, 2 full, 3 CPR
+    tp::DBuf<double> cw, cb;  // CPR: first-stage pressure x1 (n) and the residual r - J x1 (2n)
     tp::DBuf<double> rs, zs;  // split work vectors (2n) for the interleaved entry point
 };
 
@@ -143,6 +148,40 @@ k_block_spmv(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restric
             zcopy[n + i] = z[n + i];
         }
     }
+}
+
+// CPR stage residual, field order: b1 = r - J [x1; 0] (x1 in the pressure rows)
+__global__ void __launch_bounds__(KB)
+k_cpr_resid(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+            const double* __restrict__ pp, const double* __restrict__ Tp, const double* __restrict__ x1,
+            const double* __restrict__ r, double* __restrict__ b1) {
+    const int64_t tid = (int64_t)blockIdx.x * KB + threadIdx.x;
+    const int32_t i = (int32_t)(tid / JG);
+    const int lane = (int)(tid % JG);
+    double sm = 0.0, se = 0.0;
+    if (i < n) {
+        for (int32_t q = rp[i] + lane; q < rp[i + 1]; q += JG) {
+            const double a = x1[ci[q]];
+            sm += pp[q] * a;
+            se += Tp[q] * a;
+        }
+    }
+#pragma unroll
+    for (int off = JG / 2; off > 0; off >>= 1) {
+        sm += __shfl_down(sm, off, JG);
+        se += __shfl_down(se, off, JG);
+    }
+    if (i < n && lane == 0) {
+        b1[i] = r[i] - sm;
+        b1[n + i] = r[n + i] - se;
+    }
+}
+
+// z_p += x1 (the correction of the second stage plus the first stage)
+__global__ void __launch_bounds__(KB)
+k_add_into(int32_t n, const double* __restrict__ a, double* __restrict__ z) {
+    const int32_t i = blockIdx.x * KB + threadIdx.x;
+    if (i < n) z[i] += a[i];
 }
 
 // ---- CGS2 building blocks -------------------------------------------------------------
@@ -359,12 +398,29 @@ static void run_from_b(tp_amg* h, double* out, int32_t n, hipStream_t s) {
     if (x != out) cast_s2d(n, x, out, es, s);
 }
 
+// work vectors of the CPR form, allocated outside any capture
+static void prec_buffers(tp_prec* M, hipStream_t s) {
+    const int32_t n = M->J.n;
+    if (M->variant == 3 && M->cw.n != (size_t)n) {
+        M->cw.alloc(n, s);
+        M->cb.alloc(2 * (size_t)n, s);
+    }
+}
+
 void prec_apply_split(tp_prec* M, const double* r, double* z, hipStream_t s) {
     const int32_t n = M->J.n;
     const double* rp = r;
     const double* rT = r + n;
     double* zp = z;
     double* zT = z + n;
+    if (M->variant == 3) {
+        vsolve(M->pp, rp, M->cw.p, n, s);  // stage 1: x1 = V_pp(r_p)
+        TP_LAUNCH(k_cpr_resid, cdiv((int64_t)n * JG, KB), KB, 0, s, n, M->J.rowptr, M->J.col, M->J.pp, M->J.Tp,
+                  M->cw.p, r, M->cb.p);
+        ilu_solve(M->ilu, M->cb.p, z, s);  // stage 2
+        TP_LAUNCH(k_add_into, cdiv(n, KB), KB, 0, s, n, M->cw.p, z);
+        return;
+    }
     if (M->variant == 1) {
         vsolve(M->S, rT, zT, n, s);
         sub_into_b(M->J, M->J.pT, zT, rp, M->pp, s);
@@ -404,7 +460,7 @@ static hipStream_t capture_stream() {
 // switches off, and the smoother timer keep the apply eager)
 static bool graph_usable(tp_prec* M) { return !(M->pp->cnn && M->pp->cnn->enabled) && !timer().on; }
 
-static bool schur_cnn_on(tp_prec* M) { return M->S->cnn && M->S->cnn->enabled; }
+static bool schur_cnn_on(tp_prec* M) { return M->S && M->S->cnn && M->S->cnn->enabled; }
 
 // Graph of prec_apply_split(rin -> zout), with or without the Schur hierarchy's
 // learned post-smoother (captured the first time each is needed, the learned one
@@ -424,8 +480,9 @@ static hipGraphExec_t graph_ensure(tp_prec* M, hipStream_t s, bool with_cnn) {
         M->rin.alloc(2 * (size_t)n, s);
         M->zout.alloc(2 * (size_t)n, s);
     }
+    prec_buffers(M, s);
     const hipStream_t c = capture_stream();
-    tp_cnn_attach* a = M->S->cnn.get();
+    tp_cnn_attach* a = M->S ? M->S->cnn.get() : nullptr;
     const bool was = a && a->enabled;
     if (a) a->enabled = with_cnn;
     hipGraph_t g = nullptr;
@@ -526,6 +583,7 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
     const int32_t n = J.n;
     const int m = kp.restart;
     note_stream(M, s);
+    prec_buffers(M, s);
     if (!M->ws || M->ws->n != n || M->ws->m != m) {
         if (M->ws) {
             TP_HIP(hipDeviceSynchronize());
@@ -545,7 +603,7 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
     int it = 0, restarts = 0;
     double rel = 0.0, est = 0.0;
     std::vector<double> ests;
-    bool cnn_on = M->S->cnn && M->S->cnn->enabled;
+    bool cnn_on = schur_cnn_on(M);
     int fallback_iter = -1;
     if (cnn_on) TP_LAUNCH(k_zero_i32, 1, 64, 0, s, M->S->cnn->bad.p);
     int status = TP_OK;
@@ -647,7 +705,7 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
     TP_LAUNCH(k_interleave, gn, KB, 0, s, n, G.x.p, x_il);
     TP_HIP(hipStreamSynchronize(s));
     if (!std::isfinite(rel)) fail(TP_ERR_NUMERIC, "non-finite true residual in FGMRES");
-    if (M->S->cnn) M->S->cnn->enabled = true;  // the switch lasts for one solve
+    if (M->S && M->S->cnn) M->S->cnn->enabled = true;  // the switch lasts for one solve
     if (st) {
         st->fallback_iter = fallback_iter;
         st->iters = it;
@@ -681,12 +739,30 @@ int precond_create(const tp_jacobian* J, tp_amg_t amg_pp, tp_amg_t amg_S, int32_
     return TP_OK;
 }
 
+int precond_create_cpr(const tp_jacobian* J, tp_amg_t amg_pp, tp_ilu_t ilu, tp_prec_t* out) {
+    TP_GUARD({
+        TP_CHECK_ARG(J && amg_pp && ilu && out, "precond_create_cpr: null argument");
+        TP_CHECK_ARG(J->rowptr && J->col && J->pp && J->pT && J->Tp && J->TT, "precond_create_cpr: null Jacobian array");
+        TP_CHECK_ARG(amg_pp->lev[0].A.n == J->n, "precond_create_cpr: hierarchy size does not match J->n");
+        TP_CHECK_ARG(tp::ilu_cells(ilu) == J->n,
+                     "precond_create_cpr: the ILU(0) handle was not built from a Jacobian of this size");
+        tp_prec* M = new tp_prec();
+        M->J = *J;
+        M->pp = amg_pp;
+        M->ilu = ilu;
+        M->variant = 3;
+        *out = M;
+    });
+    return TP_OK;
+}
+
 int precond_apply(tp_prec_t M, const double* r, double* z, void* stream) {
     TP_GUARD({
         TP_CHECK_ARG(M && r && z, "precond_apply: null argument");
         hipStream_t s = (hipStream_t)stream;
         const int32_t n = M->J.n;
         tp::note_stream(M, s);
+        tp::prec_buffers(M, s);
         if (tp::graph_usable(M)) {
             hipGraphExec_t ex = tp::graph_ensure(M, s, tp::schur_cnn_on(M));
             TP_LAUNCH(tp::k_deinterleave, tp::cdiv(n, tp::KB), tp::KB, 0, s, n, r, M->rin.p);

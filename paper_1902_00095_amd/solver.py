@@ -1,7 +1,8 @@
 """One coupled pressure-temperature solve on the GPU, end to end.
 
 assemble_tpfa -> amg_setup(A_pp) and amg_setup(S) -> precond_create ->
-fgmres_solve, all through the C ABI.  The Schur-approximation hierarchy uses
+fgmres_solve, all through the C ABI (the CPR comparator: amg_setup(A_pp) and
+ilu0_create_jacobian -> precond_create_cpr).  The Schur-approximation hierarchy uses
 the Petrov-Galerkin restriction (its columns, not its rows, are diagonally
 dominant); the pressure hierarchy the Galerkin one.
 """
@@ -24,6 +25,9 @@ class SolveConfig:
     # S~_T (eq. Se), "ATT" the energy block A_TT alone, "diag"
     # A_TT - A_Tp diag(A_pp)^{-1} A_pT (the simple forms it is compared with)
     schur: str = "T"
+    # "block": the block-triangular preconditioner (Section 3.2); "cpr": the
+    # two-stage CPR comparator (Section 3.1: AMG on A_pp, then ILU(0) of J)
+    method: str = "block"
 
 
 def to_device(prob, device="cuda"):
@@ -69,10 +73,18 @@ def setup(J, cfg: SolveConfig, concurrent: bool = True):
     import torch
     p_pp = dataclasses.replace(cfg.amg, restriction=0, storage=cfg.storage)
     p_S = dataclasses.replace(cfg.amg, restriction=1, storage=cfg.storage)
+    if cfg.method == "cpr":
+        second = lambda st: tps.ILU0.jacobian(J, stream=st)
+        make = lambda a, b: tps.Precond.cpr(J, a, b)
+    elif cfg.method == "block":
+        second = lambda st: _schur_amg(J, cfg, p_S, st)
+        make = lambda a, b: tps.Precond(J, a, b, cfg.variant)
+    else:
+        raise ValueError(f"unknown method {cfg.method!r}")
     if not concurrent:
         a_pp = tps.AMG(J.rowptr, J.col, J.pp, p_pp)
-        a_S = _schur_amg(J, cfg, p_S)
-        return a_pp, a_S, tps.Precond(J, a_pp, a_S, cfg.variant)
+        a_S = second(None)
+        return a_pp, a_S, make(a_pp, a_S)
     s1, s2 = _side_streams()
     ev = torch.cuda.Event()
     ev.record()                       # J is complete on the current stream
@@ -86,17 +98,18 @@ def setup(J, cfg: SolveConfig, concurrent: bool = True):
         except Exception as e:        # re-raised below
             err.append(e)
 
-    th = threading.Thread(target=run, args=("S", lambda st: _schur_amg(J, cfg, p_S, st), s2))
+    th = threading.Thread(target=run, args=("S", second, s2))
     th.start()
     run("pp", lambda st: tps.AMG(J.rowptr, J.col, J.pp, p_pp, stream=st), s1)
     th.join()
     if err:
         raise err[0]
-    return out["pp"], out["S"], tps.Precond(J, out["pp"], out["S"], cfg.variant)
+    return out["pp"], out["S"], make(out["pp"], out["S"])
 
 
 def solve(J, G, cfg: SolveConfig, history=False):
-    """Newton step: J dx = -G.  Returns (dx, stats, (a_pp, a_S, M))."""
+    """Newton step: J dx = -G.  Returns (dx, stats, (a_pp, a_S, M)); a_S is
+    the ILU(0) handle for the CPR method."""
     a_pp, a_S, M = setup(J, cfg)
     b = -G
     dx, st = tps.fgmres_solve(J, M, b, rtol=cfg.rtol, restart=cfg.restart, maxit=cfg.maxit,
@@ -134,6 +147,8 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None):
     import time
 
     import torch
+    if net is not None and cfg.method != "block":
+        raise ValueError("the learned smoother belongs to the Schur hierarchy of the block preconditioner")
     dev = to_device(prob)
     x = dev["x_prev"].clone()
     dev["x_k"] = x
@@ -150,7 +165,8 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None):
                 a_S.attach(None, None)
             M.close(); a_pp.close(); a_S.close()
 
-    reusable = ncfg.reuse and cfg.schur in ("T", "ATT")   # S_diag has a pattern of its own
+    # S_diag has a pattern of its own; CPR refactorises its ILU(0) in place
+    reusable = ncfg.reuse and (cfg.method == "cpr" or cfg.schur in ("T", "ATT"))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     try:
@@ -172,7 +188,10 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None):
                 ts = time.perf_counter()
                 if hier is not None and reusable and k > 0:
                     hier[0].refresh_fine(J.pp)
-                    hier[1].refresh_fine(_schur_values(J, cfg))
+                    if cfg.method == "cpr":
+                        hier[1].refactor(J)
+                    else:
+                        hier[1].refresh_fine(_schur_values(J, cfg))
                 else:
                     close(hier)
                     hier = None

@@ -77,6 +77,8 @@ class _Allocator(C.Structure):
 EXPORTS = ["tp_last_error", "tp_init", "tp_jacobian_sizes", "assemble_tpfa", "amg_setup", "amg_setup_schur_diag", "amg_refresh_fine",
            "amg_num_levels", "amg_level_info", "amg_level_format", "amg_level_copy", "amg_vcycle", "amg_destroy",
            "precond_create", "precond_apply", "precond_destroy", "fgmres_solve",
+           "ilu0_create", "ilu0_create_jacobian", "ilu0_refactor_jacobian", "ilu0_solve", "ilu0_info",
+           "ilu0_copy", "ilu0_destroy", "precond_create_cpr",
            "cnn_create", "cnn_get_params", "cnn_get_grad", "cnn_destroy", "cnn_forward", "cnn_loss_grad",
            "cnn_adam_step", "amg_attach_post_smoother", "amg_features", "amg_presmoothed_pair",
            "amg_cnn_loss_grad",
@@ -408,6 +410,68 @@ class AMG:
 VARIANTS = {"lower": 0, "upper": 1, "full": 2}
 
 
+class ILU0:
+    """Device ILU(0) factors: of a CSR matrix (tensors), or with
+    ``ILU0.jacobian(J)`` of the whole Jacobian in field-by-field order."""
+
+    def __init__(self, rowptr, col, val, stream=None):
+        lib = load()
+        h = C.c_void_p()
+        self._keep = (rowptr,)
+        _check(lib.ilu0_create(C.c_int32(int(rowptr.numel() - 1)), _ptr(rowptr), _ptr(col), _ptr(val),
+                               _stream(stream), C.byref(h)))
+        self.h = h
+
+    @classmethod
+    def jacobian(cls, J: "Jacobian", stream=None):
+        lib = load()
+        self = cls.__new__(cls)
+        self._keep = (J.rowptr,)
+        h = C.c_void_p()
+        jc = J.c()
+        _check(lib.ilu0_create_jacobian(C.byref(jc), _stream(stream), C.byref(h)))
+        self.h = h
+        return self
+
+    def refactor(self, J: "Jacobian", stream=None):
+        jc = J.c()
+        _check(_lib.ilu0_refactor_jacobian(self.h, C.byref(jc), _stream(stream)))
+
+    def info(self):
+        N, nnz, ll, lu = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(_lib.ilu0_info(self.h, C.byref(N), C.byref(nnz), C.byref(ll), C.byref(lu)))
+        return dict(N=N.value, nnz=nnz.value, levels_lower=ll.value, levels_upper=lu.value)
+
+    def factors(self, stream=None):
+        """(rowptr, col, lu) device tensors: L strictly below the diagonal, U on and above."""
+        torch = _torch()
+        inf = self.info()
+        dev = self._keep[0].device
+        rp = torch.empty(inf["N"] + 1, dtype=torch.int32, device=dev)
+        ci = torch.empty(inf["nnz"], dtype=torch.int32, device=dev)
+        lu = torch.empty(inf["nnz"], dtype=torch.float64, device=dev)
+        _check(_lib.ilu0_copy(self.h, _ptr(rp), _ptr(ci), _ptr(lu), _stream(stream)))
+        return rp, ci, lu
+
+    def solve(self, b, x=None, stream=None):
+        torch = _torch()
+        if x is None:
+            x = torch.empty_like(b)
+        _check(_lib.ilu0_solve(self.h, _ptr(b), _ptr(x), _stream(stream)))
+        return x
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            _check(_lib.ilu0_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Precond:
     def __init__(self, J: Jacobian, amg_pp: AMG, amg_S: AMG, variant="lower"):
         lib = load()
@@ -417,6 +481,18 @@ class Precond:
         _check(lib.precond_create(C.byref(self._jc), amg_pp.h, amg_S.h,
                                   C.c_int32(VARIANTS[variant]), C.byref(h)))
         self.h = h
+
+    @classmethod
+    def cpr(cls, J: Jacobian, amg_pp: AMG, ilu: ILU0):
+        """CPR two-stage preconditioner: AMG V-cycle on A_pp, then ILU(0) of J."""
+        lib = load()
+        self = cls.__new__(cls)
+        self._keep = (J, amg_pp, ilu)
+        self._jc = J.c()
+        h = C.c_void_p()
+        _check(lib.precond_create_cpr(C.byref(self._jc), amg_pp.h, ilu.h, C.byref(h)))
+        self.h = h
+        return self
 
     def apply(self, r, z=None, stream=None):
         torch = _torch()
