@@ -124,11 +124,16 @@ typedef struct {
                               time-to-solution on the layered and channelised fields) */
     double omega;          /* l1-Jacobi weight; 1.0 */
     int32_t nu_pre, nu_post; /* sweeps; 1, 1 */
-    int32_t restriction;   /* 0 R = P^T; 1 R = Q^T, Q direct interpolation of A^T */
+    int32_t restriction;   /* 0 R = P^T; 1 R = Q^T, Q the interpolation built from A^T */
     int32_t storage;       /* 0 FP64; 1 FP32 (values and V-cycle vectors); 2 FP32 vectors,
                               P, R and level-operator diagonal, level-operator
                               off-diagonal entries in BF16 (round to nearest even) */
     int32_t cheb_degree_coarse; /* Chebyshev degree on levels >= 1, 0..16 (0: cheb_degree); 1 */
+    int32_t interp;        /* 0 direct interpolation (default); 1 extended+i: an F point
+                              also interpolates from the strong C neighbours of its
+                              strong F neighbours (De Sterck, Falgout, Nolting, Yang,
+                              Numer. Linear Algebra Appl. 15, 2008); with restriction 1
+                              Q is built the same way from A^T */
 } tp_amg_params;
 
 typedef struct tp_amg* tp_amg_t;

@@ -12,7 +12,10 @@
  *                (lambda_i, splitmix64(seed ^ (level << 40) ^ i), i);
  *   interpolation direct interpolation (Stueben, "An introduction to
  *                algebraic multigrid", 2001), positive couplings lumped into
- *                the diagonal;
+ *                the diagonal; or (interp = 1) extended+i interpolation
+ *                (De Sterck, Falgout, Nolting, Yang, "Distance-two
+ *                interpolation for parallel algebraic multigrid", Numer.
+ *                Linear Algebra Appl. 15, 2008), see ext_interp;
  *   coarse op.   Galerkin A_c = R (A P) with R = P^T, every entry summed
  *                sequentially in ascending inner index, structural pattern kept;
  *   restriction  Galerkin R = P^T, or Petrov-Galerkin R = Q^T where Q is the
@@ -234,6 +237,123 @@ static void direct_interp(const csr_t* A, const csr_t* S, const int32_t* cf,
     P->nnz = q;
 }
 
+/* hat a_kl: a_kl where its sign is opposite to the diagonal a_kk's, else 0 */
+static double opp(double a, double akk)
+{
+    return (akk > 0.0 ? a < 0.0 : a > 0.0) ? a : 0.0;
+}
+
+static int in_sorted(const int32_t* v, int32_t len, int32_t x)
+{
+    int32_t lo = 0, hi = len;
+    while (lo < hi) {
+        int32_t mid = lo + (hi - lo) / 2;
+        if (v[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo < len && v[lo] == x ? lo : -1;
+}
+
+static int cmp_i32(const void* a, const void* b)
+{
+    int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+    return (x > y) - (x < y);
+}
+
+/* Interpolatory set of F point i: its strong C neighbours and the strong C
+ * neighbours of its strong F neighbours, ascending; returns the count. */
+static int32_t ext_set(const csr_t* S, const int32_t* cf, int32_t i, int32_t* mark, int32_t* list)
+{
+    int32_t len = 0;
+    for (int32_t q = S->rowptr[i]; q < S->rowptr[i + 1]; ++q) {
+        int32_t k = S->col[q];
+        if (cf[k]) {
+            if (mark[k] != i) { mark[k] = i; list[len++] = k; }
+        } else {
+            for (int32_t t = S->rowptr[k]; t < S->rowptr[k + 1]; ++t) {
+                int32_t j = S->col[t];
+                if (cf[j] && mark[j] != i) { mark[j] = i; list[len++] = j; }
+            }
+        }
+    }
+    qsort(list, (size_t)len, sizeof(int32_t), cmp_i32);
+    return len;
+}
+
+/* Extended+i interpolation.  For F point i with interpolatory set C^_i (see
+ * ext_set), and for each strong F neighbour k the sum
+ * den_k = sum of hat a_kl over l in C^_i and l = i:
+ *   a~_ii = a_ii + (sum of a_in over neighbours n that are neither strong nor
+ *           in C^_i) + sum_k a_ik hat a_ki / den_k,
+ *   w_ij  = -(a_ij + sum_k a_ik hat a_kj / den_k) / a~_ii,   j in C^_i
+ * (a_ij = 0 when j is not a neighbour).  A strong F neighbour with den_k = 0
+ * is lumped into a~_ii like a weak one.  Sums run in ascending column order
+ * (the row's own entries first, then the strong F neighbours k ascending,
+ * each over row k ascending).  C points interpolate themselves; an F point
+ * with an empty set gets an empty row. */
+static void ext_interp(const csr_t* A, const csr_t* S, const int32_t* cf,
+                       const int32_t* cmap, int32_t nc, csr_t* P)
+{
+    int32_t n = A->n;
+    int32_t* mark = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t* list = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    double* w = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int32_t j = 0; j < n; ++j) mark[j] = -1;
+    int64_t nnz = 0;
+    for (int32_t i = 0; i < n; ++i) nnz += cf[i] ? 1 : ext_set(S, cf, i, mark, list);
+    csr_alloc(P, n, nc, (int32_t)nnz);
+    for (int32_t j = 0; j < n; ++j) mark[j] = -1;
+    int32_t q = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        P->rowptr[i] = q;
+        if (cf[i]) { P->col[q] = cmap[i]; P->val[q] = 1.0; ++q; continue; }
+        int32_t len = ext_set(S, cf, i, mark, list);
+        if (len == 0) continue;
+        const int32_t* Si = S->col + S->rowptr[i];
+        int32_t slen = S->rowptr[i + 1] - S->rowptr[i];
+        double aii = 0.0;
+        for (int32_t t = A->rowptr[i]; t < A->rowptr[i + 1]; ++t)
+            if (A->col[t] == i) aii = A->val[t];
+        for (int32_t s = 0; s < len; ++s) w[s] = 0.0;
+        double at = aii;
+        /* the row's own couplings: interpolatory ones to w, weak others lumped */
+        for (int32_t t = A->rowptr[i]; t < A->rowptr[i + 1]; ++t) {
+            int32_t j = A->col[t];
+            if (j == i) continue;
+            int32_t pos = in_sorted(list, len, j);
+            if (pos >= 0) w[pos] += A->val[t];
+            else if (in_sorted(Si, slen, j) < 0) at += A->val[t];
+        }
+        /* strong F neighbours, distributed over C^_i and i */
+        for (int32_t t = A->rowptr[i]; t < A->rowptr[i + 1]; ++t) {
+            int32_t k = A->col[t];
+            if (k == i || cf[k] || in_sorted(Si, slen, k) < 0) continue;
+            double aik = A->val[t], akk = 0.0, den = 0.0;
+            for (int32_t u = A->rowptr[k]; u < A->rowptr[k + 1]; ++u)
+                if (A->col[u] == k) akk = A->val[u];
+            for (int32_t u = A->rowptr[k]; u < A->rowptr[k + 1]; ++u) {
+                int32_t l = A->col[u];
+                if (l == i || in_sorted(list, len, l) >= 0) den += opp(A->val[u], akk);
+            }
+            if (den == 0.0) { at += aik; continue; }
+            for (int32_t u = A->rowptr[k]; u < A->rowptr[k + 1]; ++u) {
+                int32_t l = A->col[u];
+                double c = (aik * opp(A->val[u], akk)) / den;
+                int32_t pos = in_sorted(list, len, l);
+                if (pos >= 0) w[pos] += c;
+                else if (l == i) at += c;
+            }
+        }
+        for (int32_t s = 0; s < len; ++s) {
+            P->col[q] = cmap[list[s]];
+            P->val[q] = -w[s] / at;
+            ++q;
+        }
+    }
+    P->rowptr[n] = q;
+    P->nnz = q;
+    free(mark); free(list); free(w);
+}
+
 /* C = A B (Gustavson, dense accumulator); each output entry is summed in
  * ascending inner index; output columns ascending; structural zeros kept */
 static void spgemm(const csr_t* A, const csr_t* B, csr_t* C)
@@ -362,13 +482,15 @@ int or_amg_setup(int32_t n, const int32_t* rowptr, const int32_t* col,
             break;
         }
         h->cf[l] = cf;
-        direct_interp(A, &S, cf, cmap, nc, &h->P[l]);
+        if (prm->interp == 1) ext_interp(A, &S, cf, cmap, nc, &h->P[l]);
+        else direct_interp(A, &S, cf, cmap, nc, &h->P[l]);
         if (prm->restriction == 1) {
-            /* Q = direct interpolation of A^T on the same split; R = Q^T */
+            /* Q = the same interpolation built from A^T on the same split; R = Q^T */
             csr_t At, St, Q;
             transpose(A, &At);
             strength(&At, prm->theta, &St);
-            direct_interp(&At, &St, cf, cmap, nc, &Q);
+            if (prm->interp == 1) ext_interp(&At, &St, cf, cmap, nc, &Q);
+            else direct_interp(&At, &St, cf, cmap, nc, &Q);
             transpose(&Q, &h->R[l]);
             csr_free(&At); csr_free(&St); csr_free(&Q);
         } else {

@@ -62,6 +62,7 @@ typedef struct {
     double cheb_lo;      /* interval [cheb_lo, 1] of D_l1^{-1} A (0.3) */
     int32_t restriction; /* 0 Galerkin R = P^T; 1 Petrov-Galerkin R = P(A^T)^T */
     int32_t cheb_degree_coarse; /* degree on levels >= 1 (0: cheb_degree) */
+    int32_t interp;      /* 0 direct interpolation; 1 extended+i */
 } or_amg_params;
 
 typedef struct or_amg or_amg;

@@ -33,6 +33,13 @@ struct tp_ilu {
     tp::DBuf<int32_t> lrows, urows;      // rows grouped by forward and by backward level
     std::vector<int32_t> lptr, uptr;     // level offsets into lrows / urows (host)
     tp::DBuf<int32_t> bad;               // zero-pivot flag of the last factorisation
+    int32_t maxrow = 0;                  // longest row (the lane-per-entry elimination needs <= 16)
+    // Solve copies in level order, fixed width per row (position t of lrows /
+    // urows holds its row's entries at [t * W, t * W + W), column -1 padding):
+    // the strictly lower part, the strictly upper part and U's diagonal.
+    int32_t wl = 0, wu = 0;
+    tp::DBuf<int32_t> lci, uci;
+    tp::DBuf<double> lval, uval, udiag;
 };
 
 namespace tp {
@@ -97,12 +104,99 @@ k_ilu_factor_level(int32_t cnt, const int32_t* __restrict__ rows, const int32_t*
     if (!(piv != 0.0) || !std::isfinite(piv)) bad[0] = 1;
 }
 
-// ---- triangular solves, one level per launch ------------------------------------------------
-// forward: y_i = b_i - sum_{k<i} l_ik y_k  (b and y may alias)
+// Lane-per-entry form of the same elimination (rows of at most G entries):
+// lane l holds entry l of row i.  The columns k of the row's lower part are
+// taken in increasing order as before; the lanes load row k's upper part in
+// one coalesced read and each finds its own column there by shuffles.  Every
+// entry sees the same operations in the same order as in the thread-per-row
+// kernel, so the factors are identical.
+template <int G>
 __global__ void __launch_bounds__(IB)
-k_ilu_lower_level(int32_t cnt, const int32_t* __restrict__ rows, const int32_t* __restrict__ rp,
-                  const int32_t* __restrict__ ci, const int32_t* __restrict__ dg, const double* __restrict__ lu,
-                  const double* b, double* y) {
+k_ilu_factor_level_w(int32_t cnt, const int32_t* __restrict__ rows, const int32_t* __restrict__ rp,
+                     const int32_t* __restrict__ ci, const int32_t* __restrict__ dg, double* __restrict__ lu,
+                     int32_t* __restrict__ bad) {
+    const int64_t tid = (int64_t)blockIdx.x * IB + threadIdx.x;
+    const int32_t t = (int32_t)(tid / G);
+    const int lane = (int)(tid % G);
+    const bool valid = t < cnt;
+    int32_t b = 0, len = 0, nl = 0;
+    if (valid) {
+        const int32_t i = rows[t];
+        b = rp[i];
+        len = rp[i + 1] - b;
+        nl = dg[i] - b;
+    }
+    const bool mine = lane < len;
+    int32_t c = -1;
+    double a = 0.0;
+    int32_t dk = 0, ke = 0;
+    if (mine) {
+        c = ci[b + lane];
+        a = lu[b + lane];
+        if (lane < nl) {  // prefetch where row c's upper part lies
+            dk = dg[c];
+            ke = rp[c + 1];
+        }
+    }
+    for (int m = 0; m < nl; ++m) {  // uniform within the row's lanes
+        const int32_t k = __shfl(c, m, G);
+        const int32_t dkk = __shfl(dk, m, G), kee = __shfl(ke, m, G);
+        const double ukk = lu[dkk];
+        const double lik = __shfl(a, m, G) / ukk;
+        const int32_t u = dkk + 1 + lane;
+        int32_t cu = -1;
+        double vu = 0.0;
+        if (u < kee) {
+            cu = ci[u];
+            vu = lu[u];
+        }
+        double ukj = 0.0;
+        bool hit = false;
+#pragma unroll
+        for (int w = 0; w < G; ++w) {
+            const int32_t cw = __shfl(cu, w, G);
+            const double vw = __shfl(vu, w, G);
+            if (cw == c && cw >= 0) {
+                ukj = vw;
+                hit = true;
+            }
+        }
+        if (lane == m) a = lik;
+        else if (mine && c > k && hit) a -= lik * ukj;
+    }
+    if (mine) lu[b + lane] = a;
+    if (mine && lane == nl && (!(a != 0.0) || !std::isfinite(a))) bad[0] = 1;
+}
+
+// Level-ordered fixed-width copies of the factors for the solves: for
+// position t of a level ordering (row i = rows[t]), entries of the chosen part
+// go to [t * W, t * W + W) with column -1 after the last; with `ud`, also
+// U's diagonal ud[t] = u_ii.
+__global__ void __launch_bounds__(IB)
+k_ilu_ell(int32_t N, const int32_t* __restrict__ rows, const int32_t* __restrict__ rp,
+          const int32_t* __restrict__ ci, const int32_t* __restrict__ dg, const double* __restrict__ lu, int upper,
+          int32_t W, int32_t* __restrict__ oci, double* __restrict__ oval, double* __restrict__ ud) {
+    const int32_t t = blockIdx.x * IB + threadIdx.x;
+    if (t >= N) return;
+    const int32_t i = rows[t];
+    const int32_t q0 = upper ? dg[i] + 1 : rp[i];
+    const int32_t q1 = upper ? rp[i + 1] : dg[i];
+    const int64_t o = (int64_t)t * W;
+    for (int32_t k = 0; k < W; ++k) {
+        const int32_t q = q0 + k;
+        const bool in = q < q1;
+        if (oci) oci[o + k] = in ? ci[q] : -1;
+        oval[o + k] = in ? lu[q] : 0.0;
+    }
+    if (ud) ud[t] = lu[dg[i]];
+}
+
+// ---- triangular solves, one level per launch ------------------------------------------------
+// forward: y_i = b_i - sum_{k<i} l_ik y_k (b and y may alias); the level's
+// rows in the fixed-width level-ordered copy of L
+__global__ void __launch_bounds__(IB)
+k_ilu_lower_level(int32_t cnt, const int32_t* __restrict__ rows, int32_t W, const int32_t* __restrict__ lci,
+                  const double* __restrict__ lval, const double* b, double* y) {
     const int64_t tid = (int64_t)blockIdx.x * IB + threadIdx.x;
     const int32_t t = (int32_t)(tid / IG);
     const int lane = (int)(tid % IG);
@@ -110,8 +204,11 @@ k_ilu_lower_level(int32_t cnt, const int32_t* __restrict__ rows, const int32_t* 
     double s = 0.0;
     if (t < cnt) {
         i = rows[t];
-        const int32_t d = dg[i];
-        for (int32_t q = rp[i] + lane; q < d; q += IG) s += lu[q] * y[ci[q]];
+        const int64_t o = (int64_t)t * W;
+        for (int32_t k = lane; k < W; k += IG) {
+            const int32_t c = lci[o + k];
+            if (c >= 0) s += lval[o + k] * y[c];
+        }
     }
 #pragma unroll
     for (int off = IG / 2; off > 0; off >>= 1) s += __shfl_down(s, off, IG);
@@ -120,22 +217,24 @@ k_ilu_lower_level(int32_t cnt, const int32_t* __restrict__ rows, const int32_t* 
 
 // backward, in place: x_i = (y_i - sum_{k>i} u_ik x_k) / u_ii
 __global__ void __launch_bounds__(IB)
-k_ilu_upper_level(int32_t cnt, const int32_t* __restrict__ rows, const int32_t* __restrict__ rp,
-                  const int32_t* __restrict__ ci, const int32_t* __restrict__ dg, const double* __restrict__ lu,
-                  double* x) {
+k_ilu_upper_level(int32_t cnt, const int32_t* __restrict__ rows, int32_t W, const int32_t* __restrict__ uci,
+                  const double* __restrict__ uval, const double* __restrict__ ud, double* x) {
     const int64_t tid = (int64_t)blockIdx.x * IB + threadIdx.x;
     const int32_t t = (int32_t)(tid / IG);
     const int lane = (int)(tid % IG);
-    int32_t i = 0, d = 0;
+    int32_t i = 0;
     double s = 0.0;
     if (t < cnt) {
         i = rows[t];
-        d = dg[i];
-        for (int32_t q = d + 1 + lane; q < rp[i + 1]; q += IG) s += lu[q] * x[ci[q]];
+        const int64_t o = (int64_t)t * W;
+        for (int32_t k = lane; k < W; k += IG) {
+            const int32_t c = uci[o + k];
+            if (c >= 0) s += uval[o + k] * x[c];
+        }
     }
 #pragma unroll
     for (int off = IG / 2; off > 0; off >>= 1) s += __shfl_down(s, off, IG);
-    if (t < cnt && lane == 0) x[i] = (x[i] - s) / lu[d];
+    if (t < cnt && lane == 0) x[i] = (x[i] - s) / ud[t];
 }
 
 __global__ void k_ilu_clear(int32_t* p) {
@@ -186,18 +285,40 @@ static void analyse(tp_ilu* F, hipStream_t s) {
         lev[i] = l;
     }
     group(F->uptr, F->urows);
+    F->maxrow = F->wl = F->wu = 0;
+    for (int32_t i = 0; i < N; ++i) {
+        F->maxrow = std::max(F->maxrow, rp[i + 1] - rp[i]);
+        F->wl = std::max(F->wl, dg[i] - rp[i]);
+        F->wu = std::max(F->wu, rp[i + 1] - dg[i] - 1);
+    }
+    F->wl = std::max(F->wl, 1);
+    F->wu = std::max(F->wu, 1);
+    F->lci.alloc((size_t)N * F->wl, s);
+    F->lval.alloc((size_t)N * F->wl, s);
+    F->uci.alloc((size_t)N * F->wu, s);
+    F->uval.alloc((size_t)N * F->wu, s);
+    F->udiag.alloc(N, s);
     F->dg.alloc(N, s);
     TP_HIP(hipMemcpyAsync(F->dg.p, dg.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, s));
     TP_HIP(hipStreamSynchronize(s));
 }
 
-static void factorise(tp_ilu* F, hipStream_t s) {
+static void factorise(tp_ilu* F, bool pattern, hipStream_t s) {
     TP_LAUNCH(k_ilu_clear, 1, 64, 0, s, F->bad.p);
     for (size_t l = 0; l + 1 < F->lptr.size(); ++l) {
         const int32_t b = F->lptr[l], cnt = F->lptr[l + 1] - b;
-        TP_LAUNCH(k_ilu_factor_level, cdiv(cnt, IB), IB, 0, s, cnt, F->lrows.p + b, F->rowptr.p, F->col.p,
-                  F->dg.p, F->lu.p, F->bad.p);
+        if (F->maxrow <= 16)
+            TP_LAUNCH(k_ilu_factor_level_w<16>, cdiv((int64_t)cnt * 16, IB), IB, 0, s, cnt, F->lrows.p + b,
+                      F->rowptr.p, F->col.p, F->dg.p, F->lu.p, F->bad.p);
+        else
+            TP_LAUNCH(k_ilu_factor_level, cdiv(cnt, IB), IB, 0, s, cnt, F->lrows.p + b, F->rowptr.p, F->col.p,
+                      F->dg.p, F->lu.p, F->bad.p);
     }
+    const int g = cdiv(F->N, IB);
+    TP_LAUNCH(k_ilu_ell, g, IB, 0, s, F->N, F->lrows.p, F->rowptr.p, F->col.p, F->dg.p, F->lu.p, 0, F->wl,
+              pattern ? F->lci.p : nullptr, F->lval.p, (double*)nullptr);
+    TP_LAUNCH(k_ilu_ell, g, IB, 0, s, F->N, F->urows.p, F->rowptr.p, F->col.p, F->dg.p, F->lu.p, 1, F->wu,
+              pattern ? F->uci.p : nullptr, F->uval.p, F->udiag.p);
     if (read_i32(F->bad.p, s))
         fail(TP_ERR_NUMERIC, "ilu0: zero or non-finite pivot in the incomplete factorisation");
 }
@@ -205,13 +326,13 @@ static void factorise(tp_ilu* F, hipStream_t s) {
 void ilu_solve(tp_ilu* F, const double* b, double* x, hipStream_t s) {
     for (size_t l = 0; l + 1 < F->lptr.size(); ++l) {
         const int32_t o = F->lptr[l], cnt = F->lptr[l + 1] - o;
-        TP_LAUNCH(k_ilu_lower_level, cdiv((int64_t)cnt * IG, IB), IB, 0, s, cnt, F->lrows.p + o, F->rowptr.p,
-                  F->col.p, F->dg.p, F->lu.p, b, x);
+        TP_LAUNCH(k_ilu_lower_level, cdiv((int64_t)cnt * IG, IB), IB, 0, s, cnt, F->lrows.p + o, F->wl,
+                  F->lci.p + (int64_t)o * F->wl, F->lval.p + (int64_t)o * F->wl, b, x);
     }
     for (size_t l = 0; l + 1 < F->uptr.size(); ++l) {
         const int32_t o = F->uptr[l], cnt = F->uptr[l + 1] - o;
-        TP_LAUNCH(k_ilu_upper_level, cdiv((int64_t)cnt * IG, IB), IB, 0, s, cnt, F->urows.p + o, F->rowptr.p,
-                  F->col.p, F->dg.p, F->lu.p, x);
+        TP_LAUNCH(k_ilu_upper_level, cdiv((int64_t)cnt * IG, IB), IB, 0, s, cnt, F->urows.p + o, F->wu,
+                  F->uci.p + (int64_t)o * F->wu, F->uval.p + (int64_t)o * F->wu, F->udiag.p + o, x);
     }
 }
 
@@ -256,7 +377,7 @@ int ilu0_create(int32_t N, const int32_t* rowptr, const int32_t* col, const doub
             TP_HIP(hipMemcpyAsync(F->col.p, col, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, s));
             TP_HIP(hipMemcpyAsync(F->lu.p, val, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
             tp::analyse(F, s);
-            tp::factorise(F, s);
+            tp::factorise(F, true, s);
         } catch (...) {
             (void)hipStreamSynchronize(s);
             delete F;
@@ -284,7 +405,7 @@ int ilu0_create_jacobian(const tp_jacobian* J, void* stream, tp_ilu_t* out) {
             F->bad.alloc(1, s);
             tp::fill_fieldwise(F, J, true, s);
             tp::analyse(F, s);
-            tp::factorise(F, s);
+            tp::factorise(F, true, s);
         } catch (...) {
             (void)hipStreamSynchronize(s);
             delete F;
@@ -303,7 +424,7 @@ int ilu0_refactor_jacobian(tp_ilu_t F, const tp_jacobian* J, void* stream) {
                      "ilu0_refactor_jacobian: the handle was not built from a Jacobian of this size");
         hipStream_t s = (hipStream_t)stream;
         tp::fill_fieldwise(F, J, false, s);
-        tp::factorise(F, s);
+        tp::factorise(F, false, s);
     });
     return TP_OK;
 }

@@ -64,17 +64,24 @@ def _schur_amg(J, cfg, prm, stream=None):
     raise ValueError(f"unknown Schur approximation {cfg.schur!r}")
 
 
-def setup(J, cfg: SolveConfig, concurrent: bool = True):
+def setup(J, cfg: SolveConfig, concurrent: bool = True, ilu=None):
     """Both hierarchies; with `concurrent`, built at the same time on two
     streams from two host threads (the two setups are independent; each
-    call synchronises its own stream before returning)."""
+    call synchronises its own stream before returning).  CPR: the pressure
+    hierarchy and the ILU(0) factors of J; `ilu`, a handle built earlier from
+    a Jacobian with J's pattern, is refactorised in place (numeric
+    factorisation only, the level analysis kept)."""
     import threading
 
     import torch
     p_pp = dataclasses.replace(cfg.amg, restriction=0, storage=cfg.storage)
     p_S = dataclasses.replace(cfg.amg, restriction=1, storage=cfg.storage)
     if cfg.method == "cpr":
-        second = lambda st: tps.ILU0.jacobian(J, stream=st)
+        def second(st):
+            if ilu is None:
+                return tps.ILU0.jacobian(J, stream=st)
+            ilu.refactor(J, stream=st)
+            return ilu
         make = lambda a, b: tps.Precond.cpr(J, a, b)
     elif cfg.method == "block":
         second = lambda st: _schur_amg(J, cfg, p_S, st)
@@ -158,12 +165,16 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None):
     J = G = None
     hier = None
 
-    def close(h):
+    ilu = None   # CPR: one ILU(0) handle per run, refactorised for every Jacobian
+
+    def close(h, final=False):
         if h is not None:
             a_pp, a_S, M = h
             if net is not None:
                 a_S.attach(None, None)
-            M.close(); a_pp.close(); a_S.close()
+            M.close(); a_pp.close()
+            if cfg.method != "cpr" or final:
+                a_S.close()
 
     # S_diag has a pattern of its own; CPR refactorises its ILU(0) in place
     reusable = ncfg.reuse and (cfg.method == "cpr" or cfg.schur in ("T", "ATT"))
@@ -195,7 +206,9 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None):
                 else:
                     close(hier)
                     hier = None
-                    hier = setup(J, cfg)
+                    hier = setup(J, cfg, ilu=ilu)
+                    if cfg.method == "cpr":
+                        ilu = hier[1]
                     builds += 1
                     if net is not None:
                         hier[1].attach(net, prob.grid)
@@ -215,7 +228,9 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None):
             if log:
                 log(f"step {step}: newton {its}, |G|/|G0| {gn / g0 if g0 else 0.0:.2e}")
     finally:
-        close(hier)
+        close(hier, final=True)
+        if ilu is not None:
+            ilu.close()
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     return x, dict(steps=ncfg.steps, newton_iters=newton, linear_iters=lin, solves=solves,
