@@ -449,6 +449,148 @@ k_interp_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __re
     }
 }
 
+// ---- extended+i interpolation -----------------------------------------------------------
+// F point i interpolates from C^_i, its strong C neighbours and the strong C
+// neighbours of its strong F neighbours (De Sterck, Falgout, Nolting, Yang,
+// Numer. Linear Algebra Appl. 15, 2008).  C^_i is the pattern of row i of
+// X Y with X(i,:) = {i} and the strong F neighbours of i (F rows only) and
+// Y(k,:) = the strong C neighbours of k (F rows only), formed by the SpGEMM
+// below (sorted columns).
+__global__ void __launch_bounds__(B)
+k_ext_xy_count(int32_t n, const int32_t* __restrict__ Srp, const int32_t* __restrict__ Sc,
+               const int32_t* __restrict__ cf, int32_t* __restrict__ xc, int32_t* __restrict__ yc) {
+    const int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n) return;
+    int32_t f = 0, c = 0;
+    if (!cf[i]) {
+        for (int32_t q = Srp[i]; q < Srp[i + 1]; ++q) {
+            if (cf[Sc[q]]) ++c;
+            else ++f;
+        }
+        ++f;  // i itself
+    }
+    xc[i] = f;
+    yc[i] = c;
+}
+
+__global__ void __launch_bounds__(B)
+k_ext_xy_fill(int32_t n, const int32_t* __restrict__ Srp, const int32_t* __restrict__ Sc,
+              const int32_t* __restrict__ cf, const int32_t* __restrict__ Xrp, int32_t* __restrict__ Xc,
+              double* __restrict__ Xv, const int32_t* __restrict__ Yrp, int32_t* __restrict__ Yc,
+              double* __restrict__ Yv) {
+    const int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n || cf[i]) return;
+    int32_t x = Xrp[i], y = Yrp[i];
+    bool self = false;
+    for (int32_t q = Srp[i]; q < Srp[i + 1]; ++q) {
+        const int32_t j = Sc[q];
+        if (!self && j > i) {  // keep X's row ascending
+            Xc[x] = i;
+            Xv[x++] = 1.0;
+            self = true;
+        }
+        if (cf[j]) {
+            Yc[y] = j;
+            Yv[y++] = 1.0;
+        } else {
+            Xc[x] = j;
+            Xv[x++] = 1.0;
+        }
+    }
+    if (!self) {
+        Xc[x] = i;
+        Xv[x] = 1.0;
+    }
+}
+
+__global__ void __launch_bounds__(B)
+k_ext_count(int32_t n, const int32_t* __restrict__ cf, const int32_t* __restrict__ Trp, int32_t* __restrict__ cnt) {
+    const int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i < n) cnt[i] = cf[i] ? 1 : Trp[i + 1] - Trp[i];
+}
+
+// index of x in the ascending v[0..len), or -1
+__device__ inline int32_t find_sorted(const int32_t* __restrict__ v, int32_t len, int32_t x) {
+    int32_t lo = 0, hi = len;
+    while (lo < hi) {
+        const int32_t mid = lo + (hi - lo) / 2;
+        if (v[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < len && v[lo] == x) ? lo : -1;
+}
+
+__device__ inline double opposite(double a, double akk) { return (akk > 0.0 ? a < 0.0 : a > 0.0) ? a : 0.0; }
+
+// Weights of row i: with den_k = sum of hat a_kl over l in C^_i and l = i
+// for each strong F neighbour k (hat a_kl = a_kl where its sign is opposite
+// to a_kk's, else 0),
+//   a~_ii = a_ii + (weak couplings outside C^_i) + sum_k a_ik hat a_ki / den_k,
+//   w_ij  = -(a_ij + sum_k a_ik hat a_kj / den_k) / a~_ii,
+// summed in the row's column order, then k ascending over row k's order; a
+// strong F neighbour with den_k = 0 is lumped like a weak one.
+__global__ void __launch_bounds__(B)
+k_ext_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+           const double* __restrict__ val, const int32_t* __restrict__ Srp, const int32_t* __restrict__ Sc,
+           const int32_t* __restrict__ cf, const int32_t* __restrict__ cmap, const int32_t* __restrict__ Trp,
+           const int32_t* __restrict__ Tc, const int32_t* __restrict__ Prp, int32_t* __restrict__ Pc,
+           double* __restrict__ Pv) {
+    const int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n) return;
+    const int32_t p0 = Prp[i];
+    if (cf[i]) {
+        Pc[p0] = cmap[i];
+        Pv[p0] = 1.0;
+        return;
+    }
+    const int32_t* list = Tc + Trp[i];
+    const int32_t len = Trp[i + 1] - Trp[i];
+    if (len == 0) return;
+    const int32_t* Si = Sc + Srp[i];
+    const int32_t slen = Srp[i + 1] - Srp[i];
+    double* w = Pv + p0;
+    for (int32_t t = 0; t < len; ++t) {
+        Pc[p0 + t] = cmap[list[t]];
+        w[t] = 0.0;
+    }
+    double aii = 0.0;
+    for (int32_t t = rowptr[i]; t < rowptr[i + 1]; ++t)
+        if (col[t] == i) aii = val[t];
+    double at = aii;
+    for (int32_t t = rowptr[i]; t < rowptr[i + 1]; ++t) {
+        const int32_t j = col[t];
+        if (j == i) continue;
+        const int32_t pos = find_sorted(list, len, j);
+        if (pos >= 0) w[pos] += val[t];
+        else if (find_sorted(Si, slen, j) < 0) at += val[t];
+    }
+    for (int32_t t = rowptr[i]; t < rowptr[i + 1]; ++t) {
+        const int32_t k = col[t];
+        if (k == i || cf[k] || find_sorted(Si, slen, k) < 0) continue;
+        const double aik = val[t];
+        double akk = 0.0, den = 0.0;
+        const int32_t kb = rowptr[k], ke = rowptr[k + 1];
+        for (int32_t u = kb; u < ke; ++u)
+            if (col[u] == k) akk = val[u];
+        for (int32_t u = kb; u < ke; ++u) {
+            const int32_t l = col[u];
+            if (l == i || find_sorted(list, len, l) >= 0) den += opposite(val[u], akk);
+        }
+        if (den == 0.0) {
+            at += aik;
+            continue;
+        }
+        for (int32_t u = kb; u < ke; ++u) {
+            const int32_t l = col[u];
+            const double c = (aik * opposite(val[u], akk)) / den;
+            const int32_t pos = find_sorted(list, len, l);
+            if (pos >= 0) w[pos] += c;
+            else if (l == i) at += c;
+        }
+    }
+    for (int32_t t = 0; t < len; ++t) w[t] = -w[t] / at;
+}
+
 // ---- SpGEMM C = A B with an LDS hash per row --------------------------------------------
 constexpr int HASH = 2048;
 constexpr int HASH_LOG = 11;
@@ -1331,6 +1473,42 @@ static void direct_interp(const Csr& A, const Csr& S, const int32_t* cf, const i
     }
 }
 
+static void ext_interp(const Csr& A, const Csr& S, const int32_t* cf, const int32_t* cmap, int32_t nc,
+                       Csr& P, int32_t* flag, hipStream_t s) {
+    const int32_t n = A.n;
+    Csr X, Y, T;
+    X.n = Y.n = n;
+    X.m = Y.m = n;
+    X.rowptr.alloc(n + 1, s);
+    Y.rowptr.alloc(n + 1, s);
+    if (n > 0) TP_LAUNCH(k_ext_xy_count, cdiv(n, B), B, 0, s, n, S.rowptr.p, S.col.p, cf, X.rowptr.p, Y.rowptr.p);
+    scan_exclusive(X.rowptr.p, X.rowptr.p, n, s);
+    scan_exclusive(Y.rowptr.p, Y.rowptr.p, n, s);
+    // upper bounds (one entry of S, or i itself, per entry of X and Y); the
+    // SpGEMM reads the exact sizes from the row pointers
+    X.nnz = S.nnz + n;
+    Y.nnz = S.nnz;
+    X.col.alloc(std::max(X.nnz, 1), s);
+    X.val.alloc(std::max(X.nnz, 1), s);
+    Y.col.alloc(std::max(Y.nnz, 1), s);
+    Y.val.alloc(std::max(Y.nnz, 1), s);
+    if (n > 0)
+        TP_LAUNCH(k_ext_xy_fill, cdiv(n, B), B, 0, s, n, S.rowptr.p, S.col.p, cf, X.rowptr.p, X.col.p, X.val.p,
+                  Y.rowptr.p, Y.col.p, Y.val.p);
+    spgemm(X, Y, T, flag, s);
+    P.n = n;
+    P.m = nc;
+    P.rowptr.alloc(n + 1, s);
+    if (n > 0) TP_LAUNCH(k_ext_count, cdiv(n, B), B, 0, s, n, cf, T.rowptr.p, P.rowptr.p);
+    scan_exclusive(P.rowptr.p, P.rowptr.p, n, s);
+    P.nnz = read_i32(P.rowptr.p + n, s);
+    P.col.alloc(std::max(P.nnz, 1), s);
+    P.val.alloc(std::max(P.nnz, 1), s);
+    if (n > 0)
+        TP_LAUNCH(k_ext_fill, cdiv(n, B), B, 0, s, n, A.rowptr.p, A.col.p, A.val.p, S.rowptr.p, S.col.p, cf, cmap,
+                  T.rowptr.p, T.col.p, P.rowptr.p, P.col.p, P.val.p);
+}
+
 static void make_f32(DBuf<float>& dst, const DBuf<double>& src, size_t n, hipStream_t s) {
     dst.alloc(n, s);
     if (n) TP_LAUNCH(k_to_f32, cdiv(n, B), B, 0, s, (int64_t)n, src.p, dst.p);
@@ -1535,12 +1713,14 @@ static void setup(tp_amg* h, int32_t n, const int32_t* rowptr, const int32_t* co
             L.cf.release();
             break;
         }
-        direct_interp(A, S, L.cf.p, cmap.p, nc, L.P, s);
+        if (prm.interp == 1) ext_interp(A, S, L.cf.p, cmap.p, nc, L.P, sg_flag.p, s);
+        else direct_interp(A, S, L.cf.p, cmap.p, nc, L.P, s);
         if (prm.restriction == 1) {
             Csr At, St, Q;
             transpose(A.rowptr.p, A.col.p, A.val.p, A.n, A.n, A.nnz, true, At, s);
             strength(At, prm.theta, St, s);
-            direct_interp(At, St, L.cf.p, cmap.p, nc, Q, s);
+            if (prm.interp == 1) ext_interp(At, St, L.cf.p, cmap.p, nc, Q, sg_flag.p, s);
+            else direct_interp(At, St, L.cf.p, cmap.p, nc, Q, s);
             transpose(Q.rowptr.p, Q.col.p, Q.val.p, Q.n, nc, Q.nnz, true, L.R, s);
         } else {
             transpose(L.P.rowptr.p, L.P.col.p, L.P.val.p, L.P.n, nc, L.P.nnz, true, L.R, s);
@@ -1691,6 +1871,7 @@ int amg_setup(int32_t n, const int32_t* rowptr, const int32_t* col, const double
                      "amg_setup: sweeps must be in [0,8]");
         TP_CHECK_ARG(p.restriction == 0 || p.restriction == 1, "amg_setup: restriction must be 0 or 1");
         TP_CHECK_ARG(p.storage >= 0 && p.storage <= 2, "amg_setup: storage must be 0, 1 or 2");
+        TP_CHECK_ARG(p.interp == 0 || p.interp == 1, "amg_setup: interp must be 0 or 1");
         hipStream_t s = (hipStream_t)stream;
         tp_amg* h = new tp_amg();
         h->prm = p;

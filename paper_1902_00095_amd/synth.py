@@ -216,6 +216,22 @@ def make_problem(name: str, seed: int | None = None, props: Props | None = None,
         x_prev[1::2] = props.T0
         return Problem(name, grid, props, K, phi, kap, corner_wells(grid, 450.0),
                        DAY, x_prev, x_prev.copy(), seed)
+    if name == "R2":
+        # mesh-refinement recipe: N x N cells of a 20 m x 20 m x 1 m slab,
+        # homogeneous, uniform start, an injector (450 K) and a producer at
+        # opposite corners; the flow the wells drive stays smooth as the mesh
+        # is refined
+        seed = 0 if seed is None else seed
+        grid = grid or Grid(80, 80, 1, 20.0 / 80, 20.0 / 80, 1.0)
+        n = grid.n
+        K = np.full(n, 1.0e-13)
+        phi = np.full(n, 0.2)
+        kap = np.full(n, 2.0 if kappa is None else kappa)
+        x_prev = np.empty(2 * n)
+        x_prev[0::2] = props.p0
+        x_prev[1::2] = props.T0
+        return Problem(name, grid, props, K, phi, kap, corner_wells(grid, 450.0, rate=1.0e-6),
+                       DAY, x_prev, x_prev.copy(), seed)
     raise ValueError(f"unknown workload {name!r}")
 
 

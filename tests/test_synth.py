@@ -37,3 +37,13 @@ def test_perturbation_statistics():
     dp = p.x_k[0::2] - p.x_prev[0::2]
     dT = p.x_k[1::2] - p.x_prev[1::2]
     assert abs(np.std(dp) / 1e5 - 1) < 0.02 and abs(np.std(dT) / 5 - 1) < 0.02
+
+
+def test_refinement_recipe_uniform_start_and_corner_wells():
+    for N in (20, 40):
+        g = synth.Grid(N, N, 1, 20.0 / N, 20.0 / N, 1.0)
+        p = synth.make_problem("R2", grid=g)
+        assert p.grid.n == N * N and np.all(p.K == 1e-13) and np.all(p.phi == 0.2)
+        assert np.array_equal(p.x_prev, p.x_k)
+        assert np.all(p.x_k[0::2] == p.props.p0) and np.all(p.x_k[1::2] == p.props.T0)
+        assert [(w.cell, w.kind) for w in p.wells] == [(0, 0), (N * N - 1, 1)]
