@@ -304,8 +304,18 @@ def run_variants(prob, dev, cfg, iters64, ms64):
         _progress(f"W5 {key}: {st5['solves']} solves, {st5['total_s']:.1f} s")
         st5.pop("newton_per_step", None)
         w5[key] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st5.items()}
-    out["W5_256x256x64_20_steps"] = dict(w5, note="per Newton iteration: assembly, both AMG setups, FGMRES to rtol; "
+    out["W5_256x256x64_20_steps"] = dict(w5, note="thermal conductivity 20 W/m/K (conduction-dominated); "
+                                         "per Newton iteration: assembly, both AMG setups, FGMRES to rtol; "
                                          "Newton stops at |G|/|G0| or |dx|/|x| <= 1e-8 or after 4 iterations")
+    # the same run advection-dominated (thermal conductivity 0.5 W/m/K)
+    p5a = synth.make_problem("W5", kappa=0.5)
+    w5a = {}
+    for key, c5, nt in (("fp64", cfg, None), ("mixed_learned", dc.replace(cfg, storage=1), net)):
+        _, st5 = solver.simulate(p5a, c5, nc, net=nt)
+        _progress(f"W5 kappa 0.5 {key}: {st5['solves']} solves, {st5['total_s']:.1f} s")
+        st5.pop("newton_per_step", None)
+        w5a[key] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st5.items()}
+    out["W5_256x256x64_20_steps_kappa_0.5"] = dict(w5a, note="thermal conductivity 0.5 W/m/K (advection-dominated)")
     net.close()
     return out
 
