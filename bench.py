@@ -310,7 +310,8 @@ def run_variants(prob, dev, cfg, iters64, ms64):
     # the same run advection-dominated (thermal conductivity 0.5 W/m/K)
     p5a = synth.make_problem("W5", kappa=0.5)
     w5a = {}
-    for key, c5, nt in (("fp64", cfg, None), ("mixed_learned", dc.replace(cfg, storage=1), net)):
+    for key, c5, nt in (("fp64", cfg, None), ("fp32_hierarchy", dc.replace(cfg, storage=1), None),
+                        ("mixed_learned", dc.replace(cfg, storage=1), net)):
         _, st5 = solver.simulate(p5a, c5, nc, net=nt)
         _progress(f"W5 kappa 0.5 {key}: {st5['solves']} solves, {st5['total_s']:.1f} s")
         st5.pop("newton_per_step", None)
