@@ -134,6 +134,9 @@ typedef struct {
                               strong F neighbours (De Sterck, Falgout, Nolting, Yang,
                               Numer. Linear Algebra Appl. 15, 2008); with restriction 1
                               Q is built the same way from A^T */
+    int32_t interp_pmax;   /* extended+i only, 0..16: a row of more weights keeps the
+                              interp_pmax of largest magnitude (ties: smaller column),
+                              scaled to the row's full sum; 0 keeps all; 4 */
 } tp_amg_params;
 
 typedef struct tp_amg* tp_amg_t;

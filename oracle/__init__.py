@@ -67,7 +67,7 @@ class _AmgParams(C.Structure):
                 ("coarse_max", C.c_int32), ("omega", C.c_double), ("nu_pre", C.c_int32),
                 ("nu_post", C.c_int32), ("skip_lu", C.c_int32), ("smoother", C.c_int32),
                 ("cheb_degree", C.c_int32), ("cheb_lo", C.c_double), ("restriction", C.c_int32),
-                ("cheb_degree_coarse", C.c_int32), ("interp", C.c_int32)]
+                ("cheb_degree_coarse", C.c_int32), ("interp", C.c_int32), ("interp_pmax", C.c_int32)]
 
 
 class _Ilu(C.Structure):
@@ -274,11 +274,11 @@ class AMG:
 
     def __init__(self, n, rowptr, col, val, theta=0.25, seed=12345, max_levels=25,
                  coarse_max=256, omega=1.0, nu_pre=1, nu_post=1, skip_lu=False,
-                 smoother=1, cheb_degree=3, cheb_lo=0.3, restriction=0, cheb_degree_coarse=0, interp=0):
+                 smoother=1, cheb_degree=3, cheb_lo=0.3, restriction=0, cheb_degree_coarse=0, interp=0, interp_pmax=0):
         self._rowptr, self._col, self._val = _i32(rowptr), _i32(col), _f64(val)
         prm = _AmgParams(theta, seed, max_levels, coarse_max, omega, nu_pre, nu_post,
                          1 if skip_lu else 0, smoother, cheb_degree, cheb_lo, restriction,
-                         cheb_degree_coarse, interp)
+                         cheb_degree_coarse, interp, interp_pmax)
         h = C.c_void_p()
         self.status = lib().or_amg_setup(C.c_int32(n), _p(self._rowptr), _p(self._col),
                                          _p(self._val), C.byref(prm), C.byref(h))

@@ -289,17 +289,26 @@ static int32_t ext_set(const csr_t* S, const int32_t* cf, int32_t i, int32_t* ma
  * is lumped into a~_ii like a weak one.  Sums run in ascending column order
  * (the row's own entries first, then the strong F neighbours k ascending,
  * each over row k ascending).  C points interpolate themselves; an F point
- * with an empty set gets an empty row. */
+ * with an empty set gets an empty row.
+ * Truncation (pmax > 0): a row of more than pmax weights keeps the pmax of
+ * largest magnitude (ties: the smaller column), scaled by
+ * f = (sum of all its weights) / (sum of the kept ones), both sums in
+ * ascending column order (no scaling when the kept sum is 0): the row sum
+ * is preserved. */
 static void ext_interp(const csr_t* A, const csr_t* S, const int32_t* cf,
-                       const int32_t* cmap, int32_t nc, csr_t* P)
+                       const int32_t* cmap, int32_t nc, int32_t pmax, csr_t* P)
 {
     int32_t n = A->n;
     int32_t* mark = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     int32_t* list = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     double* w = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    char* keep = malloc((size_t)(n > 0 ? n : 1));
     for (int32_t j = 0; j < n; ++j) mark[j] = -1;
     int64_t nnz = 0;
-    for (int32_t i = 0; i < n; ++i) nnz += cf[i] ? 1 : ext_set(S, cf, i, mark, list);
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t len = cf[i] ? 1 : ext_set(S, cf, i, mark, list);
+        nnz += (pmax > 0 && len > pmax) ? pmax : len;
+    }
     csr_alloc(P, n, nc, (int32_t)nnz);
     for (int32_t j = 0; j < n; ++j) mark[j] = -1;
     int32_t q = 0;
@@ -343,15 +352,36 @@ static void ext_interp(const csr_t* A, const csr_t* S, const int32_t* cf,
                 else if (l == i) at += c;
             }
         }
-        for (int32_t s = 0; s < len; ++s) {
-            P->col[q] = cmap[list[s]];
-            P->val[q] = -w[s] / at;
-            ++q;
+        for (int32_t s = 0; s < len; ++s) w[s] = -w[s] / at;
+        if (pmax > 0 && len > pmax) {
+            for (int32_t s = 0; s < len; ++s) keep[s] = 0;
+            for (int32_t r = 0; r < pmax; ++r) {
+                int32_t best = -1;
+                for (int32_t s = 0; s < len; ++s)
+                    if (!keep[s] && (best < 0 || fabs(w[s]) > fabs(w[best]))) best = s;
+                keep[best] = 1;
+            }
+            double all = 0.0, kept = 0.0;
+            for (int32_t s = 0; s < len; ++s) all += w[s];
+            for (int32_t s = 0; s < len; ++s) if (keep[s]) kept += w[s];
+            double f = kept != 0.0 ? all / kept : 1.0;
+            for (int32_t s = 0; s < len; ++s)
+                if (keep[s]) {
+                    P->col[q] = cmap[list[s]];
+                    P->val[q] = kept != 0.0 ? w[s] * f : w[s];
+                    ++q;
+                }
+        } else {
+            for (int32_t s = 0; s < len; ++s) {
+                P->col[q] = cmap[list[s]];
+                P->val[q] = w[s];
+                ++q;
+            }
         }
     }
     P->rowptr[n] = q;
     P->nnz = q;
-    free(mark); free(list); free(w);
+    free(mark); free(list); free(w); free(keep);
 }
 
 /* C = A B (Gustavson, dense accumulator); each output entry is summed in
@@ -482,14 +512,14 @@ int or_amg_setup(int32_t n, const int32_t* rowptr, const int32_t* col,
             break;
         }
         h->cf[l] = cf;
-        if (prm->interp == 1) ext_interp(A, &S, cf, cmap, nc, &h->P[l]);
+        if (prm->interp == 1) ext_interp(A, &S, cf, cmap, nc, prm->interp_pmax, &h->P[l]);
         else direct_interp(A, &S, cf, cmap, nc, &h->P[l]);
         if (prm->restriction == 1) {
             /* Q = the same interpolation built from A^T on the same split; R = Q^T */
             csr_t At, St, Q;
             transpose(A, &At);
             strength(&At, prm->theta, &St);
-            if (prm->interp == 1) ext_interp(&At, &St, cf, cmap, nc, &Q);
+            if (prm->interp == 1) ext_interp(&At, &St, cf, cmap, nc, prm->interp_pmax, &Q);
             else direct_interp(&At, &St, cf, cmap, nc, &Q);
             transpose(&Q, &h->R[l]);
             csr_free(&At); csr_free(&St); csr_free(&Q);

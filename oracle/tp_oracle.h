@@ -63,6 +63,7 @@ typedef struct {
     int32_t restriction; /* 0 Galerkin R = P^T; 1 Petrov-Galerkin R = P(A^T)^T */
     int32_t cheb_degree_coarse; /* degree on levels >= 1 (0: cheb_degree) */
     int32_t interp;      /* 0 direct interpolation; 1 extended+i */
+    int32_t interp_pmax; /* extended+i: keep at most this many weights per row (0: all) */
 } or_amg_params;
 
 typedef struct or_amg or_amg;

@@ -529,14 +529,12 @@ __device__ inline double opposite(double a, double akk) { return (akk > 0.0 ? a 
 //   w_ij  = -(a_ij + sum_k a_ik hat a_kj / den_k) / a~_ii,
 // summed in the row's column order, then k ascending over row k's order; a
 // strong F neighbour with den_k = 0 is lumped like a weak one.
-__global__ void __launch_bounds__(B)
-k_ext_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-           const double* __restrict__ val, const int32_t* __restrict__ Srp, const int32_t* __restrict__ Sc,
-           const int32_t* __restrict__ cf, const int32_t* __restrict__ cmap, const int32_t* __restrict__ Trp,
-           const int32_t* __restrict__ Tc, const int32_t* __restrict__ Prp, int32_t* __restrict__ Pc,
-           double* __restrict__ Pv) {
-    const int32_t i = blockIdx.x * B + threadIdx.x;
-    if (i >= n) return;
+__device__ void ext_row(int32_t i, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                        const double* __restrict__ val, const int32_t* __restrict__ Srp,
+                        const int32_t* __restrict__ Sc, const int32_t* __restrict__ cf,
+                        const int32_t* __restrict__ cmap, const int32_t* __restrict__ Trp,
+                        const int32_t* __restrict__ Tc, const int32_t* __restrict__ Prp, int32_t* __restrict__ Pc,
+                        double* __restrict__ Pv) {
     const int32_t p0 = Prp[i];
     if (cf[i]) {
         Pc[p0] = cmap[i];
@@ -589,6 +587,153 @@ k_ext_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restr
         }
     }
     for (int32_t t = 0; t < len; ++t) w[t] = -w[t] / at;
+}
+
+__global__ void __launch_bounds__(B)
+k_ext_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+           const double* __restrict__ val, const int32_t* __restrict__ Srp, const int32_t* __restrict__ Sc,
+           const int32_t* __restrict__ cf, const int32_t* __restrict__ cmap, const int32_t* __restrict__ Trp,
+           const int32_t* __restrict__ Tc, const int32_t* __restrict__ Prp, int32_t* __restrict__ Pc,
+           double* __restrict__ Pv) {
+    const int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i < n) ext_row(i, rowptr, col, val, Srp, Sc, cf, cmap, Trp, Tc, Prp, Pc, Pv);
+}
+
+// Wavefront-per-row form for levels of long rows.  Weight slot t of the row
+// lives in a register of lane t mod 64; the terms of each sum are broadcast
+// to the wavefront one by one in the order of the one-thread form, so every
+// slot, a~_ii and every den_k receive the same operations in the same order
+// (identical results).  Rows of more than EXT_SLOTS slots take the one-thread
+// form on lane 0.
+constexpr int EXT_NW = 4;
+constexpr int EXT_SLOTS = WR * EXT_NW;
+
+__global__ void __launch_bounds__(B)
+k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+             const double* __restrict__ val, const int32_t* __restrict__ Srp, const int32_t* __restrict__ Sc,
+             const int32_t* __restrict__ cf, const int32_t* __restrict__ cmap, const int32_t* __restrict__ Trp,
+             const int32_t* __restrict__ Tc, const int32_t* __restrict__ Prp, int32_t* __restrict__ Pc,
+             double* __restrict__ Pv) {
+    const int32_t i = blockIdx.x * WR_ROWS + threadIdx.x / WR;
+    const int lane = threadIdx.x % WR;
+    if (i >= n) return;
+    const int32_t p0 = Prp[i];
+    if (cf[i]) {
+        if (lane == 0) {
+            Pc[p0] = cmap[i];
+            Pv[p0] = 1.0;
+        }
+        return;
+    }
+    const int32_t* list = Tc + Trp[i];
+    const int32_t len = Trp[i + 1] - Trp[i];
+    if (len == 0) return;
+    if (len > EXT_SLOTS) {
+        if (lane == 0) ext_row(i, rowptr, col, val, Srp, Sc, cf, cmap, Trp, Tc, Prp, Pc, Pv);
+        return;
+    }
+    const int32_t* Si = Sc + Srp[i];
+    const int32_t slen = Srp[i + 1] - Srp[i];
+    double w[EXT_NW];
+#pragma unroll
+    for (int r = 0; r < EXT_NW; ++r) w[r] = 0.0;
+    auto add = [&](int32_t pos, double c) {  // slot pos += c, on its owner lane
+#pragma unroll
+        for (int r = 0; r < EXT_NW; ++r)
+            if (pos == r * WR + lane) w[r] += c;
+    };
+    const int32_t a = rowptr[i], e = rowptr[i + 1];
+    double aii = 0.0;
+    bool has = false;
+    for (int32_t q = a + lane; q < e; q += WR)
+        if (col[q] == i) { aii = val[q]; has = true; }
+    const uint64_t hm = __ballot(has);
+    aii = hm ? __shfl(aii, __ffsll((unsigned long long)hm) - 1, WR) : 0.0;
+    double at = aii;
+    // the row's own couplings
+    for (int32_t b = a; b < e; b += WR) {
+        const int32_t q = b + lane;
+        const bool ok = q < e;
+        const int32_t j = ok ? col[q] : i;
+        const double v = ok ? val[q] : 0.0;
+        int32_t pos = -1;
+        bool lump = false;
+        if (ok && j != i) {
+            pos = find_sorted(list, len, j);
+            lump = pos < 0 && find_sorted(Si, slen, j) < 0;
+        }
+        const int cnt = min(WR, (int)(e - b));
+        for (int l = 0; l < cnt; ++l) {
+            const int32_t pl = __shfl(pos, l, WR);
+            const double vl = __shfl(v, l, WR);
+            const bool ll = __shfl((int)lump, l, WR);
+            if (pl >= 0) add(pl, vl);
+            else if (ll) at += vl;
+        }
+    }
+    // strong F neighbours k, ascending
+    for (int32_t b = a; b < e; b += WR) {
+        const int32_t q = b + lane;
+        const bool ok = q < e;
+        const int32_t k0 = ok ? col[q] : i;
+        const bool sf = ok && k0 != i && !cf[k0] && find_sorted(Si, slen, k0) >= 0;
+        uint64_t m = __ballot(sf);
+        while (m) {
+            const int l = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            const int32_t k = __shfl(k0, l, WR);
+            const double aik = __shfl(ok ? val[q] : 0.0, l, WR);
+            const int32_t kb = rowptr[k], ke = rowptr[k + 1];
+            double akk = 0.0;
+            bool hk = false;
+            for (int32_t u = kb + lane; u < ke; u += WR)
+                if (col[u] == k) { akk = val[u]; hk = true; }
+            const uint64_t km = __ballot(hk);
+            akk = km ? __shfl(akk, __ffsll((unsigned long long)km) - 1, WR) : 0.0;
+            double den = 0.0;
+            for (int32_t c0 = kb; c0 < ke; c0 += WR) {
+                const int32_t u = c0 + lane;
+                const bool in = u < ke;
+                const int32_t lc = in ? col[u] : -1;
+                const bool mem = in && (lc == i || find_sorted(list, len, lc) >= 0);
+                const double h = mem ? opposite(val[u], akk) : 0.0;
+                const uint64_t mm = __ballot(mem);
+                const int cnt = min(WR, (int)(ke - c0));
+                for (int t = 0; t < cnt; ++t) {
+                    const double ht = __shfl(h, t, WR);
+                    if ((mm >> t) & 1ull) den += ht;
+                }
+            }
+            if (den == 0.0) {
+                at += aik;
+                continue;
+            }
+            for (int32_t c0 = kb; c0 < ke; c0 += WR) {
+                const int32_t u = c0 + lane;
+                const bool in = u < ke;
+                const int32_t lc = in ? col[u] : -1;
+                const double c = in ? (aik * opposite(val[u], akk)) / den : 0.0;
+                const int32_t pos = in ? find_sorted(list, len, lc) : -1;
+                const bool self = in && pos < 0 && lc == i;
+                const int cnt = min(WR, (int)(ke - c0));
+                for (int t = 0; t < cnt; ++t) {
+                    const int32_t pt = __shfl(pos, t, WR);
+                    const double ct = __shfl(c, t, WR);
+                    const bool st = __shfl((int)self, t, WR);
+                    if (pt >= 0) add(pt, ct);
+                    else if (st) at += ct;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < EXT_NW; ++r) {
+        const int32_t t = r * WR + lane;
+        if (t < len) {
+            Pc[p0 + t] = cmap[list[t]];
+            Pv[p0 + t] = -w[r] / at;
+        }
+    }
 }
 
 // ---- SpGEMM C = A B with an LDS hash per row --------------------------------------------
@@ -1504,7 +1649,10 @@ static void ext_interp(const Csr& A, const Csr& S, const int32_t* cf, const int3
     P.nnz = read_i32(P.rowptr.p + n, s);
     P.col.alloc(std::max(P.nnz, 1), s);
     P.val.alloc(std::max(P.nnz, 1), s);
-    if (n > 0)
+    if (n > 0 && long_rows(A.n, A.nnz))
+        TP_LAUNCH(k_ext_fill_w, cdiv(n, WR_ROWS), B, 0, s, n, A.rowptr.p, A.col.p, A.val.p, S.rowptr.p, S.col.p, cf,
+                  cmap, T.rowptr.p, T.col.p, P.rowptr.p, P.col.p, P.val.p);
+    else if (n > 0)
         TP_LAUNCH(k_ext_fill, cdiv(n, B), B, 0, s, n, A.rowptr.p, A.col.p, A.val.p, S.rowptr.p, S.col.p, cf, cmap,
                   T.rowptr.p, T.col.p, P.rowptr.p, P.col.p, P.val.p);
 }

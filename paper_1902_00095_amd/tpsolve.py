@@ -53,7 +53,7 @@ class _AmgParams(C.Structure):
                 ("coarse_max", C.c_int32), ("smoother", C.c_int32), ("cheb_degree", C.c_int32),
                 ("cheb_lo", C.c_double), ("omega", C.c_double), ("nu_pre", C.c_int32),
                 ("nu_post", C.c_int32), ("restriction", C.c_int32), ("storage", C.c_int32),
-                ("cheb_degree_coarse", C.c_int32), ("interp", C.c_int32)]
+                ("cheb_degree_coarse", C.c_int32), ("interp", C.c_int32), ("interp_pmax", C.c_int32)]
 
 
 class _KParams(C.Structure):
@@ -129,6 +129,7 @@ class AmgParams:
     storage: int = 0           # 0 FP64, 1 FP32, 2 FP32 with BF16 off-diagonal operator entries
     cheb_degree_coarse: int = 1  # degree on levels >= 1 (0: cheb_degree)
     interp: int = 0            # 0 direct interpolation, 1 extended+i (distance two)
+    interp_pmax: int = 4       # extended+i: at most this many weights per row (0: all)
 
     def oracle_kwargs(self):
         """The same parameters as keyword arguments of the CPU oracle's AMG
@@ -137,12 +138,14 @@ class AmgParams:
                     coarse_max=self.coarse_max, omega=self.omega, nu_pre=self.nu_pre,
                     nu_post=self.nu_post, smoother=self.smoother, cheb_degree=self.cheb_degree,
                     cheb_lo=self.cheb_lo, restriction=self.restriction,
-                    cheb_degree_coarse=self.cheb_degree_coarse, interp=self.interp)
+                    cheb_degree_coarse=self.cheb_degree_coarse, interp=self.interp,
+                    interp_pmax=self.interp_pmax)
 
     def c(self):
         return _AmgParams(self.theta, self.seed, self.max_levels, self.coarse_max, self.smoother,
                           self.cheb_degree, self.cheb_lo, self.omega, self.nu_pre, self.nu_post,
-                          self.restriction, self.storage, self.cheb_degree_coarse, self.interp)
+                          self.restriction, self.storage, self.cheb_degree_coarse, self.interp,
+                          self.interp_pmax)
 
 
 def _torch():

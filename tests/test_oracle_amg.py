@@ -195,6 +195,35 @@ def test_extended_interpolation_weights_from_definition():
     assert checked > 0 and any(len([k for k in S[i] if not cf[k]]) for i in np.nonzero(cf == 0)[0])
 
 
+def test_extended_interpolation_truncation():
+    """With at most 4 weights per row, a longer row keeps the 4 of largest
+    magnitude of the full extended+i row (same C/F split on the finest
+    level), scaled so that the row sum is unchanged; shorter rows are the
+    full rows."""
+    J = _problem_ops(dims=(6, 5, 4))
+    kw = dict(max_levels=2, coarse_max=0, skip_lu=True, interp=1)
+    hf = oracle.AMG(J.n, J.rowptr, J.col, J.S, interp_pmax=0, **kw)
+    ht = oracle.AMG(J.n, J.rowptr, J.col, J.S, interp_pmax=4, **kw)
+    Lf, Lt = hf.level(0), ht.level(0)
+    assert np.array_equal(Lf["cf"], Lt["cf"])
+    cut = 0
+    for i in range(J.n):
+        fc = Lf["P_col"][Lf["P_rowptr"][i]:Lf["P_rowptr"][i + 1]]
+        fv = Lf["P_val"][Lf["P_rowptr"][i]:Lf["P_rowptr"][i + 1]]
+        tc = Lt["P_col"][Lt["P_rowptr"][i]:Lt["P_rowptr"][i + 1]]
+        tv = Lt["P_val"][Lt["P_rowptr"][i]:Lt["P_rowptr"][i + 1]]
+        if len(fc) <= 4:
+            assert np.array_equal(fc, tc) and np.array_equal(fv, tv)
+            continue
+        cut += 1
+        order = sorted(range(len(fc)), key=lambda t: (-abs(fv[t]), fc[t]))[:4]
+        keep = sorted(order)
+        assert np.array_equal(tc, fc[keep])
+        np.testing.assert_allclose(tv, fv[keep] * (fv.sum() / fv[keep].sum()), rtol=1e-14)
+        assert abs(tv.sum() - fv.sum()) <= 1e-14 * abs(fv).sum()
+    assert cut > 0
+
+
 @pytest.mark.parametrize("restriction,interp", [(0, 0), (1, 0), (0, 1), (1, 1)])
 def test_coarse_operator_is_RAP(restriction, interp):
     J = _problem_ops()
@@ -294,6 +323,8 @@ def test_two_level_cycle_closed_form(smoother, restriction):
     ((32, 32, 32), dict(cheb_degree=10, cheb_degree_coarse=1, cheb_lo=0.03, coarse_max=1200), 0.25),
     ((32, 32, 32), dict(cheb_degree=10, cheb_degree_coarse=0, cheb_lo=0.03, coarse_max=1200), 0.20),
     ((128, 128), dict(cheb_degree=10, cheb_degree_coarse=1, cheb_lo=0.03, coarse_max=1200, interp=1), 0.20),
+    ((128, 128), dict(cheb_degree=10, cheb_degree_coarse=1, cheb_lo=0.03, coarse_max=1200, interp=1,
+                      interp_pmax=4), 0.20),
     ((32, 32, 32), dict(cheb_degree=10, cheb_degree_coarse=1, cheb_lo=0.03, coarse_max=1200, interp=1), 0.20)])
 def test_poisson_stationary_factor(dims, kw, bound):
     """Stationary V(1,1) factor on the constant-coefficient Dirichlet
