@@ -215,6 +215,8 @@ def run_variants(prob, dev, cfg, iters64, ms64):
     out["fp64"] = r64
     out["fp32_hierarchy"] = r32
     out["bf16_offdiag_hierarchy"] = r16
+    rx, _ = _time_solves(prob, dev, dc.replace(cfg, interp_pp=1), 2)
+    out["fp64_ext_i_pressure"] = rx
     _progress("W2 storage variants done")
     # 128x128x64 (2.1M unknowns): FP64 and FP32 hierarchy, V-cycle throughput
     p3 = synth.make_problem("W3")
@@ -227,8 +229,10 @@ def run_variants(prob, dev, cfg, iters64, ms64):
     w64.update(_apply_numbers(p3, d3, cfg))
     w32.update(_apply_numbers(p3, d3, dc.replace(cfg, storage=1)))
     w16.update(_apply_numbers(p3, d3, dc.replace(cfg, storage=2)))
+    wx, _ = _time_solves(p3, d3, dc.replace(cfg, interp_pp=1), 2)
     _progress("W3 done")
     out["W3_128x128x64"] = {"fp64": w64, "fp32_hierarchy": w32, "bf16_offdiag_hierarchy": w16,
+                            "fp64_ext_i_pressure": wx,
                             "note": "FP32 error is against the FP64 GPU solution at the same rtol"}
     del d3, y64, y32, y16
     # learned post-smoother: train (operator-norm loss) on seeded W4-recipe fields
@@ -298,8 +302,11 @@ def run_variants(prob, dev, cfg, iters64, ms64):
     p5 = synth.make_problem("W5")
     nc = solver.NewtonConfig(steps=20)
     w5 = {}
+    ext = dict(interp_pp=1)   # extended+i interpolation (truncated to 4 weights) on the pressure hierarchy
     for key, c5, nt in (("fp64", cfg, None), ("fp32_hierarchy", dc.replace(cfg, storage=1), None),
-                        ("mixed_learned", dc.replace(cfg, storage=1), net)):
+                        ("mixed_learned", dc.replace(cfg, storage=1), net),
+                        ("fp32_ext_i_pressure", dc.replace(cfg, storage=1, **ext), None),
+                        ("mixed_learned_ext_i_pressure", dc.replace(cfg, storage=1, **ext), net)):
         _, st5 = solver.simulate(p5, c5, nc, net=nt)
         _progress(f"W5 {key}: {st5['solves']} solves, {st5['total_s']:.1f} s")
         st5.pop("newton_per_step", None)
@@ -311,7 +318,8 @@ def run_variants(prob, dev, cfg, iters64, ms64):
     p5a = synth.make_problem("W5", kappa=0.5)
     w5a = {}
     for key, c5, nt in (("fp64", cfg, None), ("fp32_hierarchy", dc.replace(cfg, storage=1), None),
-                        ("mixed_learned", dc.replace(cfg, storage=1), net)):
+                        ("mixed_learned", dc.replace(cfg, storage=1), net),
+                        ("mixed_learned_ext_i_pressure", dc.replace(cfg, storage=1, **ext), net)):
         _, st5 = solver.simulate(p5a, c5, nc, net=nt)
         _progress(f"W5 kappa 0.5 {key}: {st5['solves']} solves, {st5['total_s']:.1f} s")
         st5.pop("newton_per_step", None)

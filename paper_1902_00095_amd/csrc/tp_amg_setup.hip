@@ -504,10 +504,15 @@ k_ext_xy_fill(int32_t n, const int32_t* __restrict__ Srp, const int32_t* __restr
 }
 
 __global__ void __launch_bounds__(B)
-k_ext_count(int32_t n, const int32_t* __restrict__ cf, const int32_t* __restrict__ Trp, int32_t* __restrict__ cnt) {
+k_ext_count(int32_t n, const int32_t* __restrict__ cf, const int32_t* __restrict__ Trp, int pmax,
+            int32_t* __restrict__ cnt) {
     const int32_t i = blockIdx.x * B + threadIdx.x;
-    if (i < n) cnt[i] = cf[i] ? 1 : Trp[i + 1] - Trp[i];
+    if (i >= n) return;
+    const int32_t len = Trp[i + 1] - Trp[i];
+    cnt[i] = cf[i] ? 1 : (pmax > 0 && len > pmax ? pmax : len);
 }
+
+constexpr int EXT_PMAX = 16;  // largest accepted interp_pmax
 
 // index of x in the ascending v[0..len), or -1
 __device__ inline int32_t find_sorted(const int32_t* __restrict__ v, int32_t len, int32_t x) {
@@ -529,12 +534,14 @@ __device__ inline double opposite(double a, double akk) { return (akk > 0.0 ? a 
 //   w_ij  = -(a_ij + sum_k a_ik hat a_kj / den_k) / a~_ii,
 // summed in the row's column order, then k ascending over row k's order; a
 // strong F neighbour with den_k = 0 is lumped like a weak one.
+// Row i's weights are formed in w (scratch of the row's interpolatory-set
+// length), then written to P, truncated as described at k_ext_fill_w.
 __device__ void ext_row(int32_t i, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                         const double* __restrict__ val, const int32_t* __restrict__ Srp,
                         const int32_t* __restrict__ Sc, const int32_t* __restrict__ cf,
                         const int32_t* __restrict__ cmap, const int32_t* __restrict__ Trp,
                         const int32_t* __restrict__ Tc, const int32_t* __restrict__ Prp, int32_t* __restrict__ Pc,
-                        double* __restrict__ Pv) {
+                        double* __restrict__ Pv, double* __restrict__ wbuf, int pmax) {
     const int32_t p0 = Prp[i];
     if (cf[i]) {
         Pc[p0] = cmap[i];
@@ -546,11 +553,8 @@ __device__ void ext_row(int32_t i, const int32_t* __restrict__ rowptr, const int
     if (len == 0) return;
     const int32_t* Si = Sc + Srp[i];
     const int32_t slen = Srp[i + 1] - Srp[i];
-    double* w = Pv + p0;
-    for (int32_t t = 0; t < len; ++t) {
-        Pc[p0 + t] = cmap[list[t]];
-        w[t] = 0.0;
-    }
+    double* w = wbuf + Trp[i];
+    for (int32_t t = 0; t < len; ++t) w[t] = 0.0;
     double aii = 0.0;
     for (int32_t t = rowptr[i]; t < rowptr[i + 1]; ++t)
         if (col[t] == i) aii = val[t];
@@ -587,6 +591,37 @@ __device__ void ext_row(int32_t i, const int32_t* __restrict__ rowptr, const int
         }
     }
     for (int32_t t = 0; t < len; ++t) w[t] = -w[t] / at;
+    if (pmax > 0 && len > pmax) {
+        int32_t sel[EXT_PMAX];
+        for (int r = 0; r < pmax; ++r) {  // largest magnitude first, ties: smaller column
+            int32_t best = -1;
+            for (int32_t t = 0; t < len; ++t) {
+                bool taken = false;
+                for (int q = 0; q < r; ++q) taken |= sel[q] == t;
+                if (!taken && (best < 0 || fabs(w[t]) > fabs(w[best]))) best = t;
+            }
+            sel[r] = best;
+        }
+        for (int r = 1; r < pmax; ++r)  // ascending column order
+            for (int q = r; q > 0 && sel[q - 1] > sel[q]; --q) {
+                const int32_t x = sel[q];
+                sel[q] = sel[q - 1];
+                sel[q - 1] = x;
+            }
+        double all = 0.0, kept = 0.0;
+        for (int32_t t = 0; t < len; ++t) all += w[t];
+        for (int r = 0; r < pmax; ++r) kept += w[sel[r]];
+        const double f = kept != 0.0 ? all / kept : 1.0;
+        for (int r = 0; r < pmax; ++r) {
+            Pc[p0 + r] = cmap[list[sel[r]]];
+            Pv[p0 + r] = kept != 0.0 ? w[sel[r]] * f : w[sel[r]];
+        }
+    } else {
+        for (int32_t t = 0; t < len; ++t) {
+            Pc[p0 + t] = cmap[list[t]];
+            Pv[p0 + t] = w[t];
+        }
+    }
 }
 
 __global__ void __launch_bounds__(B)
@@ -594,9 +629,9 @@ k_ext_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restr
            const double* __restrict__ val, const int32_t* __restrict__ Srp, const int32_t* __restrict__ Sc,
            const int32_t* __restrict__ cf, const int32_t* __restrict__ cmap, const int32_t* __restrict__ Trp,
            const int32_t* __restrict__ Tc, const int32_t* __restrict__ Prp, int32_t* __restrict__ Pc,
-           double* __restrict__ Pv) {
+           double* __restrict__ Pv, double* __restrict__ wbuf, int pmax) {
     const int32_t i = blockIdx.x * B + threadIdx.x;
-    if (i < n) ext_row(i, rowptr, col, val, Srp, Sc, cf, cmap, Trp, Tc, Prp, Pc, Pv);
+    if (i < n) ext_row(i, rowptr, col, val, Srp, Sc, cf, cmap, Trp, Tc, Prp, Pc, Pv, wbuf, pmax);
 }
 
 // Wavefront-per-row form for levels of long rows.  Weight slot t of the row
@@ -604,7 +639,10 @@ k_ext_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restr
 // to the wavefront one by one in the order of the one-thread form, so every
 // slot, a~_ii and every den_k receive the same operations in the same order
 // (identical results).  Rows of more than EXT_SLOTS slots take the one-thread
-// form on lane 0.
+// form on lane 0.  Truncation (pmax > 0, longer rows): pmax rounds of a
+// wavefront arg-max over (|w|, then the smaller slot) select the kept slots,
+// the full and the kept sums run slot by slot in column order, and the kept
+// weights, scaled by their ratio, are written in column order.
 constexpr int EXT_NW = 4;
 constexpr int EXT_SLOTS = WR * EXT_NW;
 
@@ -613,7 +651,7 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
              const double* __restrict__ val, const int32_t* __restrict__ Srp, const int32_t* __restrict__ Sc,
              const int32_t* __restrict__ cf, const int32_t* __restrict__ cmap, const int32_t* __restrict__ Trp,
              const int32_t* __restrict__ Tc, const int32_t* __restrict__ Prp, int32_t* __restrict__ Pc,
-             double* __restrict__ Pv) {
+             double* __restrict__ Pv, double* __restrict__ wbuf, int pmax) {
     const int32_t i = blockIdx.x * WR_ROWS + threadIdx.x / WR;
     const int lane = threadIdx.x % WR;
     if (i >= n) return;
@@ -629,7 +667,7 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
     const int32_t len = Trp[i + 1] - Trp[i];
     if (len == 0) return;
     if (len > EXT_SLOTS) {
-        if (lane == 0) ext_row(i, rowptr, col, val, Srp, Sc, cf, cmap, Trp, Tc, Prp, Pc, Pv);
+        if (lane == 0) ext_row(i, rowptr, col, val, Srp, Sc, cf, cmap, Trp, Tc, Prp, Pc, Pv, wbuf, pmax);
         return;
     }
     const int32_t* Si = Sc + Srp[i];
@@ -727,12 +765,66 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
         }
     }
 #pragma unroll
-    for (int r = 0; r < EXT_NW; ++r) {
-        const int32_t t = r * WR + lane;
-        if (t < len) {
-            Pc[p0 + t] = cmap[list[t]];
-            Pv[p0 + t] = -w[r] / at;
+    for (int r = 0; r < EXT_NW; ++r) w[r] = -w[r] / at;
+    if (!(pmax > 0 && len > pmax)) {
+#pragma unroll
+        for (int r = 0; r < EXT_NW; ++r) {
+            const int32_t t = r * WR + lane;
+            if (t < len) {
+                Pc[p0 + t] = cmap[list[t]];
+                Pv[p0 + t] = w[r];
+            }
         }
+        return;
+    }
+    unsigned selm = 0;  // bit r: slot r * WR + lane kept
+    for (int round = 0; round < pmax; ++round) {
+        double bm = -1.0;
+        int32_t bt = INT32_MAX;
+#pragma unroll
+        for (int r = 0; r < EXT_NW; ++r) {
+            const int32_t t = r * WR + lane;
+            if (t < len && !((selm >> r) & 1u) && fabs(w[r]) > bm) {
+                bm = fabs(w[r]);
+                bt = t;
+            }
+        }
+#pragma unroll
+        for (int d = WR / 2; d > 0; d >>= 1) {
+            const double om = __shfl_xor(bm, d, WR);
+            const int32_t ot = __shfl_xor(bt, d, WR);
+            if (om > bm || (om == bm && ot < bt)) {
+                bm = om;
+                bt = ot;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < EXT_NW; ++r)
+            if (bt == r * WR + lane) selm |= 1u << r;
+    }
+    double all = 0.0, kept = 0.0;
+    int32_t below = 0;  // kept slots before this lane's, register by register
+#pragma unroll
+    for (int r = 0; r < EXT_NW; ++r) {
+        const int cnt = min(WR, (int)(len - r * WR));
+        for (int l = 0; l < cnt; ++l) {
+            const double v = __shfl(w[r], l, WR);
+            const bool k = (__shfl((int)selm, l, WR) >> r) & 1;
+            all += v;
+            if (k) kept += v;
+        }
+    }
+    const double f = kept != 0.0 ? all / kept : 1.0;
+#pragma unroll
+    for (int r = 0; r < EXT_NW; ++r) {
+        const bool k = (selm >> r) & 1u;
+        const uint64_t km = __ballot(k);
+        if (k) {
+            const int32_t pos = below + __popcll(km & ((1ull << lane) - 1ull));
+            Pc[p0 + pos] = cmap[list[r * WR + lane]];
+            Pv[p0 + pos] = kept != 0.0 ? w[r] * f : w[r];
+        }
+        below += __popcll(km);
     }
 }
 
@@ -1619,7 +1711,7 @@ static void direct_interp(const Csr& A, const Csr& S, const int32_t* cf, const i
 }
 
 static void ext_interp(const Csr& A, const Csr& S, const int32_t* cf, const int32_t* cmap, int32_t nc,
-                       Csr& P, int32_t* flag, hipStream_t s) {
+                       int pmax, Csr& P, int32_t* flag, hipStream_t s) {
     const int32_t n = A.n;
     Csr X, Y, T;
     X.n = Y.n = n;
@@ -1644,17 +1736,18 @@ static void ext_interp(const Csr& A, const Csr& S, const int32_t* cf, const int3
     P.n = n;
     P.m = nc;
     P.rowptr.alloc(n + 1, s);
-    if (n > 0) TP_LAUNCH(k_ext_count, cdiv(n, B), B, 0, s, n, cf, T.rowptr.p, P.rowptr.p);
+    if (n > 0) TP_LAUNCH(k_ext_count, cdiv(n, B), B, 0, s, n, cf, T.rowptr.p, pmax, P.rowptr.p);
     scan_exclusive(P.rowptr.p, P.rowptr.p, n, s);
     P.nnz = read_i32(P.rowptr.p + n, s);
     P.col.alloc(std::max(P.nnz, 1), s);
     P.val.alloc(std::max(P.nnz, 1), s);
+    DBuf<double> wbuf(std::max(T.nnz, 1), s);  // one weight per interpolatory-set entry
     if (n > 0 && long_rows(A.n, A.nnz))
         TP_LAUNCH(k_ext_fill_w, cdiv(n, WR_ROWS), B, 0, s, n, A.rowptr.p, A.col.p, A.val.p, S.rowptr.p, S.col.p, cf,
-                  cmap, T.rowptr.p, T.col.p, P.rowptr.p, P.col.p, P.val.p);
+                  cmap, T.rowptr.p, T.col.p, P.rowptr.p, P.col.p, P.val.p, wbuf.p, pmax);
     else if (n > 0)
         TP_LAUNCH(k_ext_fill, cdiv(n, B), B, 0, s, n, A.rowptr.p, A.col.p, A.val.p, S.rowptr.p, S.col.p, cf, cmap,
-                  T.rowptr.p, T.col.p, P.rowptr.p, P.col.p, P.val.p);
+                  T.rowptr.p, T.col.p, P.rowptr.p, P.col.p, P.val.p, wbuf.p, pmax);
 }
 
 static void make_f32(DBuf<float>& dst, const DBuf<double>& src, size_t n, hipStream_t s) {
@@ -1861,13 +1954,13 @@ static void setup(tp_amg* h, int32_t n, const int32_t* rowptr, const int32_t* co
             L.cf.release();
             break;
         }
-        if (prm.interp == 1) ext_interp(A, S, L.cf.p, cmap.p, nc, L.P, sg_flag.p, s);
+        if (prm.interp == 1) ext_interp(A, S, L.cf.p, cmap.p, nc, prm.interp_pmax, L.P, sg_flag.p, s);
         else direct_interp(A, S, L.cf.p, cmap.p, nc, L.P, s);
         if (prm.restriction == 1) {
             Csr At, St, Q;
             transpose(A.rowptr.p, A.col.p, A.val.p, A.n, A.n, A.nnz, true, At, s);
             strength(At, prm.theta, St, s);
-            if (prm.interp == 1) ext_interp(At, St, L.cf.p, cmap.p, nc, Q, sg_flag.p, s);
+            if (prm.interp == 1) ext_interp(At, St, L.cf.p, cmap.p, nc, prm.interp_pmax, Q, sg_flag.p, s);
             else direct_interp(At, St, L.cf.p, cmap.p, nc, Q, s);
             transpose(Q.rowptr.p, Q.col.p, Q.val.p, Q.n, nc, Q.nnz, true, L.R, s);
         } else {
@@ -2020,6 +2113,8 @@ int amg_setup(int32_t n, const int32_t* rowptr, const int32_t* col, const double
         TP_CHECK_ARG(p.restriction == 0 || p.restriction == 1, "amg_setup: restriction must be 0 or 1");
         TP_CHECK_ARG(p.storage >= 0 && p.storage <= 2, "amg_setup: storage must be 0, 1 or 2");
         TP_CHECK_ARG(p.interp == 0 || p.interp == 1, "amg_setup: interp must be 0 or 1");
+        TP_CHECK_ARG(p.interp_pmax >= 0 && p.interp_pmax <= tp::EXT_PMAX, "amg_setup: interp_pmax must be in [0,%d]",
+                     tp::EXT_PMAX);
         hipStream_t s = (hipStream_t)stream;
         tp_amg* h = new tp_amg();
         h->prm = p;

@@ -89,17 +89,17 @@ def _oracle_J_on_device(p):
     return Jo, tps.Jacobian.from_host(Jo.n, Jo.rowptr, Jo.col, Jo.pp, Jo.pT, Jo.Tp, Jo.TT, Jo.S)
 
 
-@pytest.mark.parametrize("interp", [0, 1])
+@pytest.mark.parametrize("interp,pmax", [(0, 4), (1, 0), (1, 4)])
 @pytest.mark.parametrize("case", ["W1", "W2s", "W4s"])
 @pytest.mark.parametrize("which,restr", [("pp", 0), ("S", 1), ("S", 0)])
-def test_amg_setup_bit_exact_on_identical_input(case, which, restr, interp):
+def test_amg_setup_bit_exact_on_identical_input(case, which, restr, interp, pmax):
     """Same matrix in: identical C/F splits, patterns, and values (direct and
-    extended+i interpolation)."""
-    say("amg setup", case, which, restr, interp)
+    extended+i interpolation, the latter with and without truncation)."""
+    say("amg setup", case, which, restr, interp, pmax)
     p = CASES[case]()
     Jo, Jd = _oracle_J_on_device(p)
     val = getattr(Jo, which)
-    prm = tps.AmgParams(restriction=restr, coarse_max=SMALL, interp=interp)
+    prm = tps.AmgParams(restriction=restr, coarse_max=SMALL, interp=interp, interp_pmax=pmax)
     ho = o_amg(Jo.n, Jo.rowptr, Jo.col, val, prm)
     hg = tps.AMG(Jd.rowptr, Jd.col, getattr(Jd, which), prm)
     assert hg.nlev == ho.nlev
