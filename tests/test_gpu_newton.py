@@ -23,19 +23,20 @@ def _init():
     yield
 
 
-@pytest.mark.parametrize("storage,reuse,method", [(0, False, "block"), (1, False, "block"), (0, True, "block"),
-                                                  (1, True, "block"), (0, False, "cpr"), (0, True, "cpr")])
-def test_newton_time_steps_match_oracle(storage, reuse, method):
+@pytest.mark.parametrize("storage,reuse,method,interp_pp", [
+    (0, False, "block", None), (1, False, "block", None), (0, True, "block", None), (1, True, "block", None),
+    (0, False, "cpr", None), (0, True, "cpr", None), (1, False, "block", 1)])
+def test_newton_time_steps_match_oracle(storage, reuse, method, interp_pp):
     """With hierarchy reuse the later Newton iterations of a step run on
     hierarchies refreshed on the finest level only; the Newton root, and so
     the states, must not change.  CPR keeps one ILU(0) handle for the run and
     refactorises it for every Jacobian."""
-    say("newton", storage, reuse, method)
+    say("newton", storage, reuse, method, interp_pp)
     p = synth.make_problem("W5", grid=synth.Grid(16, 16, 8, 1.0, 1.0, 1.0))
     steps = 2
     xo, its_o, _ = oracle.newton_simulate(p, steps)
     x, st = solver.simulate(p, solver.SolveConfig(storage=storage, amg=tps.AmgParams(coarse_max=200),
-                                                  method=method),
+                                                  method=method, interp_pp=interp_pp),
                             solver.NewtonConfig(steps=steps, reuse=reuse))
     if reuse:
         assert st["hierarchy_builds"] == steps < st["solves"]
