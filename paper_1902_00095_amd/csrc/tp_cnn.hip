@@ -369,8 +369,7 @@ k_cnn_wgrad(tp_grid g, const float* __restrict__ f, const float* __restrict__ h,
             const bf16x8 dhh = *(const bf16x8*)&s_dh[0][ka], dhl = *(const bf16x8*)&s_dh[1][ka];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int job = wv + 4 * i;
-                if (i < 3 || wv < 2) {  // jobs 0..13: [W1 | b1]; 14, 15: W2
+                if (i < 3 || wv < 2) {  // job wv + 4 i: 0..13 [W1 | b1]; 14, 15 W2
                     bf16x8 b;
 #pragma unroll
                     for (int j = 0; j < 8; ++j)
@@ -568,7 +567,6 @@ template void cnn_features_into<float>(tp_cnn_attach*, const float*, float*, hip
 
 // gradient of the loss from c->dout (set by the caller) and c->h of the last forward
 void cnn_backward_from_dout(tp_cnn* c, const tp_grid& g, const float* feat, hipStream_t s) {
-    const int32_t n = g.nx * g.ny * g.nz;
     const int64_t tiles = (int64_t)((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + TZ - 1) / TZ);
     const int nwg = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, GW_MAX));
     TP_LAUNCH(k_cnn_wgrad, nwg, MF_T, 0, s, g, feat, c->h.p, c->dout.p, c->wbf.p + CNN_OFF_W2, c->gpart.p);

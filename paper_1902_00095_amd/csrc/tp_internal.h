@@ -80,6 +80,7 @@ struct Arena {
 };
 bool arena_active();
 void release_chunk_cache();  // frees every cached arena chunk
+void release_ws_cache();     // frees every idle FGMRES workspace
 struct ArenaScope {
     Arena* prev;
     explicit ArenaScope(Arena* a);

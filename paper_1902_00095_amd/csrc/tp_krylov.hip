@@ -18,6 +18,7 @@
 #include "tp_amg.h"
 
 #include <cmath>
+#include <mutex>
 
 namespace tp {
 void cast_d2s(int32_t n, const double* a, void* b, size_t es, hipStream_t s);
@@ -515,14 +516,13 @@ struct Gmres {
     int nb;
     DBuf<double> V, Z, w, b, x, r, H, cs, sn, g, y, h1, h2, nrm2, part, sc;
     DBuf<unsigned int> ticket;
-    HostMail& mail;
     hipEvent_t ev[2] = {nullptr, nullptr};  // one per mailbox slot (pipelined iterations)
     static HostMail& host_mail() {
         // one pinned mailbox per host thread, kept for the process lifetime
         static thread_local HostMail* box = new HostMail();
         return *box;
     }
-    Gmres(int32_t n_, int m_, hipStream_t s) : n(n_), N(2 * (int64_t)n_), m(m_), mail(host_mail()) {
+    Gmres(int32_t n_, int m_, hipStream_t s) : n(n_), N(2 * (int64_t)n_), m(m_) {
         nb = (int)std::min<int64_t>(512, std::max<int64_t>(1, (N + 2 * CG_T - 1) / (2 * CG_T)));
         V.alloc((size_t)(m + 1) * N, s);
         Z.alloc((size_t)m * N, s);
@@ -548,7 +548,57 @@ struct Gmres {
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
     }
+    // after the device work on the buffers has finished: free them on the
+    // null stream later (the stream they were allocated on may be gone)
+    void detach_streams() {
+        for (DBuf<double>* q : {&V, &Z, &w, &b, &x, &r, &H, &cs, &sn, &g, &y, &h1, &h2, &nrm2, &part, &sc}) q->s = nullptr;
+        ticket.s = nullptr;
+    }
 };
+
+// Idle workspaces, kept per device for the next preconditioner of the same
+// size: a Newton loop creates a preconditioner per iteration, and allocating
+// the Krylov basis anew each time (4 GB at 8.4M unknowns) is slow.  A
+// workspace enters the list only after its handle's streams have drained.
+constexpr size_t WS_KEEP = 2;  // per device
+static std::mutex g_ws_mu;
+static std::vector<std::pair<int, Gmres*>> g_ws;
+
+static Gmres* ws_take(int32_t n, int m) {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    const int dev = current_device();
+    for (size_t i = 0; i < g_ws.size(); ++i)
+        if (g_ws[i].first == dev && g_ws[i].second->n == n && g_ws[i].second->m == m) {
+            Gmres* g = g_ws[i].second;
+            g_ws.erase(g_ws.begin() + i);
+            return g;
+        }
+    return nullptr;
+}
+
+void ws_give(Gmres* g) {
+    if (!g) return;
+    g->detach_streams();
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    const int dev = current_device();
+    size_t held = 0;
+    for (auto& e : g_ws) held += e.first == dev;
+    if (held >= WS_KEEP) {  // drop the oldest of this device
+        for (size_t i = 0; i < g_ws.size(); ++i)
+            if (g_ws[i].first == dev) {
+                delete g_ws[i].second;
+                g_ws.erase(g_ws.begin() + i);
+                break;
+            }
+    }
+    g_ws.emplace_back(dev, g);
+}
+
+void release_ws_cache() {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    for (auto& e : g_ws) delete e.second;
+    g_ws.clear();
+}
 
 static void dots(Gmres& G, int k, const double* h, double* w, int mode, double* out, hipStream_t s,
                  int arn = 0, int j = 0) {
@@ -576,7 +626,7 @@ static double read_d(const double* dptr, HostMail& mail, hipStream_t s) {
     return *mail.as<double>();
 }
 
-void gmres_free(Gmres* g) { delete g; }
+void gmres_free(Gmres* g) { ws_give(g); }
 
 static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* x_il,
                   const tp_krylov_params& kp, tp_krylov_stats* st, double* history, hipStream_t s) {
@@ -587,19 +637,21 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
     if (!M->ws || M->ws->n != n || M->ws->m != m) {
         if (M->ws) {
             TP_HIP(hipDeviceSynchronize());
-            delete M->ws;
+            ws_give(M->ws);
             M->ws = nullptr;
         }
-        M->ws = new Gmres(n, m, s);
+        M->ws = ws_take(n, m);
+        if (!M->ws) M->ws = new Gmres(n, m, s);
     }
     Gmres& G = *M->ws;
+    HostMail& mail = Gmres::host_mail();  // the calling thread's pinned mailbox
     const int gn = cdiv(n, KB);
     const int gN = cdiv(G.N, KB);
     const int gJ = cdiv((int64_t)n * JG, KB);
     TP_LAUNCH(k_deinterleave, gn, KB, 0, s, n, b_il, G.b.p);
     TP_LAUNCH(k_deinterleave, gn, KB, 0, s, n, x_il, G.x.p);
     dots(G, 0, nullptr, G.b.p, 2, G.nrm2.p, s);
-    const double bnorm = std::sqrt(read_d(G.nrm2.p, G.mail, s));
+    const double bnorm = std::sqrt(read_d(G.nrm2.p, mail, s));
     int it = 0, restarts = 0;
     double rel = 0.0, est = 0.0;
     std::vector<double> ests;
@@ -615,7 +667,7 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
         TP_LAUNCH(k_block_spmv, gJ, KB, 0, s, n, J.rowptr, J.col, J.pp, J.pT, J.Tp, J.TT, G.x.p, G.b.p, G.r.p,
                   (double*)nullptr);
         dots(G, 0, nullptr, G.r.p, 2, G.nrm2.p, s);
-        rel = std::sqrt(read_d(G.nrm2.p, G.mail, s)) / bnorm;
+        rel = std::sqrt(read_d(G.nrm2.p, mail, s)) / bnorm;
         est = rel;
         if (history) history[0] = rel;
         while (rel > kp.rtol && it < kp.maxit) {
@@ -648,7 +700,7 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
                 TP_LAUNCH(k_scale_div, gN, KB, 0, s, G.N, G.w.p, G.sc.p, G.V.p + (int64_t)(j + 1) * G.N,
                           use_graph ? M->rin.p : nullptr, cnn_on ? (const int32_t*)M->S->cnn->bad.p : nullptr,
                           G.sc.p + 2);
-                TP_HIP(hipMemcpyAsync(G.mail.as<double>() + 4 * slot, G.sc.p, 3 * sizeof(double),
+                TP_HIP(hipMemcpyAsync(mail.as<double>() + 4 * slot, G.sc.p, 3 * sizeof(double),
                                       hipMemcpyDeviceToHost, s));
                 TP_HIP(hipEventRecord(G.ev[slot], s));
             };
@@ -672,9 +724,9 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
                 const bool ahead = pipelined && !likely_last && j + 1 < m && it + 1 < kp.maxit;
                 if (ahead) enqueue(j + 1, slot ^ 1);
                 TP_HIP(hipEventSynchronize(G.ev[slot]));
-                const double hn = G.mail.as<double>()[4 * slot];
-                est = G.mail.as<double>()[4 * slot + 1] / bnorm;
-                const bool bad = G.mail.as<double>()[4 * slot + 2] != 0.0;
+                const double hn = mail.as<double>()[4 * slot];
+                est = mail.as<double>()[4 * slot + 1] / bnorm;
+                const bool bad = mail.as<double>()[4 * slot + 2] != 0.0;
                 ++it;
                 k = j + 1;
                 if (history) history[it] = est;
@@ -698,7 +750,7 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
             TP_LAUNCH(k_block_spmv, gJ, KB, 0, s, n, J.rowptr, J.col, J.pp, J.pT, J.Tp, J.TT, G.x.p, G.b.p,
                       G.r.p, (double*)nullptr);
             dots(G, 0, nullptr, G.r.p, 2, G.nrm2.p, s);
-            rel = std::sqrt(read_d(G.nrm2.p, G.mail, s)) / bnorm;
+            rel = std::sqrt(read_d(G.nrm2.p, mail, s)) / bnorm;
             ++restarts;
         }
     }

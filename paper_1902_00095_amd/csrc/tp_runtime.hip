@@ -42,7 +42,7 @@ static void* raw_alloc(size_t bytes, hipStream_t s);
 // bytes): one hierarchy per operator is built and dropped every Newton step,
 // and returning its chunks to the device allocator is slow for the large ones.
 // A chunk enters the cache only after the arena's stream has drained.
-constexpr size_t CACHE_MAX = size_t(4) << 30;
+constexpr size_t CACHE_MAX = size_t(32) << 30;  // of 288 GB
 static std::mutex g_cache_mu;
 static std::vector<ArenaChunk> g_cache;
 static size_t g_cache_bytes = 0;
@@ -332,7 +332,10 @@ int tp_init(const tp_allocator* alloc, int device) {
         TP_HIP(hipGetDeviceCount(&count));
         TP_CHECK_ARG(device >= 0 && device < count, "device %d out of range (%d devices)", device, count);
         // cached arena chunks belong to the previous device and allocator
-        if (tp::g_device >= 0) tp::release_chunk_cache();
+        if (tp::g_device >= 0) {
+            tp::release_chunk_cache();
+            tp::release_ws_cache();
+        }
         TP_HIP(hipSetDevice(device));
         tp::g_device = device;
         // keep freed blocks in the device's stream-ordered pool instead of
