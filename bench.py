@@ -301,26 +301,30 @@ def run_variants(prob, dev, cfg, iters64, ms64):
     # plain FP64 against the FP32 hierarchy and the FP32 hierarchy with the learned smoother
     p5 = synth.make_problem("W5")
     nc = solver.NewtonConfig(steps=20)
+    ncr = solver.NewtonConfig(steps=20, reuse=True)   # hierarchies built once per time step
     w5 = {}
     ext = dict(interp_pp=1)   # extended+i interpolation (truncated to 4 weights) on the pressure hierarchy
-    for key, c5, nt in (("fp64", cfg, None), ("fp32_hierarchy", dc.replace(cfg, storage=1), None),
-                        ("mixed_learned", dc.replace(cfg, storage=1), net),
-                        ("fp32_ext_i_pressure", dc.replace(cfg, storage=1, **ext), None),
-                        ("mixed_learned_ext_i_pressure", dc.replace(cfg, storage=1, **ext), net)):
-        _, st5 = solver.simulate(p5, c5, nc, net=nt)
+    for key, c5, nt, ncx in (("fp64", cfg, None, nc), ("fp32_hierarchy", dc.replace(cfg, storage=1), None, nc),
+                             ("mixed_learned", dc.replace(cfg, storage=1), net, nc),
+                             ("mixed_learned_ext_i_pressure", dc.replace(cfg, storage=1, **ext), net, nc),
+                             ("fp32_ext_i_pressure_reuse", dc.replace(cfg, storage=1, **ext), None, ncr),
+                             ("mixed_learned_ext_i_pressure_reuse", dc.replace(cfg, storage=1, **ext), net, ncr)):
+        _, st5 = solver.simulate(p5, c5, ncx, net=nt)
         _progress(f"W5 {key}: {st5['solves']} solves, {st5['total_s']:.1f} s")
         st5.pop("newton_per_step", None)
         w5[key] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st5.items()}
     out["W5_256x256x64_20_steps"] = dict(w5, note="thermal conductivity 20 W/m/K (conduction-dominated); "
-                                         "per Newton iteration: assembly, both AMG setups, FGMRES to rtol; "
-                                         "Newton stops at |G|/|G0| or |dx|/|x| <= 1e-8 or after 4 iterations")
+                                         "per Newton iteration: assembly, both AMG setups (with _reuse: at a "
+                                         "step's first iteration only, the finest level refreshed at the later "
+                                         "ones), FGMRES to rtol; Newton stops at |G|/|G0| or |dx|/|x| <= 1e-8 "
+                                         "or after 4 iterations")
     # the same run advection-dominated (thermal conductivity 0.5 W/m/K)
     p5a = synth.make_problem("W5", kappa=0.5)
     w5a = {}
-    for key, c5, nt in (("fp64", cfg, None), ("fp32_hierarchy", dc.replace(cfg, storage=1), None),
-                        ("mixed_learned", dc.replace(cfg, storage=1), net),
-                        ("mixed_learned_ext_i_pressure", dc.replace(cfg, storage=1, **ext), net)):
-        _, st5 = solver.simulate(p5a, c5, nc, net=nt)
+    for key, c5, nt, ncx in (("fp64", cfg, None, nc), ("fp32_hierarchy", dc.replace(cfg, storage=1), None, nc),
+                             ("mixed_learned", dc.replace(cfg, storage=1), net, nc),
+                             ("mixed_learned_ext_i_pressure_reuse", dc.replace(cfg, storage=1, **ext), net, ncr)):
+        _, st5 = solver.simulate(p5a, c5, ncx, net=nt)
         _progress(f"W5 kappa 0.5 {key}: {st5['solves']} solves, {st5['total_s']:.1f} s")
         st5.pop("newton_per_step", None)
         w5a[key] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st5.items()}

@@ -25,7 +25,7 @@ def _init():
 
 @pytest.mark.parametrize("storage,reuse,method,interp_pp", [
     (0, False, "block", None), (1, False, "block", None), (0, True, "block", None), (1, True, "block", None),
-    (0, False, "cpr", None), (0, True, "cpr", None), (1, False, "block", 1)])
+    (0, False, "cpr", None), (0, True, "cpr", None), (1, False, "block", 1), (1, True, "block", 1)])
 def test_newton_time_steps_match_oracle(storage, reuse, method, interp_pp):
     """With hierarchy reuse the later Newton iterations of a step run on
     hierarchies refreshed on the finest level only; the Newton root, and so
