@@ -307,6 +307,7 @@ def run_variants(prob, dev, cfg, iters64, ms64):
     for key, c5, nt, ncx in (("fp64", cfg, None, nc), ("fp32_hierarchy", dc.replace(cfg, storage=1), None, nc),
                              ("mixed_learned", dc.replace(cfg, storage=1), net, nc),
                              ("mixed_learned_ext_i_pressure", dc.replace(cfg, storage=1, **ext), net, nc),
+                             ("fp64_ext_i_pressure_reuse", dc.replace(cfg, **ext), None, ncr),
                              ("fp32_ext_i_pressure_reuse", dc.replace(cfg, storage=1, **ext), None, ncr),
                              ("mixed_learned_ext_i_pressure_reuse", dc.replace(cfg, storage=1, **ext), net, ncr)):
         _, st5 = solver.simulate(p5, c5, ncx, net=nt)
@@ -323,6 +324,7 @@ def run_variants(prob, dev, cfg, iters64, ms64):
     w5a = {}
     for key, c5, nt, ncx in (("fp64", cfg, None, nc), ("fp32_hierarchy", dc.replace(cfg, storage=1), None, nc),
                              ("mixed_learned", dc.replace(cfg, storage=1), net, nc),
+                             ("fp64_ext_i_pressure_reuse", dc.replace(cfg, **ext), None, ncr),
                              ("mixed_learned_ext_i_pressure_reuse", dc.replace(cfg, storage=1, **ext), net, ncr)):
         _, st5 = solver.simulate(p5a, c5, ncx, net=nt)
         _progress(f"W5 kappa 0.5 {key}: {st5['solves']} solves, {st5['total_s']:.1f} s")
