@@ -232,6 +232,34 @@ def make_problem(name: str, seed: int | None = None, props: Props | None = None,
         x_prev[1::2] = props.T0
         return Problem(name, grid, props, K, phi, kap, corner_wells(grid, 450.0, rate=1.0e-6),
                        DAY, x_prev, x_prev.copy(), seed)
+    if name in ("CaseII", "CaseIII"):
+        # the problem-size study's well cases (Section 4): N x N cells of a
+        # 20 m x 20 m x 1 m square, k = 3e-13 m^2, porosity 0.2, uniform start
+        # at 288.706 K (Case III: 320 K), 3 injectors (422.039 K) and 3
+        # producers at constant rates 5e-8 m^3/s (Case III: 1e-6), 10-day steps;
+        # the paper does not place the wells: injectors at x = 2.5 m and
+        # producers at x = 17.5 m, both at y = 2.5, 10 and 17.5 m
+        seed = 0 if seed is None else seed
+        N = 80
+        grid = grid or Grid(N, N, 1, 20.0 / N, 20.0 / N, 1.0)
+        n = grid.n
+        K = np.full(n, 3.0e-13)
+        phi = np.full(n, 0.2)
+        kap = np.full(n, 2.0 if kappa is None else kappa)
+        hot = name == "CaseIII"
+        T_init = 320.0 if hot else 288.706
+        rate = 1.0e-6 if hot else 5.0e-8
+
+        def cell(x, y):
+            ix = min(grid.nx - 1, int(x / grid.dx))
+            iy = min(grid.ny - 1, int(y / grid.dy))
+            return ix + grid.nx * iy
+        wells = [Well(cell(2.5, y), 0, rate, 422.039) for y in (2.5, 10.0, 17.5)]
+        wells += [Well(cell(17.5, y), 1, rate, 422.039) for y in (2.5, 10.0, 17.5)]
+        x_prev = np.empty(2 * n)
+        x_prev[0::2] = props.p0
+        x_prev[1::2] = T_init
+        return Problem(name, grid, props, K, phi, kap, wells, 10.0 * DAY, x_prev, x_prev.copy(), seed)
     raise ValueError(f"unknown workload {name!r}")
 
 

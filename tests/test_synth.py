@@ -47,3 +47,15 @@ def test_refinement_recipe_uniform_start_and_corner_wells():
         assert np.array_equal(p.x_prev, p.x_k)
         assert np.all(p.x_k[0::2] == p.props.p0) and np.all(p.x_k[1::2] == p.props.T0)
         assert [(w.cell, w.kind) for w in p.wells] == [(0, 0), (N * N - 1, 1)]
+
+
+def test_paper_well_cases():
+    for name, T0, q in (("CaseII", 288.706, 5e-8), ("CaseIII", 320.0, 1e-6)):
+        for N in (20, 80):
+            g = synth.Grid(N, N, 1, 20.0 / N, 20.0 / N, 1.0)
+            p = synth.make_problem(name, grid=g)
+            assert np.all(p.K == 3e-13) and np.all(p.x_k[1::2] == T0) and p.dt == 10 * 86400.0
+            assert [w.kind for w in p.wells] == [0, 0, 0, 1, 1, 1]
+            assert all(w.rate == q for w in p.wells) and all(w.T_inj == 422.039 for w in p.wells)
+            cells = {w.cell for w in p.wells}
+            assert len(cells) == 6 and all(0 <= c < N * N for c in cells)
