@@ -293,15 +293,16 @@ def run_variants(prob, dev, cfg, iters64, ms64):
             row[key] = {"linear_per_newton": round(sr["linear_per_newton"], 2), "newton_iters": sr["newton_iters"],
                         "ms_per_solve": round(sr["ms_per_solve"], 3), "unconverged_steps": sr["unconverged_steps"]}
         ref[f"{N}x{N}"] = row
-    # the paper's own well cases of the problem-size study (Section 4, tables isoW and
+    # the paper's own cases of the problem-size study (Section 4, tables isoH, isoW and
     # isoHighW), on this build's physics: linear iterations per Newton iteration over two
     # 10-day steps, with the published figures beside them (PETSc/BoomerAMG, serial CPU)
-    paper_tab = {"CaseII": {"block": [2.43, 2.43, 2.86, 3.28, 3.71], "cpr": [3.71, 5.71, 9.86, 19.4, 37.4],
+    paper_tab = {"CaseI": {"block": [2.57, 3.23, 2.86, 3.44, 3.71], "cpr": [3.4, 5.38, 9.09, 16.3, 30.7]},
+                 "CaseII": {"block": [2.43, 2.43, 2.86, 3.28, 3.71], "cpr": [3.71, 5.71, 9.86, 19.4, 37.4],
                             "block_S_ATT": [4.57, 5.0, 5.57, 6.29, 6.57],
                             "block_S_diag": [4.14, 4.43, 5.29, 5.86, 6.43]},
                  "CaseIII": {"block": [3.67, 4.38, 4.7, 5.10, 5.52], "cpr": [4.71, 7.31, 13.1, 24.7, 50.6]}}
     cases = {}
-    for case in ("CaseII", "CaseIII"):
+    for case in ("CaseI", "CaseII", "CaseIII"):
         rows = {}
         for N in (20, 40, 80, 160, 320):
             g = synth.Grid(N, N, 1, 20.0 / N, 20.0 / N, 1.0)
@@ -318,7 +319,8 @@ def run_variants(prob, dev, cfg, iters64, ms64):
             rows[f"{N}x{N}"] = row
         cases[case] = {"this_build": rows, "paper": paper_tab[case]}
     out["paper_cases_2d"] = dict(cases, note="linear iterations per Newton iteration, 2 steps of 10 days; "
-                                 "paper: Section 4 tables isoW (Case II) and isoHighW (Case III), N = 20..320")
+                                 "paper: Section 4 tables isoH (Case I), isoW (Case II) and isoHighW (Case III), "
+                                 "N = 20..320")
     _progress("paper cases done")
     out["refinement_2d"] = dict(ref, note="R2 recipe: N x N cells of a 20 m x 20 m x 1 m slab, k = 1e-13 m^2, "
                                 "injector 450 K and producer 1e-6 m^3/s at opposite corners, 2 steps of 1 day "

@@ -72,7 +72,10 @@ typedef struct { double rho0, p0, T0, c_p, c_T, mu0, mu_B, cv, rho_r, c_r, g; } 
 
 /* Constant-rate point well (eq. f, eq. fT): kind 0 injector (mass
  * rate*rho(p, T_inj), enthalpy c_v T_inj), kind 1 producer (mass
- * rate*rho(p, T), enthalpy c_v T). rate >= 0 in m^3/s. */
+ * rate*rho(p, T), enthalpy c_v T). rate >= 0 in m^3/s.  Kind 2 is a heater
+ * (Section 2.1, source terms): energy source U (T_heater - T) with
+ * rate = U >= 0 in W/K and T_inj = T_heater; it adds U to A_TT and to the
+ * Schur approximation (eq. Se). */
 typedef struct { int32_t cell; int32_t kind; double rate, T_inj; } tp_well;
 #define TP_MAX_WELLS 32
 

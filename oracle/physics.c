@@ -143,10 +143,13 @@ void or_residual_c(const or_grid* g, const or_props* pr, const double* K,
                 double complex Qm = w[k].rate * rho_c(pr, p, w[k].T_inj);
                 Rm -= Qm;
                 Re -= pr->cv * w[k].T_inj * Qm;
-            } else {
+            } else if (w[k].kind == 1) {
                 double complex Qm = -w[k].rate * r;
                 Rm -= Qm;
                 Re -= pr->cv * T * Qm;
+            } else {
+                /* heater (Section 2.1, source terms): f_T = U (T_heater - T) */
+                Re -= w[k].rate * (w[k].T_inj - T);
             }
         }
         G[2 * i] = Rm;
@@ -285,13 +288,17 @@ void or_jacobian(const or_grid* g, const or_props* pr, const double* K,
                 double Qm = q * rho_r(pr, p, w[k].T_inj);
                 App[kd] -= pr->c_p * Qm;
                 ATp[kd] -= cv * w[k].T_inj * pr->c_p * Qm;
-            } else {
+            } else if (w[k].kind == 1) {
                 /* Q^m = -q rho_i, Q^e = -c_v T_i q rho_i */
                 App[kd] += q * pr->c_p * r;
                 ApT[kd] += q * pr->c_T * r;
                 ATp[kd] += cv * T * q * pr->c_p * r;
                 ATT[kd] += cv * q * (r + T * pr->c_T * r);
                 S[kd] += cv * q * r;
+            } else {
+                /* heater: d(-U (T_h - T))/dT = U, in A_TT and in eq. Se (U D_heaters) */
+                ATT[kd] += q;
+                S[kd] += q;
             }
         }
     }

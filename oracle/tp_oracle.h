@@ -23,6 +23,8 @@ extern "C" {
 
 typedef struct { int32_t nx, ny, nz; double dx, dy, dz; } or_grid;
 typedef struct { double rho0, p0, T0, c_p, c_T, mu0, mu_B, cv, rho_r, c_r, g; } or_props;
+/* kind 0 injector, 1 producer (rate in m^3/s); kind 2 heater: rate is the
+ * heat-transfer coefficient U (W/K) and T_inj the heater temperature */
 typedef struct { int32_t cell, kind; double rate, T_inj; } or_well;
 
 /* ---- Section 2.2: TPFA discretisation ---------------------------------- */

@@ -171,7 +171,7 @@ k_assemble(tp_grid g, tp_props pr, WellSet ws, double dt, const double* __restri
             Re -= cv * ws.w[w].T_inj * Qm;
             dpp -= pr.c_p * Qm;
             dTp -= cv * ws.w[w].T_inj * pr.c_p * Qm;
-        } else {
+        } else if (ws.w[w].kind == 1) {
             const double Qm = -q * r;
             Rm -= Qm;
             Re -= cv * T * Qm;
@@ -180,6 +180,10 @@ k_assemble(tp_grid g, tp_props pr, WellSet ws, double dt, const double* __restri
             dTp += cv * T * q * pr.c_p * r;
             dTT += cv * q * (r + T * pr.c_T * r);
             dS += cv * q * r;
+        } else {  // heater: energy source U (T_heater - T)
+            Re -= q * (ws.w[w].T_inj - T);
+            dTT += q;
+            dS += q;
         }
     }
     App[kd] = dpp;
@@ -236,7 +240,7 @@ int assemble_tpfa(const tp_grid* grid, const tp_props* props, const double* K,
         ws.n = nwells;
         for (int32_t w = 0; w < nwells; ++w) {
             TP_CHECK_ARG(wells[w].cell >= 0 && wells[w].cell < n, "well %d cell %d out of range", w, wells[w].cell);
-            TP_CHECK_ARG(wells[w].kind == 0 || wells[w].kind == 1, "well %d kind must be 0 or 1", w);
+            TP_CHECK_ARG(wells[w].kind >= 0 && wells[w].kind <= 2, "well %d kind must be 0, 1 or 2", w);
             TP_CHECK_ARG(wells[w].rate >= 0.0, "well %d rate must be >= 0", w);
             ws.w[w] = wells[w];
         }

@@ -70,9 +70,9 @@ class Props:
 @dataclasses.dataclass(frozen=True)
 class Well:
     cell: int
-    kind: int          # 0 injector, 1 producer
-    rate: float        # m^3/s, >= 0
-    T_inj: float       # K (used by injectors)
+    kind: int          # 0 injector, 1 producer, 2 heater
+    rate: float        # m^3/s, >= 0 (heater: the heat-transfer coefficient U in W/K)
+    T_inj: float       # K (injectors; heater: its temperature)
 
 
 @dataclasses.dataclass
@@ -232,6 +232,25 @@ def make_problem(name: str, seed: int | None = None, props: Props | None = None,
         x_prev[1::2] = props.T0
         return Problem(name, grid, props, K, phi, kap, corner_wells(grid, 450.0, rate=1.0e-6),
                        DAY, x_prev, x_prev.copy(), seed)
+    if name == "CaseI":
+        # the problem-size study's heater case (Section 4): as Case II with six
+        # heaters (coefficient 5.44409e-6 W/K, 422.039 K) instead of wells; the
+        # paper does not place them: x = 5, 10, 15 m at y = 5 and 15 m
+        seed = 0 if seed is None else seed
+        N = 80
+        grid = grid or Grid(N, N, 1, 20.0 / N, 20.0 / N, 1.0)
+        n = grid.n
+        K = np.full(n, 3.0e-13)
+        phi = np.full(n, 0.2)
+        kap = np.full(n, 2.0 if kappa is None else kappa)
+
+        def cell(x, y):
+            return min(grid.nx - 1, int(x / grid.dx)) + grid.nx * min(grid.ny - 1, int(y / grid.dy))
+        heaters = [Well(cell(x, y), 2, 5.44409e-6, 422.039) for y in (5.0, 15.0) for x in (5.0, 10.0, 15.0)]
+        x_prev = np.empty(2 * n)
+        x_prev[0::2] = props.p0
+        x_prev[1::2] = 288.706
+        return Problem(name, grid, props, K, phi, kap, heaters, 10.0 * DAY, x_prev, x_prev.copy(), seed)
     if name in ("CaseII", "CaseIII"):
         # the problem-size study's well cases (Section 4): N x N cells of a
         # 20 m x 20 m x 1 m square, k = 3e-13 m^2, porosity 0.2, uniform start

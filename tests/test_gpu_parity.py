@@ -65,7 +65,14 @@ CASES = {
                                       props=synth.Props(g=9.80665)),
     "W4s": lambda: synth.make_problem("W4", grid=synth.Grid(24, 24, 24, 1, 1, 1)),
     "line": lambda: synth.make_problem("W2", grid=synth.Grid(17, 1, 1, 1, 1, 1)),
+    # heaters (energy sources U (T_h - T)) beside wells, on a perturbed state
+    "heat": lambda: _with_heaters(synth.make_problem("W2", grid=synth.Grid(9, 8, 3, 1, 1, 1))),
 }
+
+
+def _with_heaters(p):
+    p.wells = p.wells + [synth.Well(5, 2, 150.0, 420.0), synth.Well(100, 2, 2.5, 300.0)]
+    return p
 
 
 @pytest.mark.parametrize("case", list(CASES))

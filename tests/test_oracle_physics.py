@@ -117,11 +117,17 @@ def _complex_step_jacobian(p, h=1e-30):
     return Jc
 
 
-@pytest.mark.parametrize("g", [0.0, 9.80665])
-def test_jacobian_matches_complex_step(g):
+HEATER = synth.Well(4, 2, 150.0, 420.0)   # cell 4, U = 150 W/K, T_heater = 420 K
+
+
+@pytest.mark.parametrize("g,heater", [(0.0, False), (9.80665, False), (0.0, True)])
+def test_jacobian_matches_complex_step(g, heater):
     """eq. AXR blocks equal the complex-step derivative of the oracle's own
-    residual (upwind decided on real parts = frozen upwind)."""
+    residual (upwind decided on real parts = frozen upwind), also with a
+    heater's energy source."""
     p = tiny(g=g, dims=(3, 3, 2))
+    if heater:
+        p.wells = p.wells + [HEATER]
     J = oracle.jacobian(p)
     Jd = J.dense()
     Jc = _complex_step_jacobian(p)
@@ -159,6 +165,7 @@ def test_schur_equals_ATT_for_constant_properties():
     exact: S~_T = A_TT = S (Section 3.3, eq. Se)."""
     pr = synth.Props(c_p=0.0, c_T=0.0, mu_B=0.0)
     p = tiny(props=pr)
+    p.wells = p.wells + [HEATER]   # a heater adds U to both (eq. Se: U D_heaters)
     J = oracle.jacobian(p)
     assert np.all(J.pT == 0.0)
     np.testing.assert_array_equal(J.S, J.TT)
@@ -292,3 +299,28 @@ def test_well_terms_signs_and_enthalpy():
     assert abs(G[2 * prod.cell + 1] / G[2 * prod.cell] - p.props.cv * 360.0) <= 1e-12 * p.props.cv * 360
     others = [i for i in range(grid.n) if i not in (inj.cell, prod.cell)]
     assert np.all(G[2 * np.array(others)] == 0.0)
+
+
+def test_heaters_drive_the_steady_state_to_the_heater_temperature():
+    """With no-flow boundaries, no wells and two heaters at the same
+    temperature, the only steady state is the uniform heater temperature
+    (conduction equalises, the heaters' sources U (T_h - T) vanish only
+    there); long backward-Euler steps reach it.  With different heater
+    temperatures the steady state has the heat balance sum_k U_k (T_k - T)
+    = 0 over the heaters' cells (no energy leaves through the boundary)."""
+    grid = synth.Grid(5, 4, 1, 1.0, 1.0, 1.0)
+    p = synth.make_problem("W2", grid=grid)
+    p.wells = [synth.Well(0, 2, 200.0, 420.0), synth.Well(19, 2, 200.0, 420.0)]
+    p.x_k[:] = p.x_prev
+    p = dataclasses.replace(p, dt=1.0e9)
+    xs, its, _ = oracle.newton_simulate(p, 3, max_newton=12)
+    T = xs[-1][1::2]
+    assert np.abs(T - 420.0).max() <= 1e-6 * 420.0
+    # two heaters with different temperatures and coefficients
+    p.wells = [synth.Well(0, 2, 300.0, 400.0), synth.Well(19, 2, 100.0, 320.0)]
+    xs, its, _ = oracle.newton_simulate(p, 6, max_newton=12)
+    T = xs[-1][1::2]
+    q0, q1 = 300.0 * (400.0 - T[0]), 100.0 * (320.0 - T[19])
+    assert q0 > 0 and q1 < 0                        # heat flows from the hot heater to the cold one
+    assert abs(q0 + q1) <= 1e-6 * abs(q0)
+    assert 320.0 < T.min() and T.max() < 400.0

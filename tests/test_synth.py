@@ -49,6 +49,15 @@ def test_refinement_recipe_uniform_start_and_corner_wells():
         assert [(w.cell, w.kind) for w in p.wells] == [(0, 0), (N * N - 1, 1)]
 
 
+def test_paper_heater_case():
+    for N in (20, 80):
+        g = synth.Grid(N, N, 1, 20.0 / N, 20.0 / N, 1.0)
+        p = synth.make_problem("CaseI", grid=g)
+        assert [w.kind for w in p.wells] == [2] * 6 and len({w.cell for w in p.wells}) == 6
+        assert all(w.rate == 5.44409e-6 and w.T_inj == 422.039 for w in p.wells)
+        assert np.all(p.x_k[1::2] == 288.706) and p.dt == 10 * 86400.0
+
+
 def test_paper_well_cases():
     for name, T0, q in (("CaseII", 288.706, 5e-8), ("CaseIII", 320.0, 1e-6)):
         for N in (20, 80):
