@@ -293,33 +293,46 @@ def run_variants(prob, dev, cfg, iters64, ms64):
             row[key] = {"linear_per_newton": round(sr["linear_per_newton"], 2), "newton_iters": sr["newton_iters"],
                         "ms_per_solve": round(sr["ms_per_solve"], 3), "unconverged_steps": sr["unconverged_steps"]}
         ref[f"{N}x{N}"] = row
-    # the paper's own cases of the problem-size study (Section 4, tables isoH, isoW and
-    # isoHighW), on this build's physics: linear iterations per Newton iteration over two
-    # 10-day steps, with the published figures beside them (PETSc/BoomerAMG, serial CPU)
+    # the paper's own cases of the problem-size study (Section 4, tables isoH, isoW,
+    # isoHighW, anisoH and anisoW), on this build's physics: linear iterations per Newton
+    # iteration over two steps, with the published figures beside them (PETSc/BoomerAMG,
+    # serial CPU; the paper's "> 200" entries as None); GMRES to rtol 1e-5, the paper's
+    # tolerance for this study (Section 5).  At 1e-8 the heater cases sit below FP64's
+    # attainable accuracy on the finer grids (|A| |x| / |b| ~ 1e7: even a direct solve
+    # leaves 3e-8), so FGMRES would run to its cap there
     paper_tab = {"CaseI": {"block": [2.57, 3.23, 2.86, 3.44, 3.71], "cpr": [3.4, 5.38, 9.09, 16.3, 30.7]},
                  "CaseII": {"block": [2.43, 2.43, 2.86, 3.28, 3.71], "cpr": [3.71, 5.71, 9.86, 19.4, 37.4],
                             "block_S_ATT": [4.57, 5.0, 5.57, 6.29, 6.57],
                             "block_S_diag": [4.14, 4.43, 5.29, 5.86, 6.43]},
-                 "CaseIII": {"block": [3.67, 4.38, 4.7, 5.10, 5.52], "cpr": [4.71, 7.31, 13.1, 24.7, 50.6]}}
+                 "CaseIII": {"block": [3.67, 4.38, 4.7, 5.10, 5.52], "cpr": [4.71, 7.31, 13.1, 24.7, 50.6]},
+                 "CaseIV": {"block": [2.31, 2.67, 3.25, 3.67, 3.86], "cpr": [3.11, 4.56, 8.56, 15.8, 30.4]},
+                 "CaseV": {"block": [2.38, 3.27, 4.52, 4.68, 5.36], "cpr": [2.86, 3.6, 4.76, 7.0, 12.04],
+                           "block_S_ATT": [9, 17.1, 24.1, 27.9, 31.6], "block_S_diag": [None] * 5}}
     cases = {}
-    for case in ("CaseI", "CaseII", "CaseIII"):
+    for case in ("CaseI", "CaseII", "CaseIII", "CaseIV", "CaseV"):
         rows = {}
         for N in (20, 40, 80, 160, 320):
             g = synth.Grid(N, N, 1, 20.0 / N, 20.0 / N, 1.0)
             pc = synth.make_problem(case, grid=g)
-            forms = [("block", dc.replace(cfg, maxit=400)), ("block_ext_i_pressure", dc.replace(cfg, maxit=400, interp_pp=1)),
-                     ("cpr", dc.replace(cfg, method="cpr", maxit=400))]
-            if case == "CaseII":
-                forms += [("block_S_ATT", dc.replace(cfg, schur="ATT", maxit=400)),
-                          ("block_S_diag", dc.replace(cfg, schur="diag", maxit=400))]
+            c5 = dc.replace(cfg, rtol=1e-5, maxit=400)
+            forms = [("block", c5), ("block_ext_i_pressure", dc.replace(c5, interp_pp=1)),
+                     ("cpr", dc.replace(c5, method="cpr"))]
+            if case in ("CaseII", "CaseV"):
+                forms += [("block_S_ATT", dc.replace(c5, schur="ATT")),
+                          ("block_S_diag", dc.replace(c5, schur="diag")),
+                          ("block_S_ATT_ext_i_pressure", dc.replace(c5, schur="ATT", interp_pp=1)),
+                          ("block_S_diag_ext_i_pressure", dc.replace(c5, schur="diag", interp_pp=1))]
             row = {}
             for key, cr in forms:
                 _, sr = solver.simulate(pc, cr, solver.NewtonConfig(steps=2))
                 row[key] = round(sr["linear_per_newton"], 2)
+                if sr["unconverged_steps"]:
+                    row[key + "_unconverged_steps"] = sr["unconverged_steps"]
             rows[f"{N}x{N}"] = row
         cases[case] = {"this_build": rows, "paper": paper_tab[case]}
-    out["paper_cases_2d"] = dict(cases, note="linear iterations per Newton iteration, 2 steps of 10 days; "
-                                 "paper: Section 4 tables isoH (Case I), isoW (Case II) and isoHighW (Case III), "
+    out["paper_cases_2d"] = dict(cases, note="linear iterations per Newton iteration, 2 steps of 10 days "
+                                 "(Case V: 12 hours), FGMRES to rtol 1e-5 capped at 400; paper: Section 4 tables isoH (Case I), "
+                                 "isoW (Case II), isoHighW (Case III), anisoH (Case IV) and anisoW (Case V), "
                                  "N = 20..320")
     _progress("paper cases done")
     out["refinement_2d"] = dict(ref, note="R2 recipe: N x N cells of a 20 m x 20 m x 1 m slab, k = 1e-13 m^2, "

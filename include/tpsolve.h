@@ -105,6 +105,16 @@ int assemble_tpfa(const tp_grid* grid, const tp_props* props, const double* K,
                   const tp_well* wells, double dt, const double* x_prev,
                   const double* x_k, tp_jacobian* J, double* G, void* stream);
 
+/* As assemble_tpfa with the diagonal permeability tensor K = diag(K_x, K_y,
+ * K_z) of the Peaceman discussion in Section 2.1 (anisotropic media, the
+ * problem-size study's Cases IV and V in Section 4): K3 is a 3n device array
+ * [K_x(0..n-1), K_y(0..n-1), K_z(0..n-1)], and a face normal to axis a takes
+ * the harmonic mean of its two cells' K_a.  Same errors as assemble_tpfa. */
+int assemble_tpfa_aniso(const tp_grid* grid, const tp_props* props, const double* K3,
+                        const double* phi, const double* kappa, int32_t nwells,
+                        const tp_well* wells, double dt, const double* x_prev,
+                        const double* x_k, tp_jacobian* J, double* G, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Algebraic multigrid (Section 3: A_pp and the Schur approximation are each
  * applied by one AMG V-cycle).  Strength theta, seeded PMIS coarsening with

@@ -143,12 +143,23 @@ def stencil_pattern(grid):
     return rowptr, col
 
 
+def _perm(K):
+    """Pointer and stride of the permeability: a scalar per cell (shape (n,))
+    or the diagonal tensor (shape (3, n): K_x, K_y, K_z)."""
+    K = _f64(K)
+    if K.ndim == 1:
+        return _p(K), C.c_int32(0)
+    if K.ndim != 2 or K.shape[0] != 3:
+        raise ValueError("K must have shape (n,) or (3, n)")
+    return _p(K), C.c_int32(K.shape[1])
+
+
 def residual(prob, x=None):
     x = prob.x_k if x is None else x
     G = np.zeros(2 * prob.grid.n)
     ws = _wells(prob.wells)
     lib().or_residual(C.byref(_grid(prob.grid)), C.byref(_props(prob.props)),
-                      _p(_f64(prob.K)), _p(_f64(prob.phi)), _p(_f64(prob.kappa)),
+                      *_perm(prob.K), _p(_f64(prob.phi)), _p(_f64(prob.kappa)),
                       C.c_int32(len(prob.wells)), ws, C.c_double(prob.dt),
                       _p(_f64(prob.x_prev)), _p(_f64(x)), _p(G))
     return G
@@ -160,7 +171,7 @@ def residual_complex(prob, xc):
     G = np.zeros(2 * prob.grid.n, dtype=np.complex128)
     ws = _wells(prob.wells)
     lib().or_residual_c(C.byref(_grid(prob.grid)), C.byref(_props(prob.props)),
-                        _p(_f64(prob.K)), _p(_f64(prob.phi)), _p(_f64(prob.kappa)),
+                        *_perm(prob.K), _p(_f64(prob.phi)), _p(_f64(prob.kappa)),
                         C.c_int32(len(prob.wells)), ws, C.c_double(prob.dt),
                         _p(_f64(prob.x_prev)), _p(xc), _p(G))
     return G
@@ -204,7 +215,7 @@ def jacobian(prob, x=None):
     arrs = [np.zeros(nnz) for _ in range(5)]
     ws = _wells(prob.wells)
     lib().or_jacobian(C.byref(_grid(prob.grid)), C.byref(_props(prob.props)),
-                      _p(_f64(prob.K)), _p(_f64(prob.phi)), _p(_f64(prob.kappa)),
+                      *_perm(prob.K), _p(_f64(prob.phi)), _p(_f64(prob.kappa)),
                       C.c_int32(len(prob.wells)), ws, C.c_double(prob.dt),
                       _p(_f64(prob.x_prev)), _p(_f64(x)), _p(rowptr), _p(col),
                       *[_p(a) for a in arrs])

@@ -89,12 +89,13 @@ static double complex mu_c(const or_props* pr, double complex T)
 
 /* mass flux from lo to hi across one face and the upwinded temperature */
 static void face_flux_c(const or_grid* g, const or_props* pr, const double* K,
-                        const double* kappa, const double complex* x, int32_t lo,
+                        int32_t kstride, const double* kappa, const double complex* x, int32_t lo,
                         int32_t hi, int axis, double complex* F, double complex* Tup,
                         double* Th)
 {
     double ad = area_over_dist(g, axis);
-    double Ups = ad * harmonic(K[lo], K[hi]);
+    const double* Ka = K + (size_t)axis * (size_t)kstride;  /* K's diagonal entry along this axis */
+    double Ups = ad * harmonic(Ka[lo], Ka[hi]);
     *Th = ad * harmonic(kappa[lo], kappa[hi]);
     double complex pl = x[2 * lo], Tl = x[2 * lo + 1], ph = x[2 * hi], Thh = x[2 * hi + 1];
     double complex rl = rho_c(pr, pl, Tl), rh = rho_c(pr, ph, Thh);
@@ -109,7 +110,7 @@ static void face_flux_c(const or_grid* g, const or_props* pr, const double* K,
 }
 
 void or_residual_c(const or_grid* g, const or_props* pr, const double* K,
-                   const double* phi, const double* kappa, int32_t nw,
+                   int32_t kstride, const double* phi, const double* kappa, int32_t nw,
                    const or_well* w, double dt, const double* x_prev,
                    const double complex* x, double complex* G)
 {
@@ -131,7 +132,7 @@ void or_residual_c(const or_grid* g, const or_props* pr, const double* K,
             int32_t lo = i < j ? i : j, hi = i < j ? j : i;
             double complex F, Tup;
             double Th;
-            face_flux_c(g, pr, K, kappa, x, lo, hi, ax, &F, &Tup, &Th);
+            face_flux_c(g, pr, K, kstride, kappa, x, lo, hi, ax, &F, &Tup, &Th);
             double complex Fout = (i == lo) ? F : -F;
             Rm += Fout;
             Re += pr->cv * Tup * Fout + Th * (T - x[2 * j + 1]);
@@ -158,7 +159,7 @@ void or_residual_c(const or_grid* g, const or_props* pr, const double* K,
 }
 
 void or_residual(const or_grid* g, const or_props* pr, const double* K,
-                 const double* phi, const double* kappa, int32_t nw,
+                 int32_t kstride, const double* phi, const double* kappa, int32_t nw,
                  const or_well* w, double dt, const double* x_prev,
                  const double* x, double* G)
 {
@@ -166,7 +167,7 @@ void or_residual(const or_grid* g, const or_props* pr, const double* K,
     double complex* xc = (double complex*)malloc(sizeof(double complex) * 2 * (size_t)n);
     double complex* Gc = malloc(sizeof(double complex) * 2 * (size_t)n);
     for (int32_t i = 0; i < 2 * n; ++i) xc[i] = x[i];
-    or_residual_c(g, pr, K, phi, kappa, nw, w, dt, x_prev, xc, Gc);
+    or_residual_c(g, pr, K, kstride, phi, kappa, nw, w, dt, x_prev, xc, Gc);
     for (int32_t i = 0; i < 2 * n; ++i) G[i] = creal(Gc[i]);
     free(xc);
     free(Gc);
@@ -192,12 +193,13 @@ typedef struct {
 } face_t;
 
 static face_t face_real(const or_grid* g, const or_props* pr, const double* K,
-                        const double* kappa, const double* x, int32_t lo, int32_t hi,
+                        int32_t kstride, const double* kappa, const double* x, int32_t lo, int32_t hi,
                         int axis)
 {
     face_t f;
     double ad = area_over_dist(g, axis);
-    double Ups = ad * harmonic(K[lo], K[hi]);
+    const double* Ka = K + (size_t)axis * (size_t)kstride;
+    double Ups = ad * harmonic(Ka[lo], Ka[hi]);
     f.Th = ad * harmonic(kappa[lo], kappa[hi]);
     double pl = x[2 * lo], Tl = x[2 * lo + 1], ph = x[2 * hi], Thv = x[2 * hi + 1];
     double rl = rho_r(pr, pl, Tl), rh = rho_r(pr, ph, Thv);
@@ -224,7 +226,7 @@ static face_t face_real(const or_grid* g, const or_props* pr, const double* K,
 }
 
 void or_jacobian(const or_grid* g, const or_props* pr, const double* K,
-                 const double* phi, const double* kappa, int32_t nw,
+                 int32_t kstride, const double* phi, const double* kappa, int32_t nw,
                  const or_well* w, double dt, const double* x_prev,
                  const double* x, const int32_t* rowptr, const int32_t* col,
                  double* App, double* ApT, double* ATp, double* ATT, double* S)
@@ -257,7 +259,7 @@ void or_jacobian(const or_grid* g, const or_props* pr, const double* K,
             for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
                 if (col[k] == j) kj = k;
             int32_t lo = i < j ? i : j, hi = i < j ? j : i;
-            face_t f = face_real(g, pr, K, kappa, x, lo, hi, ax);
+            face_t f = face_real(g, pr, K, kstride, kappa, x, lo, hi, ax);
             /* flux out of i and its derivatives w.r.t. (own, neighbour) */
             double s = (i == lo) ? 1.0 : -1.0;
             double Fout = s * f.F;

@@ -32,20 +32,24 @@ int32_t or_stencil_nnz(const or_grid* g);
 /* Sorted 5/7-point stencil pattern; returns nnz. */
 int32_t or_stencil_pattern(const or_grid* g, int32_t* rowptr, int32_t* col);
 
-/* Residual G(x) of eq. (Fm)/(Fe) on complex states (complex-step checks). */
+/* K is the permeability: kstride 0 for a scalar per cell (n values), or
+ * kstride n for the diagonal tensor diag(K_x, K_y, K_z) of the Peaceman
+ * discussion in Section 2.1, stored as [K_x(n), K_y(n), K_z(n)]; a face
+ * normal to axis a takes the harmonic mean of its two cells' K_a.
+ * Residual G(x) of eq. (Fm)/(Fe) on complex states (complex-step checks). */
 void or_residual_c(const or_grid* g, const or_props* pr, const double* K,
-                   const double* phi, const double* kappa, int32_t nw,
+                   int32_t kstride, const double* phi, const double* kappa, int32_t nw,
                    const or_well* w, double dt, const double* x_prev,
                    const double complex* x, double complex* G);
 /* Residual on real states (interleaved [p_i, T_i]). */
 void or_residual(const or_grid* g, const or_props* pr, const double* K,
-                 const double* phi, const double* kappa, int32_t nw,
+                 int32_t kstride, const double* phi, const double* kappa, int32_t nw,
                  const or_well* w, double dt, const double* x_prev,
                  const double* x, double* G);
 /* Jacobian blocks (eq. AXR) and the Schur approximation of eq. (Se), all on
  * the stencil pattern. */
 void or_jacobian(const or_grid* g, const or_props* pr, const double* K,
-                 const double* phi, const double* kappa, int32_t nw,
+                 int32_t kstride, const double* phi, const double* kappa, int32_t nw,
                  const or_well* w, double dt, const double* x_prev,
                  const double* x, const int32_t* rowptr, const int32_t* col,
                  double* App, double* ApT, double* ATp, double* ATT, double* S);

@@ -82,7 +82,7 @@ k_stencil_counts(tp_grid g, int32_t* __restrict__ cnt) {
 
 __global__ void __launch_bounds__(256)
 k_assemble(tp_grid g, tp_props pr, WellSet ws, double dt, const double* __restrict__ K,
-           const double* __restrict__ phi, const double* __restrict__ kap,
+           int32_t kstride, const double* __restrict__ phi, const double* __restrict__ kap,
            const double* __restrict__ xprev, const double* __restrict__ x,
            const int32_t* __restrict__ rowptr, int32_t* __restrict__ col,
            double* __restrict__ App, double* __restrict__ ApT, double* __restrict__ ATp,
@@ -135,7 +135,8 @@ k_assemble(tp_grid g, tp_props pr, WellSet ws, double dt, const double* __restri
         const int32_t lo = i_lo ? i : j, hi = i_lo ? j : i;
         const double zlo = (lo / nxy + 0.5) * g.dz, zhi = (hi / nxy + 0.5) * g.dz;
         (void)zi;
-        FaceOut f = face_eval(pr, ad_axis[axis], K[lo], K[hi], kap[lo], kap[hi], x[2 * lo],
+        const double* Ka = K + (size_t)axis * (size_t)kstride;
+        FaceOut f = face_eval(pr, ad_axis[axis], Ka[lo], Ka[hi], kap[lo], kap[hi], x[2 * lo],
                               x[2 * lo + 1], x[2 * hi], x[2 * hi + 1], zlo - zhi);
         const double s = i_lo ? 1.0 : -1.0;
         const double Fout = s * f.F;
@@ -217,10 +218,12 @@ int tp_jacobian_sizes(const tp_grid* grid, int32_t* n, int32_t* nnz) {
     return TP_OK;
 }
 
-int assemble_tpfa(const tp_grid* grid, const tp_props* props, const double* K,
-                  const double* phi, const double* kappa, int32_t nwells,
-                  const tp_well* wells, double dt, const double* x_prev,
-                  const double* x_k, tp_jacobian* J, double* G, void* stream) {
+namespace {
+
+int assemble(const tp_grid* grid, const tp_props* props, const double* K, bool diag_tensor,
+             const double* phi, const double* kappa, int32_t nwells, const tp_well* wells,
+             double dt, const double* x_prev, const double* x_k, tp_jacobian* J, double* G,
+             void* stream) {
     TP_GUARD({
         TP_CHECK_ARG(grid && props && K && phi && kappa && x_prev && x_k && J && G,
                      "assemble_tpfa: null argument");
@@ -248,10 +251,29 @@ int assemble_tpfa(const tp_grid* grid, const tp_props* props, const double* K,
         const int B = 256;
         TP_LAUNCH(tp::k_stencil_counts, tp::cdiv(n, B), B, 0, s, *grid, J->rowptr);
         tp::scan_exclusive(J->rowptr, J->rowptr, n, s);
-        TP_LAUNCH(tp::k_assemble, tp::cdiv(n, B), B, 0, s, *grid, *props, ws, dt, K, phi, kappa,
-                  x_prev, x_k, J->rowptr, J->col, J->pp, J->pT, J->Tp, J->TT, J->S, G);
+        TP_LAUNCH(tp::k_assemble, tp::cdiv(n, B), B, 0, s, *grid, *props, ws, dt, K,
+                  diag_tensor ? n : 0, phi, kappa, x_prev, x_k, J->rowptr, J->col, J->pp, J->pT,
+                  J->Tp, J->TT, J->S, G);
     });
     return TP_OK;
+}
+
+}  // namespace
+
+int assemble_tpfa(const tp_grid* grid, const tp_props* props, const double* K,
+                  const double* phi, const double* kappa, int32_t nwells,
+                  const tp_well* wells, double dt, const double* x_prev,
+                  const double* x_k, tp_jacobian* J, double* G, void* stream) {
+    return assemble(grid, props, K, false, phi, kappa, nwells, wells, dt, x_prev, x_k, J, G,
+                    stream);
+}
+
+int assemble_tpfa_aniso(const tp_grid* grid, const tp_props* props, const double* K3,
+                        const double* phi, const double* kappa, int32_t nwells,
+                        const tp_well* wells, double dt, const double* x_prev,
+                        const double* x_k, tp_jacobian* J, double* G, void* stream) {
+    return assemble(grid, props, K3, true, phi, kappa, nwells, wells, dt, x_prev, x_k, J, G,
+                    stream);
 }
 
 }  // extern "C"

@@ -81,7 +81,7 @@ class Problem:
     name: str
     grid: Grid
     props: Props
-    K: np.ndarray          # (n,) permeability, m^2
+    K: np.ndarray          # (n,) permeability, m^2, or (3, n): diag(K_x, K_y, K_z)
     phi: np.ndarray        # (n,) porosity
     kappa: np.ndarray      # (n,) thermal conductivity, W/m/K
     wells: list
@@ -158,6 +158,16 @@ def corner_wells(grid: Grid, T_inj: float, rate: float = WELL_RATE):
     return [Well(0, 0, rate, T_inj), Well(grid.n - 1, 1, rate, T_inj)]
 
 
+def _paper_perm(n: int, anisotropic: bool) -> np.ndarray:
+    """Homogeneous 3e-13 m^2; anisotropic: diag(3e-11, 3e-13, 3e-13) (Section 4,
+    Cases IV and V)."""
+    if not anisotropic:
+        return np.full(n, 3.0e-13)
+    K = np.full((3, n), 3.0e-13)
+    K[0] = 3.0e-11
+    return K
+
+
 def make_problem(name: str, seed: int | None = None, props: Props | None = None,
                  kappa: float | None = None, grid: Grid | None = None) -> Problem:
     """Build one of the named workloads (W1..W5) or a scaled variant.
@@ -232,15 +242,16 @@ def make_problem(name: str, seed: int | None = None, props: Props | None = None,
         x_prev[1::2] = props.T0
         return Problem(name, grid, props, K, phi, kap, corner_wells(grid, 450.0, rate=1.0e-6),
                        DAY, x_prev, x_prev.copy(), seed)
-    if name == "CaseI":
-        # the problem-size study's heater case (Section 4): as Case II with six
+    if name in ("CaseI", "CaseIV"):
+        # the problem-size study's heater cases (Section 4): as Case II with six
         # heaters (coefficient 5.44409e-6 W/K, 422.039 K) instead of wells; the
-        # paper does not place them: x = 5, 10, 15 m at y = 5 and 15 m
+        # paper does not place them: x = 5, 10, 15 m at y = 5 and 15 m.  Case IV
+        # raises the permeability along x to 3e-11 m^2
         seed = 0 if seed is None else seed
         N = 80
         grid = grid or Grid(N, N, 1, 20.0 / N, 20.0 / N, 1.0)
         n = grid.n
-        K = np.full(n, 3.0e-13)
+        K = _paper_perm(n, name == "CaseIV")
         phi = np.full(n, 0.2)
         kap = np.full(n, 2.0 if kappa is None else kappa)
 
@@ -251,23 +262,24 @@ def make_problem(name: str, seed: int | None = None, props: Props | None = None,
         x_prev[0::2] = props.p0
         x_prev[1::2] = 288.706
         return Problem(name, grid, props, K, phi, kap, heaters, 10.0 * DAY, x_prev, x_prev.copy(), seed)
-    if name in ("CaseII", "CaseIII"):
+    if name in ("CaseII", "CaseIII", "CaseV"):
         # the problem-size study's well cases (Section 4): N x N cells of a
         # 20 m x 20 m x 1 m square, k = 3e-13 m^2, porosity 0.2, uniform start
         # at 288.706 K (Case III: 320 K), 3 injectors (422.039 K) and 3
-        # producers at constant rates 5e-8 m^3/s (Case III: 1e-6), 10-day steps;
-        # the paper does not place the wells: injectors at x = 2.5 m and
-        # producers at x = 17.5 m, both at y = 2.5, 10 and 17.5 m
+        # producers at constant rates 5e-8 m^3/s (Cases III and V: 1e-6),
+        # 10-day steps (Case V: 12 hours, with K_x raised to 3e-11 m^2); the
+        # paper does not place the wells: injectors at x = 2.5 m and producers
+        # at x = 17.5 m, both at y = 2.5, 10 and 17.5 m
         seed = 0 if seed is None else seed
         N = 80
         grid = grid or Grid(N, N, 1, 20.0 / N, 20.0 / N, 1.0)
         n = grid.n
-        K = np.full(n, 3.0e-13)
+        K = _paper_perm(n, name == "CaseV")
         phi = np.full(n, 0.2)
         kap = np.full(n, 2.0 if kappa is None else kappa)
-        hot = name == "CaseIII"
-        T_init = 320.0 if hot else 288.706
-        rate = 1.0e-6 if hot else 5.0e-8
+        T_init = 320.0 if name == "CaseIII" else 288.706
+        rate = 5.0e-8 if name == "CaseII" else 1.0e-6
+        dt = 0.5 * DAY if name == "CaseV" else 10.0 * DAY
 
         def cell(x, y):
             ix = min(grid.nx - 1, int(x / grid.dx))
@@ -278,7 +290,7 @@ def make_problem(name: str, seed: int | None = None, props: Props | None = None,
         x_prev = np.empty(2 * n)
         x_prev[0::2] = props.p0
         x_prev[1::2] = T_init
-        return Problem(name, grid, props, K, phi, kap, wells, 10.0 * DAY, x_prev, x_prev.copy(), seed)
+        return Problem(name, grid, props, K, phi, kap, wells, dt, x_prev, x_prev.copy(), seed)
     raise ValueError(f"unknown workload {name!r}")
 
 

@@ -74,7 +74,7 @@ class _Allocator(C.Structure):
     _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", C.c_void_p)]
 
 
-EXPORTS = ["tp_last_error", "tp_init", "tp_jacobian_sizes", "assemble_tpfa", "amg_setup", "amg_setup_schur_diag", "amg_refresh_fine",
+EXPORTS = ["tp_last_error", "tp_init", "tp_jacobian_sizes", "assemble_tpfa", "assemble_tpfa_aniso", "amg_setup", "amg_setup_schur_diag", "amg_refresh_fine",
            "amg_num_levels", "amg_level_info", "amg_level_format", "amg_level_copy", "amg_vcycle", "amg_destroy",
            "precond_create", "precond_apply", "precond_destroy", "fgmres_solve",
            "ilu0_create", "ilu0_create_jacobian", "ilu0_refactor_jacobian", "ilu0_solve", "ilu0_info",
@@ -232,10 +232,19 @@ class Jacobian:
 
 def assemble_tpfa(grid, props, K, phi, kappa, wells, dt, x_prev, x_k, J=None, G=None,
                   stream=None):
-    """Assemble G(x_k) and the Jacobian on the device (tensors in, tensors out)."""
+    """Assemble G(x_k) and the Jacobian on the device (tensors in, tensors out).
+    K is a scalar permeability per cell (n,) or the diagonal tensor (3, n)."""
     torch = _torch()
     lib = load()
     n, nnz = jacobian_sizes(grid)
+    if K.dim() == 2:
+        if tuple(K.shape) != (3, n) or not K.is_contiguous():
+            raise ValueError("anisotropic K must be a contiguous (3, n) tensor")
+        entry = lib.assemble_tpfa_aniso
+    elif K.dim() == 1 and K.numel() == n:
+        entry = lib.assemble_tpfa
+    else:
+        raise ValueError("K must have shape (n,) or (3, n)")
     if J is None:
         J = Jacobian(n, nnz, device=x_k.device)
     if G is None:
@@ -245,7 +254,7 @@ def assemble_tpfa(grid, props, K, phi, kappa, wells, dt, x_prev, x_k, J=None, G=
         ws[i] = _Well(w.cell, w.kind, w.rate, w.T_inj)
     pr = _Props(*props.as_tuple())
     jc = J.c()
-    _check(lib.assemble_tpfa(C.byref(grid_c(grid)), C.byref(pr), _ptr(K), _ptr(phi), _ptr(kappa),
+    _check(entry(C.byref(grid_c(grid)), C.byref(pr), _ptr(K), _ptr(phi), _ptr(kappa),
                              C.c_int32(len(wells)), ws, C.c_double(dt), _ptr(x_prev), _ptr(x_k),
                              C.byref(jc), _ptr(G), _stream(stream)))
     return J, G

@@ -67,11 +67,20 @@ CASES = {
     "line": lambda: synth.make_problem("W2", grid=synth.Grid(17, 1, 1, 1, 1, 1)),
     # heaters (energy sources U (T_h - T)) beside wells, on a perturbed state
     "heat": lambda: _with_heaters(synth.make_problem("W2", grid=synth.Grid(9, 8, 3, 1, 1, 1))),
+    # diagonal permeability tensor, each component varying cell by cell, with gravity
+    "aniso": lambda: _aniso(synth.make_problem("W2", grid=synth.Grid(9, 7, 6, 1, 1.5, 2.0),
+                                               props=synth.Props(g=9.80665))),
 }
 
 
 def _with_heaters(p):
     p.wells = p.wells + [synth.Well(5, 2, 150.0, 420.0), synth.Well(100, 2, 2.5, 300.0)]
+    return p
+
+
+def _aniso(p):
+    rng = np.random.default_rng(23)
+    p.K = np.stack([p.K * 10.0 ** rng.uniform(-1.5, 1.5, p.grid.n) for _ in range(3)])
     return p
 
 

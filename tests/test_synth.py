@@ -58,6 +58,19 @@ def test_paper_heater_case():
         assert np.all(p.x_k[1::2] == 288.706) and p.dt == 10 * 86400.0
 
 
+def test_paper_anisotropic_cases():
+    """Cases IV and V: K_x raised to 3e-11 m^2, K_y = K_z = 3e-13 m^2; Case IV
+    heats as Case I, Case V runs the wells of Case III at 12-hour steps from
+    288.706 K."""
+    g = synth.Grid(40, 40, 1, 0.5, 0.5, 1.0)
+    a, b = synth.make_problem("CaseIV", grid=g), synth.make_problem("CaseI", grid=g)
+    assert a.K.shape == (3, g.n) and np.all(a.K[0] == 3e-11) and np.all(a.K[1:] == 3e-13)
+    assert a.wells == b.wells and a.dt == b.dt
+    v, w = synth.make_problem("CaseV", grid=g), synth.make_problem("CaseIII", grid=g)
+    assert np.array_equal(v.K, a.K) and v.wells == w.wells and v.dt == 43200.0
+    assert np.all(v.x_k[1::2] == 288.706)
+
+
 def test_paper_well_cases():
     for name, T0, q in (("CaseII", 288.706, 5e-8), ("CaseIII", 320.0, 1e-6)):
         for N in (20, 80):
