@@ -245,24 +245,51 @@ def schur_diag(J):
     return S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data.copy()
 
 
-def newton_simulate(prob, steps, max_newton=4, rtol_f=1e-8, rtol_dx=1e-8):
+def line_search_step(G_at, x, dx, g2, alpha=1e-4, max_backtracks=10):
+    """Backtracking line search on f(lam) = |G(x + lam dx)|^2 / 2 along a
+    Newton direction (Section 5: Newton's method with line search; the
+    backtracking rule of Dennis and Schnabel, "Numerical Methods for
+    Unconstrained Optimization and Nonlinear Equations", 1983, Section 6.3).
+    For the Newton direction the slope of f at lam = 0 is -|G(x)|^2 = -g2.
+    lam = 1 is tried first; a trial is accepted when
+    f(lam) <= f(0) - alpha lam g2, else the next lam minimises the quadratic
+    through f(0), f'(0) and f(lam), kept within [lam/10, lam/2].  After
+    `max_backtracks` rejections the last trial is taken.  Returns (lam, the
+    accepted point, its G, the number of rejected trials)."""
+    f0 = 0.5 * g2
+    lam, rejected = 1.0, 0
+    while True:
+        xt = x + lam * dx
+        Gt = G_at(xt)
+        f1 = 0.5 * float(Gt @ Gt)
+        if f1 <= f0 - alpha * lam * g2 or rejected == max_backtracks:
+            return lam, xt, Gt, rejected
+        lq = g2 * lam * lam / (2.0 * (f1 - f0 + g2 * lam))
+        lam = min(max(lq, 0.1 * lam), 0.5 * lam)
+        rejected += 1
+
+
+def newton_simulate(prob, steps, max_newton=4, rtol_f=1e-8, rtol_dx=1e-8, line_search=False):
     """Backward-Euler time stepping from prob.x_prev with Newton's method on
     G(x) = 0 (Section 2.2: each Newton iteration solves eq. AXR for the
     increment; Section 5: a step has converged when |G| relative to the
     step's first |G|, or |dx| relative to |x|, is below 1e-8).  The linear
     step is a sparse direct solve (SuperLU through SciPy), so the result is
-    the exact-Newton reference.  Returns (states after each step, Newton
-    iterations per step, relative |G| histories per step)."""
+    the exact-Newton reference.  With `line_search` each increment is scaled
+    by `line_search_step` (the step-norm test then uses the scaled
+    increment).  Returns (states after each step, Newton iterations per step,
+    relative |G| histories per step); with `line_search` also the step
+    lengths taken, per step."""
     import dataclasses
 
     import scipy.sparse.linalg as spla
     x = np.array(prob.x_prev, dtype=np.float64)
-    states, its, hists = [], [], []
+    states, its, hists, lams = [], [], [], []
     for _ in range(steps):
         p = dataclasses.replace(prob, x_prev=x.copy(), x_k=x.copy())
-        g0, done, k_its, hist = None, False, 0, []
+        g0, done, k_its, hist, lam_s = None, False, 0, [], []
+        G = residual(p, x)
         for k in range(max_newton + 1):
-            G = residual(p, x)
             gn = float(np.linalg.norm(G))
             if g0 is None:
                 g0 = gn
@@ -271,12 +298,21 @@ def newton_simulate(prob, steps, max_newton=4, rtol_f=1e-8, rtol_dx=1e-8):
                 break
             A = sparse_interleaved(jacobian(p, x))
             dx = spla.spsolve(A.tocsc(), -G)
-            x = x + dx
+            if line_search:
+                lam, x, G, _ = line_search_step(lambda xt: residual(p, xt), x, dx, gn * gn)
+                dx = lam * dx
+                lam_s.append(lam)
+            else:
+                x = x + dx
+                G = residual(p, x)
             k_its += 1
             done = float(np.linalg.norm(dx)) <= rtol_dx * float(np.linalg.norm(x))
         states.append(x.copy())
         its.append(k_its)
         hists.append(hist)
+        lams.append(lam_s)
+    if line_search:
+        return states, its, hists, lams
     return states, its, hists
 
 

@@ -138,16 +138,43 @@ class NewtonConfig:
     iteration has converged when the function norm relative to the step's
     first one, or the step norm relative to the iterate's, is below 1e-8).
     reuse: build both hierarchies at a step's first Newton iteration only and
-    refresh their finest level at the later ones (coarse levels lagged)."""
+    refresh their finest level at the later ones (coarse levels lagged).
+    line_search: scale each increment by backtracking on |G|^2 / 2 (Section 5:
+    Newton with line search; Dennis and Schnabel's rule: try the full step,
+    accept when the sufficient-decrease test with alpha = 1e-4 holds, else
+    minimise the quadratic model within [lam/10, lam/2], at most 10 times)."""
     steps: int = 20
     max_newton: int = 4
     rtol_f: float = 1e-8
     rtol_dx: float = 1e-8
     reuse: bool = False
+    line_search: bool = False
 
 
 def _schur_values(J, cfg):
     return {"T": J.S, "ATT": J.TT}.get(cfg.schur)
+
+
+def _backtrack(prob, dev, J, G, x, dx, gn, alpha=1e-4, max_backtracks=10):
+    """Line search along the Newton increment dx from x (|G(x)| = gn).  For a
+    Newton direction f(lam) = |G(x + lam dx)|^2 / 2 has slope -gn^2 at 0.  The
+    full step is tried first; a trial passes when f(lam) <= f(0) - alpha lam
+    gn^2; otherwise the next trial is the minimiser of the quadratic matching
+    f(0), f'(0) and f(lam), clamped to [lam/10, lam/2]; after max_backtracks
+    failures the last trial stands.  J and G are left assembled at the
+    accepted point, which dev["x_k"] holds.  Returns (lam, rejected trials,
+    |G| there)."""
+    import torch
+    g2 = gn * gn
+    lam, rejected = 1.0, 0
+    while True:
+        dev["x_k"] = torch.add(x, dx, alpha=lam)
+        assemble(prob, dev, J, G)
+        gt = float(torch.linalg.vector_norm(G))
+        if 0.5 * gt * gt <= 0.5 * g2 - alpha * lam * g2 or rejected == max_backtracks:
+            return lam, rejected, gt
+        lam = min(max(g2 * lam * lam / (2.0 * (0.5 * gt * gt - 0.5 * g2 + g2 * lam)), 0.1 * lam), 0.5 * lam)
+        rejected += 1
 
 
 def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None):
@@ -166,7 +193,8 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None):
     dev = to_device(prob)
     x = dev["x_prev"].clone()
     dev["x_k"] = x
-    newton, lin, solves, unconverged, builds = 0, 0, 0, 0, 0
+    newton, lin, solves, unconverged, builds, backtracks = 0, 0, 0, 0, 0, 0
+    step_lengths = []
     solve_s = 0.0
     per_step = []
     J = G = None
@@ -193,8 +221,11 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None):
             g0 = None
             its = 0
             done = False
+            fresh = False   # J and G already assembled at x (by the line search)
             for k in range(ncfg.max_newton + 1):
-                J, G = assemble(prob, dev, J, G)
+                if not fresh:
+                    J, G = assemble(prob, dev, J, G)
+                fresh = False
                 gn = float(torch.linalg.vector_norm(G))
                 if g0 is None:
                     g0 = gn
@@ -225,7 +256,16 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None):
                 if not reusable:
                     close(hier)
                     hier = None
-                x += dx
+                if ncfg.line_search:
+                    lam, rej, gn = _backtrack(prob, dev, J, G, x, dx, gn)
+                    x.copy_(dev["x_k"])
+                    dev["x_k"] = x
+                    dx *= lam
+                    backtracks += rej
+                    step_lengths.append(lam)
+                    fresh = True
+                else:
+                    x += dx
                 its += 1
                 lin += st["iters"]
                 solves += 1
@@ -241,6 +281,7 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None):
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     return x, dict(steps=ncfg.steps, newton_iters=newton, linear_iters=lin, solves=solves,
+                   backtracks=backtracks, step_lengths=step_lengths,
                    hierarchy_builds=builds, unconverged_steps=unconverged, newton_per_step=per_step,
                    linear_per_newton=lin / max(newton, 1), total_s=total,
                    ms_per_solve=1e3 * solve_s / max(solves, 1))

@@ -82,3 +82,31 @@ def test_refresh_fine_in_place():
             a.refresh_fine(v1.clone())
             assert np.array_equal(a.vcycle(b).cpu().numpy(), y0), (storage, which)
             a.close()
+
+
+def test_newton_line_search_matches_oracle():
+    """Newton with line search (Section 5) on high-rate wells, where the first
+    increment of the step is damped: the GPU takes the oracle's step lengths
+    and reaches its state."""
+    import dataclasses
+    say("newton line search")
+    p = synth.make_problem("W5", grid=synth.Grid(10, 10, 2, 2.0, 2.0, 1.0))
+    p.wells = [dataclasses.replace(w, rate=1e-4) for w in p.wells]
+    xo, its_o, _, lams_o = oracle.newton_simulate(p, 1, max_newton=12, line_search=True)
+    x, st = solver.simulate(p, solver.SolveConfig(amg=tps.AmgParams(coarse_max=100)),
+                            solver.NewtonConfig(steps=1, max_newton=12, line_search=True))
+    say(f"  step lengths gpu {st['step_lengths']} oracle {lams_o[0]}")
+    assert st["unconverged_steps"] == 0 and st["backtracks"] >= 1
+    assert abs(st["newton_per_step"][0] - its_o[0]) <= 1
+    n = min(len(lams_o[0]), len(st["step_lengths"]))
+    # the increments are FGMRES solutions to rtol 1e-8 (the oracle solves directly), and the
+    # rejected full step lies far from the root, where G magnifies that difference
+    assert np.allclose(st["step_lengths"][:n], lams_o[0][:n], rtol=1e-4, atol=0)
+    # both stop on the step-norm test |dx| <= 1e-8 |x|, which the pressure (1e7 Pa)
+    # dominates; from the damped start the two iterations end 1e-7 apart
+    xg = x.cpu().numpy()
+    for blk in (0, 1):
+        ref = xo[-1][blk::2]
+        err = np.linalg.norm(xg[blk::2] - ref) / np.linalg.norm(ref)
+        say(f"  block {blk}: rel err {err:.2e}")
+        assert err <= 1e-6

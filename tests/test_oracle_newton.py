@@ -52,3 +52,54 @@ def test_newton_step_balances_well_mass():
         moved += w.rate * (rho(pc, w.T_inj) if w.kind == 0 else -rho(pc, Tc))
     assert its[0] >= 1
     assert abs(stored - moved) <= 1e-6 * max(abs(stored), abs(moved), 1e-300), (stored, moved)
+
+
+def test_line_search_affine_takes_the_full_step():
+    """For affine G the Newton step is exact: lam = 1 with no backtracking."""
+    A = np.array([[3.0, 1.0], [1.0, 2.0]])
+    b = np.array([1.0, -2.0])
+    x = np.array([5.0, 7.0])
+    G = A @ x - b
+    dx = np.linalg.solve(A, -G)
+    lam, xt, Gt, rej = oracle.line_search_step(lambda y: A @ y - b, x, dx, float(G @ G))
+    assert lam == 1.0 and rej == 0 and np.abs(Gt).max() < 1e-12
+
+
+def test_line_search_rescues_newton_on_arctan():
+    """Textbook case: Newton on arctan(x) = 0 diverges from x0 = 3 (any start
+    with |x0| beyond about 1.39); the damped iteration converges to 0.  Every
+    rejected trial violates the sufficient-decrease test and every accepted
+    one satisfies it."""
+    G = lambda y: np.arctan(y)
+    x = np.array([3.0])
+    xf = x.copy()
+    for _ in range(4):
+        xf = xf - np.arctan(xf) * (1.0 + xf * xf)
+    assert abs(xf[0]) > 1e3
+    for _ in range(30):
+        g = G(x)
+        g2 = float(g @ g)
+        if g2 < 1e-28:
+            break
+        dx = -g * (1.0 + x * x)
+        lam, xn, gn, rej = oracle.line_search_step(G, x, dx, g2)
+        assert 0.5 * float(gn @ gn) <= 0.5 * g2 - 1e-4 * lam * g2
+        if rej:
+            assert 0.5 * float(G(x + dx) @ G(x + dx)) > 0.5 * g2 - 1e-4 * g2
+            assert lam <= 0.5
+        x = xn
+    assert abs(x[0]) < 1e-14
+
+
+def test_line_search_newton_reaches_the_same_root():
+    """With high-rate wells the first Newton step of a step is damped (lam < 1);
+    the damped iteration still converges, to the root the full-step iteration
+    finds."""
+    import dataclasses
+    p = synth.make_problem("W5", grid=synth.Grid(10, 10, 2, 2.0, 2.0, 1.0))
+    p.wells = [dataclasses.replace(w, rate=1e-4) for w in p.wells]
+    xs, its, _ = oracle.newton_simulate(p, 1, max_newton=12)
+    xl, itl, hl, lams = oracle.newton_simulate(p, 1, max_newton=12, line_search=True)
+    assert min(lams[0]) < 1.0 and hl[0][-1] <= 1e-8
+    for blk in (0, 1):
+        assert np.linalg.norm(xl[0][blk::2] - xs[0][blk::2]) <= 1e-9 * np.linalg.norm(xs[0][blk::2])
