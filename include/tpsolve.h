@@ -65,10 +65,14 @@ int tp_init(const tp_allocator* alloc, int device);
  * ------------------------------------------------------------------------ */
 typedef struct { int32_t nx, ny, nz; double dx, dy, dz; } tp_grid;  /* cell i = ix + nx (iy + ny iz) */
 
-/* rho = rho0 exp(c_p (p - p0) + c_T (T - T0)); mu = mu0 exp(mu_B (1/T - 1/T0));
- * cv, c_r specific heats of fluid and rock; rho_r rock density; g gravity
- * along -z (0 disables). SI units. */
-typedef struct { double rho0, p0, T0, c_p, c_T, mu0, mu_B, cv, rho_r, c_r, g; } tp_props;
+/* rho = rho0 exp(c_p (p - p0) + c_T (T - T0)); mu = mu0 exp(mu_B (1/T - 1/T0))
+ * when api = 0, else the Bennison heavy-oil correlation (Section 2.1,
+ * eq. bennison with the constants of table bennison): mu = 1e-3
+ * 10^(A1 api + A2) T_F^(A3 api + A4) Pa s, T_F = 1.8 (T - 273.15) + 32 the
+ * temperature in Fahrenheit, api the API gravity; cv, c_r specific heats of
+ * fluid and rock; rho_r rock density; g gravity along -z (0 disables). SI
+ * units. */
+typedef struct { double rho0, p0, T0, c_p, c_T, mu0, mu_B, cv, rho_r, c_r, g, api; } tp_props;
 
 /* Constant-rate point well (eq. f, eq. fT): kind 0 injector (mass
  * rate*rho(p, T_inj), enthalpy c_v T_inj), kind 1 producer (mass

@@ -82,8 +82,18 @@ static double complex rho_c(const or_props* pr, double complex p, double complex
     return pr->rho0 * cexp(pr->c_p * (p - pr->p0) + pr->c_T * (T - pr->T0));
 }
 
+/* Bennison's heavy-oil correlation (Section 2.1, eq. bennison; constants of
+ * table bennison): viscosity in centipoise 10^(A1 api + A2) T_F^(A3 api + A4)
+ * with T_F the temperature in degrees Fahrenheit; returned in Pa s. */
+static const double BEN_A1 = -0.8021, BEN_A2 = 23.8765, BEN_A3 = 0.31458, BEN_A4 = -9.21592;
+
 static double complex mu_c(const or_props* pr, double complex T)
 {
+    if (pr->api > 0.0) {
+        double complex TF = (T - 273.15) * 9.0 / 5.0 + 32.0;
+        double centipoise_scale = pow(10.0, BEN_A1 * pr->api + BEN_A2);
+        return 1e-3 * centipoise_scale * cpow(TF, BEN_A3 * pr->api + BEN_A4);
+    }
     return pr->mu0 * cexp(pr->mu_B * (1.0 / T - 1.0 / pr->T0));
 }
 
@@ -182,7 +192,22 @@ static double rho_r(const or_props* pr, double p, double T)
 
 static double mu_r(const or_props* pr, double T)
 {
+    if (pr->api > 0.0) {
+        double TF = (T - 273.15) * 9.0 / 5.0 + 32.0;
+        return 1e-3 * pow(10.0, BEN_A1 * pr->api + BEN_A2) * pow(TF, BEN_A3 * pr->api + BEN_A4);
+    }
     return pr->mu0 * exp(pr->mu_B * (1.0 / T - 1.0 / pr->T0));
+}
+
+/* -d ln(mu) / dT by hand: mu_B / T^2 for the exponential law; for Bennison's,
+ * ln mu = const + (A3 api + A4) ln T_F and dT_F/dT = 9/5 */
+static double minus_dlnmu_dT(const or_props* pr, double T)
+{
+    if (pr->api > 0.0) {
+        double TF = (T - 273.15) * 9.0 / 5.0 + 32.0;
+        return -(BEN_A3 * pr->api + BEN_A4) * (9.0 / 5.0) / TF;
+    }
+    return pr->mu_B / (T * T);
 }
 
 /* Face oriented lo->hi: flux F and its partial derivatives with respect to
@@ -215,7 +240,7 @@ static face_t face_real(const or_grid* g, const or_props* pr, const double* K,
     if (f.up_is_lo) { lam = rl / mu_r(pr, Tl); Tup = Tl; }
     else            { lam = rh / mu_r(pr, Thv); Tup = Thv; }
     double dlam_dp = pr->c_p * lam;
-    double dlam_dT = (pr->c_T + pr->mu_B / (Tup * Tup)) * lam;
+    double dlam_dT = (pr->c_T + minus_dlnmu_dT(pr, Tup)) * lam;
     f.F = Ups * lam * dphi;
     f.Tup = Tup;
     f.dF_plo = Ups * ((f.up_is_lo ? dlam_dp : 0.0) * dphi + lam * dd_plo);

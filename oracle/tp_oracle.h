@@ -22,7 +22,9 @@ extern "C" {
 #endif
 
 typedef struct { int32_t nx, ny, nz; double dx, dy, dz; } or_grid;
-typedef struct { double rho0, p0, T0, c_p, c_T, mu0, mu_B, cv, rho_r, c_r, g; } or_props;
+/* api > 0 selects the Bennison viscosity (Section 2.1, eq. bennison) in
+ * place of mu0 exp(mu_B (1/T - 1/T0)). */
+typedef struct { double rho0, p0, T0, c_p, c_T, mu0, mu_B, cv, rho_r, c_r, g, api; } or_props;
 /* kind 0 injector, 1 producer (rate in m^3/s); kind 2 heater: rate is the
  * heat-transfer coefficient U (W/K) and T_inj the heater temperature */
 typedef struct { int32_t cell, kind; double rate, T_inj; } or_well;

@@ -39,8 +39,24 @@ __device__ inline double rho_of(const tp_props& pr, double p, double T) {
     return pr.rho0 * exp(pr.c_p * (p - pr.p0) + pr.c_T * (T - pr.T0));
 }
 
+// Bennison correlation (table bennison): log10 of the viscosity in cp is
+// (A1 api + A2) + (A3 api + A4) log10(T_F)
+constexpr double kBenA1 = -0.8021, kBenA2 = 23.8765, kBenA3 = 0.31458, kBenA4 = -9.21592;
+constexpr double kLn10 = 2.302585092994045684;
+
+__device__ inline double fahrenheit(double T) { return 1.8 * (T - 273.15) + 32.0; }
+
 __device__ inline double mu_of(const tp_props& pr, double T) {
+    if (pr.api > 0.0)
+        return 1e-3 * exp(kLn10 * (kBenA1 * pr.api + kBenA2)
+                          + (kBenA3 * pr.api + kBenA4) * log(fahrenheit(T)));
     return pr.mu0 * exp(pr.mu_B * (1.0 / T - 1.0 / pr.T0));
+}
+
+// d ln(mu) / dT
+__device__ inline double dlnmu_dT(const tp_props& pr, double T) {
+    if (pr.api > 0.0) return (kBenA3 * pr.api + kBenA4) * 1.8 / fahrenheit(T);
+    return -pr.mu_B / (T * T);
 }
 
 // flux of one face oriented lo -> hi and its partial derivatives
@@ -61,7 +77,7 @@ __device__ inline FaceOut face_eval(const tp_props& pr, double ad, double Klo, d
     if (f.up_lo) { lam = rl / mu_of(pr, Tl); Tup = Tl; }
     else         { lam = rh / mu_of(pr, Th); Tup = Th; }
     double dlam_dp = pr.c_p * lam;
-    double dlam_dT = (pr.c_T + pr.mu_B / (Tup * Tup)) * lam;
+    double dlam_dT = (pr.c_T - dlnmu_dT(pr, Tup)) * lam;
     f.F = Ups * lam * dphi;
     f.Tup = Tup;
     f.dplo = Ups * ((f.up_lo ? dlam_dp : 0.0) * dphi + lam * dd_plo);

@@ -45,10 +45,11 @@ class Grid:
 class Props:
     """Fluid/rock constants, SI units.
 
-    rho = rho0*exp(c_p (p-p0) + c_T (T-T0));  mu = mu0*exp(mu_B (1/T - 1/T0)).
-    cv, c_r: specific heats of fluid and rock (values of the paper's
-    parameter table); rho_r: rock density (not given by the paper);
-    g: gravitational acceleration along -z (0 disables gravity).
+    rho = rho0*exp(c_p (p-p0) + c_T (T-T0));  mu = mu0*exp(mu_B (1/T - 1/T0)),
+    or, with api > 0, the Bennison heavy-oil correlation of API gravity `api`
+    (Section 2.1, eq. bennison).  cv, c_r: specific heats of fluid and rock
+    (values of the paper's parameter table); rho_r: rock density (not given
+    by the paper); g: gravitational acceleration along -z (0 disables gravity).
     """
     rho0: float = 1000.0
     p0: float = 1.0e7
@@ -61,10 +62,11 @@ class Props:
     rho_r: float = 2500.0
     c_r: float = 920.0
     g: float = 0.0
+    api: float = 0.0
 
     def as_tuple(self):
         return (self.rho0, self.p0, self.T0, self.c_p, self.c_T, self.mu0,
-                self.mu_B, self.cv, self.rho_r, self.c_r, self.g)
+                self.mu_B, self.cv, self.rho_r, self.c_r, self.g, self.api)
 
 
 @dataclasses.dataclass(frozen=True)

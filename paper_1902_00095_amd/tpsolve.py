@@ -34,7 +34,8 @@ class _Grid(C.Structure):
 
 class _Props(C.Structure):
     _fields_ = [(k, C.c_double) for k in
-                ("rho0", "p0", "T0", "c_p", "c_T", "mu0", "mu_B", "cv", "rho_r", "c_r", "g")]
+                ("rho0", "p0", "T0", "c_p", "c_T", "mu0", "mu_B", "cv", "rho_r", "c_r", "g",
+                 "api")]
 
 
 class _Well(C.Structure):

@@ -67,6 +67,9 @@ CASES = {
     "line": lambda: synth.make_problem("W2", grid=synth.Grid(17, 1, 1, 1, 1, 1)),
     # heaters (energy sources U (T_h - T)) beside wells, on a perturbed state
     "heat": lambda: _with_heaters(synth.make_problem("W2", grid=synth.Grid(9, 8, 3, 1, 1, 1))),
+    # Bennison heavy-oil viscosity (api 10) with gravity and heaters
+    "bennison": lambda: _with_heaters(synth.make_problem("W2", grid=synth.Grid(9, 7, 4, 1, 1, 1),
+                                                         props=synth.Props(api=10.0, g=9.80665))),
     # diagonal permeability tensor, each component varying cell by cell, with gravity
     "aniso": lambda: _aniso(synth.make_problem("W2", grid=synth.Grid(9, 7, 6, 1, 1.5, 2.0),
                                                props=synth.Props(g=9.80665))),

@@ -128,13 +128,15 @@ def _aniso(p, seed=11):
     return dataclasses.replace(p, K=K3)
 
 
-@pytest.mark.parametrize("g,heater,aniso", [(0.0, False, False), (9.80665, False, False),
-                                            (0.0, True, False), (9.80665, False, True)])
-def test_jacobian_matches_complex_step(g, heater, aniso):
+@pytest.mark.parametrize("g,heater,aniso,api", [(0.0, False, False, 0.0), (9.80665, False, False, 0.0),
+                                                (0.0, True, False, 0.0), (9.80665, False, True, 0.0),
+                                                (9.80665, True, False, 12.0)])
+def test_jacobian_matches_complex_step(g, heater, aniso, api):
     """eq. AXR blocks equal the complex-step derivative of the oracle's own
     residual (upwind decided on real parts = frozen upwind), also with a
-    heater's energy source and with a diagonal permeability tensor."""
-    p = tiny(g=g, dims=(3, 3, 2))
+    heater's energy source, with a diagonal permeability tensor and with the
+    Bennison viscosity."""
+    p = tiny(g=g, dims=(3, 3, 2), props=synth.Props(g=g, api=api))
     if heater:
         p.wells = p.wells + [HEATER]
     if aniso:
@@ -350,3 +352,51 @@ def test_heaters_drive_the_steady_state_to_the_heater_temperature():
     assert q0 > 0 and q1 < 0                        # heat flows from the hot heater to the cold one
     assert abs(q0 + q1) <= 1e-6 * abs(q0)
     assert 320.0 < T.min() and T.max() < 400.0
+
+
+def _bennison_constants():
+    vals = {}
+    for line in open("tests/golden/bennison.txt"):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, v = line.split()
+        vals[k] = float(v)
+    return vals
+
+
+@pytest.mark.parametrize("api,T_F", [(10.0, 100.0), (12.0, 60.0), (8.0, 300.0)])
+def test_bennison_viscosity_from_the_face_flux(api, T_F):
+    """Section 2.1, eq. bennison: with constant density and a linear pressure
+    along a line of cells, the boundary cell's mass residual is the face flux
+    K rho0 dp / (mu dx) (area 1); the viscosity it implies equals the
+    correlation evaluated in log10 form from table bennison's constants, in cp
+    converted to Pa s."""
+    A = _bennison_constants()
+    T = (T_F - 32.0) * 5.0 / 9.0 + 273.15
+    pr = synth.Props(c_p=0.0, c_T=0.0, api=api)
+    grid = synth.Grid(5, 1, 1, 0.5, 1.0, 1.0)
+    p = synth.make_problem("W1", grid=grid, props=pr, kappa=0.0)
+    p.wells = []
+    p.x_k[0::2] = pr.p0 + 1000.0 * np.arange(5)
+    p.x_k[1::2] = T
+    p.x_prev[:] = p.x_k
+    G = oracle.residual(p)
+    mu = 1e-13 * (1.0 / 0.5) * pr.rho0 * 1000.0 / -G[0]
+    log10_cp = A["A1"] * api + A["A2"] + (A["A3"] * api + A["A4"]) * np.log10(T_F)
+    assert abs(mu / (1e-3 * 10.0 ** log10_cp) - 1.0) <= 1e-12
+
+
+def test_bennison_heavy_oil_thins_when_heated():
+    """Heavy oil (api 10) is over 1e4 times more viscous at 60 F than at 300 F
+    by the correlation; the mobility through a face follows."""
+    fl = []
+    for T_F in (60.0, 300.0):
+        T = (T_F - 32.0) * 5.0 / 9.0 + 273.15
+        pr = synth.Props(c_p=0.0, c_T=0.0, api=10.0)
+        p = synth.make_problem("W1", grid=synth.Grid(2, 1, 1, 1.0, 1.0, 1.0), props=pr, kappa=0.0)
+        p.wells = []
+        p.x_k[0::2] = [pr.p0, pr.p0 + 1.0]
+        p.x_k[1::2] = T
+        p.x_prev[:] = p.x_k
+        fl.append(abs(oracle.residual(p)[0]))
+    assert fl[1] / fl[0] > 1e4
