@@ -79,8 +79,15 @@ typedef struct { double rho0, p0, T0, c_p, c_T, mu0, mu_B, cv, rho_r, c_r, g, ap
  * rate*rho(p, T), enthalpy c_v T). rate >= 0 in m^3/s.  Kind 2 is a heater
  * (Section 2.1, source terms): energy source U (T_heater - T) with
  * rate = U >= 0 in W/K and T_inj = T_heater; it adds U to A_TT and to the
- * Schur approximation (eq. Se). */
-typedef struct { int32_t cell; int32_t kind; double rate, T_inj; } tp_well;
+ * Schur approximation (eq. Se).  Kinds 3 and 4 are Peaceman wells (Section
+ * 2.1, well model): an injector (3) or producer (4) whose volumetric rate is
+ * wi (p_bh - p) / mu(T) (injector) or wi (p - p_bh) / mu(T) (producer), mu
+ * the cell fluid's viscosity, wi = 2 pi h K_e / ln(r_e / r_w) > 0 the well
+ * index in m^3 (computed by the caller), clamped to [0, rate] with rate the
+ * maximum rate; mass and enthalpy as kinds 0 and 1.  A producer adds c_v
+ * times its mass rate to the Schur approximation (eq. wellschurapprox).
+ * p_bh and wi are ignored for kinds 0 to 2. */
+typedef struct { int32_t cell; int32_t kind; double rate, T_inj, p_bh, wi; } tp_well;
 #define TP_MAX_WELLS 32
 
 /* Jacobian storage: one CSR pattern (sorted columns, full 5/7-point stencil

@@ -60,7 +60,7 @@ class _Props(C.Structure):
 
 class _Well(C.Structure):
     _fields_ = [("cell", C.c_int32), ("kind", C.c_int32), ("rate", C.c_double),
-                ("T_inj", C.c_double)]
+                ("T_inj", C.c_double), ("p_bh", C.c_double), ("wi", C.c_double)]
 
 
 class _AmgParams(C.Structure):
@@ -127,7 +127,7 @@ def _props(pr):
 def _wells(ws):
     arr = (_Well * max(1, len(ws)))()
     for k, w in enumerate(ws):
-        arr[k] = _Well(w.cell, w.kind, w.rate, w.T_inj)
+        arr[k] = _Well(w.cell, w.kind, w.rate, w.T_inj, w.p_bh, w.wi)
     return arr
 
 

@@ -158,9 +158,20 @@ void or_residual_c(const or_grid* g, const or_props* pr, const double* K,
                 double complex Qm = -w[k].rate * r;
                 Rm -= Qm;
                 Re -= pr->cv * T * Qm;
-            } else {
+            } else if (w[k].kind == 2) {
                 /* heater (Section 2.1, source terms): f_T = U (T_heater - T) */
                 Re -= w[k].rate * (w[k].T_inj - T);
+            } else {
+                /* Peaceman well (Section 2.1): volumetric rate from the pressure
+                 * difference to the bottom hole, the cell fluid's viscosity, and the
+                 * limits 0 (no backflow) and the maximum rate */
+                double complex dpw = w[k].kind == 3 ? w[k].p_bh - p : p - w[k].p_bh;
+                double complex qv = w[k].wi * dpw / mu_c(pr, T);
+                if (creal(qv) >= w[k].rate) qv = w[k].rate;
+                if (creal(qv) <= 0.0) qv = 0.0;
+                double complex Qm = w[k].kind == 3 ? qv * rho_c(pr, p, w[k].T_inj) : -qv * r;
+                Rm -= Qm;
+                Re -= pr->cv * (w[k].kind == 3 ? w[k].T_inj : T) * Qm;
             }
         }
         G[2 * i] = Rm;
@@ -322,10 +333,40 @@ void or_jacobian(const or_grid* g, const or_props* pr, const double* K,
                 ATp[kd] += cv * T * q * pr->c_p * r;
                 ATT[kd] += cv * q * (r + T * pr->c_T * r);
                 S[kd] += cv * q * r;
-            } else {
+            } else if (w[k].kind == 2) {
                 /* heater: d(-U (T_h - T))/dT = U, in A_TT and in eq. Se (U D_heaters) */
                 ATT[kd] += q;
                 S[kd] += q;
+            } else {
+                /* Peaceman well: q_v = wi s (p_bh - p) / mu(T), s = +1 injector, -1
+                 * producer; between its limits dq_v/dp = -s wi / mu and
+                 * dq_v/dT = -q_v dln(mu)/dT, at a limit both vanish */
+                int inj = w[k].kind == 3;
+                double mu = mu_r(pr, T);
+                double qv = w[k].wi * (inj ? w[k].p_bh - p : p - w[k].p_bh) / mu;
+                double dq_dp = (inj ? -w[k].wi : w[k].wi) / mu;
+                double dq_dT = qv * minus_dlnmu_dT(pr, T);
+                if (qv >= q) { qv = q; dq_dp = 0.0; dq_dT = 0.0; }
+                if (qv <= 0.0) { qv = 0.0; dq_dp = 0.0; dq_dT = 0.0; }
+                if (inj) {
+                    /* Q^m = q_v rho(p, T_inj), Q^e = c_v T_inj Q^m; G gets -Q */
+                    double ri = rho_r(pr, p, w[k].T_inj);
+                    double dQ_dp = dq_dp * ri + qv * pr->c_p * ri, dQ_dT = dq_dT * ri;
+                    App[kd] -= dQ_dp;
+                    ApT[kd] -= dQ_dT;
+                    ATp[kd] -= cv * w[k].T_inj * dQ_dp;
+                    ATT[kd] -= cv * w[k].T_inj * dQ_dT;
+                } else {
+                    /* Q^m = -q_v rho(p, T), Q^e = c_v T Q^m; eq. wellschurapprox keeps
+                     * -c_v f_prod with the derivatives of the rate dropped */
+                    double dM_dp = dq_dp * r + qv * pr->c_p * r;   /* d(q_v rho)/dp */
+                    double dM_dT = dq_dT * r + qv * pr->c_T * r;   /* d(q_v rho)/dT */
+                    App[kd] += dM_dp;
+                    ApT[kd] += dM_dT;
+                    ATp[kd] += cv * T * dM_dp;
+                    ATT[kd] += cv * (qv * r + T * dM_dT);
+                    S[kd] += cv * qv * r;
+                }
             }
         }
     }

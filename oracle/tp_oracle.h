@@ -27,7 +27,10 @@ typedef struct { int32_t nx, ny, nz; double dx, dy, dz; } or_grid;
 typedef struct { double rho0, p0, T0, c_p, c_T, mu0, mu_B, cv, rho_r, c_r, g, api; } or_props;
 /* kind 0 injector, 1 producer (rate in m^3/s); kind 2 heater: rate is the
  * heat-transfer coefficient U (W/K) and T_inj the heater temperature */
-typedef struct { int32_t cell, kind; double rate, T_inj; } or_well;
+/* kind 0 injector, 1 producer (rate m^3/s), 2 heater (rate = U, T_inj =
+ * T_heater), 3 / 4 Peaceman injector / producer (Section 2.1: rate
+ * wi (p_bh - p) / mu or wi (p - p_bh) / mu, clamped to [0, rate]). */
+typedef struct { int32_t cell, kind; double rate, T_inj, p_bh, wi; } or_well;
 
 /* ---- Section 2.2: TPFA discretisation ---------------------------------- */
 int32_t or_stencil_nnz(const or_grid* g);

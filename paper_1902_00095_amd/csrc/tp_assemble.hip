@@ -197,10 +197,39 @@ k_assemble(tp_grid g, tp_props pr, WellSet ws, double dt, const double* __restri
             dTp += cv * T * q * pr.c_p * r;
             dTT += cv * q * (r + T * pr.c_T * r);
             dS += cv * q * r;
-        } else {  // heater: energy source U (T_heater - T)
+        } else if (ws.w[w].kind == 2) {  // heater: energy source U (T_heater - T)
             Re -= q * (ws.w[w].T_inj - T);
             dTT += q;
             dS += q;
+        } else {  // Peaceman well: rate from the bottom-hole pressure, within [0, q]
+            const bool inj = ws.w[w].kind == 3;
+            const double mu = mu_of(pr, T);
+            double qv = ws.w[w].wi * (inj ? ws.w[w].p_bh - p : p - ws.w[w].p_bh) / mu;
+            double dq_dp = (inj ? -ws.w[w].wi : ws.w[w].wi) / mu;
+            double dq_dT = -qv * dlnmu_dT(pr, T);
+            if (qv >= q) { qv = q; dq_dp = 0.0; dq_dT = 0.0; }
+            if (qv <= 0.0) { qv = 0.0; dq_dp = 0.0; dq_dT = 0.0; }
+            if (inj) {
+                const double ri = rho_of(pr, p, ws.w[w].T_inj);
+                const double Qm = qv * ri;
+                const double dQp = dq_dp * ri + pr.c_p * Qm, dQT = dq_dT * ri;
+                Rm -= Qm;
+                Re -= cv * ws.w[w].T_inj * Qm;
+                dpp -= dQp;
+                dpT -= dQT;
+                dTp -= cv * ws.w[w].T_inj * dQp;
+                dTT -= cv * ws.w[w].T_inj * dQT;
+            } else {
+                const double M = qv * r;  // produced mass rate
+                const double dMp = dq_dp * r + pr.c_p * M, dMT = dq_dT * r + pr.c_T * M;
+                Rm += M;
+                Re += cv * T * M;
+                dpp += dMp;
+                dpT += dMT;
+                dTp += cv * T * dMp;
+                dTT += cv * (M + T * dMT);
+                dS += cv * M;
+            }
         }
     }
     App[kd] = dpp;
@@ -259,7 +288,8 @@ int assemble(const tp_grid* grid, const tp_props* props, const double* K, bool d
         ws.n = nwells;
         for (int32_t w = 0; w < nwells; ++w) {
             TP_CHECK_ARG(wells[w].cell >= 0 && wells[w].cell < n, "well %d cell %d out of range", w, wells[w].cell);
-            TP_CHECK_ARG(wells[w].kind >= 0 && wells[w].kind <= 2, "well %d kind must be 0, 1 or 2", w);
+            TP_CHECK_ARG(wells[w].kind >= 0 && wells[w].kind <= 4, "well %d kind must be 0 to 4", w);
+            TP_CHECK_ARG(wells[w].kind < 3 || wells[w].wi > 0.0, "well %d: Peaceman well index must be > 0", w);
             TP_CHECK_ARG(wells[w].rate >= 0.0, "well %d rate must be >= 0", w);
             ws.w[w] = wells[w];
         }

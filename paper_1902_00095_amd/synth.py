@@ -72,9 +72,23 @@ class Props:
 @dataclasses.dataclass(frozen=True)
 class Well:
     cell: int
-    kind: int          # 0 injector, 1 producer, 2 heater
-    rate: float        # m^3/s, >= 0 (heater: the heat-transfer coefficient U in W/K)
+    kind: int          # 0 injector, 1 producer, 2 heater, 3 / 4 Peaceman injector / producer
+    rate: float        # m^3/s, >= 0 (heater: the heat-transfer coefficient U in W/K;
+                       # Peaceman wells: the maximum rate)
     T_inj: float       # K (injectors; heater: its temperature)
+    p_bh: float = 0.0  # Pa, bottom-hole pressure (Peaceman wells)
+    wi: float = 0.0    # m^3, well index 2 pi h K_e / ln(r_e / r_w) (Peaceman wells)
+
+
+def peaceman_wi(Kx: float, Ky: float, h: float = 5.0, r_w: float = 0.1,
+                Dx: float = 5.0, Dy: float = 5.0) -> float:
+    """Well index of the Peaceman model for K = diag(Kx, Ky, .) (Section 2.1):
+    2 pi h K_e / ln(r_e / r_w) with K_e = sqrt(Kx Ky) and the equivalent radius
+    r_e of the paper's formula; the paper fixes Dx = Dy = 5 m, h = 5 m and
+    r_w = 0.1 m so that the model does not change under mesh refinement."""
+    a, b = (Ky / Kx) ** 0.5, (Kx / Ky) ** 0.5
+    r_e = 0.14 * (a * Dx * Dx + b * Dy * Dy) ** 0.5 / (0.5 * ((Ky / Kx) ** 0.25 + (Kx / Ky) ** 0.25))
+    return 2.0 * np.pi * h * (Kx * Ky) ** 0.5 / np.log(r_e / r_w)
 
 
 @dataclasses.dataclass

@@ -40,7 +40,7 @@ class _Props(C.Structure):
 
 class _Well(C.Structure):
     _fields_ = [("cell", C.c_int32), ("kind", C.c_int32), ("rate", C.c_double),
-                ("T_inj", C.c_double)]
+                ("T_inj", C.c_double), ("p_bh", C.c_double), ("wi", C.c_double)]
 
 
 class _Jac(C.Structure):
@@ -252,7 +252,7 @@ def assemble_tpfa(grid, props, K, phi, kappa, wells, dt, x_prev, x_k, J=None, G=
         G = torch.empty(2 * n, dtype=torch.float64, device=x_k.device)
     ws = (_Well * max(1, len(wells)))()
     for i, w in enumerate(wells):
-        ws[i] = _Well(w.cell, w.kind, w.rate, w.T_inj)
+        ws[i] = _Well(w.cell, w.kind, w.rate, w.T_inj, w.p_bh, w.wi)
     pr = _Props(*props.as_tuple())
     jc = J.c()
     _check(entry(C.byref(grid_c(grid)), C.byref(pr), _ptr(K), _ptr(phi), _ptr(kappa),

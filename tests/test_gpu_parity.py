@@ -70,6 +70,9 @@ CASES = {
     # Bennison heavy-oil viscosity (api 10) with gravity and heaters
     "bennison": lambda: _with_heaters(synth.make_problem("W2", grid=synth.Grid(9, 7, 4, 1, 1, 1),
                                                          props=synth.Props(api=10.0, g=9.80665))),
+    # Peaceman wells between their limits and at the maximum rate, heavy oil
+    "peaceman": lambda: _with_peaceman(synth.make_problem("W2", grid=synth.Grid(9, 8, 3, 1, 1, 1),
+                                                          props=synth.Props(api=10.0))),
     # diagonal permeability tensor, each component varying cell by cell, with gravity
     "aniso": lambda: _aniso(synth.make_problem("W2", grid=synth.Grid(9, 7, 6, 1, 1.5, 2.0),
                                                props=synth.Props(g=9.80665))),
@@ -78,6 +81,14 @@ CASES = {
 
 def _with_heaters(p):
     p.wells = p.wells + [synth.Well(5, 2, 150.0, 420.0), synth.Well(100, 2, 2.5, 300.0)]
+    return p
+
+
+def _with_peaceman(p):
+    wi = synth.peaceman_wi(1e-13, 1e-13)
+    p0 = p.props.p0
+    p.wells = [synth.Well(5, 3, 1.0, 420.0, p0 + 5e5, wi), synth.Well(100, 4, 1e-6, 0.0, p0 - 5e5, wi),
+               synth.Well(150, 4, 1.0, 0.0, p0 - 5e5, wi), synth.Well(60, 3, 1.0, 420.0, p0 - 5e5, wi)]
     return p
 
 

@@ -400,3 +400,51 @@ def test_bennison_heavy_oil_thins_when_heated():
         p.x_prev[:] = p.x_k
         fl.append(abs(oracle.residual(p)[0]))
     assert fl[1] / fl[0] > 1e4
+
+
+def test_peaceman_equivalent_radius_isotropic_square_block():
+    """Section 2.1's equivalent radius reduces, for isotropic K and a square
+    block, to Peaceman's classical r_e = 0.14 sqrt(2) D = 0.198 D; the well
+    index of an anisotropic K is symmetric in K_x and K_y."""
+    h, rw, D = 5.0, 0.1, 5.0
+    wi = synth.peaceman_wi(3e-13, 3e-13)
+    r_e = rw * np.exp(2 * np.pi * h * 3e-13 / wi)
+    assert abs(r_e / D - 0.198) < 5e-4
+    assert synth.peaceman_wi(3e-11, 3e-13) == pytest.approx(synth.peaceman_wi(3e-13, 3e-11), rel=1e-14)
+    assert synth.peaceman_wi(3e-11, 3e-13) > wi
+
+
+def _peaceman_case(qmax, p_off=5e5):
+    p = tiny(dims=(3, 3, 2), wells=False)
+    wi = synth.peaceman_wi(1e-13, 1e-13)
+    p.wells = [synth.Well(4, 3, qmax, 420.0, p.props.p0 + p_off, wi),
+               synth.Well(10, 4, qmax, 0.0, p.props.p0 - p_off, wi)]
+    return p
+
+
+def test_peaceman_wells_at_their_limits_equal_rate_wells():
+    """A Peaceman well driven far past its maximum rate produces exactly what a
+    constant-rate well of that rate does; one whose bottom-hole pressure equals
+    the cell pressure, or lies on the wrong side of it, produces nothing."""
+    p = _peaceman_case(qmax=1e-4, p_off=1e9)
+    q = dataclasses.replace(p, wells=[synth.Well(4, 0, 1e-4, 420.0), synth.Well(10, 1, 1e-4, 0.0)])
+    assert np.array_equal(oracle.residual(p), oracle.residual(q))
+    none = dataclasses.replace(p, wells=[])
+    for off in (0.0, -1e9):
+        r = dataclasses.replace(p, wells=[synth.Well(4, 3, 1e-4, 420.0, p.x_k[8] + off, 1e-12),
+                                          synth.Well(10, 4, 1e-4, 0.0, p.x_k[20] - off, 1e-12)])
+        assert np.array_equal(oracle.residual(r), oracle.residual(none))
+
+
+@pytest.mark.parametrize("qmax", [1.0, 1e-4])
+def test_peaceman_jacobian_matches_complex_step(qmax):
+    """Peaceman wells between their limits (rate set by the bottom-hole
+    pressure and the viscosity) and at the maximum rate: eq. AXR blocks equal
+    the complex-step derivative of the residual."""
+    p = _peaceman_case(qmax)
+    J = oracle.jacobian(p)
+    Jd = J.dense()
+    Jc = _complex_step_jacobian(p)
+    for r0, c0 in [(0, 0), (0, 1), (1, 0), (1, 1)]:
+        a, b = Jd[r0::2, c0::2], Jc[r0::2, c0::2]
+        assert np.abs(a - b).max() <= 1e-10 * max(np.abs(b).max(), 1e-300), (r0, c0)
