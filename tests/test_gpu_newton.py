@@ -110,3 +110,31 @@ def test_newton_line_search_matches_oracle():
         err = np.linalg.norm(xg[blk::2] - ref) / np.linalg.norm(ref)
         say(f"  block {blk}: rel err {err:.2e}")
         assert err <= 1e-6
+
+
+@pytest.mark.parametrize("case", ["CaseV", "CaseI"])
+def test_newton_paper_physics_matches_oracle(case):
+    """The paper's physics together: Bennison heavy oil, the anisotropic well case
+    (V) with its constant-rate wells replaced by Peaceman wells, or the heater
+    case (I); Newton with line search, no iteration cap of 4.  States as the
+    oracle's exact-Newton reference."""
+    import dataclasses
+    say("newton paper physics", case)
+    g = synth.Grid(16, 16, 1, 20.0 / 16, 20.0 / 16, 1.0)
+    p = synth.make_problem(case, grid=g, props=synth.Props(api=10.0))
+    if case == "CaseV":
+        wi = synth.peaceman_wi(3e-11, 3e-13)
+        p0 = p.props.p0
+        p.wells = [dataclasses.replace(w, kind=3 + w.kind, rate=5e-6, p_bh=p0 + (2e5 if w.kind == 0 else -2e5), wi=wi)
+                   for w in p.wells]
+    xo, its_o, hists, lams_o = oracle.newton_simulate(p, 2, max_newton=20, line_search=True)
+    x, st = solver.simulate(p, solver.SolveConfig(interp_pp=1), solver.NewtonConfig(steps=2, max_newton=20, line_search=True))
+    say(f"  newton per step gpu {st['newton_per_step']} oracle {its_o}, backtracks {st['backtracks']}")
+    assert st["unconverged_steps"] == 0
+    assert all(abs(a - b) <= 1 for a, b in zip(st["newton_per_step"], its_o))
+    xg = x.cpu().numpy()
+    for blk in (0, 1):
+        ref = xo[-1][blk::2]
+        err = np.linalg.norm(xg[blk::2] - ref) / np.linalg.norm(ref)
+        say(f"  block {blk}: rel err {err:.2e}")
+        assert err <= 1e-6
