@@ -184,6 +184,20 @@ def test_schur_equals_ATT_for_constant_properties():
     np.testing.assert_array_equal(J.S, J.TT)
 
 
+def test_schur_equals_ATT_with_peaceman_producer_constant_properties():
+    """eq. wellschurapprox drops the rate's derivatives; with constant rho and
+    mu a Peaceman producer's rate has no temperature derivative, so S~_T
+    still equals A_TT (the producer's c_v f_prod in both)."""
+    pr = synth.Props(c_p=0.0, c_T=0.0, mu_B=0.0)
+    p = tiny(props=pr, wells=False)
+    wi = synth.peaceman_wi(1e-13, 1e-13)
+    p.wells = [synth.Well(10, 4, 1.0, 0.0, pr.p0 - 5e5, wi)]
+    J = oracle.jacobian(p)
+    k = [q for q in range(J.rowptr[10], J.rowptr[11]) if J.col[q] == 10][0]
+    assert J.S[k] != oracle.jacobian(dataclasses.replace(p, wells=[])).S[k]
+    np.testing.assert_allclose(J.S, J.TT, rtol=1e-15, atol=0)
+
+
 def test_schur_approximation_structure():
     """S~_T is a Z-matrix (off-diagonals <= 0); with zero flux it is the
     symmetric conduction + accumulation operator."""
