@@ -1554,59 +1554,62 @@ k_bgj_w(int32_t n, int32_t k, int32_t nb, const double* __restrict__ X, const do
 }
 
 // Y_ij = W_i,j-k (j in the block), else [i not in the block] X_ij + sum_c W_ic X_k+c,j.
-// 64 x 64 tiles; each thread a 4 x 4 micro-tile, all its loads of X before
-// its stores.
+// TS x TS tiles (TS = 16 MT); each thread an MT x MT micro-tile, all its loads
+// of X before its stores.  Every output sums its terms in the same order for
+// any TS, so the tile size changes only the launch shape.
 constexpr int BU_T = 256;
+template <int MT>
 __global__ void __launch_bounds__(BU_T)
 k_bgj_update(int32_t n, int32_t k, int32_t nb, const double* __restrict__ X, const double* __restrict__ W,
              double* __restrict__ Y) {
-    __shared__ double s_W[64][BG_NB + 1];
-    __shared__ double s_B[BG_NB][64 + 2];
+    constexpr int TS = 16 * MT;
+    __shared__ double s_W[TS][BG_NB + 1];
+    __shared__ double s_B[BG_NB][TS + 2];
     const int t = threadIdx.x, tx = t % 16, ty = t / 16;
-    const int32_t j0 = blockIdx.x * 64, i0 = blockIdx.y * 64;
-    for (int e = t; e < 64 * BG_NB; e += BU_T) {
+    const int32_t j0 = blockIdx.x * TS, i0 = blockIdx.y * TS;
+    for (int e = t; e < TS * BG_NB; e += BU_T) {
         const int r = e / BG_NB, c = e % BG_NB;
         const int32_t i = i0 + r;
         s_W[r][c] = (i < n && c < nb) ? W[(int64_t)i * BG_NB + c] : 0.0;
     }
-    for (int e = t; e < BG_NB * 64; e += BU_T) {
-        const int c = e / 64, x = e % 64;
+    for (int e = t; e < BG_NB * TS; e += BU_T) {
+        const int c = e / TS, x = e % TS;
         const int32_t j = j0 + x;
         s_B[c][x] = (j < n && c < nb) ? X[(int64_t)(k + c) * n + j] : 0.0;
     }
-    double acc[4][4];
+    double acc[MT][MT];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int32_t i = i0 + 4 * ty + a;
+    for (int a = 0; a < MT; ++a) {
+        const int32_t i = i0 + MT * ty + a;
         const bool keep = i < n && !(i >= k && i < k + nb);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int32_t j = j0 + 4 * tx + q;
+        for (int q = 0; q < MT; ++q) {
+            const int32_t j = j0 + MT * tx + q;
             acc[a][q] = (keep && j < n && !(j >= k && j < k + nb)) ? X[(int64_t)i * n + j] : 0.0;
         }
     }
     __syncthreads();
 #pragma unroll 8
     for (int c = 0; c < BG_NB; ++c) {
-        double wv[4], bv[4];
+        double wv[MT], bv[MT];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) wv[a] = s_W[4 * ty + a][c];
+        for (int a = 0; a < MT; ++a) wv[a] = s_W[MT * ty + a][c];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) bv[q] = s_B[c][4 * tx + q];
+        for (int q = 0; q < MT; ++q) bv[q] = s_B[c][MT * tx + q];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < MT; ++a)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[a][q] += wv[a] * bv[q];
+            for (int q = 0; q < MT; ++q) acc[a][q] += wv[a] * bv[q];
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int32_t i = i0 + 4 * ty + a;
+    for (int a = 0; a < MT; ++a) {
+        const int32_t i = i0 + MT * ty + a;
         if (i >= n) continue;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int32_t j = j0 + 4 * tx + q;
+        for (int q = 0; q < MT; ++q) {
+            const int32_t j = j0 + MT * tx + q;
             if (j >= n) continue;
-            Y[(int64_t)i * n + j] = (j >= k && j < k + nb) ? s_W[4 * ty + a][j - k] : acc[a][q];
+            Y[(int64_t)i * n + j] = (j >= k && j < k + nb) ? s_W[MT * ty + a][j - k] : acc[a][q];
         }
     }
 }
@@ -1629,13 +1632,18 @@ static void build_coarse_inverse(tp_amg* h, const Csr& A, hipStream_t s) {
     double* Y = steps % 2 == 0 ? W.p : h->cinv.p;
     TP_LAUNCH(k_fill_f64, fill_grid, B, 0, s, nn, X, 0.0);
     TP_LAUNCH(k_csr_to_dense, cdiv(n, B), B, 0, s, n, A.rowptr.p, A.col.p, A.val.p, X);
-    const dim3 g(cdiv(n, 64), cdiv(n, 64));
+    // 32 x 32 tiles while 64 x 64 ones would leave the chip under-filled
+    const bool small_tiles = n <= 2048;
+    const dim3 g = small_tiles ? dim3(cdiv(n, 32), cdiv(n, 32)) : dim3(cdiv(n, 64), cdiv(n, 64));
     for (int32_t k = 0; k < n; k += BG_NB) {
         TP_LAUNCH(k_bgj_block, 1, BK_T, 0, s, n, k, (const double*)X, binv.p, U.p, flags.p);
         const int32_t nb = std::min(BG_NB, n - k);
         TP_LAUNCH(k_bgj_w, cdiv(n, BW_T / BG_NB), BW_T, 0, s, n, k, nb, (const double*)X, (const double*)binv.p,
                   (const double*)U.p, Wk.p, flags.p);
-        TP_LAUNCH(k_bgj_update, g, BU_T, 0, s, n, k, nb, (const double*)X, (const double*)Wk.p, Y);
+        if (small_tiles)
+            TP_LAUNCH(k_bgj_update<2>, g, BU_T, 0, s, n, k, nb, (const double*)X, (const double*)Wk.p, Y);
+        else
+            TP_LAUNCH(k_bgj_update<4>, g, BU_T, 0, s, n, k, nb, (const double*)X, (const double*)Wk.p, Y);
         std::swap(X, Y);
     }
     if (read_i32(flags.p, s) == 0) return;  // no interchange needed: cinv holds the inverse
