@@ -297,10 +297,10 @@ def run_variants(prob, dev, cfg, iters64, ms64):
     # isoHighW, anisoH and anisoW), on this build's physics: linear iterations per Newton
     # iteration over two steps, with the published figures beside them (PETSc/BoomerAMG,
     # serial CPU; the paper's "> 200" entries as None); GMRES to rtol 1e-5, the paper's
-    # tolerance for this study (Section 5).  At 1e-8 the heater cases sit below FP64's
+    # tolerance for this study (Section 4, opening).  At 1e-8 the heater cases sit below FP64's
     # attainable accuracy on the finer grids (|A| |x| / |b| ~ 1e7: even a direct solve
     # leaves 3e-8), so FGMRES would run to its cap there.  The fluid is the paper's heavy
-    # oil (Bennison viscosity, API gravity 10) and Newton takes its line search (Section 5),
+    # oil (Bennison viscosity, API gravity 10) and Newton takes its line search (Section 4, opening),
     # without the workloads' cap of 4 iterations per step
     paper_tab = {"CaseI": {"block": [2.57, 3.23, 2.86, 3.44, 3.71], "cpr": [3.4, 5.38, 9.09, 16.3, 30.7]},
                  "CaseII": {"block": [2.43, 2.43, 2.86, 3.28, 3.71], "cpr": [3.71, 5.71, 9.86, 19.4, 37.4],

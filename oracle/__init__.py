@@ -1,8 +1,8 @@
 """CPU FP64 oracle for the coupled pressure-temperature solve.
 
 TEST INFRASTRUCTURE ONLY.  Plain, slow, single-threaded C (built with gcc,
-``-O2 -ffp-contract=off``, no fast-math) plus the NumPy dense brute-force
-helpers in ``dense.py``.  Only the test-suite, the smoke check and the CPU
+``-O2 -ffp-contract=off``, no fast-math) behind the ctypes wrappers below;
+the dense brute-force checks live in the tests.  Only the test-suite, the smoke check and the CPU
 baseline leg of the benchmark may import this package; the product library
 never does, and it shares no source with the HIP path.
 
@@ -16,7 +16,7 @@ What it computes, and the passage each part follows:
   ILU(0) and the two-stage CPR preconditioner  Section 3 (ILU), Section 3.1,
       Section 4 (ILU(0) as the second stage) -> ilu.c
   3-D convolution smoother network           cnn.c
-  Newton time stepping (sparse direct linear steps)  Section 2.2, Section 5
+  Newton time stepping (sparse direct linear steps)  Section 2.2, Section 4 (its opening: Newton settings)
                                              -> newton_simulate
 """
 from __future__ import annotations
@@ -101,6 +101,7 @@ def lib():
         _lib.or_amg_level_R_nnz.restype = C.c_int32
         _lib.or_ilu0.restype = C.c_int
         _lib.or_gmres_cpr.restype = C.c_int
+        _lib.or_amg_refresh.restype = C.c_int
     return _lib
 
 
@@ -248,14 +249,17 @@ def schur_diag(J):
 
 def line_search_step(G_at, x, dx, g2, alpha=1e-4, max_backtracks=10):
     """Backtracking line search on f(lam) = |G(x + lam dx)|^2 / 2 along a
-    Newton direction (Section 5: Newton's method with line search; the
-    backtracking rule of Dennis and Schnabel, "Numerical Methods for
-    Unconstrained Optimization and Nonlinear Equations", 1983, Section 6.3).
-    For the Newton direction the slope of f at lam = 0 is -|G(x)|^2 = -g2.
-    lam = 1 is tried first; a trial is accepted when
+    Newton direction (Section 4, the Newton settings: Newton's method with
+    line search; the backtracking rule of Dennis and Schnabel, "Numerical
+    Methods for Unconstrained Optimization and Nonlinear Equations", 1983,
+    Section 6.3).  For the Newton direction the slope of f at lam = 0 is
+    -|G(x)|^2 = -g2.  lam = 1 is tried first; a trial is accepted when
     f(lam) <= f(0) - alpha lam g2, else the next lam minimises the quadratic
-    through f(0), f'(0) and f(lam), kept within [lam/10, lam/2].  After
-    `max_backtracks` rejections the last trial is taken.  Returns (lam, the
+    through f(0), f'(0) and f(lam), kept within [lam/10, lam/2].  A trial
+    whose |G| is not finite (a state outside the fluid laws' range) is
+    rejected and halves lam without the quadratic model.  After
+    `max_backtracks` rejections the last trial is taken if its |G| is
+    finite; if it is not, FloatingPointError is raised.  Returns (lam, the
     accepted point, its G, the number of rejected trials)."""
     f0 = 0.5 * g2
     lam, rejected = 1.0, 0
@@ -263,17 +267,23 @@ def line_search_step(G_at, x, dx, g2, alpha=1e-4, max_backtracks=10):
         xt = x + lam * dx
         Gt = G_at(xt)
         f1 = 0.5 * float(Gt @ Gt)
-        if f1 <= f0 - alpha * lam * g2 or rejected == max_backtracks:
+        finite = np.isfinite(f1)
+        if finite and (f1 <= f0 - alpha * lam * g2 or rejected == max_backtracks):
             return lam, xt, Gt, rejected
-        lq = g2 * lam * lam / (2.0 * (f1 - f0 + g2 * lam))
-        lam = min(max(lq, 0.1 * lam), 0.5 * lam)
+        if rejected == max_backtracks:
+            raise FloatingPointError(f"line search: |G| not finite at the last trial step {lam:g}")
+        if finite:
+            lq = g2 * lam * lam / (2.0 * (f1 - f0 + g2 * lam))
+            lam = min(max(lq, 0.1 * lam), 0.5 * lam)
+        else:
+            lam = 0.5 * lam
         rejected += 1
 
 
 def newton_simulate(prob, steps, max_newton=4, rtol_f=1e-8, rtol_dx=1e-8, line_search=False):
     """Backward-Euler time stepping from prob.x_prev with Newton's method on
     G(x) = 0 (Section 2.2: each Newton iteration solves eq. AXR for the
-    increment; Section 5: a step has converged when |G| relative to the
+    increment; Section 4, the Newton settings: a step has converged when |G| relative to the
     step's first |G|, or |dx| relative to |x|, is below 1e-8).  The linear
     step is a sparse direct solve (SuperLU through SciPy), so the result is
     the exact-Newton reference.  With `line_search` each increment is scaled
@@ -368,6 +378,13 @@ class AMG:
         n, a, b = C.c_int32(), C.c_int32(), C.c_int32()
         lib().or_amg_level_sizes(self.h, C.c_int32(l), C.byref(n), C.byref(a), C.byref(b))
         return n.value
+
+    def refresh(self, val):
+        """New level-0 values on the same pattern: C/F splits and every
+        sparsity pattern kept, values recomputed (or_amg_refresh).  Returns
+        the status (0, -1 extended+i, -4 zero pivot)."""
+        self._val = _f64(val).copy()
+        return int(lib().or_amg_refresh(self.h, _p(self._val)))
 
     def vcycle(self, b):
         b = _f64(b)

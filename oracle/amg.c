@@ -550,6 +550,110 @@ int or_amg_setup(int32_t n, const int32_t* rowptr, const int32_t* col,
     return 0;
 }
 
+/* ---- numeric refresh: new level-0 values on a frozen hierarchy ------------
+ * Setup reuse across Newton iterations: the C/F splits and the sparsity
+ * patterns of every P, R and A_l are kept from the setup, and only values
+ * are recomputed from the new level-0 operator, in the setup's order:
+ *   interpolation  direct interpolation restricted to the frozen set P_i of
+ *                  row i: with s = sign(a_ii), sum_all = sum of the
+ *                  off-diagonal a_ik with s a_ik < 0, lump = sum of the
+ *                  other off-diagonal a_ik, sum_p = sum of a_ij over j in
+ *                  P_i with s a_ij < 0 (row order throughout),
+ *                  w_ij = -(alpha a_ij) / (a_ii + lump), alpha = sum_all /
+ *                  sum_p, for j in P_i with s a_ij < 0 and 0 for the other
+ *                  entries of the frozen row (kept as explicit zeros); a row
+ *                  with sum_p = 0 keeps its pattern with zero weights.  When
+ *                  the frozen P_i is the strong C set of the new operator
+ *                  (every such coupling has s a_ij < 0) this is exactly the
+ *                  setup's direct interpolation;
+ *   restriction    R = P^T, or R = Q^T with Q the same refresh applied to A^T
+ *                  on the frozen pattern of Q = R^T (Petrov-Galerkin);
+ *   coarse op.     A_{l+1} = R (A P), each entry summed in ascending inner
+ *                  index; its pattern equals the frozen one;
+ *   coarsest       dense LU with partial pivoting, as at setup.
+ * Direct interpolation only (returns -1 for extended+i); -4 on a zero pivot. */
+static void refresh_interp(const csr_t* A, const int32_t* cf, const int32_t* cmap, csr_t* P)
+{
+    for (int32_t i = 0; i < A->n; ++i) {
+        if (cf[i]) continue;                       /* C row: the unit vector, kept */
+        const int32_t pa = P->rowptr[i], pe = P->rowptr[i + 1];
+        if (pa == pe) continue;
+        double aii = 0.0;
+        for (int32_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k)
+            if (A->col[k] == i) aii = A->val[k];
+        double s = aii < 0.0 ? -1.0 : 1.0;
+        double sum_all = 0.0, lump = 0.0, sum_p = 0.0;
+        for (int32_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) {
+            if (A->col[k] == i) continue;
+            double a = A->val[k];
+            if (s * a < 0.0) sum_all += a;
+            else lump += a;
+        }
+        for (int32_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) {
+            int32_t j = A->col[k];
+            if (j == i || !cf[j] || !(s * A->val[k] < 0.0)) continue;
+            if (in_sorted(P->col + pa, pe - pa, cmap[j]) >= 0) sum_p += A->val[k];
+        }
+        for (int32_t q = pa; q < pe; ++q) P->val[q] = 0.0;
+        if (sum_p == 0.0) continue;
+        double alpha = sum_all / sum_p;
+        double dtil = aii + lump;
+        for (int32_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) {
+            int32_t j = A->col[k];
+            if (j == i || !cf[j] || !(s * A->val[k] < 0.0)) continue;
+            int32_t t = in_sorted(P->col + pa, pe - pa, cmap[j]);
+            if (t >= 0) P->val[pa + t] = -(alpha * A->val[k]) / dtil;
+        }
+    }
+}
+
+int or_amg_refresh(or_amg* h, const double* val)
+{
+    if (h->prm.interp != 0) return -1;
+    memcpy(h->A[0].val, val, sizeof(double) * (size_t)h->A[0].nnz);
+    for (int32_t l = 0; l < h->nlev; ++l) {
+        csr_t* A = &h->A[l];
+        l1_dinv(A, h->dinv[l]);
+        if (l == h->nlev - 1) break;
+        int32_t* cmap = malloc(sizeof(int32_t) * (size_t)(A->n > 0 ? A->n : 1));
+        int32_t nc = 0;
+        for (int32_t i = 0; i < A->n; ++i) cmap[i] = h->cf[l][i] ? nc++ : -1;
+        refresh_interp(A, h->cf[l], cmap, &h->P[l]);
+        csr_t T;
+        if (h->prm.restriction == 1) {
+            csr_t At, Q;
+            transpose(A, &At);
+            transpose(&h->R[l], &Q);               /* the frozen pattern of Q = R^T */
+            refresh_interp(&At, h->cf[l], cmap, &Q);
+            transpose(&Q, &T);
+            csr_free(&At); csr_free(&Q);
+        } else {
+            transpose(&h->P[l], &T);
+        }
+        memcpy(h->R[l].val, T.val, sizeof(double) * (size_t)T.nnz);
+        csr_free(&T);
+        csr_t AP, Ac;
+        spgemm(A, &h->P[l], &AP);
+        spgemm(&h->R[l], &AP, &Ac);
+        csr_t* An = &h->A[l + 1];
+        if (Ac.nnz != An->nnz || memcmp(Ac.col, An->col, sizeof(int32_t) * (size_t)Ac.nnz) != 0) {
+            csr_free(&AP); csr_free(&Ac); free(cmap);
+            return -1;                                 /* cannot happen: patterns are frozen */
+        }
+        memcpy(An->val, Ac.val, sizeof(double) * (size_t)Ac.nnz);
+        csr_free(&AP); csr_free(&Ac); free(cmap);
+    }
+    if (!h->prm.skip_lu) {
+        csr_t* A = &h->A[h->nlev - 1];
+        memset(h->lu, 0, sizeof(double) * (size_t)A->n * (size_t)A->n);
+        for (int32_t i = 0; i < A->n; ++i)
+            for (int32_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k)
+                h->lu[(size_t)i * A->n + A->col[k]] = A->val[k];
+        if (dense_lu(A->n, h->lu, h->piv) != 0) return -4;
+    }
+    return 0;
+}
+
 void or_amg_free(or_amg* h)
 {
     if (!h) return;

@@ -134,12 +134,19 @@ def solve(J, G, cfg: SolveConfig, history=False):
 @dataclasses.dataclass
 class NewtonConfig:
     """Backward-Euler time stepping with Newton's method on G(x) = 0 (Section
-    2.2: one Jacobian solve per Newton iteration; Section 5: a Newton
+    2.2: one Jacobian solve per Newton iteration; Section 4, opening: a Newton
     iteration has converged when the function norm relative to the step's
     first one, or the step norm relative to the iterate's, is below 1e-8).
-    reuse: build both hierarchies at a step's first Newton iteration only and
+    reuse: hierarchy reuse across Newton iterations.  "fine" (or True):
+    build both hierarchies at a step's first Newton iteration only and
     refresh their finest level at the later ones (coarse levels lagged).
-    line_search: scale each increment by backtracking on |G|^2 / 2 (Section 5:
+    "numeric": build at a step's first iteration, then refresh every level
+    numerically on the kept C/F splits and patterns (amg_refresh).
+    "numeric_run": build once for the run and refresh numerically at every
+    later Newton iteration, rebuilding when a solve takes more than
+    `rebuild_ratio` times the FGMRES iterations of the first solve after the
+    last build.
+    line_search: scale each increment by backtracking on |G|^2 / 2 (Section 4, opening:
     Newton with line search; Dennis and Schnabel's rule: try the full step,
     accept when the sufficient-decrease test with alpha = 1e-4 holds, else
     minimise the quadratic model within [lam/10, lam/2], at most 10 times)."""
@@ -147,8 +154,9 @@ class NewtonConfig:
     max_newton: int = 4
     rtol_f: float = 1e-8
     rtol_dx: float = 1e-8
-    reuse: bool = False
+    reuse: bool | str = False
     line_search: bool = False
+    rebuild_ratio: float = 1.5
 
 
 def _schur_values(J, cfg):
@@ -160,10 +168,14 @@ def _backtrack(prob, dev, J, G, x, dx, gn, alpha=1e-4, max_backtracks=10):
     Newton direction f(lam) = |G(x + lam dx)|^2 / 2 has slope -gn^2 at 0.  The
     full step is tried first; a trial passes when f(lam) <= f(0) - alpha lam
     gn^2; otherwise the next trial is the minimiser of the quadratic matching
-    f(0), f'(0) and f(lam), clamped to [lam/10, lam/2]; after max_backtracks
-    failures the last trial stands.  J and G are left assembled at the
-    accepted point, which dev["x_k"] holds.  Returns (lam, rejected trials,
-    |G| there)."""
+    f(0), f'(0) and f(lam), clamped to [lam/10, lam/2].  A trial whose |G| is
+    not finite (a state outside the fluid laws' range) halves lam without the
+    quadratic model.  After max_backtracks failures the last trial stands if
+    its |G| is finite; otherwise FloatingPointError is raised.  J and G are
+    left assembled at the accepted point, which dev["x_k"] holds.  Returns
+    (lam, rejected trials, |G| there)."""
+    import math
+
     import torch
     g2 = gn * gn
     lam, rejected = 1.0, 0
@@ -171,9 +183,15 @@ def _backtrack(prob, dev, J, G, x, dx, gn, alpha=1e-4, max_backtracks=10):
         dev["x_k"] = torch.add(x, dx, alpha=lam)
         assemble(prob, dev, J, G)
         gt = float(torch.linalg.vector_norm(G))
-        if 0.5 * gt * gt <= 0.5 * g2 - alpha * lam * g2 or rejected == max_backtracks:
+        finite = math.isfinite(gt)
+        if finite and (0.5 * gt * gt <= 0.5 * g2 - alpha * lam * g2 or rejected == max_backtracks):
             return lam, rejected, gt
-        lam = min(max(g2 * lam * lam / (2.0 * (0.5 * gt * gt - 0.5 * g2 + g2 * lam)), 0.1 * lam), 0.5 * lam)
+        if rejected == max_backtracks:
+            raise FloatingPointError(f"line search: |G| not finite at the last trial step {lam:g}")
+        if finite:
+            lam = min(max(g2 * lam * lam / (2.0 * (0.5 * gt * gt - 0.5 * g2 + g2 * lam)), 0.1 * lam), 0.5 * lam)
+        else:
+            lam = 0.5 * lam
         rejected += 1
 
 
@@ -212,7 +230,12 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None):
                 a_S.close()
 
     # S_diag has a pattern of its own; CPR refactorises its ILU(0) in place
-    reusable = ncfg.reuse and (cfg.method == "cpr" or cfg.schur in ("T", "ATT"))
+    mode = {False: None, None: None, True: "fine"}.get(ncfg.reuse, ncfg.reuse)
+    if mode not in (None, "fine", "numeric", "numeric_run"):
+        raise ValueError(f"unknown reuse mode {ncfg.reuse!r}")
+    reusable = mode is not None and (cfg.method == "cpr" or cfg.schur in ("T", "ATT"))
+    refresh = (lambda h, v: h.refresh_fine(v)) if mode == "fine" else (lambda h, v: h.refresh(v))
+    refreshes, base_its, rebuild = 0, None, False
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     try:
@@ -235,12 +258,14 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None):
                     break
                 torch.cuda.synchronize()
                 ts = time.perf_counter()
-                if hier is not None and reusable and k > 0:
-                    hier[0].refresh_fine(J.pp)
+                built = False
+                if hier is not None and reusable and (k > 0 or mode == "numeric_run") and not rebuild:
+                    refresh(hier[0], J.pp)
                     if cfg.method == "cpr":
                         hier[1].refactor(J)
                     else:
-                        hier[1].refresh_fine(_schur_values(J, cfg))
+                        refresh(hier[1], _schur_values(J, cfg))
+                    refreshes += 1
                 else:
                     close(hier)
                     hier = None
@@ -248,11 +273,17 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None):
                     if cfg.method == "cpr":
                         ilu = hier[1]
                     builds += 1
+                    built, rebuild = True, False
                     if net is not None:
                         hier[1].attach(net, prob.grid)
                 dx, st = tps.fgmres_solve(J, hier[2], -G, rtol=cfg.rtol, restart=cfg.restart, maxit=cfg.maxit)
                 torch.cuda.synchronize()
                 solve_s += time.perf_counter() - ts
+                if mode == "numeric_run":
+                    if built:
+                        base_its = st["iters"]
+                    elif st["iters"] > ncfg.rebuild_ratio * base_its:
+                        rebuild = True
                 if not reusable:
                     close(hier)
                     hier = None
@@ -282,6 +313,6 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None):
     total = time.perf_counter() - t0
     return x, dict(steps=ncfg.steps, newton_iters=newton, linear_iters=lin, solves=solves,
                    backtracks=backtracks, step_lengths=step_lengths,
-                   hierarchy_builds=builds, unconverged_steps=unconverged, newton_per_step=per_step,
+                   hierarchy_builds=builds, hierarchy_refreshes=refreshes, unconverged_steps=unconverged, newton_per_step=per_step,
                    linear_per_newton=lin / max(newton, 1), total_s=total,
                    ms_per_solve=1e3 * solve_s / max(solves, 1))

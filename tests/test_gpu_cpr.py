@@ -16,6 +16,7 @@ import scipy.sparse as sp
 import oracle
 from paper_1902_00095_amd import solver, synth
 from paper_1902_00095_amd import tpsolve as tps
+from parity_bars import history_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -220,8 +221,20 @@ def test_fgmres_cpr_matches_oracle(case):
     assert st["converged"] and st["rel_true"] <= rtol
     assert io["converged"]
     assert abs(st["iters"] - io["iters"]) <= 1
-    k = min(10, len(st["history"]), len(io["history"]))
-    np.testing.assert_allclose(st["history"][:k], io["history"][:k], rtol=2e-5)
+    # the ILU(0) factors are bit-identical; the pressure V-cycle is the one
+    # rounding difference: estimates within 1e-8 relative, or (one-level
+    # A_pp hierarchy, the whole block solved by the dense inverse) within
+    # u kappa(A_pp) h_0 (derivation in test_gpu_parity.history_bound)
+    h_g, h_o = st["history"], io["history"]
+    k = min(11, len(h_g), len(h_o))
+    bound = history_bound(Jo, (hand[0].nlev,), h_o[:k], blocks=("pp",))
+    say(f"  history max |d|/bound {np.max(np.abs(h_g[:k] - h_o[:k]) / bound):.2e}")
+    assert np.all(np.abs(h_g[:k] - h_o[:k]) <= bound)
+    x = np_(dx)
+    for blk in (0, 1):
+        d_go = np.linalg.norm(x[blk::2] - xo[blk::2]) / np.linalg.norm(xo[blk::2])
+        say(f"  block {blk}: |gpu-oracle|/|oracle| {d_go:.2e}")
+        assert d_go <= 1e-8
     for h in reversed(hand):
         h.close()
 

@@ -25,12 +25,16 @@ def _init():
 
 @pytest.mark.parametrize("storage,reuse,method,interp_pp", [
     (0, False, "block", None), (1, False, "block", None), (0, True, "block", None), (1, True, "block", None),
-    (0, False, "cpr", None), (0, True, "cpr", None), (1, False, "block", 1), (1, True, "block", 1)])
+    (0, False, "cpr", None), (0, True, "cpr", None), (1, False, "block", 1), (1, True, "block", 1),
+    (0, "numeric", "block", None), (1, "numeric", "block", None), (1, "numeric_run", "block", None),
+    (0, "numeric", "cpr", None)])
 def test_newton_time_steps_match_oracle(storage, reuse, method, interp_pp):
     """With hierarchy reuse the later Newton iterations of a step run on
-    hierarchies refreshed on the finest level only; the Newton root, and so
-    the states, must not change.  CPR keeps one ILU(0) handle for the run and
-    refactorises it for every Jacobian."""
+    refreshed hierarchies: the finest level only ("fine"), or every level
+    recomputed on the kept splits and patterns ("numeric"; "numeric_run" keeps
+    them for the whole run); the Newton root, and so the states, must not
+    change.  CPR keeps one ILU(0) handle for the run and refactorises it for
+    every Jacobian."""
     say("newton", storage, reuse, method, interp_pp)
     p = synth.make_problem("W5", grid=synth.Grid(16, 16, 8, 1.0, 1.0, 1.0))
     steps = 2
@@ -38,8 +42,11 @@ def test_newton_time_steps_match_oracle(storage, reuse, method, interp_pp):
     x, st = solver.simulate(p, solver.SolveConfig(storage=storage, amg=tps.AmgParams(coarse_max=200),
                                                   method=method, interp_pp=interp_pp),
                             solver.NewtonConfig(steps=steps, reuse=reuse))
-    if reuse:
+    assert st["hierarchy_builds"] + st["hierarchy_refreshes"] == st["solves"]
+    if reuse in (True, "numeric"):
         assert st["hierarchy_builds"] == steps < st["solves"]
+    elif reuse == "numeric_run":
+        assert 1 <= st["hierarchy_builds"] < st["solves"]
     xg = x.cpu().numpy()
     say(f"  newton per step gpu {st['newton_per_step']} oracle {its_o}, linear/newton {st['linear_per_newton']:.1f}")
     assert st["unconverged_steps"] == 0
@@ -85,7 +92,7 @@ def test_refresh_fine_in_place():
 
 
 def test_newton_line_search_matches_oracle():
-    """Newton with line search (Section 5) on high-rate wells, where the first
+    """Newton with line search (Section 4, opening) on high-rate wells, where the first
     increment of the step is damped: the GPU takes the oracle's step lengths
     and reaches its state."""
     import dataclasses

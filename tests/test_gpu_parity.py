@@ -3,11 +3,16 @@
 Bars: integer outputs (C/F splits, sparsity patterns) bit-exact; assembly
 within 1e-12 relative (the device exp() may differ from glibc's by an ulp);
 AMG setup values within 1e-13 relative on identical inputs (the setup runs
-one fixed operation order without contraction on both sides); V-cycle and
-preconditioner within 1e-10 relative (row sums in a different order, and
-the coarsest level applied as an explicit inverse instead of triangular
-solves); Krylov solves to a true relative residual <= 1e-8 and solution
-error <= 1e-6 per block against a tightly converged oracle solution.
+one fixed operation order without contraction on both sides; measured
+bit-identical at full size); V-cycle and preconditioner within 1e-10
+relative on the small grids and 1e-12 at production size (row sums in a
+different order, and the coarsest level applied as an explicit inverse
+instead of triangular solves); Krylov solves at the same rtol: iteration
+count +-1, residual estimates within 1e-8 relative over the first ten
+iterations (or the derived bound of a one-level hierarchy,
+parity_bars.history_bound), solutions within 1e-8 relative L2 per block;
+and, at a stated rtol per grid, a solution error <= 1e-6 per block against
+a direct solve for both the GPU and the oracle.
 """
 import sys
 
@@ -17,6 +22,7 @@ import pytest
 import oracle
 from paper_1902_00095_amd import solver, synth
 from paper_1902_00095_amd import tpsolve as tps
+from parity_bars import history_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -248,19 +254,23 @@ def test_precond_matches_oracle(variant):
 
 @pytest.mark.parametrize("case", ["W1", "W2s", "W2g", "W4s"])
 def test_fgmres_end_to_end(case):
-    """GPU assembly + setup + FGMRES vs the oracle at the same rtol: same
-    iteration count (+-1), residual histories agree, true residual <= rtol,
-    solutions agree, and the GPU solution is as close to a tightly converged
-    reference as the oracle's own.  The interleaved FP64 Jacobian has a
-    2-norm condition number near 1e17 (mass rows ~1e-7, energy rows ~1e4),
-    so a relative residual bound leaves the pressure block loosely
-    determined; the error against the reference is reported per block."""
+    """GPU assembly + setup + FGMRES vs the oracle at the same rtol: the same
+    iteration count (+-1), residual estimates that agree iteration by
+    iteration over the first ten (1e-8 relative, or the derived bound of a
+    one-level hierarchy, `history_bound`), true residual <= rtol, and
+    solutions that agree to 1e-8 relative L2 per block (measured 1e-11 ..
+    1e-13).  The error of both against a tightly converged solution is
+    printed: at rtol 1e-10 the pressure block of these layered grids is
+    only loosely fixed by the interleaved residual norm (the energy rows
+    dominate it), which is why parity is stated GPU against oracle and the
+    error bar of the method description has its own test
+    (`test_solution_error_within_1e_6`)."""
     say("fgmres", case)
     rtol = 1e-10
     p = CASES[case]()
     d = solver.to_device(p)
     J, G = solver.assemble(p, d)
-    dx, st, _ = solver.solve(J, G, solver.SolveConfig(rtol=rtol), history=True)
+    dx, st, hs = solver.solve(J, G, solver.SolveConfig(rtol=rtol), history=True)
     Jo = oracle.jacobian(p)
     bo = -oracle.residual(p)
     ao_pp = o_amg(Jo.n, Jo.rowptr, Jo.col, Jo.pp, tps.AmgParams(restriction=0))
@@ -271,19 +281,78 @@ def test_fgmres_end_to_end(case):
     assert st["converged"] and st["rel_true"] <= rtol
     assert abs(st["iters"] - io["iters"]) <= 1
     h_g, h_o = st["history"], io["history"]
-    k = min(10, len(h_g), len(h_o))
-    # the coarsest-level solves differ in rounding order (Gauss-Jordan inverse
-    # against LU solves), amplified by the block's conditioning
-    np.testing.assert_allclose(h_g[:k], h_o[:k], rtol=2e-5)
+    k = min(11, len(h_g), len(h_o))
+    bound = history_bound(Jo, (hs[0].nlev, hs[1].nlev), h_o[:k])
+    diff = np.abs(h_g[:k] - h_o[:k])
+    say(f"  history: max |d|/h_o {np.max(diff / h_o[:k]):.2e}, max |d|/bound {np.max(diff / bound):.2e}")
+    assert np.all(diff <= bound)
     x = np_(dx)
     for blk in (0, 1):
         nrm = np.linalg.norm(xt[blk::2])
         e_g = np.linalg.norm(x[blk::2] - xt[blk::2]) / nrm
         e_o = np.linalg.norm(xo[blk::2] - xt[blk::2]) / nrm
-        d_go = np.linalg.norm(x[blk::2] - xo[blk::2]) / nrm
-        say(f"  block {blk}: err gpu {e_g:.2e} oracle {e_o:.2e} |gpu-oracle| {d_go:.2e}")
-        assert e_g <= 2.0 * e_o + 1e-9
-        assert d_go <= max(1e-6, 2.0 * e_o)
+        d_go = np.linalg.norm(x[blk::2] - xo[blk::2]) / np.linalg.norm(xo[blk::2])
+        say(f"  block {blk}: err gpu {e_g:.2e} oracle {e_o:.2e} |gpu-oracle|/|oracle| {d_go:.2e}")
+        assert d_go <= 1e-8
+    for h in reversed(hs):
+        h.close()
+
+
+def _direct_reference(Jo, bo, refine=3):
+    """The solution of J x = b by a sparse direct solve of the row-equilibrated
+    system (each row scaled to unit 2-norm: the mass rows are ~1e-7, the
+    energy rows ~1e4, and without the scaling a backward-stable solve leaves
+    the pressure block undetermined at the 1e-5 level), followed by
+    `refine` steps of iterative refinement.  SciPy's SuperLU; tiny and
+    small grids only."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    A = oracle.sparse_interleaved(Jo).tocsr()
+    dsc = 1.0 / np.sqrt(np.asarray(A.multiply(A).sum(axis=1)).ravel())
+    As = (sp.diags(dsc) @ A).tocsc()
+    lu = spla.splu(As)
+    x = lu.solve(dsc * bo)
+    for _ in range(refine):
+        x = x + lu.solve(dsc * bo - As @ x)
+    return x
+
+
+# the rtol at which the solution error of both solvers falls below the method
+# description's 1e-6 per block: the headline 1e-8 on the 2-D grid (W1, the
+# 32x32 workload) and on a gravity grid; 1e-10 on the channelised grid; 1e-14
+# on the layered grid, whose pressure block the interleaved residual norm
+# (dominated by the energy rows) constrains least
+NS_RTOL = [("W1", 1e-8), ("W2g", 1e-8), ("W4s", 1e-10), ("W2s", 1e-14)]
+
+
+@pytest.mark.parametrize("case,rtol", NS_RTOL)
+def test_solution_error_within_1e_6(case, rtol):
+    """The floating-point bar of the method description: true relative
+    residual <= rtol and a relative L2 error <= 1e-6 per block (dp, dT)
+    against a direct solve, for the GPU and for the oracle, at the stated
+    rtol."""
+    say("NS error bar", case, rtol)
+    p = CASES[case]()
+    d = solver.to_device(p)
+    J, G = solver.assemble(p, d)
+    dx, st, hs = solver.solve(J, G, solver.SolveConfig(rtol=rtol, maxit=3000))
+    Jo = oracle.jacobian(p)
+    bo = -oracle.residual(p)
+    ao_pp = o_amg(Jo.n, Jo.rowptr, Jo.col, Jo.pp, tps.AmgParams(restriction=0))
+    ao_S = o_amg(Jo.n, Jo.rowptr, Jo.col, Jo.S, tps.AmgParams(restriction=1))
+    xo, io = oracle.gmres(Jo, ao_pp, ao_S, bo, rtol=rtol, maxit=3000)
+    xd = _direct_reference(Jo, bo)
+    x = np_(dx)
+    say(f"  gpu its {st['iters']} rel {st['rel_true']:.2e}; oracle its {io['iters']} rel {io['rel_true']:.2e}")
+    assert st["converged"] and st["rel_true"] <= rtol and io["converged"]
+    for blk in (0, 1):
+        nrm = np.linalg.norm(xd[blk::2])
+        e_g = np.linalg.norm(x[blk::2] - xd[blk::2]) / nrm
+        e_o = np.linalg.norm(xo[blk::2] - xd[blk::2]) / nrm
+        say(f"  block {blk}: err gpu {e_g:.2e} oracle {e_o:.2e}")
+        assert e_g <= 1e-6 and e_o <= 1e-6
+    for h in reversed(hs):
+        h.close()
 
 
 def test_fgmres_rtol_1e8_and_determinism():
@@ -342,39 +411,38 @@ def test_graph_replay_matches_eager(variant, storage):
     del a_pp, a_S
 
 
-@pytest.mark.parametrize("storage,extra", [(1, 3), (2, 5)])
-def test_mixed_precision_solve(storage, extra):
+@pytest.mark.parametrize("storage", [1, 2])
+@pytest.mark.parametrize("case,rtol", NS_RTOL)
+def test_mixed_precision_solve(case, rtol, storage):
     """A reduced-precision hierarchy (FP32, or FP32 with BF16 off-diagonal
-    operator entries) inside the FP64 outer loop reaches the same FP64 true
-    residual within a few more iterations (BF16 perturbs the operator by up
-    to 2^-9 relative, FGMRES absorbs it), and its solution error against a
-    tight oracle reference is of the order of the FP64 path's.  (The error
-    of any iterate with true residual <= rtol spreads over an order of
-    magnitude here: the interleaved Jacobian's condition number is ~1e17,
-    so the pressure block is only loosely fixed by a residual bound; at
-    rtol 1e-13 the FP32 path's error was even the smaller one.)"""
-    say("mixed fgmres", storage)
-    p = CASES["W2s"]()
+    operator entries) inside the FP64 outer loop: at the rtol where the FP64
+    path meets the 1e-6 error bar (NS_RTOL) it reaches the same FP64 true
+    residual and meets the same bar: relative L2 error <= 1e-6 per block
+    against the direct solution.  FP32 storage takes at most 3 iterations
+    more than FP64; BF16 off-diagonals perturb every entry by up to 2^-9
+    relative, which flexible GMRES absorbs at the price of more iterations
+    the tighter the rtol (W4s at 1e-10: 28 against 21), bounded here by
+    1.5 times the FP64 count plus 2."""
+    say("mixed fgmres", case, rtol, storage)
+    p = CASES[case]()
     d = solver.to_device(p)
     J, G = solver.assemble(p, d)
-    rtol = 1e-12
-    x64, s64, _ = solver.solve(J, G, solver.SolveConfig(rtol=rtol))
-    x32, s32, _ = solver.solve(J, G, solver.SolveConfig(rtol=rtol, storage=storage))
-    say(f"  fp64 its {s64['iters']}, storage {storage} its {s32['iters']}")
+    x64, s64, h64 = solver.solve(J, G, solver.SolveConfig(rtol=rtol, maxit=3000))
+    x32, s32, h32 = solver.solve(J, G, solver.SolveConfig(rtol=rtol, maxit=3000, storage=storage))
+    say(f"  fp64 its {s64['iters']}, storage {storage} its {s32['iters']} rel {s32['rel_true']:.2e}")
     assert s64["converged"] and s32["converged"] and s32["rel_true"] <= rtol
-    assert s32["iters"] <= s64["iters"] + extra
+    assert s32["iters"] <= (s64["iters"] + 3 if storage == 1 else 1.5 * s64["iters"] + 2)
     Jo = oracle.jacobian(p)
-    bo = -oracle.residual(p)
-    ao_pp = oracle.AMG(Jo.n, Jo.rowptr, Jo.col, Jo.pp, coarse_max=SMALL)
-    ao_S = oracle.AMG(Jo.n, Jo.rowptr, Jo.col, Jo.S, restriction=1, coarse_max=SMALL)
-    xt, _ = oracle.gmres(Jo, ao_pp, ao_S, bo, rtol=1e-14, maxit=3000)
+    xd = _direct_reference(Jo, -oracle.residual(p))
     a, b = np_(x32), np_(x64)
     for blk in (0, 1):
-        nrm = np.linalg.norm(xt[blk::2])
-        e32 = np.linalg.norm(a[blk::2] - xt[blk::2]) / nrm
-        e64 = np.linalg.norm(b[blk::2] - xt[blk::2]) / nrm
-        say(f"  block {blk}: err fp32-hierarchy {e32:.2e}, fp64 {e64:.2e}")
-        assert e32 <= 20.0 * e64 + 1e-9
+        nrm = np.linalg.norm(xd[blk::2])
+        e32 = np.linalg.norm(a[blk::2] - xd[blk::2]) / nrm
+        e64 = np.linalg.norm(b[blk::2] - xd[blk::2]) / nrm
+        say(f"  block {blk}: err storage-{storage} hierarchy {e32:.2e}, fp64 {e64:.2e}")
+        assert e32 <= 1e-6 and e64 <= 1e-6
+    for h in list(reversed(h32)) + list(reversed(h64)):
+        h.close()
 
 
 def test_poisson_factor_below_0_2_in_3d():
@@ -421,7 +489,9 @@ def test_poisson_factor_below_0_2_in_2d_with_extended_interpolation():
 @pytest.mark.parametrize("case", ["W1", "W2s", "W2g"])
 def test_fgmres_extended_interpolation(case):
     """Both hierarchies with extended+i interpolation: the GPU solve takes
-    the oracle's iteration count (+-1) to the same true residual."""
+    the oracle's iteration count (+-1) to the same true residual, with the
+    residual estimates and the solution held to the bars of
+    test_fgmres_end_to_end."""
     say("fgmres ext+i", case)
     rtol = 1e-10
     p = CASES[case]()
@@ -437,8 +507,12 @@ def test_fgmres_extended_interpolation(case):
     say(f"  gpu its {st['iters']} rel {st['rel_true']:.2e}; oracle its {io['iters']}")
     assert st["converged"] and st["rel_true"] <= rtol
     assert abs(st["iters"] - io["iters"]) <= 1
-    k = min(10, len(st["history"]), len(io["history"]))
-    np.testing.assert_allclose(st["history"][:k], io["history"][:k], rtol=2e-5)
+    h_g, h_o = st["history"], io["history"]
+    k = min(11, len(h_g), len(h_o))
+    assert np.all(np.abs(h_g[:k] - h_o[:k]) <= history_bound(Jo, (hs[0].nlev, hs[1].nlev), h_o[:k]))
+    x = np_(dx)
+    for blk in (0, 1):
+        assert np.linalg.norm(x[blk::2] - xo[blk::2]) <= 1e-8 * np.linalg.norm(xo[blk::2])
     for h in reversed(hs):
         h.close()
 
@@ -491,21 +565,99 @@ def test_error_paths():
     del bad
 
 
-def test_full_size_w2_solve_and_coarsening():
-    """The benchmark workload (64x64x32): GPU solve to 1e-8; the oracle's
-    coarsening of the GPU-assembled operators reproduces the GPU splits."""
+def _compare_hierarchies(hg, ho, tag):
+    """Every level: size, A pattern bit-exact and values within 1e-13; above
+    the coarsest also the C/F split, the P and R patterns bit-exact and
+    their values within 1e-13."""
+    assert hg.nlev == ho.nlev, tag
+    for l in range(ho.nlev):
+        Lo, Lg = ho.level(l), hg.level(l)
+        assert Lg["n"] == Lo["n"], (tag, l)
+        assert np.array_equal(np_(Lg["A_rowptr"]), Lo["A_rowptr"]), (tag, l)
+        assert np.array_equal(np_(Lg["A_col"]), Lo["A_col"]), (tag, l)
+        assert relmax(np_(Lg["A_val"]), Lo["A_val"]) <= 1e-13, (tag, l)
+        if l < ho.nlev - 1:
+            assert np.array_equal(np_(Lg["cf"]), Lo["cf"]), (tag, l)
+            for k in ("P_rowptr", "P_col", "R_rowptr", "R_col"):
+                assert np.array_equal(np_(Lg[k]), Lo[k]), (tag, l, k)
+            assert relmax(np_(Lg["P_val"]), Lo["P_val"]) <= 1e-13, (tag, l)
+            assert relmax(np_(Lg["R_val"]), Lo["R_val"]) <= 1e-13, (tag, l)
+        say(f"  {tag} level {l}: n={Lo['n']} format {hg.level_format(l)} matches")
+
+
+def test_full_size_w2_end_to_end():
+    """The 64x64x32 layered workload (262,144 unknowns) at full size against
+    the oracle.  (1) GPU assembly: G and all five Jacobian blocks within
+    1e-12.  (2) Both hierarchies built from the oracle's Jacobian: every
+    level's C/F split and patterns bit-exact, values within 1e-13.  (3) The
+    solve to rtol 1e-8 from the same Jacobian: iteration count +-1, residual
+    estimates within 1e-8 relative over the first ten iterations, solutions
+    within 1e-8 per block.  (4) The solve from the GPU-assembled Jacobian
+    converges to 1e-8 in the same count."""
     say("full W2")
     p = synth.make_problem("W2")
     d = solver.to_device(p)
     J, G = solver.assemble(p, d)
-    dx, st, (a_pp, a_S, M) = solver.solve(J, G, solver.SolveConfig(rtol=1e-8))
-    say(f"  W2 its {st['iters']} rel {st['rel_true']:.2e} levels {a_pp.nlev}/{a_S.nlev}")
-    assert st["converged"] and st["rel_true"] <= 1e-8
-    # sampled assembly rows against the oracle
-    Go = oracle.residual(p)
-    assert relmax(np_(G), Go) <= 1e-12
-    for h in (a_pp, a_S):
-        L = h.level(0)
-        ho = oracle.AMG(L["n"], np_(L["A_rowptr"]), np_(L["A_col"]), np_(L["A_val"]),
-                        max_levels=2, coarse_max=0, skip_lu=True)
-        assert np.array_equal(ho.level(0)["cf"], np_(L["cf"]))
+    Jo = oracle.jacobian(p)
+    bo = -oracle.residual(p)
+    assert np.array_equal(np_(J.rowptr), Jo.rowptr) and np.array_equal(np_(J.col), Jo.col)
+    assert relmax(np_(G), -bo) <= 1e-12
+    for k in ("pp", "pT", "Tp", "TT", "S"):
+        assert relmax(np_(getattr(J, k)), getattr(Jo, k)) <= 1e-12, k
+    rtol = 1e-8
+    cfg = solver.SolveConfig(rtol=rtol)
+    dx_a, st_a, hs_a = solver.solve(J, G, cfg)
+    for h in reversed(hs_a):
+        h.close()
+    Jd = tps.Jacobian.from_host(Jo.n, Jo.rowptr, Jo.col, Jo.pp, Jo.pT, Jo.Tp, Jo.TT, Jo.S)
+    dx, st, hs = solver.solve(Jd, dev(-bo), cfg, history=True)
+    ao_pp = o_amg(Jo.n, Jo.rowptr, Jo.col, Jo.pp, tps.AmgParams(restriction=0))
+    ao_S = o_amg(Jo.n, Jo.rowptr, Jo.col, Jo.S, tps.AmgParams(restriction=1))
+    _compare_hierarchies(hs[0], ao_pp, "A_pp")
+    _compare_hierarchies(hs[1], ao_S, "S")
+    xo, io = oracle.gmres(Jo, ao_pp, ao_S, bo, rtol=rtol)
+    say(f"  gpu its {st['iters']} rel {st['rel_true']:.2e} (GPU-assembled: {st_a['iters']}, "
+        f"{st_a['rel_true']:.2e}); oracle its {io['iters']} rel {io['rel_true']:.2e}")
+    assert st["converged"] and st["rel_true"] <= rtol
+    assert st_a["converged"] and st_a["rel_true"] <= rtol and abs(st_a["iters"] - io["iters"]) <= 1
+    assert abs(st["iters"] - io["iters"]) <= 1
+    h_g, h_o = st["history"], io["history"]
+    k = min(11, len(h_g), len(h_o))
+    diff = np.abs(h_g[:k] - h_o[:k])
+    say(f"  history max |d|/h_o {np.max(diff / h_o[:k]):.2e}")
+    assert np.all(diff <= 1e-8 * h_o[:k])
+    x = np_(dx)
+    for blk in (0, 1):
+        d_go = np.linalg.norm(x[blk::2] - xo[blk::2]) / np.linalg.norm(xo[blk::2])
+        say(f"  block {blk}: |gpu-oracle|/|oracle| {d_go:.2e}")
+        assert d_go <= 1e-8
+    for h in reversed(hs):
+        h.close()
+
+
+@pytest.mark.parametrize("storage,bound", [(0, 1e-12), (1, 1e-3)])
+def test_vcycle_production_size_kernels(storage, bound):
+    """A 96x96x32 layered grid (294,912 cells): its finest level takes the
+    256-thread two-rows-per-thread DIA kernels (n/2 > 131072) and its first
+    coarse level (~97k rows) the halved CSR lane groups of levels of >= 65536
+    rows, neither of which the small grids reach.  Both hierarchies are
+    compared level by level with the oracle's (FP64), and one V-cycle on a
+    random right-hand side within 1e-12 (FP64; measured 4e-16 .. 8e-16) or
+    the FP32 storage bound."""
+    say("vcycle 96x96x32", storage)
+    p = synth.make_problem("W2", grid=synth.Grid(96, 96, 32, 1, 1, 1))
+    Jo, Jd = _oracle_J_on_device(p)
+    b = synth.random_rhs(7, Jo.n)
+    for which, restr in (("pp", 0), ("S", 1)):
+        prm = tps.AmgParams(restriction=restr, storage=storage)
+        ho = o_amg(Jo.n, Jo.rowptr, Jo.col, getattr(Jo, which), prm)
+        hg = tps.AMG(Jd.rowptr, Jd.col, getattr(Jd, which), prm)
+        nd, _ = hg.level_format(0)
+        n1 = hg.level_sizes(1)[0]
+        assert nd == 7 and Jo.n // 2 > 131072 and n1 >= 65536
+        if storage == 0:
+            _compare_hierarchies(hg, ho, which)
+        err = relmax(np_(hg.vcycle(dev(b))), ho.vcycle(b))
+        say(f"  {which} storage {storage}: V-cycle rel err {err:.2e}")
+        assert err <= bound
+        hg.close()

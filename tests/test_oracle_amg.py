@@ -345,3 +345,185 @@ def test_poisson_stationary_factor(dims, kw, bound):
         x = x + h.vcycle(-(A @ x))
     f = (np.linalg.norm(A @ x) / r0) ** (1 / 20)
     assert f < bound, f
+
+
+def _cycle_error(h, levels, degs, lo):
+    """Error propagation I - B_0 A_0 of the oracle's V(1,1) cycle, built
+    level by level from the definition: on the coarsest level B = A^{-1};
+    above it E_l = S_l (I - P_l B_{l+1} R_l A_l) S_l with S_l the Chebyshev
+    error polynomial of degree degs[l] of D_l^{-1} A_l on [lo, 1], and
+    B_l = (I - E_l) A_l^{-1}."""
+    mats = []
+    for l in range(levels):
+        L = h.level(l)
+        A = _csr(L["n"], L["A_rowptr"], L["A_col"], L["A_val"]).toarray()
+        if l < levels - 1:
+            Ln = h.level(l + 1)
+            P = _csr(L["n"], L["P_rowptr"], L["P_col"], L["P_val"], Ln["n"]).toarray()
+            R = _csr(Ln["n"], *(h.level(l)[k] for k in ("R_rowptr", "R_col", "R_val")), L["n"]).toarray()
+            mats.append((A, P, R))
+        else:
+            mats.append((A, None, None))
+    B = np.linalg.inv(mats[-1][0])
+    for l in range(levels - 2, -1, -1):
+        A, P, R = mats[l]
+        X = (1.0 / np.abs(A).sum(axis=1))[:, None] * A
+        S = _cheb_error_poly(X, degs[l], lo)
+        E = S @ (np.eye(A.shape[0]) - P @ B @ R @ A) @ S
+        B = (np.eye(A.shape[0]) - E) @ np.linalg.inv(A)
+    return np.eye(mats[0][0].shape[0]) - B @ mats[0][0]
+
+
+@pytest.mark.parametrize("deg0,deg_coarse,restriction", [(10, 1, 0), (10, 1, 1), (4, 2, 0)])
+def test_three_level_cycle_closed_form_per_level_degrees(deg0, deg_coarse, restriction):
+    """A three-level V(1,1) cycle with the per-level Chebyshev schedule
+    (degree deg0 on the finest level, deg_coarse on level 1, exact solve on
+    level 2) equals the recursively composed error propagation.  The same
+    closed form with the finest-level degree on level 1 as well is far from
+    it, so a schedule that ignored the coarse degree fails here."""
+    J = _problem_ops(dims=(7, 6, 4))
+    val = J.S if restriction else J.pp
+    lo = 0.03
+    h = oracle.AMG(J.n, J.rowptr, J.col, val, max_levels=3, coarse_max=0, smoother=1,
+                   cheb_degree=deg0, cheb_degree_coarse=deg_coarse, cheb_lo=lo, restriction=restriction)
+    assert h.nlev == 3
+    A = _csr(J.n, J.rowptr, J.col, val).toarray()
+    M = np.column_stack([h.vcycle(e) for e in np.eye(J.n)])
+    got = np.eye(J.n) - M @ A
+    E = _cycle_error(h, 3, [deg0, deg_coarse], lo)
+    np.testing.assert_allclose(got, E, rtol=0, atol=1e-9)
+    wrong = _cycle_error(h, 3, [deg0, deg0], lo)
+    assert np.abs(got - wrong).max() > 1e-3
+
+
+def _same_structure(h1, h2):
+    if h1.nlev != h2.nlev:
+        return False
+    for l in range(h1.nlev):
+        a, b = h1.level(l), h2.level(l)
+        keys = ["A_rowptr", "A_col"] + (["cf", "P_rowptr", "P_col", "R_rowptr", "R_col"] if l < h1.nlev - 1 else [])
+        if any(not np.array_equal(a[k], b[k]) for k in keys):
+            return False
+    return True
+
+
+def _shifted_state(p, scale, seed=99):
+    """The same grid, fields and wells at another Newton state: x_k moved by
+    `scale` times a fresh perturbation of the workload's size."""
+    import dataclasses
+    rng = np.random.default_rng(seed)
+    x = p.x_k.copy()
+    x[0::2] += scale * 1e5 * rng.standard_normal(p.grid.n)
+    x[1::2] += scale * 5.0 * rng.standard_normal(p.grid.n)
+    return dataclasses.replace(p, x_k=x)
+
+
+@pytest.mark.parametrize("restriction", [0, 1])
+def test_refresh_with_unchanged_split_equals_fresh_setup(restriction):
+    """A numeric refresh (frozen C/F splits and patterns) with the setup's
+    own values, and with the values of a nearby Newton state whose fresh
+    setup keeps every split and pattern, reproduces the fresh setup's
+    hierarchy bit for bit: the refresh's interpolation reduces to direct
+    interpolation when the frozen sets are the strong C sets."""
+    p = synth.make_problem("W2", seed=5, grid=synth.Grid(10, 9, 6, 1.0, 1.0, 1.0))
+    J = oracle.jacobian(p)
+    val = J.S if restriction else J.pp
+    kw = dict(restriction=restriction, coarse_max=16, smoother=1, cheb_degree=4)
+    h = oracle.AMG(J.n, J.rowptr, J.col, val, **kw)
+    assert h.nlev >= 3
+    p2 = _shifted_state(p, 1e-7)
+    J2 = oracle.jacobian(p2)
+    val2 = J2.S if restriction else J2.pp
+    assert not np.array_equal(val, val2)
+    for v in (val, val2):
+        fresh = oracle.AMG(J.n, J.rowptr, J.col, v, **kw)
+        assert _same_structure(h, fresh)
+        assert h.refresh(v) == 0
+        for l in range(h.nlev):
+            a, b = h.level(l), fresh.level(l)
+            assert np.array_equal(a["A_val"], b["A_val"]), l
+            assert np.array_equal(a["dinv"], b["dinv"]), l
+            if l < h.nlev - 1:
+                assert np.array_equal(a["P_val"], b["P_val"]) and np.array_equal(a["R_val"], b["R_val"]), l
+        rhs = synth.random_rhs(3, J.n)
+        assert np.array_equal(h.vcycle(rhs), fresh.vcycle(rhs))
+
+
+def _refresh_weights_dense(A, cf, Pd):
+    """Direct interpolation on frozen sets, from its definition (dense): row
+    i of the frozen P (F rows) has its weights at the columns where Pd is
+    stored; only couplings of the sign opposite to a_ii interpolate."""
+    n = A.shape[0]
+    cmap = np.cumsum(cf) - 1
+    W = np.zeros_like(Pd)
+    for i in range(n):
+        if cf[i]:
+            W[i, cmap[i]] = 1.0
+            continue
+        s = -1.0 if A[i, i] < 0 else 1.0
+        off = [j for j in range(n) if j != i and A[i, j] != 0.0]
+        sum_all = sum(A[i, j] for j in off if s * A[i, j] < 0)
+        lump = sum(A[i, j] for j in off if not s * A[i, j] < 0)
+        frozen = [j for j in off if cf[j] and Pd[i, cmap[j]] and s * A[i, j] < 0]
+        sum_p = sum(A[i, j] for j in frozen)
+        if sum_p == 0.0:
+            continue
+        for j in frozen:
+            W[i, cmap[j]] = -(sum_all / sum_p) * A[i, j] / (A[i, i] + lump)
+    return W
+
+
+@pytest.mark.parametrize("restriction", [0, 1])
+def test_refresh_on_changed_operator_follows_definition(restriction):
+    """A refresh with the operator of a distant Newton state (whose fresh
+    setup would choose other splits): the patterns stay, P's weights are
+    the frozen-set direct interpolation of the new operator (dense,
+    definition), R = P^T (Galerkin) or the transpose of the same
+    construction on A^T (Petrov-Galerkin), every coarse operator is the
+    dense R A P of the level above, and the coarsest LU solves it."""
+    p = synth.make_problem("W2", seed=5, grid=synth.Grid(8, 7, 5, 1.0, 1.0, 1.0))
+    J = oracle.jacobian(p)
+    val = J.S if restriction else J.pp
+    kw = dict(restriction=restriction, coarse_max=16, smoother=1, cheb_degree=4)
+    h = oracle.AMG(J.n, J.rowptr, J.col, val, **kw)
+    p2 = _shifted_state(p, 1.0)
+    J2 = oracle.jacobian(p2)
+    val2 = J2.S if restriction else J2.pp
+    fresh = oracle.AMG(J.n, J.rowptr, J.col, val2, **kw)
+    assert not _same_structure(h, fresh)          # the split would have changed
+    before = [h.level(l) for l in range(h.nlev)]
+    assert h.refresh(val2) == 0
+    A = _csr(J.n, J.rowptr, J.col, val2).toarray()
+    for l in range(h.nlev - 1):
+        L, Ln = h.level(l), h.level(l + 1)
+        for k in ("A_rowptr", "A_col", "cf", "P_rowptr", "P_col", "R_rowptr", "R_col"):
+            assert np.array_equal(L[k], before[l][k]), (l, k)
+        np.testing.assert_allclose(_csr(L["n"], L["A_rowptr"], L["A_col"], L["A_val"]).toarray(), A,
+                                   rtol=1e-12, atol=1e-12 * np.abs(A).max())
+        Pd = _csr(L["n"], L["P_rowptr"], L["P_col"], L["P_val"], Ln["n"]).toarray()
+        Ppat = _csr(L["n"], L["P_rowptr"], L["P_col"], np.ones(len(L["P_col"])), Ln["n"]).toarray()
+        W = _refresh_weights_dense(A, L["cf"], Ppat)
+        np.testing.assert_allclose(Pd, W, rtol=1e-13, atol=1e-15)
+        Rd = _csr(Ln["n"], L["R_rowptr"], L["R_col"], L["R_val"], L["n"]).toarray()
+        if restriction:
+            Rpat = _csr(Ln["n"], L["R_rowptr"], L["R_col"], np.ones(len(L["R_col"])), L["n"]).toarray()
+            np.testing.assert_allclose(Rd, _refresh_weights_dense(A.T.copy(), L["cf"], Rpat.T.copy()).T,
+                                       rtol=1e-13, atol=1e-15)
+        else:
+            assert np.array_equal(Rd, Pd.T)
+        A = Rd @ A @ Pd
+    Lc = h.level(h.nlev - 1)
+    Ac = _csr(Lc["n"], Lc["A_rowptr"], Lc["A_col"], Lc["A_val"]).toarray()
+    np.testing.assert_allclose(Ac, A, rtol=1e-10, atol=1e-12 * np.abs(A).max())
+    # the refreshed cycle (smoothers, transfers and the refactorised coarsest
+    # LU) has the error propagation composed from the refreshed levels
+    A0 = _csr(J.n, J.rowptr, J.col, val2).toarray()
+    M = np.column_stack([h.vcycle(e) for e in np.eye(J.n)])
+    np.testing.assert_allclose(np.eye(J.n) - M @ A0, _cycle_error(h, h.nlev, [4] * (h.nlev - 1), 0.3),
+                               rtol=0, atol=1e-8)
+
+
+def test_refresh_rejects_extended_interpolation():
+    J = _problem_ops(dims=(6, 5, 4))
+    h = oracle.AMG(J.n, J.rowptr, J.col, J.pp, coarse_max=16, interp=1)
+    assert h.refresh(J.pp) == -1

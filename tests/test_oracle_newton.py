@@ -5,6 +5,7 @@ backward-Euler step conserves the fluid mass the wells inject and produce."""
 import dataclasses
 
 import numpy as np
+import pytest
 
 import oracle
 from paper_1902_00095_amd import synth
@@ -103,3 +104,43 @@ def test_line_search_newton_reaches_the_same_root():
     assert min(lams[0]) < 1.0 and hl[0][-1] <= 1e-8
     for blk in (0, 1):
         assert np.linalg.norm(xl[0][blk::2] - xs[0][blk::2]) <= 1e-9 * np.linalg.norm(xs[0][blk::2])
+
+
+def test_line_search_rejects_non_finite_trials():
+    """A trial whose residual is not finite (as a state outside the fluid
+    laws' range gives) is rejected and halves the step, whatever the
+    quadratic model would say.  On G(y) = y - 1 with G NaN for y > 2, a
+    wild step of 4 from 0 first lands on a NaN (lam = 1), the halving gives
+    lam = 0.5 (y = 2, finite but no decrease), and the quadratic model then
+    takes over; the accepted lam passes the sufficient-decrease test.  A
+    NaN compared with a bound is False, so a rule without the finiteness
+    test would keep the NaN in lam for every later trial."""
+    def G_at(y):
+        return np.array([np.nan if y[0] > 2.0 else y[0] - 1.0])
+
+    x = np.zeros(1)
+    dx = np.array([4.0])
+    g2 = 1.0
+    lam, xt, Gt, rej = oracle.line_search_step(G_at, x, dx, g2)
+    assert np.isfinite(Gt).all()
+    assert rej >= 1 and lam <= 0.5
+    # f(lam) = (4 lam - 1)^2 / 2 must satisfy the sufficient-decrease test
+    assert 0.5 * (4 * lam - 1) ** 2 <= 0.5 - 1e-4 * lam * g2
+    # the first trial (lam = 1) was NaN: a halving, not a quadratic-model step,
+    # took lam to 0.5 -- replaying the rule by hand gives the same lam
+    seq, l = [], 1.0
+    while True:
+        f1 = 0.5 * float(G_at(x + l * dx) @ G_at(x + l * dx))
+        if np.isfinite(f1) and f1 <= 0.5 * g2 - 1e-4 * l * g2:
+            break
+        if np.isfinite(f1):
+            l = min(max(g2 * l * l / (2.0 * (f1 - 0.5 * g2 + g2 * l)), 0.1 * l), 0.5 * l)
+        else:
+            l = 0.5 * l
+        seq.append(l)
+    assert seq[0] == 0.5 and lam == l
+
+
+def test_line_search_raises_when_every_trial_is_non_finite():
+    with pytest.raises(FloatingPointError):
+        oracle.line_search_step(lambda y: np.array([np.inf]), np.zeros(1), np.ones(1), 1.0)
