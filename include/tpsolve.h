@@ -197,6 +197,28 @@ int amg_setup_schur_diag(const tp_jacobian* J, const tp_amg_params* params, tp_a
  * Synchronises `stream`. */
 int amg_refresh_fine(tp_amg_t amg, const double* val, void* stream);
 
+/* Setup reuse across Newton iterations (Section 4, opening: each Newton
+ * iteration solves a new Jacobian; the AMG setup is rebuilt for it
+ * otherwise): new values `val` (device, nnz of level 0) for the finest-level
+ * operator on the pattern the hierarchy was built on, with the C/F split of
+ * every level and every sparsity pattern (P, R, the coarse operators) kept.
+ * All values are recomputed from `val` in the setup's order: direct
+ * interpolation weights restricted to the kept interpolation sets (only
+ * couplings of the sign opposite to the diagonal interpolate; a kept entry
+ * that no longer does holds an explicit zero), R = P^T or its
+ * Petrov-Galerkin counterpart on the kept pattern, the Galerkin products
+ * R (A P) on their kept patterns (each entry summed in ascending inner
+ * index), the l1 diagonals, stencil-diagonal and reduced-precision copies,
+ * the coarsest inverse, and an attached learned smoother's static features.
+ * When the kept splits and patterns are the ones a fresh amg_setup would
+ * choose for `val`, the hierarchy equals that fresh setup bit for bit.
+ * Everything is rewritten in place: preconditioner handles and their
+ * captured graphs stay valid.  Direct interpolation only (interp 0: else
+ * TP_ERR_ARG); not for hierarchies from amg_setup_schur_diag.  Errors:
+ * TP_ERR_ARG (null, interp), TP_ERR_NUMERIC (zero pivot in the coarsest
+ * inverse).  Synchronises `stream`. */
+int amg_refresh(tp_amg_t amg, const double* val, void* stream);
+
 int amg_num_levels(tp_amg_t amg, int32_t* nlev);
 /* sizes of level l (P/R sizes are 0 on the coarsest level) */
 int amg_level_info(tp_amg_t amg, int32_t level, int32_t* n, int32_t* nnzA,

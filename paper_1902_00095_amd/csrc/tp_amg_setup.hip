@@ -1980,11 +1980,10 @@ static void setup(tp_amg* h, int32_t n, const int32_t* rowptr, const int32_t* co
         } else {
             transpose(L.P.rowptr.p, L.P.col.p, L.P.val.p, L.P.n, nc, L.P.nnz, true, L.R, s);
         }
-        Csr AP;
-        spgemm(A, L.P, AP, sg_flag.p, s);
+        spgemm(A, L.P, L.AP, sg_flag.p, s);
         h->lev.emplace_back();
         Level& Ln = h->lev[l + 1];        // (reference after emplace_back)
-        spgemm(h->lev[l].R, AP, Ln.A, sg_flag.p, s);
+        spgemm(h->lev[l].R, h->lev[l].AP, Ln.A, sg_flag.p, s);
         Ln.A.m = nc;
     }
     exact_sizes(h, sg_flag.p, s);
@@ -2102,6 +2101,189 @@ static void refresh_fine(tp_amg* h, const double* val, hipStream_t s) {
     if (h->cnn) cnn_attach_refresh(h->cnn.get(), L.A.rowptr.p, L.A.col.p, L.A.val.p, s);
 }
 
+// ---- numeric refresh: new level-0 values on a frozen hierarchy -------------------------
+// Setup reuse across Newton iterations.  The C/F splits and every sparsity
+// pattern (P, R, the kept A P and the coarse operators) stay; values are
+// recomputed from the new finest-level operator in the setup's own order:
+//   interpolation  direct interpolation restricted to the frozen set P_i:
+//                  sum_all and lump as at setup; sum_p = sum of a_ij over the
+//                  frozen j with s a_ij < 0 (row order); w_ij = -(alpha a_ij)
+//                  / (a_ii + lump) for those j, an explicit zero for the
+//                  other frozen entries, and a zero row where sum_p = 0.
+//                  With the frozen set equal to the new strong C set this is
+//                  the setup's direct interpolation, bit for bit;
+//   restriction    R = P^T; or (Petrov-Galerkin) Q = the same construction
+//                  on A^T over the frozen pattern of R^T, and R = Q^T;
+//   coarse op.     A P and R (A P) on their kept patterns, each entry summed
+//                  in ascending inner index from zero (the SpGEMM's order).
+__global__ void __launch_bounds__(B)
+k_refresh_interp(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                 const double* __restrict__ val, const int32_t* __restrict__ cf,
+                 const int32_t* __restrict__ cmap, const int32_t* __restrict__ Prp,
+                 const int32_t* __restrict__ Pc, double* __restrict__ Pv) {
+    const int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n || cf[i]) return;  // C rows keep their unit entry
+    const int32_t pa = Prp[i], pe = Prp[i + 1];
+    if (pa == pe) return;
+    const int32_t a = rowptr[i], e = rowptr[i + 1];
+    double aii = 0.0;
+    for (int32_t k = a; k < e; ++k)
+        if (col[k] == i) aii = val[k];
+    const double s = aii < 0.0 ? -1.0 : 1.0;
+    double sum_all = 0.0, lump = 0.0;
+    for (int32_t k = a; k < e; ++k) {
+        if (col[k] == i) continue;
+        const double v = val[k];
+        if (s * v < 0.0) sum_all += v;
+        else lump += v;
+    }
+    double sum_p = 0.0;
+    int32_t q = pa;
+    for (int32_t k = a; k < e; ++k) {
+        const int32_t j = col[k];
+        if (j == i || !cf[j]) continue;
+        const int32_t c = cmap[j];
+        while (q < pe && Pc[q] < c) ++q;
+        if (q < pe && Pc[q] == c && s * val[k] < 0.0) sum_p += val[k];
+    }
+    for (int32_t t = pa; t < pe; ++t) Pv[t] = 0.0;
+    if (sum_p == 0.0) return;
+    const double alpha = sum_all / sum_p;
+    const double dtil = aii + lump;
+    q = pa;
+    for (int32_t k = a; k < e; ++k) {
+        const int32_t j = col[k];
+        if (j == i || !cf[j]) continue;
+        const int32_t c = cmap[j];
+        while (q < pe && Pc[q] < c) ++q;
+        if (q < pe && Pc[q] == c && s * val[k] < 0.0) Pv[q] = -(alpha * val[k]) / dtil;
+    }
+}
+
+// T = X^T on T's kept (sorted) pattern: entry (i, J) of X goes to row J of T
+// at column i, found by bisection.
+__global__ void __launch_bounds__(B)
+k_scatter_transpose(int32_t n, const int32_t* __restrict__ Xrp, const int32_t* __restrict__ Xc,
+                    const double* __restrict__ Xv, const int32_t* __restrict__ Trp,
+                    const int32_t* __restrict__ Tc, double* __restrict__ Tv) {
+    const int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n) return;
+    for (int32_t q = Xrp[i]; q < Xrp[i + 1]; ++q) {
+        const int32_t J = Xc[q];
+        int32_t lo = Trp[J], hi = Trp[J + 1];
+        while (lo < hi) {
+            const int32_t mid = lo + (hi - lo) / 2;
+            if (Tc[mid] < i) lo = mid + 1;
+            else hi = mid;
+        }
+        Tv[lo] = Xv[q];
+    }
+}
+
+// C = A B on C's kept pattern: one thread per entry (its row by bisection of
+// C's row pointer), the products summed over A's row in ascending inner
+// index from zero, as the SpGEMM sums them.
+__global__ void __launch_bounds__(B)
+k_spgemm_values(int32_t n, int64_t nnz, const int32_t* __restrict__ Crp, const int32_t* __restrict__ Cc,
+                double* __restrict__ Cv, const int32_t* __restrict__ Arp, const int32_t* __restrict__ Ac,
+                const double* __restrict__ Av, const int32_t* __restrict__ Brp,
+                const int32_t* __restrict__ Bc, const double* __restrict__ Bv) {
+    for (int64_t q = (int64_t)blockIdx.x * B + threadIdx.x; q < nnz; q += (int64_t)gridDim.x * B) {
+        int32_t lo = 0, hi = n;  // the row i with Crp[i] <= q < Crp[i + 1]
+        while (hi - lo > 1) {
+            const int32_t mid = lo + (hi - lo) / 2;
+            if (Crp[mid] <= q) lo = mid;
+            else hi = mid;
+        }
+        const int32_t i = lo, c = Cc[q];
+        double acc = 0.0;
+        for (int32_t kk = Arp[i]; kk < Arp[i + 1]; ++kk) {
+            const int32_t r = Ac[kk];
+            int32_t l2 = Brp[r], h2 = Brp[r + 1] - 1;
+            while (l2 <= h2) {
+                const int32_t mid = (l2 + h2) >> 1;
+                const int32_t v = Bc[mid];
+                if (v == c) { acc += Av[kk] * Bv[mid]; break; }
+                if (v < c) l2 = mid + 1;
+                else h2 = mid - 1;
+            }
+        }
+        Cv[q] = acc;
+    }
+}
+
+static void spgemm_values(const Csr& A, const Csr& Bm, Csr& C, hipStream_t s) {
+    if (C.nnz == 0) return;
+    const int grid = (int)std::min<int64_t>(cdiv(C.nnz, B), 65536);
+    TP_LAUNCH(k_spgemm_values, grid, B, 0, s, C.n, (int64_t)C.nnz, C.rowptr.p, C.col.p, C.val.p, A.rowptr.p,
+              A.col.p, A.val.p, Bm.rowptr.p, Bm.col.p, Bm.val.p);
+}
+
+// Everything a level derives from its values alone: the DIA copy and the
+// reduced-precision copies of A, 1/D, P and R (rewritten in place).
+static void refresh_level_copies(tp_amg* h, Level& L, bool transfers, hipStream_t s) {
+    const int32_t n = L.A.n;
+    const int64_t nnz = L.A.nnz;
+    const int64_t nd_n = (int64_t)L.ndia * n;
+    if (L.ndia) {
+        DiaOffs o{};
+        for (int d = 0; d < L.ndia; ++d) o.o[d] = L.dia_off[d];
+        TP_LAUNCH(k_dia_refill, cdiv(n, B), B, 0, s, n, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.ndia, o, L.dia.p);
+    }
+    if (h->prm.storage == 0 || n == 0) return;
+    TP_LAUNCH(k_to_f32, cdiv(n, B), B, 0, s, (int64_t)n, L.dinv.p, L.dinv32.p);
+    if (h->prm.storage == 1) {
+        TP_LAUNCH(k_to_f32, cdiv(nnz, B), B, 0, s, nnz, L.A.val.p, L.A32.p);
+        if (L.ndia) TP_LAUNCH(k_to_f32, cdiv(nd_n, B), B, 0, s, nd_n, L.dia.p, L.dia32.p);
+    } else {
+        TP_LAUNCH(k_split_bf16_csr, cdiv(n, B), B, 0, s, n, L.A.rowptr.p, L.A.col.p, L.A.val.p, (__bf16*)L.A16.p,
+                  L.diag32.p);
+        if (L.ndia) {
+            int d0 = -1;
+            for (int d = 0; d < L.ndia; ++d)
+                if (L.dia_off[d] == 0) d0 = d;
+            TP_LAUNCH(k_split_bf16_dia, cdiv(nd_n, B), B, 0, s, nd_n, n, d0, L.dia.p, (__bf16*)L.dia16.p);
+        }
+    }
+    if (transfers) {
+        if (L.P.nnz) TP_LAUNCH(k_to_f32, cdiv(L.P.nnz, B), B, 0, s, (int64_t)L.P.nnz, L.P.val.p, L.P32.p);
+        if (L.R.nnz) TP_LAUNCH(k_to_f32, cdiv(L.R.nnz, B), B, 0, s, (int64_t)L.R.nnz, L.R.val.p, L.R32.p);
+    }
+}
+
+static void refresh_numeric(tp_amg* h, const double* val, hipStream_t s) {
+    TP_CHECK_ARG(h->prm.interp == 0, "amg_refresh: the numeric refresh needs direct interpolation (interp 0)");
+    const int nl = (int)h->lev.size();
+    TP_HIP(hipMemcpyAsync(h->lev[0].A.val.p, val, sizeof(double) * h->lev[0].A.nnz, hipMemcpyDeviceToDevice, s));
+    for (int l = 0; l < nl; ++l) {
+        Level& L = h->lev[l];
+        const int32_t n = L.A.n;
+        if (n > 0) TP_LAUNCH(k_l1_dinv, cdiv(n, B), B, 0, s, n, L.A.rowptr.p, L.A.val.p, L.dinv.p);
+        if (l == nl - 1) break;
+        DBuf<int32_t> cmap(n + 1, s);
+        scan_exclusive(L.cf.p, cmap.p, n, s);
+        TP_LAUNCH(k_refresh_interp, cdiv(n, B), B, 0, s, n, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.cf.p, cmap.p,
+                  L.P.rowptr.p, L.P.col.p, L.P.val.p);
+        if (h->prm.restriction == 1) {
+            Csr At, Q;
+            transpose(L.A.rowptr.p, L.A.col.p, L.A.val.p, n, n, L.A.nnz, true, At, s);
+            transpose(L.R.rowptr.p, L.R.col.p, L.R.val.p, L.R.n, n, L.R.nnz, true, Q, s);  // pattern of R^T
+            TP_LAUNCH(k_refresh_interp, cdiv(n, B), B, 0, s, n, At.rowptr.p, At.col.p, At.val.p, L.cf.p, cmap.p,
+                      Q.rowptr.p, Q.col.p, Q.val.p);
+            TP_LAUNCH(k_scatter_transpose, cdiv(n, B), B, 0, s, n, Q.rowptr.p, Q.col.p, Q.val.p, L.R.rowptr.p,
+                      L.R.col.p, L.R.val.p);
+        } else {
+            TP_LAUNCH(k_scatter_transpose, cdiv(n, B), B, 0, s, n, L.P.rowptr.p, L.P.col.p, L.P.val.p,
+                      L.R.rowptr.p, L.R.col.p, L.R.val.p);
+        }
+        spgemm_values(L.A, L.P, L.AP, s);
+        spgemm_values(L.R, L.AP, h->lev[l + 1].A, s);
+    }
+    for (int l = 0; l < nl; ++l) refresh_level_copies(h, h->lev[l], l < nl - 1, s);
+    build_coarse_inverse(h, h->lev.back().A, s);
+    if (h->cnn) cnn_attach_refresh(h->cnn.get(), h->lev[0].A.rowptr.p, h->lev[0].A.col.p, h->lev[0].A.val.p, s);
+}
+
 }  // namespace tp
 
 extern "C" {
@@ -2164,6 +2346,16 @@ int amg_refresh_fine(tp_amg_t amg, const double* val, void* stream) {
         TP_CHECK_ARG(amg && val, "amg_refresh_fine: null argument");
         hipStream_t s = (hipStream_t)stream;
         tp::refresh_fine(amg, val, s);
+        TP_HIP(hipStreamSynchronize(s));
+    });
+    return TP_OK;
+}
+
+int amg_refresh(tp_amg_t amg, const double* val, void* stream) {
+    TP_GUARD({
+        TP_CHECK_ARG(amg && val, "amg_refresh: null argument");
+        hipStream_t s = (hipStream_t)stream;
+        tp::refresh_numeric(amg, val, s);
         TP_HIP(hipStreamSynchronize(s));
     });
     return TP_OK;

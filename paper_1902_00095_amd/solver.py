@@ -195,14 +195,16 @@ def _backtrack(prob, dev, J, G, x, dx, gn, alpha=1e-4, max_backtracks=10):
         rejected += 1
 
 
-def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None):
+def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None, on_solve=None):
     """Run `ncfg.steps` time steps of `prob` from its x_prev.  Each Newton
     iteration assembles at the current iterate (into the same Jacobian
     buffers), builds both hierarchies (or, with `ncfg.reuse`, refreshes their
     finest level after a step's first iteration; `net` attached to the Schur
-    hierarchy when given) and solves J dx = -G to `cfg.rtol`.  Returns (x,
-    stats): the final state (device, interleaved) and per-run counts and
-    times."""
+    hierarchy when given) and solves J dx = -G to `cfg.rtol`.  `on_solve`,
+    when given, is called before each linear solve with (step, Newton
+    iteration, x_prev, x_k) (device tensors; copy them to keep them).
+    Returns (x, stats): the final state (device, interleaved) and per-run
+    counts and times."""
     import time
 
     import torch
@@ -256,6 +258,8 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None):
                     if not (gn <= ncfg.rtol_f * g0 or done):
                         unconverged += 1
                     break
+                if on_solve is not None:
+                    on_solve(step, k, dev["x_prev"], dev["x_k"])
                 torch.cuda.synchronize()
                 ts = time.perf_counter()
                 built = False

@@ -75,7 +75,7 @@ class _Allocator(C.Structure):
     _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", C.c_void_p)]
 
 
-EXPORTS = ["tp_last_error", "tp_init", "tp_jacobian_sizes", "assemble_tpfa", "assemble_tpfa_aniso", "amg_setup", "amg_setup_schur_diag", "amg_refresh_fine",
+EXPORTS = ["tp_last_error", "tp_init", "tp_jacobian_sizes", "assemble_tpfa", "assemble_tpfa_aniso", "amg_setup", "amg_setup_schur_diag", "amg_refresh_fine", "amg_refresh",
            "amg_num_levels", "amg_level_info", "amg_level_format", "amg_level_copy", "amg_vcycle", "amg_destroy",
            "precond_create", "precond_apply", "precond_destroy", "fgmres_solve",
            "ilu0_create", "ilu0_create_jacobian", "ilu0_refactor_jacobian", "ilu0_solve", "ilu0_info",
@@ -294,6 +294,12 @@ class AMG:
         """New finest-level values on the same pattern; coarse levels kept."""
         self._keep = self._keep[:2] + (val,)
         _check(_lib.amg_refresh_fine(self.h, _ptr(val), _stream(stream)))
+
+    def refresh(self, val, stream=None):
+        """New finest-level values on the same pattern; C/F splits and every
+        pattern kept, all values recomputed (numeric-only setup)."""
+        self._keep = self._keep[:2] + (val,)
+        _check(_lib.amg_refresh(self.h, _ptr(val), _stream(stream)))
 
     def close(self):
         if getattr(self, "h", None) and self.h.value:
