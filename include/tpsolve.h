@@ -254,6 +254,23 @@ int precond_create(const tp_jacobian* J, tp_amg_t amg_pp, tp_amg_t amg_S,
  * (they share the handle's staging vectors and the hierarchies' work
  * vectors). */
 int precond_apply(tp_prec_t M, const double* r, double* z, void* stream);
+
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): precond_apply without any device
+ * allocation by the library.  The same kernels in the same order as
+ * precond_apply (identical z), launched one by one on `stream` (no graph is
+ * captured or instantiated).  Its work vectors -- the split r and z (2n + 2n
+ * doubles) and, for CPR handles, the first-stage pressure and residual
+ * (n + 2n) -- live in a fixed 256 MiB device array that every GPU the library
+ * runs on holds for the life of the process: at most 8,388,608 cells (block
+ * variants) or 4,793,490 (CPR) per call; larger handles get
+ * TP_ERR_CAPACITY.  Nothing in the array has to start at zero.  All calls on
+ * one GPU share that array: calls that overlap in time on one GPU (two
+ * streams, two threads) race and must be serialised by the caller.  The
+ * handle's hierarchies and an attached learned smoother use the buffers they
+ * allocated at setup / attachment.  Errors: TP_ERR_ARG (null; the smoother
+ * timer is on, since it records events), TP_ERR_CAPACITY, TP_ERR_HIP. */
+int precond_apply_noalloc(tp_prec_t M, const double* r, double* z, void* stream);
 int precond_destroy(tp_prec_t M);
 
 /* ---------------------------------------------------------------------------

@@ -155,6 +155,9 @@ struct KernelTimer {
     size_t used = 0;
 };
 KernelTimer& timer();
+// The current device's copy of the fixed scratch array of the allocation-free
+// preconditioner apply (resolved once per device; defined with the array).
+double* scratch_ptr();
 // When the timer is on, reserve an event pair for one launch of the timed
 // kernel (returns false when off).  The pair is handed to
 // hipExtLaunchKernelGGL, which stamps the kernel's own dispatch start and

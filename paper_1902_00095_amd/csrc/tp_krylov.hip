@@ -408,18 +408,22 @@ static void prec_buffers(tp_prec* M, hipStream_t s) {
     }
 }
 
-void prec_apply_split(tp_prec* M, const double* r, double* z, hipStream_t s) {
+// cw, cb: CPR work vectors (n and 2n); null takes the handle's own
+void prec_apply_split(tp_prec* M, const double* r, double* z, hipStream_t s, double* cw = nullptr,
+                      double* cb = nullptr) {
     const int32_t n = M->J.n;
     const double* rp = r;
     const double* rT = r + n;
     double* zp = z;
     double* zT = z + n;
     if (M->variant == 3) {
-        vsolve(M->pp, rp, M->cw.p, n, s);  // stage 1: x1 = V_pp(r_p)
+        if (!cw) cw = M->cw.p;
+        if (!cb) cb = M->cb.p;
+        vsolve(M->pp, rp, cw, n, s);  // stage 1: x1 = V_pp(r_p)
         TP_LAUNCH(k_cpr_resid, cdiv((int64_t)n * JG, KB), KB, 0, s, n, M->J.rowptr, M->J.col, M->J.pp, M->J.Tp,
-                  M->cw.p, r, M->cb.p);
-        ilu_solve(M->ilu, M->cb.p, z, s);  // stage 2
-        TP_LAUNCH(k_add_into, cdiv(n, KB), KB, 0, s, n, M->cw.p, z);
+                  cw, r, cb);
+        ilu_solve(M->ilu, cb, z, s);  // stage 2
+        TP_LAUNCH(k_add_into, cdiv(n, KB), KB, 0, s, n, cw, z);
         return;
     }
     if (M->variant == 1) {
@@ -770,7 +774,37 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
     return status;
 }
 
+// ---- allocation-free apply: fixed device scratch ---------------------------------------
+// precond_apply_noalloc keeps its work vectors (the split right-hand side and
+// result, 2n + 2n doubles, and for CPR the first-stage pressure and residual,
+// n + 2n) in this array instead of buffers the library allocates: 256 MiB,
+// enough for 4.79M cells (the 256 x 256 x 64 grid's 4.19M fit).  Each device
+// holds its own copy for the life of the process.  In host code the name is
+// a host-side stand-in: device code reaches the array only through the
+// address hipGetSymbolAddress returns for the current device (kept below).
+constexpr size_t SCRATCH_DOUBLES = (size_t)32 << 20;
+__device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+
+constexpr int SCRATCH_MAX_DEV = 64;
+static double* g_scratch[SCRATCH_MAX_DEV] = {nullptr};
+
+// The current device's copy of `scratch` (resolved once per device, with
+// that device current; tp_init calls it, the entry point too on a device
+// tp_init has not seen).
+double* scratch_ptr() {
+    int dev = 0;
+    TP_HIP(hipGetDevice(&dev));
+    TP_CHECK_ARG(dev >= 0 && dev < SCRATCH_MAX_DEV, "device %d beyond the scratch table", dev);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        TP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch[dev] = static_cast<double*>(p);
+    }
+    return g_scratch[dev];
+}
+
 }  // namespace tp
+
 
 extern "C" {
 
@@ -829,6 +863,31 @@ int precond_apply(tp_prec_t M, const double* r, double* z, void* stream) {
             tp::prec_apply_split(M, M->rs.p, M->zs.p, s);
             TP_LAUNCH(tp::k_interleave, tp::cdiv(n, tp::KB), tp::KB, 0, s, n, M->zs.p, z);
         }
+    });
+    return TP_OK;
+}
+
+int precond_apply_noalloc(tp_prec_t M, const double* r, double* z, void* stream) {
+    TP_GUARD({
+        TP_CHECK_ARG(M && r && z, "precond_apply_noalloc: null argument");
+        TP_CHECK_ARG(!tp::timer().on, "precond_apply_noalloc: the smoother timer is on (it records events)");
+        hipStream_t s = (hipStream_t)stream;
+        const int32_t n = M->J.n;
+        const size_t need = 4 * (size_t)n + (M->variant == 3 ? 3 * (size_t)n : 0);
+        if (need > tp::SCRATCH_DOUBLES)
+            tp::fail(TP_ERR_CAPACITY,
+                     "precond_apply_noalloc: %zu doubles of work space needed, the fixed scratch holds %zu "
+                     "(n = %d cells; at most %zu cells, %zu for CPR)",
+                     need, tp::SCRATCH_DOUBLES, n, tp::SCRATCH_DOUBLES / 4, tp::SCRATCH_DOUBLES / 7);
+        double* w = tp::scratch_ptr();
+        double* rs = w;
+        double* zs = w + 2 * (size_t)n;
+        double* cw = M->variant == 3 ? w + 4 * (size_t)n : nullptr;
+        double* cb = M->variant == 3 ? w + 5 * (size_t)n : nullptr;
+        tp::note_stream(M, s);
+        TP_LAUNCH(tp::k_deinterleave, tp::cdiv(n, tp::KB), tp::KB, 0, s, n, r, rs);
+        tp::prec_apply_split(M, rs, zs, s, cw, cb);
+        TP_LAUNCH(tp::k_interleave, tp::cdiv(n, tp::KB), tp::KB, 0, s, n, zs, z);
     });
     return TP_OK;
 }

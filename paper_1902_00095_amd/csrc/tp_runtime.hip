@@ -338,6 +338,7 @@ int tp_init(const tp_allocator* alloc, int device) {
         }
         TP_HIP(hipSetDevice(device));
         tp::g_device = device;
+        (void)tp::scratch_ptr();  // the device's copy of the allocation-free apply's scratch
         // keep freed blocks in the device's stream-ordered pool instead of
         // returning them to the driver at every synchronisation
         hipMemPool_t pool = nullptr;

@@ -77,7 +77,7 @@ class _Allocator(C.Structure):
 
 EXPORTS = ["tp_last_error", "tp_init", "tp_jacobian_sizes", "assemble_tpfa", "assemble_tpfa_aniso", "amg_setup", "amg_setup_schur_diag", "amg_refresh_fine", "amg_refresh",
            "amg_num_levels", "amg_level_info", "amg_level_format", "amg_level_copy", "amg_vcycle", "amg_destroy",
-           "precond_create", "precond_apply", "precond_destroy", "fgmres_solve",
+           "precond_create", "precond_apply", "precond_apply_noalloc", "precond_destroy", "fgmres_solve",
            "ilu0_create", "ilu0_create_jacobian", "ilu0_refactor_jacobian", "ilu0_solve", "ilu0_info",
            "ilu0_copy", "ilu0_destroy", "precond_create_cpr",
            "cnn_create", "cnn_get_params", "cnn_get_grad", "cnn_destroy", "cnn_forward", "cnn_loss_grad",
@@ -519,6 +519,12 @@ class Precond:
         if z is None:
             z = torch.empty_like(r)
         _check(_lib.precond_apply(self.h, _ptr(r), _ptr(z), _stream(stream)))
+        return z
+
+    def apply_noalloc(self, r, z, stream=None):
+        """The same apply with no device allocation by the library (fixed
+        device scratch; see precond_apply_noalloc)."""
+        _check(_lib.precond_apply_noalloc(self.h, _ptr(r), _ptr(z), _stream(stream)))
         return z
 
     def close(self):
