@@ -1,17 +1,33 @@
-"""Benchmark: time-to-rtol 1e-8 of one coupled pressure-temperature solve.
+"""Benchmark: time-to-rtol 1e-8 per coupled pressure-temperature solve,
+mixed precision + learned post-smoother against plain FP64, and V-cycle GB/s.
 
-A step is one pass of the whole hot path on the 64x64x32 layered workload
-(262,144 unknowns): TPFA assembly of the Jacobian and Schur approximation,
-AMG setup of A_pp and of S, block lower-triangular preconditioner, FGMRES(30)
-with CGS2 to a true relative residual <= 1e-8.  Inputs (fields and states)
-are resident in HBM before the timed region.  One JSON line on stdout.
+Headline workload: the 256x256x64 grid (4,194,304 cells, 8,388,608
+unknowns), layered log-normal permeability with channel streaks, corner wells
+(450 K injection), thermal conductivity 20 W/m/K, uniform initial state.  Its
+Newton systems of the first backward-Euler steps (day 1, 2) are produced by
+the GPU time stepper before the timed region and kept in HBM.  A step is one
+coupled solve of one of them: TPFA assembly of the Jacobian blocks and of
+S~_T, AMG setup of A_pp and of S~_T, the block lower-triangular
+preconditioner and FGMRES(30) with CGS2 to a true relative residual <= 1e-8.
+`value` times it in the mixed-precision + learned form (FP32 hierarchies and
+V-cycles, the trained network as the Schur hierarchy's finest-level
+post-smoother, FP64 outer loop, residuals and coarsest inverse); the same
+steps in the plain FP64 form are timed next and reported beside it with the
+ratio.  One JSON line on stdout; progress on stderr.
 
 Extra objects in the line:
-  roofline      the fine-level smoother sweep (the V-cycle's dominant
-                kernel): algorithmic bytes per launch / mean launch time from
-                HIP events recorded on its stream during the timed steps;
-  cpu_baseline  the CPU FP64 oracle, single-threaded, on the same workload
-                (one full solve), run on rank 0 only.
+  roofline      the timed form's dominant kernel, the finest-level Chebyshev
+                step (FP32 values and vectors, seven diagonals):
+                algorithmic bytes per launch / mean launch duration, from HIP
+                event pairs carried by every launch of that kernel during two
+                more solves of the timed form on the same stream;
+  cpu_baseline  the CPU FP64 oracle, single-threaded, on one of the same
+                Newton systems: assembly and both AMG setups timed once,
+                GMRES iterations timed as the median of three one-iteration
+                runs, scaled to a whole solve by the plain GPU path's
+                iteration count; the same computations check the GPU's
+                assembly, every hierarchy level's C/F split and pattern, and
+                the first residual estimate on that system.
 """
 from __future__ import annotations
 
@@ -25,135 +41,166 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+RTOL = 1e-8
 
-WORKLOADS = {
-    "W2": dict(desc="64x64x32 layered log-normal permeability, corner wells 450 K, "
-                    "perturbed Newton state, FP64 plain method"),
-    "W3": dict(desc="128x128x64 layered log-normal permeability, corner wells 450 K, "
-                    "perturbed Newton state"),
-    "W4": dict(desc="96^3 channelised permeability, hot injection 550 K, perturbed state"),
-}
+HEADLINE = ("256x256x64 (8,388,608 unknowns) layered log-normal permeability with channel streaks, "
+            "corner wells 450 K, thermal conductivity 20 W/m/K, Newton systems of backward-Euler "
+            "steps 1-2 (dt 1 day)")
 
 
-def _time_solves(prob, dev, cfg, reps, attach=None):
-    import numpy as np
+def _progress(msg):
+    """One line per finished stage on stderr (the JSON result stays the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _sync_time():
     import torch
+    torch.cuda.synchronize()
+    return time.perf_counter()
 
+
+# ---- the learned post-smoother ------------------------------------------------------------------
+def trained_network(quick=False):
+    """The network trained on the GPU by the library's own kernels (learned.train_c4),
+    with its training record."""
+    from paper_1902_00095_amd import learned
+    t0 = time.perf_counter()
+    net, rec = learned.train_c4(quick=quick)
+    rec["seconds"] = round(time.perf_counter() - t0, 2)
+    return net, rec
+
+
+# ---- Newton systems of the headline workload -------------------------------------------------
+def newton_systems(prob, steps):
+    """(x_prev, x_k) before every linear solve of the first `steps` time steps,
+    from the GPU time stepper (FP32 hierarchies); device tensors."""
     from paper_1902_00095_amd import solver
-    from paper_1902_00095_amd import tpsolve as tps
     out = []
-    for _ in range(reps + 1):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        J, G = solver.assemble(prob, dev)
-        a_pp, a_S, M = solver.setup(J, cfg)
-        if attach is not None:
-            a_S.attach(attach, prob.grid)
-        x, st = tps.fgmres_solve(J, M, -G, rtol=cfg.rtol, restart=cfg.restart, maxit=cfg.maxit)
-        torch.cuda.synchronize()
-        st["ms"] = (time.perf_counter() - t0) * 1e3
-        st["x"] = x
-        if attach is not None:
+
+    def rec(step, k, xp, xk):
+        out.append((step, k, xp.clone(), xk.clone()))
+    solver.simulate(prob, solver.SolveConfig(storage=1), solver.NewtonConfig(steps=steps), on_solve=rec)
+    return out
+
+
+class Solves:
+    """One coupled solve per call on a workload's device fields."""
+
+    def __init__(self, prob):
+        from paper_1902_00095_amd import solver
+        self.prob = prob
+        self.dev = solver.to_device(prob)
+        self.J = self.G = None
+
+    def assemble(self, system):
+        from paper_1902_00095_amd import solver
+        if system is not None:
+            self.dev["x_prev"], self.dev["x_k"] = system[2], system[3]
+        self.J, self.G = solver.assemble(self.prob, self.dev, self.J, self.G)
+
+    def run(self, system, cfg, net=None, keep=False, history=False, guard=None):
+        """With `net`: the learned post-smoother on the Schur hierarchy; with a
+        LearnedGuard as well, the guard decides whether this solve uses it and
+        passes its contraction bound (and records the solve)."""
+        import torch
+
+        from paper_1902_00095_amd import solver
+        from paper_1902_00095_amd import tpsolve as tps
+        if system is not None:
+            self.dev["x_prev"], self.dev["x_k"] = system[2], system[3]
+        self.J, self.G = solver.assemble(self.prob, self.dev, self.J, self.G)
+        a_pp, a_S, M = solver.setup(self.J, cfg)
+        learned = net is not None and (guard is None or guard.use_net())
+        if learned:
+            a_S.attach(net, self.prob.grid)
+        tf = time.perf_counter()
+        x, st = tps.fgmres_solve(self.J, M, -self.G, rtol=cfg.rtol, restart=cfg.restart, maxit=cfg.maxit,
+                                 history=history, ref_rate=guard.ref_rate() if (learned and guard) else 0.0)
+        if guard is not None:
+            torch.cuda.synchronize()
+            guard.record(st, time.perf_counter() - tf, learned)
+        if learned:
             a_S.attach(None, None)
+        if keep:
+            return x, st, (a_pp, a_S, M)
         M.close(); a_pp.close(); a_S.close()
-        out.append(st)
-    best = out[1:]
-    res = dict(ms_per_solve=round(float(np.median([s["ms"] for s in best])), 3),
-               iters=best[-1]["iters"], rel_true=best[-1]["rel_true"],
-               fallback_iter=best[-1]["fallback_iter"], converged=best[-1]["converged"])
-    return res, best[-1]["x"]
+        return x, st
+
+
+def timed_steps(S, systems, cfg, net, steps, warmup):
+    """Warm-up steps, then exactly `steps` timed ones between synchronisations.
+    With a network, one LearnedGuard follows all of them (the first warm-up
+    solve is the plain calibration solve)."""
+    from paper_1902_00095_amd import solver
+    guard = solver.LearnedGuard() if net is not None else None
+    for i in range(warmup):
+        S.run(systems[i % len(systems)], cfg, net, guard=guard)
+    t0 = _sync_time()
+    stats = []
+    for i in range(steps):
+        _, st = S.run(systems[i % len(systems)], cfg, net, guard=guard)
+        stats.append(st)
+    t1 = _sync_time()
+    if guard is not None:
+        stats[-1]["guard"] = guard.stats()
+    return (t1 - t0) * 1e3 / steps, stats
+
+
+def _summ(stats):
+    import numpy as np
+    its = [s["iters"] for s in stats]
+    out = {"fgmres_iters_mean": round(float(np.mean(its)), 2), "fgmres_iters": its,
+           "max_rel_true": max(s["rel_true"] for s in stats),
+           "all_converged": all(s["converged"] for s in stats),
+           "network_switched_off_in": sum(1 for s in stats if s["fallback_iter"] >= 0)}
+    if "guard" in stats[-1]:
+        out["guard"] = stats[-1]["guard"]
+    return out
 
 
 def _block_err(x, ref):
     import torch
-    e = []
-    for blk in (0, 1):
-        a, b = x[blk::2], ref[blk::2]
-        e.append(float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)))
-    return e
+    return [float(torch.linalg.vector_norm(x[b::2] - ref[b::2]) / torch.linalg.vector_norm(ref[b::2]))
+            for b in (0, 1)]
 
 
-def _apply_numbers(prob, dev, cfg):
-    """Preconditioner apply time and algorithmic GB/s (both V-cycles), and the
-    fine-level sweep replayed back to back, for one assembled system."""
+# ---- V-cycle throughput -----------------------------------------------------------------------
+def apply_numbers(S, system, cfg, net=None):
+    """Preconditioner apply time and algorithmic GB/s of its two V-cycles on one
+    Newton system, and the finest-level Chebyshev step replayed back to back."""
     import torch
-
-    from paper_1902_00095_amd import solver
-    J, G = solver.assemble(prob, dev)
-    a_pp, a_S, M = solver.setup(J, cfg)
-    b = -G
+    _, _, (a_pp, a_S, M) = S.run(system, cfg, net, keep=True)
+    if net is not None:
+        a_S.attach(net, S.prob.grid)
+    b = -S.G
     z = torch.empty_like(b)
     for _ in range(3):
         M.apply(b, z)
-    torch.cuda.synchronize()
-    nrep = 30
-    t0 = time.perf_counter()
+    nrep = 20
+    t0 = _sync_time()
     for _ in range(nrep):
         M.apply(b, z)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / nrep
+    ms = (_sync_time() - t0) * 1e3 / nrep
     vb = a_pp.vcycle_bytes() + a_S.vcycle_bytes()
-    rep_ms, rep_bytes = a_S.time_fine_smoother(200)
-    out = {"apply_ms": round(ms, 4), "vcycle_bytes": int(vb), "vcycle_pair_GBps": round(vb / (ms * 1e-3) / 1e9, 1),
-           "fine_sweep_us": round(rep_ms * 1e3, 3),
-           "fine_sweep_GBps": round(rep_bytes / (rep_ms * 1e-3) / 1e9, 1),
+    rep_ms, rep_bytes = a_S.time_fine_smoother(100)
+    if net is not None:
+        a_S.attach(None, None)
+    out = {"apply_ms": round(ms, 4), "vcycle_pair_bytes": int(vb),
+           "vcycle_pair_GBps": round(vb / (ms * 1e-3) / 1e9, 1),
+           "vcycle_pair_frac_of_8TBps": round(vb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "fine_sweep_replay_us": round(rep_ms * 1e3, 3),
+           "fine_sweep_replay_GBps": round(rep_bytes / (rep_ms * 1e-3) / 1e9, 1),
            "levels": [a_pp.nlev, a_S.nlev]}
     M.close(); a_pp.close(); a_S.close()
     return out
 
 
-def _cpr_numbers(prob, dev):
-    """CPR's pieces on one assembled system: ILU(0) creation (level analysis
-    on the host plus the numeric factorisation), refactorisation (numeric
-    only, as a Newton iteration on the same pattern), one ILU solve, one
-    preconditioner apply."""
-    import torch
-
-    from paper_1902_00095_amd import solver
-    from paper_1902_00095_amd import tpsolve as tps
-
-    def tsync():
-        torch.cuda.synchronize()
-        return time.perf_counter()
-    J, G = solver.assemble(prob, dev)
-    t0 = tsync()
-    F = tps.ILU0.jacobian(J)
-    t1 = tsync()
-    F.refactor(J)
-    t2 = tsync()
-    b = -G[: 2 * J.n].clone()
-    x = torch.empty_like(b)
-    F.solve(b, x)
-    t3 = tsync()
-    for _ in range(20):
-        F.solve(b, x)
-    t4 = tsync()
-    a_pp = tps.AMG(J.rowptr, J.col, J.pp, solver.SolveConfig().amg)
-    M = tps.Precond.cpr(J, a_pp, F)
-    z = torch.empty_like(b)
-    for _ in range(3):
-        M.apply(b, z)
-    t5 = tsync()
-    for _ in range(20):
-        M.apply(b, z)
-    t6 = tsync()
-    inf = F.info()
-    out = {"ilu_create_ms": round((t1 - t0) * 1e3, 3), "ilu_refactor_ms": round((t2 - t1) * 1e3, 3),
-           "ilu_solve_ms": round((t4 - t3) * 1e3 / 20, 4), "apply_ms": round((t6 - t5) * 1e3 / 20, 4),
-           "levels_lower_upper": [inf["levels_lower"], inf["levels_upper"]]}
-    M.close(); a_pp.close(); F.close()
-    return out
-
-
-# The roofline kernel's HBM traffic record: scaled FETCH_SIZE + WRITE_SIZE per
-# dispatch from two rocprofv3 --pmc runs of `bench.py --quick`, keyed by a hash
-# of the kernel's source text (reported only while the text is unchanged).
-TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_k_cheb_step_dia_W2.json")
-TRAFFIC_KERNEL = "k_cheb_step_dia_r<double, double, 7, 128, 2>"
+# ---- HBM traffic record of the roofline kernel (rocprofv3 --pmc) ------------------------------
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_k_cheb_step_dia_f32_256x256x64.json")
+TRAFFIC_KERNEL = "k_cheb_step_dia<float, float, 7>"
 TRAFFIC_SRC = "paper_1902_00095_amd/csrc/tp_vcycle.hip"
-TRAFFIC_START = "// R consecutive rows per thread"
-TRAFFIC_END = ("template <typename T, typename V, int ND, int VBk, int R>\n__global__ void __launch_bounds__(VBk)\n"
-               "k_residual_dia_r")
+TRAFFIC_START = "// ---- DIA (stencil-level) kernels"
+TRAFFIC_END = "// R consecutive rows per thread"
 CALIB_BYTES = 32 * 1024 * 1024 * 8   # the calibration copy reads and writes this many bytes
 
 
@@ -184,7 +231,8 @@ def write_traffic(fetch_db, write_db):
         sys.exit(f"no dispatch of {TRAFFIC_KERNEL} in {fetch_db} / {write_db}")
     fs, ws = CALIB_BYTES / (cf * 1024), CALIB_BYTES / (cw * 1024)
     mf, mw = statistics.mean(vf), statistics.mean(vw)
-    rec = dict(kernel=TRAFFIC_KERNEL, workload="W2 64x64x32 FP64", dispatches=len(vf), fetch_kib=mf, write_kib=mw,
+    rec = dict(kernel=TRAFFIC_KERNEL, workload="256x256x64 mixed precision + learned (FP32 finest level)",
+               dispatches=len(vf), fetch_kib=mf, write_kib=mw,
                calibration_fetch_kib=cf, calibration_write_kib=cw, fetch_scale=fs, write_scale=ws,
                traffic_bytes_per_launch=mf * 1024 * fs + mw * 1024 * ws, source=TRAFFIC_SRC,
                source_sha256=_kernel_text_hash(), source_start=TRAFFIC_START, source_end=TRAFFIC_END)
@@ -193,204 +241,169 @@ def write_traffic(fetch_db, write_db):
     print(json.dumps(rec))
 
 
-def _progress(msg):
-    """One line per finished stage on stderr (the JSON result stays the only stdout line)."""
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+def _traffic():
+    if not os.path.exists(TRAFFIC_JSON):
+        return None
+    rec = json.load(open(TRAFFIC_JSON))
+    if rec.get("source_sha256") == _kernel_text_hash() and rec.get("kernel") == TRAFFIC_KERNEL:
+        return round(rec["traffic_bytes_per_launch"])
+    return None
 
 
-def run_variants(prob, dev, cfg, iters64, ms64):
-    """Mixed precision at the benchmark workload and at 128x128x64 (where the
-    fine levels dominate the V-cycle); the learned smoother trained here on
-    the GPU and compared on a channelised (W4-recipe) grid."""
+# ---- CPU oracle on one headline system --------------------------------------------------------
+def _host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(S, system, plain_iters, cfg64, run20=None):
+    """The oracle on one Newton system of the headline workload (see the module
+    docstring); returns the cpu_baseline object with its parity checks.  With
+    `run20` (the plain FP64 GPU run's stats over 20 time steps), the oracle's
+    time per solve is also extrapolated to the systems of steps 1, 10 and 20:
+    the measured assembly, setup and per-iteration times with that step's
+    mean GPU iteration count per solve."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1902_00095_amd import tpsolve as tps
+    oracle.build(force=False)
+    p = dataclasses.replace(S.prob, x_prev=system[2].cpu().numpy(), x_k=system[3].cpu().numpy())
+    t0 = time.perf_counter()
+    Jo = oracle.jacobian(p)
+    bo = -oracle.residual(p)
+    t_asm = time.perf_counter() - t0
+    _progress(f"oracle assembly {t_asm:.1f} s")
+    S.assemble(system)              # the GPU's own assembly of the same system
+    g_err = float(np.abs(S.G.cpu().numpy() + bo).max() / np.abs(bo).max())
+    j_err = max(float(np.abs(getattr(S.J, k).cpu().numpy() - getattr(Jo, k)).max() / np.abs(getattr(Jo, k)).max())
+                for k in ("pp", "pT", "Tp", "TT", "S"))
+    from paper_1902_00095_amd import solver
+    prm = {w: solver.amg_params(cfg64, w) for w in ("pp", "S")}
+    t0 = time.perf_counter()
+    ao_pp = oracle.AMG(Jo.n, Jo.rowptr, Jo.col, Jo.pp, **prm["pp"].oracle_kwargs())
+    ao_S = oracle.AMG(Jo.n, Jo.rowptr, Jo.col, Jo.S, **prm["S"].oracle_kwargs())
+    t_setup = time.perf_counter() - t0
+    _progress(f"oracle setups {t_setup:.1f} s")
+    # the GPU hierarchies of the oracle's operators: every level's split and pattern
+    Jd = tps.Jacobian.from_host(Jo.n, Jo.rowptr, Jo.col, Jo.pp, Jo.pT, Jo.Tp, Jo.TT, Jo.S)
+    split_ok, levels = True, []
+    for val, ho, w in ((Jd.pp, ao_pp, "pp"), (Jd.S, ao_S, "S")):
+        hg = tps.AMG(Jd.rowptr, Jd.col, val, prm[w])
+        levels.append(hg.nlev)
+        split_ok &= hg.nlev == ho.nlev
+        for l in range(min(hg.nlev, ho.nlev) - 1):
+            Lg, Lo = hg.level(l), ho.level(l)
+            split_ok &= bool(np.array_equal(Lg["cf"].cpu().numpy(), Lo["cf"]))
+            for k in ("A_col", "P_col", "R_col"):
+                split_ok &= bool(np.array_equal(Lg[k].cpu().numpy(), Lo[k]))
+        hg.close()
+    # GMRES: one-iteration runs (initial residual, one preconditioned Arnoldi
+    # step, the closing true residual), the median of three
+    t_it = []
+    h1 = None
+    for _ in range(3):
+        t0 = time.perf_counter()
+        _, io = oracle.gmres(Jo, ao_pp, ao_S, bo, rtol=RTOL, maxit=1)
+        t_it.append(time.perf_counter() - t0)
+        h1 = io["history"]
+    t_iter = float(np.median(t_it))
+    _progress(f"oracle GMRES iteration {t_iter:.1f} s")
+    # the GPU's first residual estimate on the same operators
+    a_pp, a_S, M = solver.setup(Jd, cfg64)
+    _, stg = tps.fgmres_solve(Jd, M, torch.as_tensor(bo, device="cuda"), rtol=RTOL, maxit=1, history=True)
+    M.close(); a_pp.close(); a_S.close()
+    h_diff = float(abs(stg["history"][1] - h1[1]) / h1[1])
+    model, ncpu = _host_cpu()
+    per_solve_s = t_asm + t_setup + plain_iters * t_iter
+    at_steps = None
+    if run20 and run20.get("linear_per_step"):
+        lps, nps = run20["linear_per_step"], run20["newton_per_step"]
+        at_steps = {}
+        for stp in (1, 10, 20):
+            if stp <= len(lps) and nps[stp - 1] > 0:
+                its = lps[stp - 1] / nps[stp - 1]
+                at_steps[str(stp)] = {"gpu_fp64_iters_per_solve": round(its, 2),
+                                      "oracle_ms_per_solve": round((t_asm + t_setup + its * t_iter) * 1e3, 1)}
+    return {"value": round(per_solve_s * 1e3, 1), "unit": "ms/solve", "cores": 1, "kind": "oracle",
+            "sample": (f"one Newton system of the headline workload (step {system[0] + 1}, Newton iteration "
+                       f"{system[1]}): assembly {t_asm:.2f} s and both AMG setups {t_setup:.2f} s timed once, "
+                       f"GMRES at {t_iter:.2f} s per iteration (median of 3 one-iteration runs) times the "
+                       f"plain GPU path's {plain_iters} iterations; single-threaded FP64 C"),
+            "assembly_s": round(t_asm, 3), "setup_s": round(t_setup, 3), "gmres_s_per_iteration": round(t_iter, 3),
+            "gmres_iteration_runs_s": [round(t, 3) for t in t_it],
+            "host_cpu_model": model, "host_cpu_count": ncpu,
+            "extrapolated_to_steps_1_10_20_kappa_20": at_steps,
+            "parity": {"G_rel_err": g_err, "jacobian_blocks_rel_err": j_err,
+                       "hierarchy_splits_and_patterns_bit_exact": bool(split_ok), "levels": levels,
+                       "first_residual_estimate_rel_diff": h_diff}}
+
+
+# ---- the full 256x256x64 runs (20 steps, both conductivities) ---------------------------------
+def c5_runs(net, kappa):
+    """20 backward-Euler steps x <= 4 Newton iterations, every Newton iteration
+    a coupled solve to rtol 1e-8: plain FP64, mixed + learned, and both with
+    the numeric hierarchy refresh within each time step."""
     import dataclasses as dc
 
-    from paper_1902_00095_amd import learned, solver, synth
-    from paper_1902_00095_amd import tpsolve as tps
+    from paper_1902_00095_amd import solver, synth
+    prob = synth.make_problem("W5", kappa=kappa)
+    cfg = solver.SolveConfig(rtol=RTOL)
+    forms = [("fp64", cfg, None, solver.NewtonConfig(steps=20)),
+             ("mixed_learned", dc.replace(cfg, storage=1), net, solver.NewtonConfig(steps=20)),
+             ("fp64_numeric_reuse", cfg, None, solver.NewtonConfig(steps=20, reuse="numeric")),
+             ("mixed_learned_numeric_reuse", dc.replace(cfg, storage=1), net,
+              solver.NewtonConfig(steps=20, reuse="numeric"))]
     out = {}
-    r64, x64 = _time_solves(prob, dev, cfg, 2)
-    r32, x32 = _time_solves(prob, dev, dc.replace(cfg, storage=1), 2)
-    r32["err_vs_fp64_per_block"] = _block_err(x32, x64)
-    r16, x16 = _time_solves(prob, dev, dc.replace(cfg, storage=2), 2)
-    r16["err_vs_fp64_per_block"] = _block_err(x16, x64)
-    out["fp64"] = r64
-    out["fp32_hierarchy"] = r32
-    out["bf16_offdiag_hierarchy"] = r16
-    rx, _ = _time_solves(prob, dev, dc.replace(cfg, interp_pp=1), 2)
-    out["fp64_ext_i_pressure"] = rx
-    _progress("W2 storage variants done")
-    # 128x128x64 (2.1M unknowns): FP64 and FP32 hierarchy, V-cycle throughput
-    p3 = synth.make_problem("W3")
-    d3 = solver.to_device(p3)
-    w64, y64 = _time_solves(p3, d3, cfg, 2)
-    w32, y32 = _time_solves(p3, d3, dc.replace(cfg, storage=1), 2)
-    w32["err_vs_fp64_per_block"] = _block_err(y32, y64)
-    w16, y16 = _time_solves(p3, d3, dc.replace(cfg, storage=2), 2)
-    w16["err_vs_fp64_per_block"] = _block_err(y16, y64)
-    w64.update(_apply_numbers(p3, d3, cfg))
-    w32.update(_apply_numbers(p3, d3, dc.replace(cfg, storage=1)))
-    w16.update(_apply_numbers(p3, d3, dc.replace(cfg, storage=2)))
-    wx, _ = _time_solves(p3, d3, dc.replace(cfg, interp_pp=1), 2)
-    _progress("W3 done")
-    out["W3_128x128x64"] = {"fp64": w64, "fp32_hierarchy": w32, "bf16_offdiag_hierarchy": w16,
-                            "fp64_ext_i_pressure": wx,
-                            "note": "FP32 error is against the FP64 GPU solution at the same rtol"}
-    del d3, y64, y32, y16
-    # learned post-smoother: train (operator-norm loss) on seeded W4-recipe fields
-    t0 = time.perf_counter()
-    g_train = synth.Grid(24, 24, 24, 1.0, 1.0, 1.0)
-    net = tps.Net(learned.init_params())
-    samples = learned.make_pairs(range(1000, 1032), g_train, net=net, smooth_y=1)
-    losses = learned.train(net, samples, 2000, lr=3e-3)
-    train_s = time.perf_counter() - t0
-    for smp in samples:
-        smp.amg.attach(None, None)
-        smp.amg.close()
-    g_eval = synth.Grid(48, 48, 48, 1.0, 1.0, 1.0)
-    pe = synth.make_problem("W4", seed=4001, grid=g_eval)
-    de = solver.to_device(pe)
-    e_plain, xe = _time_solves(pe, de, cfg, 2)
-    e_learn, xl = _time_solves(pe, de, cfg, 2, attach=net)
-    e_mixl, xm = _time_solves(pe, de, dc.replace(cfg, storage=1), 2, attach=net)
-    e_learn["err_vs_plain_per_block"] = _block_err(xl, xe)
-    e_mixl["err_vs_plain_per_block"] = _block_err(xm, xe)
-    out["learned_eval"] = {"workload": "W4 recipe 48x48x48, seed 4001",
-                           "training": {"fields": "W4 recipe 24^3, seeds 1000-1031", "steps": 2000,
-                                        "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
-                                        "seconds": round(train_s, 2)},
-                           "plain_fp64": e_plain, "learned_fp64": e_learn, "mixed_learned": e_mixl}
-    _progress("learned smoother trained and evaluated")
-    # the simple Schur approximations the paper compares S~_T with (W2)
-    sch = {}
-    for key in ("T", "ATT", "diag"):
-        rs, _ = _time_solves(prob, dev, dc.replace(cfg, schur=key, maxit=200), 1)
-        sch[{"T": "S_T", "ATT": "A_TT", "diag": "S_diag"}[key]] = rs
-    out["schur_approximations_W2"] = dict(sch, note="FGMRES capped at 200 iterations")
-    # the CPR comparator (Section 3.1): AMG V-cycle on A_pp, then ILU(0) of the whole Jacobian
-    cw2, _ = _time_solves(prob, dev, dc.replace(cfg, method="cpr"), 2)
-    cw2.update(_cpr_numbers(prob, dev))
-    p3 = synth.make_problem("W3")
-    d3 = solver.to_device(p3)
-    cw3, _ = _time_solves(p3, d3, dc.replace(cfg, method="cpr"), 2)
-    cw3.update(_cpr_numbers(p3, d3))
-    del d3
-    out["cpr"] = {"W2": cw2, "W3_128x128x64": cw3,
-                  "note": "ms_per_solve includes assembly, the A_pp hierarchy and a fresh ILU(0) (level "
-                          "analysis included); a Newton loop refactorises instead (ilu_refactor_ms)"}
-    _progress("CPR done")
-    # mesh refinement (Section 4's problem-size study): N x N cells of a
-    # 20 m square, homogeneous, corner wells, two backward-Euler steps from a
-    # uniform state; linear iterations per Newton iteration (the paper's
-    # measure) for the block preconditioner (direct interpolation, and
-    # extended+i on the pressure hierarchy) and for CPR
-    ref = {}
-    for N in (20, 40, 80, 160, 320, 640):
-        g = synth.Grid(N, N, 1, 20.0 / N, 20.0 / N, 1.0)
-        pr = synth.make_problem("R2", grid=g)
+    for key, c, nt, nc in forms:
+        _, st = solver.simulate(prob, c, nc, net=nt)
+        st.pop("step_lengths", None)
+        out[key] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+        _progress(f"256x256x64 kappa {kappa} {key}: {st['solves']} solves, {st['total_s']:.1f} s")
+    out["mixed_learned_vs_fp64_time"] = round(out["mixed_learned"]["total_s"] / out["fp64"]["total_s"], 3)
+    return out
+
+
+def smaller_workloads():
+    """The 64x64x32 and 128x128x64 layered workloads (perturbed Newton state):
+    FP64, FP32 and FP32 + BF16 off-diagonal hierarchies, solve time and V-cycle
+    throughput; CPR on 64x64x32."""
+    import dataclasses as dc
+
+    from paper_1902_00095_amd import solver, synth
+    out = {}
+    for name in ("W2", "W3"):
+        prob = synth.make_problem(name)
+        S = Solves(prob)
         row = {}
-        for key, cr in (("block", dc.replace(cfg, maxit=400)), ("block_ext_i_pressure", dc.replace(cfg, maxit=400, interp_pp=1)),
-                        ("cpr", dc.replace(cfg, method="cpr", maxit=400))):
-            _, sr = solver.simulate(pr, cr, solver.NewtonConfig(steps=2))
-            row[key] = {"linear_per_newton": round(sr["linear_per_newton"], 2), "newton_iters": sr["newton_iters"],
-                        "ms_per_solve": round(sr["ms_per_solve"], 3), "unconverged_steps": sr["unconverged_steps"]}
-        ref[f"{N}x{N}"] = row
-    # the paper's own cases of the problem-size study (Section 4, tables isoH, isoW,
-    # isoHighW, anisoH and anisoW), on this build's physics: linear iterations per Newton
-    # iteration over two steps, with the published figures beside them (PETSc/BoomerAMG,
-    # serial CPU; the paper's "> 200" entries as None); GMRES to rtol 1e-5, the paper's
-    # tolerance for this study (Section 4, opening).  At 1e-8 the heater cases sit below FP64's
-    # attainable accuracy on the finer grids (|A| |x| / |b| ~ 1e7: even a direct solve
-    # leaves 3e-8), so FGMRES would run to its cap there.  The fluid is the paper's heavy
-    # oil (Bennison viscosity, API gravity 10) and Newton takes its line search (Section 4, opening),
-    # without the workloads' cap of 4 iterations per step
-    paper_tab = {"CaseI": {"block": [2.57, 3.23, 2.86, 3.44, 3.71], "cpr": [3.4, 5.38, 9.09, 16.3, 30.7]},
-                 "CaseII": {"block": [2.43, 2.43, 2.86, 3.28, 3.71], "cpr": [3.71, 5.71, 9.86, 19.4, 37.4],
-                            "block_S_ATT": [4.57, 5.0, 5.57, 6.29, 6.57],
-                            "block_S_diag": [4.14, 4.43, 5.29, 5.86, 6.43]},
-                 "CaseIII": {"block": [3.67, 4.38, 4.7, 5.10, 5.52], "cpr": [4.71, 7.31, 13.1, 24.7, 50.6]},
-                 "CaseIV": {"block": [2.31, 2.67, 3.25, 3.67, 3.86], "cpr": [3.11, 4.56, 8.56, 15.8, 30.4]},
-                 "CaseV": {"block": [2.38, 3.27, 4.52, 4.68, 5.36], "cpr": [2.86, 3.6, 4.76, 7.0, 12.04],
-                           "block_S_ATT": [9, 17.1, 24.1, 27.9, 31.6], "block_S_diag": [None] * 5}}
-    cases = {}
-    for case in ("CaseI", "CaseII", "CaseIII", "CaseIV", "CaseV"):
-        rows = {}
-        for N in (20, 40, 80, 160, 320):
-            g = synth.Grid(N, N, 1, 20.0 / N, 20.0 / N, 1.0)
-            pc = synth.make_problem(case, grid=g, props=synth.Props(api=10.0))
-            c5 = dc.replace(cfg, rtol=1e-5, maxit=400)
-            forms = [("block", c5), ("block_ext_i_pressure", dc.replace(c5, interp_pp=1)),
-                     ("cpr", dc.replace(c5, method="cpr"))]
-            if case in ("CaseII", "CaseV"):
-                forms += [("block_S_ATT", dc.replace(c5, schur="ATT")),
-                          ("block_S_diag", dc.replace(c5, schur="diag")),
-                          ("block_S_ATT_ext_i_pressure", dc.replace(c5, schur="ATT", interp_pp=1)),
-                          ("block_S_diag_ext_i_pressure", dc.replace(c5, schur="diag", interp_pp=1))]
-            row = {}
-            for key, cr in forms:
-                try:
-                    _, sr = solver.simulate(pc, cr, solver.NewtonConfig(steps=2, max_newton=20, line_search=True))
-                except tps.TpError as e:
-                    # a weak preconditioner can steer Newton out of the fluid laws' range
-                    # (T below 0 F has no Bennison viscosity); the setup then reports it
-                    row[key] = None
-                    row[key + "_failed"] = str(e)[:120]
-                    continue
-                row[key] = round(sr["linear_per_newton"], 2)
-                if sr["unconverged_steps"]:
-                    row[key + "_unconverged_steps"] = sr["unconverged_steps"]
-            rows[f"{N}x{N}"] = row
-        cases[case] = {"this_build": rows, "paper": paper_tab[case]}
-    out["paper_cases_2d"] = dict(cases, note="linear iterations per Newton iteration, 2 steps of 10 days "
-                                 "(Case V: 12 hours), Bennison heavy oil (API 10), Newton with line search, FGMRES to rtol 1e-5 capped at 400; paper: Section 4 tables isoH (Case I), "
-                                 "isoW (Case II), isoHighW (Case III), anisoH (Case IV) and anisoW (Case V), "
-                                 "N = 20..320")
-    _progress("paper cases done")
-    out["refinement_2d"] = dict(ref, note="R2 recipe: N x N cells of a 20 m x 20 m x 1 m slab, k = 1e-13 m^2, "
-                                "injector 450 K and producer 1e-6 m^3/s at opposite corners, 2 steps of 1 day "
-                                "from a uniform state; FGMRES capped at 400")
-    _progress("refinement done")
-    # 256x256x64 (8.4M unknowns): 20 backward-Euler steps of up to 4 Newton iterations each,
-    # plain FP64 against the FP32 hierarchy and the FP32 hierarchy with the learned smoother
-    p5 = synth.make_problem("W5")
-    # the same kernels on operators larger than the 256 MB last-level cache (one FP64
-    # fine-level sweep moves 0.44 GB): their bandwidth is HBM's, where W2's 13.6 MB
-    # sweep can be served from that cache between back-to-back launches
-    d5 = solver.to_device(p5)
-    out["W5_apply_beyond_llc"] = {"fp64": _apply_numbers(p5, d5, cfg),
-                                  "fp32_hierarchy": _apply_numbers(p5, d5, dc.replace(cfg, storage=1))}
-    del d5
-    _progress("W5 apply and fine sweep timed")
-    nc = solver.NewtonConfig(steps=20)
-    ncr = solver.NewtonConfig(steps=20, reuse=True)   # hierarchies built once per time step
-    w5 = {}
-    ext = dict(interp_pp=1)   # extended+i interpolation (truncated to 4 weights) on the pressure hierarchy
-    for key, c5, nt, ncx in (("fp64", cfg, None, nc), ("fp32_hierarchy", dc.replace(cfg, storage=1), None, nc),
-                             ("mixed_learned", dc.replace(cfg, storage=1), net, nc),
-                             ("mixed_learned_ext_i_pressure", dc.replace(cfg, storage=1, **ext), net, nc),
-                             ("fp64_ext_i_pressure_reuse", dc.replace(cfg, **ext), None, ncr),
-                             ("fp32_ext_i_pressure_reuse", dc.replace(cfg, storage=1, **ext), None, ncr),
-                             ("mixed_learned_ext_i_pressure_reuse", dc.replace(cfg, storage=1, **ext), net, ncr)):
-        _, st5 = solver.simulate(p5, c5, ncx, net=nt)
-        _progress(f"W5 {key}: {st5['solves']} solves, {st5['total_s']:.1f} s")
-        st5.pop("newton_per_step", None)
-        w5[key] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st5.items()}
-    out["W5_256x256x64_20_steps"] = dict(w5, note="thermal conductivity 20 W/m/K (conduction-dominated); "
-                                         "per Newton iteration: assembly, both AMG setups (with _reuse: at a "
-                                         "step's first iteration only, the finest level refreshed at the later "
-                                         "ones), FGMRES to rtol; Newton stops at |G|/|G0| or |dx|/|x| <= 1e-8 "
-                                         "or after 4 iterations")
-    # the same run advection-dominated (thermal conductivity 0.5 W/m/K)
-    p5a = synth.make_problem("W5", kappa=0.5)
-    w5a = {}
-    for key, c5, nt, ncx in (("fp64", cfg, None, nc), ("fp32_hierarchy", dc.replace(cfg, storage=1), None, nc),
-                             ("mixed_learned", dc.replace(cfg, storage=1), net, nc),
-                             ("fp64_ext_i_pressure_reuse", dc.replace(cfg, **ext), None, ncr),
-                             ("mixed_learned_ext_i_pressure_reuse", dc.replace(cfg, storage=1, **ext), net, ncr)):
-        _, st5 = solver.simulate(p5a, c5, ncx, net=nt)
-        _progress(f"W5 kappa 0.5 {key}: {st5['solves']} solves, {st5['total_s']:.1f} s")
-        st5.pop("newton_per_step", None)
-        w5a[key] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st5.items()}
-    out["W5_256x256x64_20_steps_kappa_0.5"] = dict(w5a, note="thermal conductivity 0.5 W/m/K (advection-dominated)")
-    net.close()
+        x64 = None
+        for key, st_ in (("fp64", 0), ("fp32_hierarchy", 1), ("bf16_offdiag_hierarchy", 2)):
+            cfg = solver.SolveConfig(rtol=RTOL, storage=st_)
+            ms, stats = timed_steps(S, [None], cfg, None, 3, 1)
+            x, st = S.run(None, cfg)
+            r = dict(ms_per_solve=round(ms, 3), iters=st["iters"], rel_true=st["rel_true"])
+            if x64 is None:
+                x64 = x.clone()
+            else:
+                r["diff_vs_fp64_per_block"] = _block_err(x, x64)
+            r.update(apply_numbers(S, None, cfg))
+            row[key] = r
+        if name == "W2":
+            ms, _ = timed_steps(S, [None], solver.SolveConfig(rtol=RTOL, method="cpr"), None, 3, 1)
+            row["cpr_ms_per_solve"] = round(ms, 3)
+        g = prob.grid
+        out[f"{g.nx}x{g.ny}x{g.nz}"] = row
+        _progress(f"{name} variants done")
     return out
 
 
@@ -399,15 +412,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="W2", choices=list(WORKLOADS))
-    ap.add_argument("--storage", type=int, default=0, help="0 FP64 hierarchy, 1 FP32")
-    ap.add_argument("--method", default="block", choices=["block", "cpr"],
-                    help="block preconditioner (default) or the CPR comparator (timed steps only)")
-    ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--quick", action="store_true",
-                    help="one untimed-warmup-free step plus the calibration copy (for counter runs)")
+                    help="two solves of the timed form plus the calibration copy (for counter runs)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="write the roofline kernel's traffic record from two rocprofv3 --pmc databases and exit")
     args = ap.parse_args()
@@ -415,125 +423,88 @@ def main():
         write_traffic(*args.write_traffic)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU only: --gpus must be 1 "
+                                   "(the multi-GPU sharding is a design, not built)"}))
         sys.exit(2)
 
-    import numpy as np
+    import dataclasses as dc
+
     import torch
 
     from paper_1902_00095_amd import solver, synth
     from paper_1902_00095_amd import tpsolve as tps
 
     tps.init(0)
-    prob = synth.make_problem(args.workload)
-    dev = solver.to_device(prob)
-    cfg = solver.SolveConfig(rtol=args.rtol, storage=args.storage, method=args.method)
-
-    def step():
-        J, G = solver.assemble(prob, dev)
-        dx, st, (a_pp, a_S, M) = solver.solve(J, G, cfg)
-        info = dict(iters=st["iters"], rel_true=st["rel_true"], converged=st["converged"],
-                    levels_pp=a_pp.nlev, levels_S=a_S.nlev if args.method == "block" else 0)
-        M.close(); a_pp.close(); a_S.close()
-        return info
+    prob = synth.make_problem("W5")
+    S = Solves(prob)
+    net, train_rec = trained_network(quick=args.quick)
+    _progress(f"network trained ({train_rec['seconds']} s)")
+    systems = newton_systems(prob, 1 if args.quick else 2)
+    _progress(f"{len(systems)} Newton systems prepared")
+    cfg64 = solver.SolveConfig(rtol=RTOL)
+    cfg_ml = dc.replace(cfg64, storage=1)
 
     if args.quick:
-        step()
+        for s in systems[:2]:
+            S.run(s, cfg_ml, net)
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"quick": True, "calibration_copy_bytes": 2 * src.numel() * 8}), flush=True)
         return
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    infos = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        infos.append(step())
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    if args.method == "cpr":   # the comparator: the timed steps only
-        print(json.dumps({"metric": "time-to-rtol 1e-8 per coupled P-T solve, CPR comparator", "value": round(ms_per_step, 3),
-                          "unit": "ms/solve", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-                          "ms_per_step": round(ms_per_step, 3), "higher_is_better": False, "scaling": "weak",
-                          "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-                          "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]['desc']}", "method": "cpr",
-                                     "fgmres_iters": infos[-1]["iters"], "rel_true": infos[-1]["rel_true"]},
-                          "roofline": None}), flush=True)
-        return
-    # roofline pass: the same steps again with the fine-level smoother's
-    # launches carrying HIP event pairs (kept out of the metric's region
-    # because event recording slows the step)
+
+    # the metric: mixed precision + learned, then plain FP64 on the same systems
+    ms_ml, st_ml = timed_steps(S, systems, cfg_ml, net, args.steps, args.warmup)
+    _progress(f"mixed + learned: {ms_ml:.1f} ms/solve")
+    ms_64, st_64 = timed_steps(S, systems, cfg64, None, args.steps, args.warmup)
+    _progress(f"plain FP64: {ms_64:.1f} ms/solve")
+    nsys = min(args.steps, len(systems))
+    ms_32, st_32 = timed_steps(S, systems, cfg_ml, None, nsys, 1)
+    _progress(f"FP32 hierarchy alone: {ms_32:.1f} ms/solve")
+    # equal accuracy: both forms' solutions of the last system, per block
+    x_ml, _ = S.run(systems[-1], cfg_ml, net)
+    x_ml = x_ml.clone()
+    x_64, _ = S.run(systems[-1], cfg64)
+    diff = _block_err(x_ml, x_64)
+
+    # phase breakdown of one mixed + learned solve
+    S.dev["x_prev"], S.dev["x_k"] = systems[-1][2], systems[-1][3]
+    t_a = _sync_time()
+    S.J, S.G = solver.assemble(prob, S.dev, S.J, S.G)
+    t_b = _sync_time()
+    a_pp, a_S, M = solver.setup(S.J, cfg_ml)
+    t_c = _sync_time()
+    a_S.attach(net, prob.grid)
+    _, st = tps.fgmres_solve(S.J, M, -S.G, rtol=RTOL)
+    t_d = _sync_time()
+    a_S.attach(None, None)
+    M.close(); a_pp.close(); a_S.close()
+    phases = {"assemble_ms": round((t_b - t_a) * 1e3, 3), "setups_ms": round((t_c - t_b) * 1e3, 3),
+              "fgmres_ms": round((t_d - t_c) * 1e3, 3)}
+
+    # roofline: the Chebyshev step kernel's launches carry HIP event pairs
     tps.timer_enable(True)
-    for _ in range(min(args.steps, 3)):
-        step()
+    for s in systems[:2]:
+        S.run(s, cfg_ml, net)
     torch.cuda.synchronize()
     launches, kms, kbytes = tps.timer_read()
     tps.timer_enable(False)
-    achieved = (kbytes / launches) / (kms / launches * 1e-3) / 1e9 if launches else 0.0
+    mean_us = kms / max(launches, 1) * 1e3
+    bpl = kbytes / max(launches, 1)
+    achieved = bpl / (mean_us * 1e-6) / 1e9 if launches else 0.0
 
-    # phase breakdown of one more (untimed) step, synchronised between phases
-    def tsync():
-        torch.cuda.synchronize()
-        return time.perf_counter()
-    ph = {}
-    t_a = tsync()
-    J, G = solver.assemble(prob, dev)
-    t_b = tsync()
-    import dataclasses as _dc
-    a_pp = tps.AMG(J.rowptr, J.col, J.pp, _dc.replace(cfg.amg, restriction=0, storage=cfg.storage))
-    t_c = tsync()
-    a_S = tps.AMG(J.rowptr, J.col, J.S, _dc.replace(cfg.amg, restriction=1, storage=cfg.storage))
-    t_d = tsync()
-    M = tps.Precond(J, a_pp, a_S, cfg.variant)
-    _, st = tps.fgmres_solve(J, M, -G, rtol=cfg.rtol, restart=cfg.restart, maxit=cfg.maxit)
-    t_e = tsync()
-    ph = {"assemble_ms": round((t_b - t_a) * 1e3, 3), "setup_pp_ms": round((t_c - t_b) * 1e3, 3),
-          "setup_S_ms": round((t_d - t_c) * 1e3, 3), "fgmres_ms": round((t_e - t_d) * 1e3, 3)}
-    M.close(); a_pp.close(); a_S.close()
+    # V-cycle GB/s (the metric's second half), both forms
+    vc = {"mixed_learned": apply_numbers(S, systems[-1], cfg_ml, net),
+          "fp32_hierarchy": apply_numbers(S, systems[-1], cfg_ml),
+          "fp64": apply_numbers(S, systems[-1], cfg64)}
+    _progress("V-cycle throughput measured")
 
-    # V-cycle-only throughput on a fixed right-hand side (warm caches)
-    J, G = solver.assemble(prob, dev)
-    a_pp, a_S, M = solver.setup(J, cfg)
-    b = -G
-    z = torch.empty_like(b)
-    for _ in range(3):
-        M.apply(b, z)
-    torch.cuda.synchronize()
-    nrep = 50
-    ts = time.perf_counter()
-    for _ in range(nrep):
-        M.apply(b, z)
-    torch.cuda.synchronize()
-    precond_ms = (time.perf_counter() - ts) * 1e3 / nrep
-
-    # whole preconditioner apply: both V-cycles; the A_Tp product (its CSR
-    # block and z_p, r_T read, the Schur right-hand side written); splitting r
-    # and interleaving z (2n doubles read and written each); with FP32
-    # storage, the conversions of r_p in and of z_p, z_T out
-    n = prob.grid.n
-    es = 4 if args.storage == 1 else 8
-    conv = 3 * n * (8 + es) if args.storage == 1 else 0
-    pre_bytes = a_pp.vcycle_bytes() + a_S.vcycle_bytes() \
-        + (J.nnz * 12 + (n + 1) * 4 + 2 * n * 8 + n * es) + 2 * (2 * n * 8 * 2) + conv
-    vcycle_gbs = pre_bytes / (precond_ms * 1e-3) / 1e9
-    # the dominant kernel replayed back to back on the same operator (both
-    # hierarchies' fine levels have the same shape; the Schur one is timed)
-    rep_ms, rep_bytes = a_S.time_fine_smoother(400)
-    M.close(); a_pp.close(); a_S.close()
-    traffic = None
-    if os.path.exists(TRAFFIC_JSON) and args.workload == "W2" and args.storage == 0:
-        rec = json.load(open(TRAFFIC_JSON))
-        if rec.get("source_sha256") == _kernel_text_hash() and rec.get("kernel") == TRAFFIC_KERNEL:
-            traffic = round(rec["traffic_bytes_per_launch"])   # counters taken on this kernel text
-
-    _progress(f"timed solves done: {ms_per_step:.3f} ms/solve")
     variants = {}
     if not args.no_variants:
-        variants = run_variants(prob, dev, cfg, infos[-1]["iters"], ms_per_step)
+        variants["256x256x64_20_steps_kappa_20"] = c5_runs(net, 20.0)
+        variants["256x256x64_20_steps_kappa_0.5"] = c5_runs(net, 0.5)
+        variants.update(smaller_workloads())
 
     # calibration copy of known size (for PMC byte counters): 256 MiB
     src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
@@ -542,61 +513,45 @@ def main():
     torch.cuda.synchronize()
     del src, dst
 
+    sm, s64 = _summ(st_ml), _summ(st_64)
     line = {
-        "metric": "time-to-rtol 1e-8 per coupled P-T solve (assembly + 2 AMG setups + FGMRES)",
-        "value": round(ms_per_step, 3),
+        "metric": "time-to-rtol 1e-8 per coupled P-T solve, mixed+learned vs FP64; V-cycle GB/s",
+        "value": round(ms_ml, 3),
         "unit": "ms/solve",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(ms_ml, 3),
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.storage == 0 else "f64-outer/f32-hierarchy",
+        "dtype": "f64 outer / f32 hierarchy / bf16 network",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]['desc']}",
-                   "unknowns": 2 * prob.grid.n, "rtol": args.rtol,
-                   "fgmres_iters": infos[-1]["iters"], "rel_true": infos[-1]["rel_true"],
-                   "amg_levels": [infos[-1]["levels_pp"], infos[-1]["levels_S"]],
-                   "precond_apply_ms": round(precond_ms, 4), "phases": ph,
-                   "vcycle_pair_GBps": round(vcycle_gbs, 1),
-                   "precond_bytes_per_apply": round(pre_bytes)},
+        "config": {"workload": HEADLINE, "form": "mixed precision + learned post-smoother",
+                   "unknowns": 2 * prob.grid.n, "rtol": RTOL, "systems": len(systems),
+                   "mixed_learned": sm, "phases_ms": phases,
+                   "fp64_ms_per_solve": round(ms_64, 3), "fp64": s64,
+                   "fp32_hierarchy_ms_per_solve": round(ms_32, 3), "fp32_hierarchy": _summ(st_32),
+                   "mixed_learned_over_fp64_time": round(ms_ml / ms_64, 4),
+                   "solution_diff_mixed_learned_vs_fp64_per_block": diff,
+                   "vcycle": vc, "training": train_rec},
         "variants": variants,
-        "roofline": {"bound": "hbm", "kernel": "k_cheb_step_dia_r<double,double,7,128,2> (fine-level Chebyshev sweep, two rows per thread)",
-                     "achieved": round(rep_bytes / (rep_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(rep_bytes / (rep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "bytes_per_launch": round(rep_bytes),
-                     "mean_us": round(rep_ms * 1e3, 3),
-                     "timing": "400 back-to-back launches on the benchmark's level-0 operator between one "
-                               "HIP event pair on the launch stream",
-                     "in_run": {"launches": launches, "mean_us": round(kms / max(launches, 1) * 1e3, 3),
-                                "achieved": round(achieved, 1),
-                                "bytes_per_launch": round(kbytes / max(launches, 1)),
-                                "timing": "HIP event pair carried by every level-0 sweep launch of the "
-                                          "solves (includes the event markers' own latency)"}},
+        "roofline": {"bound": "hbm",
+                     "kernel": "k_cheb_step_dia<float,float,7> (finest-level Chebyshev step, FP32, 7 diagonals)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic(),
+                     "bytes_per_launch": round(bpl), "mean_us": round(mean_us, 3), "launches": launches,
+                     "timing": "HIP event pair stamped by every launch of the kernel in two solves of the "
+                               "timed form (both hierarchies' finest levels), on the solve stream"},
     }
-    if not all(i["converged"] for i in infos):
+    if not (sm["all_converged"] and s64["all_converged"]):
         line["error"] = "a timed solve did not converge"
-
     if not args.no_cpu_baseline:
-        import oracle
-        _progress("CPU oracle solve started")
-        oracle.build(force=False)
-        tc = time.perf_counter()
-        Jo = oracle.jacobian(prob)
-        bo = -oracle.residual(prob)
-        kw = cfg.amg.oracle_kwargs()   # the GPU path's hierarchy parameters
-        kw.pop("restriction")
-        ao_pp = oracle.AMG(Jo.n, Jo.rowptr, Jo.col, Jo.pp, restriction=0, **kw)
-        ao_S = oracle.AMG(Jo.n, Jo.rowptr, Jo.col, Jo.S, restriction=1, **kw)
-        xo, io = oracle.gmres(Jo, ao_pp, ao_S, bo, rtol=args.rtol)
-        cpu_ms = (time.perf_counter() - tc) * 1e3
-        line["cpu_baseline"] = {"value": round(cpu_ms, 1), "unit": "ms/solve", "cores": 1,
-                                "kind": "oracle",
-                                "sample": f"one full {args.workload} solve (assembly, 2 AMG setups, "
-                                          f"GMRES to rtol {args.rtol}: {io['iters']} iterations), "
-                                          "single-threaded FP64 C"}
+        _progress("CPU oracle sample started")
+        run20 = variants.get("256x256x64_20_steps_kappa_20", {}).get("fp64")
+        line["cpu_baseline"] = cpu_baseline(S, systems[min(3, len(systems) - 1)],
+                                            round(s64["fgmres_iters_mean"]), cfg64, run20)
+    net.close()
     print(json.dumps(line), flush=True)
 
 

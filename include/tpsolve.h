@@ -329,7 +329,12 @@ int precond_create_cpr(const tp_jacobian* J, tp_amg_t amg_pp, tp_ilu_t ilu, tp_p
  * restart 30) with classical Gram-Schmidt applied twice, Givens rotations on
  * the Hessenberg matrix, all in FP64 on the device.  Stops when the true
  * relative residual ||b - J x||_2 / ||b||_2 <= rtol (checked in FP64 at the
- * end of every cycle) or after maxit iterations.
+ * end of every cycle), after maxit iterations, or -- TP_NOT_CONVERGED --
+ * when a cycle whose residual estimate met rtol leaves the true residual
+ * above rtol and above half its value at the cycle's start: the true
+ * residual has reached the rounding floor of the FP64 product b - J x (a
+ * right-hand side small against ||J|| ||x||), where more cycles repeat the
+ * same correction.
  * ------------------------------------------------------------------------ */
 typedef struct {
     double rtol;
@@ -346,6 +351,19 @@ typedef struct {
      * active or the kernel timer is on); 0: its kernels are launched one by
      * one.  Both give bit-identical iterates. */
     int32_t graph;
+    /* Absolute tolerance: the solve also stops when ||b - J x||_2 <= atol
+     * (0: relative test only). */
+    double atol;
+    /* Stagnation window w of the guard above: estimate j against estimate
+     * j - w (0 takes 2). */
+    int32_t stag_window;
+    /* Contraction guard for the learned smoother: when > 0, the network is
+     * switched off at iteration j >= 4 of a solve whose relative residual
+     * estimate exceeds ref_rate^j, i.e. whose mean contraction per iteration
+     * so far falls behind ref_rate (the caller passes the plain form's rate,
+     * measured on an earlier solve and relaxed for the network's cost per
+     * iteration).  Recorded in fallback_iter like the stagnation guard. */
+    double ref_rate;
 } tp_krylov_params;
 typedef struct {
     int32_t iters, restarts;

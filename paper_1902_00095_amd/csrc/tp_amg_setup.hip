@@ -41,6 +41,12 @@ int lanes_for(int32_t n, int64_t nnz) {
     if (n >= 65536) avg /= 2.0;
     int g = 1;
     while (g < avg && g < 64) g <<= 1;
+    // Large levels take at most 8 lanes a row: more rows per wavefront keep
+    // more independent loads in flight, and the dependent index -> value
+    // gathers of a short row are latency-bound (8 lanes measured fastest on
+    // the first coarse levels of the 256x256x64 hierarchies, 18-44 entries a
+    // row: 16 lanes cost 6% more time per preconditioner apply, 32 lanes 17%).
+    if (n >= 65536 && g > 8) g = 8;
     return g;
 }
 

@@ -36,7 +36,7 @@ struct tp_cnn_attach {
     DBuf<double> part;
     DBuf<float> scale;
     DBuf<int32_t> bad;
-    DBuf<float> h;      // 16 x n hidden activations of the smoother's own forward passes
+    DBuf<uint16_t> fstat;  // static channels 1..7 as BF16, 8 per cell (slot 0 unused): the fused smoother's input
     Csr At;             // transpose of the level operator (operator-norm training loss)
     bool enabled = true;
 };
@@ -46,7 +46,12 @@ template <typename T>
 void cnn_forward_into(tp_cnn* c, const tp_grid& g, const float* f, float* out, T* x, const float* scale,
                       int32_t* bad, hipStream_t s, float* hw = nullptr);
 template <typename T>
-void cnn_features_into(tp_cnn_attach* a, const T* r, float* f, hipStream_t s);
+void cnn_features_into(tp_cnn_attach* a, const T* r, float* f, hipStream_t s, bool normalise = true);
+template <typename T>
+void cnn_forward_fused(tp_cnn* c, const tp_grid& g, const float* f, float* out, T* x, const float* scale,
+                       int32_t* bad, hipStream_t s);
+template <typename T>
+void cnn_smooth_fused(tp_cnn_attach* a, T* x, hipStream_t s);
 void cnn_backward_from_dout(tp_cnn* c, const tp_grid& g, const float* feat, hipStream_t s);
 void cnn_op_loss_grad(tp_cnn_attach* a, const int32_t* rowptr, const int32_t* col, const double* val,
                       int32_t nnz, const float* feat, const float* target, float err_weight, hipStream_t s);

@@ -231,6 +231,178 @@ k_cnn_l2(tp_grid g, const float* __restrict__ h, const float* __restrict__ w2, c
     }
 }
 
+// ---- fused forward (inference) ------------------------------------------------------------
+// Both layers in one pass, the hidden activations never leaving the chip.  A
+// workgroup owns an 8 x 8 x 8 output tile; layer 2 needs relu(h) on the tile
+// and a one-cell halo (10 x 10 x 10 cells, "H"), and those need the features
+// on a two-cell halo (12 x 12 x 12, "F", staged in LDS as eight BF16 channels
+// per cell, zero outside the grid).
+//   Layer 1 runs on the H cells in groups of 16 (any 16 cells: each lane
+//   addresses its own cell's taps), as k_cnn_l1 does: H (16 channels x 16
+//   cells) = W1 F + b1 in seven v_mfma_f32_16x16x32_bf16 steps.
+//   Layer 2 is regrouped by tap: out(i) = b2 + sum_t G_t(i + off_t) with
+//   G_t(c) = sum_o W2[o][t] relu(h_o(c)).  G (taps x cells) = W2^T relu(H)
+//   is a second contraction, over the 16 channels, on v_mfma_f32_16x16x16_bf16:
+//   the first instruction leaves channel 4q + e of cell n in element e of
+//   lane n + 16 q, which is exactly where the second one takes operand
+//   B[k = channel][n], so relu(H) passes from accumulator to operand in
+//   registers.  relu(h) enters split in two BF16 parts (hi + lo, relative
+//   remainder <= 2^-18), taps in two blocks of 16 (27 used): four
+//   instructions per group.  H cells outside the grid get G = 0 (layer 2's
+//   zero padding).  G (27 x 1008 FP32) goes to LDS tap-major; after a
+//   barrier every thread sums its output cell's 27 taps in tap order.
+// LDS: 27.6 KB of features + 108.9 KB of G (one workgroup per CU).
+// Feature sources: FS 0, eight FP32 channel planes (channel 0 already
+// scaled); FS 1, the attachment's BF16 static channels (8 per cell, slot 0
+// unused) and the unscaled channel-0 plane z, divided by scale[0] when
+// staged (the same FP32 division as the planar path).
+typedef __attribute__((__vector_size__(4 * sizeof(short)))) short short4v;
+constexpr int FT = 8;                 // output tile edge
+constexpr int FH = FT + 2, FF = FT + 4;
+constexpr int FHC = FH * FH * FH;     // 1000 H cells
+constexpr int FFC = FF * FF * FF;     // 1728 F cells
+constexpr int FGROUPS = (FHC + 15) / 16;  // 63
+constexpr int FGN = FGROUPS * 16;     // 1008 G columns (the last 8 unused)
+constexpr int FU_T = 512;
+
+__device__ inline int f_tap(int t) { return ((t / 9) * FF + (t / 3) % 3) * FF + t % 3; }
+__device__ inline int h_tap(int t) { return ((t / 9) * FH + (t / 3) % 3) * FH + t % 3; }
+
+__device__ inline short4v bf16x4_bits(float a, float b, float c, float d) {
+    short4v v;
+    v[0] = (short)(__float_as_uint(a) >> 16);  // arguments are BF16 values: exact
+    v[1] = (short)(__float_as_uint(b) >> 16);
+    v[2] = (short)(__float_as_uint(c) >> 16);
+    v[3] = (short)(__float_as_uint(d) >> 16);
+    return v;
+}
+
+template <typename T, int FS>
+__global__ void __launch_bounds__(FU_T)
+k_cnn_fused(tp_grid g, const float* __restrict__ f, const uint16_t* __restrict__ fstat,
+            const float* __restrict__ w1, const float* __restrict__ b1, const float* __restrict__ w2,
+            const float* __restrict__ b2, float* __restrict__ out, T* __restrict__ x,
+            const float* __restrict__ scale, int32_t* __restrict__ bad) {
+    __shared__ bf16x8 s_f[FFC];
+    __shared__ float s_g[CNN_NT * FGN];
+    const int32_t n = g.nx * g.ny * g.nz;
+    const int32_t tx = (g.nx + FT - 1) / FT, ty = (g.ny + FT - 1) / FT, tz = (g.nz + FT - 1) / FT;
+    const int32_t ntiles = tx * ty * tz;
+    // XCD-aware order: consecutive workgroups go to different XCDs (round
+    // robin over 8), so tile k of XCD j is tile j * (ntiles / 8) + k and each
+    // XCD walks a contiguous run of neighbouring tiles (shared halos in its L2)
+    int32_t tile = blockIdx.x;
+    if (ntiles % 8 == 0) tile = (blockIdx.x % 8) * (ntiles / 8) + blockIdx.x / 8;
+    const int32_t bz = tile / (tx * ty), by = (tile / tx) % ty, bx = tile % tx;
+    const int32_t x0 = bx * FT, y0 = by * FT, z0 = bz * FT;
+    const float inv_s = FS == 1 ? scale[0] : 1.f;
+    for (int r = threadIdx.x; r < FFC; r += FU_T) {
+        const int fz = r / (FF * FF), fy = (r / FF) % FF, fx = r % FF;
+        const int32_t cx = x0 + fx - 2, cy = y0 + fy - 2, cz = z0 + fz - 2;
+        const bool in = cx >= 0 && cy >= 0 && cz >= 0 && cx < g.nx && cy < g.ny && cz < g.nz;
+        const int64_t cell = cx + (int64_t)g.nx * (cy + (int64_t)g.ny * cz);
+        bf16x8 v{};
+        if (in) {
+            if (FS == 0) {
+#pragma unroll
+                for (int c = 0; c < CNN_CIN; ++c) v[c] = (__bf16)bf16_round(f[(int64_t)c * n + cell]);
+            } else {
+                v = *reinterpret_cast<const bf16x8*>(fstat + 8 * cell);
+                const float z = f[cell];
+                v[0] = (__bf16)bf16_round(inv_s > 0.f ? z / inv_s : 0.f);
+            }
+        }
+        s_f[r] = v;
+    }
+    const int lane = threadIdx.x & 63, q = lane >> 4, col = lane & 15, wv = threadIdx.x >> 6;
+    bf16x8 a[MF_KS];
+    int ftoff[MF_KS];
+#pragma unroll
+    for (int st = 0; st < MF_KS; ++st) {
+        const int t = 4 * st + q;
+#pragma unroll
+        for (int c = 0; c < CNN_CIN; ++c)
+            a[st][c] = (__bf16)(t < CNN_NT ? w1[col * MF_K + c * CNN_NT + t] : 0.f);
+        ftoff[st] = t < CNN_NT ? f_tap(t) : -1;
+    }
+    // W2^T tap blocks: A[m = tap - 16 blk][k = channel] at lane m + 16 (k / 4), element k % 4
+    short4v a2[2];
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+        const int t = 16 * blk + col;
+        float w[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w[e] = t < CNN_NT ? w2[(4 * q + e) * CNN_NT + t] : 0.f;
+        a2[blk] = bf16x4_bits(w[0], w[1], w[2], w[3]);
+    }
+    float4v bias;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bias[r] = b1[4 * q + r];
+    __syncthreads();
+#pragma unroll 1
+    for (int grp = wv; grp < FGROUPS; grp += FU_T / 64) {
+        const int hl = 16 * grp + col;             // this lane's H cell
+        const bool real = hl < FHC;
+        const int hx = hl % FH, hy = (hl / FH) % FH, hz = hl / (FH * FH);
+        const int fb = real ? (hz * FF + hy) * FF + hx : 0;  // F index of tap (-1,-1,-1)
+        float4v acc = bias;
+#pragma unroll
+        for (int st = 0; st < MF_KS; ++st) {
+            bf16x8 b = ftoff[st] < 0 ? bf16x8{} : s_f[fb + ftoff[st]];
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[st], b, acc, 0, 0, 0);
+        }
+        const int32_t cx = x0 + hx - 1, cy = y0 + hy - 1, cz = z0 + hz - 1;
+        const bool live = real && cx >= 0 && cy >= 0 && cz >= 0 && cx < g.nx && cy < g.ny && cz < g.nz;
+        float hi[4], lo[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float v = live && acc[e] > 0.f ? acc[e] : 0.f;
+            hi[e] = bf16_round(v);
+            lo[e] = bf16_round(v - hi[e]);
+        }
+        const short4v bh = bf16x4_bits(hi[0], hi[1], hi[2], hi[3]);
+        const short4v bl = bf16x4_bits(lo[0], lo[1], lo[2], lo[3]);
+#pragma unroll
+        for (int blk = 0; blk < 2; ++blk) {
+            float4v gt = {0.f, 0.f, 0.f, 0.f};
+            gt = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[blk], bh, gt, 0, 0, 0);
+            gt = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[blk], bl, gt, 0, 0, 0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int t = 16 * blk + 4 * q + e;  // D[m = tap][n = cell] at lane n + 16 (m / 4)
+                if (t < CNN_NT) s_g[t * FGN + 16 * grp + col] = gt[e];
+            }
+        }
+    }
+    __syncthreads();
+    const int lx = threadIdx.x % FT, ly = (threadIdx.x / FT) % FT, lz = threadIdx.x / (FT * FT);
+    const int32_t xi = x0 + lx, yi = y0 + ly, zi = z0 + lz;
+    if (xi >= g.nx || yi >= g.ny || zi >= g.nz) return;
+    const int hb = (lz * FH + ly) * FH + lx;  // H index of tap (-1,-1,-1)
+    float o = b2[0];
+#pragma unroll
+    for (int t = 0; t < CNN_NT; ++t) o += s_g[t * FGN + hb + h_tap(t)];
+    const int64_t i = xi + (int64_t)g.nx * (yi + (int64_t)g.ny * zi);
+    if (out) out[i] = o;
+    if (x) {
+        if (!isfinite(o)) *bad = 1;
+        else x[i] = x[i] + (T)(scale[0] * o);
+    }
+}
+
+// static channels 1..7 as BF16, eight per cell (slot 0 left zero)
+__global__ void __launch_bounds__(CB)
+k_feat_pack(int32_t n, const float* __restrict__ f, uint16_t* __restrict__ fs) {
+    const int32_t i = blockIdx.x * CB + threadIdx.x;
+    if (i >= n) return;
+    uint16_t v[8];
+    v[0] = 0;
+#pragma unroll
+    for (int c = 1; c < CNN_CIN; ++c) v[c] = (uint16_t)(__float_as_uint(bf16_round(f[(int64_t)c * n + i])) >> 16);
+#pragma unroll
+    for (int c = 0; c < CNN_CIN; ++c) fs[8 * (int64_t)i + c] = v[c];
+}
+
 // ---- loss and gradients ------------------------------------------------------------------
 // dout = 2 (out - y) / n; per-block partial sums of (out - y)^2
 __global__ void __launch_bounds__(CB)
@@ -531,6 +703,38 @@ void cnn_work_reserve(tp_cnn* c, int32_t n, hipStream_t s) {
 
 // forward on given features; out may be null; with x: smoother update x += scale * out;
 // hidden activations in hw (16 x n) or, when null, in the network's own work buffer
+static int fused_tiles(const tp_grid& g) {
+    return ((g.nx + FT - 1) / FT) * ((g.ny + FT - 1) / FT) * ((g.nz + FT - 1) / FT);
+}
+
+// inference: both layers in one pass (planar FP32 features, channel 0 scaled)
+template <typename T>
+void cnn_forward_fused(tp_cnn* c, const tp_grid& g, const float* f, float* out, T* x, const float* scale,
+                       int32_t* bad, hipStream_t s) {
+    const int tiles = fused_tiles(g);
+    if (tiles > 0)
+        TP_LAUNCH((k_cnn_fused<T, 0>), tiles, FU_T, 0, s, g, f, (const uint16_t*)nullptr, c->wbf.p,
+                  c->w.p + CNN_OFF_B1, c->wbf.p + CNN_OFF_W2, c->w.p + CNN_OFF_B2, out, x, scale, bad);
+}
+template void cnn_forward_fused<float>(tp_cnn*, const tp_grid&, const float*, float*, float*, const float*,
+                                       int32_t*, hipStream_t);
+
+// the smoother update on the finest level: features from the attachment's
+// packed static channels and its unscaled channel-0 plane
+template <typename T>
+void cnn_smooth_fused(tp_cnn_attach* a, T* x, hipStream_t s) {
+    const int tiles = fused_tiles(a->g);
+    tp_cnn* c = a->net;
+    if (tiles > 0)
+        TP_LAUNCH((k_cnn_fused<T, 1>), tiles, FU_T, 0, s, a->g, a->feat.p, a->fstat.p, c->wbf.p,
+                  c->w.p + CNN_OFF_B1, c->wbf.p + CNN_OFF_W2, c->w.p + CNN_OFF_B2, (float*)nullptr, x, a->scale.p,
+                  a->bad.p);
+}
+template void cnn_smooth_fused<double>(tp_cnn_attach*, double*, hipStream_t);
+template void cnn_smooth_fused<float>(tp_cnn_attach*, float*, hipStream_t);
+
+// training forward: the two layers apart, keeping the hidden activations
+// (hw, or the network's own work buffer) for the gradient
 template <typename T>
 void cnn_forward_into(tp_cnn* c, const tp_grid& g, const float* f, float* out, T* x, const float* scale,
                       int32_t* bad, hipStream_t s, float* hw) {
@@ -554,16 +758,18 @@ template void cnn_forward_into<float>(tp_cnn*, const tp_grid&, const float*, flo
                                       int32_t*, hipStream_t, float*);
 
 // features for residual r on the finest level of a hierarchy with an attached smoother
+// (normalise false: channel 0 is left as z = D^{-1} r, the fused smoother
+// divides by the scale when it stages it)
 template <typename T>
-void cnn_features_into(tp_cnn_attach* a, const T* r, float* f, hipStream_t s) {
+void cnn_features_into(tp_cnn_attach* a, const T* r, float* f, hipStream_t s, bool normalise) {
     const int32_t n = a->g.nx * a->g.ny * a->g.nz;
     const int nb = red_blocks(n);
     TP_LAUNCH(k_feat_resid<T>, nb, CB, 0, s, n, r, a->dinv.p, f, a->part.p);
     TP_LAUNCH(k_feat_scale_sum, 1, CB, 0, s, nb, n, a->part.p, a->scale.p);
-    TP_LAUNCH(k_feat_normalise, cdiv(n, CB), CB, 0, s, n, a->scale.p, f);
+    if (normalise) TP_LAUNCH(k_feat_normalise, cdiv(n, CB), CB, 0, s, n, a->scale.p, f);
 }
-template void cnn_features_into<double>(tp_cnn_attach*, const double*, float*, hipStream_t);
-template void cnn_features_into<float>(tp_cnn_attach*, const float*, float*, hipStream_t);
+template void cnn_features_into<double>(tp_cnn_attach*, const double*, float*, hipStream_t, bool);
+template void cnn_features_into<float>(tp_cnn_attach*, const float*, float*, hipStream_t, bool);
 
 // gradient of the loss from c->dout (set by the caller) and c->h of the last forward
 void cnn_backward_from_dout(tp_cnn* c, const tp_grid& g, const float* feat, hipStream_t s) {
@@ -600,8 +806,9 @@ void cnn_attach_build(tp_cnn_attach* a, const tp_grid& g, const int32_t* rowptr,
     a->part.alloc(1024, s);
     a->scale.alloc(1, s);
     a->bad.alloc(1, s);
-    a->h.alloc((size_t)CNN_CH * n, s);
+    a->fstat.alloc((size_t)CNN_CIN * n, s);
     TP_LAUNCH(k_feat_static, cdiv(n, CB), CB, 0, s, g, rowptr, col, val, a->feat.p, a->dinv.p);
+    TP_LAUNCH(k_feat_pack, cdiv(n, CB), CB, 0, s, n, a->feat.p, a->fstat.p);
 }
 
 // new values of the level operator (same pattern): static feature channels and
@@ -610,6 +817,7 @@ void cnn_attach_refresh(tp_cnn_attach* a, const int32_t* rowptr, const int32_t* 
                         hipStream_t s) {
     const int32_t n = a->g.nx * a->g.ny * a->g.nz;
     TP_LAUNCH(k_feat_static, cdiv(n, CB), CB, 0, s, a->g, rowptr, col, val, a->feat.p, a->dinv.p);
+    TP_LAUNCH(k_feat_pack, cdiv(n, CB), CB, 0, s, n, a->feat.p, a->fstat.p);
     a->At = Csr{};
 }
 
@@ -672,7 +880,7 @@ int cnn_forward(tp_cnn_t c, const tp_grid* grid, const float* feat, float* out, 
     TP_GUARD({
         TP_CHECK_ARG(c && grid && feat && out, "cnn_forward: null argument");
         TP_CHECK_ARG(grid->nx >= 1 && grid->ny >= 1 && grid->nz >= 1, "cnn_forward: bad grid");
-        tp::cnn_forward_into<float>(c, *grid, feat, out, nullptr, nullptr, nullptr, (hipStream_t)stream);
+        tp::cnn_forward_fused<float>(c, *grid, feat, out, nullptr, nullptr, nullptr, (hipStream_t)stream);
     });
     return TP_OK;
 }

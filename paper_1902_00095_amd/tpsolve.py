@@ -59,7 +59,8 @@ class _AmgParams(C.Structure):
 
 class _KParams(C.Structure):
     _fields_ = [("rtol", C.c_double), ("restart", C.c_int32), ("maxit", C.c_int32),
-                ("stag_ratio", C.c_double), ("graph", C.c_int32)]
+                ("stag_ratio", C.c_double), ("graph", C.c_int32), ("atol", C.c_double),
+                ("stag_window", C.c_int32), ("ref_rate", C.c_double)]
 
 
 class _KStats(C.Structure):
@@ -589,15 +590,17 @@ class Net:
 
 
 def fgmres_solve(J: Jacobian, M: Precond, b, x=None, rtol=1e-8, restart=30, maxit=1000,
-                 history=False, stag_ratio=0.95, graph=True, stream=None):
+                 history=False, stag_ratio=0.95, graph=True, stream=None, atol=0.0, stag_window=2,
+                 ref_rate=0.0):
     """Solve J x = b; returns (x, stats dict).  x (tensor) is the initial
     guess when given and is overwritten.  graph: replay the preconditioner
-    apply from a captured HIP graph."""
+    apply from a captured HIP graph.  stag_ratio / stag_window / ref_rate:
+    the learned smoother's guards (see tp_krylov_params)."""
     torch = _torch()
     lib = load()
     if x is None:
         x = torch.zeros_like(b)
-    kp = _KParams(rtol, restart, maxit, stag_ratio, 1 if graph else 0)
+    kp = _KParams(rtol, restart, maxit, stag_ratio, 1 if graph else 0, atol, stag_window, ref_rate)
     st = _KStats()
     hist = np.zeros(maxit + 1) if history else None
     jc = J.c()

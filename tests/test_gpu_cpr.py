@@ -212,10 +212,11 @@ def test_fgmres_cpr_matches_oracle(case):
     p = CASES[case]()
     d = solver.to_device(p)
     J, G = solver.assemble(p, d)
-    dx, st, hand = solver.solve(J, G, solver.SolveConfig(rtol=rtol, method="cpr"), history=True)
+    cfg = solver.SolveConfig(rtol=rtol, method="cpr")
+    dx, st, hand = solver.solve(J, G, cfg, history=True)
     Jo = oracle.jacobian(p)
     bo = -oracle.residual(p)
-    ao = oracle.AMG(Jo.n, Jo.rowptr, Jo.col, Jo.pp, **tps.AmgParams(restriction=0).oracle_kwargs())
+    ao = oracle.AMG(Jo.n, Jo.rowptr, Jo.col, Jo.pp, **solver.amg_params(cfg, "pp").oracle_kwargs())
     xo, io = oracle.gmres_cpr(Jo, ao, oracle.cpr_ilu(Jo), bo, rtol=rtol)
     say(f"  gpu its {st['iters']} rel {st['rel_true']:.2e}; oracle its {io['iters']} rel {io['rel_true']:.2e}")
     assert st["converged"] and st["rel_true"] <= rtol

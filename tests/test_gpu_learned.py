@@ -1,7 +1,7 @@
 """GPU tests of the learned post-smoother: network forward and gradients
 against the CPU oracle on the same BF16-rounded inputs, features, the Adam
 step's closed form, the training-pair invariant, the stagnation fallback,
-and what training gains over the plain smoother."""
+and the C4 training and evaluation protocol with its contraction guard."""
 import sys
 
 import numpy as np
@@ -113,6 +113,42 @@ def test_features_match_oracle():
     fo, so = oracle.cnn_features(p.grid, Jo.rowptr, Jo.col, Jo.S, r)
     assert abs(s - so) <= 1e-6 * so
     np.testing.assert_allclose(f.cpu().numpy().reshape(8, -1), fo, rtol=2e-6, atol=1e-6)
+
+
+@pytest.mark.parametrize("storage,dims", [(0, (24, 24, 24)), (1, (24, 24, 24)), (0, (19, 13, 11))])
+def test_smoother_in_vcycle_is_state_plus_scaled_forward(storage, dims):
+    """The learned post-smoother inside the V-cycle (one fused kernel staging
+    the packed static channels and the unscaled residual plane) equals its
+    definition assembled from separately tested pieces: the cycle's state
+    before post-smoothing x_pre = y - e (from the pair of b = S y), the
+    features of r = b - S x_pre with their scale s, the forward pass checked
+    against the oracle, and x_post = x_pre + s out.  Grids with full and
+    ragged 8 x 8 x 8 tiles; FP64 and FP32 hierarchies."""
+    import scipy.sparse as sp
+    import torch
+    say("smoother in vcycle", storage, dims)
+    p = synth.make_problem("W4", seed=1003, grid=synth.Grid(*dims, 1, 1, 1))
+    d = solver.to_device(p)
+    J, G = solver.assemble(p, d)
+    a_S = learned.schur_hierarchy(J, storage=storage, coarse_max=64)
+    net = tps.Net(learned.init_params(11) * 2)
+    a_S.attach(net, p.grid)
+    y = torch.as_tensor(synth.random_rhs(6, p.grid.n), device="cuda")
+    r, e = a_S.presmoothed_pair(y)
+    x_pre = y - e
+    f, sc = a_S.features(r)
+    out = net.forward(p.grid, f)
+    expect = (x_pre + sc * out.double()).cpu().numpy()
+    S = sp.csr_matrix((np_(J.S), np_(J.col), np_(J.rowptr)), shape=(p.grid.n, p.grid.n))
+    b = torch.as_tensor(S @ np_(y), device="cuda")
+    got = np_(a_S.vcycle(b))
+    tol = 1e-6 if storage == 0 else 1e-4
+    err = np.abs(got - expect).max() / np.abs(expect).max()
+    say(f"  rel err {err:.2e}")
+    assert err <= tol
+    a_S.attach(None, None)
+    net.close()
+    a_S.close()
 
 
 def test_pair_invariant():
@@ -232,24 +268,48 @@ def test_operator_loss_gradient_matches_oracle(ew):
         assert abs(fd - gg[k]) <= 2e-3 * scale, (k, fd, gg[k])
 
 
-def test_training_lowers_loss_and_reports_gain():
-    """Train on seeded fields (seeds 1000+) with the operator-norm loss,
-    evaluate on held-out seeds (4001+): the held-out loss falls at least
-    tenfold, the learned form (with the stagnation guard) reaches the same
-    true residual, and the iteration counts of both forms are reported."""
-    say("training")
-    grid = synth.Grid(24, 24, 24, 1, 1, 1)
-    net = tps.Net(learned.init_params())
-    train = learned.make_pairs(range(1000, 1032), grid, net=net, smooth_y=1)
-    held = learned.make_pairs(range(4001, 4003), grid, net=net, smooth_y=1)
-    l0 = learned.eval_loss(net, held)
-    learned.train(net, train, 2000, lr=3e-3)
-    l1 = learned.eval_loss(net, held)
-    say(f"  held-out loss {l0:.4e} -> {l1:.4e}")
-    assert l1 < 0.1 * l0
-    for seed in (4001, 4002):
-        p = synth.make_problem("W4", seed=seed, grid=grid)
-        res = learned.compare(net, p)
-        say(f"  seed {seed}: plain {res['plain']['iters']} its, learned {res['learned']['iters']} its "
-            f"(fallback {res['learned']['fallback_iter']}), rel {res['learned']['rel_true']:.2e}")
-        assert res["learned"]["converged"] and res["learned"]["rel_true"] <= 1e-8
+def test_c4_training_and_guarded_evaluation():
+    """The C4 protocol: train on pairs from plain solves of fields 1000-1199
+    (24^3), then evaluate at 96^3 on held-out fields 4001 and 4002.
+
+    Training must work and generalise: the loss falls at least fivefold, and
+    on held-out pairs at 96^3 the network removes most of the residual it is
+    given (operator-norm loss at most 0.2 of what no correction leaves).
+    The measured outcome in FGMRES is negative -- the learned
+    post-smoother needs more iterations than the Chebyshev post-smoother it
+    replaces, at the same cost per iteration -- so what is asserted is the
+    guard: with the contraction guard (the plain solve's mean contraction as
+    reference) the learned form still reaches true rtol 1e-8, never takes
+    more iterations than the unguarded learned form, and stays within 1.6x
+    of plain's iterations; when it falls behind the guard has switched it
+    off (fallback_iter set).  The iteration counts of every form are printed."""
+    import torch
+    say("C4 training")
+    net, rec = learned.train_c4()
+    say(f"  {rec['pairs']} pairs, loss {rec['loss_first']:.3e} -> {rec['loss_last_100_mean']:.3e}")
+    assert rec["pairs"] == 600
+    assert rec["loss_last_100_mean"] < 0.2 * rec["loss_first"]
+    g96 = synth.Grid(96, 96, 96, 1.0, 1.0, 1.0)
+    zero = tps.Net(np.zeros(learned.NPARAM, dtype=np.float32))
+    held = learned.plain_solve_pairs(synth.make_problem("W4", seed=4001, grid=g96), net, arnoldi_steps=2)
+    ln = learned.eval_loss(net, held)
+    held[0].amg.attach(zero, g96)
+    lz = learned.eval_loss(zero, held)
+    held[0].amg.attach(None, None)
+    held[0].amg.close()
+    say(f"  held-out 96^3 pairs: loss {ln:.3e}, no correction {lz:.3e}")
+    assert ln < 0.2 * lz
+    rows = learned.evaluate_c4(net, seeds=(4001, 4002))
+    for r in rows:
+        say("  seed", r["seed"], {k: (v["iters"], v["fgmres_ms"], v["fallback_iter"]) for k, v in r.items()
+                                  if k != "seed"})
+        p, l, gd = r["plain"], r["learned"], r["learned_guarded"]
+        for key in ("plain", "learned", "learned_guarded", "no_post"):
+            assert r[key]["converged"] and r[key]["rel_true"] <= 1e-8, (key, r[key])
+        assert gd["iters"] <= l["iters"]
+        assert gd["iters"] <= 1.6 * p["iters"]
+        if gd["iters"] > p["iters"]:
+            assert gd["fallback_iter"] >= 4
+    zero.close()
+    net.close()
+    torch.cuda.synchronize()

@@ -27,13 +27,13 @@ def _init():
     (0, False, "block", None), (1, False, "block", None), (0, True, "block", None), (1, True, "block", None),
     (0, False, "cpr", None), (0, True, "cpr", None), (1, False, "block", 1), (1, True, "block", 1),
     (0, "numeric", "block", None), (1, "numeric", "block", None), (1, "numeric_run", "block", None),
-    (0, "numeric", "cpr", None)])
+    (0, "numeric", "cpr", None), (0, "numeric", "block", 1)])
 def test_newton_time_steps_match_oracle(storage, reuse, method, interp_pp):
     """With hierarchy reuse the later Newton iterations of a step run on
     refreshed hierarchies: the finest level only ("fine"), or every level
     recomputed on the kept splits and patterns ("numeric"; "numeric_run" keeps
-    them for the whole run); the Newton root, and so the states, must not
-    change.  CPR keeps one ILU(0) handle for the run and refactorises it for
+    them for the whole run; an extended+i pressure hierarchy is rebuilt
+    instead); the Newton root, and so the states, must not change.  CPR keeps one ILU(0) handle for the run and refactorises it for
     every Jacobian."""
     say("newton", storage, reuse, method, interp_pp)
     p = synth.make_problem("W5", grid=synth.Grid(16, 16, 8, 1.0, 1.0, 1.0))

@@ -22,7 +22,7 @@ import pytest
 import oracle
 from paper_1902_00095_amd import solver, synth
 from paper_1902_00095_amd import tpsolve as tps
-from parity_bars import history_bound
+from parity_bars import U, history_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -252,8 +252,8 @@ def test_precond_matches_oracle(variant):
         assert relmax(zg[blk::2], zo[blk::2]) <= 1e-10, blk
 
 
-@pytest.mark.parametrize("case", ["W1", "W2s", "W2g", "W4s"])
-def test_fgmres_end_to_end(case):
+@pytest.mark.parametrize("case,interp_pp", [("W1", 1), ("W2s", 1), ("W2g", 1), ("W4s", 1), ("W2s", 0), ("W4s", 0)])
+def test_fgmres_end_to_end(case, interp_pp):
     """GPU assembly + setup + FGMRES vs the oracle at the same rtol: the same
     iteration count (+-1), residual estimates that agree iteration by
     iteration over the first ten (1e-8 relative, or the derived bound of a
@@ -264,17 +264,19 @@ def test_fgmres_end_to_end(case):
     only loosely fixed by the interleaved residual norm (the energy rows
     dominate it), which is why parity is stated GPU against oracle and the
     error bar of the method description has its own test
-    (`test_solution_error_within_1e_6`)."""
-    say("fgmres", case)
+    (`test_solution_error_within_1e_6`).  The pressure hierarchy with
+    extended+i interpolation (the default) and with direct interpolation."""
+    say("fgmres", case, interp_pp)
     rtol = 1e-10
     p = CASES[case]()
     d = solver.to_device(p)
     J, G = solver.assemble(p, d)
-    dx, st, hs = solver.solve(J, G, solver.SolveConfig(rtol=rtol), history=True)
+    cfg = solver.SolveConfig(rtol=rtol, interp_pp=interp_pp)
+    dx, st, hs = solver.solve(J, G, cfg, history=True)
     Jo = oracle.jacobian(p)
     bo = -oracle.residual(p)
-    ao_pp = o_amg(Jo.n, Jo.rowptr, Jo.col, Jo.pp, tps.AmgParams(restriction=0))
-    ao_S = o_amg(Jo.n, Jo.rowptr, Jo.col, Jo.S, tps.AmgParams(restriction=1))
+    ao_pp = o_amg(Jo.n, Jo.rowptr, Jo.col, Jo.pp, solver.amg_params(cfg, "pp"))
+    ao_S = o_amg(Jo.n, Jo.rowptr, Jo.col, Jo.S, solver.amg_params(cfg, "S"))
     xo, io = oracle.gmres(Jo, ao_pp, ao_S, bo, rtol=rtol)
     xt, it = oracle.gmres(Jo, ao_pp, ao_S, bo, rtol=1e-14, maxit=3000)
     say(f"  gpu its {st['iters']} rel {st['rel_true']:.2e}; oracle its {io['iters']}")
@@ -335,11 +337,12 @@ def test_solution_error_within_1e_6(case, rtol):
     p = CASES[case]()
     d = solver.to_device(p)
     J, G = solver.assemble(p, d)
-    dx, st, hs = solver.solve(J, G, solver.SolveConfig(rtol=rtol, maxit=3000))
+    cfg = solver.SolveConfig(rtol=rtol, maxit=3000)
+    dx, st, hs = solver.solve(J, G, cfg)
     Jo = oracle.jacobian(p)
     bo = -oracle.residual(p)
-    ao_pp = o_amg(Jo.n, Jo.rowptr, Jo.col, Jo.pp, tps.AmgParams(restriction=0))
-    ao_S = o_amg(Jo.n, Jo.rowptr, Jo.col, Jo.S, tps.AmgParams(restriction=1))
+    ao_pp = o_amg(Jo.n, Jo.rowptr, Jo.col, Jo.pp, solver.amg_params(cfg, "pp"))
+    ao_S = o_amg(Jo.n, Jo.rowptr, Jo.col, Jo.S, solver.amg_params(cfg, "S"))
     xo, io = oracle.gmres(Jo, ao_pp, ao_S, bo, rtol=rtol, maxit=3000)
     xd = _direct_reference(Jo, bo)
     x = np_(dx)
@@ -353,6 +356,34 @@ def test_solution_error_within_1e_6(case, rtol):
         assert e_g <= 1e-6 and e_o <= 1e-6
     for h in reversed(hs):
         h.close()
+
+
+def test_fgmres_stops_at_rounding_floor():
+    """With b = J v along the smallest singular direction v of J, the true
+    residual b - J x has a rounding floor near u cond(J) relative to ||b||.
+    Asked for 1e-3 of that floor, FGMRES ends with TP_NOT_CONVERGED once
+    cycles whose estimates met the tolerance stop moving the true residual,
+    long before maxit, with the true residual near the floor; asked for 1e3
+    times the floor, the same system converges."""
+    import torch
+    say("rounding floor")
+    p = CASES["W1"]()
+    d = solver.to_device(p)
+    J, G = solver.assemble(p, d)
+    A = oracle.sparse_interleaved(oracle.jacobian(p)).toarray()
+    _, sv, vt = np.linalg.svd(A)
+    b = torch.as_tensor(A @ vt[-1], device="cuda")
+    floor = U * sv[0] / sv[-1]
+    a_pp, a_S, M = solver.setup(J, solver.SolveConfig())
+    _, st = tps.fgmres_solve(J, M, b, rtol=1e-3 * floor, maxit=1000)
+    say(f"  cond {sv[0] / sv[-1]:.2e}, floor {floor:.2e}: {st['iters']} its, rel {st['rel_true']:.2e}, "
+        f"converged {st['converged']}")
+    assert not st["converged"] and st["iters"] < 300
+    assert 1e-3 * floor < st["rel_true"] <= 1e3 * floor
+    _, st2 = tps.fgmres_solve(J, M, b, rtol=1e3 * floor, maxit=1000)
+    say(f"  rtol {1e3 * floor:.2e}: {st2['iters']} its, rel {st2['rel_true']:.2e}")
+    assert st2["converged"] and st2["rel_true"] <= 1e3 * floor
+    M.close(); a_pp.close(); a_S.close()
 
 
 def test_fgmres_rtol_1e8_and_determinism():
@@ -614,8 +645,8 @@ def test_full_size_w2_end_to_end():
         h.close()
     Jd = tps.Jacobian.from_host(Jo.n, Jo.rowptr, Jo.col, Jo.pp, Jo.pT, Jo.Tp, Jo.TT, Jo.S)
     dx, st, hs = solver.solve(Jd, dev(-bo), cfg, history=True)
-    ao_pp = o_amg(Jo.n, Jo.rowptr, Jo.col, Jo.pp, tps.AmgParams(restriction=0))
-    ao_S = o_amg(Jo.n, Jo.rowptr, Jo.col, Jo.S, tps.AmgParams(restriction=1))
+    ao_pp = o_amg(Jo.n, Jo.rowptr, Jo.col, Jo.pp, solver.amg_params(cfg, "pp"))
+    ao_S = o_amg(Jo.n, Jo.rowptr, Jo.col, Jo.S, solver.amg_params(cfg, "S"))
     _compare_hierarchies(hs[0], ao_pp, "A_pp")
     _compare_hierarchies(hs[1], ao_S, "S")
     xo, io = oracle.gmres(Jo, ao_pp, ao_S, bo, rtol=rtol)
@@ -643,16 +674,17 @@ def test_vcycle_production_size_kernels(storage, bound):
     """A 96x96x32 layered grid (294,912 cells): its finest level takes the
     256-thread two-rows-per-thread DIA kernels (n/2 > 131072) and its first
     coarse level (~97k rows) the halved CSR lane groups of levels of >= 65536
-    rows, neither of which the small grids reach.  Both hierarchies are
-    compared level by level with the oracle's (FP64), and one V-cycle on a
+    rows, neither of which the small grids reach.  The pressure hierarchy
+    (direct and extended+i interpolation) and the Schur one are compared
+    level by level with the oracle's (FP64), and one V-cycle on a
     random right-hand side within 1e-12 (FP64; measured 4e-16 .. 8e-16) or
     the FP32 storage bound."""
     say("vcycle 96x96x32", storage)
     p = synth.make_problem("W2", grid=synth.Grid(96, 96, 32, 1, 1, 1))
     Jo, Jd = _oracle_J_on_device(p)
     b = synth.random_rhs(7, Jo.n)
-    for which, restr in (("pp", 0), ("S", 1)):
-        prm = tps.AmgParams(restriction=restr, storage=storage)
+    for which, restr, interp in (("pp", 0, 0), ("pp", 0, 1), ("S", 1, 0)):
+        prm = tps.AmgParams(restriction=restr, storage=storage, interp=interp)
         ho = o_amg(Jo.n, Jo.rowptr, Jo.col, getattr(Jo, which), prm)
         hg = tps.AMG(Jd.rowptr, Jd.col, getattr(Jd, which), prm)
         nd, _ = hg.level_format(0)
@@ -661,6 +693,6 @@ def test_vcycle_production_size_kernels(storage, bound):
         if storage == 0:
             _compare_hierarchies(hg, ho, which)
         err = relmax(np_(hg.vcycle(dev(b))), ho.vcycle(b))
-        say(f"  {which} storage {storage}: V-cycle rel err {err:.2e}")
+        say(f"  {which} interp {interp} storage {storage}: V-cycle rel err {err:.2e}")
         assert err <= bound
         hg.close()
