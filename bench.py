@@ -218,10 +218,13 @@ def write_traffic(fetch_db, write_db):
     import statistics
 
     def load(path):
+        # the calibration copy is the largest device-to-device copy dispatch
+        # (the runtime's blit kernel) of the run
         cur = sqlite3.connect(path).cursor()
         vals, top = [], 0.0
         for name, v in cur.execute("select name, counter_value from pmc_events"):
-            top = max(top, float(v))
+            if "copyBuffer" in name:
+                top = max(top, float(v))
             if TRAFFIC_KERNEL in name:
                 vals.append(float(v))
         return vals, top
@@ -239,6 +242,60 @@ def write_traffic(fetch_db, write_db):
     with open(TRAFFIC_JSON, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec))
+
+
+KERNELS_MD = os.path.join(ROOT, "profiles", "kernels_256x256x64_mixed_learned.md")
+
+
+def write_kernel_summary(db, bench_line, unprofiled=None):
+    """Per-kernel summary of a rocprofv3 --kernel-trace database of
+    `bench.py --steps 2 --warmup 1 --no-variants --no-cpu-baseline` (with
+    the JSON line that run printed): dispatches, total and mean duration of
+    the kernels that take most time, and the roofline kernel's mean beside
+    the means measured with HIP events by that run and (`unprofiled`, the
+    JSON line of a default run without the profiler) by an unprofiled run."""
+    import re
+    import sqlite3
+    import statistics
+    cur = sqlite3.connect(db).cursor()
+    agg = {}
+    for name, s, e in cur.execute("select name, start, end from kernels"):
+        k = re.sub(r"\(.*", "", name).replace("void ", "")
+        agg.setdefault(k, []).append((e - s) / 1e3)
+    line = json.loads(open(bench_line).read().strip().splitlines()[-1])
+    rf = line["roofline"]
+    rk = [v for k, v in agg.items() if k.endswith(TRAFFIC_KERNEL)]
+    rk = rk[0] if rk else []
+    tot = sum(sum(v) for v in agg.values())
+    out = ["# Kernel trace: 256x256x64, mixed precision + learned form (short bench run)", "",
+           "Commands (repository root, one MI355X):", "", "```",
+           "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_bench -o run -- "
+           "python3 -u bench.py --steps 2 --warmup 1 --no-variants --no-cpu-baseline > gpurun_out/prof_bench.json",
+           "python3 bench.py --write-kernel-summary gpurun_out/prof_bench/run_results.db gpurun_out/prof_bench.json"
+           + (f" {unprofiled}" if unprofiled else ""),
+           "```", "",
+           "The run trains the network, prepares the Newton systems, times the mixed + learned, FP64 and FP32 "
+           "forms, stamps every launch of the roofline kernel with HIP events over two solves, and measures the "
+           "preconditioner applies.  All kernels of the whole run are counted.", "",
+           f"Roofline kernel `{TRAFFIC_KERNEL}`: rocprofv3 {len(rk)} dispatches, mean "
+           f"{statistics.mean(rk) if rk else 0:.3f} us, median {statistics.median(rk) if rk else 0:.3f} us; "
+           f"the run's HIP events: {rf['launches']} launches, mean {rf['mean_us']} us "
+           f"({rf['bytes_per_launch']} algorithmic bytes per launch, {rf['achieved']} GB/s, frac {rf['frac']}).", ""]
+    if unprofiled:
+        ru = json.loads(open(unprofiled).read().strip().splitlines()[-1])["roofline"]
+        out += [f"The default run without the profiler (`python3 bench.py`) measured {ru['launches']} launches "
+                f"at a mean of {ru['mean_us']} us ({ru['achieved']} GB/s, frac {ru['frac']}), within "
+                f"{100 * abs(ru['mean_us'] / statistics.mean(rk) - 1) if rk else 0:.1f}% of the profiler's "
+                "kernel-trace mean; under the profiler the event pairs read longer, since the profiler's own "
+                "handling of each dispatch falls between them.", ""]
+    out += [f"Total kernel time {tot / 1e3:.1f} ms.", "",
+            "| kernel | dispatches | total ms | mean us | share |", "|---|---|---|---|---|"]
+    for k, v in sorted(agg.items(), key=lambda x: -sum(x[1]))[:40]:
+        out.append(f"| `{k[:90]}` | {len(v)} | {sum(v) / 1e3:.2f} | {statistics.mean(v):.1f} | "
+                   f"{100 * sum(v) / tot:.1f}% |")
+    with open(KERNELS_MD, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print(f"wrote {KERNELS_MD}")
 
 
 def _traffic():
@@ -418,9 +475,15 @@ def main():
                     help="two solves of the timed form plus the calibration copy (for counter runs)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="write the roofline kernel's traffic record from two rocprofv3 --pmc databases and exit")
+    ap.add_argument("--write-kernel-summary", nargs="+", metavar="PATH",
+                    help="TRACE_DB BENCH_JSON [UNPROFILED_JSON]: write the kernel-trace summary of a short "
+                         "bench run and exit")
     args = ap.parse_args()
     if args.write_traffic:
         write_traffic(*args.write_traffic)
+        return
+    if args.write_kernel_summary:
+        write_kernel_summary(*args.write_kernel_summary)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only: --gpus must be 1 "
