@@ -647,11 +647,14 @@ k_ext_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restr
 }
 
 // Wavefront-per-row form for levels of long rows.  Weight slot t of the row
-// lives in a register of lane t mod 64; the terms of each sum are broadcast
-// to the wavefront one by one in the order of the one-thread form, so every
-// slot, a~_ii and every den_k receive the same operations in the same order
-// (identical results).  Rows of more than EXT_SLOTS slots take the one-thread
-// form on lane 0.  Truncation (pmax > 0, longer rows): pmax rounds of a
+// lives in a register of lane t mod 64, and that lane forms the slot's sum:
+// the row's own coupling, then for each strong F neighbour k in the row's
+// order the term of row k's entry in the slot's column (binary search; a
+// row holds a column once), as the one-thread form adds them.  a~_ii and
+// every den_k are sums over a row: their terms are broadcast to the
+// wavefront one by one in row order.  So every slot, a~_ii and every den_k
+// receive the same operations in the same order (identical results).  Rows
+// of more than EXT_SLOTS slots take the one-thread form on lane 0.  Truncation (pmax > 0, longer rows): pmax rounds of a
 // wavefront arg-max over (|w|, then the smaller slot) select the kept slots,
 // the full and the kept sums run slot by slot in column order, and the kept
 // weights, scaled by their ratio, are written in column order.
@@ -684,15 +687,39 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
     }
     const int32_t* Si = Sc + Srp[i];
     const int32_t slen = Srp[i + 1] - Srp[i];
+    // the row's interpolatory set in LDS (binary searches of the den sums)
+    __shared__ int32_t s_list[WR_ROWS][EXT_SLOTS];
+    int32_t* const sl = s_list[threadIdx.x / WR];
+    for (int32_t t = lane; t < len; t += WR) sl[t] = list[t];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // slot t = r * WR + lane lives in w[r] of its lane; its column
+    int32_t lc[EXT_NW];
+#pragma unroll
+    for (int r = 0; r < EXT_NW; ++r) lc[r] = r * WR + lane < len ? sl[r * WR + lane] : -1;
+    const int32_t a = rowptr[i], e = rowptr[i + 1];
+    // position of column x in row k's sorted columns, or -1
+    auto find_in_row = [&](int32_t kb, int32_t ke, int32_t x) -> int32_t {
+        int32_t lo = kb, hi = ke;
+        while (lo < hi) {
+            const int32_t mid = lo + (hi - lo) / 2;
+            if (col[mid] < x) lo = mid + 1;
+            else hi = mid;
+        }
+        return (lo < ke && col[lo] == x) ? lo : -1;
+    };
+    // slot sums start from the row's own coupling (0.0 + a_ij: each column
+    // occurs once in row i) -- found by each slot's lane
     double w[EXT_NW];
 #pragma unroll
-    for (int r = 0; r < EXT_NW; ++r) w[r] = 0.0;
-    auto add = [&](int32_t pos, double c) {  // slot pos += c, on its owner lane
-#pragma unroll
-        for (int r = 0; r < EXT_NW; ++r)
-            if (pos == r * WR + lane) w[r] += c;
-    };
-    const int32_t a = rowptr[i], e = rowptr[i + 1];
+    for (int r = 0; r < EXT_NW; ++r) {
+        w[r] = 0.0;
+        if (lc[r] >= 0) {
+            const int32_t q = find_in_row(a, e, lc[r]);
+            if (q >= 0) w[r] += val[q];
+        }
+    }
     double aii = 0.0;
     bool has = false;
     for (int32_t q = a + lane; q < e; q += WR)
@@ -700,28 +727,23 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
     const uint64_t hm = __ballot(has);
     aii = hm ? __shfl(aii, __ffsll((unsigned long long)hm) - 1, WR) : 0.0;
     double at = aii;
-    // the row's own couplings
+    // weak couplings outside the set, lumped in row order
     for (int32_t b = a; b < e; b += WR) {
         const int32_t q = b + lane;
         const bool ok = q < e;
         const int32_t j = ok ? col[q] : i;
         const double v = ok ? val[q] : 0.0;
-        int32_t pos = -1;
-        bool lump = false;
-        if (ok && j != i) {
-            pos = find_sorted(list, len, j);
-            lump = pos < 0 && find_sorted(Si, slen, j) < 0;
-        }
+        const bool lump = ok && j != i && find_sorted(sl, len, j) < 0 && find_sorted(Si, slen, j) < 0;
+        const uint64_t lm = __ballot(lump);
         const int cnt = min(WR, (int)(e - b));
         for (int l = 0; l < cnt; ++l) {
-            const int32_t pl = __shfl(pos, l, WR);
             const double vl = __shfl(v, l, WR);
-            const bool ll = __shfl((int)lump, l, WR);
-            if (pl >= 0) add(pl, vl);
-            else if (ll) at += vl;
+            if ((lm >> l) & 1ull) at += vl;
         }
     }
-    // strong F neighbours k, ascending
+    // strong F neighbours k, ascending: each adds its term to every slot
+    // whose column row k holds (one term per slot and k, so each slot's sum
+    // runs over k in the row's order) and at most one term to a~_ii
     for (int32_t b = a; b < e; b += WR) {
         const int32_t q = b + lane;
         const bool ok = q < e;
@@ -744,36 +766,28 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
             for (int32_t c0 = kb; c0 < ke; c0 += WR) {
                 const int32_t u = c0 + lane;
                 const bool in = u < ke;
-                const int32_t lc = in ? col[u] : -1;
-                const bool mem = in && (lc == i || find_sorted(list, len, lc) >= 0);
+                const int32_t lcu = in ? col[u] : -1;
+                const bool mem = in && (lcu == i || find_sorted(sl, len, lcu) >= 0);
                 const double h = mem ? opposite(val[u], akk) : 0.0;
                 const uint64_t mm = __ballot(mem);
                 const int cnt = min(WR, (int)(ke - c0));
-                for (int t = 0; t < cnt; ++t) {
-                    const double ht = __shfl(h, t, WR);
-                    if ((mm >> t) & 1ull) den += ht;
+                for (int tt = 0; tt < cnt; ++tt) {
+                    const double ht = __shfl(h, tt, WR);
+                    if ((mm >> tt) & 1ull) den += ht;
                 }
             }
             if (den == 0.0) {
                 at += aik;
                 continue;
             }
-            for (int32_t c0 = kb; c0 < ke; c0 += WR) {
-                const int32_t u = c0 + lane;
-                const bool in = u < ke;
-                const int32_t lc = in ? col[u] : -1;
-                const double c = in ? (aik * opposite(val[u], akk)) / den : 0.0;
-                const int32_t pos = in ? find_sorted(list, len, lc) : -1;
-                const bool self = in && pos < 0 && lc == i;
-                const int cnt = min(WR, (int)(ke - c0));
-                for (int t = 0; t < cnt; ++t) {
-                    const int32_t pt = __shfl(pos, t, WR);
-                    const double ct = __shfl(c, t, WR);
-                    const bool st = __shfl((int)self, t, WR);
-                    if (pt >= 0) add(pt, ct);
-                    else if (st) at += ct;
-                }
+#pragma unroll
+            for (int r = 0; r < EXT_NW; ++r) {
+                if (lc[r] < 0) continue;
+                const int32_t u = find_in_row(kb, ke, lc[r]);
+                if (u >= 0) w[r] += (aik * opposite(val[u], akk)) / den;
             }
+            const int32_t ui = find_in_row(kb, ke, i);
+            if (ui >= 0) at += (aik * opposite(val[ui], akk)) / den;
         }
     }
 #pragma unroll
@@ -990,17 +1004,272 @@ k_spgemm_fill(const int32_t* __restrict__ rows, const int32_t* __restrict__ nrow
     }
 }
 
+// list[0 .. n) = 0 .. n-1 and *count = n
+__global__ void __launch_bounds__(B)
+k_iota_i32(int32_t n, int32_t* __restrict__ list, int32_t* __restrict__ count) {
+    const int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i < n) list[i] = i;
+    if (i == 0) *count = n;
+}
+
+// ---- long rows: a workgroup per output row ------------------------------------------------
+// The rows the short path hands over (more A entries than its lane group, or
+// more products than it sorts).  A workgroup of LG_T threads takes a row:
+// the B-row lengths of its A entries are scanned into first-product slots,
+// every thread loads product slots e, e + LG_T, ... (slot e belongs to the
+// last A entry whose first slot is <= e) and inserts the column into the
+// LDS hash table (a slot already holding the column is seen by a plain
+// read; only an empty slot takes an atomic).  The numeric pass sorts the
+// distinct columns (rank sort), then sends every product a_iq b_qc to
+// M[p][q], p the output position of c (binary search in the sorted
+// columns), in LDS -- each A entry's B row holds a column at most once, and
+// absent pairs hold +0.0 -- and sums each output's row of M over q
+// ascending from +0.0.  That is the sum of the hash-table kernels above, in
+// their order (a +0.0 term never changes a sum that starts at +0.0), so the
+// values are identical.  Rows whose M would exceed LG_M entries search the
+// B rows in global memory instead, as those kernels do; rows with more than
+// LA_MAX A entries are listed for them.
+constexpr int LG_T = 256;
+constexpr int LG_W = LG_T / 64;
+constexpr int LG_M = 3072;
+constexpr int LA_MAX = 512;
+
+// exclusive prefix of v over the workgroup (thread order) and the total
+__device__ inline int32_t block_exscan(int32_t v, int32_t* s_wave, int32_t* total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int32_t inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t o = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += o;
+    }
+    if (lane == 63) s_wave[w] = inc;
+    __syncthreads();
+    int32_t before = 0, all = 0;
+    for (int q = 0; q < LG_W; ++q) {
+        if (q < w) before += s_wave[q];
+        all += s_wave[q];
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - v;
+}
+
+// index of the last A entry whose first product slot is <= e
+__device__ inline int32_t owner_entry(const int32_t* s_off, int32_t la, int32_t e) {
+    int32_t lo = 0, hi = la - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (s_off[mid] <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// insert c into the open-addressed table (size mask + 1); counts new keys
+__device__ inline void lg_insert(int32_t* tab, int32_t c, int lg, int32_t mask, int32_t* count,
+                                 int32_t* overflow) {
+    int32_t hh = hslot(c, lg);
+    int probes = 0;
+    while (true) {
+        const int32_t cur = __hip_atomic_load(&tab[hh], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (cur == c) return;
+        if (cur == -1) {
+            const int32_t old = atomicCAS(&tab[hh], -1, c);
+            if (old == -1) {
+                atomicAdd(count, 1);
+                return;
+            }
+            if (old == c) return;
+        }
+        hh = (hh + 1) & mask;
+        if (++probes > mask) {
+            *overflow = 1;
+            return;
+        }
+    }
+}
+
+template <bool NUMERIC>
+__global__ void __launch_bounds__(LG_T)
+k_spgemm_long(const int32_t* __restrict__ rows, const int32_t* __restrict__ nrows,
+              const int32_t* __restrict__ Arp, const int32_t* __restrict__ Ac, const double* __restrict__ Av,
+              const int32_t* __restrict__ Brp, const int32_t* __restrict__ Bc, const double* __restrict__ Bv,
+              int32_t* __restrict__ cnt, const int32_t* __restrict__ Crp, int32_t* __restrict__ Cc,
+              double* __restrict__ Cv, int32_t* __restrict__ vlong, int32_t* __restrict__ nvlong,
+              int32_t* __restrict__ gflag) {
+    __shared__ int32_t tab[HASH];
+    // the compacted keys (before the sort) and M (after it) share this space
+    __shared__ double s_m[NUMERIC ? (LG_M > HASH / 2 ? LG_M : HASH / 2) : 1];
+    int32_t* const list = reinterpret_cast<int32_t*>(s_m);
+    __shared__ int32_t s_off[LA_MAX + 1];
+    __shared__ int32_t s_b0[LA_MAX];
+    __shared__ double s_av[NUMERIC ? LA_MAX : 1];
+    __shared__ int32_t s_wave[LG_W];
+    __shared__ int32_t count, overflow, ncomp;
+    constexpr int LG_U = 4;  // products a thread loads before it uses them
+    const int t = threadIdx.x;
+    const int32_t nr = *nrows;
+    for (int32_t idx = blockIdx.x; idx < nr; idx += gridDim.x) {
+        const int32_t i = rows[idx];
+        const int32_t a0 = Arp[i], la = Arp[i + 1] - a0;
+        if (la > LA_MAX) {  // (uniform across the workgroup)
+            if (t == 0) vlong[atomicAdd(nvlong, 1)] = i;
+            continue;
+        }
+        // entries 2t, 2t + 1: B-row starts and lengths, scanned into first slots
+        int32_t len2[2] = {0, 0};
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int32_t q = 2 * t + k;
+            if (q < la) {
+                const int32_t r = Ac[a0 + q];
+                const int32_t b0 = Brp[r];
+                s_b0[q] = b0;
+                len2[k] = Brp[r + 1] - b0;
+                if (NUMERIC) s_av[q] = Av[a0 + q];
+            }
+        }
+        int32_t total = 0;
+        const int32_t ex = block_exscan(len2[0] + len2[1], s_wave, &total);
+        if (2 * t < la) s_off[2 * t] = ex;
+        if (2 * t + 1 < la) s_off[2 * t + 1] = ex + len2[0];
+        if (t == 0) {
+            s_off[la] = total;
+            count = 0;
+            overflow = 0;
+            ncomp = 0;
+        }
+        int lg = 6;
+        while (lg < HASH_LOG && (1 << lg) < 2 * total) ++lg;
+        const int32_t mask = (1 << lg) - 1;
+        for (int h = t; h < (1 << lg); h += LG_T) tab[h] = -1;
+        __syncthreads();
+        for (int32_t e0 = t; e0 < total; e0 += LG_U * LG_T) {
+            int32_t cc[LG_U];
+#pragma unroll
+            for (int u = 0; u < LG_U; ++u) {
+                const int32_t e = e0 + u * LG_T;
+                cc[u] = -1;
+                if (e < total) {
+                    const int32_t q = owner_entry(s_off, la, e);
+                    cc[u] = Bc[s_b0[q] + (e - s_off[q])];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < LG_U; ++u)
+                if (e0 + u * LG_T < total) lg_insert(tab, cc[u], lg, mask, &count, &overflow);
+        }
+        __syncthreads();
+        if (!NUMERIC) {
+            if (t == 0) {
+                cnt[i] = count;
+                if (overflow) *gflag = 1;
+            }
+            __syncthreads();
+            continue;
+        }
+        const int32_t base = Crp[i];
+        if (overflow || count != Crp[i + 1] - base) {
+            // keep the row's slots valid (column 0, value 0) for the kernels
+            // that follow; the flag fails the setup at its end
+            for (int32_t q = base + t; q < Crp[i + 1]; q += LG_T) {
+                Cc[q] = 0;
+                Cv[q] = 0.0;
+            }
+            if (t == 0) *gflag = overflow ? 1 : 2;
+            __syncthreads();
+            continue;
+        }
+        for (int h = t; h < (1 << lg); h += LG_T) {
+            const int32_t c = tab[h];
+            if (c != -1) list[atomicAdd(&ncomp, 1)] = c;
+        }
+        __syncthreads();
+        const int32_t u = ncomp;
+        for (int32_t e = t; e < u; e += LG_T) {  // rank sort into tab[0 .. u)
+            const int32_t key = list[e];
+            int32_t rank = 0;
+            for (int32_t x = 0; x < u; ++x) rank += list[x] < key;
+            tab[rank] = key;
+        }
+        __syncthreads();  // (list is read until here; M takes its space)
+        const bool staged = (int64_t)u * la <= LG_M;
+        if (staged)
+            for (int32_t m = t; m < u * la; m += LG_T) s_m[m] = 0.0;
+        __syncthreads();
+        if (staged) {
+            for (int32_t e0 = t; e0 < total; e0 += LG_U * LG_T) {
+                int32_t cc[LG_U], qq[LG_U];
+                double vv[LG_U];
+#pragma unroll
+                for (int uu = 0; uu < LG_U; ++uu) {
+                    const int32_t e = e0 + uu * LG_T;
+                    qq[uu] = -1;
+                    if (e < total) {
+                        const int32_t q = owner_entry(s_off, la, e);
+                        const int32_t src = s_b0[q] + (e - s_off[q]);
+                        qq[uu] = q;
+                        cc[uu] = Bc[src];
+                        vv[uu] = s_av[q] * Bv[src];
+                    }
+                }
+#pragma unroll
+                for (int uu = 0; uu < LG_U; ++uu) {
+                    if (qq[uu] < 0) continue;
+                    int32_t lo = 0, hi = u - 1;  // the column's output position
+                    while (lo < hi) {
+                        const int32_t mid = (lo + hi) >> 1;
+                        if (tab[mid] < cc[uu]) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    s_m[lo * la + qq[uu]] = vv[uu];
+                }
+            }
+            __syncthreads();
+            for (int32_t e = t; e < u; e += LG_T) {
+                double acc = 0.0;
+                for (int32_t q = 0; q < la; ++q) acc += s_m[e * la + q];
+                Cc[base + e] = tab[e];
+                Cv[base + e] = acc;
+            }
+        } else {
+            for (int32_t e = t; e < u; e += LG_T) {
+                const int32_t c = tab[e];
+                double acc = 0.0;
+                for (int32_t q = 0; q < la; ++q) {
+                    const int32_t b0 = s_b0[q];
+                    int32_t lo = b0, hi = b0 + (s_off[q + 1] - s_off[q]) - 1;
+                    while (lo <= hi) {
+                        const int32_t mid = (lo + hi) >> 1;
+                        const int32_t v = Bc[mid];
+                        if (v == c) { acc += s_av[q] * Bv[mid]; break; }
+                        if (v < c) lo = mid + 1; else hi = mid - 1;
+                    }
+                }
+                Cc[base + e] = c;
+                Cv[base + e] = acc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ---- short rows: a lane group per output row ---------------------------------------------
 // A row with at most SR_G entries whose products number at most SR_MAX is
 // expanded into LDS in A-entry-major order (inner index ascending, and within
-// it B's sorted columns).  A column's output position is the number of
-// distinct smaller columns; its value is the sum of its products in that
-// order, i.e. in ascending inner index, the order of the hash-table path.
-// Other rows are appended to a list for the hash-table kernels. The per-lane
-// work grows with the square of the row's product count over SR_G, so
-// products with long rows (coarse levels, the Galerkin product) take 64-lane
-// groups with room for 256 products; the fine-level A P takes 16 lanes, 128
-// products. Both give the same values, in the same order.
+// it B's sorted columns): product e has column c_e and value a_ik b_kc.  The
+// keys c_e * SR_MAX + e are sorted in LDS by a bitonic network (padded to a
+// power of two), which groups each column's products in ascending e.  A
+// column's output position is the number of distinct smaller columns (heads
+// of the sorted runs before it); its value is the sum of its products in
+// ascending e from 0, i.e. in ascending inner index, the order of the
+// hash-table path.  Other rows are appended to a list for the long-row
+// kernels.  Products with long rows (coarse levels, the Galerkin product)
+// take 64-lane groups with room for 256 products; the fine-level A P takes
+// 16 lanes, 128 products.  Both give the same values, in the same order.
+// The keys need c < 2^31 / SR_MAX (the caller sends every row of a wider B
+// to the long-row kernels).
 constexpr int SR_T = 256;
 
 template <int SR_G, int SR_MAX>
@@ -1011,9 +1280,12 @@ k_spgemm_short(int32_t n, const int32_t* __restrict__ Arp, const int32_t* __rest
                int32_t* __restrict__ Cc, double* __restrict__ Cv, int32_t* __restrict__ long_rows,
                int32_t* __restrict__ nlong, int32_t* __restrict__ gflag, int numeric) {
     constexpr int SR_ROWS = SR_T / SR_G;
-    __shared__ int32_t s_c[SR_ROWS][SR_MAX];
+    constexpr int SHIFT = __builtin_ctz(SR_MAX);  // key = c << SHIFT | e
+    __shared__ uint32_t s_k[SR_ROWS][SR_MAX];
     __shared__ double s_v[SR_ROWS][SR_MAX];
-    __shared__ int8_t s_first[SR_ROWS][SR_MAX];
+    __shared__ int32_t s_off[SR_ROWS][SR_G];  // per A entry: first product slot, B-row start, value
+    __shared__ int32_t s_b0[SR_ROWS][SR_G];
+    __shared__ double s_av[SR_ROWS][SR_G];
     const int g = threadIdx.x / SR_G, lane = threadIdx.x % SR_G;
     const int32_t i = blockIdx.x * SR_ROWS + g;
     const bool valid = i < n;
@@ -1042,52 +1314,96 @@ k_spgemm_short(int32_t n, const int32_t* __restrict__ Arp, const int32_t* __rest
         return;  // the whole group leaves together (uniform across its lanes)
     }
     if (!valid) return;
-    for (int32_t q = 0; q < lb; ++q) {
-        s_c[g][off + q] = Bc[b0 + q];
-        if (numeric) s_v[g][off + q] = av * Bv[b0 + q];
+    // Expansion, product slot e on lane e mod SR_G: its A entry t is the last
+    // one whose first slot is <= e (entries with empty B rows share their
+    // successor's first slot and are never the last such one), and its
+    // product is B's entry e - off_t of that row.  Every lane loads its own
+    // slots, so the row's loads are in flight together.
+    if (lane < la) {
+        s_off[g][lane] = off;
+        s_b0[g][lane] = b0;
+        s_av[g][lane] = av;
+    }
+    int np = 2;  // sorted length: a power of two >= total
+    while (np < total) np <<= 1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int32_t e = lane; e < np; e += SR_G) {
+        if (e >= total) {
+            s_k[g][e] = 0xFFFFFFFFu;
+            continue;
+        }
+        int32_t lo = 0, hi = la - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (s_off[g][mid] <= e) lo = mid;
+            else hi = mid - 1;
+        }
+        const int32_t src = s_b0[g][lo] + (e - s_off[g][lo]);
+        s_k[g][e] = ((uint32_t)Bc[src] << SHIFT) | (uint32_t)e;
+        if (numeric) s_v[g][e] = s_av[g][lo] * Bv[src];
+    }
+    // bitonic sort of the np keys, ascending
+    for (int size = 2; size <= np; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int pi = lane; pi < np / 2; pi += SR_G) {
+                const int lo = 2 * stride * (pi / stride) + (pi % stride);
+                const int hi = lo + stride;
+                const uint32_t x = s_k[g][lo], y = s_k[g][hi];
+                const bool up = (lo & size) == 0;
+                if ((x > y) == up) {
+                    s_k[g][lo] = y;
+                    s_k[g][hi] = x;
+                }
+            }
+        }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // first occurrences of every column
-    int32_t nfirst = 0;
-    for (int32_t e = lane; e < total; e += SR_G) {
-        const int32_t c = s_c[g][e];
-        bool first = true;
-        for (int32_t e2 = 0; e2 < e; ++e2) first = first && s_c[g][e2] != c;
-        s_first[g][e] = first ? 1 : 0;
-        nfirst += first ? 1 : 0;
+    // heads of the column runs, counted round by round (lanes of one round
+    // hold consecutive sorted elements)
+    const int gshift = (int)((threadIdx.x % 64) / SR_G) * SR_G;  // the group's first lane in its wavefront
+    const uint64_t gmask = SR_G == 64 ? ~0ull : ((1ull << SR_G) - 1ull) << gshift;
+    int32_t heads_before = 0;
+    int32_t base = 0;
+    if (numeric) base = Crp[i];
+    for (int32_t e0 = 0; e0 < total; e0 += SR_G) {
+        const int32_t e = e0 + lane;
+        const bool in = e < total;
+        const uint32_t key = in ? s_k[g][e] : 0u;
+        const uint32_t c = key >> SHIFT;
+        const bool head = in && (e == 0 || (s_k[g][e - 1] >> SHIFT) != c);
+        const uint64_t hm = __ballot(head) & gmask;
+        if (numeric && head) {
+            const int32_t pos = heads_before + __popcll(hm & ((1ull << (threadIdx.x % 64)) - 1ull));
+            double acc = 0.0;
+            for (int32_t e2 = e; e2 < total; ++e2) {
+                const uint32_t k2 = s_k[g][e2];
+                if ((k2 >> SHIFT) != c) break;
+                acc += s_v[g][k2 & (SR_MAX - 1)];
+            }
+            if (pos < Crp[i + 1] - base) {  // (a count mismatch is cleared and flagged below)
+                Cc[base + pos] = (int32_t)c;
+                Cv[base + pos] = acc;
+            }
+        }
+        heads_before += __popcll(hm);
     }
-#pragma unroll
-    for (int d = SR_G / 2; d > 0; d >>= 1) nfirst += __shfl_xor(nfirst, d, SR_G);
     if (!numeric) {
-        if (lane == 0) cnt[i] = nfirst;
+        if (lane == 0) cnt[i] = heads_before;
         return;
     }
-    const int32_t base = Crp[i];
-    if (nfirst != Crp[i + 1] - base) {  // must equal the symbolic count
+    if (heads_before != Crp[i + 1] - base) {  // must equal the symbolic count
         for (int32_t q = base + lane; q < Crp[i + 1]; q += SR_G) {
             Cc[q] = 0;
             Cv[q] = 0.0;
         }
         if (lane == 0) *gflag = 2;
-        return;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int32_t e = lane; e < total; e += SR_G) {
-        if (!s_first[g][e]) continue;
-        const int32_t c = s_c[g][e];
-        int32_t pos = 0;
-        double acc = 0.0;
-        for (int32_t e2 = 0; e2 < total; ++e2) {
-            const int32_t c2 = s_c[g][e2];
-            pos += (s_first[g][e2] && c2 < c) ? 1 : 0;
-            if (c2 == c) acc += s_v[g][e2];
-        }
-        Cc[base + pos] = c;
-        Cv[base + pos] = acc;
     }
 }
 
@@ -1097,15 +1413,19 @@ static void spgemm(const Csr& A, const Csr& Bm, Csr& C, int32_t* flag, hipStream
     C.n = A.n;
     C.m = Bm.m;
     C.rowptr.alloc(A.n + 1, s);
-    DBuf<int32_t> long_rows(std::max(A.n, 1), s), nlong(1, s);
+    DBuf<int32_t> long_rows(std::max(A.n, 1), s), nlong(1, s), vlong(std::max(A.n, 1), s), nvlong(1, s);
     TP_LAUNCH(k_fill_i32, 1, B, 0, s, nlong.p, 0, (int64_t)1);
     const int grid = std::min<int>(std::max<int>(A.n, 1), 16384);
     // products per output row, estimated from the operands' mean row lengths
     // (host sizes: exact for level operators, upper bounds for P and R)
     const double est = ((double)A.nnz / std::max(A.n, 1)) * ((double)Bm.nnz / std::max(Bm.n, 1));
     const bool wide = est >= 64.0;
+    // the short kernels' sort keys hold a column in 23 bits
+    const bool keys_fit = Bm.m < (1 << 23);
     auto short_pass = [&](int32_t* cnt, const int32_t* crp, int32_t* cc, double* cv, int numeric) {
-        if (wide) {
+        if (!keys_fit) {  // every row to the long-row kernels
+            TP_LAUNCH(k_iota_i32, cdiv(A.n, B), B, 0, s, A.n, long_rows.p, nlong.p);
+        } else if (wide) {
             TP_LAUNCH((k_spgemm_short<64, 256>), cdiv(A.n, SR_T / 64), SR_T, 0, s, A.n, A.rowptr.p, A.col.p,
                       A.val.p, Bm.rowptr.p, Bm.col.p, Bm.val.p, cnt, crp, cc, cv, long_rows.p, nlong.p, flag,
                       numeric);
@@ -1115,9 +1435,16 @@ static void spgemm(const Csr& A, const Csr& Bm, Csr& C, int32_t* flag, hipStream
                       numeric);
         }
     };
+    // long rows: a workgroup per row (k_spgemm_long); rows of more than
+    // LA_MAX A entries go on to the one-wavefront hash-table kernels
+    const int lgrid = std::min<int>(std::max<int>(A.n, 1), 8192);
     if (A.n > 0) {
+        TP_LAUNCH(k_fill_i32, 1, B, 0, s, nvlong.p, 0, (int64_t)1);
         short_pass(C.rowptr.p, nullptr, nullptr, nullptr, 0);
-        TP_LAUNCH(k_spgemm_count, grid, SG_WAVE, 0, s, (const int32_t*)long_rows.p, (const int32_t*)nlong.p,
+        TP_LAUNCH(k_spgemm_long<false>, lgrid, LG_T, 0, s, (const int32_t*)long_rows.p, (const int32_t*)nlong.p,
+                  A.rowptr.p, A.col.p, A.val.p, Bm.rowptr.p, Bm.col.p, Bm.val.p, C.rowptr.p, (const int32_t*)nullptr,
+                  (int32_t*)nullptr, (double*)nullptr, vlong.p, nvlong.p, flag);
+        TP_LAUNCH(k_spgemm_count, grid, SG_WAVE, 0, s, (const int32_t*)vlong.p, (const int32_t*)nvlong.p,
                   A.rowptr.p, A.col.p, Bm.rowptr.p, Bm.col.p, C.rowptr.p, flag);
     }
     scan_exclusive(C.rowptr.p, C.rowptr.p, A.n, s);
@@ -1127,10 +1454,14 @@ static void spgemm(const Csr& A, const Csr& Bm, Csr& C, int32_t* flag, hipStream
     C.col.alloc(C.nnz, s);
     C.val.alloc(C.nnz, s);
     if (A.n > 0) {
-        // the short pass lists the long rows again: start the list afresh
+        // the passes list the long rows again: start the lists afresh
         TP_LAUNCH(k_fill_i32, 1, B, 0, s, nlong.p, 0, (int64_t)1);
+        TP_LAUNCH(k_fill_i32, 1, B, 0, s, nvlong.p, 0, (int64_t)1);
         short_pass(nullptr, C.rowptr.p, C.col.p, C.val.p, 1);
-        TP_LAUNCH(k_spgemm_fill, grid, SG_WAVE, 0, s, (const int32_t*)long_rows.p, (const int32_t*)nlong.p,
+        TP_LAUNCH(k_spgemm_long<true>, lgrid, LG_T, 0, s, (const int32_t*)long_rows.p, (const int32_t*)nlong.p,
+                  A.rowptr.p, A.col.p, A.val.p, Bm.rowptr.p, Bm.col.p, Bm.val.p, (int32_t*)nullptr,
+                  (const int32_t*)C.rowptr.p, C.col.p, C.val.p, vlong.p, nvlong.p, flag);
+        TP_LAUNCH(k_spgemm_fill, grid, SG_WAVE, 0, s, (const int32_t*)vlong.p, (const int32_t*)nvlong.p,
                   A.rowptr.p, A.col.p, A.val.p, Bm.rowptr.p, Bm.col.p, Bm.val.p, C.rowptr.p, C.col.p, C.val.p,
                   flag);
     }
