@@ -660,6 +660,7 @@ k_ext_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restr
 // weights, scaled by their ratio, are written in column order.
 constexpr int EXT_NW = 4;
 constexpr int EXT_SLOTS = WR * EXT_NW;
+constexpr int EXT_KROW = 256;  // rows of strong F neighbours up to this long are staged in LDS
 
 __global__ void __launch_bounds__(B)
 k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
@@ -689,7 +690,11 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
     const int32_t slen = Srp[i + 1] - Srp[i];
     // the row's interpolatory set in LDS (binary searches of the den sums)
     __shared__ int32_t s_list[WR_ROWS][EXT_SLOTS];
+    __shared__ int32_t s_kc[WR_ROWS][EXT_KROW];  // the current strong F neighbour's row
+    __shared__ double s_kv[WR_ROWS][EXT_KROW];
     int32_t* const sl = s_list[threadIdx.x / WR];
+    int32_t* const s_kc_w = s_kc[threadIdx.x / WR];
+    double* const s_kv_w = s_kv[threadIdx.x / WR];
     for (int32_t t = lane; t < len; t += WR) sl[t] = list[t];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -756,21 +761,40 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
             const int32_t k = __shfl(k0, l, WR);
             const double aik = __shfl(ok ? val[q] : 0.0, l, WR);
             const int32_t kb = rowptr[k], ke = rowptr[k + 1];
+            // row k in LDS (one coalesced load; the searches below then stay
+            // on chip) when it fits, else read in place
+            const bool kst = ke - kb <= EXT_KROW;
+            const int32_t* kc = col + kb;
+            const double* kv = val + kb;
+            if (kst) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                for (int32_t u = lane; u < ke - kb; u += WR) {
+                    s_kc_w[u] = col[kb + u];
+                    s_kv_w[u] = val[kb + u];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                kc = s_kc_w;
+                kv = s_kv_w;
+            }
+            const int32_t kl = ke - kb;
             double akk = 0.0;
             bool hk = false;
-            for (int32_t u = kb + lane; u < ke; u += WR)
-                if (col[u] == k) { akk = val[u]; hk = true; }
+            for (int32_t u = lane; u < kl; u += WR)
+                if (kc[u] == k) { akk = kv[u]; hk = true; }
             const uint64_t km = __ballot(hk);
             akk = km ? __shfl(akk, __ffsll((unsigned long long)km) - 1, WR) : 0.0;
             double den = 0.0;
-            for (int32_t c0 = kb; c0 < ke; c0 += WR) {
+            for (int32_t c0 = 0; c0 < kl; c0 += WR) {
                 const int32_t u = c0 + lane;
-                const bool in = u < ke;
-                const int32_t lcu = in ? col[u] : -1;
+                const bool in = u < kl;
+                const int32_t lcu = in ? kc[u] : -1;
                 const bool mem = in && (lcu == i || find_sorted(sl, len, lcu) >= 0);
-                const double h = mem ? opposite(val[u], akk) : 0.0;
+                const double h = mem ? opposite(kv[u], akk) : 0.0;
                 const uint64_t mm = __ballot(mem);
-                const int cnt = min(WR, (int)(ke - c0));
+                const int cnt = min(WR, (int)(kl - c0));
                 for (int tt = 0; tt < cnt; ++tt) {
                     const double ht = __shfl(h, tt, WR);
                     if ((mm >> tt) & 1ull) den += ht;
@@ -783,11 +807,11 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
 #pragma unroll
             for (int r = 0; r < EXT_NW; ++r) {
                 if (lc[r] < 0) continue;
-                const int32_t u = find_in_row(kb, ke, lc[r]);
-                if (u >= 0) w[r] += (aik * opposite(val[u], akk)) / den;
+                const int32_t u = find_sorted(kc, kl, lc[r]);
+                if (u >= 0) w[r] += (aik * opposite(kv[u], akk)) / den;
             }
-            const int32_t ui = find_in_row(kb, ke, i);
-            if (ui >= 0) at += (aik * opposite(val[ui], akk)) / den;
+            const int32_t ui = find_sorted(kc, kl, i);
+            if (ui >= 0) at += (aik * opposite(kv[ui], akk)) / den;
         }
     }
 #pragma unroll
@@ -1264,8 +1288,9 @@ k_spgemm_long(const int32_t* __restrict__ rows, const int32_t* __restrict__ nrow
 // column's output position is the number of distinct smaller columns (heads
 // of the sorted runs before it); its value is the sum of its products in
 // ascending e from 0, i.e. in ascending inner index, the order of the
-// hash-table path.  Other rows are appended to a list for the long-row
-// kernels.  Products with long rows (coarse levels, the Galerkin product)
+// hash-table path.  The row's columns and values go to its staging offset
+// Crp[i], their count to cnt[i].  Other rows are appended to a list for the
+// long-row kernels.  Products with long rows (coarse levels, the Galerkin product)
 // take 64-lane groups with room for 256 products; the fine-level A P takes
 // 16 lanes, 128 products.  Both give the same values, in the same order.
 // The keys need c < 2^31 / SR_MAX (the caller sends every row of a wider B
@@ -1278,7 +1303,7 @@ k_spgemm_short(int32_t n, const int32_t* __restrict__ Arp, const int32_t* __rest
                const double* __restrict__ Av, const int32_t* __restrict__ Brp, const int32_t* __restrict__ Bc,
                const double* __restrict__ Bv, int32_t* __restrict__ cnt, const int32_t* __restrict__ Crp,
                int32_t* __restrict__ Cc, double* __restrict__ Cv, int32_t* __restrict__ long_rows,
-               int32_t* __restrict__ nlong, int32_t* __restrict__ gflag, int numeric) {
+               int32_t* __restrict__ nlong) {
     constexpr int SR_ROWS = SR_T / SR_G;
     constexpr int SHIFT = __builtin_ctz(SR_MAX);  // key = c << SHIFT | e
     __shared__ uint32_t s_k[SR_ROWS][SR_MAX];
@@ -1342,7 +1367,7 @@ k_spgemm_short(int32_t n, const int32_t* __restrict__ Arp, const int32_t* __rest
         }
         const int32_t src = s_b0[g][lo] + (e - s_off[g][lo]);
         s_k[g][e] = ((uint32_t)Bc[src] << SHIFT) | (uint32_t)e;
-        if (numeric) s_v[g][e] = s_av[g][lo] * Bv[src];
+        s_v[g][e] = s_av[g][lo] * Bv[src];
     }
     // bitonic sort of the np keys, ascending
     for (int size = 2; size <= np; size <<= 1) {
@@ -1370,8 +1395,7 @@ k_spgemm_short(int32_t n, const int32_t* __restrict__ Arp, const int32_t* __rest
     const int gshift = (int)((threadIdx.x % 64) / SR_G) * SR_G;  // the group's first lane in its wavefront
     const uint64_t gmask = SR_G == 64 ? ~0ull : ((1ull << SR_G) - 1ull) << gshift;
     int32_t heads_before = 0;
-    int32_t base = 0;
-    if (numeric) base = Crp[i];
+    const int32_t base = Crp[i];
     for (int32_t e0 = 0; e0 < total; e0 += SR_G) {
         const int32_t e = e0 + lane;
         const bool in = e < total;
@@ -1379,7 +1403,7 @@ k_spgemm_short(int32_t n, const int32_t* __restrict__ Arp, const int32_t* __rest
         const uint32_t c = key >> SHIFT;
         const bool head = in && (e == 0 || (s_k[g][e - 1] >> SHIFT) != c);
         const uint64_t hm = __ballot(head) & gmask;
-        if (numeric && head) {
+        if (head) {
             const int32_t pos = heads_before + __popcll(hm & ((1ull << (threadIdx.x % 64)) - 1ull));
             double acc = 0.0;
             for (int32_t e2 = e; e2 < total; ++e2) {
@@ -1387,23 +1411,48 @@ k_spgemm_short(int32_t n, const int32_t* __restrict__ Arp, const int32_t* __rest
                 if ((k2 >> SHIFT) != c) break;
                 acc += s_v[g][k2 & (SR_MAX - 1)];
             }
-            if (pos < Crp[i + 1] - base) {  // (a count mismatch is cleared and flagged below)
-                Cc[base + pos] = (int32_t)c;
-                Cv[base + pos] = acc;
-            }
+            Cc[base + pos] = (int32_t)c;
+            Cv[base + pos] = acc;
         }
         heads_before += __popcll(hm);
     }
-    if (!numeric) {
-        if (lane == 0) cnt[i] = heads_before;
-        return;
-    }
-    if (heads_before != Crp[i + 1] - base) {  // must equal the symbolic count
-        for (int32_t q = base + lane; q < Crp[i + 1]; q += SR_G) {
-            Cc[q] = 0;
-            Cv[q] = 0.0;
+    if (lane == 0) cnt[i] = heads_before;
+}
+
+// Staging offsets of the short path: ub[i] = the row's product count when
+// k_spgemm_short<SR_G, SR_MAX> takes it (at most SR_G A entries and SR_MAX
+// products), else 0.  (Its distinct columns number at most that.)
+template <int SR_G, int SR_MAX>
+__global__ void __launch_bounds__(B)
+k_spgemm_ub(int32_t n, const int32_t* __restrict__ Arp, const int32_t* __restrict__ Ac,
+            const int32_t* __restrict__ Brp, int32_t* __restrict__ ub) {
+    const int32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= n) return;
+    const int32_t a0 = Arp[i], la = Arp[i + 1] - a0;
+    int32_t total = 0;
+    if (la <= SR_G)
+        for (int32_t q = 0; q < la; ++q) {
+            const int32_t r = Ac[a0 + q];
+            total += Brp[r + 1] - Brp[r];
         }
-        if (lane == 0) *gflag = 2;
+    ub[i] = (la <= SR_G && total <= SR_MAX) ? total : 0;
+}
+
+// C's rows from the short path's staging (rows of nonzero staging length;
+// the long rows were written in place), SR_C lanes a row
+constexpr int SR_C = 16;
+__global__ void __launch_bounds__(B)
+k_spgemm_compact(int32_t n, const int32_t* __restrict__ ubp, const int32_t* __restrict__ Tc,
+                 const double* __restrict__ Tv, const int32_t* __restrict__ Crp, int32_t* __restrict__ Cc,
+                 double* __restrict__ Cv) {
+    const int64_t tid = (int64_t)blockIdx.x * B + threadIdx.x;
+    const int32_t i = (int32_t)(tid / SR_C);
+    const int lane = (int)(tid % SR_C);
+    if (i >= n || ubp[i + 1] == ubp[i]) return;
+    const int32_t src = ubp[i], dst = Crp[i], len = Crp[i + 1] - dst;
+    for (int32_t q = lane; q < len; q += SR_C) {
+        Cc[dst + q] = Tc[src + q];
+        Cv[dst + q] = Tv[src + q];
     }
 }
 
@@ -1414,33 +1463,50 @@ static void spgemm(const Csr& A, const Csr& Bm, Csr& C, int32_t* flag, hipStream
     C.m = Bm.m;
     C.rowptr.alloc(A.n + 1, s);
     DBuf<int32_t> long_rows(std::max(A.n, 1), s), nlong(1, s), vlong(std::max(A.n, 1), s), nvlong(1, s);
+    DBuf<int32_t> ubp(A.n + 1, s);
     TP_LAUNCH(k_fill_i32, 1, B, 0, s, nlong.p, 0, (int64_t)1);
+    TP_LAUNCH(k_fill_i32, 1, B, 0, s, nvlong.p, 0, (int64_t)1);
     const int grid = std::min<int>(std::max<int>(A.n, 1), 16384);
     // products per output row, estimated from the operands' mean row lengths
     // (host sizes: exact for level operators, upper bounds for P and R)
     const double est = ((double)A.nnz / std::max(A.n, 1)) * ((double)Bm.nnz / std::max(Bm.n, 1));
     const bool wide = est >= 64.0;
-    // the short kernels' sort keys hold a column in 23 bits
-    const bool keys_fit = Bm.m < (1 << 23);
-    auto short_pass = [&](int32_t* cnt, const int32_t* crp, int32_t* cc, double* cv, int numeric) {
-        if (!keys_fit) {  // every row to the long-row kernels
-            TP_LAUNCH(k_iota_i32, cdiv(A.n, B), B, 0, s, A.n, long_rows.p, nlong.p);
-        } else if (wide) {
-            TP_LAUNCH((k_spgemm_short<64, 256>), cdiv(A.n, SR_T / 64), SR_T, 0, s, A.n, A.rowptr.p, A.col.p,
-                      A.val.p, Bm.rowptr.p, Bm.col.p, Bm.val.p, cnt, crp, cc, cv, long_rows.p, nlong.p, flag,
-                      numeric);
-        } else {
-            TP_LAUNCH((k_spgemm_short<16, 128>), cdiv(A.n, SR_T / 16), SR_T, 0, s, A.n, A.rowptr.p, A.col.p,
-                      A.val.p, Bm.rowptr.p, Bm.col.p, Bm.val.p, cnt, crp, cc, cv, long_rows.p, nlong.p, flag,
-                      numeric);
-        }
-    };
+    // the short kernels' sort keys hold a column in 23 bits, and their
+    // staging offsets (at most SR_MAX a row) are 32-bit; otherwise every row
+    // takes the long-row kernels
+    const bool keys_fit =
+        Bm.m < (1 << 23) && (int64_t)A.n * (wide ? 256 : 128) < ((int64_t)1 << 31);
+    // Short rows in one pass: each writes its sorted distinct columns and
+    // values to a staging area at its product-count offset and its count to
+    // C.rowptr; the long rows are counted by the long-row kernels; once the
+    // counts are scanned, the staged rows are compacted into C and the long
+    // rows computed in place.
+    if (A.n > 0) {
+        if (!keys_fit)
+            TP_LAUNCH(k_fill_i32, cdiv(A.n, B), B, 0, s, ubp.p, 0, (int64_t)A.n);
+        else if (wide)
+            TP_LAUNCH((k_spgemm_ub<64, 256>), cdiv(A.n, B), B, 0, s, A.n, A.rowptr.p, A.col.p, Bm.rowptr.p, ubp.p);
+        else
+            TP_LAUNCH((k_spgemm_ub<16, 128>), cdiv(A.n, B), B, 0, s, A.n, A.rowptr.p, A.col.p, Bm.rowptr.p, ubp.p);
+    }
+    scan_exclusive(ubp.p, ubp.p, A.n, s);
+    const int32_t staged = read_i32(ubp.p + A.n, s);
+    DBuf<int32_t> Tc(std::max(staged, 1), s);
+    DBuf<double> Tv(std::max(staged, 1), s);
     // long rows: a workgroup per row (k_spgemm_long); rows of more than
     // LA_MAX A entries go on to the one-wavefront hash-table kernels
     const int lgrid = std::min<int>(std::max<int>(A.n, 1), 8192);
     if (A.n > 0) {
-        TP_LAUNCH(k_fill_i32, 1, B, 0, s, nvlong.p, 0, (int64_t)1);
-        short_pass(C.rowptr.p, nullptr, nullptr, nullptr, 0);
+        if (!keys_fit)  // every row to the long-row kernels
+            TP_LAUNCH(k_iota_i32, cdiv(A.n, B), B, 0, s, A.n, long_rows.p, nlong.p);
+        else if (wide)
+            TP_LAUNCH((k_spgemm_short<64, 256>), cdiv(A.n, SR_T / 64), SR_T, 0, s, A.n, A.rowptr.p, A.col.p,
+                      A.val.p, Bm.rowptr.p, Bm.col.p, Bm.val.p, C.rowptr.p, (const int32_t*)ubp.p, Tc.p, Tv.p,
+                      long_rows.p, nlong.p);
+        else
+            TP_LAUNCH((k_spgemm_short<16, 128>), cdiv(A.n, SR_T / 16), SR_T, 0, s, A.n, A.rowptr.p, A.col.p,
+                      A.val.p, Bm.rowptr.p, Bm.col.p, Bm.val.p, C.rowptr.p, (const int32_t*)ubp.p, Tc.p, Tv.p,
+                      long_rows.p, nlong.p);
         TP_LAUNCH(k_spgemm_long<false>, lgrid, LG_T, 0, s, (const int32_t*)long_rows.p, (const int32_t*)nlong.p,
                   A.rowptr.p, A.col.p, A.val.p, Bm.rowptr.p, Bm.col.p, Bm.val.p, C.rowptr.p, (const int32_t*)nullptr,
                   (int32_t*)nullptr, (double*)nullptr, vlong.p, nvlong.p, flag);
@@ -1454,10 +1520,10 @@ static void spgemm(const Csr& A, const Csr& Bm, Csr& C, int32_t* flag, hipStream
     C.col.alloc(C.nnz, s);
     C.val.alloc(C.nnz, s);
     if (A.n > 0) {
-        // the passes list the long rows again: start the lists afresh
-        TP_LAUNCH(k_fill_i32, 1, B, 0, s, nlong.p, 0, (int64_t)1);
+        TP_LAUNCH(k_spgemm_compact, cdiv((int64_t)A.n * SR_C, B), B, 0, s, A.n, (const int32_t*)ubp.p,
+                  (const int32_t*)Tc.p, (const double*)Tv.p, (const int32_t*)C.rowptr.p, C.col.p, C.val.p);
+        // the long-row pass lists the longest rows again: start that list afresh
         TP_LAUNCH(k_fill_i32, 1, B, 0, s, nvlong.p, 0, (int64_t)1);
-        short_pass(nullptr, C.rowptr.p, C.col.p, C.val.p, 1);
         TP_LAUNCH(k_spgemm_long<true>, lgrid, LG_T, 0, s, (const int32_t*)long_rows.p, (const int32_t*)nlong.p,
                   A.rowptr.p, A.col.p, A.val.p, Bm.rowptr.p, Bm.col.p, Bm.val.p, (int32_t*)nullptr,
                   (const int32_t*)C.rowptr.p, C.col.p, C.val.p, vlong.p, nvlong.p, flag);
