@@ -141,6 +141,17 @@ k_sort_rows(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __rest
 // equal the thread-per-row kernels' bit for bit.
 constexpr int WR = 64;
 constexpr int WR_ROWS = B / WR;
+
+// Lane l's value broadcast to the wavefront, l uniform (v_readlane: no
+// LDS round trip, unlike a shuffle -- the row sums below broadcast their
+// terms one by one)
+__device__ inline int32_t bcast_i(int32_t v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ inline double bcast_d(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)b, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 constexpr double WR_MIN_AVG = 10.0;  // mean row length from which a level uses them
 
 __device__ inline int below_count(uint64_t mask, int lane) {
@@ -155,7 +166,7 @@ __device__ inline void row_sign_max_w(const int32_t* rowptr, const int32_t* col,
     for (int32_t q = a + lane; q < e; q += WR)
         if (col[q] == i) { aii = val[q]; has = true; }
     const uint64_t hm = __ballot(has);
-    aii = hm ? __shfl(aii, __ffsll((unsigned long long)hm) - 1, WR) : 0.0;
+    aii = hm ? bcast_d(aii, __ffsll((unsigned long long)hm) - 1) : 0.0;
     const double s = aii < 0.0 ? -1.0 : 1.0;
     double m = 0.0;
     for (int32_t q = a + lane; q < e; q += WR)
@@ -234,7 +245,7 @@ k_interp_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __
     for (int32_t q = a + lane; q < e; q += WR)
         if (col[q] == i) { aii = val[q]; has = true; }
     const uint64_t hm = __ballot(has);
-    aii = hm ? __shfl(aii, __ffsll((unsigned long long)hm) - 1, WR) : 0.0;
+    aii = hm ? bcast_d(aii, __ffsll((unsigned long long)hm) - 1) : 0.0;
     const double s = aii < 0.0 ? -1.0 : 1.0;
     // the three sums in row order, exactly as one thread would take them
     double sum_all = 0.0, lump = 0.0, sum_p = 0.0;
@@ -247,8 +258,8 @@ k_interp_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __
         const uint64_t scm = __ballot(sc);
         const int len = min(WR, (int)(e - b));
         for (int l = 0; l < len; ++l) {
-            const int32_t jl = __shfl(j, l, WR);
-            const double vl = __shfl(v, l, WR);
+            const int32_t jl = bcast_i(j, l);
+            const double vl = bcast_d(v, l);
             if (jl != i) {
                 if (s * vl < 0.0) sum_all += vl;
                 else lump += vl;
@@ -730,7 +741,7 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
     for (int32_t q = a + lane; q < e; q += WR)
         if (col[q] == i) { aii = val[q]; has = true; }
     const uint64_t hm = __ballot(has);
-    aii = hm ? __shfl(aii, __ffsll((unsigned long long)hm) - 1, WR) : 0.0;
+    aii = hm ? bcast_d(aii, __ffsll((unsigned long long)hm) - 1) : 0.0;
     double at = aii;
     // weak couplings outside the set, lumped in row order
     for (int32_t b = a; b < e; b += WR) {
@@ -742,7 +753,7 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
         const uint64_t lm = __ballot(lump);
         const int cnt = min(WR, (int)(e - b));
         for (int l = 0; l < cnt; ++l) {
-            const double vl = __shfl(v, l, WR);
+            const double vl = bcast_d(v, l);
             if ((lm >> l) & 1ull) at += vl;
         }
     }
@@ -754,13 +765,16 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
         const bool ok = q < e;
         const int32_t k0 = ok ? col[q] : i;
         const bool sf = ok && k0 != i && !cf[k0] && find_sorted(Si, slen, k0) >= 0;
+        // every strong F neighbour's row extent and a_ik, loaded at once
+        const int32_t kb0 = sf ? rowptr[k0] : 0, ke0 = sf ? rowptr[k0 + 1] : 0;
+        const double aik0 = sf ? val[q] : 0.0;
         uint64_t m = __ballot(sf);
         while (m) {
             const int l = __ffsll((unsigned long long)m) - 1;
             m &= m - 1;
-            const int32_t k = __shfl(k0, l, WR);
-            const double aik = __shfl(ok ? val[q] : 0.0, l, WR);
-            const int32_t kb = rowptr[k], ke = rowptr[k + 1];
+            const int32_t k = bcast_i(k0, l);
+            const double aik = bcast_d(aik0, l);
+            const int32_t kb = bcast_i(kb0, l), ke = bcast_i(ke0, l);
             // row k in LDS (one coalesced load; the searches below then stay
             // on chip) when it fits, else read in place
             const bool kst = ke - kb <= EXT_KROW;
@@ -785,7 +799,7 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
             for (int32_t u = lane; u < kl; u += WR)
                 if (kc[u] == k) { akk = kv[u]; hk = true; }
             const uint64_t km = __ballot(hk);
-            akk = km ? __shfl(akk, __ffsll((unsigned long long)km) - 1, WR) : 0.0;
+            akk = km ? bcast_d(akk, __ffsll((unsigned long long)km) - 1) : 0.0;
             double den = 0.0;
             for (int32_t c0 = 0; c0 < kl; c0 += WR) {
                 const int32_t u = c0 + lane;
@@ -796,7 +810,7 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
                 const uint64_t mm = __ballot(mem);
                 const int cnt = min(WR, (int)(kl - c0));
                 for (int tt = 0; tt < cnt; ++tt) {
-                    const double ht = __shfl(h, tt, WR);
+                    const double ht = bcast_d(h, tt);
                     if ((mm >> tt) & 1ull) den += ht;
                 }
             }
@@ -858,8 +872,8 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
     for (int r = 0; r < EXT_NW; ++r) {
         const int cnt = min(WR, (int)(len - r * WR));
         for (int l = 0; l < cnt; ++l) {
-            const double v = __shfl(w[r], l, WR);
-            const bool k = (__shfl((int)selm, l, WR) >> r) & 1;
+            const double v = bcast_d(w[r], l);
+            const bool k = (bcast_i((int)selm, l) >> r) & 1;
             all += v;
             if (k) kept += v;
         }
@@ -1369,17 +1383,19 @@ k_spgemm_short(int32_t n, const int32_t* __restrict__ Arp, const int32_t* __rest
         s_k[g][e] = ((uint32_t)Bc[src] << SHIFT) | (uint32_t)e;
         s_v[g][e] = s_av[g][lo] * Bv[src];
     }
-    // bitonic sort of the np keys, ascending
-    for (int size = 2; size <= np; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+    // bitonic sort of the np keys, ascending: stage (size 2^ls, stride 2^lt)
+    // compares the pairs (lo, lo + stride), lo = pair index pi with a zero
+    // bit inserted at position lt
+    for (int ls = 1; (1 << ls) <= np; ++ls) {
+        for (int lt = ls - 1; lt >= 0; --lt) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             for (int pi = lane; pi < np / 2; pi += SR_G) {
-                const int lo = 2 * stride * (pi / stride) + (pi % stride);
-                const int hi = lo + stride;
+                const int lo = ((pi >> lt) << (lt + 1)) | (pi & ((1 << lt) - 1));
+                const int hi = lo + (1 << lt);
                 const uint32_t x = s_k[g][lo], y = s_k[g][hi];
-                const bool up = (lo & size) == 0;
+                const bool up = (lo & (1 << ls)) == 0;
                 if ((x > y) == up) {
                     s_k[g][lo] = y;
                     s_k[g][hi] = x;
@@ -1476,13 +1492,14 @@ static void spgemm(const Csr& A, const Csr& Bm, Csr& C, int32_t* flag, hipStream
     // takes the long-row kernels
     const bool keys_fit =
         Bm.m < (1 << 23) && (int64_t)A.n * (wide ? 256 : 128) < ((int64_t)1 << 31);
+    const bool all_long = !keys_fit;
     // Short rows in one pass: each writes its sorted distinct columns and
     // values to a staging area at its product-count offset and its count to
     // C.rowptr; the long rows are counted by the long-row kernels; once the
     // counts are scanned, the staged rows are compacted into C and the long
     // rows computed in place.
     if (A.n > 0) {
-        if (!keys_fit)
+        if (all_long)
             TP_LAUNCH(k_fill_i32, cdiv(A.n, B), B, 0, s, ubp.p, 0, (int64_t)A.n);
         else if (wide)
             TP_LAUNCH((k_spgemm_ub<64, 256>), cdiv(A.n, B), B, 0, s, A.n, A.rowptr.p, A.col.p, Bm.rowptr.p, ubp.p);
@@ -1497,7 +1514,7 @@ static void spgemm(const Csr& A, const Csr& Bm, Csr& C, int32_t* flag, hipStream
     // LA_MAX A entries go on to the one-wavefront hash-table kernels
     const int lgrid = std::min<int>(std::max<int>(A.n, 1), 8192);
     if (A.n > 0) {
-        if (!keys_fit)  // every row to the long-row kernels
+        if (all_long)  // every row to the long-row kernels
             TP_LAUNCH(k_iota_i32, cdiv(A.n, B), B, 0, s, A.n, long_rows.p, nlong.p);
         else if (wide)
             TP_LAUNCH((k_spgemm_short<64, 256>), cdiv(A.n, SR_T / 64), SR_T, 0, s, A.n, A.rowptr.p, A.col.p,
