@@ -703,10 +703,14 @@ static typename M::T* vcycle_level(tp_amg* h, int l, const typename M::T* b, hip
     const tp_amg_params& p = h->prm;
     T* cur = x;
     T* r = (T*)L.r.p;
-    // a pre-smoothing that is a single step from zero on a CSR level (the
-    // coarse levels of the degree-1 schedule) runs fused with the residual
+    // a pre-smoothing that is a single step from zero on a small CSR level
+    // (the coarse levels of the degree-1 schedule) runs fused with the
+    // residual: one launch fewer.  On levels of >= 65536 rows the two passes
+    // are cheaper than the fused one, which gathers D^{-1} and b at every
+    // neighbour instead of x (first coarse level of the 256x256x64 pressure
+    // hierarchy: 186 us fused against ~145 us for the pair).
     const int deg = (l > 0 && p.cheb_degree_coarse > 0) ? p.cheb_degree_coarse : p.cheb_degree;
-    if (p.nu_pre == 1 && !L.ndia && (p.smoother == 0 || deg == 1)) {
+    if (p.nu_pre == 1 && !L.ndia && (p.smoother == 0 || deg == 1) && n < 65536) {
         const double theta = 0.5 * (1.0 + p.cheb_lo);
         TP_G_DISPATCH(L.gA, TP_LAUNCH((k_smooth0_res<T, V, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p,
                                       L.A.col.p, LevelVals<M>::A(L), LevelVals<M>::diag(L), LevelVals<M>::dinv(L),

@@ -619,17 +619,18 @@ def _compare_hierarchies(hg, ho, tag):
         say(f"  {tag} level {l}: n={Lo['n']} format {hg.level_format(l)} matches")
 
 
-def test_full_size_w2_end_to_end():
-    """The 64x64x32 layered workload (262,144 unknowns) at full size against
-    the oracle.  (1) GPU assembly: G and all five Jacobian blocks within
-    1e-12.  (2) Both hierarchies built from the oracle's Jacobian: every
-    level's C/F split and patterns bit-exact, values within 1e-13.  (3) The
-    solve to rtol 1e-8 from the same Jacobian: iteration count +-1, residual
-    estimates within 1e-8 relative over the first ten iterations, solutions
-    within 1e-8 per block.  (4) The solve from the GPU-assembled Jacobian
-    converges to 1e-8 in the same count."""
-    say("full W2")
-    p = synth.make_problem("W2")
+@pytest.mark.parametrize("case", ["W2", "W3"])
+def test_full_size_end_to_end(case):
+    """The 64x64x32 and 128x128x64 layered workloads (262,144 and 2,097,152
+    unknowns) at full size against the oracle.  (1) GPU assembly: G and all
+    five Jacobian blocks within 1e-12.  (2) Both hierarchies built from the
+    oracle's Jacobian: every level's C/F split and patterns bit-exact, values
+    within 1e-13.  (3) The solve to rtol 1e-8 from the same Jacobian:
+    iteration count +-1, residual estimates within 1e-8 relative over the
+    first ten iterations, solutions within 1e-8 per block.  (4) The solve
+    from the GPU-assembled Jacobian converges to 1e-8 in the same count."""
+    say("full", case)
+    p = synth.make_problem(case)
     d = solver.to_device(p)
     J, G = solver.assemble(p, d)
     Jo = oracle.jacobian(p)
