@@ -22,6 +22,10 @@ struct Level {
     DBuf<uint16_t> A16, dia16;
     DBuf<float> diag32;
     int gA = 1, gP = 1, gR = 1;
+    // Row-block (stream) form of A's row products on large CSR levels: blocks
+    // of sb_rows consecutive rows whose products are staged in LDS (at most
+    // sb_lds of them per block); sb_rows = 0 when the level does not use it.
+    int sb_rows = 0, sb_lds = 0;
     // Diagonal (DIA) copy of A when its column offsets form a small set
     // (stencil levels): dia[d * n + i] = a(i, i + off[d]), zero outside.
     int ndia = 0;

@@ -41,12 +41,13 @@ int lanes_for(int32_t n, int64_t nnz) {
     if (n >= 65536) avg /= 2.0;
     int g = 1;
     while (g < avg && g < 64) g <<= 1;
-    // Large levels take at most 8 lanes a row: more rows per wavefront keep
-    // more independent loads in flight, and the dependent index -> value
-    // gathers of a short row are latency-bound (8 lanes measured fastest on
-    // the first coarse levels of the 256x256x64 hierarchies, 18-44 entries a
-    // row: 16 lanes cost 6% more time per preconditioner apply, 32 lanes 17%).
-    if (n >= 65536 && g > 8) g = 8;
+    // Large levels take at most 8 lanes a row (16 for rows of more than 32
+    // entries): more rows per wavefront keep more independent loads in
+    // flight.  Measured on the 256x256x64 hierarchies' first coarse levels
+    // (18-29 entries a row): 8 lanes fastest, 16 lanes +4% time per
+    // preconditioner apply, 32 lanes +13%, 4 lanes +2%; on the second
+    // levels (46-60 entries) 16 lanes are 1% faster than 8.
+    if (n >= 65536 && g > 8) g = avg > 16.0 ? 16 : 8;
     return g;
 }
 
@@ -2251,6 +2252,40 @@ k_dia_check(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __rest
 }
 
 // DIA copy of a stencil level: one device probe and check, one host read.
+// most entries in any block of rb consecutive rows
+__global__ void __launch_bounds__(B)
+k_block_nnz_max(int32_t n, const int32_t* __restrict__ rowptr, int32_t rb, int32_t* __restrict__ out) {
+    const int32_t b = blockIdx.x * B + threadIdx.x;
+    const int64_t r0 = (int64_t)b * rb;
+    if (r0 >= n) return;
+    const int32_t r1 = r0 + rb < n ? (int32_t)(r0 + rb) : n;
+    atomicMax(out, rowptr[r1] - rowptr[r0]);
+}
+
+// Row-block form of a large CSR level (n >= 65536): 64-row blocks (32 when
+// those would hold more products than the LDS budget) whose products fit in
+// 48 KB of LDS; else the level keeps the lane-group kernels.  Measured on the
+// 256x256x64 hierarchies (18-60 entries a row), time per preconditioner
+// apply against the lane-group kernels: 64 rows -2.0% (FP32) / -1.4%
+// (FP64), 32 rows -1.2% / -1.5%, 128 rows -1.6% / 0, 256 rows +1.8% / +0.2%.
+static void try_stream(tp_amg* h, Level& L, hipStream_t s) {
+    const int32_t n = L.A.n;
+    L.sb_rows = L.sb_lds = 0;
+    if (L.ndia || n < 65536) return;
+    const int32_t cap = (int32_t)(48 * 1024 / storage_bytes(h));
+    DBuf<int32_t> mx(1, s);
+    for (int32_t rb : {64, 32}) {
+        TP_LAUNCH(k_fill_i32, 1, B, 0, s, mx.p, 0, (int64_t)1);
+        TP_LAUNCH(k_block_nnz_max, cdiv(cdiv(n, rb), B), B, 0, s, n, L.A.rowptr.p, rb, mx.p);
+        const int32_t m = read_i32(mx.p, s);
+        if (m <= cap) {
+            L.sb_rows = rb;
+            L.sb_lds = std::max(m, 1);
+            return;
+        }
+    }
+}
+
 static void try_dia(tp_amg* h, Level& L, hipStream_t s) {
     const int32_t n = L.A.n;
     if (n < 1024 || L.A.nnz > 8LL * n) return;
@@ -2293,7 +2328,10 @@ static void alloc_work(tp_amg* h, hipStream_t s) {
         L.gA = lanes_for(L.A.n, L.A.nnz);
         L.gP = lanes_for(L.P.n, L.P.nnz);
         L.gR = lanes_for(L.R.n, L.R.nnz);
-        if (&L != &h->lev.back()) try_dia(h, L, s);
+        if (&L != &h->lev.back()) {
+            try_dia(h, L, s);
+            try_stream(h, L, s);
+        }
         if (h->prm.storage >= 1) {
             if (h->prm.storage == 1) {
                 make_f32(L.A32, L.A.val, L.A.nnz, s);

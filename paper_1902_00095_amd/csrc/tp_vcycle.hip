@@ -433,6 +433,59 @@ k_smooth0_res(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restri
     }
 }
 
+// Row-block (stream) form of the row products on a large CSR level: the
+// workgroup takes rows [r0, r0 + rb); its threads stream the block's entries
+// (consecutive threads, consecutive entries: every index and value load is
+// coalesced across the wavefront) and put the products a_ij x_j in LDS;
+// then thread t sums row r0 + t's products in entry order.  (The lane-group
+// kernels read each row's entries through a group of lanes, so a wavefront's
+// load touches a cache line per row it serves.)  MODE 0: a Chebyshev step
+// as k_cheb_step; MODE 1: the residual r = b - A x as k_residual.
+template <typename T, typename V, int MODE>
+__global__ void __launch_bounds__(VB)
+k_rows_stream(int32_t n, int32_t rb, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+              const V* __restrict__ av, const T* __restrict__ diag, const T* __restrict__ dinv,
+              const T* __restrict__ b, const T* __restrict__ xin, T* __restrict__ xout, T* __restrict__ d,
+              int first, T theta, T c1, T c2) {
+    extern __shared__ double s_raw[];  // (typed double for its alignment)
+    T* const prod = reinterpret_cast<T*>(s_raw);
+    const int32_t r0 = blockIdx.x * rb;
+    const int32_t r1 = r0 + rb < n ? r0 + rb : n;
+    const int32_t base = rp[r0], end = rp[r1];
+    // four entries a thread before any product is formed: their loads are in
+    // flight together
+    for (int32_t e0 = base + threadIdx.x; e0 < end; e0 += 4 * VB) {
+        int32_t cc[4];
+        T aa[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int32_t e = e0 + u * VB;
+            cc[u] = e < end ? ci[e] : 0;
+            aa[u] = e < end ? (T)av[e] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int32_t e = e0 + u * VB;
+            if (e < end) prod[e - base] = aa[u] * xin[cc[u]];
+        }
+    }
+    __syncthreads();
+    const int32_t i = r0 + (int32_t)threadIdx.x;
+    if ((int32_t)threadIdx.x >= rb || i >= r1) return;
+    T s = 0;
+    for (int32_t q = rp[i] - base, qe = rp[i + 1] - base; q < qe; ++q) s += prod[q];
+    const T bi = b[i], xi = xin[i];
+    if (diag) s += diag[i] * xi;
+    if (MODE == 1) {
+        xout[i] = bi - s;
+        return;
+    }
+    const T r = dinv[i] * (bi - s);
+    const T dn = first ? r / theta : c1 * d[i] + c2 * r;
+    d[i] = dn;
+    xout[i] = xi + dn;
+}
+
 // first sweep from a zero guess
 template <typename T>
 __global__ void __launch_bounds__(VB)
@@ -676,6 +729,10 @@ static typename M::T* smooth(tp_amg* h, int l, const typename M::T* b, typename 
             if (L.ndia) {
                 dia_cheb_step<T, V>(L, n, LevelVals<M>::D(L), dg, dv, b, cur, nx, d, first, (T)theta, (T)c1, (T)c2,
                                     s, timed, bytes);
+            } else if (L.sb_rows) {
+                TP_LAUNCH((k_rows_stream<T, V, 0>), cdiv(n, L.sb_rows), VB, (size_t)L.sb_lds * sizeof(T), s, n,
+                          L.sb_rows, L.A.rowptr.p, L.A.col.p, av, dg, dv, b, cur, nx, d, first, (T)theta, (T)c1,
+                          (T)c2);
             } else {
                 TP_G_DISPATCH(L.gA, TP_LAUNCH_TIMED(timed, bytes, (k_cheb_step<T, V, GG>), grid_rows(n, GG), VB, 0, s,
                                                     n, L.A.rowptr.p, L.A.col.p, av, dg, dv, b, cur, nx, d, first,
@@ -723,6 +780,10 @@ static typename M::T* vcycle_level(tp_amg* h, int l, const typename M::T* b, hip
         // every coarse row that holds it and serialises its gathers)
         if (L.ndia) {
             dia_residual<T, V>(L, n, LevelVals<M>::D(L), LevelVals<M>::diag(L), b, cur, r, s);
+        } else if (L.sb_rows) {
+            TP_LAUNCH((k_rows_stream<T, V, 1>), cdiv(n, L.sb_rows), VB, (size_t)L.sb_lds * sizeof(T), s, n,
+                      L.sb_rows, L.A.rowptr.p, L.A.col.p, LevelVals<M>::A(L), LevelVals<M>::diag(L),
+                      (const T*)nullptr, b, cur, r, (T*)nullptr, 0, (T)0, (T)0, (T)0);
         } else {
             TP_G_DISPATCH(L.gA, TP_LAUNCH((k_residual<T, V, GG>), grid_rows(n, GG), VB, 0, s, n, L.A.rowptr.p,
                                           L.A.col.p, LevelVals<M>::A(L), LevelVals<M>::diag(L), b, cur, r));
