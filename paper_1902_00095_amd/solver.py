@@ -9,6 +9,7 @@ dominant); the pressure hierarchy the Galerkin one.
 from __future__ import annotations
 
 import dataclasses
+import math
 
 from . import tpsolve as tps
 
@@ -232,14 +233,19 @@ class LearnedGuard:
     iteration (t_p until one has been timed): the rate at which it reaches
     the plain solve's residual in the plain solve's time, so the network is
     switched off as soon as it falls behind the plain form in time, not
-    only when it stagnates.  After the network has been switched off in two
-    learned solves in a row, the rest of the run is plain."""
+    only when it stagnates.  A learned solve that ran to the end without
+    being switched off is still behind when its time per decade of
+    residual reduction, FGMRES time / -log10(rel_true), exceeds the last
+    plain solve's (short solves end before the per-iteration check can
+    act).  After two learned solves in a row that were behind (switched off
+    or slower per decade), the rest of the run is plain."""
 
     def __init__(self):
         self.rho_p = self.t_p = self.t_l = None
+        self.tau_p = None   # plain solve's FGMRES seconds per decade
         self.streak = 0
         self.off = False
-        self.learned_solves = self.plain_solves = self.switched_off = 0
+        self.learned_solves = self.plain_solves = self.switched_off = self.slower = 0
 
     def use_net(self):
         return self.rho_p is not None and not self.off
@@ -247,6 +253,11 @@ class LearnedGuard:
     def ref_rate(self):
         c = self.t_l / self.t_p if (self.t_l and self.t_p) else 1.0
         return min(self.rho_p ** c, 0.999)
+
+    @staticmethod
+    def _per_decade(st, fgmres_s):
+        d = -math.log10(st["rel_true"]) if st["rel_true"] > 0.0 else 0.0
+        return fgmres_s / d if d > 0.0 else math.inf
 
     def record(self, st, fgmres_s, learned):
         its = max(st["iters"], 1)
@@ -256,19 +267,25 @@ class LearnedGuard:
             if st["converged"] and st["rel_true"] > 0.0:
                 self.rho_p = st["rel_true"] ** (1.0 / its)
                 self.t_p = per_it
+                self.tau_p = self._per_decade(st, fgmres_s)
             return
         self.learned_solves += 1
+        behind = False
         if st["fallback_iter"] >= 0:
             self.switched_off += 1
-            self.streak += 1
-            self.off = self.streak >= 2
+            behind = True
         else:
-            self.streak = 0
             self.t_l = per_it
+            if self.tau_p is not None and self._per_decade(st, fgmres_s) > self.tau_p:
+                self.slower += 1
+                behind = True
+        self.streak = self.streak + 1 if behind else 0
+        self.off = self.off or self.streak >= 2
 
     def stats(self):
         return dict(learned_solves=self.learned_solves, plain_solves=self.plain_solves,
-                    network_switched_off=self.switched_off, network_off_for_rest=self.off)
+                    network_switched_off=self.switched_off, slower_per_decade=self.slower,
+                    network_off_for_rest=self.off)
 
 
 def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None, on_solve=None):
