@@ -1070,8 +1070,8 @@ k_iota_i32(int32_t n, int32_t* __restrict__ list, int32_t* __restrict__ count) {
 // LA_MAX A entries are listed for them.
 constexpr int LG_T = 256;
 constexpr int LG_W = LG_T / 64;
-constexpr int LG_M = 3072;
-constexpr int LA_MAX = 512;
+constexpr int LG_M = 2048;
+constexpr int LA_MAX = 128;
 
 // exclusive prefix of v over the workgroup (thread order) and the total
 __device__ inline int32_t block_exscan(int32_t v, int32_t* s_wave, int32_t* total) {
