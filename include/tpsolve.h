@@ -205,7 +205,10 @@ int amg_refresh_fine(tp_amg_t amg, const double* val, void* stream);
  * All values are recomputed from `val` in the setup's order: direct
  * interpolation weights restricted to the kept interpolation sets (only
  * couplings of the sign opposite to the diagonal interpolate; a kept entry
- * that no longer does holds an explicit zero), R = P^T or its
+ * that no longer does holds an explicit zero), or, for extended+i
+ * interpolation (interp 1), the extended+i weights over each row's
+ * interpolatory set taken from the kept strength pattern, a row truncated at
+ * setup keeping its kept columns scaled to the full row sum; R = P^T or its
  * Petrov-Galerkin counterpart on the kept pattern, the Galerkin products
  * R (A P) on their kept patterns (each entry summed in ascending inner
  * index), the l1 diagonals, stencil-diagonal and reduced-precision copies,
@@ -213,10 +216,9 @@ int amg_refresh_fine(tp_amg_t amg, const double* val, void* stream);
  * When the kept splits and patterns are the ones a fresh amg_setup would
  * choose for `val`, the hierarchy equals that fresh setup bit for bit.
  * Everything is rewritten in place: preconditioner handles and their
- * captured graphs stay valid.  Direct interpolation only (interp 0: else
- * TP_ERR_ARG); not for hierarchies from amg_setup_schur_diag.  Errors:
- * TP_ERR_ARG (null, interp), TP_ERR_NUMERIC (zero pivot in the coarsest
- * inverse).  Synchronises `stream`. */
+ * captured graphs stay valid.  Not for hierarchies from
+ * amg_setup_schur_diag.  Errors: TP_ERR_ARG (null), TP_ERR_NUMERIC (zero
+ * pivot in the coarsest inverse).  Synchronises `stream`. */
 int amg_refresh(tp_amg_t amg, const double* val, void* stream);
 
 int amg_num_levels(tp_amg_t amg, int32_t* nlev);

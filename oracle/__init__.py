@@ -380,9 +380,9 @@ class AMG:
         return n.value
 
     def refresh(self, val):
-        """New level-0 values on the same pattern: C/F splits and every
-        sparsity pattern kept, values recomputed (or_amg_refresh).  Returns
-        the status (0, -1 extended+i, -4 zero pivot)."""
+        """New level-0 values on the same pattern: C/F splits, strength
+        patterns and every sparsity pattern kept, values recomputed
+        (or_amg_refresh).  Returns the status (0, -4 zero pivot)."""
         self._val = _f64(val).copy()
         return int(lib().or_amg_refresh(self.h, _p(self._val)))
 

@@ -43,6 +43,9 @@ struct or_amg {
     or_amg_params prm;
     int32_t nlev;
     csr_t A[OR_MAXLEV], P[OR_MAXLEV], R[OR_MAXLEV];
+    /* extended+i: the strength patterns of A_l (and of A_l^T when R = Q^T),
+     * kept for the numeric refresh */
+    csr_t S[OR_MAXLEV], Sq[OR_MAXLEV];
     double* dinv[OR_MAXLEV];
     int32_t* cf[OR_MAXLEV];
     int32_t nc;
@@ -295,6 +298,62 @@ static int32_t ext_set(const csr_t* S, const int32_t* cf, int32_t i, int32_t* ma
  * f = (sum of all its weights) / (sum of the kept ones), both sums in
  * ascending column order (no scaling when the kept sum is 0): the row sum
  * is preserved. */
+
+/* the weights w[0..len) of F row i over its set list[0..len) */
+static void ext_weights(const csr_t* A, const csr_t* S, const int32_t* cf, int32_t i,
+                        const int32_t* list, int32_t len, double* w)
+{
+    const int32_t* Si = S->col + S->rowptr[i];
+    int32_t slen = S->rowptr[i + 1] - S->rowptr[i];
+    double aii = 0.0;
+    for (int32_t t = A->rowptr[i]; t < A->rowptr[i + 1]; ++t)
+        if (A->col[t] == i) aii = A->val[t];
+    for (int32_t s = 0; s < len; ++s) w[s] = 0.0;
+    double at = aii;
+    /* the row's own couplings: interpolatory ones to w, weak others lumped */
+    for (int32_t t = A->rowptr[i]; t < A->rowptr[i + 1]; ++t) {
+        int32_t j = A->col[t];
+        if (j == i) continue;
+        int32_t pos = in_sorted(list, len, j);
+        if (pos >= 0) w[pos] += A->val[t];
+        else if (in_sorted(Si, slen, j) < 0) at += A->val[t];
+    }
+    /* strong F neighbours, distributed over C^_i and i */
+    for (int32_t t = A->rowptr[i]; t < A->rowptr[i + 1]; ++t) {
+        int32_t k = A->col[t];
+        if (k == i || cf[k] || in_sorted(Si, slen, k) < 0) continue;
+        double aik = A->val[t], akk = 0.0, den = 0.0;
+        for (int32_t u = A->rowptr[k]; u < A->rowptr[k + 1]; ++u)
+            if (A->col[u] == k) akk = A->val[u];
+        for (int32_t u = A->rowptr[k]; u < A->rowptr[k + 1]; ++u) {
+            int32_t l = A->col[u];
+            if (l == i || in_sorted(list, len, l) >= 0) den += opp(A->val[u], akk);
+        }
+        if (den == 0.0) { at += aik; continue; }
+        for (int32_t u = A->rowptr[k]; u < A->rowptr[k + 1]; ++u) {
+            int32_t l = A->col[u];
+            double c = (aik * opp(A->val[u], akk)) / den;
+            int32_t pos = in_sorted(list, len, l);
+            if (pos >= 0) w[pos] += c;
+            else if (l == i) at += c;
+        }
+    }
+    for (int32_t s = 0; s < len; ++s) w[s] = -w[s] / at;
+}
+
+/* the kept weights of a truncated row, scaled to the full row sum, written
+ * in ascending column order to val (keep[s] marks the kept slots) */
+static void ext_scale_kept(const double* w, const char* keep, int32_t len, double* val)
+{
+    double all = 0.0, kept = 0.0;
+    for (int32_t s = 0; s < len; ++s) all += w[s];
+    for (int32_t s = 0; s < len; ++s) if (keep[s]) kept += w[s];
+    double f = kept != 0.0 ? all / kept : 1.0;
+    int32_t q = 0;
+    for (int32_t s = 0; s < len; ++s)
+        if (keep[s]) val[q++] = kept != 0.0 ? w[s] * f : w[s];
+}
+
 static void ext_interp(const csr_t* A, const csr_t* S, const int32_t* cf,
                        const int32_t* cmap, int32_t nc, int32_t pmax, csr_t* P)
 {
@@ -317,42 +376,7 @@ static void ext_interp(const csr_t* A, const csr_t* S, const int32_t* cf,
         if (cf[i]) { P->col[q] = cmap[i]; P->val[q] = 1.0; ++q; continue; }
         int32_t len = ext_set(S, cf, i, mark, list);
         if (len == 0) continue;
-        const int32_t* Si = S->col + S->rowptr[i];
-        int32_t slen = S->rowptr[i + 1] - S->rowptr[i];
-        double aii = 0.0;
-        for (int32_t t = A->rowptr[i]; t < A->rowptr[i + 1]; ++t)
-            if (A->col[t] == i) aii = A->val[t];
-        for (int32_t s = 0; s < len; ++s) w[s] = 0.0;
-        double at = aii;
-        /* the row's own couplings: interpolatory ones to w, weak others lumped */
-        for (int32_t t = A->rowptr[i]; t < A->rowptr[i + 1]; ++t) {
-            int32_t j = A->col[t];
-            if (j == i) continue;
-            int32_t pos = in_sorted(list, len, j);
-            if (pos >= 0) w[pos] += A->val[t];
-            else if (in_sorted(Si, slen, j) < 0) at += A->val[t];
-        }
-        /* strong F neighbours, distributed over C^_i and i */
-        for (int32_t t = A->rowptr[i]; t < A->rowptr[i + 1]; ++t) {
-            int32_t k = A->col[t];
-            if (k == i || cf[k] || in_sorted(Si, slen, k) < 0) continue;
-            double aik = A->val[t], akk = 0.0, den = 0.0;
-            for (int32_t u = A->rowptr[k]; u < A->rowptr[k + 1]; ++u)
-                if (A->col[u] == k) akk = A->val[u];
-            for (int32_t u = A->rowptr[k]; u < A->rowptr[k + 1]; ++u) {
-                int32_t l = A->col[u];
-                if (l == i || in_sorted(list, len, l) >= 0) den += opp(A->val[u], akk);
-            }
-            if (den == 0.0) { at += aik; continue; }
-            for (int32_t u = A->rowptr[k]; u < A->rowptr[k + 1]; ++u) {
-                int32_t l = A->col[u];
-                double c = (aik * opp(A->val[u], akk)) / den;
-                int32_t pos = in_sorted(list, len, l);
-                if (pos >= 0) w[pos] += c;
-                else if (l == i) at += c;
-            }
-        }
-        for (int32_t s = 0; s < len; ++s) w[s] = -w[s] / at;
+        ext_weights(A, S, cf, i, list, len, w);
         if (pmax > 0 && len > pmax) {
             for (int32_t s = 0; s < len; ++s) keep[s] = 0;
             for (int32_t r = 0; r < pmax; ++r) {
@@ -361,16 +385,9 @@ static void ext_interp(const csr_t* A, const csr_t* S, const int32_t* cf,
                     if (!keep[s] && (best < 0 || fabs(w[s]) > fabs(w[best]))) best = s;
                 keep[best] = 1;
             }
-            double all = 0.0, kept = 0.0;
-            for (int32_t s = 0; s < len; ++s) all += w[s];
-            for (int32_t s = 0; s < len; ++s) if (keep[s]) kept += w[s];
-            double f = kept != 0.0 ? all / kept : 1.0;
             for (int32_t s = 0; s < len; ++s)
-                if (keep[s]) {
-                    P->col[q] = cmap[list[s]];
-                    P->val[q] = kept != 0.0 ? w[s] * f : w[s];
-                    ++q;
-                }
+                if (keep[s]) P->col[q++] = cmap[list[s]];
+            ext_scale_kept(w, keep, len, P->val + q - pmax);
         } else {
             for (int32_t s = 0; s < len; ++s) {
                 P->col[q] = cmap[list[s]];
@@ -381,6 +398,38 @@ static void ext_interp(const csr_t* A, const csr_t* S, const int32_t* cf,
     }
     P->rowptr[n] = q;
     P->nnz = q;
+    free(mark); free(list); free(w); free(keep);
+}
+
+/* Extended+i interpolation on a frozen hierarchy: the strength pattern S,
+ * the split and P's pattern (the kept set of each row) are those of the
+ * setup; the weights of each F row are formed over its full interpolatory
+ * set C^_i (from the frozen S and split) as in ext_interp, from the new
+ * values, and a row that the setup truncated keeps its frozen columns,
+ * scaled to the full row sum as in ext_interp.  When S, the split and the
+ * kept sets are those that a fresh setup on the new values would choose,
+ * this is exactly that setup's interpolation. */
+static void ext_refresh(const csr_t* A, const csr_t* S, const int32_t* cf, const int32_t* cmap, csr_t* P)
+{
+    int32_t n = A->n;
+    int32_t* mark = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t* list = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    double* w = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    char* keep = malloc((size_t)(n > 0 ? n : 1));
+    for (int32_t j = 0; j < n; ++j) mark[j] = -1;
+    for (int32_t i = 0; i < n; ++i) {
+        if (cf[i]) continue;                       /* C row: the unit vector, kept */
+        int32_t len = ext_set(S, cf, i, mark, list);
+        if (len == 0) continue;
+        const int32_t pa = P->rowptr[i], plen = P->rowptr[i + 1] - pa;
+        ext_weights(A, S, cf, i, list, len, w);
+        if (plen < len) {
+            for (int32_t s = 0; s < len; ++s) keep[s] = in_sorted(P->col + pa, plen, cmap[list[s]]) >= 0;
+            ext_scale_kept(w, keep, len, P->val + pa);
+        } else {
+            for (int32_t s = 0; s < len; ++s) P->val[pa + s] = w[s];
+        }
+    }
     free(mark); free(list); free(w); free(keep);
 }
 
@@ -522,7 +571,9 @@ int or_amg_setup(int32_t n, const int32_t* rowptr, const int32_t* col,
             if (prm->interp == 1) ext_interp(&At, &St, cf, cmap, nc, prm->interp_pmax, &Q);
             else direct_interp(&At, &St, cf, cmap, nc, &Q);
             transpose(&Q, &h->R[l]);
-            csr_free(&At); csr_free(&St); csr_free(&Q);
+            if (prm->interp == 1) h->Sq[l] = St;
+            else csr_free(&St);
+            csr_free(&At); csr_free(&Q);
         } else {
             transpose(&h->P[l], &h->R[l]);
         }
@@ -530,7 +581,8 @@ int or_amg_setup(int32_t n, const int32_t* rowptr, const int32_t* col,
         spgemm(A, &h->P[l], &AP);
         spgemm(&h->R[l], &AP, &h->A[l + 1]);
         csr_free(&AP);
-        csr_free(&S);
+        if (prm->interp == 1) h->S[l] = S;
+        else csr_free(&S);
         free(cmap);
         ++l;
     }
@@ -554,7 +606,8 @@ int or_amg_setup(int32_t n, const int32_t* rowptr, const int32_t* col,
  * Setup reuse across Newton iterations: the C/F splits and the sparsity
  * patterns of every P, R and A_l are kept from the setup, and only values
  * are recomputed from the new level-0 operator, in the setup's order:
- *   interpolation  direct interpolation restricted to the frozen set P_i of
+ *   interpolation  extended+i: see ext_refresh (the strength patterns are
+ *                  kept too).  Direct: interpolation restricted to the frozen set P_i of
  *                  row i: with s = sign(a_ii), sum_all = sum of the
  *                  off-diagonal a_ik with s a_ik < 0, lump = sum of the
  *                  other off-diagonal a_ik, sum_p = sum of a_ij over j in
@@ -571,7 +624,7 @@ int or_amg_setup(int32_t n, const int32_t* rowptr, const int32_t* col,
  *   coarse op.     A_{l+1} = R (A P), each entry summed in ascending inner
  *                  index; its pattern equals the frozen one;
  *   coarsest       dense LU with partial pivoting, as at setup.
- * Direct interpolation only (returns -1 for extended+i); -4 on a zero pivot. */
+ * Returns -4 on a zero pivot. */
 static void refresh_interp(const csr_t* A, const int32_t* cf, const int32_t* cmap, csr_t* P)
 {
     for (int32_t i = 0; i < A->n; ++i) {
@@ -609,7 +662,6 @@ static void refresh_interp(const csr_t* A, const int32_t* cf, const int32_t* cma
 
 int or_amg_refresh(or_amg* h, const double* val)
 {
-    if (h->prm.interp != 0) return -1;
     memcpy(h->A[0].val, val, sizeof(double) * (size_t)h->A[0].nnz);
     for (int32_t l = 0; l < h->nlev; ++l) {
         csr_t* A = &h->A[l];
@@ -618,13 +670,15 @@ int or_amg_refresh(or_amg* h, const double* val)
         int32_t* cmap = malloc(sizeof(int32_t) * (size_t)(A->n > 0 ? A->n : 1));
         int32_t nc = 0;
         for (int32_t i = 0; i < A->n; ++i) cmap[i] = h->cf[l][i] ? nc++ : -1;
-        refresh_interp(A, h->cf[l], cmap, &h->P[l]);
+        if (h->prm.interp == 1) ext_refresh(A, &h->S[l], h->cf[l], cmap, &h->P[l]);
+        else refresh_interp(A, h->cf[l], cmap, &h->P[l]);
         csr_t T;
         if (h->prm.restriction == 1) {
             csr_t At, Q;
             transpose(A, &At);
             transpose(&h->R[l], &Q);               /* the frozen pattern of Q = R^T */
-            refresh_interp(&At, h->cf[l], cmap, &Q);
+            if (h->prm.interp == 1) ext_refresh(&At, &h->Sq[l], h->cf[l], cmap, &Q);
+            else refresh_interp(&At, h->cf[l], cmap, &Q);
             transpose(&Q, &T);
             csr_free(&At); csr_free(&Q);
         } else {
@@ -659,6 +713,7 @@ void or_amg_free(or_amg* h)
     if (!h) return;
     for (int32_t l = 0; l < OR_MAXLEV; ++l) {
         csr_free(&h->A[l]); csr_free(&h->P[l]); csr_free(&h->R[l]);
+        csr_free(&h->S[l]); csr_free(&h->Sq[l]);
         free(h->dinv[l]); free(h->cf[l]);
     }
     free(h->lu); free(h->piv);

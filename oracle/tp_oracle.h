@@ -93,8 +93,8 @@ void or_amg_level_copy(const or_amg* h, int32_t l, int32_t* A_rowptr, int32_t* A
 int32_t or_amg_level_R_nnz(const or_amg* h, int32_t l);
 void or_amg_level_R_copy(const or_amg* h, int32_t l, int32_t* rowptr, int32_t* col, double* val);
 /* Numeric refresh for a new level-0 operator on the same pattern: C/F
- * splits and every sparsity pattern frozen, values recomputed (see amg.c).
- * 0 on success, -1 for extended+i interpolation, -4 on a zero pivot. */
+ * splits, strength patterns (extended+i) and every sparsity pattern frozen,
+ * values recomputed (see amg.c).  0 on success, -4 on a zero pivot. */
 int or_amg_refresh(or_amg* h, const double* val);
 /* one V-cycle with zero initial guess: x = V(b) */
 void or_vcycle(const or_amg* h, const double* b, double* x);

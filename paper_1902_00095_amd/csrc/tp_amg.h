@@ -14,6 +14,10 @@ int lanes_for(int32_t n, int64_t nnz);
 struct Level {
     Csr A, P, R;          // FP64 setup results (P, R empty on the coarsest level)
     Csr AP;               // the product A P formed for the Galerkin operator (kept for numeric refreshes)
+    // extended+i interpolation, kept for numeric refreshes: the strength
+    // pattern of A and the interpolatory sets (S, T), and the same for A^T
+    // when R = Q^T (Sq, Tq)
+    Csr S, T, Sq, Tq;
     DBuf<int32_t> cf;     // 1 C, 0 F
     DBuf<double> dinv;    // 1 / sum_j |a_ij|
     DBuf<float> A32, P32, R32, dinv32;  // storage 1 copies (storage 2: P32, R32, dinv32)

@@ -560,14 +560,18 @@ __device__ inline double opposite(double a, double akk) { return (akk > 0.0 ? a 
 // strong F neighbour with den_k = 0 is lumped like a weak one.
 // Row i's weights are formed in w (scratch of the row's interpolatory-set
 // length), then written to P, truncated as described at k_ext_fill_w.
+// refresh != 0: P's pattern is frozen (a numeric refresh) -- a row shorter
+// than its interpolatory set keeps its frozen columns instead of the pmax of
+// largest magnitude, and only values are written.
 __device__ void ext_row(int32_t i, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                         const double* __restrict__ val, const int32_t* __restrict__ Srp,
                         const int32_t* __restrict__ Sc, const int32_t* __restrict__ cf,
                         const int32_t* __restrict__ cmap, const int32_t* __restrict__ Trp,
                         const int32_t* __restrict__ Tc, const int32_t* __restrict__ Prp, int32_t* __restrict__ Pc,
-                        double* __restrict__ Pv, double* __restrict__ wbuf, int pmax) {
+                        double* __restrict__ Pv, double* __restrict__ wbuf, int pmax, int refresh) {
     const int32_t p0 = Prp[i];
     if (cf[i]) {
+        if (refresh) return;  // the unit row is kept
         Pc[p0] = cmap[i];
         Pv[p0] = 1.0;
         return;
@@ -615,6 +619,22 @@ __device__ void ext_row(int32_t i, const int32_t* __restrict__ rowptr, const int
         }
     }
     for (int32_t t = 0; t < len; ++t) w[t] = -w[t] / at;
+    if (refresh) {
+        const int32_t plen = Prp[i + 1] - p0;
+        if (plen >= len) {
+            for (int32_t t = 0; t < len; ++t) Pv[p0 + t] = w[t];
+            return;
+        }
+        double all = 0.0, kept = 0.0;
+        for (int32_t t = 0; t < len; ++t) all += w[t];
+        for (int32_t t = 0; t < len; ++t)
+            if (find_sorted(Pc + p0, plen, cmap[list[t]]) >= 0) kept += w[t];
+        const double f = kept != 0.0 ? all / kept : 1.0;
+        int32_t r = 0;
+        for (int32_t t = 0; t < len; ++t)
+            if (find_sorted(Pc + p0, plen, cmap[list[t]]) >= 0) Pv[p0 + r++] = kept != 0.0 ? w[t] * f : w[t];
+        return;
+    }
     if (pmax > 0 && len > pmax) {
         int32_t sel[EXT_PMAX];
         for (int r = 0; r < pmax; ++r) {  // largest magnitude first, ties: smaller column
@@ -653,9 +673,9 @@ k_ext_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restr
            const double* __restrict__ val, const int32_t* __restrict__ Srp, const int32_t* __restrict__ Sc,
            const int32_t* __restrict__ cf, const int32_t* __restrict__ cmap, const int32_t* __restrict__ Trp,
            const int32_t* __restrict__ Tc, const int32_t* __restrict__ Prp, int32_t* __restrict__ Pc,
-           double* __restrict__ Pv, double* __restrict__ wbuf, int pmax) {
+           double* __restrict__ Pv, double* __restrict__ wbuf, int pmax, int refresh) {
     const int32_t i = blockIdx.x * B + threadIdx.x;
-    if (i < n) ext_row(i, rowptr, col, val, Srp, Sc, cf, cmap, Trp, Tc, Prp, Pc, Pv, wbuf, pmax);
+    if (i < n) ext_row(i, rowptr, col, val, Srp, Sc, cf, cmap, Trp, Tc, Prp, Pc, Pv, wbuf, pmax, refresh);
 }
 
 // Wavefront-per-row form for levels of long rows.  Weight slot t of the row
@@ -669,7 +689,9 @@ k_ext_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restr
 // of more than EXT_SLOTS slots take the one-thread form on lane 0.  Truncation (pmax > 0, longer rows): pmax rounds of a
 // wavefront arg-max over (|w|, then the smaller slot) select the kept slots,
 // the full and the kept sums run slot by slot in column order, and the kept
-// weights, scaled by their ratio, are written in column order.
+// weights, scaled by their ratio, are written in column order.  A refresh
+// (frozen P pattern, see ext_row) marks the kept slots by membership in the
+// row's frozen columns instead and writes values only.
 constexpr int EXT_NW = 4;
 constexpr int EXT_SLOTS = WR * EXT_NW;
 constexpr int EXT_KROW = 256;  // rows of strong F neighbours up to this long are staged in LDS
@@ -679,13 +701,13 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
              const double* __restrict__ val, const int32_t* __restrict__ Srp, const int32_t* __restrict__ Sc,
              const int32_t* __restrict__ cf, const int32_t* __restrict__ cmap, const int32_t* __restrict__ Trp,
              const int32_t* __restrict__ Tc, const int32_t* __restrict__ Prp, int32_t* __restrict__ Pc,
-             double* __restrict__ Pv, double* __restrict__ wbuf, int pmax) {
+             double* __restrict__ Pv, double* __restrict__ wbuf, int pmax, int refresh) {
     const int32_t i = blockIdx.x * WR_ROWS + threadIdx.x / WR;
     const int lane = threadIdx.x % WR;
     if (i >= n) return;
     const int32_t p0 = Prp[i];
     if (cf[i]) {
-        if (lane == 0) {
+        if (lane == 0 && !refresh) {
             Pc[p0] = cmap[i];
             Pv[p0] = 1.0;
         }
@@ -695,7 +717,7 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
     const int32_t len = Trp[i + 1] - Trp[i];
     if (len == 0) return;
     if (len > EXT_SLOTS) {
-        if (lane == 0) ext_row(i, rowptr, col, val, Srp, Sc, cf, cmap, Trp, Tc, Prp, Pc, Pv, wbuf, pmax);
+        if (lane == 0) ext_row(i, rowptr, col, val, Srp, Sc, cf, cmap, Trp, Tc, Prp, Pc, Pv, wbuf, pmax, refresh);
         return;
     }
     const int32_t* Si = Sc + Srp[i];
@@ -831,19 +853,25 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
     }
 #pragma unroll
     for (int r = 0; r < EXT_NW; ++r) w[r] = -w[r] / at;
-    if (!(pmax > 0 && len > pmax)) {
+    const int32_t plen = Prp[i + 1] - p0;
+    if (refresh ? plen >= len : !(pmax > 0 && len > pmax)) {
 #pragma unroll
         for (int r = 0; r < EXT_NW; ++r) {
             const int32_t t = r * WR + lane;
             if (t < len) {
-                Pc[p0 + t] = cmap[list[t]];
+                if (!refresh) Pc[p0 + t] = cmap[lc[r]];
                 Pv[p0 + t] = w[r];
             }
         }
         return;
     }
     unsigned selm = 0;  // bit r: slot r * WR + lane kept
-    for (int round = 0; round < pmax; ++round) {
+    if (refresh) {
+#pragma unroll
+        for (int r = 0; r < EXT_NW; ++r)
+            if (lc[r] >= 0 && find_sorted(Pc + p0, plen, cmap[lc[r]]) >= 0) selm |= 1u << r;
+    }
+    for (int round = 0; round < (refresh ? 0 : pmax); ++round) {
         double bm = -1.0;
         int32_t bt = INT32_MAX;
 #pragma unroll
@@ -886,7 +914,7 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
         const uint64_t km = __ballot(k);
         if (k) {
             const int32_t pos = below + __popcll(km & ((1ull << lane) - 1ull));
-            Pc[p0 + pos] = cmap[list[r * WR + lane]];
+            if (!refresh) Pc[p0 + pos] = cmap[lc[r]];
             Pv[p0 + pos] = kept != 0.0 ? w[r] * f : w[r];
         }
         below += __popcll(km);
@@ -2145,10 +2173,29 @@ static void direct_interp(const Csr& A, const Csr& S, const int32_t* cf, const i
     }
 }
 
-static void ext_interp(const Csr& A, const Csr& S, const int32_t* cf, const int32_t* cmap, int32_t nc,
-                       int pmax, Csr& P, int32_t* flag, hipStream_t s) {
+// Extended+i weights of every row of A over its interpolatory set (row i of
+// T) written to P: at setup (refresh 0) P's columns too, truncated to the
+// pmax of largest magnitude; in a numeric refresh (refresh 1) P's pattern is
+// frozen and only its values are rewritten.
+static void ext_fill(const Csr& A, const Csr& S, const Csr& T, const int32_t* cf, const int32_t* cmap, Csr& P,
+                     int pmax, int refresh, hipStream_t s) {
     const int32_t n = A.n;
-    Csr X, Y, T;
+    if (n == 0) return;
+    DBuf<double> wbuf(std::max(T.nnz, 1), s);  // one weight per interpolatory-set entry
+    if (long_rows(A.n, A.nnz))
+        TP_LAUNCH(k_ext_fill_w, cdiv(n, WR_ROWS), B, 0, s, n, A.rowptr.p, A.col.p, A.val.p, S.rowptr.p, S.col.p, cf,
+                  cmap, T.rowptr.p, T.col.p, P.rowptr.p, P.col.p, P.val.p, wbuf.p, pmax, refresh);
+    else
+        TP_LAUNCH(k_ext_fill, cdiv(n, B), B, 0, s, n, A.rowptr.p, A.col.p, A.val.p, S.rowptr.p, S.col.p, cf, cmap,
+                  T.rowptr.p, T.col.p, P.rowptr.p, P.col.p, P.val.p, wbuf.p, pmax, refresh);
+}
+
+// T (out): the interpolatory sets C^_i, one row per point (fine columns,
+// ascending), kept by the caller for numeric refreshes.
+static void ext_interp(const Csr& A, const Csr& S, const int32_t* cf, const int32_t* cmap, int32_t nc,
+                       int pmax, Csr& P, Csr& T, int32_t* flag, hipStream_t s) {
+    const int32_t n = A.n;
+    Csr X, Y;
     X.n = Y.n = n;
     X.m = Y.m = n;
     X.rowptr.alloc(n + 1, s);
@@ -2176,13 +2223,7 @@ static void ext_interp(const Csr& A, const Csr& S, const int32_t* cf, const int3
     P.nnz = read_i32(P.rowptr.p + n, s);
     P.col.alloc(std::max(P.nnz, 1), s);
     P.val.alloc(std::max(P.nnz, 1), s);
-    DBuf<double> wbuf(std::max(T.nnz, 1), s);  // one weight per interpolatory-set entry
-    if (n > 0 && long_rows(A.n, A.nnz))
-        TP_LAUNCH(k_ext_fill_w, cdiv(n, WR_ROWS), B, 0, s, n, A.rowptr.p, A.col.p, A.val.p, S.rowptr.p, S.col.p, cf,
-                  cmap, T.rowptr.p, T.col.p, P.rowptr.p, P.col.p, P.val.p, wbuf.p, pmax);
-    else if (n > 0)
-        TP_LAUNCH(k_ext_fill, cdiv(n, B), B, 0, s, n, A.rowptr.p, A.col.p, A.val.p, S.rowptr.p, S.col.p, cf, cmap,
-                  T.rowptr.p, T.col.p, P.rowptr.p, P.col.p, P.val.p, wbuf.p, pmax);
+    ext_fill(A, S, T, cf, cmap, P, pmax, 0, s);
 }
 
 static void make_f32(DBuf<float>& dst, const DBuf<double>& src, size_t n, hipStream_t s) {
@@ -2426,14 +2467,22 @@ static void setup(tp_amg* h, int32_t n, const int32_t* rowptr, const int32_t* co
             L.cf.release();
             break;
         }
-        if (prm.interp == 1) ext_interp(A, S, L.cf.p, cmap.p, nc, prm.interp_pmax, L.P, sg_flag.p, s);
-        else direct_interp(A, S, L.cf.p, cmap.p, nc, L.P, s);
+        if (prm.interp == 1) {
+            ext_interp(A, S, L.cf.p, cmap.p, nc, prm.interp_pmax, L.P, L.T, sg_flag.p, s);
+            L.S = std::move(S);
+        } else {
+            direct_interp(A, S, L.cf.p, cmap.p, nc, L.P, s);
+        }
         if (prm.restriction == 1) {
             Csr At, St, Q;
             transpose(A.rowptr.p, A.col.p, A.val.p, A.n, A.n, A.nnz, true, At, s);
             strength(At, prm.theta, St, s);
-            if (prm.interp == 1) ext_interp(At, St, L.cf.p, cmap.p, nc, prm.interp_pmax, Q, sg_flag.p, s);
-            else direct_interp(At, St, L.cf.p, cmap.p, nc, Q, s);
+            if (prm.interp == 1) {
+                ext_interp(At, St, L.cf.p, cmap.p, nc, prm.interp_pmax, Q, L.Tq, sg_flag.p, s);
+                L.Sq = std::move(St);
+            } else {
+                direct_interp(At, St, L.cf.p, cmap.p, nc, Q, s);
+            }
             transpose(Q.rowptr.p, Q.col.p, Q.val.p, Q.n, nc, Q.nnz, true, L.R, s);
         } else {
             transpose(L.P.rowptr.p, L.P.col.p, L.P.val.p, L.P.n, nc, L.P.nnz, true, L.R, s);
@@ -2710,7 +2759,7 @@ static void refresh_level_copies(tp_amg* h, Level& L, bool transfers, hipStream_
 }
 
 static void refresh_numeric(tp_amg* h, const double* val, hipStream_t s) {
-    TP_CHECK_ARG(h->prm.interp == 0, "amg_refresh: the numeric refresh needs direct interpolation (interp 0)");
+    const bool ext = h->prm.interp == 1;
     const int nl = (int)h->lev.size();
     TP_HIP(hipMemcpyAsync(h->lev[0].A.val.p, val, sizeof(double) * h->lev[0].A.nnz, hipMemcpyDeviceToDevice, s));
     for (int l = 0; l < nl; ++l) {
@@ -2720,14 +2769,18 @@ static void refresh_numeric(tp_amg* h, const double* val, hipStream_t s) {
         if (l == nl - 1) break;
         DBuf<int32_t> cmap(n + 1, s);
         scan_exclusive(L.cf.p, cmap.p, n, s);
-        TP_LAUNCH(k_refresh_interp, cdiv(n, B), B, 0, s, n, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.cf.p, cmap.p,
-                  L.P.rowptr.p, L.P.col.p, L.P.val.p);
+        if (ext) ext_fill(L.A, L.S, L.T, L.cf.p, cmap.p, L.P, h->prm.interp_pmax, 1, s);
+        else
+            TP_LAUNCH(k_refresh_interp, cdiv(n, B), B, 0, s, n, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.cf.p, cmap.p,
+                      L.P.rowptr.p, L.P.col.p, L.P.val.p);
         if (h->prm.restriction == 1) {
             Csr At, Q;
             transpose(L.A.rowptr.p, L.A.col.p, L.A.val.p, n, n, L.A.nnz, true, At, s);
             transpose(L.R.rowptr.p, L.R.col.p, L.R.val.p, L.R.n, n, L.R.nnz, true, Q, s);  // pattern of R^T
-            TP_LAUNCH(k_refresh_interp, cdiv(n, B), B, 0, s, n, At.rowptr.p, At.col.p, At.val.p, L.cf.p, cmap.p,
-                      Q.rowptr.p, Q.col.p, Q.val.p);
+            if (ext) ext_fill(At, L.Sq, L.Tq, L.cf.p, cmap.p, Q, h->prm.interp_pmax, 1, s);
+            else
+                TP_LAUNCH(k_refresh_interp, cdiv(n, B), B, 0, s, n, At.rowptr.p, At.col.p, At.val.p, L.cf.p, cmap.p,
+                          Q.rowptr.p, Q.col.p, Q.val.p);
             TP_LAUNCH(k_scatter_transpose, cdiv(n, B), B, 0, s, n, Q.rowptr.p, Q.col.p, Q.val.p, L.R.rowptr.p,
                       L.R.col.p, L.R.val.p);
         } else {

@@ -155,9 +155,7 @@ class NewtonConfig:
     build both hierarchies at a step's first Newton iteration only and
     refresh their finest level at the later ones (coarse levels lagged).
     "numeric": build at a step's first iteration, then refresh every level
-    numerically on the kept C/F splits and patterns (amg_refresh; a pressure
-    hierarchy with extended+i interpolation, which has no numeric refresh, is
-    rebuilt instead).
+    numerically on the kept C/F splits and patterns (amg_refresh).
     "numeric_run": build once for the run and refresh numerically at every
     later Newton iteration, rebuilding when a solve takes more than
     `rebuild_ratio` times the FGMRES iterations of the first solve after the
@@ -177,17 +175,6 @@ class NewtonConfig:
 
 def _schur_values(J, cfg):
     return {"T": J.S, "ATT": J.TT}.get(cfg.schur)
-
-
-def _rebuild_pp(J, cfg, hier):
-    """A new pressure hierarchy for J and a new preconditioner handle on it,
-    keeping the second one (the Schur hierarchy or the CPR factors)."""
-    a_pp, second, M = hier
-    M.close()
-    a_pp.close()
-    a_pp = tps.AMG(J.rowptr, J.col, J.pp, amg_params(cfg, "pp"))
-    M = tps.Precond.cpr(J, a_pp, second) if cfg.method == "cpr" else tps.Precond(J, a_pp, second, cfg.variant)
-    return a_pp, second, M
 
 
 def _backtrack(prob, dev, J, G, x, dx, gn, alpha=1e-4, max_backtracks=10):
@@ -333,7 +320,6 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None, on_
         raise ValueError(f"unknown reuse mode {ncfg.reuse!r}")
     reusable = mode is not None and (cfg.method == "cpr" or cfg.schur in ("T", "ATT"))
     refresh = (lambda h, v: h.refresh_fine(v)) if mode == "fine" else (lambda h, v: h.refresh(v))
-    pp_refreshable = amg_params(cfg, "pp").interp == 0
     refreshes, base_its, rebuild = 0, None, False
     guard = LearnedGuard() if net is not None else None
     attached = False
@@ -364,10 +350,7 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None, on_
                 ts = time.perf_counter()
                 built = False
                 if hier is not None and reusable and (k > 0 or mode == "numeric_run") and not rebuild:
-                    if mode == "fine" or pp_refreshable:
-                        refresh(hier[0], J.pp)
-                    else:
-                        hier = _rebuild_pp(J, cfg, hier)
+                    refresh(hier[0], J.pp)
                     if cfg.method == "cpr":
                         hier[1].refactor(J)
                     else:

@@ -66,18 +66,22 @@ def _same_structure(La, Lb):
     return all(np.array_equal(a[k], b[k]) for a, b in zip(La, Lb) for k in KEYS if k in a and k in b)
 
 
-@pytest.mark.parametrize("which,restr,storage", [("pp", 0, 0), ("S", 1, 0), ("S", 1, 1), ("pp", 0, 2)])
-def test_refresh_equals_fresh_setup_when_split_unchanged(which, restr, storage):
+@pytest.mark.parametrize("which,restr,storage,interp", [
+    ("pp", 0, 0, 0), ("S", 1, 0, 0), ("S", 1, 1, 0), ("pp", 0, 2, 0),
+    ("pp", 0, 0, 1), ("pp", 0, 1, 1), ("S", 1, 0, 1)])
+def test_refresh_equals_fresh_setup_when_split_unchanged(which, restr, storage, interp):
     """Refreshing with the values of a nearby Newton state whose fresh setup
-    keeps every split and pattern gives the fresh setup's hierarchy bit for
-    bit (all levels: operators, P, R), and the same V-cycle output."""
-    say("refresh == fresh", which, restr, storage)
+    keeps every split and pattern (and, for extended+i interpolation, every
+    strength pattern and truncation choice) gives the fresh setup's
+    hierarchy bit for bit (all levels: operators, P, R), and the same
+    V-cycle output."""
+    say("refresh == fresh", which, restr, storage, interp)
     p = synth.make_problem("W2", grid=synth.Grid(24, 20, 12, 1, 1, 1))
     Jo = oracle.jacobian(p)
     Jo2 = oracle.jacobian(_shifted(p, 1e-7))
     v1, v2 = getattr(Jo, which), getattr(Jo2, which)
     assert not np.array_equal(v1, v2)
-    prm = tps.AmgParams(restriction=restr, storage=storage, coarse_max=64)
+    prm = tps.AmgParams(restriction=restr, storage=storage, coarse_max=64, interp=interp)
     rp, ci = dev(Jo.rowptr), dev(Jo.col)
     h = tps.AMG(rp, ci, dev(v1), prm)
     fresh = tps.AMG(rp, ci, dev(v2), prm)
@@ -104,18 +108,18 @@ def test_refresh_equals_fresh_setup_when_split_unchanged(which, restr, storage):
     fresh.close()
 
 
-@pytest.mark.parametrize("which,restr", [("pp", 0), ("S", 1)])
-def test_refresh_matches_oracle_refresh_on_changed_operator(which, restr):
+@pytest.mark.parametrize("which,restr,interp", [("pp", 0, 0), ("S", 1, 0), ("pp", 0, 1), ("S", 1, 1)])
+def test_refresh_matches_oracle_refresh_on_changed_operator(which, restr, interp):
     """Refreshing with a distant Newton state's operator (a fresh setup would
     pick other splits): the GPU's refreshed hierarchy equals the oracle's
     refreshed hierarchy (patterns bit-exact, values within 1e-13), and the
     refreshed V-cycle agrees within 1e-10."""
-    say("refresh vs oracle refresh", which, restr)
+    say("refresh vs oracle refresh", which, restr, interp)
     p = synth.make_problem("W2", grid=synth.Grid(24, 20, 12, 1, 1, 1))
     Jo = oracle.jacobian(p)
     Jo2 = oracle.jacobian(_shifted(p, 1.0))
     v1, v2 = getattr(Jo, which), getattr(Jo2, which)
-    prm = tps.AmgParams(restriction=restr, coarse_max=64)
+    prm = tps.AmgParams(restriction=restr, coarse_max=64, interp=interp)
     h = tps.AMG(dev(Jo.rowptr), dev(Jo.col), dev(v1), prm)
     ho = oracle.AMG(Jo.n, Jo.rowptr, Jo.col, v1, **prm.oracle_kwargs())
     before = _levels(h)
@@ -139,16 +143,17 @@ def test_refresh_matches_oracle_refresh_on_changed_operator(which, restr):
     h.close()
 
 
-def test_refresh_keeps_captured_graph_valid():
+@pytest.mark.parametrize("interp_pp", [0, 1])
+def test_refresh_keeps_captured_graph_valid(interp_pp):
     """A preconditioner whose apply is replayed from a captured HIP graph
     keeps working after both of its hierarchies are refreshed in place for
     the next Newton system: the solve converges, and its iterates equal, bit
     for bit, those of the same solve with the kernels launched one by one."""
-    say("refresh keeps graph")
+    say("refresh keeps graph", interp_pp)
     p = synth.make_problem("W2", grid=synth.Grid(20, 18, 10, 1, 1, 1))
     d = solver.to_device(p)
     J, G = solver.assemble(p, d)
-    a_pp, a_S, M = solver.setup(J, solver.SolveConfig(interp_pp=0))   # (direct: refreshable)
+    a_pp, a_S, M = solver.setup(J, solver.SolveConfig(interp_pp=interp_pp))
     x0, s0 = tps.fgmres_solve(J, M, -G, rtol=1e-10, graph=True)
     d["x_k"] = d["x_k"] + x0
     J, G = solver.assemble(p, d, J, G)
@@ -160,13 +165,3 @@ def test_refresh_keeps_captured_graph_valid():
     assert s0["converged"] and sg["converged"] and sg["rel_true"] <= 1e-10
     assert np.array_equal(sg["history"], se["history"]) and np.array_equal(np_(xg), np_(xe))
     M.close(); a_pp.close(); a_S.close()
-
-
-def test_refresh_rejects_extended_interpolation():
-    p = synth.make_problem("W1")
-    Jo = oracle.jacobian(p)
-    h = tps.AMG(dev(Jo.rowptr), dev(Jo.col), dev(Jo.pp), tps.AmgParams(interp=1, coarse_max=64))
-    with pytest.raises(tps.TpError) as e:
-        h.refresh(dev(Jo.pp))
-    assert e.value.code == tps.TP_ERR_ARG
-    h.close()

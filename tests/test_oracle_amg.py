@@ -523,7 +523,162 @@ def test_refresh_on_changed_operator_follows_definition(restriction):
                                rtol=0, atol=1e-8)
 
 
-def test_refresh_rejects_extended_interpolation():
-    J = _problem_ops(dims=(6, 5, 4))
-    h = oracle.AMG(J.n, J.rowptr, J.col, J.pp, coarse_max=16, interp=1)
-    assert h.refresh(J.pp) == -1
+def _ext_row_dense(A, S, cf, i):
+    """Extended+i weights of F row i from the formula (dense): S[i] the
+    strong set of row i; returns {fine column j: w_ij} over the row's
+    interpolatory set (empty when it has none)."""
+    n = A.shape[0]
+    opp = lambda a, d: a if (a < 0 if d > 0 else a > 0) else 0.0
+    Fs = [k for k in S[i] if not cf[k]]
+    Ch = {j for j in S[i] if cf[j]} | {j for k in Fs for j in S[k] if cf[j]}
+    if not Ch:
+        return {}
+    w = {j: A[i, j] for j in Ch}
+    at = A[i, i] + sum(A[i, j] for j in range(n)
+                       if j != i and A[i, j] != 0 and j not in S[i] and j not in Ch)
+    for k in Fs:
+        den = sum(opp(A[k, l], A[k, k]) for l in Ch | {i})
+        if den == 0:
+            at += A[i, k]
+            continue
+        for j in Ch:
+            w[j] += A[i, k] * opp(A[k, j], A[k, k]) / den
+        at += A[i, k] * opp(A[k, i], A[k, k]) / den
+    return {j: -v / at for j, v in w.items()}
+
+
+def _ext_refresh_dense(A, S, cf, Ppat):
+    """The refreshed extended+i P (dense): full weights of the new operator A
+    on the frozen strong sets S; a row whose frozen pattern Ppat holds fewer
+    columns than its interpolatory set keeps those, scaled to the full row
+    sum."""
+    n = A.shape[0]
+    cmap = np.cumsum(cf) - 1
+    W = np.zeros_like(Ppat)
+    for i in range(n):
+        if cf[i]:
+            W[i, cmap[i]] = 1.0
+            continue
+        w = _ext_row_dense(A, S, cf, i)
+        kept = [j for j in w if Ppat[i, cmap[j]]]
+        if len(kept) < len(w):
+            ks = sum(w[j] for j in kept)
+            f = sum(w.values()) / ks if ks != 0 else 1.0
+            for j in kept:
+                W[i, cmap[j]] = w[j] * f
+        else:
+            for j, v in w.items():
+                W[i, cmap[j]] = v
+    return W
+
+
+@pytest.mark.parametrize("restriction,pmax", [(0, 4), (0, 0), (1, 4)])
+def test_ext_refresh_with_unchanged_split_equals_fresh_setup(restriction, pmax):
+    """Extended+i: a refresh with the setup's own values, and with the
+    values of a nearby Newton state whose fresh setup keeps every split,
+    strength pattern and kept set, reproduces the fresh setup's hierarchy
+    bit for bit."""
+    p = synth.make_problem("W2", seed=5, grid=synth.Grid(10, 9, 6, 1.0, 1.0, 1.0))
+    J = oracle.jacobian(p)
+    val = J.S if restriction else J.pp
+    kw = dict(restriction=restriction, coarse_max=16, smoother=1, cheb_degree=4, interp=1, interp_pmax=pmax)
+    h = oracle.AMG(J.n, J.rowptr, J.col, val, **kw)
+    assert h.nlev >= 3
+    J2 = oracle.jacobian(_shifted_state(p, 1e-7))
+    val2 = J2.S if restriction else J2.pp
+    assert not np.array_equal(val, val2)
+    for v in (val, val2):
+        fresh = oracle.AMG(J.n, J.rowptr, J.col, v, **kw)
+        assert _same_structure(h, fresh)
+        assert h.refresh(v) == 0
+        for l in range(h.nlev):
+            a, b = h.level(l), fresh.level(l)
+            assert np.array_equal(a["A_val"], b["A_val"]), l
+            if l < h.nlev - 1:
+                assert np.array_equal(a["P_val"], b["P_val"]) and np.array_equal(a["R_val"], b["R_val"]), l
+        rhs = synth.random_rhs(3, J.n)
+        assert np.array_equal(h.vcycle(rhs), fresh.vcycle(rhs))
+
+
+@pytest.mark.parametrize("restriction", [0, 1])
+def test_ext_refresh_on_changed_operator_follows_definition(restriction):
+    """Extended+i refresh with a distant Newton state's operator: the
+    patterns stay; P is the extended+i formula of the new operator on the
+    frozen strong sets (those of the setup operator), truncated rows keeping
+    their frozen columns scaled to the full row sum (dense, definition); R is
+    P^T or the same construction on A^T; every coarse operator is the dense
+    R A P of the level above."""
+    p = synth.make_problem("W2", seed=5, grid=synth.Grid(8, 7, 5, 1.0, 1.0, 1.0))
+    J = oracle.jacobian(p)
+    val = J.S if restriction else J.pp
+    kw = dict(restriction=restriction, coarse_max=16, smoother=1, cheb_degree=4, interp=1, interp_pmax=4)
+    h = oracle.AMG(J.n, J.rowptr, J.col, val, **kw)
+    J2 = oracle.jacobian(_shifted_state(p, 1.0))
+    val2 = J2.S if restriction else J2.pp
+    assert not _same_structure(h, oracle.AMG(J.n, J.rowptr, J.col, val2, **kw))
+    before = [h.level(l) for l in range(h.nlev)]
+    assert h.refresh(val2) == 0
+    A = _csr(J.n, J.rowptr, J.col, val2).toarray()
+    A_setup = _csr(J.n, J.rowptr, J.col, val).toarray()     # the frozen strong sets come from it
+    truncated = 0
+    for l in range(h.nlev - 1):
+        L, Ln = h.level(l), h.level(l + 1)
+        for k in ("A_rowptr", "A_col", "cf", "P_rowptr", "P_col", "R_rowptr", "R_col"):
+            assert np.array_equal(L[k], before[l][k]), (l, k)
+        Pd = _csr(L["n"], L["P_rowptr"], L["P_col"], L["P_val"], Ln["n"]).toarray()
+        Ppat = _csr(L["n"], L["P_rowptr"], L["P_col"], np.ones(len(L["P_col"])), Ln["n"]).toarray()
+        W = _ext_refresh_dense(A, _strength_sets(A_setup), L["cf"], Ppat)
+        np.testing.assert_allclose(Pd, W, rtol=1e-12, atol=1e-15)
+        truncated += int((np.diff(L["P_rowptr"]) == 4).sum())
+        Rd = _csr(Ln["n"], L["R_rowptr"], L["R_col"], L["R_val"], L["n"]).toarray()
+        if restriction:
+            Rpat = _csr(Ln["n"], L["R_rowptr"], L["R_col"], np.ones(len(L["R_col"])), L["n"]).toarray()
+            Wq = _ext_refresh_dense(A.T.copy(), _strength_sets(A_setup.T.copy()), L["cf"], Rpat.T.copy())
+            np.testing.assert_allclose(Rd, Wq.T, rtol=1e-12, atol=1e-15)
+        else:
+            assert np.array_equal(Rd, Pd.T)
+        # the next level's frozen strong sets come from the setup's operator
+        A_setup = _csr(Ln["n"], before[l + 1]["A_rowptr"], before[l + 1]["A_col"],
+                       before[l + 1]["A_val"]).toarray()
+        A = Rd @ A @ Pd
+        An = _csr(Ln["n"], Ln["A_rowptr"], Ln["A_col"], Ln["A_val"]).toarray()
+        np.testing.assert_allclose(An, A, rtol=1e-10, atol=1e-12 * np.abs(A).max())
+        A = An
+    assert truncated > 0
+
+
+def test_ext_refresh_preserves_constants():
+    """A refresh of an extended+i hierarchy with other zero-row-sum values
+    (a graph Laplacian with new random edge weights, frozen strength
+    patterns that no longer match the new values): every level's refreshed
+    interpolation still maps the coarse constant to the fine one, truncated
+    rows included."""
+    n, rp, c, v = synth.poisson_csr((20, 16, 6), dirichlet=False)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+
+    def laplacian(seed):
+        rng = np.random.default_rng(seed)
+        w = np.zeros(len(c))
+        off = rows != c
+        lo = np.minimum(rows, c)[off] * n + np.maximum(rows, c)[off]
+        ew = dict(zip(np.unique(lo), rng.uniform(0.05, 2.0, len(np.unique(lo)))))
+        w[off] = [-ew[k] for k in lo]
+        diag = np.nonzero(~off)[0]
+        w[diag] = -np.add.reduceat(np.where(off, w, 0.0), rp[:-1])
+        return w
+
+    v1, v2 = laplacian(1), laplacian(2)
+    kw = dict(coarse_max=16, skip_lu=True, interp=1, interp_pmax=4)
+    h = oracle.AMG(n, rp, c, v1, **kw)
+    assert h.nlev >= 3 and not _same_structure(h, oracle.AMG(n, rp, c, v2, **kw))
+    P_before = [h.level(l)["P_val"].copy() for l in range(h.nlev - 1)]
+    assert h.refresh(v2) == 0
+    cut = 0
+    for l in range(h.nlev - 1):
+        L0, L1 = h.level(l), h.level(l + 1)
+        assert not np.array_equal(L0["P_val"], P_before[l])
+        P = _csr(L0["n"], L0["P_rowptr"], L0["P_col"], L0["P_val"], L1["n"])
+        nonempty = np.diff(L0["P_rowptr"]) > 0
+        np.testing.assert_allclose((P @ np.ones(L1["n"]))[nonempty], 1.0, rtol=0, atol=1e-12)
+        cut += int((np.diff(L0["P_rowptr"]) == 4).sum())
+    assert cut > 0
