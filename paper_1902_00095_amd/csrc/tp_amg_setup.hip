@@ -400,15 +400,23 @@ k_pmis_select(int32_t n, uint64_t hseed, const int32_t* __restrict__ Srp, const 
 }
 
 // undecided points with a strong C dependence become F; count the rest
+// (one atomic per wavefront)
 __global__ void __launch_bounds__(B)
 k_pmis_fmark(int32_t n, const int32_t* __restrict__ Srp, const int32_t* __restrict__ Sc,
              int8_t* st, int32_t* __restrict__ undecided) {
-    int32_t i = blockIdx.x * B + threadIdx.x;
-    if (i >= n) return;
-    if (st[i] != 0) return;
-    for (int32_t q = Srp[i]; q < Srp[i + 1]; ++q)
-        if (st[Sc[q]] == 1) { st[i] = -1; return; }
-    atomicAdd(undecided, 1);
+    const int32_t i = blockIdx.x * B + threadIdx.x;
+    bool und = false;
+    if (i < n && st[i] == 0) {
+        und = true;
+        for (int32_t q = Srp[i]; q < Srp[i + 1]; ++q)
+            if (st[Sc[q]] == 1) {
+                st[i] = -1;
+                und = false;
+                break;
+            }
+    }
+    const uint64_t m = __ballot(und);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(undecided, (int32_t)__popcll(m));
 }
 
 __global__ void __launch_bounds__(B)
@@ -681,12 +689,13 @@ k_ext_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restr
 // Wavefront-per-row form for levels of long rows.  Weight slot t of the row
 // lives in a register of lane t mod 64, and that lane forms the slot's sum:
 // the row's own coupling, then for each strong F neighbour k in the row's
-// order the term of row k's entry in the slot's column (binary search; a
-// row holds a column once), as the one-thread form adds them.  a~_ii and
-// every den_k are sums over a row: their terms are broadcast to the
-// wavefront one by one in row order.  So every slot, a~_ii and every den_k
-// receive the same operations in the same order (identical results).  Rows
-// of more than EXT_SLOTS slots take the one-thread form on lane 0.  Truncation (pmax > 0, longer rows): pmax rounds of a
+// order the term of row k's entry in the slot's column, as the one-thread
+// form adds them (the neighbours' rows are processed in chunks, see the
+// loop).  a~_ii is a sum over the row: its terms are broadcast to the
+// wavefront one by one in row order; each den_k is summed in row k's order
+// by one lane.  So every slot, a~_ii and every den_k receive the same
+// operations in the same order (identical results).  Rows of more than
+// EXT_SLOTS slots take the one-thread form on lane 0.  Truncation (pmax > 0, longer rows): pmax rounds of a
 // wavefront arg-max over (|w|, then the smaller slot) select the kept slots,
 // the full and the kept sums run slot by slot in column order, and the kept
 // weights, scaled by their ratio, are written in column order.  A refresh
@@ -694,7 +703,14 @@ k_ext_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restr
 // row's frozen columns instead and writes values only.
 constexpr int EXT_NW = 4;
 constexpr int EXT_SLOTS = WR * EXT_NW;
-constexpr int EXT_KROW = 256;  // rows of strong F neighbours up to this long are staged in LDS
+// Chunk sizes: LDS per workgroup stays near 32 KB, so that occupancy is
+// set by registers (measured: 512-entry chunks were 25% slower on the
+// 256x256x64 pressure hierarchy's first coarse level, for the occupancy
+// they cost).
+constexpr int EXT_EC = 256;  // staged neighbour-row entries per chunk
+constexpr int EXT_TC = 256;  // entries of the chunk's term matrix (neighbours x slots)
+constexpr int EXT_KC = 16;   // neighbours per chunk
+constexpr int EXT_SI = 256;  // strength rows up to this long are staged in LDS
 
 __global__ void __launch_bounds__(B)
 k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
@@ -724,12 +740,27 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
     const int32_t slen = Srp[i + 1] - Srp[i];
     // the row's interpolatory set in LDS (binary searches of the den sums)
     __shared__ int32_t s_list[WR_ROWS][EXT_SLOTS];
-    __shared__ int32_t s_kc[WR_ROWS][EXT_KROW];  // the current strong F neighbour's row
-    __shared__ double s_kv[WR_ROWS][EXT_KROW];
-    int32_t* const sl = s_list[threadIdx.x / WR];
-    int32_t* const s_kc_w = s_kc[threadIdx.x / WR];
-    double* const s_kv_w = s_kv[threadIdx.x / WR];
-    for (int32_t t = lane; t < len; t += WR) sl[t] = list[t];
+    // one chunk of strong F neighbours: their rows (columns, then slot
+    // positions; values, then hat values), offsets, and per-row data
+    __shared__ int32_t s_ec[WR_ROWS][EXT_EC];
+    __shared__ double s_ev[WR_ROWS][EXT_EC];
+    __shared__ double s_t[WR_ROWS][EXT_TC];  // T[k][slot]
+    __shared__ int32_t s_ko[WR_ROWS][EXT_KC + 1], s_kb[WR_ROWS][EXT_KC], s_kk[WR_ROWS][EXT_KC],
+        s_kf[WR_ROWS][EXT_KC];
+    __shared__ double s_ka[WR_ROWS][EXT_KC], s_kd[WR_ROWS][EXT_KC], s_kn[WR_ROWS][EXT_KC], s_kt[WR_ROWS][EXT_KC];
+    __shared__ int32_t s_si[WR_ROWS][EXT_SI];
+    double* const s_w0 = s_t[threadIdx.x / WR];  // (the slots' starting sums, before T is used)
+    const int wv = threadIdx.x / WR;
+    int32_t* const sl = s_list[wv];
+    for (int32_t t = lane; t < len; t += WR) {
+        sl[t] = list[t];
+        s_w0[t] = 0.0;
+    }
+    // row i's strong set in LDS when it fits (membership tests below)
+    const bool si_lds = slen <= EXT_SI;
+    if (si_lds)
+        for (int32_t t = lane; t < slen; t += WR) s_si[wv][t] = Si[t];
+    const int32_t* const si = si_lds ? s_si[wv] : Si;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -738,27 +769,6 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
 #pragma unroll
     for (int r = 0; r < EXT_NW; ++r) lc[r] = r * WR + lane < len ? sl[r * WR + lane] : -1;
     const int32_t a = rowptr[i], e = rowptr[i + 1];
-    // position of column x in row k's sorted columns, or -1
-    auto find_in_row = [&](int32_t kb, int32_t ke, int32_t x) -> int32_t {
-        int32_t lo = kb, hi = ke;
-        while (lo < hi) {
-            const int32_t mid = lo + (hi - lo) / 2;
-            if (col[mid] < x) lo = mid + 1;
-            else hi = mid;
-        }
-        return (lo < ke && col[lo] == x) ? lo : -1;
-    };
-    // slot sums start from the row's own coupling (0.0 + a_ij: each column
-    // occurs once in row i) -- found by each slot's lane
-    double w[EXT_NW];
-#pragma unroll
-    for (int r = 0; r < EXT_NW; ++r) {
-        w[r] = 0.0;
-        if (lc[r] >= 0) {
-            const int32_t q = find_in_row(a, e, lc[r]);
-            if (q >= 0) w[r] += val[q];
-        }
-    }
     double aii = 0.0;
     bool has = false;
     for (int32_t q = a + lane; q < e; q += WR)
@@ -766,13 +776,17 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
     const uint64_t hm = __ballot(has);
     aii = hm ? bcast_d(aii, __ffsll((unsigned long long)hm) - 1) : 0.0;
     double at = aii;
-    // weak couplings outside the set, lumped in row order
+    // The row's own couplings: a coupling in the set starts its slot's sum
+    // (0.0 + a_ij, placed by the entry's lane: a row holds a column once);
+    // weak couplings outside the set are lumped into a~_ii in row order.
     for (int32_t b = a; b < e; b += WR) {
         const int32_t q = b + lane;
         const bool ok = q < e;
         const int32_t j = ok ? col[q] : i;
         const double v = ok ? val[q] : 0.0;
-        const bool lump = ok && j != i && find_sorted(sl, len, j) < 0 && find_sorted(Si, slen, j) < 0;
+        const int32_t pos = j != i ? find_sorted(sl, len, j) : -1;
+        if (pos >= 0) s_w0[pos] = 0.0 + v;
+        const bool lump = ok && j != i && pos < 0 && find_sorted(si, slen, j) < 0;
         const uint64_t lm = __ballot(lump);
         const int cnt = min(WR, (int)(e - b));
         for (int l = 0; l < cnt; ++l) {
@@ -780,75 +794,178 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
             if ((lm >> l) & 1ull) at += vl;
         }
     }
-    // strong F neighbours k, ascending: each adds its term to every slot
-    // whose column row k holds (one term per slot and k, so each slot's sum
-    // runs over k in the row's order) and at most one term to a~_ii
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double w[EXT_NW];
+#pragma unroll
+    for (int r = 0; r < EXT_NW; ++r) w[r] = lc[r] >= 0 ? s_w0[r * WR + lane] : 0.0;
+    // Strong F neighbours k in the row's order, in chunks.  A chunk's rows
+    // are staged in LDS together (one pass of loads for all of them); for
+    // all of them at once each row's diagonal, the values hat a_kl of its
+    // entries with l in C^_i or l = i (0 for the others) and den_k, their
+    // sum in row k's order, are formed; the terms a_ik hat a_kl / den_k go
+    // to an LDS matrix T[k][slot] (+0.0 where row k lacks the slot's
+    // column).  Then every slot adds its column of T over the chunk's k in
+    // order, and a~_ii its terms likewise: each sum receives the terms of
+    // the one-row-at-a-time form in the same order (adding +0.0 leaves these
+    // sums, which are never -0.0, unchanged).  A neighbour row of more than
+    // EXT_EC entries is a chunk of its own, read in place.
+    auto wsync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    int32_t* const ko = s_ko[wv];
+    int32_t* const ec = s_ec[wv];
+    double* const ev = s_ev[wv];
+    double* const tm = s_t[wv];
+    // the chunk row that holds staged entry x
+    auto owner = [&](int32_t cnt, int32_t x) -> int {
+        int lo = 0, hi = cnt - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (ko[mid] <= x) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
+    };
+    // one strong F neighbour k (row kc/kv of length kl): its den_k, then its
+    // terms to the slots and to a~_ii, the row's sums broadcast in order
+    auto one_row = [&](int32_t k, double aik, const int32_t* kc, const double* kv, int32_t kl) {
+        double akk = 0.0;
+        bool hk = false;
+        for (int32_t u = lane; u < kl; u += WR)
+            if (kc[u] == k) { akk = kv[u]; hk = true; }
+        const uint64_t km = __ballot(hk);
+        akk = km ? bcast_d(akk, __ffsll((unsigned long long)km) - 1) : 0.0;
+        double den = 0.0;
+        for (int32_t c0 = 0; c0 < kl; c0 += WR) {
+            const int32_t u = c0 + lane;
+            const bool inr = u < kl;
+            const int32_t lcu = inr ? kc[u] : -1;
+            const bool mem = inr && (lcu == i || find_sorted(sl, len, lcu) >= 0);
+            const double h = mem ? opposite(kv[u], akk) : 0.0;
+            const uint64_t mm2 = __ballot(mem);
+            const int c = min(WR, (int)(kl - c0));
+            for (int tt = 0; tt < c; ++tt) {
+                const double ht = bcast_d(h, tt);
+                if ((mm2 >> tt) & 1ull) den += ht;
+            }
+        }
+        if (den == 0.0) {
+            at += aik;
+            return;
+        }
+#pragma unroll
+        for (int r = 0; r < EXT_NW; ++r) {
+            if (lc[r] < 0) continue;
+            const int32_t u = find_sorted(kc, kl, lc[r]);
+            if (u >= 0) w[r] += (aik * opposite(kv[u], akk)) / den;
+        }
+        const int32_t ui = find_sorted(kc, kl, i);
+        if (ui >= 0) at += (aik * opposite(kv[ui], akk)) / den;
+    };
     for (int32_t b = a; b < e; b += WR) {
         const int32_t q = b + lane;
         const bool ok = q < e;
         const int32_t k0 = ok ? col[q] : i;
-        const bool sf = ok && k0 != i && !cf[k0] && find_sorted(Si, slen, k0) >= 0;
-        // every strong F neighbour's row extent and a_ik, loaded at once
+        const bool sf = ok && k0 != i && find_sorted(si, slen, k0) >= 0 && !cf[k0];
         const int32_t kb0 = sf ? rowptr[k0] : 0, ke0 = sf ? rowptr[k0 + 1] : 0;
         const double aik0 = sf ? val[q] : 0.0;
+        const int32_t kl0 = ke0 - kb0;
         uint64_t m = __ballot(sf);
         while (m) {
-            const int l = __ffsll((unsigned long long)m) - 1;
-            m &= m - 1;
-            const int32_t k = bcast_i(k0, l);
-            const double aik = bcast_d(aik0, l);
-            const int32_t kb = bcast_i(kb0, l), ke = bcast_i(ke0, l);
-            // row k in LDS (one coalesced load; the searches below then stay
-            // on chip) when it fits, else read in place
-            const bool kst = ke - kb <= EXT_KROW;
-            const int32_t* kc = col + kb;
-            const double* kv = val + kb;
-            if (kst) {
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                for (int32_t u = lane; u < ke - kb; u += WR) {
-                    s_kc_w[u] = col[kb + u];
-                    s_kv_w[u] = val[kb + u];
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                kc = s_kc_w;
-                kv = s_kv_w;
+            uint64_t cm = 0;  // the chunk: the next neighbours while they fit
+            int cnt = 0;
+            int32_t tot = 0;
+            for (uint64_t mm = m; mm; mm &= mm - 1) {
+                const int l = __ffsll((unsigned long long)mm) - 1;
+                const int32_t kl = bcast_i(kl0, l);
+                if (cnt > 0 && (tot + kl > EXT_EC || cnt == EXT_KC || (cnt + 1) * len > EXT_TC)) break;
+                cm |= 1ull << l;
+                ++cnt;
+                tot += kl;
+                if (kl > EXT_EC) break;
             }
-            const int32_t kl = ke - kb;
-            double akk = 0.0;
-            bool hk = false;
-            for (int32_t u = lane; u < kl; u += WR)
-                if (kc[u] == k) { akk = kv[u]; hk = true; }
-            const uint64_t km = __ballot(hk);
-            akk = km ? bcast_d(akk, __ffsll((unsigned long long)km) - 1) : 0.0;
-            double den = 0.0;
-            for (int32_t c0 = 0; c0 < kl; c0 += WR) {
-                const int32_t u = c0 + lane;
-                const bool in = u < kl;
-                const int32_t lcu = in ? kc[u] : -1;
-                const bool mem = in && (lcu == i || find_sorted(sl, len, lcu) >= 0);
-                const double h = mem ? opposite(kv[u], akk) : 0.0;
-                const uint64_t mm = __ballot(mem);
-                const int cnt = min(WR, (int)(kl - c0));
-                for (int tt = 0; tt < cnt; ++tt) {
-                    const double ht = bcast_d(h, tt);
-                    if ((mm >> tt) & 1ull) den += ht;
-                }
-            }
-            if (den == 0.0) {
-                at += aik;
+            m &= ~cm;
+            if (tot > EXT_EC) {  // one long neighbour row, read in place
+                const int l = __ffsll((unsigned long long)cm) - 1;
+                const int32_t kb = bcast_i(kb0, l);
+                one_row(bcast_i(k0, l), bcast_d(aik0, l), col + kb, val + kb, bcast_i(kl0, l));
                 continue;
             }
+            const bool in = (cm >> lane) & 1ull;
+            const int kx = __popcll(cm & ((1ull << lane) - 1ull));
+            int32_t inc = in ? kl0 : 0;  // inclusive scan of the rows' lengths
 #pragma unroll
-            for (int r = 0; r < EXT_NW; ++r) {
-                if (lc[r] < 0) continue;
-                const int32_t u = find_sorted(kc, kl, lc[r]);
-                if (u >= 0) w[r] += (aik * opposite(kv[u], akk)) / den;
+            for (int d = 1; d < WR; d <<= 1) {
+                const int32_t o = __shfl_up(inc, d, WR);
+                if (lane >= d) inc += o;
             }
-            const int32_t ui = find_sorted(kc, kl, i);
-            if (ui >= 0) at += (aik * opposite(kv[ui], akk)) / den;
+            if (in) {
+                ko[kx] = inc - kl0;
+                s_kb[wv][kx] = kb0;
+                s_kk[wv][kx] = k0;
+                s_ka[wv][kx] = aik0;
+                s_kd[wv][kx] = 0.0;
+                s_kf[wv][kx] = 0;
+            }
+            if (lane == 0) ko[cnt] = tot;
+            wsync();
+            for (int32_t x = lane; x < tot; x += WR) {  // stage the rows
+                const int kk = owner(cnt, x);
+                const int32_t src = s_kb[wv][kk] + (x - ko[kk]);
+                ec[x] = col[src];
+                ev[x] = val[src];
+            }
+            for (int32_t x = lane; x < cnt * len; x += WR) tm[x] = 0.0;
+            wsync();
+            for (int32_t x = lane; x < tot; x += WR) {  // each row's diagonal (a row holds it once)
+                const int kk = owner(cnt, x);
+                if (ec[x] == s_kk[wv][kk]) s_kd[wv][kk] = ev[x];
+            }
+            wsync();
+            for (int32_t x = lane; x < tot; x += WR) {  // hat values; slot positions (-2: column i)
+                const int kk = owner(cnt, x);
+                const int32_t l = ec[x];
+                const int32_t pos = l == i ? -2 : find_sorted(sl, len, l);
+                ev[x] = pos != -1 ? opposite(ev[x], s_kd[wv][kk]) : 0.0;
+                ec[x] = pos;
+            }
+            wsync();
+            if (in) {  // den_k over row k in its order
+                double den = 0.0;
+                for (int32_t x = ko[kx]; x < ko[kx + 1]; ++x) den += ev[x];
+                s_kn[wv][kx] = den;
+            }
+            wsync();
+            for (int32_t x = lane; x < tot; x += WR) {  // the terms
+                const int kk = owner(cnt, x);
+                const double den = s_kn[wv][kk];
+                const int32_t pos = ec[x];
+                if (den != 0.0 && pos != -1) {
+                    const double c = (s_ka[wv][kk] * ev[x]) / den;
+                    if (pos >= 0) {
+                        tm[kk * len + pos] = c;
+                    } else {
+                        s_kt[wv][kk] = c;
+                        s_kf[wv][kk] = 1;
+                    }
+                }
+            }
+            wsync();
+            for (int kk = 0; kk < cnt; ++kk) {  // the sums, k in order
+                if (s_kn[wv][kk] == 0.0) {
+                    at += s_ka[wv][kk];
+                    continue;
+                }
+#pragma unroll
+                for (int r = 0; r < EXT_NW; ++r)
+                    if (lc[r] >= 0) w[r] += tm[kk * len + r * WR + lane];
+                if (s_kf[wv][kk]) at += s_kt[wv][kk];
+            }
+            wsync();  // (the next chunk reuses the arrays)
         }
     }
 #pragma unroll
@@ -1261,19 +1378,30 @@ k_spgemm_long(const int32_t* __restrict__ rows, const int32_t* __restrict__ nrow
             tab[rank] = key;
         }
         __syncthreads();  // (list is read until here; M takes its space)
-        const bool staged = (int64_t)u * la <= LG_M;
-        if (staged)
-            for (int32_t m = t; m < u * la; m += LG_T) s_m[m] = 0.0;
-        __syncthreads();
-        if (staged) {
-            for (int32_t e0 = t; e0 < total; e0 += LG_U * LG_T) {
+        // The A entries in chunks of qc, each chunk's products placed in
+        // the LDS product matrix M[e][q - q0] (+0.0 where row q of B lacks
+        // column e) and added to the entries' sums chunk after chunk: every
+        // output entry is summed over q ascending from 0.0, as in the
+        // one-pass form (adding +0.0 leaves a sum that is never -0.0
+        // unchanged).
+        const int32_t qc = u > 0 ? max(1, LG_M / u) : la;
+        constexpr int LG_E = HASH / LG_T;  // output entries per thread
+        double acc[LG_E];
+#pragma unroll
+        for (int j = 0; j < LG_E; ++j) acc[j] = 0.0;
+        for (int32_t q0 = 0; q0 < la; q0 += qc) {
+            const int32_t q1 = min(la, q0 + qc), wq = q1 - q0;
+            for (int32_t m = t; m < u * wq; m += LG_T) s_m[m] = 0.0;
+            __syncthreads();
+            const int32_t e_end = s_off[q1];
+            for (int32_t e0 = s_off[q0] + t; e0 < e_end; e0 += LG_U * LG_T) {
                 int32_t cc[LG_U], qq[LG_U];
                 double vv[LG_U];
 #pragma unroll
                 for (int uu = 0; uu < LG_U; ++uu) {
                     const int32_t e = e0 + uu * LG_T;
                     qq[uu] = -1;
-                    if (e < total) {
+                    if (e < e_end) {
                         const int32_t q = owner_entry(s_off, la, e);
                         const int32_t src = s_b0[q] + (e - s_off[q]);
                         qq[uu] = q;
@@ -1290,32 +1418,24 @@ k_spgemm_long(const int32_t* __restrict__ rows, const int32_t* __restrict__ nrow
                         if (tab[mid] < cc[uu]) lo = mid + 1;
                         else hi = mid;
                     }
-                    s_m[lo * la + qq[uu]] = vv[uu];
+                    s_m[lo * wq + (qq[uu] - q0)] = vv[uu];
                 }
             }
             __syncthreads();
-            for (int32_t e = t; e < u; e += LG_T) {
-                double acc = 0.0;
-                for (int32_t q = 0; q < la; ++q) acc += s_m[e * la + q];
-                Cc[base + e] = tab[e];
-                Cv[base + e] = acc;
+#pragma unroll
+            for (int j = 0; j < LG_E; ++j) {
+                const int32_t e = t + j * LG_T;
+                if (e < u)
+                    for (int32_t q = 0; q < wq; ++q) acc[j] += s_m[e * wq + q];
             }
-        } else {
-            for (int32_t e = t; e < u; e += LG_T) {
-                const int32_t c = tab[e];
-                double acc = 0.0;
-                for (int32_t q = 0; q < la; ++q) {
-                    const int32_t b0 = s_b0[q];
-                    int32_t lo = b0, hi = b0 + (s_off[q + 1] - s_off[q]) - 1;
-                    while (lo <= hi) {
-                        const int32_t mid = (lo + hi) >> 1;
-                        const int32_t v = Bc[mid];
-                        if (v == c) { acc += s_av[q] * Bv[mid]; break; }
-                        if (v < c) lo = mid + 1; else hi = mid - 1;
-                    }
-                }
-                Cc[base + e] = c;
-                Cv[base + e] = acc;
+            __syncthreads();
+        }
+#pragma unroll
+        for (int j = 0; j < LG_E; ++j) {
+            const int32_t e = t + j * LG_T;
+            if (e < u) {
+                Cc[base + e] = tab[e];
+                Cv[base + e] = acc[j];
             }
         }
         __syncthreads();
