@@ -51,67 +51,11 @@ int lanes_for(int32_t n, int64_t nnz) {
     return g;
 }
 
-// ---- strength ------------------------------------------------------------------
-__device__ inline void row_sign_max(const int32_t* rowptr, const int32_t* col, const double* val,
-                                    int32_t i, double* s_out, double* m_out) {
-    double aii = 0.0;
-    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q)
-        if (col[q] == i) aii = val[q];
-    double s = aii < 0.0 ? -1.0 : 1.0;
-    double m = 0.0;
-    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q)
-        if (col[q] != i && -s * val[q] > m) m = -s * val[q];
-    *s_out = s;
-    *m_out = m;
-}
-
-__global__ void __launch_bounds__(B)
-k_strength(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-           const double* __restrict__ val, double theta, int32_t* __restrict__ cnt,
-           const int32_t* __restrict__ Srowptr, int32_t* __restrict__ Scol) {
-    int32_t i = blockIdx.x * B + threadIdx.x;
-    if (i >= n) return;
-    double s, m;
-    row_sign_max(rowptr, col, val, i, &s, &m);
-    int32_t c = 0;
-    int32_t out = Scol ? Srowptr[i] : 0;
-    if (m > 0.0) {
-        for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
-            if (col[q] != i && -s * val[q] >= theta * m) {
-                if (Scol) Scol[out + c] = col[q];
-                ++c;
-            }
-        }
-    }
-    if (cnt) cnt[i] = c;
-}
-
 // ---- transpose ------------------------------------------------------------------
 __global__ void __launch_bounds__(B)
 k_fill_i32(int32_t* __restrict__ a, int32_t v, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * B + threadIdx.x;
     if (i < n) a[i] = v;
-}
-
-__global__ void __launch_bounds__(B)
-k_col_count(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-            int32_t* __restrict__ cnt) {
-    int32_t i = blockIdx.x * B + threadIdx.x;
-    if (i >= n) return;
-    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) atomicAdd(&cnt[col[q]], 1);
-}
-
-__global__ void __launch_bounds__(B)
-k_transpose_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                 const double* __restrict__ val, int32_t* __restrict__ cursor,
-                 int32_t* __restrict__ Tcol, double* __restrict__ Tval) {
-    int32_t i = blockIdx.x * B + threadIdx.x;
-    if (i >= n) return;
-    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
-        int32_t pos = atomicAdd(&cursor[col[q]], 1);
-        Tcol[pos] = i;
-        if (Tval) Tval[pos] = val[q];
-    }
 }
 
 // Sorted copy of each row: one 64-lane workgroup per row; an entry's
@@ -132,14 +76,15 @@ k_sort_rows(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __rest
     }
 }
 
-// ---- one wavefront per row (levels with long rows) ---------------------------------------
-// On coarse levels rows hold tens of entries and the levels have few rows, so a
-// thread per row walks a long dependent chain of loads with little parallelism.
-// These variants give each row a 64-lane wavefront: entries are loaded
-// lane-parallel; a floating-point sum is still taken in row order (each entry's
-// term is broadcast to the wavefront in turn, all lanes adding the same
-// sequence), and outputs are compacted in row order by ballot, so the results
-// equal the thread-per-row kernels' bit for bit.
+// ---- a lane group per row: strength, direct interpolation, transpose -------------------
+// Each row gets a group of lanes sized to the level's rows (row_group: 8 on
+// the finest levels, whose rows hold about 7 entries, up to 32 on coarse
+// ones; a thread per row would make every load instruction of a wavefront
+// touch a cache line per lane).  Entries are loaded lane-parallel;
+// a floating-point sum is still taken in row order (each entry's term is
+// broadcast to the group in turn, all lanes adding the same sequence), and
+// outputs are compacted in row order by ballot, so the results equal those
+// of one thread walking the row, bit for bit.
 constexpr int WR = 64;
 constexpr int WR_ROWS = B / WR;
 
@@ -159,41 +104,63 @@ __device__ inline int below_count(uint64_t mask, int lane) {
     return __popcll(mask & ((1ull << lane) - 1ull));
 }
 
+// Lane groups of G lanes per row (G a power of two dividing 64): the
+// group's mask of a predicate (bit l: lane l of the group), and a value of
+// lane l of the group (l the same in all lanes of the group).
+template <int G>
+__device__ inline uint64_t gballot(bool p) {
+    const uint64_t b = __ballot(p);
+    if constexpr (G == 64) return b;
+    else return (b >> ((threadIdx.x & 63) & ~(G - 1))) & ((1ull << G) - 1ull);
+}
+template <int G>
+__device__ inline int32_t gbcast_i(int32_t v, int l) {
+    if constexpr (G == 64) return bcast_i(v, l);
+    else return __shfl(v, l, G);
+}
+template <int G>
+__device__ inline double gbcast_d(double v, int l) {
+    if constexpr (G == 64) return bcast_d(v, l);
+    else return __shfl(v, l, G);
+}
+
+template <int G>
 __device__ inline void row_sign_max_w(const int32_t* rowptr, const int32_t* col, const double* val, int32_t i,
                                       int lane, double* s_out, double* m_out) {
     const int32_t a = rowptr[i], e = rowptr[i + 1];
     double aii = 0.0;
     bool has = false;
-    for (int32_t q = a + lane; q < e; q += WR)
+    for (int32_t q = a + lane; q < e; q += G)
         if (col[q] == i) { aii = val[q]; has = true; }
-    const uint64_t hm = __ballot(has);
-    aii = hm ? bcast_d(aii, __ffsll((unsigned long long)hm) - 1) : 0.0;
+    const uint64_t hm = gballot<G>(has);
+    aii = hm ? gbcast_d<G>(aii, __ffsll((unsigned long long)hm) - 1) : 0.0;
     const double s = aii < 0.0 ? -1.0 : 1.0;
     double m = 0.0;
-    for (int32_t q = a + lane; q < e; q += WR)
+    for (int32_t q = a + lane; q < e; q += G)
         if (col[q] != i && -s * val[q] > m) m = -s * val[q];
 #pragma unroll
-    for (int d = WR / 2; d > 0; d >>= 1) m = fmax(m, __shfl_xor(m, d, WR));
+    for (int d = G / 2; d > 0; d >>= 1) m = fmax(m, __shfl_xor(m, d, G));
     *s_out = s;
     *m_out = m;
 }
 
+template <int G>
 __global__ void __launch_bounds__(B)
 k_strength_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
              const double* __restrict__ val, double theta, int32_t* __restrict__ cnt,
              const int32_t* __restrict__ Srowptr, int32_t* __restrict__ Scol) {
-    const int32_t i = blockIdx.x * WR_ROWS + threadIdx.x / WR;
-    const int lane = threadIdx.x % WR;
+    const int32_t i = blockIdx.x * (B / G) + threadIdx.x / G;
+    const int lane = threadIdx.x % G;
     if (i >= n) return;  // whole wavefront
     double s, m;
-    row_sign_max_w(rowptr, col, val, i, lane, &s, &m);
+    row_sign_max_w<G>(rowptr, col, val, i, lane, &s, &m);
     int32_t c = 0;
     const int32_t out = Scol ? Srowptr[i] : 0;
     if (m > 0.0) {
-        for (int32_t b = rowptr[i]; b < rowptr[i + 1]; b += WR) {
+        for (int32_t b = rowptr[i]; b < rowptr[i + 1]; b += G) {
             const int32_t q = b + lane;
             const bool strong = q < rowptr[i + 1] && col[q] != i && -s * val[q] >= theta * m;
-            const uint64_t mk = __ballot(strong);
+            const uint64_t mk = gballot<G>(strong);
             if (Scol && strong) Scol[out + c + below_count(mk, lane)] = col[q];
             c += __popcll(mk);
         }
@@ -201,16 +168,17 @@ k_strength_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
     if (cnt && lane == 0) cnt[i] = c;
 }
 
+template <int G>
 __global__ void __launch_bounds__(B)
 k_interp_count_w(int32_t n, const int32_t* __restrict__ Srp, const int32_t* __restrict__ Sc,
                  const int32_t* __restrict__ cf, int32_t* __restrict__ cnt) {
-    const int32_t i = blockIdx.x * WR_ROWS + threadIdx.x / WR;
-    const int lane = threadIdx.x % WR;
+    const int32_t i = blockIdx.x * (B / G) + threadIdx.x / G;
+    const int lane = threadIdx.x % G;
     if (i >= n) return;
     int32_t c = 0;
-    for (int32_t q = Srp[i] + lane; q < Srp[i + 1]; q += WR) c += cf[Sc[q]];
+    for (int32_t q = Srp[i] + lane; q < Srp[i + 1]; q += G) c += cf[Sc[q]];
 #pragma unroll
-    for (int d = WR / 2; d > 0; d >>= 1) c += __shfl_xor(c, d, WR);
+    for (int d = G / 2; d > 0; d >>= 1) c += __shfl_xor(c, d, G);
     if (lane == 0) cnt[i] = cf[i] ? 1 : c;
 }
 
@@ -225,14 +193,15 @@ __device__ inline bool in_sorted(const int32_t* Sc, int32_t a, int32_t e, int32_
     return lo < e && Sc[lo] == j;
 }
 
+template <int G>
 __global__ void __launch_bounds__(B)
 k_interp_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                 const double* __restrict__ val, const int32_t* __restrict__ Srp,
                 const int32_t* __restrict__ Sc, const int32_t* __restrict__ cf,
                 const int32_t* __restrict__ cmap, const int32_t* __restrict__ Prp,
                 int32_t* __restrict__ Pc, double* __restrict__ Pv) {
-    const int32_t i = blockIdx.x * WR_ROWS + threadIdx.x / WR;
-    const int lane = threadIdx.x % WR;
+    const int32_t i = blockIdx.x * (B / G) + threadIdx.x / G;
+    const int lane = threadIdx.x % G;
     if (i >= n) return;
     const int32_t q0 = Prp[i];
     if (cf[i]) {
@@ -243,24 +212,24 @@ k_interp_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __
     const int32_t a = rowptr[i], e = rowptr[i + 1], sa = Srp[i], se = Srp[i + 1];
     double aii = 0.0;
     bool has = false;
-    for (int32_t q = a + lane; q < e; q += WR)
+    for (int32_t q = a + lane; q < e; q += G)
         if (col[q] == i) { aii = val[q]; has = true; }
-    const uint64_t hm = __ballot(has);
-    aii = hm ? bcast_d(aii, __ffsll((unsigned long long)hm) - 1) : 0.0;
+    const uint64_t hm = gballot<G>(has);
+    aii = hm ? gbcast_d<G>(aii, __ffsll((unsigned long long)hm) - 1) : 0.0;
     const double s = aii < 0.0 ? -1.0 : 1.0;
     // the three sums in row order, exactly as one thread would take them
     double sum_all = 0.0, lump = 0.0, sum_p = 0.0;
-    for (int32_t b = a; b < e; b += WR) {
+    for (int32_t b = a; b < e; b += G) {
         const int32_t q = b + lane;
         const bool ok = q < e;
         const int32_t j = ok ? col[q] : -1;
         const double v = ok ? val[q] : 0.0;
         const bool sc = ok && j != i && cf[j] && in_sorted(Sc, sa, se, j);
-        const uint64_t scm = __ballot(sc);
-        const int len = min(WR, (int)(e - b));
+        const uint64_t scm = gballot<G>(sc);
+        const int len = min(G, (int)(e - b));
         for (int l = 0; l < len; ++l) {
-            const int32_t jl = bcast_i(j, l);
-            const double vl = bcast_d(v, l);
+            const int32_t jl = gbcast_i<G>(j, l);
+            const double vl = gbcast_d<G>(v, l);
             if (jl != i) {
                 if (s * vl < 0.0) sum_all += vl;
                 else lump += vl;
@@ -271,12 +240,12 @@ k_interp_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __
     const double alpha = sum_all / sum_p;
     const double dtil = aii + lump;
     int32_t c = 0;
-    for (int32_t b = a; b < e; b += WR) {
+    for (int32_t b = a; b < e; b += G) {
         const int32_t q = b + lane;
         const bool ok = q < e;
         const int32_t j = ok ? col[q] : -1;
         const bool sc = ok && j != i && cf[j] && in_sorted(Sc, sa, se, j);
-        const uint64_t scm = __ballot(sc);
+        const uint64_t scm = gballot<G>(sc);
         if (sc) {
             const int32_t pos = q0 + c + below_count(scm, lane);
             Pc[pos] = cmap[j];
@@ -286,30 +255,78 @@ k_interp_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __
     }
 }
 
+template <int G>
 __global__ void __launch_bounds__(B)
 k_col_count_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
               int32_t* __restrict__ cnt) {
-    const int32_t i = blockIdx.x * WR_ROWS + threadIdx.x / WR;
-    const int lane = threadIdx.x % WR;
+    const int32_t i = blockIdx.x * (B / G) + threadIdx.x / G;
+    const int lane = threadIdx.x % G;
     if (i >= n) return;
-    for (int32_t q = rowptr[i] + lane; q < rowptr[i + 1]; q += WR) atomicAdd(&cnt[col[q]], 1);
+    for (int32_t q = rowptr[i] + lane; q < rowptr[i + 1]; q += G) atomicAdd(&cnt[col[q]], 1);
 }
 
+template <int G>
 __global__ void __launch_bounds__(B)
 k_transpose_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                    const double* __restrict__ val, int32_t* __restrict__ cursor,
                    int32_t* __restrict__ Tcol, double* __restrict__ Tval) {
-    const int32_t i = blockIdx.x * WR_ROWS + threadIdx.x / WR;
-    const int lane = threadIdx.x % WR;
+    const int32_t i = blockIdx.x * (B / G) + threadIdx.x / G;
+    const int lane = threadIdx.x % G;
     if (i >= n) return;
-    for (int32_t q = rowptr[i] + lane; q < rowptr[i + 1]; q += WR) {
+    for (int32_t q = rowptr[i] + lane; q < rowptr[i + 1]; q += G) {
         const int32_t pos = atomicAdd(&cursor[col[q]], 1);
         Tcol[pos] = i;
         if (Tval) Tval[pos] = val[q];
     }
 }
 
+// Values of A^T on A's own pattern, for a square A whose pattern is
+// symmetric: entry (i, j) goes to the position of column i in row j (binary
+// search).  *asym is set when some (i, j) has no (j, i).
+template <int G>
+__global__ void __launch_bounds__(B)
+k_transpose_sym(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                const double* __restrict__ val, double* __restrict__ Tval, int32_t* __restrict__ asym) {
+    const int32_t i = blockIdx.x * (B / G) + threadIdx.x / G;
+    const int lane = threadIdx.x % G;
+    if (i >= n) return;
+    for (int32_t q = rowptr[i] + lane; q < rowptr[i + 1]; q += G) {
+        const int32_t j = col[q];
+        int32_t lo = rowptr[j], hi = rowptr[j + 1];
+        while (lo < hi) {
+            const int32_t mid = lo + (hi - lo) / 2;
+            if (col[mid] < i) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo < rowptr[j + 1] && col[lo] == i) Tval[lo] = val[q];
+        else *asym = 1;
+    }
+}
+
 static bool long_rows(int32_t n, int32_t nnz) { return n > 0 && (double)nnz / n >= WR_MIN_AVG; }
+
+// Lanes per row for the row kernels: the mean row length rounded up to a
+// power of two, at least 4 and at most 32 (a group then loads a row, or a
+// 32-entry piece of it, in one contiguous access; wider groups left most
+// lanes idle on the coarse levels' rows of 18-60 entries).
+static int row_group(int32_t n, int64_t nnz) {
+    const double avg = n > 0 ? (double)nnz / n : 1.0;
+    int g = 4;
+    while (g < avg && g < 32) g <<= 1;
+    return g;
+}
+
+// A row kernel templated on its lane-group size G, launched with the group
+// size g of row_group.
+#define TP_ROWS_LAUNCH(kernel, g, n, stream, ...)                                             \
+    do {                                                                                      \
+        switch (g) {                                                                          \
+        case 4: TP_LAUNCH(kernel<4>, cdiv((n), B / 4), B, 0, stream, __VA_ARGS__); break;     \
+        case 8: TP_LAUNCH(kernel<8>, cdiv((n), B / 8), B, 0, stream, __VA_ARGS__); break;     \
+        case 16: TP_LAUNCH(kernel<16>, cdiv((n), B / 16), B, 0, stream, __VA_ARGS__); break;  \
+        default: TP_LAUNCH(kernel<32>, cdiv((n), B / 32), B, 0, stream, __VA_ARGS__); break;  \
+        }                                                                                     \
+    } while (0)
 
 // T = A^T (m rows); values optional; rows sorted when `sorted`.  nnz is the
 // entry count or an upper bound of it: it only sizes the allocations (the
@@ -324,15 +341,10 @@ void transpose(const int32_t* rowptr, const int32_t* col, const double* val, int
     if (val) T.val.alloc(nnz, s);
     DBuf<int32_t> cursor(m + 1, s);
     TP_LAUNCH(k_fill_i32, cdiv(m + 1, B), B, 0, s, T.rowptr.p, 0, (int64_t)m + 1);
-    const bool w = long_rows(n, nnz);
-    if (n > 0) {
-        if (w) TP_LAUNCH(k_col_count_w, cdiv(n, WR_ROWS), B, 0, s, n, rowptr, col, T.rowptr.p);
-        else TP_LAUNCH(k_col_count, cdiv(n, B), B, 0, s, n, rowptr, col, T.rowptr.p);
-    }
+    const int g = row_group(n, nnz);
+    if (n > 0) TP_ROWS_LAUNCH(k_col_count_w, g, n, s, n, rowptr, col, T.rowptr.p);
     auto fill = [&](int32_t* tc, double* tv) {
-        if (n == 0) return;
-        if (w) TP_LAUNCH(k_transpose_fill_w, cdiv(n, WR_ROWS), B, 0, s, n, rowptr, col, val, cursor.p, tc, tv);
-        else TP_LAUNCH(k_transpose_fill, cdiv(n, B), B, 0, s, n, rowptr, col, val, cursor.p, tc, tv);
+        if (n > 0) TP_ROWS_LAUNCH(k_transpose_fill_w, g, n, s, n, rowptr, col, val, cursor.p, tc, tv);
     };
     scan_exclusive(T.rowptr.p, T.rowptr.p, m, s);
     TP_HIP(hipMemcpyAsync(cursor.p, T.rowptr.p, sizeof(int32_t) * (m + 1), hipMemcpyDeviceToDevice, s));
@@ -346,6 +358,30 @@ void transpose(const int32_t* rowptr, const int32_t* col, const double* val, int
     if (m > 0)
         TP_LAUNCH(k_sort_rows, std::min(m, 65536), 64, 0, s, m, T.rowptr.p, tcol.p,
                   val ? tval.p : nullptr, T.col.p, val ? T.val.p : nullptr);
+}
+
+// T = A^T (square A, values, sorted rows).  The finest operators share a
+// symmetric stencil pattern: when `try_sym`, A^T is first formed on A's own
+// pattern (no atomics, no sort); a pattern found asymmetric falls back to the
+// general transpose.
+static void transpose_square(const Csr& A, bool try_sym, Csr& T, hipStream_t s) {
+    if (try_sym && A.n > 0) {
+        T.n = T.m = A.n;
+        T.nnz = A.nnz;
+        T.rowptr.alloc(A.n + 1, s);
+        T.col.alloc(A.nnz, s);
+        T.val.alloc(A.nnz, s);
+        DBuf<int32_t> asym(1, s);
+        TP_LAUNCH(k_fill_i32, 1, B, 0, s, asym.p, 0, (int64_t)1);
+        TP_ROWS_LAUNCH(k_transpose_sym, row_group(A.n, A.nnz), A.n, s, A.n, A.rowptr.p, A.col.p, A.val.p, T.val.p,
+                       asym.p);
+        if (read_i32(asym.p, s) == 0) {
+            TP_HIP(hipMemcpyAsync(T.rowptr.p, A.rowptr.p, sizeof(int32_t) * (A.n + 1), hipMemcpyDeviceToDevice, s));
+            TP_HIP(hipMemcpyAsync(T.col.p, A.col.p, sizeof(int32_t) * A.nnz, hipMemcpyDeviceToDevice, s));
+            return;
+        }
+    }
+    transpose(A.rowptr.p, A.col.p, A.val.p, A.n, A.n, A.nnz, true, T, s);
 }
 
 // ---- PMIS -------------------------------------------------------------------------
@@ -399,8 +435,10 @@ k_pmis_select(int32_t n, uint64_t hseed, const int32_t* __restrict__ Srp, const 
     nxt[i] = isC ? (int8_t)1 : (int8_t)0;
 }
 
-// undecided points with a strong C dependence become F; count the rest
-// (one atomic per wavefront)
+// undecided points with a strong C dependence become F; *undecided is set
+// to 1 when some point stays undecided (a plain store by one lane of each
+// such wavefront: a same-address atomic per wavefront serialised across
+// the chip and cost up to 0.75 ms per round on 4M points)
 __global__ void __launch_bounds__(B)
 k_pmis_fmark(int32_t n, const int32_t* __restrict__ Srp, const int32_t* __restrict__ Sc,
              int8_t* st, int32_t* __restrict__ undecided) {
@@ -415,70 +453,14 @@ k_pmis_fmark(int32_t n, const int32_t* __restrict__ Srp, const int32_t* __restri
                 break;
             }
     }
-    const uint64_t m = __ballot(und);
-    if ((threadIdx.x & 63) == 0 && m) atomicAdd(undecided, (int32_t)__popcll(m));
+    const uint64_t m = __ballot(und);  // (all lanes take part)
+    if ((threadIdx.x & 63) == 0 && m) *undecided = 1;
 }
 
 __global__ void __launch_bounds__(B)
 k_cf_flags(int32_t n, const int8_t* __restrict__ st, int32_t* __restrict__ cf) {
     int32_t i = blockIdx.x * B + threadIdx.x;
     if (i < n) cf[i] = st[i] == 1 ? 1 : 0;
-}
-
-// ---- direct interpolation -------------------------------------------------------------
-__global__ void __launch_bounds__(B)
-k_interp_count(int32_t n, const int32_t* __restrict__ Srp, const int32_t* __restrict__ Sc,
-               const int32_t* __restrict__ cf, int32_t* __restrict__ cnt) {
-    int32_t i = blockIdx.x * B + threadIdx.x;
-    if (i >= n) return;
-    if (cf[i]) { cnt[i] = 1; return; }
-    int32_t c = 0;
-    for (int32_t q = Srp[i]; q < Srp[i + 1]; ++q) c += cf[Sc[q]];
-    cnt[i] = c;
-}
-
-__global__ void __launch_bounds__(B)
-k_interp_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-              const double* __restrict__ val, const int32_t* __restrict__ Srp,
-              const int32_t* __restrict__ Sc, const int32_t* __restrict__ cf,
-              const int32_t* __restrict__ cmap, const int32_t* __restrict__ Prp,
-              int32_t* __restrict__ Pc, double* __restrict__ Pv) {
-    int32_t i = blockIdx.x * B + threadIdx.x;
-    if (i >= n) return;
-    int32_t q = Prp[i];
-    if (cf[i]) { Pc[q] = cmap[i]; Pv[q] = 1.0; return; }
-    if (Prp[i + 1] == q) return;  // no strong C neighbour: empty row
-    double aii = 0.0;
-    for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
-        if (col[k] == i) aii = val[k];
-    double s = aii < 0.0 ? -1.0 : 1.0;
-    double sum_all = 0.0, lump = 0.0;
-    for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-        if (col[k] == i) continue;
-        double a = val[k];
-        if (s * a < 0.0) sum_all += a;
-        else lump += a;
-    }
-    double sum_p = 0.0;
-    int32_t k2 = Srp[i];
-    const int32_t se = Srp[i + 1];
-    for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-        int32_t j = col[k];
-        while (k2 < se && Sc[k2] < j) ++k2;
-        if (k2 < se && Sc[k2] == j && cf[j]) sum_p += val[k];
-    }
-    double alpha = sum_all / sum_p;
-    double dtil = aii + lump;
-    k2 = Srp[i];
-    for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-        int32_t j = col[k];
-        while (k2 < se && Sc[k2] < j) ++k2;
-        if (k2 < se && Sc[k2] == j && cf[j]) {
-            Pc[q] = cmap[j];
-            Pv[q] = -(alpha * val[k]) / dtil;
-            ++q;
-        }
-    }
 }
 
 // ---- extended+i interpolation -----------------------------------------------------------
@@ -2255,12 +2237,10 @@ static void copy_csr_in(Csr& A, int32_t n, const int32_t* rowptr, const int32_t*
 static void strength(const Csr& A, double theta, Csr& S, hipStream_t s) {
     S.n = S.m = A.n;
     S.rowptr.alloc(A.n + 1, s);
-    const bool w = long_rows(A.n, A.nnz);
+    const int g = row_group(A.n, A.nnz);
     auto pass = [&](int32_t* cnt, const int32_t* srp, int32_t* scol) {
         if (A.n == 0) return;
-        if (w) TP_LAUNCH(k_strength_w, cdiv(A.n, WR_ROWS), B, 0, s, A.n, A.rowptr.p, A.col.p, A.val.p, theta, cnt,
-                         srp, scol);
-        else TP_LAUNCH(k_strength, cdiv(A.n, B), B, 0, s, A.n, A.rowptr.p, A.col.p, A.val.p, theta, cnt, srp, scol);
+        TP_ROWS_LAUNCH(k_strength_w, g, A.n, s, A.n, A.rowptr.p, A.col.p, A.val.p, theta, cnt, srp, scol);
     };
     pass(S.rowptr.p, nullptr, nullptr);
     scan_exclusive(S.rowptr.p, S.rowptr.p, A.n, s);
@@ -2274,23 +2254,17 @@ static void direct_interp(const Csr& A, const Csr& S, const int32_t* cf, const i
     P.n = A.n;
     P.m = nc;
     P.rowptr.alloc(A.n + 1, s);
-    const bool w = long_rows(A.n, A.nnz);
-    if (A.n > 0) {
-        if (w) TP_LAUNCH(k_interp_count_w, cdiv(A.n, WR_ROWS), B, 0, s, A.n, S.rowptr.p, S.col.p, cf, P.rowptr.p);
-        else TP_LAUNCH(k_interp_count, cdiv(A.n, B), B, 0, s, A.n, S.rowptr.p, S.col.p, cf, P.rowptr.p);
-    }
+    const int g = row_group(A.n, A.nnz);
+    if (A.n > 0) TP_ROWS_LAUNCH(k_interp_count_w, g, A.n, s, A.n, S.rowptr.p, S.col.p, cf, P.rowptr.p);
     scan_exclusive(P.rowptr.p, P.rowptr.p, A.n, s);
     // an upper bound (an F row interpolates from its strong C neighbours, a
     // C row has one entry); the exact count is read once at the end of setup
     P.nnz = A.nnz;
     P.col.alloc(P.nnz, s);
     P.val.alloc(P.nnz, s);
-    if (A.n > 0) {
-        if (w) TP_LAUNCH(k_interp_fill_w, cdiv(A.n, WR_ROWS), B, 0, s, A.n, A.rowptr.p, A.col.p, A.val.p,
-                         S.rowptr.p, S.col.p, cf, cmap, P.rowptr.p, P.col.p, P.val.p);
-        else TP_LAUNCH(k_interp_fill, cdiv(A.n, B), B, 0, s, A.n, A.rowptr.p, A.col.p, A.val.p, S.rowptr.p,
-                       S.col.p, cf, cmap, P.rowptr.p, P.col.p, P.val.p);
-    }
+    if (A.n > 0)
+        TP_ROWS_LAUNCH(k_interp_fill_w, g, A.n, s, A.n, A.rowptr.p, A.col.p, A.val.p, S.rowptr.p, S.col.p, cf,
+                       cmap, P.rowptr.p, P.col.p, P.val.p);
 }
 
 // Extended+i weights of every row of A over its interpolatory set (row i of
@@ -2566,9 +2540,9 @@ static void setup(tp_amg* h, int32_t n, const int32_t* rowptr, const int32_t* co
         TP_LAUNCH(k_pmis_init, cdiv(A.n, B), B, 0, s, A.n, ST.rowptr.p, st.p);
         const uint64_t hseed = prm.seed ^ ((uint64_t)l << 40);
         // Rounds are idempotent once every point is decided, so the host
-        // reads the undecided count only after every third round.
+        // reads the undecided flag only after every third round.
         int round = 0;
-        TP_LAUNCH(k_fill_i32, 2, B, 0, s, undecided.p, 0, (int64_t)512);  // one counter per round
+        TP_LAUNCH(k_fill_i32, 2, B, 0, s, undecided.p, 0, (int64_t)512);  // one flag per round
         for (;; ++round) {
             if (round >= 510) fail(TP_ERR_NUMERIC, "PMIS did not finish in 510 rounds");
             TP_LAUNCH(k_pmis_select, cdiv(A.n, B), B, 0, s, A.n, hseed, S.rowptr.p, S.col.p, ST.rowptr.p,
@@ -2595,7 +2569,7 @@ static void setup(tp_amg* h, int32_t n, const int32_t* rowptr, const int32_t* co
         }
         if (prm.restriction == 1) {
             Csr At, St, Q;
-            transpose(A.rowptr.p, A.col.p, A.val.p, A.n, A.n, A.nnz, true, At, s);
+            transpose_square(A, l == 0, At, s);
             strength(At, prm.theta, St, s);
             if (prm.interp == 1) {
                 ext_interp(At, St, L.cf.p, cmap.p, nc, prm.interp_pmax, Q, L.Tq, sg_flag.p, s);
@@ -2895,7 +2869,7 @@ static void refresh_numeric(tp_amg* h, const double* val, hipStream_t s) {
                       L.P.rowptr.p, L.P.col.p, L.P.val.p);
         if (h->prm.restriction == 1) {
             Csr At, Q;
-            transpose(L.A.rowptr.p, L.A.col.p, L.A.val.p, n, n, L.A.nnz, true, At, s);
+            transpose_square(L.A, l == 0, At, s);
             transpose(L.R.rowptr.p, L.R.col.p, L.R.val.p, L.R.n, n, L.R.nnz, true, Q, s);  // pattern of R^T
             if (ext) ext_fill(At, L.Sq, L.Tq, L.cf.p, cmap.p, Q, h->prm.interp_pmax, 1, s);
             else
