@@ -703,23 +703,30 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
     const int32_t i = blockIdx.x * WR_ROWS + threadIdx.x / WR;
     const int lane = threadIdx.x % WR;
     if (i >= n) return;
-    const int32_t p0 = Prp[i];
-    if (cf[i]) {
+    // The loads are grouped by what they depend on, so that each group is
+    // one round trip: the row's extents; then its set, strong set and first
+    // WR entries; then those entries' points' C/F flags and row extents.
+    const int32_t p0 = Prp[i], ci = cf[i], ta = Trp[i], tb = Trp[i + 1], sa = Srp[i], sb = Srp[i + 1];
+    const int32_t a = rowptr[i], e = rowptr[i + 1];
+    if (ci) {
         if (lane == 0 && !refresh) {
             Pc[p0] = cmap[i];
             Pv[p0] = 1.0;
         }
         return;
     }
-    const int32_t* list = Tc + Trp[i];
-    const int32_t len = Trp[i + 1] - Trp[i];
+    const int32_t* list = Tc + ta;
+    const int32_t len = tb - ta;
     if (len == 0) return;
     if (len > EXT_SLOTS) {
         if (lane == 0) ext_row(i, rowptr, col, val, Srp, Sc, cf, cmap, Trp, Tc, Prp, Pc, Pv, wbuf, pmax, refresh);
         return;
     }
-    const int32_t* Si = Sc + Srp[i];
-    const int32_t slen = Srp[i + 1] - Srp[i];
+    const int32_t* Si = Sc + sa;
+    const int32_t slen = sb - sa;
+    const bool ok0 = a + lane < e;
+    const int32_t j0 = ok0 ? col[a + lane] : i;
+    const double v0 = ok0 ? val[a + lane] : 0.0;
     // the row's interpolatory set in LDS (binary searches of the den sums)
     __shared__ int32_t s_list[WR_ROWS][EXT_SLOTS];
     // one chunk of strong F neighbours: their rows (columns, then slot
@@ -743,18 +750,37 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
     if (si_lds)
         for (int32_t t = lane; t < slen; t += WR) s_si[wv][t] = Si[t];
     const int32_t* const si = si_lds ? s_si[wv] : Si;
+    // (j0 = i on lanes past the row: a valid index)
+    const int32_t cfj0 = cf[j0], kbj0 = rowptr[j0], kej0 = rowptr[j0 + 1];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // slot t = r * WR + lane lives in w[r] of its lane; its column
-    int32_t lc[EXT_NW];
+    // slot t = r * WR + lane lives in w[r] of its lane; its column, and that
+    // column's coarse index (used at the end)
+    int32_t lc[EXT_NW], lcm[EXT_NW];
 #pragma unroll
     for (int r = 0; r < EXT_NW; ++r) lc[r] = r * WR + lane < len ? sl[r * WR + lane] : -1;
-    const int32_t a = rowptr[i], e = rowptr[i + 1];
+#pragma unroll
+    for (int r = 0; r < EXT_NW; ++r) lcm[r] = lc[r] >= 0 ? cmap[lc[r]] : 0;
+    // entry b + lane of row i (the first WR are held in registers)
+    auto entry = [&](int32_t b, int32_t* j, double* v) {
+        if (b == a) {
+            *j = j0;
+            *v = v0;
+        } else {
+            const bool ok = b + lane < e;
+            *j = ok ? col[b + lane] : i;
+            *v = ok ? val[b + lane] : 0.0;
+        }
+    };
     double aii = 0.0;
     bool has = false;
-    for (int32_t q = a + lane; q < e; q += WR)
-        if (col[q] == i) { aii = val[q]; has = true; }
+    for (int32_t b = a; b < e; b += WR) {
+        int32_t j;
+        double v;
+        entry(b, &j, &v);
+        if (b + lane < e && j == i) { aii = v; has = true; }
+    }
     const uint64_t hm = __ballot(has);
     aii = hm ? bcast_d(aii, __ffsll((unsigned long long)hm) - 1) : 0.0;
     double at = aii;
@@ -762,19 +788,15 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
     // (0.0 + a_ij, placed by the entry's lane: a row holds a column once);
     // weak couplings outside the set are lumped into a~_ii in row order.
     for (int32_t b = a; b < e; b += WR) {
-        const int32_t q = b + lane;
-        const bool ok = q < e;
-        const int32_t j = ok ? col[q] : i;
-        const double v = ok ? val[q] : 0.0;
+        const bool ok = b + lane < e;
+        int32_t j;
+        double v;
+        entry(b, &j, &v);
         const int32_t pos = j != i ? find_sorted(sl, len, j) : -1;
         if (pos >= 0) s_w0[pos] = 0.0 + v;
         const bool lump = ok && j != i && pos < 0 && find_sorted(si, slen, j) < 0;
-        const uint64_t lm = __ballot(lump);
-        const int cnt = min(WR, (int)(e - b));
-        for (int l = 0; l < cnt; ++l) {
-            const double vl = bcast_d(v, l);
-            if ((lm >> l) & 1ull) at += vl;
-        }
+        // the lumped terms in lane (row) order
+        for (uint64_t lm = __ballot(lump); lm; lm &= lm - 1) at += bcast_d(v, __ffsll((unsigned long long)lm) - 1);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -828,12 +850,8 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
             const int32_t lcu = inr ? kc[u] : -1;
             const bool mem = inr && (lcu == i || find_sorted(sl, len, lcu) >= 0);
             const double h = mem ? opposite(kv[u], akk) : 0.0;
-            const uint64_t mm2 = __ballot(mem);
-            const int c = min(WR, (int)(kl - c0));
-            for (int tt = 0; tt < c; ++tt) {
-                const double ht = bcast_d(h, tt);
-                if ((mm2 >> tt) & 1ull) den += ht;
-            }
+            for (uint64_t mm2 = __ballot(mem); mm2; mm2 &= mm2 - 1)
+                den += bcast_d(h, __ffsll((unsigned long long)mm2) - 1);
         }
         if (den == 0.0) {
             at += aik;
@@ -849,12 +867,23 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
         if (ui >= 0) at += (aik * opposite(kv[ui], akk)) / den;
     };
     for (int32_t b = a; b < e; b += WR) {
-        const int32_t q = b + lane;
-        const bool ok = q < e;
-        const int32_t k0 = ok ? col[q] : i;
-        const bool sf = ok && k0 != i && find_sorted(si, slen, k0) >= 0 && !cf[k0];
-        const int32_t kb0 = sf ? rowptr[k0] : 0, ke0 = sf ? rowptr[k0 + 1] : 0;
-        const double aik0 = sf ? val[q] : 0.0;
+        const bool ok = b + lane < e;
+        int32_t k0;
+        double v;
+        entry(b, &k0, &v);
+        int32_t cfk, kbk, kek;
+        if (b == a) {
+            cfk = cfj0;
+            kbk = kbj0;
+            kek = kej0;
+        } else {
+            cfk = cf[k0];
+            kbk = rowptr[k0];
+            kek = rowptr[k0 + 1];
+        }
+        const bool sf = ok && k0 != i && !cfk && find_sorted(si, slen, k0) >= 0;
+        const int32_t kb0 = sf ? kbk : 0, ke0 = sf ? kek : 0;
+        const double aik0 = sf ? v : 0.0;
         const int32_t kl0 = ke0 - kb0;
         uint64_t m = __ballot(sf);
         while (m) {
@@ -958,7 +987,7 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
         for (int r = 0; r < EXT_NW; ++r) {
             const int32_t t = r * WR + lane;
             if (t < len) {
-                if (!refresh) Pc[p0 + t] = cmap[lc[r]];
+                if (!refresh) Pc[p0 + t] = lcm[r];
                 Pv[p0 + t] = w[r];
             }
         }
@@ -968,7 +997,7 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
     if (refresh) {
 #pragma unroll
         for (int r = 0; r < EXT_NW; ++r)
-            if (lc[r] >= 0 && find_sorted(Pc + p0, plen, cmap[lc[r]]) >= 0) selm |= 1u << r;
+            if (lc[r] >= 0 && find_sorted(Pc + p0, plen, lcm[r]) >= 0) selm |= 1u << r;
     }
     for (int round = 0; round < (refresh ? 0 : pmax); ++round) {
         double bm = -1.0;
@@ -1013,7 +1042,7 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
         const uint64_t km = __ballot(k);
         if (k) {
             const int32_t pos = below + __popcll(km & ((1ull << lane) - 1ull));
-            if (!refresh) Pc[p0 + pos] = cmap[lc[r]];
+            if (!refresh) Pc[p0 + pos] = lcm[r];
             Pv[p0 + pos] = kept != 0.0 ? w[r] * f : w[r];
         }
         below += __popcll(km);
