@@ -999,29 +999,35 @@ k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __res
         for (int r = 0; r < EXT_NW; ++r)
             if (lc[r] >= 0 && find_sorted(Pc + p0, plen, lcm[r]) >= 0) selm |= 1u << r;
     }
-    for (int round = 0; round < (refresh ? 0 : pmax); ++round) {
-        double bm = -1.0;
-        int32_t bt = INT32_MAX;
+    if (!refresh) {
+        // slot t is kept when fewer than pmax slots precede it in the order
+        // (|w| descending, then slot ascending) -- the slots that pmax rounds
+        // of an arg-max over that order would pick; each slot's rank is
+        // counted over the broadcast magnitudes of all slots
+        double aw[EXT_NW];
+        int32_t rank[EXT_NW];
 #pragma unroll
         for (int r = 0; r < EXT_NW; ++r) {
-            const int32_t t = r * WR + lane;
-            if (t < len && !((selm >> r) & 1u) && fabs(w[r]) > bm) {
-                bm = fabs(w[r]);
-                bt = t;
-            }
+            aw[r] = fabs(w[r]);
+            rank[r] = 0;
         }
 #pragma unroll
-        for (int d = WR / 2; d > 0; d >>= 1) {
-            const double om = __shfl_xor(bm, d, WR);
-            const int32_t ot = __shfl_xor(bt, d, WR);
-            if (om > bm || (om == bm && ot < bt)) {
-                bm = om;
-                bt = ot;
+        for (int r2 = 0; r2 < EXT_NW; ++r2) {
+            if (r2 * WR >= len) continue;  // (uniform)
+            const int cnt = min(WR, (int)(len - r2 * WR));
+            for (int l = 0; l < cnt; ++l) {
+                const double au = bcast_d(aw[r2], l);
+                const int32_t u = r2 * WR + l;
+#pragma unroll
+                for (int r = 0; r < EXT_NW; ++r) {
+                    if (r * WR >= len) continue;  // (uniform)
+                    if (au > aw[r] || (au == aw[r] && u < r * WR + lane)) ++rank[r];
+                }
             }
         }
 #pragma unroll
         for (int r = 0; r < EXT_NW; ++r)
-            if (bt == r * WR + lane) selm |= 1u << r;
+            if (r * WR + lane < len && rank[r] < pmax) selm |= 1u << r;
     }
     double all = 0.0, kept = 0.0;
     int32_t below = 0;  // kept slots before this lane's, register by register
