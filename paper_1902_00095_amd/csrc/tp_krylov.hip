@@ -53,6 +53,13 @@ struct tp_prec {
     int variant = 0;      // 0 lower, 1 upper, 2 full, 3 CPR
     tp::DBuf<double> cw, cb;  // CPR: first-stage pressure x1 (n) and the residual r - J x1 (2n)
     tp::DBuf<double> rs, zs;  // split work vectors (2n) for the interleaved entry point
+    // The Jacobian's stencil, for the sparse products with implied columns:
+    // st_nd offsets (column - row, ascending) from which every entry of the
+    // pattern is drawn, so that a row of st_nd entries holds all of them;
+    // st_nd = 0 when the pattern is not of that form (st_done: examined).
+    int32_t st_nd = 0;
+    int32_t st_off[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    bool st_done = false;
 };
 
 namespace tp {
@@ -150,6 +157,137 @@ k_block_spmv(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restric
         if (zcopy) {
             zcopy[i] = z[i];
             zcopy[n + i] = z[n + i];
+        }
+    }
+}
+
+// ---- the same products on a stencil pattern --------------------------------------------
+// Every entry's column is row + one of ND offsets (ascending), so a row of ND
+// entries holds them all and its columns need not be loaded.  A workgroup
+// takes ST_ROWS consecutive rows: it loads their values into LDS in one
+// coalesced sweep, then each thread sums its row in entry order (rows of
+// fewer entries, at the domain's faces, read their columns).
+constexpr int ST_ROWS = 256;
+struct StencilOffs {
+    int32_t off[8];
+};
+
+// stage the values of rows [i0, iend) (q0 = rp[i0], q1 = rp[iend], at most
+// ST_ROWS * ND of them) in s_a: every load is issued before the stores
+template <int ND>
+__device__ inline void stage_rows(const double* __restrict__ av, int32_t q0, int32_t q1, double* s_a) {
+    double v[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+        const int32_t q = q0 + (int32_t)threadIdx.x + k * ST_ROWS;
+        v[k] = q < q1 ? av[q] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+        const int32_t q = q0 + (int32_t)threadIdx.x + k * ST_ROWS;
+        if (q < q1) s_a[q - q0] = v[k];
+    }
+}
+
+template <typename To, int ND>
+__global__ void __launch_bounds__(ST_ROWS)
+k_spmv_sub_st(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+              const double* __restrict__ av, const double* __restrict__ x, const double* __restrict__ rhs,
+              To* __restrict__ out, StencilOffs st) {
+    __shared__ double s_a[ST_ROWS * ND];
+    const int32_t i0 = blockIdx.x * ST_ROWS, i = i0 + (int32_t)threadIdx.x;
+    const bool in = i < n;
+    // everything that does not wait for the staged values is loaded first
+    const int32_t q0 = rp[i0], q1 = rp[min(n, i0 + ST_ROWS)];
+    const int32_t a = in ? rp[i] : 0, e = in ? rp[i + 1] : 0;
+    const double r = in ? rhs[i] : 0.0;
+    double xv[ND];  // the stencil's x (a full row's; clamped indices elsewhere)
+#pragma unroll
+    for (int d = 0; d < ND; ++d) xv[d] = x[min(max(i + st.off[d], 0), n - 1)];
+    stage_rows<ND>(av, q0, q1, s_a);
+    __syncthreads();
+    if (!in) return;
+    double sum = 0.0;
+    if (e - a == ND) {
+#pragma unroll
+        for (int d = 0; d < ND; ++d) sum += s_a[a - q0 + d] * xv[d];
+    } else {
+        for (int32_t q = a; q < e; ++q) sum += s_a[q - q0] * x[ci[q]];
+    }
+    out[i] = (To)(r - sum);
+}
+
+// w = J z (split vectors), with b: w = b - J z; the pressure rows' two
+// blocks are staged first, then the temperature rows'
+template <int ND>
+__global__ void __launch_bounds__(ST_ROWS)
+k_block_spmv_st(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                const double* __restrict__ pp, const double* __restrict__ pT, const double* __restrict__ Tp,
+                const double* __restrict__ TT, const double* __restrict__ z, const double* __restrict__ b,
+                double* __restrict__ w, double* __restrict__ zcopy, StencilOffs st) {
+    __shared__ double s_a[ST_ROWS * ND], s_c[ST_ROWS * ND];
+    const int32_t i0 = blockIdx.x * ST_ROWS, i = i0 + (int32_t)threadIdx.x;
+    const int32_t q0 = rp[i0], q1 = rp[min(n, i0 + ST_ROWS)];
+    const bool in = i < n;
+    const int32_t a = in ? rp[i] : 0, e = in ? rp[i + 1] : 0;
+    const bool full = e - a == ND;
+    const double* zp = z;
+    const double* zT = z + n;
+    double za[ND], zc[ND];  // the stencil's z (a full row's; clamped indices elsewhere)
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        const int32_t j = min(max(i + st.off[d], 0), n - 1);
+        za[d] = zp[j];
+        zc[d] = zT[j];
+    }
+    double res[2];
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        if (half) __syncthreads();  // (the first half's values are read until here)
+        stage_rows<ND>(half ? Tp : pp, q0, q1, s_a);
+        stage_rows<ND>(half ? TT : pT, q0, q1, s_c);
+        __syncthreads();
+        double sum = 0.0;
+        if (in) {
+            if (full) {
+#pragma unroll
+                for (int d = 0; d < ND; ++d) sum += s_a[a - q0 + d] * za[d] + s_c[a - q0 + d] * zc[d];
+            } else {
+                for (int32_t q = a; q < e; ++q) {
+                    const int32_t j = ci[q];
+                    sum += s_a[q - q0] * zp[j] + s_c[q - q0] * zT[j];
+                }
+            }
+        }
+        res[half] = sum;
+    }
+    if (!in) return;
+    if (b) {
+        w[i] = b[i] - res[0];
+        w[n + i] = b[n + i] - res[1];
+    } else {
+        w[i] = res[0];
+        w[n + i] = res[1];
+    }
+    if (zcopy) {
+        zcopy[i] = z[i];
+        zcopy[n + i] = z[n + i];
+    }
+}
+
+// *bad = 1 when some entry's column - row is not among the nd offsets
+__global__ void __launch_bounds__(KB)
+k_stencil_check(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci, int32_t nd,
+                StencilOffs st, int32_t* __restrict__ bad) {
+    const int32_t i = blockIdx.x * KB + threadIdx.x;
+    if (i >= n) return;
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+        const int32_t o = ci[q] - i;
+        bool hit = false;
+        for (int d = 0; d < nd; ++d) hit |= o == st.off[d];
+        if (!hit) {
+            *bad = 1;
+            return;
         }
     }
 }
@@ -385,15 +523,92 @@ static void vsolve(tp_amg* h, const double* rhs, double* out, int32_t n, hipStre
     cast_s2d(n, x, out, es, s);
 }
 
+// The Jacobian's stencil offsets (tp_prec::st_nd), examined once per handle
+// before its first product: the longest of up to 1024 rows from the middle
+// of the grid (an interior cell when there is one) gives the candidate
+// offsets, and a check over the whole pattern confirms them.  Stencils of 5
+// (2-D) or 7 (3-D) offsets take the implied-column kernels.
+static void stencil_detect(tp_prec* P, hipStream_t s) {
+    P->st_done = true;
+    const tp_jacobian& J = P->J;
+    const int32_t n = J.n, i0 = n / 2, w = std::min(n - i0, 1024);
+    std::vector<int32_t> ext(w + 1);
+    TP_HIP(hipMemcpyAsync(ext.data(), J.rowptr + i0, sizeof(int32_t) * (w + 1), hipMemcpyDeviceToHost, s));
+    TP_HIP(hipStreamSynchronize(s));
+    int32_t i = i0, nd = 0;
+    for (int32_t k = 0; k < w; ++k)
+        if (ext[k + 1] - ext[k] > nd) {
+            nd = ext[k + 1] - ext[k];
+            i = i0 + k;
+        }
+    if (nd != 5 && nd != 7) return;
+    int32_t cols[8];
+    TP_HIP(hipMemcpyAsync(cols, J.col + ext[i - i0], sizeof(int32_t) * nd, hipMemcpyDeviceToHost, s));
+    TP_HIP(hipStreamSynchronize(s));
+    StencilOffs st{};
+    for (int d = 0; d < nd; ++d) st.off[d] = cols[d] - i;
+    DBuf<int32_t> bad(1, s);
+    TP_LAUNCH(k_zero_i32, 1, 1, 0, s, bad.p);
+    TP_LAUNCH(k_stencil_check, cdiv(n, KB), KB, 0, s, n, J.rowptr, J.col, nd, st, bad.p);
+    if (read_i32(bad.p, s)) return;
+    P->st_nd = nd;
+    for (int d = 0; d < nd; ++d) P->st_off[d] = st.off[d];
+}
+
+static StencilOffs stencil_of(const tp_prec* P) {
+    StencilOffs st{};
+    for (int d = 0; d < 8; ++d) st.off[d] = P->st_off[d];
+    return st;
+}
+
 // rhs - M x written in the storage precision of h's level-0 right-hand side
-static void sub_into_b(const tp_jacobian& J, const double* M, const double* x, const double* rhs, tp_amg* h,
+static void sub_into_b(const tp_prec* P, const double* M, const double* x, const double* rhs, tp_amg* h,
                        hipStream_t s) {
+    const tp_jacobian& J = P->J;
     const int32_t n = J.n;
     const int grid = cdiv((int64_t)n * JG, KB);
-    if (storage_bytes(h) == 4)
+    const bool f32 = storage_bytes(h) == 4;
+    if (P->st_nd == 7 || P->st_nd == 5) {
+        const int gs = cdiv(n, ST_ROWS);
+        const StencilOffs st = stencil_of(P);
+        if (P->st_nd == 7 && f32)
+            TP_LAUNCH((k_spmv_sub_st<float, 7>), gs, ST_ROWS, 0, s, n, J.rowptr, J.col, M, x, rhs,
+                      (float*)h->lev[0].b.p, st);
+        else if (P->st_nd == 7)
+            TP_LAUNCH((k_spmv_sub_st<double, 7>), gs, ST_ROWS, 0, s, n, J.rowptr, J.col, M, x, rhs,
+                      (double*)h->lev[0].b.p, st);
+        else if (f32)
+            TP_LAUNCH((k_spmv_sub_st<float, 5>), gs, ST_ROWS, 0, s, n, J.rowptr, J.col, M, x, rhs,
+                      (float*)h->lev[0].b.p, st);
+        else
+            TP_LAUNCH((k_spmv_sub_st<double, 5>), gs, ST_ROWS, 0, s, n, J.rowptr, J.col, M, x, rhs,
+                      (double*)h->lev[0].b.p, st);
+        return;
+    }
+    if (f32)
         TP_LAUNCH(k_spmv_sub<float>, grid, KB, 0, s, n, J.rowptr, J.col, M, x, rhs, (float*)h->lev[0].b.p);
     else
         TP_LAUNCH(k_spmv_sub<double>, grid, KB, 0, s, n, J.rowptr, J.col, M, x, rhs, (double*)h->lev[0].b.p);
+}
+
+// w = J z (or b - J z), zcopy <- z when given; the implied-column form when J
+// is the handle's own Jacobian and its stencil was found
+static void block_spmv(const tp_jacobian& J, const tp_prec* P, const double* z, const double* b, double* w,
+                       double* zcopy, hipStream_t s) {
+    const int32_t n = J.n;
+    const bool own = J.rowptr == P->J.rowptr && J.col == P->J.col;
+    if (own && (P->st_nd == 7 || P->st_nd == 5)) {
+        const int gs = cdiv(n, ST_ROWS);
+        if (P->st_nd == 7)
+            TP_LAUNCH(k_block_spmv_st<7>, gs, ST_ROWS, 0, s, n, J.rowptr, J.col, J.pp, J.pT, J.Tp, J.TT, z, b, w,
+                      zcopy, stencil_of(P));
+        else
+            TP_LAUNCH(k_block_spmv_st<5>, gs, ST_ROWS, 0, s, n, J.rowptr, J.col, J.pp, J.pT, J.Tp, J.TT, z, b, w,
+                      zcopy, stencil_of(P));
+        return;
+    }
+    TP_LAUNCH(k_block_spmv, cdiv((int64_t)n * JG, KB), KB, 0, s, n, J.rowptr, J.col, J.pp, J.pT, J.Tp, J.TT, z, b,
+              w, zcopy);
 }
 
 static void run_from_b(tp_amg* h, double* out, int32_t n, hipStream_t s) {
@@ -402,9 +617,11 @@ static void run_from_b(tp_amg* h, double* out, int32_t n, hipStream_t s) {
     if (x != out) cast_s2d(n, x, out, es, s);
 }
 
-// work vectors of the CPR form, allocated outside any capture
+// work vectors of the CPR form, allocated outside any capture, and the
+// stencil examined
 static void prec_buffers(tp_prec* M, hipStream_t s) {
     const int32_t n = M->J.n;
+    if (!M->st_done) stencil_detect(M, s);
     if (M->variant == 3 && M->cw.n != (size_t)n) {
         M->cw.alloc(n, s);
         M->cb.alloc(2 * (size_t)n, s);
@@ -431,15 +648,15 @@ void prec_apply_split(tp_prec* M, const double* r, double* z, hipStream_t s, dou
     }
     if (M->variant == 1) {
         vsolve(M->S, rT, zT, n, s);
-        sub_into_b(M->J, M->J.pT, zT, rp, M->pp, s);
+        sub_into_b(M, M->J.pT, zT, rp, M->pp, s);
         run_from_b(M->pp, zp, n, s);
         return;
     }
     vsolve(M->pp, rp, zp, n, s);                 // step 1
-    sub_into_b(M->J, M->J.Tp, zp, rT, M->S, s);  // step 2
+    sub_into_b(M, M->J.Tp, zp, rT, M->S, s);  // step 2
     run_from_b(M->S, zT, n, s);                  // step 3
     if (M->variant == 2) {
-        sub_into_b(M->J, M->J.pT, zT, rp, M->pp, s);  // step 4
+        sub_into_b(M, M->J.pT, zT, rp, M->pp, s);  // step 4
         run_from_b(M->pp, zp, n, s);                  // step 5
     }
 }
@@ -654,7 +871,6 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
     HostMail& mail = Gmres::host_mail();  // the calling thread's pinned mailbox
     const int gn = cdiv(n, KB);
     const int gN = cdiv(G.N, KB);
-    const int gJ = cdiv((int64_t)n * JG, KB);
     TP_LAUNCH(k_deinterleave, gn, KB, 0, s, n, b_il, G.b.p);
     TP_LAUNCH(k_deinterleave, gn, KB, 0, s, n, x_il, G.x.p);
     dots(G, 0, nullptr, G.b.p, 2, G.nrm2.p, s);
@@ -674,8 +890,7 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
         if (history) history[0] = 0.0;
         rel = est = 0.0;
     } else {
-        TP_LAUNCH(k_block_spmv, gJ, KB, 0, s, n, J.rowptr, J.col, J.pp, J.pT, J.Tp, J.TT, G.x.p, G.b.p, G.r.p,
-                  (double*)nullptr);
+        block_spmv(J, M, G.x.p, G.b.p, G.r.p, nullptr, s);
         dots(G, 0, nullptr, G.r.p, 2, G.nrm2.p, s);
         rel = std::sqrt(read_d(G.nrm2.p, mail, s)) / bnorm;
         est = rel;
@@ -698,12 +913,10 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
                 if (use_graph) {
                     // rin already holds v_j; the product kernel copies zout into Z_j
                     TP_HIP(hipGraphLaunch(graph_ensure(M, s, cnn_on), s));
-                    TP_LAUNCH(k_block_spmv, gJ, KB, 0, s, n, J.rowptr, J.col, J.pp, J.pT, J.Tp, J.TT, M->zout.p,
-                              (const double*)nullptr, G.w.p, zj);
+                    block_spmv(J, M, M->zout.p, nullptr, G.w.p, zj, s);
                 } else {
                     prec_apply_split(M, vj, zj, s);
-                    TP_LAUNCH(k_block_spmv, gJ, KB, 0, s, n, J.rowptr, J.col, J.pp, J.pT, J.Tp, J.TT, zj,
-                              (const double*)nullptr, G.w.p, (double*)nullptr);
+                    block_spmv(J, M, zj, nullptr, G.w.p, nullptr, s);
                 }
                 dots(G, j + 1, nullptr, G.w.p, 0, G.h1.p, s);
                 dots(G, j + 1, G.h1.p, G.w.p, 1, G.h2.p, s);
@@ -760,8 +973,7 @@ static int fgmres(const tp_jacobian& J, tp_prec* M, const double* b_il, double* 
             }
             TP_LAUNCH(k_hess_solve, 1, 1, 0, s, k, m, G.H.p, G.g.p, G.y.p);
             TP_LAUNCH(k_xupdate, gN, KB, 0, s, G.N, k, G.Z.p, G.y.p, G.x.p);
-            TP_LAUNCH(k_block_spmv, gJ, KB, 0, s, n, J.rowptr, J.col, J.pp, J.pT, J.Tp, J.TT, G.x.p, G.b.p,
-                      G.r.p, (double*)nullptr);
+            block_spmv(J, M, G.x.p, G.b.p, G.r.p, nullptr, s);
             dots(G, 0, nullptr, G.r.p, 2, G.nrm2.p, s);
             rel = std::sqrt(read_d(G.nrm2.p, mail, s)) / bnorm;
             ++restarts;
