@@ -30,6 +30,8 @@ struct Level {
     // of sb_rows consecutive rows whose products are staged in LDS (at most
     // sb_lds of them per block); sb_rows = 0 when the level does not use it.
     int sb_rows = 0, sb_lds = 0;
+    // the same form for the products with P and R (sbP_rows = 0: not used)
+    int sbP_rows = 0, sbP_lds = 0, sbR_rows = 0, sbR_lds = 0;
     // Diagonal (DIA) copy of A when its column offsets form a small set
     // (stencil levels): dia[d * n + i] = a(i, i + off[d]), zero outside.
     int ndia = 0;

@@ -1717,14 +1717,23 @@ static void spgemm(const Csr& A, const Csr& Bm, Csr& C, int32_t* flag, hipStream
 }
 
 // ---- l1 diagonal, precision copies ----------------------------------------------------
+// 1 / sum_j |a_ij| (0 for an empty or zero row), the sum in row order; a
+// lane group per row (row_group), each entry broadcast to the group in turn
+template <int G>
 __global__ void __launch_bounds__(B)
 k_l1_dinv(int32_t n, const int32_t* __restrict__ rowptr, const double* __restrict__ val,
           double* __restrict__ dinv) {
-    int32_t i = blockIdx.x * B + threadIdx.x;
+    const int32_t i = blockIdx.x * (B / G) + threadIdx.x / G;
+    const int lane = threadIdx.x % G;
     if (i >= n) return;
+    const int32_t a = rowptr[i], e = rowptr[i + 1];
     double d = 0.0;
-    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) d += fabs(val[q]);
-    dinv[i] = d > 0.0 ? 1.0 / d : 0.0;
+    for (int32_t b = a; b < e; b += G) {
+        const double v = b + lane < e ? fabs(val[b + lane]) : 0.0;
+        const int cnt = min(G, (int)(e - b));
+        for (int l = 0; l < cnt; ++l) d += gbcast_d<G>(v, l);
+    }
+    if (lane == 0) dinv[i] = d > 0.0 ? 1.0 / d : 0.0;
 }
 
 __global__ void __launch_bounds__(B)
@@ -2438,22 +2447,32 @@ k_block_nnz_max(int32_t n, const int32_t* __restrict__ rowptr, int32_t rb, int32
 // 256x256x64 hierarchies (18-60 entries a row), time per preconditioner
 // apply against the lane-group kernels: 64 rows -2.0% (FP32) / -1.4%
 // (FP64), 32 rows -1.2% / -1.5%, 128 rows -1.6% / 0, 256 rows +1.8% / +0.2%.
-static void try_stream(tp_amg* h, Level& L, hipStream_t s) {
-    const int32_t n = L.A.n;
-    L.sb_rows = L.sb_lds = 0;
-    if (L.ndia || n < 65536) return;
-    const int32_t cap = (int32_t)(48 * 1024 / storage_bytes(h));
+// The first block size of rbs whose blocks of rb consecutive rows of X hold at
+// most `cap` entries: its rows and that maximum (0, 0 when none fits).
+static void stream_blocks(const Csr& X, int32_t cap, std::initializer_list<int32_t> rbs, int* rows, int* lds,
+                          hipStream_t s) {
+    *rows = *lds = 0;
     DBuf<int32_t> mx(1, s);
-    for (int32_t rb : {64, 32}) {
+    for (int32_t rb : rbs) {
         TP_LAUNCH(k_fill_i32, 1, B, 0, s, mx.p, 0, (int64_t)1);
-        TP_LAUNCH(k_block_nnz_max, cdiv(cdiv(n, rb), B), B, 0, s, n, L.A.rowptr.p, rb, mx.p);
+        TP_LAUNCH(k_block_nnz_max, cdiv(cdiv(X.n, rb), B), B, 0, s, X.n, X.rowptr.p, rb, mx.p);
         const int32_t m = read_i32(mx.p, s);
         if (m <= cap) {
-            L.sb_rows = rb;
-            L.sb_lds = std::max(m, 1);
+            *rows = rb;
+            *lds = std::max(m, 1);
             return;
         }
     }
+}
+
+static void try_stream(tp_amg* h, Level& L, hipStream_t s) {
+    L.sb_rows = L.sb_lds = L.sbP_rows = L.sbP_lds = L.sbR_rows = L.sbR_lds = 0;
+    const int32_t cap = (int32_t)(48 * 1024 / storage_bytes(h));
+    if (!L.ndia && L.A.n >= 65536) stream_blocks(L.A, cap, {64, 32}, &L.sb_rows, &L.sb_lds, s);
+    // P's rows are short (a few entries), R's a few tens: blocks of a whole
+    // workgroup's rows
+    if (L.P.n >= 65536) stream_blocks(L.P, cap, {256, 128}, &L.sbP_rows, &L.sbP_lds, s);
+    if (L.R.n >= 65536) stream_blocks(L.R, cap, {256, 128, 64}, &L.sbR_rows, &L.sbR_lds, s);
 }
 
 static void try_dia(tp_amg* h, Level& L, hipStream_t s) {
@@ -2565,7 +2584,7 @@ static void setup(tp_amg* h, int32_t n, const int32_t* rowptr, const int32_t* co
         Level& L = h->lev[l];
         Csr& A = L.A;
         L.dinv.alloc(std::max(A.n, 1), s);
-        if (A.n > 0) TP_LAUNCH(k_l1_dinv, cdiv(A.n, B), B, 0, s, A.n, A.rowptr.p, A.val.p, L.dinv.p);
+        if (A.n > 0) TP_ROWS_LAUNCH(k_l1_dinv, row_group(A.n, A.nnz), A.n, s, A.n, A.rowptr.p, A.val.p, L.dinv.p);
         if (A.n <= prm.coarse_max || l + 1 >= prm.max_levels) break;
         Csr S, ST;
         strength(A, prm.theta, S, s);
@@ -2710,7 +2729,7 @@ static void refresh_fine(tp_amg* h, const double* val, hipStream_t s) {
     const int32_t n = L.A.n;
     const int64_t nnz = L.A.nnz;
     TP_HIP(hipMemcpyAsync(L.A.val.p, val, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
-    TP_LAUNCH(k_l1_dinv, cdiv(n, B), B, 0, s, n, L.A.rowptr.p, L.A.val.p, L.dinv.p);
+    TP_ROWS_LAUNCH(k_l1_dinv, row_group(n, nnz), n, s, n, L.A.rowptr.p, L.A.val.p, L.dinv.p);
     const int64_t nd_n = (int64_t)L.ndia * n;
     if (L.ndia) {
         DiaOffs o{};
@@ -2894,7 +2913,7 @@ static void refresh_numeric(tp_amg* h, const double* val, hipStream_t s) {
     for (int l = 0; l < nl; ++l) {
         Level& L = h->lev[l];
         const int32_t n = L.A.n;
-        if (n > 0) TP_LAUNCH(k_l1_dinv, cdiv(n, B), B, 0, s, n, L.A.rowptr.p, L.A.val.p, L.dinv.p);
+        if (n > 0) TP_ROWS_LAUNCH(k_l1_dinv, row_group(n, L.A.nnz), n, s, n, L.A.rowptr.p, L.A.val.p, L.dinv.p);
         if (l == nl - 1) break;
         DBuf<int32_t> cmap(n + 1, s);
         scan_exclusive(L.cf.p, cmap.p, n, s);

@@ -452,6 +452,15 @@ k_rows_stream(int32_t n, int32_t rb, const int32_t* __restrict__ rp, const int32
     const int32_t r0 = blockIdx.x * rb;
     const int32_t r1 = r0 + rb < n ? r0 + rb : n;
     const int32_t base = rp[r0], end = rp[r1];
+    // the thread's own row (its extent and vector entries), loaded before
+    // the products
+    const int32_t i = r0 + (int32_t)threadIdx.x;
+    const bool mine = (int32_t)threadIdx.x < rb && i < r1;
+    const int32_t qa = mine ? rp[i] : 0, qe = mine ? rp[i + 1] : 0;
+    const T bi = mine ? b[i] : T(0), xi = mine ? xin[i] : T(0);
+    const T di = mine && diag ? diag[i] : T(0);
+    const T dvi = mine && MODE == 0 ? dinv[i] : T(0);
+    const T dprev = mine && MODE == 0 && !first ? d[i] : T(0);
     // four entries a thread before any product is formed: their loads are in
     // flight together
     for (int32_t e0 = base + threadIdx.x; e0 < end; e0 += 4 * VB) {
@@ -470,20 +479,57 @@ k_rows_stream(int32_t n, int32_t rb, const int32_t* __restrict__ rp, const int32
         }
     }
     __syncthreads();
-    const int32_t i = r0 + (int32_t)threadIdx.x;
-    if ((int32_t)threadIdx.x >= rb || i >= r1) return;
+    if (!mine) return;
     T s = 0;
-    for (int32_t q = rp[i] - base, qe = rp[i + 1] - base; q < qe; ++q) s += prod[q];
-    const T bi = b[i], xi = xin[i];
-    if (diag) s += diag[i] * xi;
+    for (int32_t q = qa - base; q < qe - base; ++q) s += prod[q];
+    if (diag) s += di * xi;
     if (MODE == 1) {
         xout[i] = bi - s;
         return;
     }
-    const T r = dinv[i] * (bi - s);
-    const T dn = first ? r / theta : c1 * d[i] + c2 * r;
+    const T r = dvi * (bi - s);
+    const T dn = first ? r / theta : c1 * dprev + c2 * r;
     d[i] = dn;
     xout[i] = xi + dn;
+}
+
+// y = A x, or y += A x (add), in the row-block form of k_rows_stream: the
+// block's products in LDS, then one thread per row sums them in entry order
+// (the transfers P and R on large levels; rb <= VB)
+template <typename T>
+__global__ void __launch_bounds__(VB)
+k_spmv_stream(int32_t n, int32_t rb, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+              const T* __restrict__ av, const T* __restrict__ x, T* __restrict__ y, int add) {
+    extern __shared__ double s_raw[];  // (typed double for its alignment)
+    T* const prod = reinterpret_cast<T*>(s_raw);
+    const int32_t r0 = blockIdx.x * rb;
+    const int32_t r1 = r0 + rb < n ? r0 + rb : n;
+    const int32_t base = rp[r0], end = rp[r1];
+    // the thread's own row: its extent and y, loaded before the products
+    const int32_t i = r0 + (int32_t)threadIdx.x;
+    const bool mine = (int32_t)threadIdx.x < rb && i < r1;
+    const int32_t qa = mine ? rp[i] : 0, qe = mine ? rp[i + 1] : 0;
+    const T yi = mine && add ? y[i] : T(0);
+    for (int32_t e0 = base + threadIdx.x; e0 < end; e0 += 4 * VB) {
+        int32_t cc[4];
+        T aa[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int32_t e = e0 + u * VB;
+            cc[u] = e < end ? ci[e] : 0;
+            aa[u] = e < end ? av[e] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int32_t e = e0 + u * VB;
+            if (e < end) prod[e - base] = aa[u] * x[cc[u]];
+        }
+    }
+    __syncthreads();
+    if (!mine) return;
+    T sum = 0;
+    for (int32_t q = qa - base; q < qe - base; ++q) sum += prod[q];
+    y[i] = add ? yi + sum : sum;
 }
 
 // first sweep from a zero guess
@@ -791,14 +837,22 @@ static typename M::T* vcycle_level(tp_amg* h, int l, const typename M::T* b, hip
     }
     Level& Ln = h->lev[l + 1];
     T* bc = (T*)Ln.b.p;
-    TP_G_DISPATCH(L.gR, TP_LAUNCH((k_spmv<T, GG>), grid_rows(L.R.n, GG), VB, 0, s, L.R.n, L.R.rowptr.p,
-                                  L.R.col.p, LevelVals<M>::R(L), r, bc, 0));
+    if (L.sbR_rows)
+        TP_LAUNCH(k_spmv_stream<T>, cdiv(L.R.n, L.sbR_rows), VB, (size_t)L.sbR_lds * sizeof(T), s, L.R.n,
+                  L.sbR_rows, L.R.rowptr.p, L.R.col.p, LevelVals<M>::R(L), r, bc, 0);
+    else
+        TP_G_DISPATCH(L.gR, TP_LAUNCH((k_spmv<T, GG>), grid_rows(L.R.n, GG), VB, 0, s, L.R.n, L.R.rowptr.p,
+                                      L.R.col.p, LevelVals<M>::R(L), r, bc, 0));
     T* xc = vcycle_level<M>(h, l + 1, bc, s);
     // (prolongation stays a separate row-parallel pass: fusing it into the
     // first post-smoothing step recomputes P x_c for every neighbour and
     // turns the step latency-bound)
-    TP_G_DISPATCH(L.gP, TP_LAUNCH((k_spmv<T, GG>), grid_rows(n, GG), VB, 0, s, n, L.P.rowptr.p, L.P.col.p,
-                                  LevelVals<M>::P(L), xc, cur, 1));
+    if (L.sbP_rows)
+        TP_LAUNCH(k_spmv_stream<T>, cdiv(n, L.sbP_rows), VB, (size_t)L.sbP_lds * sizeof(T), s, n, L.sbP_rows,
+                  L.P.rowptr.p, L.P.col.p, LevelVals<M>::P(L), xc, cur, 1);
+    else
+        TP_G_DISPATCH(L.gP, TP_LAUNCH((k_spmv<T, GG>), grid_rows(n, GG), VB, 0, s, n, L.P.rowptr.p, L.P.col.p,
+                                      LevelVals<M>::P(L), xc, cur, 1));
     if (l == 0 && h->stop_before_post) return cur;
     if (l == 0 && h->cnn && h->cnn->enabled) {
         // learned post-smoother: r = b - A x; x += s * CNN(features(r))
