@@ -2835,43 +2835,132 @@ k_scatter_transpose(int32_t n, const int32_t* __restrict__ Xrp, const int32_t* _
     }
 }
 
-// C = A B on C's kept pattern: one thread per entry (its row by bisection of
-// C's row pointer), the products summed over A's row in ascending inner
-// index from zero, as the SpGEMM sums them.
+// C = A B on C's kept pattern.  A group of G lanes per output row i: the
+// row's output columns are staged in LDS; every product a_iq b_qc is placed
+// at M[p][q] (p the position of c in the row, found by binary search; +0.0
+// where row q of B lacks column p's), and each output entry sums its row of
+// M over q ascending from 0.0 -- the order in which the SpGEMM sums it (an
+// added +0.0 leaves a sum that is never -0.0 unchanged); the A entries are
+// taken in chunks whose part of M fits, each output entry's sum carried in a
+// register from chunk to chunk.  A row with more columns or A entries than
+// fit takes the form of one lane per output entry, which searches row q of B
+// for the entry's column in global memory.
+template <int G, int VM, int VU, int VLA>
 __global__ void __launch_bounds__(B)
-k_spgemm_values(int32_t n, int64_t nnz, const int32_t* __restrict__ Crp, const int32_t* __restrict__ Cc,
+k_spgemm_values(int32_t n, const int32_t* __restrict__ Crp, const int32_t* __restrict__ Cc,
                 double* __restrict__ Cv, const int32_t* __restrict__ Arp, const int32_t* __restrict__ Ac,
                 const double* __restrict__ Av, const int32_t* __restrict__ Brp,
                 const int32_t* __restrict__ Bc, const double* __restrict__ Bv) {
-    for (int64_t q = (int64_t)blockIdx.x * B + threadIdx.x; q < nnz; q += (int64_t)gridDim.x * B) {
-        int32_t lo = 0, hi = n;  // the row i with Crp[i] <= q < Crp[i + 1]
-        while (hi - lo > 1) {
-            const int32_t mid = lo + (hi - lo) / 2;
-            if (Crp[mid] <= q) lo = mid;
-            else hi = mid;
-        }
-        const int32_t i = lo, c = Cc[q];
-        double acc = 0.0;
-        for (int32_t kk = Arp[i]; kk < Arp[i + 1]; ++kk) {
-            const int32_t r = Ac[kk];
-            int32_t l2 = Brp[r], h2 = Brp[r + 1] - 1;
-            while (l2 <= h2) {
-                const int32_t mid = (l2 + h2) >> 1;
-                const int32_t v = Bc[mid];
-                if (v == c) { acc += Av[kk] * Bv[mid]; break; }
-                if (v < c) l2 = mid + 1;
-                else h2 = mid - 1;
+    constexpr int NG = B / G;
+    __shared__ double s_m[NG][VM];
+    __shared__ int32_t s_c[NG][VU];
+    __shared__ int32_t s_b0[NG][VLA], s_off[NG][VLA + 1];
+    __shared__ double s_av[NG][VLA];
+    const int g = threadIdx.x / G, lane = threadIdx.x % G;
+    const int32_t i = blockIdx.x * NG + g;
+    if (i >= n) return;  // (the whole group)
+    const int32_t a0 = Arp[i], la = Arp[i + 1] - a0, c0 = Crp[i], u = Crp[i + 1] - c0;
+    auto sync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    if (la > VLA || u > VU) {
+        for (int32_t p = lane; p < u; p += G) {
+            const int32_t c = Cc[c0 + p];
+            double acc = 0.0;
+            for (int32_t kk = a0; kk < a0 + la; ++kk) {
+                const int32_t r = Ac[kk];
+                int32_t l2 = Brp[r], h2 = Brp[r + 1] - 1;
+                while (l2 <= h2) {
+                    const int32_t mid = (l2 + h2) >> 1;
+                    const int32_t v = Bc[mid];
+                    if (v == c) { acc += Av[kk] * Bv[mid]; break; }
+                    if (v < c) l2 = mid + 1;
+                    else h2 = mid - 1;
+                }
             }
+            Cv[c0 + p] = acc;
         }
-        Cv[q] = acc;
+        return;
+    }
+    // the row's columns, and per A entry its B row and value with the
+    // products' offsets (a scan over the group, VLA / G entries a lane)
+    for (int32_t p = lane; p < u; p += G) s_c[g][p] = Cc[c0 + p];
+    int32_t carry = 0;
+    for (int32_t q0 = 0; q0 < la; q0 += G) {
+        const int32_t q = q0 + lane;
+        int32_t len = 0;
+        if (q < la) {
+            const int32_t r = Ac[a0 + q];
+            const int32_t b0 = Brp[r];
+            len = Brp[r + 1] - b0;
+            s_b0[g][q] = b0;
+            s_av[g][q] = Av[a0 + q];
+        }
+        int32_t inc = len;
+#pragma unroll
+        for (int d = 1; d < G; d <<= 1) {
+            const int32_t o = __shfl_up(inc, d, G);
+            if (lane >= d) inc += o;
+        }
+        if (q < la) s_off[g][q] = carry + inc - len;
+        carry += __shfl(inc, G - 1, G);
+    }
+    if (lane == 0) s_off[g][la] = carry;
+    constexpr int NE = VU / G;  // output entries a lane
+    double acc[NE];
+#pragma unroll
+    for (int j = 0; j < NE; ++j) acc[j] = 0.0;
+    const int32_t qc = u > 0 ? max(1, VM / u) : la;  // A entries a chunk
+    for (int32_t q0 = 0; q0 < la; q0 += qc) {
+        const int32_t q1 = min(la, q0 + qc), wq = q1 - q0;
+        for (int32_t m = lane; m < u * wq; m += G) s_m[g][m] = 0.0;
+        sync();
+        const int32_t e1 = s_off[g][q1];
+        for (int32_t e = s_off[g][q0] + lane; e < e1; e += G) {
+            int32_t lo = q0, hi = q1 - 1;  // the last A entry whose first product is <= e
+            while (lo < hi) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                if (s_off[g][mid] <= e) lo = mid;
+                else hi = mid - 1;
+            }
+            const int32_t src = s_b0[g][lo] + (e - s_off[g][lo]);
+            const int32_t c = Bc[src];
+            int32_t pl = 0, ph = u - 1;  // its output position
+            while (pl < ph) {
+                const int32_t mid = (pl + ph) >> 1;
+                if (s_c[g][mid] < c) pl = mid + 1;
+                else ph = mid;
+            }
+            if (s_c[g][pl] == c) s_m[g][pl * wq + (lo - q0)] = s_av[g][lo] * Bv[src];
+        }
+        sync();
+#pragma unroll
+        for (int j = 0; j < NE; ++j) {
+            const int32_t p = lane + j * G;
+            if (p < u)
+                for (int32_t q = 0; q < wq; ++q) acc[j] += s_m[g][p * wq + q];
+        }
+        sync();
+    }
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+        const int32_t p = lane + j * G;
+        if (p < u) Cv[c0 + p] = acc[j];
     }
 }
 
 static void spgemm_values(const Csr& A, const Csr& Bm, Csr& C, hipStream_t s) {
-    if (C.nnz == 0) return;
-    const int grid = (int)std::min<int64_t>(cdiv(C.nnz, B), 65536);
-    TP_LAUNCH(k_spgemm_values, grid, B, 0, s, C.n, (int64_t)C.nnz, C.rowptr.p, C.col.p, C.val.p, A.rowptr.p,
-              A.col.p, A.val.p, Bm.rowptr.p, Bm.col.p, Bm.val.p);
+    if (C.nnz == 0 || C.n == 0) return;
+    // products per output row, from the operands' mean row lengths
+    const double est = ((double)A.nnz / std::max(A.n, 1)) * ((double)Bm.nnz / std::max(Bm.n, 1));
+    if (est <= 48.0)
+        TP_LAUNCH((k_spgemm_values<16, 256, 64, 16>), cdiv(C.n, B / 16), B, 0, s, C.n, C.rowptr.p, C.col.p,
+                  C.val.p, A.rowptr.p, A.col.p, A.val.p, Bm.rowptr.p, Bm.col.p, Bm.val.p);
+    else
+        TP_LAUNCH((k_spgemm_values<64, 1024, 256, 64>), cdiv(C.n, B / 64), B, 0, s, C.n, C.rowptr.p, C.col.p,
+                  C.val.p, A.rowptr.p, A.col.p, A.val.p, Bm.rowptr.p, Bm.col.p, Bm.val.p);
 }
 
 // Everything a level derives from its values alone: the DIA copy and the
