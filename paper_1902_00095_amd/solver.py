@@ -135,6 +135,38 @@ def setup(J, cfg: SolveConfig, concurrent: bool = True, ilu=None):
     return out["pp"], out["S"], make(out["pp"], out["S"])
 
 
+def _refresh_pair(hier, J, cfg, refresh):
+    """Both hierarchies (or the pressure hierarchy and the ILU(0) factors)
+    refreshed for J at the same time, on two streams from two host threads,
+    as `setup` builds them; each refresh synchronises its own stream."""
+    import threading
+
+    import torch
+    s1, s2 = _side_streams()
+    ev = torch.cuda.Event()
+    ev.record()                       # J is complete on the current stream
+    s1.wait_event(ev)
+    s2.wait_event(ev)
+    err = []
+
+    def run(f):
+        try:
+            f()
+        except Exception as e:        # re-raised below
+            err.append(e)
+
+    if cfg.method == "cpr":
+        second = lambda: hier[1].refactor(J, stream=s2)
+    else:
+        second = lambda: refresh(hier[1], _schur_values(J, cfg), s2)
+    th = threading.Thread(target=run, args=(second,))
+    th.start()
+    run(lambda: refresh(hier[0], J.pp, s1))
+    th.join()
+    if err:
+        raise err[0]
+
+
 def solve(J, G, cfg: SolveConfig, history=False):
     """Newton step: J dx = -G.  Returns (dx, stats, (a_pp, a_S, M)); a_S is
     the ILU(0) handle for the CPR method."""
@@ -319,7 +351,8 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None, on_
     if mode not in (None, "fine", "numeric", "numeric_run"):
         raise ValueError(f"unknown reuse mode {ncfg.reuse!r}")
     reusable = mode is not None and (cfg.method == "cpr" or cfg.schur in ("T", "ATT"))
-    refresh = (lambda h, v: h.refresh_fine(v)) if mode == "fine" else (lambda h, v: h.refresh(v))
+    refresh = ((lambda h, v, st: h.refresh_fine(v, stream=st)) if mode == "fine"
+               else (lambda h, v, st: h.refresh(v, stream=st)))
     refreshes, base_its, rebuild = 0, None, False
     guard = LearnedGuard() if net is not None else None
     attached = False
@@ -350,11 +383,7 @@ def simulate(prob, cfg: SolveConfig, ncfg: NewtonConfig, net=None, log=None, on_
                 ts = time.perf_counter()
                 built = False
                 if hier is not None and reusable and (k > 0 or mode == "numeric_run") and not rebuild:
-                    refresh(hier[0], J.pp)
-                    if cfg.method == "cpr":
-                        hier[1].refactor(J)
-                    else:
-                        refresh(hier[1], _schur_values(J, cfg))
+                    _refresh_pair(hier, J, cfg, refresh)
                     refreshes += 1
                 else:
                     close(hier)
