@@ -252,6 +252,56 @@ def test_precond_matches_oracle(variant):
         assert relmax(zg[blk::2], zo[blk::2]) <= 1e-10, blk
 
 
+@pytest.mark.parametrize("case", ["W1", "W2s"])
+def test_products_on_a_pattern_that_is_not_a_stencil(case):
+    """The Jacobian products take the implied-column (stencil) form only when
+    every entry of the pattern is one of the stencil's offsets.  With one
+    long-range coupling added to all five blocks (cells 0 and n-1) the
+    check must reject the stencil: the preconditioner apply still equals the
+    oracle's (1e-10 per block), and FGMRES to rtol 1e-10 reaches the oracle
+    GMRES solution (1e-6 per block) in the same iterations (+-1)."""
+    say("not a stencil", case)
+    p = CASES[case]()
+    J0 = oracle.jacobian(p)
+    n = J0.n
+    rp0, ci0 = np.asarray(J0.rowptr), np.asarray(J0.col)
+    # (0, n-1) closes row 0 and (n-1, 0) opens row n-1; explicit zeros of
+    # the stencil stay in place
+    a1, a2 = rp0[1], rp0[n - 1]
+    rp = rp0.copy()
+    rp[1:] += 1
+    rp[n] += 1
+    ci = np.concatenate([ci0[:a1], [n - 1], ci0[a1:a2], [0], ci0[a2:]]).astype(np.int32)
+    vals = {}
+    for k in ("pp", "pT", "Tp", "TT", "S"):
+        v = np.asarray(getattr(J0, k))
+        e = -1e-6 * float(np.abs(v).mean())
+        vals[k] = np.concatenate([v[:a1], [e], v[a1:a2], [e], v[a2:]])
+    rp = rp.astype(np.int32)
+    assert len(ci) == len(ci0) + 2 and np.all(np.diff(ci[rp[0]:rp[1]]) > 0) and np.all(np.diff(ci[rp[n - 1]:]) > 0)
+    Jo = oracle.Jacobian(n, rp, ci, vals["pp"], vals["pT"], vals["Tp"], vals["TT"], vals["S"])
+    Jd = tps.Jacobian.from_host(n, rp, ci, vals["pp"], vals["pT"], vals["Tp"], vals["TT"], vals["S"])
+    p_pp, p_S = tps.AmgParams(restriction=0, coarse_max=SMALL), tps.AmgParams(restriction=1, coarse_max=SMALL)
+    ao_pp, ao_S = o_amg(n, rp, ci, vals["pp"], p_pp), o_amg(n, rp, ci, vals["S"], p_S)
+    ag_pp, ag_S = tps.AMG(Jd.rowptr, Jd.col, Jd.pp, p_pp), tps.AMG(Jd.rowptr, Jd.col, Jd.S, p_S)
+    M = tps.Precond(Jd, ag_pp, ag_S, "lower")
+    r = synth.random_rhs(3, 2 * n)
+    r[1::2] *= 1e5
+    zo = oracle.precond_apply(Jo, ao_pp, ao_S, r, "lower")
+    zg = np_(M.apply(dev(r)))
+    for blk in (0, 1):
+        assert relmax(zg[blk::2], zo[blk::2]) <= 1e-10, blk
+    b = -oracle.residual(p)
+    xo, io = oracle.gmres(Jo, ao_pp, ao_S, b, rtol=1e-10)
+    xg, sg = tps.fgmres_solve(Jd, M, dev(b), rtol=1e-10)
+    say(f"  iterations gpu {sg['iters']} oracle {io['iters']}")
+    assert io["converged"] and sg["converged"] and abs(sg["iters"] - io["iters"]) <= 1
+    xg = np_(xg)
+    for blk in (0, 1):
+        assert relmax(xg[blk::2], xo[blk::2]) <= 1e-6, blk
+    M.close(); ag_pp.close(); ag_S.close()
+
+
 @pytest.mark.parametrize("case,interp_pp", [("W1", 1), ("W2s", 1), ("W2g", 1), ("W4s", 1), ("W2s", 0), ("W4s", 0)])
 def test_fgmres_end_to_end(case, interp_pp):
     """GPU assembly + setup + FGMRES vs the oracle at the same rtol: the same
