@@ -183,6 +183,11 @@ def apply_numbers(S, system, cfg, net=None):
     ms = (_sync_time() - t0) * 1e3 / nrep
     vb = a_pp.vcycle_bytes() + a_S.vcycle_bytes()
     rep_ms, rep_bytes = a_S.time_fine_smoother(100)
+    # the same sweep with the 256 MB last-level cache evicted before every
+    # launch (a 1 GiB read pass), each launch timed alone
+    flush = torch.zeros(1 << 27, dtype=torch.float64, device="cuda")
+    fl_ms, _ = a_S.time_fine_smoother(20, flush=flush)
+    del flush
     if net is not None:
         a_S.attach(None, None)
     out = {"apply_ms": round(ms, 4), "vcycle_pair_bytes": int(vb),
@@ -190,6 +195,8 @@ def apply_numbers(S, system, cfg, net=None):
            "vcycle_pair_frac_of_8TBps": round(vb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
            "fine_sweep_replay_us": round(rep_ms * 1e3, 3),
            "fine_sweep_replay_GBps": round(rep_bytes / (rep_ms * 1e-3) / 1e9, 1),
+           "fine_sweep_llc_flushed_us": round(fl_ms * 1e3, 3),
+           "fine_sweep_llc_flushed_GBps": round(rep_bytes / (fl_ms * 1e-3) / 1e9, 1),
            "levels": [a_pp.nlev, a_S.nlev]}
     M.close(); a_pp.close(); a_S.close()
     return out
@@ -758,7 +765,14 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic(),
                      "bytes_per_launch": round(bpl), "mean_us": round(mean_us, 3), "launches": launches,
                      "timing": "HIP event pair stamped by every launch of the kernel in two solves of the "
-                               "timed form (both hierarchies' finest levels), on the solve stream"},
+                               "timed form (both hierarchies' finest levels), on the solve stream",
+                     # one sweep's working set (~218 MB) fits the 256 MB last-level cache, so
+                     # consecutive sweeps of a level are partly served from it; the same kernel
+                     # with that cache evicted before each launch:
+                     "llc_evicted": {"mean_us": vc["fp32_hierarchy"]["fine_sweep_llc_flushed_us"],
+                                     "achieved": vc["fp32_hierarchy"]["fine_sweep_llc_flushed_GBps"],
+                                     "frac": round(vc["fp32_hierarchy"]["fine_sweep_llc_flushed_GBps"]
+                                                   / HBM_PEAK_GBS, 4)}},
     }
     if not (sm["all_converged"] and s64["all_converged"]):
         line["error"] = "a timed solve did not converge"

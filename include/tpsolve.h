@@ -443,6 +443,15 @@ int amg_presmoothed_pair(tp_amg_t amg, const double* y, double* r, double* e, vo
  * hierarchy's work vectors; synchronises `stream`. */
 int amg_time_fine_smoother(tp_amg_t amg, int32_t reps, double* ms_per_launch,
                            double* bytes_per_launch, void* stream);
+/* The same sweep with the last-level cache evicted before every launch: each
+ * launch follows a read pass over `flush_buf` (device, `flush_doubles`
+ * doubles, caller-owned, finite values, left unchanged; make it several
+ * times the 256 MB cache) and is timed by an event pair of its own;
+ * ms_per_launch is the mean of those times.  Errors:
+ * TP_ERR_ARG (null, reps outside [1, 1000], empty buffer, one level).
+ * Synchronises `stream`. */
+int amg_time_fine_smoother_flushed(tp_amg_t amg, int32_t reps, double* flush_buf, int64_t flush_doubles,
+                                   double* ms_per_launch, double* bytes_per_launch, void* stream);
 /* enable (1) / disable (0) and reset the counters */
 int tp_timer_enable(int32_t on);
 /* totals since the last enable: launches, summed kernel milliseconds and

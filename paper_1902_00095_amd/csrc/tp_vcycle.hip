@@ -1000,8 +1000,21 @@ extern "C" int amg_cnn_loss_grad(tp_amg_t amg, const float* feat, const float* t
 }
 
 namespace tp {
+// a read pass over fl[0, n) that evicts the last-level cache and leaves it
+// holding clean lines (no write-back competes with the timed launch); the
+// store never happens for finite data and only keeps the loads
+__global__ void __launch_bounds__(VB)
+k_flush(int64_t n, double* __restrict__ fl) {
+    const int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x;
+    const double v = i < n ? fl[i] : 0.0;
+    if (v != v) fl[0] = 0.0;
+}
+
+// With fl (flush_n doubles): every launch follows a sweep of fl and is timed
+// by an event pair of its own; the mean of those times is returned.
 template <typename M>
-static double replay_fine_smoother(tp_amg* h, int reps, hipStream_t s, double* bytes) {
+static double replay_fine_smoother(tp_amg* h, int reps, hipStream_t s, double* bytes, double* fl = nullptr,
+                                   int64_t flush_n = 0) {
     using T = typename M::T;
     using V = typename M::V;
     Level& L = h->lev[0];
@@ -1019,10 +1032,21 @@ static double replay_fine_smoother(tp_amg* h, int reps, hipStream_t s, double* b
     hipEvent_t e0, e1;
     TP_HIP(hipEventCreate(&e0));
     TP_HIP(hipEventCreate(&e1));
+    std::vector<hipEvent_t> ev;  // (flushed: a pair per launch)
+    if (fl)
+        for (int k = 0; k < 2 * reps; ++k) {
+            hipEvent_t e;
+            TP_HIP(hipEventCreate(&e));
+            ev.push_back(e);
+        }
     TP_HIP(hipEventRecord(e0, s));
     for (int k = 0; k < reps; ++k) {
         T* in = (k & 1) ? xb : xa;
         T* out = (k & 1) ? xa : xb;
+        if (fl) {
+            TP_LAUNCH(k_flush, cdiv(flush_n, VB), VB, 0, s, flush_n, fl);
+            TP_HIP(hipEventRecord(ev[2 * k], s));
+        }
         if (L.ndia) {
             dia_cheb_step<T, V>(L, n, LevelVals<M>::D(L), dg, dv, b, in, out, d, 0, (T)theta, (T)c1, (T)c2, s,
                                 false, 0.0);
@@ -1031,11 +1055,21 @@ static double replay_fine_smoother(tp_amg* h, int reps, hipStream_t s, double* b
                                           L.A.col.p, LevelVals<M>::A(L), dg, dv, b, in, out, d, 0, (T)theta,
                                           (T)c1, (T)c2));
         }
+        if (fl) TP_HIP(hipEventRecord(ev[2 * k + 1], s));
     }
     TP_HIP(hipEventRecord(e1, s));
     TP_HIP(hipEventSynchronize(e1));
     float ms = 0.f;
     TP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (fl) {
+        ms = 0.f;
+        for (int k = 0; k < reps; ++k) {
+            float t = 0.f;
+            TP_HIP(hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]));
+            ms += t;
+        }
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
     TP_HIP(hipEventDestroy(e0));
     TP_HIP(hipEventDestroy(e1));
     *bytes = (L.ndia ? (double)L.ndia * n * vs : (double)L.A.nnz * (vs + 4) + 4.0 * (n + 1)) +
@@ -1054,6 +1088,25 @@ extern "C" int amg_time_fine_smoother(tp_amg_t amg, int32_t reps, double* ms_per
         *ms_per_launch = amg->prm.storage == 2   ? tp::replay_fine_smoother<tp::M16>(amg, reps, s, bytes_per_launch)
                          : amg->prm.storage == 1 ? tp::replay_fine_smoother<tp::M32>(amg, reps, s, bytes_per_launch)
                                                  : tp::replay_fine_smoother<tp::M64>(amg, reps, s, bytes_per_launch);
+    });
+    return TP_OK;
+}
+
+extern "C" int amg_time_fine_smoother_flushed(tp_amg_t amg, int32_t reps, double* flush_buf, int64_t flush_doubles,
+                                              double* ms_per_launch, double* bytes_per_launch, void* stream) {
+    TP_GUARD({
+        TP_CHECK_ARG(amg && flush_buf && ms_per_launch && bytes_per_launch,
+                     "amg_time_fine_smoother_flushed: null argument");
+        TP_CHECK_ARG(reps >= 1 && reps <= 1000, "amg_time_fine_smoother_flushed: reps out of range");
+        TP_CHECK_ARG(flush_doubles >= 1, "amg_time_fine_smoother_flushed: empty flush buffer");
+        TP_CHECK_ARG(amg->lev.size() >= 2, "amg_time_fine_smoother_flushed: needs at least two levels");
+        hipStream_t s = (hipStream_t)stream;
+        double* const fl = flush_buf;
+        const int64_t fn = flush_doubles;
+        *ms_per_launch =
+            amg->prm.storage == 2   ? tp::replay_fine_smoother<tp::M16>(amg, reps, s, bytes_per_launch, fl, fn)
+            : amg->prm.storage == 1 ? tp::replay_fine_smoother<tp::M32>(amg, reps, s, bytes_per_launch, fl, fn)
+                                    : tp::replay_fine_smoother<tp::M64>(amg, reps, s, bytes_per_launch, fl, fn);
     });
     return TP_OK;
 }

@@ -84,7 +84,7 @@ EXPORTS = ["tp_last_error", "tp_init", "tp_jacobian_sizes", "assemble_tpfa", "as
            "cnn_create", "cnn_get_params", "cnn_get_grad", "cnn_destroy", "cnn_forward", "cnn_loss_grad",
            "cnn_adam_step", "amg_attach_post_smoother", "amg_features", "amg_presmoothed_pair",
            "amg_cnn_loss_grad",
-           "amg_time_fine_smoother", "tp_timer_enable", "tp_timer_read"]
+           "amg_time_fine_smoother", "amg_time_fine_smoother_flushed", "tp_timer_enable", "tp_timer_read"]
 CNN_NPARAM = 3905
 
 _lib = None
@@ -325,10 +325,19 @@ class AMG:
                                    C.byref(r)))
         return n.value, a.value, p.value, r.value
 
-    def time_fine_smoother(self, reps=200, stream=None):
+    def time_fine_smoother(self, reps=200, stream=None, flush=None):
+        """(ms per launch, algorithmic bytes per launch) of the finest-level
+        sweep replayed back to back; with `flush` (a float64 device tensor),
+        each launch follows a pass over it that evicts the last-level cache
+        and is timed alone."""
         ms, b = C.c_double(), C.c_double()
-        _check(_lib.amg_time_fine_smoother(self.h, C.c_int32(reps), C.byref(ms), C.byref(b),
-                                           _stream(stream)))
+        if flush is None:
+            _check(_lib.amg_time_fine_smoother(self.h, C.c_int32(reps), C.byref(ms), C.byref(b),
+                                               _stream(stream)))
+        else:
+            _check(_lib.amg_time_fine_smoother_flushed(self.h, C.c_int32(reps), _ptr(flush),
+                                                       C.c_int64(flush.numel()), C.byref(ms), C.byref(b),
+                                                       _stream(stream)))
         return ms.value, b.value
 
     def level_format(self, l):

@@ -252,6 +252,28 @@ def test_precond_matches_oracle(variant):
         assert relmax(zg[blk::2], zo[blk::2]) <= 1e-10, blk
 
 
+def test_fine_sweep_timing_with_the_cache_evicted():
+    """The timing entry points of the finest-level sweep: back to back, and
+    with the last-level cache evicted before each launch (a pass over a
+    caller's buffer); both report the same algorithmic bytes, the evicted
+    launches take at least as long within timing noise, and the buffer (read
+    only) is left unchanged."""
+    import torch
+    say("fine sweep timing")
+    p = synth.make_problem("W2", grid=synth.Grid(48, 48, 24, 1, 1, 1))
+    Jo, Jd = _oracle_J_on_device(p)
+    h = tps.AMG(Jd.rowptr, Jd.col, Jd.S, tps.AmgParams(restriction=1, storage=1))
+    warm_ms, warm_b = h.time_fine_smoother(50)
+    buf = torch.zeros(1 << 22, dtype=torch.float64, device="cuda")
+    cold_ms, cold_b = h.time_fine_smoother(5, flush=buf)
+    say(f"  warm {warm_ms * 1e3:.2f} us, evicted {cold_ms * 1e3:.2f} us, {warm_b:.0f} B")
+    assert warm_b == cold_b > 0 and warm_ms > 0 and cold_ms >= 0.8 * warm_ms
+    assert float(buf.abs().max()) == 0.0
+    with pytest.raises(tps.TpError):
+        h.time_fine_smoother(0, flush=buf)
+    h.close()
+
+
 @pytest.mark.parametrize("case", ["W1", "W2s"])
 def test_products_on_a_pattern_that_is_not_a_stencil(case):
     """The Jacobian products take the implied-column (stencil) form only when
