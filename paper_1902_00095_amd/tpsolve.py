@@ -598,15 +598,27 @@ class Net:
             pass
 
 
+# Below this many cells the preconditioner apply is launch-bound and its
+# replay from a captured graph pays for the capture within a solve; above,
+# its kernels are long enough that launching them one by one costs nothing,
+# and a handle's first capture does not pay back (measured on 256x256x64: a
+# solve on a fresh handle, 8 iterations, 24.1 ms with the graph against
+# 23.6 ms without).
+GRAPH_MAX_CELLS = 1 << 20
+
+
 def fgmres_solve(J: Jacobian, M: Precond, b, x=None, rtol=1e-8, restart=30, maxit=1000,
-                 history=False, stag_ratio=0.95, graph=True, stream=None, atol=0.0, stag_window=2,
+                 history=False, stag_ratio=0.95, graph=None, stream=None, atol=0.0, stag_window=2,
                  ref_rate=0.0):
     """Solve J x = b; returns (x, stats dict).  x (tensor) is the initial
     guess when given and is overwritten.  graph: replay the preconditioner
-    apply from a captured HIP graph.  stag_ratio / stag_window / ref_rate:
-    the learned smoother's guards (see tp_krylov_params)."""
+    apply from a captured HIP graph (None: when J has fewer than
+    GRAPH_MAX_CELLS cells).  stag_ratio / stag_window / ref_rate: the learned
+    smoother's guards (see tp_krylov_params)."""
     torch = _torch()
     lib = load()
+    if graph is None:
+        graph = J.n < GRAPH_MAX_CELLS
     if x is None:
         x = torch.zeros_like(b)
     kp = _KParams(rtol, restart, maxit, stag_ratio, 1 if graph else 0, atol, stag_window, ref_rate)
