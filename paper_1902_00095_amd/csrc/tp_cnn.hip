@@ -249,9 +249,12 @@ k_cnn_l2(tp_grid g, const float* __restrict__ h, const float* __restrict__ w2, c
 //   registers.  relu(h) enters split in two BF16 parts (hi + lo, relative
 //   remainder <= 2^-18), taps in two blocks of 16 (27 used): four
 //   instructions per group.  H cells outside the grid get G = 0 (layer 2's
-//   zero padding).  G (27 x 1008 FP32) goes to LDS tap-major; after a
-//   barrier every thread sums its output cell's 27 taps in tap order.
-// LDS: 27.6 KB of features + 108.9 KB of G (one workgroup per CU).
+//   zero padding).  G goes to LDS tap-major, one block of 16 taps at a time
+//   (16 x 1008 FP32), into the space the features held (layer 1 is done by
+//   then: every wavefront keeps its groups' relu(h) in registers); after a
+//   barrier every thread adds its output cell's taps of the block, in tap
+//   order, to its sum.
+// LDS: max(27.6 KB of features, 64.5 KB of G) -- two workgroups per CU.
 // Feature sources: FS 0, eight FP32 channel planes (channel 0 already
 // scaled); FS 1, the attachment's BF16 static channels (8 per cell, slot 0
 // unused) and the unscaled channel-0 plane z, divided by scale[0] when
@@ -278,13 +281,15 @@ __device__ inline short4v bf16x4_bits(float a, float b, float c, float d) {
 }
 
 template <typename T, int FS>
-__global__ void __launch_bounds__(FU_T)
+__global__ void __launch_bounds__(FU_T) __attribute__((amdgpu_waves_per_eu(4)))  // two workgroups a CU
 k_cnn_fused(tp_grid g, const float* __restrict__ f, const uint16_t* __restrict__ fstat,
             const float* __restrict__ w1, const float* __restrict__ b1, const float* __restrict__ w2,
             const float* __restrict__ b2, float* __restrict__ out, T* __restrict__ x,
             const float* __restrict__ scale, int32_t* __restrict__ bad) {
-    __shared__ bf16x8 s_f[FFC];
-    __shared__ float s_g[CNN_NT * FGN];
+    constexpr int FBYTES = FFC * (int)sizeof(bf16x8), GBYTES = 16 * FGN * (int)sizeof(float);
+    __shared__ __attribute__((aligned(16))) unsigned char s_raw[FBYTES > GBYTES ? FBYTES : GBYTES];
+    bf16x8* const s_f = reinterpret_cast<bf16x8*>(s_raw);  // features (layer 1)
+    float* const s_g = reinterpret_cast<float*>(s_raw);     // then one tap block of G
     const int32_t n = g.nx * g.ny * g.nz;
     const int32_t tx = (g.nx + FT - 1) / FT, ty = (g.ny + FT - 1) / FT, tz = (g.nz + FT - 1) / FT;
     const int32_t ntiles = tx * ty * tz;
@@ -339,8 +344,16 @@ k_cnn_fused(tp_grid g, const float* __restrict__ f, const uint16_t* __restrict__
 #pragma unroll
     for (int r = 0; r < 4; ++r) bias[r] = b1[4 * q + r];
     __syncthreads();
-#pragma unroll 1
-    for (int grp = wv; grp < FGROUPS; grp += FU_T / 64) {
+    // layer 1 on this wavefront's groups: relu(h) split in two BF16 parts,
+    // kept in registers (the features' LDS space is reused for G below)
+    constexpr int FW = FU_T / 64;                   // wavefronts
+    constexpr int KG = (FGROUPS + FW - 1) / FW;     // groups a wavefront
+    short4v bh[KG], bl[KG];
+#pragma unroll
+    for (int k = 0; k < KG; ++k) {
+        const int grp = wv + FW * k;
+        bh[k] = bl[k] = short4v{0, 0, 0, 0};
+        if (grp >= FGROUPS) continue;
         const int hl = 16 * grp + col;             // this lane's H cell
         const bool real = hl < FHC;
         const int hx = hl % FH, hy = (hl / FH) % FH, hz = hl / (FH * FH);
@@ -360,28 +373,39 @@ k_cnn_fused(tp_grid g, const float* __restrict__ f, const uint16_t* __restrict__
             hi[e] = bf16_round(v);
             lo[e] = bf16_round(v - hi[e]);
         }
-        const short4v bh = bf16x4_bits(hi[0], hi[1], hi[2], hi[3]);
-        const short4v bl = bf16x4_bits(lo[0], lo[1], lo[2], lo[3]);
-#pragma unroll
-        for (int blk = 0; blk < 2; ++blk) {
-            float4v gt = {0.f, 0.f, 0.f, 0.f};
-            gt = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[blk], bh, gt, 0, 0, 0);
-            gt = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[blk], bl, gt, 0, 0, 0);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int t = 16 * blk + 4 * q + e;  // D[m = tap][n = cell] at lane n + 16 (m / 4)
-                if (t < CNN_NT) s_g[t * FGN + 16 * grp + col] = gt[e];
-            }
-        }
+        bh[k] = bf16x4_bits(hi[0], hi[1], hi[2], hi[3]);
+        bl[k] = bf16x4_bits(lo[0], lo[1], lo[2], lo[3]);
     }
-    __syncthreads();
     const int lx = threadIdx.x % FT, ly = (threadIdx.x / FT) % FT, lz = threadIdx.x / (FT * FT);
     const int32_t xi = x0 + lx, yi = y0 + ly, zi = z0 + lz;
-    if (xi >= g.nx || yi >= g.ny || zi >= g.nz) return;
+    const bool mine = xi < g.nx && yi < g.ny && zi < g.nz;
     const int hb = (lz * FH + ly) * FH + lx;  // H index of tap (-1,-1,-1)
     float o = b2[0];
 #pragma unroll
-    for (int t = 0; t < CNN_NT; ++t) o += s_g[t * FGN + hb + h_tap(t)];
+    for (int blk = 0; blk < 2; ++blk) {
+        __syncthreads();  // (the features, then the previous block, are read until here)
+#pragma unroll
+        for (int k = 0; k < KG; ++k) {
+            const int grp = wv + FW * k;
+            if (grp >= FGROUPS) continue;
+            float4v gt = {0.f, 0.f, 0.f, 0.f};
+            gt = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[blk], bh[k], gt, 0, 0, 0);
+            gt = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[blk], bl[k], gt, 0, 0, 0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int tl = 4 * q + e;  // D[m = tap][n = cell] at lane n + 16 (m / 4)
+                if (16 * blk + tl < CNN_NT) s_g[tl * FGN + 16 * grp + col] = gt[e];
+            }
+        }
+        __syncthreads();
+        if (mine)
+#pragma unroll
+            for (int tl = 0; tl < 16; ++tl) {
+                const int t = 16 * blk + tl;
+                if (t < CNN_NT) o += s_g[tl * FGN + hb + h_tap(t)];
+            }
+    }
+    if (!mine) return;
     const int64_t i = xi + (int64_t)g.nx * (yi + (int64_t)g.ny * zi);
     if (out) out[i] = o;
     if (x) {
