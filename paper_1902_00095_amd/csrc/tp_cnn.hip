@@ -260,6 +260,7 @@ k_cnn_l2(tp_grid g, const float* __restrict__ h, const float* __restrict__ w2, c
 // unused) and the unscaled channel-0 plane z, divided by scale[0] when
 // staged (the same FP32 division as the planar path).
 typedef __attribute__((__vector_size__(4 * sizeof(short)))) short short4v;
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 constexpr int FT = 8;                 // output tile edge
 constexpr int FH = FT + 2, FF = FT + 4;
 constexpr int FHC = FH * FH * FH;     // 1000 H cells
@@ -300,25 +301,7 @@ k_cnn_fused(tp_grid g, const float* __restrict__ f, const uint16_t* __restrict__
     if (ntiles % 8 == 0) tile = (blockIdx.x % 8) * (ntiles / 8) + blockIdx.x / 8;
     const int32_t bz = tile / (tx * ty), by = (tile / tx) % ty, bx = tile % tx;
     const int32_t x0 = bx * FT, y0 = by * FT, z0 = bz * FT;
-    const float inv_s = FS == 1 ? scale[0] : 1.f;
-    for (int r = threadIdx.x; r < FFC; r += FU_T) {
-        const int fz = r / (FF * FF), fy = (r / FF) % FF, fx = r % FF;
-        const int32_t cx = x0 + fx - 2, cy = y0 + fy - 2, cz = z0 + fz - 2;
-        const bool in = cx >= 0 && cy >= 0 && cz >= 0 && cx < g.nx && cy < g.ny && cz < g.nz;
-        const int64_t cell = cx + (int64_t)g.nx * (cy + (int64_t)g.ny * cz);
-        bf16x8 v{};
-        if (in) {
-            if (FS == 0) {
-#pragma unroll
-                for (int c = 0; c < CNN_CIN; ++c) v[c] = (__bf16)bf16_round(f[(int64_t)c * n + cell]);
-            } else {
-                v = *reinterpret_cast<const bf16x8*>(fstat + 8 * cell);
-                const float z = f[cell];
-                v[0] = (__bf16)bf16_round(inv_s > 0.f ? z / inv_s : 0.f);
-            }
-        }
-        s_f[r] = v;
-    }
+    // weight fragments first: their loads overlap the staging's
     const int lane = threadIdx.x & 63, q = lane >> 4, col = lane & 15, wv = threadIdx.x >> 6;
     bf16x8 a[MF_KS];
     int ftoff[MF_KS];
@@ -326,9 +309,11 @@ k_cnn_fused(tp_grid g, const float* __restrict__ f, const uint16_t* __restrict__
     for (int st = 0; st < MF_KS; ++st) {
         const int t = 4 * st + q;
 #pragma unroll
-        for (int c = 0; c < CNN_CIN; ++c)
-            a[st][c] = (__bf16)(t < CNN_NT ? w1[col * MF_K + c * CNN_NT + t] : 0.f);
-        ftoff[st] = t < CNN_NT ? f_tap(t) : -1;
+        for (int c = 0; c < CNN_CIN; ++c) {  // (padded taps load a real one, then take 0)
+            const float w = w1[col * MF_K + c * CNN_NT + min(t, CNN_NT - 1)];
+            a[st][c] = (__bf16)(t < CNN_NT ? w : 0.f);
+        }
+        ftoff[st] = t < CNN_NT ? f_tap(t) : 0;  // the padded tap reads a real cell, times zero weights
     }
     // W2^T tap blocks: A[m = tap - 16 blk][k = channel] at lane m + 16 (k / 4), element k % 4
     short4v a2[2];
@@ -337,12 +322,69 @@ k_cnn_fused(tp_grid g, const float* __restrict__ f, const uint16_t* __restrict__
         const int t = 16 * blk + col;
         float w[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) w[e] = t < CNN_NT ? w2[(4 * q + e) * CNN_NT + t] : 0.f;
+        for (int e = 0; e < 4; ++e) {
+            const float v = w2[(4 * q + e) * CNN_NT + min(t, CNN_NT - 1)];
+            w[e] = t < CNN_NT ? v : 0.f;
+        }
         a2[blk] = bf16x4_bits(w[0], w[1], w[2], w[3]);
     }
     float4v bias;
 #pragma unroll
     for (int r = 0; r < 4; ++r) bias[r] = b1[4 * q + r];
+    const float inv_s = FS == 1 ? scale[0] : 1.f;
+    // staging: a thread's cells (at most FR) are loaded all at once, then
+    // converted and stored (one round trip to memory instead of FR); a cell
+    // outside the grid loads cell 0 and takes zeros (no masked, serialised loads)
+    constexpr int FR = (FFC + FU_T - 1) / FU_T;
+    bool fin[FR];
+    int64_t fcell[FR];
+#pragma unroll
+    for (int k = 0; k < FR; ++k) {
+        const int r = threadIdx.x + k * FU_T;
+        const int fz = r / (FF * FF), fy = (r / FF) % FF, fx = r % FF;
+        const int32_t cx = x0 + fx - 2, cy = y0 + fy - 2, cz = z0 + fz - 2;
+        fin[k] = r < FFC && cx >= 0 && cy >= 0 && cz >= 0 && cx < g.nx && cy < g.ny && cz < g.nz;
+        fcell[k] = fin[k] ? cx + (int64_t)g.nx * (cy + (int64_t)g.ny * cz) : 0;
+    }
+    if (FS == 0) {
+        float fv[FR][CNN_CIN];
+#pragma unroll
+        for (int k = 0; k < FR; ++k)
+#pragma unroll
+            for (int c = 0; c < CNN_CIN; ++c) fv[k][c] = f[(int64_t)c * n + fcell[k]];
+#pragma unroll
+        for (int k = 0; k < FR; ++k) {
+            const int r = threadIdx.x + k * FU_T;
+            bf16x8 v{};
+#pragma unroll
+            for (int c = 0; c < CNN_CIN; ++c) v[c] = (__bf16)(fin[k] ? fv[k][c] : 0.f);  // nearest even
+            if (r < FFC) s_f[r] = v;
+        }
+    } else {
+        bf16x8 sv[FR];
+        float zv[FR];
+#pragma unroll
+        for (int k = 0; k < FR; ++k) {
+            sv[k] = *reinterpret_cast<const bf16x8*>(fstat + 8 * fcell[k]);
+            zv[k] = f[fcell[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < FR; ++k) {
+            const int r = threadIdx.x + k * FU_T;
+            bf16x8 v = fin[k] ? sv[k] : bf16x8{};
+            v[0] = (__bf16)(fin[k] && inv_s > 0.f ? zv[k] / inv_s : 0.f);
+            if (r < FFC) s_f[r] = v;
+        }
+    }
+    // this thread's output cell, and what its update reads, loaded now
+    const int lx = threadIdx.x % FT, ly = (threadIdx.x / FT) % FT, lz = threadIdx.x / (FT * FT);
+    const int32_t xi = x0 + lx, yi = y0 + ly, zi = z0 + lz;
+    const bool mine = xi < g.nx && yi < g.ny && zi < g.nz;
+    const int hb = (lz * FH + ly) * FH + lx;  // H index of tap (-1,-1,-1)
+    const int64_t i = mine ? xi + (int64_t)g.nx * (yi + (int64_t)g.ny * zi) : 0;
+    float o = b2[0];
+    const T xold = x && mine ? x[i] : T(0);
+    const float sc = x ? scale[0] : 0.f;
     __syncthreads();
     // layer 1 on this wavefront's groups: relu(h) split in two BF16 parts,
     // kept in registers (the features' LDS space is reused for G below)
@@ -361,26 +403,21 @@ k_cnn_fused(tp_grid g, const float* __restrict__ f, const uint16_t* __restrict__
         float4v acc = bias;
 #pragma unroll
         for (int st = 0; st < MF_KS; ++st) {
-            bf16x8 b = ftoff[st] < 0 ? bf16x8{} : s_f[fb + ftoff[st]];
+            const bf16x8 b = s_f[fb + ftoff[st]];
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[st], b, acc, 0, 0, 0);
         }
         const int32_t cx = x0 + hx - 1, cy = y0 + hy - 1, cz = z0 + hz - 1;
-        const bool live = real && cx >= 0 && cy >= 0 && cz >= 0 && cx < g.nx && cy < g.ny && cz < g.nz;
-        float hi[4], lo[4];
+        const bool live = real & (cx >= 0) & (cy >= 0) & (cz >= 0) & (cx < g.nx) & (cy < g.ny) & (cz < g.nz);
+        bf16x4 hi, lo;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const float v = live && acc[e] > 0.f ? acc[e] : 0.f;
-            hi[e] = bf16_round(v);
-            lo[e] = bf16_round(v - hi[e]);
+            const float v = live & (acc[e] > 0.f) ? acc[e] : 0.f;
+            hi[e] = (__bf16)v;                   // round to nearest even
+            lo[e] = (__bf16)(v - (float)hi[e]);  // v - hi is exact in FP32
         }
-        bh[k] = bf16x4_bits(hi[0], hi[1], hi[2], hi[3]);
-        bl[k] = bf16x4_bits(lo[0], lo[1], lo[2], lo[3]);
+        bh[k] = __builtin_bit_cast(short4v, hi);
+        bl[k] = __builtin_bit_cast(short4v, lo);
     }
-    const int lx = threadIdx.x % FT, ly = (threadIdx.x / FT) % FT, lz = threadIdx.x / (FT * FT);
-    const int32_t xi = x0 + lx, yi = y0 + ly, zi = z0 + lz;
-    const bool mine = xi < g.nx && yi < g.ny && zi < g.nz;
-    const int hb = (lz * FH + ly) * FH + lx;  // H index of tap (-1,-1,-1)
-    float o = b2[0];
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk) {
         __syncthreads();  // (the features, then the previous block, are read until here)
@@ -393,8 +430,8 @@ k_cnn_fused(tp_grid g, const float* __restrict__ f, const uint16_t* __restrict__
             gt = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[blk], bl[k], gt, 0, 0, 0);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int tl = 4 * q + e;  // D[m = tap][n = cell] at lane n + 16 (m / 4)
-                if (16 * blk + tl < CNN_NT) s_g[tl * FGN + 16 * grp + col] = gt[e];
+                // D[m = tap][n = cell] at lane n + 16 (m / 4); rows past the last tap are never read
+                s_g[(4 * q + e) * FGN + 16 * grp + col] = gt[e];
             }
         }
         __syncthreads();
@@ -406,11 +443,10 @@ k_cnn_fused(tp_grid g, const float* __restrict__ f, const uint16_t* __restrict__
             }
     }
     if (!mine) return;
-    const int64_t i = xi + (int64_t)g.nx * (yi + (int64_t)g.ny * zi);
     if (out) out[i] = o;
     if (x) {
         if (!isfinite(o)) *bad = 1;
-        else x[i] = x[i] + (T)(scale[0] * o);
+        else x[i] = xold + (T)(sc * o);
     }
 }
 
