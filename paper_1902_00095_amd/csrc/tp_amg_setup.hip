@@ -685,16 +685,22 @@ k_ext_fill(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restr
 // row's frozen columns instead and writes values only.
 constexpr int EXT_NW = 4;
 constexpr int EXT_SLOTS = WR * EXT_NW;
-// Chunk sizes: LDS per workgroup stays near 32 KB, so that occupancy is
-// set by registers (measured: 512-entry chunks were 25% slower on the
-// 256x256x64 pressure hierarchy's first coarse level, for the occupancy
-// they cost).
-constexpr int EXT_EC = 256;  // staged neighbour-row entries per chunk
+// Chunk sizes: LDS per workgroup stays near 26 KB, so that six workgroups
+// fit a CU, and the kernel is compiled for six wavefronts a SIMD (80
+// registers; the row loops are latency-bound).  Measured on the 256x256x64
+// pressure hierarchy (ms a setup): 4 wavefronts, 256-entry chunks, 9.4; 5
+// wavefronts 8.3; 6 wavefronts with 192-entry chunks and strength rows up to
+// 128 staged 8.0, with 128-entry chunks 8.4, 160-entry chunks 9.5 (five
+// workgroups fit); 512-entry chunks were 25% slower than 256.  The term
+// matrix holds a whole row's slots (a chunk always takes its first
+// neighbour, and the slots' starting sums live there too): EXT_TC >= EXT_SLOTS.
+constexpr int EXT_EC = 192;  // staged neighbour-row entries per chunk
 constexpr int EXT_TC = 256;  // entries of the chunk's term matrix (neighbours x slots)
+static_assert(EXT_TC >= EXT_SLOTS, "the term matrix must hold one neighbour's row of slots");
 constexpr int EXT_KC = 16;   // neighbours per chunk
-constexpr int EXT_SI = 256;  // strength rows up to this long are staged in LDS
+constexpr int EXT_SI = 128;  // strength rows up to this long are staged in LDS
 
-__global__ void __launch_bounds__(B)
+__global__ void __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(6)))
 k_ext_fill_w(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
              const double* __restrict__ val, const int32_t* __restrict__ Srp, const int32_t* __restrict__ Sc,
              const int32_t* __restrict__ cf, const int32_t* __restrict__ cmap, const int32_t* __restrict__ Trp,
@@ -1291,8 +1297,10 @@ __device__ inline void lg_insert(int32_t* tab, int32_t c, int lg, int32_t mask, 
     }
 }
 
+// (six workgroups a CU: the LDS allows six, and 80 registers a lane keep
+// the numeric pass unspilled; 16% faster than the five that 92 registers gave)
 template <bool NUMERIC>
-__global__ void __launch_bounds__(LG_T)
+__global__ void __launch_bounds__(LG_T) __attribute__((amdgpu_waves_per_eu(6)))
 k_spgemm_long(const int32_t* __restrict__ rows, const int32_t* __restrict__ nrows,
               const int32_t* __restrict__ Arp, const int32_t* __restrict__ Ac, const double* __restrict__ Av,
               const int32_t* __restrict__ Brp, const int32_t* __restrict__ Bc, const double* __restrict__ Bv,
