@@ -155,6 +155,57 @@ def test_amg_setup_bit_exact_on_identical_input(case, which, restr, interp, pmax
             say(f"  level {l}: n={Lo['n']} bitwise-equal A values {exact:.4f}")
 
 
+def _long_row_laplacian(n, seed):
+    """A weighted graph Laplacian (diagonally dominant M-matrix) whose rows
+    hold about 90 to 320 entries: every point couples to 8-200 random others
+    (symmetrised), weights uniform in [0.1, 1]."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    deg = rng.integers(8, 200, n)
+    r = np.repeat(np.arange(n), deg)
+    c = np.concatenate([rng.choice(n, size=d, replace=False) for d in deg])
+    keep = r != c
+    W = sp.coo_matrix((rng.uniform(0.1, 1.0, keep.sum()), (r[keep], c[keep])), shape=(n, n)).tocsr()
+    W = W + W.T
+    W.sum_duplicates()
+    A = (sp.diags(np.asarray(W.sum(axis=1)).ravel() * 1.01 + 0.01) - W).tocsr()
+    A.sort_indices()
+    return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data
+
+
+@pytest.mark.parametrize("pmax", [0, 4])
+def test_ext_interp_on_long_rows_matches_oracle(pmax):
+    """Extended+i interpolation where the weights kernel leaves its LDS
+    staging: strength rows longer than it stages (here most are), strong
+    neighbours' rows longer than one chunk (read in place), interpolatory
+    sets of up to ~80 slots (several per lane).  The GPU hierarchy equals the
+    oracle's: splits and patterns bit-exact, values within 1e-13."""
+    import torch
+    say("ext+i long rows", pmax)
+    n = 2500
+    rp, c, v = _long_row_laplacian(n, 6)
+    lens = np.diff(rp)
+    assert lens.mean() > 150 and (lens > 192).sum() > n // 4
+    prm = tps.AmgParams(coarse_max=SMALL, interp=1, interp_pmax=pmax)
+    ho = o_amg(n, rp, c, v, prm)
+    hg = tps.AMG(dev(rp, torch.int32), dev(c, torch.int32), dev(v), prm)
+    assert hg.nlev == ho.nlev >= 2
+    for l in range(ho.nlev):
+        Lo, Lg = ho.level(l), hg.level(l)
+        assert np.array_equal(np_(Lg["A_rowptr"]), Lo["A_rowptr"]) and np.array_equal(np_(Lg["A_col"]), Lo["A_col"])
+        assert relmax(np_(Lg["A_val"]), Lo["A_val"]) <= 1e-13, l
+        if l < ho.nlev - 1:
+            assert np.array_equal(np_(Lg["cf"]), Lo["cf"]), l
+            for k in ("P_rowptr", "P_col", "R_rowptr", "R_col"):
+                assert np.array_equal(np_(Lg[k]), Lo[k]), (l, k)
+            assert relmax(np_(Lg["P_val"]), Lo["P_val"]) <= 1e-13, l
+            if l == 0:
+                plen = np.diff(Lo["P_rowptr"])
+                say(f"  level 0: P rows up to {plen.max()} entries, {(plen > 64).sum()} above 64")
+                assert pmax or plen.max() > 64
+    hg.close()
+
+
 @pytest.mark.parametrize("case", ["W2s", "W4s"])
 def test_oracle_coarsening_on_gpu_levels(case):
     """The oracle's PMIS on each GPU level matrix reproduces the GPU split
