@@ -1480,7 +1480,9 @@ k_spgemm_long(const int32_t* __restrict__ rows, const int32_t* __restrict__ nrow
 // Crp[i], their count to cnt[i].  Other rows are appended to a list for the
 // long-row kernels.  Products with long rows (coarse levels, the Galerkin product)
 // take 64-lane groups with room for 256 products; the fine-level A P takes
-// 16 lanes, 128 products.  Both give the same values, in the same order.
+// 16 lanes, 128 products, or 64 when the mean product count is at most 24
+// (half the LDS: eight wavefronts a SIMD instead of five).  All give the same
+// values, in the same order.
 // The keys need c < 2^31 / SR_MAX (the caller sends every row of a wider B
 // to the long-row kernels).
 constexpr int SR_T = 256;
@@ -1661,11 +1663,12 @@ static void spgemm(const Csr& A, const Csr& Bm, Csr& C, int32_t* flag, hipStream
     // (host sizes: exact for level operators, upper bounds for P and R)
     const double est = ((double)A.nnz / std::max(A.n, 1)) * ((double)Bm.nnz / std::max(Bm.n, 1));
     const bool wide = est >= 64.0;
+    const bool narrow = est <= 24.0;  // rows of a few short B rows: 64 product slots
     // the short kernels' sort keys hold a column in 23 bits, and their
     // staging offsets (at most SR_MAX a row) are 32-bit; otherwise every row
     // takes the long-row kernels
     const bool keys_fit =
-        Bm.m < (1 << 23) && (int64_t)A.n * (wide ? 256 : 128) < ((int64_t)1 << 31);
+        Bm.m < (1 << 23) && (int64_t)A.n * (wide ? 256 : narrow ? 64 : 128) < ((int64_t)1 << 31);
     const bool all_long = !keys_fit;
     // Short rows in one pass: each writes its sorted distinct columns and
     // values to a staging area at its product-count offset and its count to
@@ -1677,6 +1680,8 @@ static void spgemm(const Csr& A, const Csr& Bm, Csr& C, int32_t* flag, hipStream
             TP_LAUNCH(k_fill_i32, cdiv(A.n, B), B, 0, s, ubp.p, 0, (int64_t)A.n);
         else if (wide)
             TP_LAUNCH((k_spgemm_ub<64, 256>), cdiv(A.n, B), B, 0, s, A.n, A.rowptr.p, A.col.p, Bm.rowptr.p, ubp.p);
+        else if (narrow)
+            TP_LAUNCH((k_spgemm_ub<16, 64>), cdiv(A.n, B), B, 0, s, A.n, A.rowptr.p, A.col.p, Bm.rowptr.p, ubp.p);
         else
             TP_LAUNCH((k_spgemm_ub<16, 128>), cdiv(A.n, B), B, 0, s, A.n, A.rowptr.p, A.col.p, Bm.rowptr.p, ubp.p);
     }
@@ -1692,6 +1697,10 @@ static void spgemm(const Csr& A, const Csr& Bm, Csr& C, int32_t* flag, hipStream
             TP_LAUNCH(k_iota_i32, cdiv(A.n, B), B, 0, s, A.n, long_rows.p, nlong.p);
         else if (wide)
             TP_LAUNCH((k_spgemm_short<64, 256>), cdiv(A.n, SR_T / 64), SR_T, 0, s, A.n, A.rowptr.p, A.col.p,
+                      A.val.p, Bm.rowptr.p, Bm.col.p, Bm.val.p, C.rowptr.p, (const int32_t*)ubp.p, Tc.p, Tv.p,
+                      long_rows.p, nlong.p);
+        else if (narrow)
+            TP_LAUNCH((k_spgemm_short<16, 64>), cdiv(A.n, SR_T / 16), SR_T, 0, s, A.n, A.rowptr.p, A.col.p,
                       A.val.p, Bm.rowptr.p, Bm.col.p, Bm.val.p, C.rowptr.p, (const int32_t*)ubp.p, Tc.p, Tv.p,
                       long_rows.p, nlong.p);
         else
