@@ -182,6 +182,19 @@ def apply_numbers(S, system, cfg, net=None):
         M.apply(b, z)
     ms = (_sync_time() - t0) * 1e3 / nrep
     vb = a_pp.vcycle_bytes() + a_S.vcycle_bytes()
+    # the two V-cycles alone, back to back, each on its field's right-hand
+    # side with its FP64 interface (the apply above adds A_Tp z_p, the split
+    # and the join of the interleaved vectors)
+    bp, bT = b[0::2].contiguous(), b[1::2].contiguous()
+    xp, xT = torch.empty_like(bp), torch.empty_like(bT)
+    for _ in range(3):
+        a_pp.vcycle(bp, xp)
+        a_S.vcycle(bT, xT)
+    t0 = _sync_time()
+    for _ in range(nrep):
+        a_pp.vcycle(bp, xp)
+        a_S.vcycle(bT, xT)
+    cyc_ms = (_sync_time() - t0) * 1e3 / nrep
     rep_ms, rep_bytes = a_S.time_fine_smoother(100)
     # the same sweep with the 256 MB last-level cache evicted before every
     # launch (a 1 GiB read pass), each launch timed alone
@@ -193,6 +206,9 @@ def apply_numbers(S, system, cfg, net=None):
     out = {"apply_ms": round(ms, 4), "vcycle_pair_bytes": int(vb),
            "vcycle_pair_GBps": round(vb / (ms * 1e-3) / 1e9, 1),
            "vcycle_pair_frac_of_8TBps": round(vb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "vcycles_alone_ms": round(cyc_ms, 4),
+           "vcycles_alone_GBps": round(vb / (cyc_ms * 1e-3) / 1e9, 1),
+           "vcycles_alone_frac_of_8TBps": round(vb / (cyc_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
            "fine_sweep_replay_us": round(rep_ms * 1e3, 3),
            "fine_sweep_replay_GBps": round(rep_bytes / (rep_ms * 1e-3) / 1e9, 1),
            "fine_sweep_llc_flushed_us": round(fl_ms * 1e3, 3),
