@@ -167,7 +167,8 @@ def _block_err(x, ref):
 # ---- V-cycle throughput -----------------------------------------------------------------------
 def apply_numbers(S, system, cfg, net=None):
     """Preconditioner apply time and algorithmic GB/s of its two V-cycles on one
-    Newton system, and the finest-level Chebyshev step replayed back to back."""
+    Newton system (over the apply, and over the two cycles timed alone), and
+    the finest-level Chebyshev step replayed back to back."""
     import torch
     _, _, (a_pp, a_S, M) = S.run(system, cfg, net, keep=True)
     if net is not None:
