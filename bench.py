@@ -636,6 +636,70 @@ def paper_studies():
     return out
 
 
+SETUP_REPS = 4
+SETUP_NAMES = {"pp": "pressure (A_pp, extended+i interpolation)", "S": "Schur (S~_T, Petrov-Galerkin)"}
+
+
+def setup_study(which):
+    """One hierarchy's AMG setup ("pp" or "S") on the first Newton system of
+    the 256x256x64 workload, with the timed form's parameters (FP32 storage):
+    SETUP_REPS setups one after another, the first a warm-up; prints one JSON
+    line with their wall times (for a kernel trace of the setup alone)."""
+    import dataclasses as dc
+    from paper_1902_00095_amd import solver, synth
+    from paper_1902_00095_amd import tpsolve as tps
+    tps.init(0)
+    prob = synth.make_problem("W5")
+    J, _ = solver.assemble(prob, solver.to_device(prob))
+    prm = solver.amg_params(dc.replace(solver.SolveConfig(rtol=RTOL), storage=1), which)
+    val = J.pp if which == "pp" else J.S
+    ms, rows = [], []
+    for _ in range(SETUP_REPS):
+        t0 = _sync_time()
+        h = tps.AMG(J.rowptr, J.col, val, prm)
+        ms.append(round((_sync_time() - t0) * 1e3, 2))
+        rows = [h.level_sizes(l)[0] for l in range(h.nlev)]
+        h.close()
+    print(json.dumps({"setup_study": which, "setups": SETUP_REPS, "setup_ms": ms, "level_rows": rows}),
+          flush=True)
+
+
+def write_setup_summary(db, study_json, out_md):
+    """Per-kernel summary of a rocprofv3 --kernel-trace database of
+    `bench.py --setup-study WHICH` (with the JSON line it printed): the
+    library's setup kernels (the assembly's left out), per setup, averaged
+    over the run's setups."""
+    import re
+    import sqlite3
+    line = json.loads(open(study_json).read().strip().splitlines()[-1])
+    which, reps = line["setup_study"], line["setups"]
+    agg = {}
+    for name, s, e in sqlite3.connect(db).cursor().execute("select name, start, end from kernels"):
+        k = re.sub(r"\(.*", "", name).replace("void ", "")
+        if k.startswith("tp::") and "assemble" not in k:
+            agg.setdefault(k, []).append((e - s) / 1e3)
+    tot = sum(sum(v) for v in agg.values()) / reps / 1e3
+    tag = "pressure" if which == "pp" else "schur"
+    out = [f"# Kernel trace: one {SETUP_NAMES[which]} hierarchy setup, 256x256x64", "",
+           "Commands (repository root, one MI355X):", "", "```",
+           f"rocprofv3 --kernel-trace --stats -d gpurun_out/prof_setup_{which} -o run -- "
+           f"python3 -u bench.py --setup-study {which} > gpurun_out/setup_{which}.json",
+           f"python3 bench.py --write-setup-summary gpurun_out/prof_setup_{which}/run_results.db "
+           f"gpurun_out/setup_{which}.json profiles/setup_{tag}_256x256x64.md", "```", "",
+           f"{reps} setups of the hierarchy on the workload's first Newton system (FP32 storage, the timed "
+           "form's parameters), one after another, the first a warm-up; the table averages the library's "
+           "kernels over all of them (the assembly's kernels left out).", "",
+           f"Wall time per setup under the profiler: {', '.join(f'{v:.1f}' for v in line['setup_ms'])} ms; "
+           f"level sizes {line['level_rows']}.", "",
+           f"Kernel time per setup {tot:.2f} ms.", "",
+           "| kernel | dispatches per setup | ms per setup | mean us | share |", "|---|---|---|---|---|"]
+    for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1]))[:30]:
+        t = sum(v) / reps / 1e3
+        out.append(f"| `{k}` | {len(v) / reps:g} | {t:.3f} | {sum(v) / len(v):.1f} | {100 * t / tot:.1f}% |")
+    open(out_md, "w").write("\n".join(out) + "\n")
+    print(f"wrote {out_md}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -653,7 +717,17 @@ def main():
     ap.add_argument("--write-kernel-summary", nargs="+", metavar="PATH",
                     help="TRACE_DB BENCH_JSON [UNPROFILED_JSON]: write the kernel-trace summary of a short "
                          "bench run and exit")
+    ap.add_argument("--setup-study", choices=("pp", "S"),
+                    help="time one hierarchy's AMG setup on the 256x256x64 workload (for a kernel trace) and exit")
+    ap.add_argument("--write-setup-summary", nargs=3, metavar=("TRACE_DB", "STUDY_JSON", "OUT_MD"),
+                    help="write the kernel-trace summary of a --setup-study run and exit")
     args = ap.parse_args()
+    if args.setup_study:
+        setup_study(args.setup_study)
+        return
+    if args.write_setup_summary:
+        write_setup_summary(*args.write_setup_summary)
+        return
     if args.write_traffic:
         write_traffic(*args.write_traffic)
         return
