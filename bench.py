@@ -700,6 +700,89 @@ def write_setup_summary(db, study_json, out_md):
     print(f"wrote {out_md}")
 
 
+APPLY_REPS = 20
+APPLY_FORMS = {"fp32": "FP32 hierarchies", "fp32_learned": "FP32 hierarchies with the network as the Schur "
+               "finest-level post-smoother", "fp64": "FP64 hierarchies"}
+PHASE_GAP_MS = 100  # host pause between the set-up and the timed applies (found again in the trace)
+
+
+def apply_study(form):
+    """The block preconditioner of the timed form on the first Newton system
+    of the 256x256x64 workload: set up, then (after a PHASE_GAP_MS host pause
+    that marks the phase in a kernel trace) 3 + APPLY_REPS applies through
+    precond_apply, the last APPLY_REPS timed; prints one JSON line.  The
+    learned form attaches an untrained network of the trained one's shape
+    (the kernels' work does not depend on the weights)."""
+    import torch
+    from paper_1902_00095_amd import learned, solver, synth
+    from paper_1902_00095_amd import tpsolve as tps
+    tps.init(0)
+    prob = synth.make_problem("W5")
+    J, G = solver.assemble(prob, solver.to_device(prob))
+    a_pp, a_S, M = solver.setup(J, solver.SolveConfig(rtol=RTOL, storage=0 if form == "fp64" else 1))
+    net = None
+    if form == "fp32_learned":
+        net = tps.Net(learned.init_params(3))
+        a_S.attach(net, prob.grid)
+    b = -G
+    z = torch.empty_like(b)
+    torch.cuda.synchronize()
+    time.sleep(PHASE_GAP_MS / 1e3)
+    for _ in range(3):
+        M.apply(b, z)
+    t0 = _sync_time()
+    for _ in range(APPLY_REPS):
+        M.apply(b, z)
+    ms = (_sync_time() - t0) * 1e3 / APPLY_REPS
+    print(json.dumps({"apply_study": form, "applies": 3 + APPLY_REPS, "apply_ms": round(ms, 4),
+                      "levels": [a_pp.nlev, a_S.nlev]}), flush=True)
+    if net is not None:
+        a_S.attach(None, None)
+        net.close()
+    M.close(); a_pp.close(); a_S.close()
+
+
+def write_apply_summary(db, study_json, out_md):
+    """Per-kernel summary of a rocprofv3 --kernel-trace database of
+    `bench.py --apply-study FORM`: the kernels after the run's last pause of
+    more than PHASE_GAP_MS / 2 (the applies), per apply."""
+    import re
+    import sqlite3
+    line = json.loads(open(study_json).read().strip().splitlines()[-1])
+    form, reps = line["apply_study"], line["applies"]
+    ks = sorted(sqlite3.connect(db).cursor().execute("select start, end, name from kernels"))
+    cut = 0
+    for j in range(1, len(ks)):
+        if ks[j][0] - ks[j - 1][1] > PHASE_GAP_MS / 2 * 1e6:
+            cut = j
+    agg = {}
+    for s0, e0, name in ks[cut:]:
+        k = re.sub(r"\(.*", "", name).replace("void ", "")
+        agg.setdefault(k, []).append((e0 - s0) / 1e3)
+    tot = sum(sum(v) for v in agg.values()) / reps
+    span = (ks[-1][1] - ks[cut][0]) / 1e3 / reps
+    out = [f"# Kernel trace: the preconditioner apply, {APPLY_FORMS[form]}, 256x256x64", "",
+           "Commands (repository root, one MI355X):", "", "```",
+           f"rocprofv3 --kernel-trace --stats -d gpurun_out/prof_apply_{form} -o run -- "
+           f"python3 -u bench.py --apply-study {form} > gpurun_out/apply_{form}.json",
+           f"python3 bench.py --write-apply-summary gpurun_out/prof_apply_{form}/run_results.db "
+           f"gpurun_out/apply_{form}.json profiles/apply_{form}_256x256x64.md", "```", "",
+           f"{reps} applies (`precond_apply`, interleaved vectors, the apply replayed from its HIP graph) of the "
+           "block preconditioner on the workload's first Newton system; the kernels after the pause that "
+           "follows the set-up, averaged per apply."
+           + (" The network is an untrained one of the trained network's shape (the kernels' work does not "
+              "depend on its weights)." if form == "fp32_learned" else ""), "",
+           f"Apply time measured by the run (host clock over {APPLY_REPS} applies): {line['apply_ms']:.3f} ms; "
+           f"under the profiler, kernel time {tot / 1e3:.3f} ms and span {span / 1e3:.3f} ms per apply; "
+           f"levels {line['levels']}.", "",
+           "| kernel | dispatches per apply | us per apply | mean us | share |", "|---|---|---|---|---|"]
+    for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1]))[:30]:
+        t = sum(v) / reps
+        out.append(f"| `{k}` | {len(v) / reps:g} | {t:.1f} | {sum(v) / len(v):.1f} | {100 * t / tot:.1f}% |")
+    open(out_md, "w").write("\n".join(out) + "\n")
+    print(f"wrote {out_md}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -721,7 +804,18 @@ def main():
                     help="time one hierarchy's AMG setup on the 256x256x64 workload (for a kernel trace) and exit")
     ap.add_argument("--write-setup-summary", nargs=3, metavar=("TRACE_DB", "STUDY_JSON", "OUT_MD"),
                     help="write the kernel-trace summary of a --setup-study run and exit")
+    ap.add_argument("--apply-study", choices=tuple(APPLY_FORMS),
+                    help="time the preconditioner apply of one form on the 256x256x64 workload (for a kernel "
+                         "trace) and exit")
+    ap.add_argument("--write-apply-summary", nargs=3, metavar=("TRACE_DB", "STUDY_JSON", "OUT_MD"),
+                    help="write the kernel-trace summary of an --apply-study run and exit")
     args = ap.parse_args()
+    if args.apply_study:
+        apply_study(args.apply_study)
+        return
+    if args.write_apply_summary:
+        write_apply_summary(*args.write_apply_summary)
+        return
     if args.setup_study:
         setup_study(args.setup_study)
         return
