@@ -783,6 +783,63 @@ def write_apply_summary(db, study_json, out_md):
     print(f"wrote {out_md}")
 
 
+CNN_KERNEL = "k_cnn_fused<float, 1>"
+CNN_PASSES = ("SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_ANY "
+              "SQ_ACTIVE_INST_LDS SQ_LDS_BANK_CONFLICT GRBM_GUI_ACTIVE",
+              "SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_INSTS_MFMA SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_LDS "
+              "SQ_WAIT_INST_LDS SQ_INSTS_SALU SQ_INSTS_SMEM")
+
+
+def _pmc_means(db, kernel):
+    """Mean per dispatch of every counter a rocprofv3 --pmc database holds
+    for the kernels whose name contains `kernel` (a dispatch's rows, one per
+    hardware instance, summed first)."""
+    import sqlite3
+    cur = sqlite3.connect(db).cursor()
+    acc = {}
+    for d, name, cn, v in cur.execute("select dispatch_id, name, counter_name, counter_value from pmc_events"):
+        if kernel in name:
+            per = acc.setdefault(cn, {})
+            per[d] = per.get(d, 0.0) + float(v)
+    return ({k: sum(v.values()) / len(v) for k, v in acc.items()},
+            max((len(v) for v in acc.values()), default=0))
+
+
+def write_cnn_counters(db_a, db_b, out_md):
+    """Counter summary of the fused network kernel in the learned apply (two
+    rocprofv3 --pmc passes of `bench.py --apply-study fp32_learned`)."""
+    ma, na = _pmc_means(db_a, CNN_KERNEL)
+    mb, nb = _pmc_means(db_b, CNN_KERNEL)
+    m = {**ma, **mb}
+    waves = m["SQ_WAVES"]
+    out = [f"# Counters: {CNN_KERNEL} (fused network, the learned post-smoother), 256x256x64", "",
+           "Commands (repository root, one MI355X; each counter pass its own run, then the summary):", "", "```"]
+    for j, c in enumerate(CNN_PASSES):
+        out.append(f"timeout -s KILL 120 rocprofv3 --pmc {c} -d gpurun_out/pmc_cnn_{j} -o run -- "
+                   "python3 -u bench.py --apply-study fp32_learned")
+    out += ["python3 bench.py --write-cnn-counters gpurun_out/pmc_cnn_0/run_results.db "
+            "gpurun_out/pmc_cnn_1/run_results.db profiles/pmc_k_cnn_fused_256x256x64.md", "```", "",
+            f"Means per dispatch over {na} and {nb} dispatches (23 applies a run; a dispatch's rows, one per "
+            "hardware instance, summed). SQ cycle counters are summed over the chip's wavefronts "
+            "(wave-cycles, in the counters' own units); the shares below divide them by SQ_WAVE_CYCLES.", "",
+            "| counter | mean per dispatch |", "|---|---|"]
+    out += [f"| {k} | {v:.6g} |" for k, v in sorted(m.items())]
+    wc = m["SQ_WAVE_CYCLES"]
+    out += ["", "| derived | value |", "|---|---|",
+            f"| wavefronts per dispatch | {waves:.0f} |",
+            f"| VALU instructions per wavefront | {m['SQ_INSTS_VALU'] / waves:.0f} |",
+            f"| MFMA instructions per wavefront | {m['SQ_INSTS_MFMA'] / waves:.0f} |",
+            f"| LDS instructions per wavefront | {m['SQ_INSTS_LDS'] / waves:.0f} |",
+            f"| scalar instructions per wavefront | {m['SQ_INSTS_SALU'] / waves:.0f} |",
+            f"| share of wave-cycles issuing (SQ_ACTIVE_INST_ANY) | {m['SQ_ACTIVE_INST_ANY'] / wc:.2f} |",
+            f"| share waiting on memory counters (SQ_WAIT_ANY) | {m['SQ_WAIT_ANY'] / wc:.2f} |",
+            f"| share waiting to issue (SQ_WAIT_INST_ANY) | {m['SQ_WAIT_INST_ANY'] / wc:.2f} |",
+            f"| LDS bank-conflict cycles / active LDS cycles | "
+            f"{m['SQ_LDS_BANK_CONFLICT'] / max(m['SQ_ACTIVE_INST_LDS'], 1):.2f} |"]
+    open(out_md, "w").write("\n".join(out) + "\n")
+    print(f"wrote {out_md}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -809,7 +866,12 @@ def main():
                          "trace) and exit")
     ap.add_argument("--write-apply-summary", nargs=3, metavar=("TRACE_DB", "STUDY_JSON", "OUT_MD"),
                     help="write the kernel-trace summary of an --apply-study run and exit")
+    ap.add_argument("--write-cnn-counters", nargs=3, metavar=("PASS0_DB", "PASS1_DB", "OUT_MD"),
+                    help="write the fused network kernel's counter summary from two --pmc runs and exit")
     args = ap.parse_args()
+    if args.write_cnn_counters:
+        write_cnn_counters(*args.write_cnn_counters)
+        return
     if args.apply_study:
         apply_study(args.apply_study)
         return
