@@ -783,8 +783,14 @@ def write_apply_summary(db, study_json, out_md):
     print(f"wrote {out_md}")
 
 
-CNN_KERNEL = "k_cnn_fused<float, 1>"
-CNN_PASSES = ("SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_ANY "
+COUNTER_SETS = {  # tag: kernel, the run profiled, what the kernel is, summary file
+    "cnn": ("k_cnn_fused<float, 1>", "--apply-study fp32_learned",
+            "fused network, the learned post-smoother, in the learned apply", "pmc_k_cnn_fused_256x256x64.md"),
+    "spgemm": ("k_spgemm_short<64, 256>", "--setup-study pp",
+               "short-row SpGEMM with 256 product slots, in the pressure hierarchy's setup",
+               "pmc_k_spgemm_short_256x256x64.md"),
+}
+COUNTER_PASSES = ("SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_ANY "
               "SQ_ACTIVE_INST_LDS SQ_LDS_BANK_CONFLICT GRBM_GUI_ACTIVE",
               "SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_INSTS_MFMA SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_LDS "
               "SQ_WAIT_INST_LDS SQ_INSTS_SALU SQ_INSTS_SMEM")
@@ -805,21 +811,22 @@ def _pmc_means(db, kernel):
             max((len(v) for v in acc.values()), default=0))
 
 
-def write_cnn_counters(db_a, db_b, out_md):
-    """Counter summary of the fused network kernel in the learned apply (two
-    rocprofv3 --pmc passes of `bench.py --apply-study fp32_learned`)."""
-    ma, na = _pmc_means(db_a, CNN_KERNEL)
-    mb, nb = _pmc_means(db_b, CNN_KERNEL)
+def write_counters(tag, db_a, db_b, out_md):
+    """Counter summary of one kernel (COUNTER_SETS[tag]) from two rocprofv3
+    --pmc passes (COUNTER_PASSES) of the run that COUNTER_SETS names."""
+    kernel, run, what, fname = COUNTER_SETS[tag]
+    ma, na = _pmc_means(db_a, kernel)
+    mb, nb = _pmc_means(db_b, kernel)
     m = {**ma, **mb}
     waves = m["SQ_WAVES"]
-    out = [f"# Counters: {CNN_KERNEL} (fused network, the learned post-smoother), 256x256x64", "",
+    out = [f"# Counters: {kernel} ({what}), 256x256x64", "",
            "Commands (repository root, one MI355X; each counter pass its own run, then the summary):", "", "```"]
-    for j, c in enumerate(CNN_PASSES):
-        out.append(f"timeout -s KILL 120 rocprofv3 --pmc {c} -d gpurun_out/pmc_cnn_{j} -o run -- "
-                   "python3 -u bench.py --apply-study fp32_learned")
-    out += ["python3 bench.py --write-cnn-counters gpurun_out/pmc_cnn_0/run_results.db "
-            "gpurun_out/pmc_cnn_1/run_results.db profiles/pmc_k_cnn_fused_256x256x64.md", "```", "",
-            f"Means per dispatch over {na} and {nb} dispatches (23 applies a run; a dispatch's rows, one per "
+    for j, c in enumerate(COUNTER_PASSES):
+        out.append(f"timeout -s KILL 120 rocprofv3 --pmc {c} -d gpurun_out/pmc_{tag}_{j} -o run -- "
+                   f"python3 -u bench.py {run}")
+    out += [f"python3 bench.py --write-counters {tag} gpurun_out/pmc_{tag}_0/run_results.db "
+            f"gpurun_out/pmc_{tag}_1/run_results.db profiles/{fname}", "```", "",
+            f"Means per dispatch over {na} and {nb} dispatches (a dispatch's rows, one per "
             "hardware instance, summed). SQ cycle counters are summed over the chip's wavefronts "
             "(wave-cycles, in the counters' own units); the shares below divide them by SQ_WAVE_CYCLES.", "",
             "| counter | mean per dispatch |", "|---|---|"]
@@ -866,11 +873,12 @@ def main():
                          "trace) and exit")
     ap.add_argument("--write-apply-summary", nargs=3, metavar=("TRACE_DB", "STUDY_JSON", "OUT_MD"),
                     help="write the kernel-trace summary of an --apply-study run and exit")
-    ap.add_argument("--write-cnn-counters", nargs=3, metavar=("PASS0_DB", "PASS1_DB", "OUT_MD"),
-                    help="write the fused network kernel's counter summary from two --pmc runs and exit")
+    ap.add_argument("--write-counters", nargs=4, metavar=("TAG", "PASS0_DB", "PASS1_DB", "OUT_MD"),
+                    help="write a kernel's counter summary (TAG: " + ", ".join(COUNTER_SETS)
+                         + ") from two --pmc runs and exit")
     args = ap.parse_args()
-    if args.write_cnn_counters:
-        write_cnn_counters(*args.write_cnn_counters)
+    if args.write_counters:
+        write_counters(*args.write_counters)
         return
     if args.apply_study:
         apply_study(args.apply_study)
